@@ -1,0 +1,187 @@
+/*
+ * topo_rom.h -- C ABI of the MI355X (gfx950) hot path of ROM-accelerated SIMP
+ * minimum-compliance topology optimisation.
+ *
+ * Method: Yano, Huang & Zahr, "A globally convergent method to accelerate topology
+ * optimization using on-the-fly model reduction".  The full-order model (HDM) is the
+ * SIMP linear-elastic state equation K(rho) u = f on a structured grid of bilinear
+ * (2D, Q4) or trilinear (3D, H8) elements (Sec. 2.1), its compliance f^T u (Sec. 2.3)
+ * and the element sensitivity dc/drho_e = -alpha'(rho_e) u_e^T K_e u_e (Sec. 2.4 and
+ * the adjoint appendix; compliance is self-adjoint).  The reduced-order model (ROM)
+ * is the Galerkin projection K_hat = Phi^T K(rho) Phi, f_hat = Phi^T f, the reduced
+ * solve K_hat y = f_hat and the residual norm ||f - K(rho) Phi y|| used as the error
+ * indicator and trust-region constraint (Sec. 3.1, 3.3, 3.4 and Sec. 4.3).
+ *
+ * General conventions
+ * -------------------
+ *  - Every array argument is a DEVICE pointer owned by the caller (e.g. memory of a
+ *    torch tensor), unless the comment says "host".  The library never frees or keeps
+ *    caller pointers beyond the call.  Outputs are written only when TOPO_OK is
+ *    returned (device outputs of a failed call are unspecified).
+ *  - Structured grid: nel = (nx, ny[, nz]) elements of edge lengths h; node (i,j[,k])
+ *    has index i + (nx+1)*(j + (ny+1)*k); element (ex,ey[,ez]) has index
+ *    ex + nx*(ey + ny*ez).
+ *  - DOF vectors are structure-of-arrays: component c of node n is entry
+ *    c*n_nodes + n; N_u = dim * n_nodes.
+ *  - mask: uint8 [N_u]; 1 marks a homogeneous Dirichlet DOF.  Those DOFs are
+ *    eliminated (Sec. 2.1): entries of f and rows of Phi there are ignored (taken as
+ *    zero), u = 0 and r = 0 there, and every norm / dot product runs over free DOFs.
+ *  - Material law (Sec. 2.1): alpha(rho) = Emin + (E0 - Emin) rho^penal; the paper's
+ *    law is the case E0 = 1, Emin = rho_l.
+ *  - Basis Phi: row-major [N_u][ldphi], rows indexed like DOF vectors; the first k
+ *    columns are used.  float32 when phi_fp32 != 0, float64 otherwise.  Phi must
+ *    have full column rank on the free DOFs (orthonormality is not required).
+ *  - stream: a hipStream_t (NULL = the null stream).  Work is stream-ordered.  Calls
+ *    that need a convergence or pivot decision (hdm_solve, rom_estimate with
+ *    max_refine > 0, rom_solve with status == NULL) synchronise that stream and
+ *    return the outcome synchronously.
+ *  - Threading: a context is used by one host thread at a time; distinct contexts
+ *    may run concurrently on distinct streams.
+ *  - Errors: a negative TOPO_E* code; topo_last_error(ctx) gives a message.
+ */
+#ifndef TOPO_ROM_H
+#define TOPO_ROM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TOPO_OK 0
+#define TOPO_EINVAL (-1)   /* invalid argument (checked before any device work) */
+#define TOPO_ENOMEM (-2)   /* device workspace allocation failed / over budget     */
+#define TOPO_ENOCONV (-3)  /* iteration limit reached or stagnation                */
+#define TOPO_ENOTSPD (-4)  /* non-positive pivot / CG breakdown: not SPD            */
+#define TOPO_EDEVICE (-5)  /* HIP runtime error                                     */
+#define TOPO_EAGAIN (-6)   /* serving: request cannot be admitted now               */
+
+/* Precision of the hot loops. */
+#define TOPO_FP64 0   /* everything in float64                                      */
+#define TOPO_MIXED 1  /* float32 apply / contraction with float64 refinement,       */
+                      /* float64 dots, norms, compliance and reduced Cholesky        */
+
+typedef struct topo_ctx topo_ctx;
+
+/* Structured-grid problem description (Sec. 2.1).  Passed by host pointer. */
+typedef struct topo_mesh {
+    int32_t dim;      /* 2 (Q4) or 3 (H8)                                          */
+    int32_t nel[3];   /* elements per axis; nel[2] ignored when dim == 2            */
+    double h[3];      /* element edge lengths (> 0); h[2] ignored when dim == 2     */
+    double E0;        /* solid stiffness (> Emin)                                   */
+    double Emin;      /* void stiffness (>= 0)                                      */
+    double nu;        /* Poisson ratio, -1 < nu < 0.5                               */
+    double penal;     /* SIMP exponent p >= 1                                       */
+    int32_t plane;    /* 2D only: 0 = plane stress, 1 = plane strain; unit thickness */
+} topo_mesh;
+
+/* Diagnostics of an HDM solve.  Host struct. */
+typedef struct topo_info {
+    int32_t iters;          /* inner PCG iterations summed over refinement steps      */
+    int32_t refinements;    /* outer float64 residual / correction steps              */
+    double rel_resid;       /* final true ||f - K u||_2 / ||f||_2 over free DOFs      */
+    double compliance_raw;  /* f^T u                                                   */
+    double compliance_corr; /* f^T u + u^T r = c* - ||u - u*||_K^2 (second order)    */
+} topo_info;
+
+/* ---- context ------------------------------------------------------------------ */
+
+/* Create a context on HIP device `device`: element tables, device workspace.
+ * Ownership of *out passes to the caller; release with topo_ctx_destroy. */
+int topo_ctx_create(topo_ctx** out, int32_t device);
+int topo_ctx_destroy(topo_ctx* ctx);
+/* Message of the last error raised on ctx (valid until the next call on ctx). */
+const char* topo_last_error(const topo_ctx* ctx);
+/* Static name of an error code. */
+const char* topo_strerror(int32_t code);
+/* Bytes of device workspace currently held by ctx (host scalar). */
+size_t topo_ctx_workspace_bytes(const topo_ctx* ctx);
+
+/* ---- element operator --------------------------------------------------------- */
+
+/* Unit-density element stiffness K_e of the mesh's element (Sec. 2.1), exact for the
+ * rectangular Q4 / H8 element.  Local DOF order: dim*a + c, tensor-order local node
+ * a = ax + 2*ay (+ 4*az).  K0: HOST array of (dim*2^dim)^2 doubles, row-major. */
+int topo_element_stiffness(const topo_mesh* mesh, double* K0);
+
+/* ---- full-order model ----------------------------------------------------------- */
+
+/* Matrix-free operator apply y_b = K(rho_b) x_b for B fields (Sec. 2.1,
+ * K = sum_e alpha(rho_e) P_e K_e P_e^T), Dirichlet DOFs eliminated: y_f = K_ff x_f,
+ * y = 0 on constrained DOFs, x ignored there.
+ *   rho: [B][n_elems] float64;  x, y: [B][N_u], float64 when prec == TOPO_FP64,
+ *   float32 when prec == TOPO_MIXED (the inner-loop apply). */
+int topo_apply(topo_ctx* ctx, const topo_mesh* mesh, const double* rho,
+               const uint8_t* mask, const void* x, void* y, int32_t B, int32_t prec,
+               void* stream);
+
+/* HDM state solve K_ff(rho) u_f = f_f (Sec. 2.1) by Jacobi-preconditioned CG on the
+ * matrix-free operator, from u = 0, until the TRUE residual satisfies
+ * ||f - K u||_2 <= rtol ||f||_2 (recomputed in float64).  TOPO_MIXED runs float32
+ * inner CG solves on the float64 residual (iterative refinement).  Then compliance
+ * f^T u (Sec. 2.3).
+ *   rho [n_elems] f64, mask [N_u] u8, f [N_u] f64, u [N_u] f64 (output).
+ *   compliance: HOST double, receives compliance_corr (may be NULL).
+ *   info: HOST, may be NULL.  maxit bounds the total inner iterations.
+ * Returns TOPO_ENOCONV when maxit is reached or refinement stagnates (u and info
+ * then hold the last iterate), TOPO_ENOTSPD on a CG breakdown. */
+int topo_hdm_solve(topo_ctx* ctx, const topo_mesh* mesh, const double* rho,
+                   const uint8_t* mask, const double* f, double* u, double rtol,
+                   int32_t maxit, int32_t prec, double* compliance, topo_info* info,
+                   void* stream);
+
+/* Element sensitivity of the compliance with respect to the filtered density,
+ * dc[e] = -penal (E0 - Emin) rho_e^(penal-1) u_e^T K_e u_e (Sec. 2.4, compliance
+ * remark: lambda* = u*, no adjoint solve), float64.
+ *   rho [n_elems] f64, u [N_u] f64 (zero on Dirichlet DOFs), dc [n_elems] f64 out. */
+int topo_hdm_gradient(topo_ctx* ctx, const topo_mesh* mesh, const double* rho,
+                      const double* u, double* dc, void* stream);
+
+/* ---- reduced-order model --------------------------------------------------------- */
+
+/* Reduced operators of B density fields sharing one basis (Sec. 3.1, element-sum
+ * form of K_hat, computed per element with dense operations as the paper's dense
+ * assembly remark suggests):
+ *   Khat[b] = sum_e alpha(rho_be) (P_e^T Phi)^T K_e (P_e^T Phi)   [B][k][k] f64 out,
+ *   fhat    = Phi^T f                                             [k] f64 out (may
+ *             be NULL; it depends on the basis only).
+ * TOPO_MIXED contracts float32 Phi on float32 matrix cores with float64 cross-tile
+ * sums; TOPO_FP64 contracts in float64 (Phi promoted when phi_fp32 != 0).
+ *   rho: [B][n_elems] f64. */
+int topo_rom_build(topo_ctx* ctx, const topo_mesh* mesh, const void* phi,
+                   int32_t phi_fp32, int32_t k, int32_t ldphi, const uint8_t* mask,
+                   const double* f, const double* rho, int32_t B, double* Khat,
+                   double* fhat, int32_t prec, void* stream);
+
+/* Reduced solve (Sec. 3.1 and 3.4): float64 Cholesky of each K_hat[b], yhat[b] =
+ * K_hat[b]^{-1} fhat, Jk[b] = fhat^T yhat[b] (the ROM compliance).
+ *   Khat [B][k][k] f64 (symmetric; lower triangle read), fhat [k] f64,
+ *   yhat [B][k] f64 out, Jk [B] f64 out.
+ *   status: [B] int32 DEVICE out (0 ok, TOPO_ENOTSPD when a pivot is not positive),
+ *   or NULL: then the call synchronises and returns TOPO_ENOTSPD if any failed. */
+int topo_rom_solve(topo_ctx* ctx, int32_t k, int32_t B, const double* Khat,
+                   const double* fhat, double* yhat, double* Jk, int32_t* status,
+                   void* stream);
+
+/* Residual-based error indicator (Sec. 3.3 primal residual; Sec. 3.4 cost
+ * analysis; Sec. 4.3 residual trust-region constraint):
+ *   u_b = Phi yhat[b] (float64 accumulation), r_b = f - K(rho_b) u_b on free DOFs in
+ *   float64, resnorm[b] = ||r_b||_2.
+ * With max_refine > 0 the reduced coefficients are refined in float64, up to
+ * max_refine times: yhat += K_hat^{-1} Phi^T r (stopping early when ||r|| no longer
+ * decreases), recovering float64 accuracy of a float32 K_hat; then
+ * Jk[b] = f^T Phi yhat[b] and resnorm are those of the refined yhat.
+ *   yhat [B][k] f64 in/out, Jk [B] f64 out (may be NULL), resnorm [B] f64 out,
+ *   Khat [B][k][k] f64 (only read when max_refine > 0). */
+int topo_rom_estimate(topo_ctx* ctx, const topo_mesh* mesh, const void* phi,
+                      int32_t phi_fp32, int32_t k, int32_t ldphi, const uint8_t* mask,
+                      const double* f, const double* rho, int32_t B, const double* Khat,
+                      double* yhat, double* Jk, double* resnorm, int32_t max_refine,
+                      void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TOPO_ROM_H */

@@ -1,0 +1,283 @@
+"""ctypes binding of libtopo_rom.so (argument marshalling only).
+
+Tensors are torch tensors on the GPU; their device pointers and the current HIP
+stream are handed to the C ABI declared in include/topo_rom.h.  No arithmetic of the
+method happens here.  Loading fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import threading
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "_lib", "libtopo_rom.so")
+
+TOPO_OK, TOPO_EINVAL, TOPO_ENOMEM, TOPO_ENOCONV, TOPO_ENOTSPD, TOPO_EDEVICE, TOPO_EAGAIN = \
+    0, -1, -2, -3, -4, -5, -6
+FP64, MIXED = 0, 1
+
+# every symbol the public headers declare
+EXPORTED = (
+    "topo_ctx_create", "topo_ctx_destroy", "topo_last_error", "topo_strerror",
+    "topo_ctx_workspace_bytes", "topo_element_stiffness", "topo_apply", "topo_hdm_solve",
+    "topo_hdm_gradient", "topo_rom_build", "topo_rom_solve", "topo_rom_estimate",
+)
+
+
+class TopoError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_strerror(code)} ({code}): {msg}")
+        self.code = code
+
+
+class TopoMesh(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("nel", C.c_int32 * 3), ("h", C.c_double * 3),
+                ("E0", C.c_double), ("Emin", C.c_double), ("nu", C.c_double),
+                ("penal", C.c_double), ("plane", C.c_int32)]
+
+
+class TopoInfo(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("refinements", C.c_int32), ("rel_resid", C.c_double),
+                ("compliance_raw", C.c_double), ("compliance_corr", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_P = C.c_void_p
+_SIGS = {
+    "topo_ctx_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32]),
+    "topo_ctx_destroy": (C.c_int, [_P]),
+    "topo_last_error": (C.c_char_p, [_P]),
+    "topo_strerror": (C.c_char_p, [C.c_int32]),
+    "topo_ctx_workspace_bytes": (C.c_size_t, [_P]),
+    "topo_element_stiffness": (C.c_int, [C.POINTER(TopoMesh), C.POINTER(C.c_double)]),
+    "topo_apply": (C.c_int, [_P, C.POINTER(TopoMesh), _P, _P, _P, _P, C.c_int32, C.c_int32, _P]),
+    "topo_hdm_solve": (C.c_int, [_P, C.POINTER(TopoMesh), _P, _P, _P, _P, C.c_double, C.c_int32,
+                                 C.c_int32, C.POINTER(C.c_double), C.POINTER(TopoInfo), _P]),
+    "topo_hdm_gradient": (C.c_int, [_P, C.POINTER(TopoMesh), _P, _P, _P, _P]),
+    "topo_rom_build": (C.c_int, [_P, C.POINTER(TopoMesh), _P, C.c_int32, C.c_int32, C.c_int32, _P,
+                                 _P, _P, C.c_int32, _P, _P, C.c_int32, _P]),
+    "topo_rom_solve": (C.c_int, [_P, C.c_int32, C.c_int32, _P, _P, _P, _P, _P, _P]),
+    "topo_rom_estimate": (C.c_int, [_P, C.POINTER(TopoMesh), _P, C.c_int32, C.c_int32, C.c_int32,
+                                    _P, _P, _P, C.c_int32, _P, _P, _P, _P, C.c_int32, _P]),
+}
+
+_lib = None
+_lock = threading.Lock()
+
+
+def load(path: str = LIB_PATH) -> C.CDLL:
+    """Load the shared library (no GPU needed) and declare every signature."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(path):
+                raise RuntimeError(f"HIP library not built: {path} (run paper_2004_05756_amd.build)")
+            lib = C.CDLL(path)
+            for name, (res, args) in _SIGS.items():
+                fn = getattr(lib, name)
+                fn.restype = res
+                fn.argtypes = args
+            _lib = lib
+        return _lib
+
+
+def _strerror(code):
+    try:
+        return load().topo_strerror(code).decode()
+    except Exception:  # pragma: no cover - library missing
+        return str(code)
+
+
+def make_mesh(mesh) -> TopoMesh:
+    """TopoMesh from any object with nel, h, E0, Emin, nu, penal (and optional plane)."""
+    m = TopoMesh()
+    nel = tuple(mesh.nel)
+    m.dim = len(nel)
+    for i in range(3):
+        m.nel[i] = nel[i] if i < len(nel) else 1
+        m.h[i] = float(mesh.h[i]) if i < len(nel) else 1.0
+    m.E0, m.Emin, m.nu, m.penal = float(mesh.E0), float(mesh.Emin), float(mesh.nu), float(mesh.penal)
+    m.plane = int(getattr(mesh, "plane", 0))
+    return m
+
+
+def element_stiffness(mesh):
+    import numpy as np
+    m = make_mesh(mesh)
+    ne = m.dim * 2 ** m.dim
+    out = (C.c_double * (ne * ne))()
+    rc = load().topo_element_stiffness(C.byref(m), out)
+    if rc != TOPO_OK:
+        raise TopoError(rc, "element stiffness")
+    return np.frombuffer(out, dtype=np.float64).reshape(ne, ne).copy()
+
+
+def _ptr(t, dtype=None, name="tensor"):
+    import torch
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t.data_ptr()
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+class Context:
+    """One library context (device workspace + element tables) on one GPU."""
+
+    def __init__(self, device: int = 0):
+        self.lib = load()
+        self.device = device
+        h = C.c_void_p()
+        rc = self.lib.topo_ctx_create(C.byref(h), device)
+        if rc != TOPO_OK:
+            raise TopoError(rc, "context creation")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.topo_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, what):
+        if rc != TOPO_OK:
+            raise TopoError(rc, f"{what}: {self.lib.topo_last_error(self.h).decode()}")
+
+    def workspace_bytes(self):
+        return self.lib.topo_ctx_workspace_bytes(self.h)
+
+    # -- full-order model -------------------------------------------------------------
+    def apply(self, mesh, rho, mask, x, y=None, prec=FP64, stream=None):
+        import torch
+        dt = torch.float64 if prec == FP64 else torch.float32
+        B = rho.shape[0] if rho.dim() == 2 else 1
+        if y is None:
+            y = torch.empty_like(x)
+        m = make_mesh(mesh)
+        rc = self.lib.topo_apply(self.h, C.byref(m), _ptr(rho, torch.float64, "rho"),
+                                 _ptr(mask, torch.uint8, "mask"), _ptr(x, dt, "x"),
+                                 _ptr(y, dt, "y"), B, prec, _stream(stream))
+        self._check(rc, "apply")
+        return y
+
+    def hdm_solve(self, mesh, rho, mask, f, u=None, rtol=1e-10, maxit=200000, prec=FP64,
+                  stream=None, check=True):
+        import torch
+        if u is None:
+            u = torch.empty_like(f)
+        m = make_mesh(mesh)
+        info = TopoInfo()
+        comp = C.c_double()
+        rc = self.lib.topo_hdm_solve(self.h, C.byref(m), _ptr(rho, torch.float64, "rho"),
+                                     _ptr(mask, torch.uint8, "mask"), _ptr(f, torch.float64, "f"),
+                                     _ptr(u, torch.float64, "u"), float(rtol), int(maxit), prec,
+                                     C.byref(comp), C.byref(info), _stream(stream))
+        if check:
+            self._check(rc, "hdm_solve")
+        d = info.as_dict()
+        d["status"] = rc
+        return u, d
+
+    def hdm_gradient(self, mesh, rho, u, dc=None, stream=None):
+        import torch
+        if dc is None:
+            dc = torch.empty_like(rho)
+        m = make_mesh(mesh)
+        rc = self.lib.topo_hdm_gradient(self.h, C.byref(m), _ptr(rho, torch.float64, "rho"),
+                                        _ptr(u, torch.float64, "u"), _ptr(dc, torch.float64, "dc"),
+                                        _stream(stream))
+        self._check(rc, "hdm_gradient")
+        return dc
+
+    # -- reduced-order model ----------------------------------------------------------
+    def rom_build(self, mesh, phi, k, mask, f, rho, prec=MIXED, with_fhat=True, Khat=None,
+                  fhat=None, stream=None):
+        import torch
+        if rho.dim() == 1:
+            rho = rho.unsqueeze(0)
+        B = rho.shape[0]
+        dev = rho.device
+        if Khat is None:
+            Khat = torch.empty((B, k, k), dtype=torch.float64, device=dev)
+        if with_fhat and fhat is None:
+            fhat = torch.empty(k, dtype=torch.float64, device=dev)
+        m = make_mesh(mesh)
+        fp32 = 1 if phi.dtype == torch.float32 else 0
+        rc = self.lib.topo_rom_build(self.h, C.byref(m), _ptr(phi, None, "phi"), fp32, int(k),
+                                     int(phi.shape[1]), _ptr(mask, torch.uint8, "mask"),
+                                     _ptr(f, torch.float64, "f"), _ptr(rho, torch.float64, "rho"), B,
+                                     _ptr(Khat, torch.float64, "Khat"),
+                                     _ptr(fhat, torch.float64, "fhat") if with_fhat else None,
+                                     prec, _stream(stream))
+        self._check(rc, "rom_build")
+        return Khat, fhat
+
+    def rom_solve(self, Khat, fhat, status=None, yhat=None, Jk=None, stream=None):
+        import torch
+        B, k, _ = Khat.shape
+        if yhat is None:
+            yhat = torch.empty((B, k), dtype=torch.float64, device=Khat.device)
+        if Jk is None:
+            Jk = torch.empty(B, dtype=torch.float64, device=Khat.device)
+        rc = self.lib.topo_rom_solve(self.h, k, B, _ptr(Khat, torch.float64, "Khat"),
+                                     _ptr(fhat, torch.float64, "fhat"), _ptr(yhat, torch.float64, "yhat"),
+                                     _ptr(Jk, torch.float64, "Jk"),
+                                     _ptr(status, torch.int32, "status") if status is not None else None,
+                                     _stream(stream))
+        self._check(rc, "rom_solve")
+        return yhat, Jk
+
+    def rom_estimate(self, mesh, phi, k, mask, f, rho, Khat, yhat, max_refine=2, stream=None,
+                     Jk=None, resnorm=None):
+        import torch
+        if rho.dim() == 1:
+            rho = rho.unsqueeze(0)
+        B = rho.shape[0]
+        dev = rho.device
+        if Jk is None:
+            Jk = torch.empty(B, dtype=torch.float64, device=dev)
+        if resnorm is None:
+            resnorm = torch.empty(B, dtype=torch.float64, device=dev)
+        m = make_mesh(mesh)
+        fp32 = 1 if phi.dtype == torch.float32 else 0
+        rc = self.lib.topo_rom_estimate(self.h, C.byref(m), _ptr(phi, None, "phi"), fp32, int(k),
+                                        int(phi.shape[1]), _ptr(mask, torch.uint8, "mask"),
+                                        _ptr(f, torch.float64, "f"), _ptr(rho, torch.float64, "rho"),
+                                        B, _ptr(Khat, torch.float64, "Khat") if Khat is not None else None,
+                                        _ptr(yhat, torch.float64, "yhat"), _ptr(Jk, torch.float64, "Jk"),
+                                        _ptr(resnorm, torch.float64, "resnorm"), int(max_refine),
+                                        _stream(stream))
+        self._check(rc, "rom_estimate")
+        return yhat, Jk, resnorm
+
+
+_ctx = {}
+
+
+def context(device: int = 0) -> Context:
+    """Process-wide default context per device."""
+    if device not in _ctx:
+        _ctx[device] = Context(device)
+    return _ctx[device]
+
+
+def lib():
+    return load()

@@ -1,0 +1,260 @@
+// Context, workspace arena, element tables and argument validation.
+#include <cmath>
+#include <cstdarg>
+
+#include "internal.hpp"
+
+namespace topo {
+
+Grid make_grid(const topo_mesh& m) {
+    Grid g;
+    g.dim = m.dim;
+    g.nx = m.nel[0];
+    g.ny = m.nel[1];
+    g.nz = m.dim == 3 ? m.nel[2] : 1;
+    g.nx1 = g.nx + 1;
+    g.ny1 = g.ny + 1;
+    g.nz1 = m.dim == 3 ? g.nz + 1 : 1;
+    g.n_nodes = g.nx1 * g.ny1 * g.nz1;
+    g.n_elems = g.nx * g.ny * g.nz;
+    g.n_dofs = (long long)g.dim * g.n_nodes;
+    return g;
+}
+
+// Element stiffness of the rectangular bilinear / trilinear element written as sums
+// of tensor products of exact 1D integrals of the linear shape functions
+// f0 = 1 - x/h, f1 = x/h on [0, h]:
+//   mass  M[a][b] = int f_a f_b     = h/3 (a == b), h/6 (a != b)
+//   stiff S[a][b] = int f_a' f_b'   = +1/h (a == b), -1/h (a != b)
+//   mixed G[a][b] = int f_a' f_b    = s(a)/2 with s(0) = -1, s(1) = +1.
+// The strain energy of the element (Sec. 2.1) then gives every entry in closed form.
+void element_stiffness(const topo_mesh& m, std::vector<double>& K) {
+    const int dim = m.dim;
+    const int nen = 1 << dim;
+    const int ne = dim * nen;
+    K.assign((size_t)ne * ne, 0.0);
+    double M[3][2][2], S[3][2][2], G[3][2][2];
+    for (int ax = 0; ax < dim; ++ax) {
+        const double h = m.h[ax];
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b) {
+                M[ax][a][b] = (a == b) ? h / 3.0 : h / 6.0;
+                S[ax][a][b] = (a == b) ? 1.0 / h : -1.0 / h;
+                G[ax][a][b] = (a == 0 ? -1.0 : 1.0) / 2.0;
+            }
+    }
+    // I(a, b, da, db) = int (d_da N_a)(d_db N_b); da/db = -1 means no derivative.
+    auto I = [&](int a, int b, int da, int db) {
+        double v = 1.0;
+        for (int ax = 0; ax < dim; ++ax) {
+            const int ia = (a >> ax) & 1, ib = (b >> ax) & 1;
+            if (da == ax && db == ax) v *= S[ax][ia][ib];
+            else if (da == ax) v *= G[ax][ia][ib];
+            else if (db == ax) v *= G[ax][ib][ia];
+            else v *= M[ax][ia][ib];
+        }
+        return v;
+    };
+    const double E = 1.0, nu = m.nu;
+    if (dim == 2) {
+        double D11, D12, D33;
+        if (m.plane == 0) {  // plane stress
+            const double c = E / (1.0 - nu * nu);
+            D11 = c;
+            D12 = c * nu;
+            D33 = c * (1.0 - nu) / 2.0;
+        } else {  // plane strain
+            const double c = E / ((1.0 + nu) * (1.0 - 2.0 * nu));
+            D11 = c * (1.0 - nu);
+            D12 = c * nu;
+            D33 = c * (1.0 - 2.0 * nu) / 2.0;
+        }
+        for (int a = 0; a < 4; ++a)
+            for (int b = 0; b < 4; ++b) {
+                const double xx = I(a, b, 0, 0), yy = I(a, b, 1, 1);
+                const double xy = I(a, b, 0, 1), yx = I(a, b, 1, 0);
+                K[(2 * a) * ne + 2 * b] = D11 * xx + D33 * yy;
+                K[(2 * a + 1) * ne + 2 * b + 1] = D11 * yy + D33 * xx;
+                K[(2 * a) * ne + 2 * b + 1] = D12 * xy + D33 * yx;
+                K[(2 * a + 1) * ne + 2 * b] = D12 * yx + D33 * xy;
+            }
+    } else {
+        const double lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+        const double mu = E / (2.0 * (1.0 + nu));
+        for (int a = 0; a < 8; ++a)
+            for (int b = 0; b < 8; ++b)
+                for (int p = 0; p < 3; ++p)
+                    for (int q = 0; q < 3; ++q) {
+                        double v;
+                        if (p == q) {
+                            v = (lam + 2.0 * mu) * I(a, b, p, p);
+                            for (int r = 0; r < 3; ++r)
+                                if (r != p) v += mu * I(a, b, r, r);
+                        } else {
+                            v = lam * I(a, b, p, q) + mu * I(a, b, q, p);
+                        }
+                        K[(3 * a + p) * ne + 3 * b + q] = v;
+                    }
+    }
+}
+
+int set_error(Ctx* c, int code, const char* fmt, ...) {
+    if (c) {
+        char buf[1024];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        c->err = buf;
+    }
+    return code;
+}
+
+int Arena::commit(Ctx* ctx, hipStream_t s) {
+    size_t total = 0;
+    for (auto& r : reqs) total += (r.bytes + 255) & ~size_t(255);
+    if (total > ctx->ws_bytes) {
+        if (ctx->ws) {
+            TOPO_HIP(hipStreamSynchronize(s));
+            TOPO_HIP(hipDeviceSynchronize());
+            TOPO_HIP(hipFree(ctx->ws));
+            ctx->ws = nullptr;
+            ctx->ws_bytes = 0;
+        }
+        size_t want = total + total / 4 + (1 << 20);
+        if (hipMalloc(&ctx->ws, want) != hipSuccess) {
+            (void)hipGetLastError();
+            ctx->ws = nullptr;
+            return set_error(ctx, TOPO_ENOMEM, "workspace allocation of %zu bytes failed", want);
+        }
+        ctx->ws_bytes = want;
+    }
+    char* p = (char*)ctx->ws;
+    for (auto& r : reqs) {
+        *r.out = p;
+        p += (r.bytes + 255) & ~size_t(255);
+    }
+    reqs.clear();
+    return TOPO_OK;
+}
+
+int pinned_host(Ctx* ctx, size_t bytes, void** out) {
+    if (bytes > ctx->pinned_bytes) {
+        if (ctx->pinned) TOPO_HIP(hipHostFree(ctx->pinned));
+        ctx->pinned = nullptr;
+        TOPO_HIP(hipHostMalloc(&ctx->pinned, bytes, hipHostMallocDefault));
+        ctx->pinned_bytes = bytes;
+    }
+    *out = ctx->pinned;
+    return TOPO_OK;
+}
+
+const ElemTables* get_tables(Ctx* ctx, const topo_mesh& m) {
+    const int dim = m.dim;
+    auto key = std::make_tuple(dim, m.h[0], m.h[1], dim == 3 ? m.h[2] : 0.0, m.nu,
+                               dim == 2 ? m.plane : 0);
+    auto it = ctx->tables.find(key);
+    if (it != ctx->tables.end()) return &it->second;
+    ElemTables t;
+    element_stiffness(m, t.host);
+    t.ne = dim * (1 << dim);
+    const size_t n = (size_t)t.ne * t.ne;
+    std::vector<float> k32(n);
+    for (size_t i = 0; i < n; ++i) k32[i] = (float)t.host[i];
+    for (int c = 0; c < 3; ++c) t.diag[c] = c < dim ? t.host[(size_t)c * t.ne + c] : 0.0;
+    if (hipMalloc(&t.K64, n * sizeof(double)) != hipSuccess) return nullptr;
+    if (hipMalloc(&t.K32, n * sizeof(float)) != hipSuccess) return nullptr;
+    if (hipMemcpy(t.K64, t.host.data(), n * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+        return nullptr;
+    if (hipMemcpy(t.K32, k32.data(), n * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
+        return nullptr;
+    return &(ctx->tables[key] = t);
+}
+
+int validate_mesh(Ctx* ctx, const topo_mesh* m) {
+    if (!m) return set_error(ctx, TOPO_EINVAL, "mesh is NULL");
+    if (m->dim != 2 && m->dim != 3) return set_error(ctx, TOPO_EINVAL, "dim must be 2 or 3");
+    for (int d = 0; d < m->dim; ++d) {
+        if (m->nel[d] < 1) return set_error(ctx, TOPO_EINVAL, "nel[%d] < 1", d);
+        if (!(m->h[d] > 0.0) || !std::isfinite(m->h[d]))
+            return set_error(ctx, TOPO_EINVAL, "h[%d] must be positive", d);
+    }
+    double nodes = 1.0;
+    for (int d = 0; d < m->dim; ++d) nodes *= (m->nel[d] + 1.0);
+    if (nodes * m->dim > 2.0e9) return set_error(ctx, TOPO_EINVAL, "mesh too large");
+    if (!(m->nu > -1.0 && m->nu < 0.5)) return set_error(ctx, TOPO_EINVAL, "nu must lie in (-1, 0.5)");
+    if (!(m->Emin >= 0.0) || !(m->E0 > m->Emin) || !std::isfinite(m->E0))
+        return set_error(ctx, TOPO_EINVAL, "need 0 <= Emin < E0");
+    if (!(m->penal >= 1.0) || !std::isfinite(m->penal))
+        return set_error(ctx, TOPO_EINVAL, "penal must be >= 1");
+    if (m->dim == 2 && m->plane != 0 && m->plane != 1)
+        return set_error(ctx, TOPO_EINVAL, "plane must be 0 (stress) or 1 (strain)");
+    return TOPO_OK;
+}
+
+}  // namespace topo
+
+using namespace topo;
+
+extern "C" {
+
+int topo_ctx_create(topo_ctx** out, int32_t device) {
+    if (!out) return TOPO_EINVAL;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n == 0) {
+        (void)hipGetLastError();
+        return TOPO_EDEVICE;
+    }
+    if (device < 0 || device >= n) return TOPO_EINVAL;
+    if (hipSetDevice(device) != hipSuccess) return TOPO_EDEVICE;
+    topo_ctx* c = new topo_ctx();
+    c->device = device;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->cu_count = prop.multiProcessorCount;
+    *out = c;
+    return TOPO_OK;
+}
+
+int topo_ctx_destroy(topo_ctx* c) {
+    if (!c) return TOPO_OK;
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+    for (auto& kv : c->tables) {
+        (void)hipFree(kv.second.K64);
+        (void)hipFree(kv.second.K32);
+    }
+    if (c->ws) (void)hipFree(c->ws);
+    if (c->pinned) (void)hipHostFree(c->pinned);
+    delete c;
+    return TOPO_OK;
+}
+
+const char* topo_last_error(const topo_ctx* c) { return c ? c->err.c_str() : "no context"; }
+
+size_t topo_ctx_workspace_bytes(const topo_ctx* c) { return c ? c->ws_bytes : 0; }
+
+const char* topo_strerror(int32_t code) {
+    switch (code) {
+        case TOPO_OK: return "TOPO_OK";
+        case TOPO_EINVAL: return "TOPO_EINVAL";
+        case TOPO_ENOMEM: return "TOPO_ENOMEM";
+        case TOPO_ENOCONV: return "TOPO_ENOCONV";
+        case TOPO_ENOTSPD: return "TOPO_ENOTSPD";
+        case TOPO_EDEVICE: return "TOPO_EDEVICE";
+        case TOPO_EAGAIN: return "TOPO_EAGAIN";
+        default: return "TOPO_UNKNOWN";
+    }
+}
+
+int topo_element_stiffness(const topo_mesh* mesh, double* K0) {
+    if (!K0) return TOPO_EINVAL;
+    int rc = validate_mesh(nullptr, mesh);
+    if (rc) return rc;
+    std::vector<double> K;
+    element_stiffness(*mesh, K);
+    std::memcpy(K0, K.data(), K.size() * sizeof(double));
+    return TOPO_OK;
+}
+
+}  // extern "C"

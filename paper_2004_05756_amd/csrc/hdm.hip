@@ -1,0 +1,709 @@
+// Full-order model on the device: matrix-free K(rho) apply, Jacobi-preconditioned CG
+// with float64 iterative refinement, compliance and element sensitivity
+// (Sec. 2.1 state equation, Sec. 2.3 compliance, Sec. 2.4 sensitivity).
+#include <cmath>
+#include <cstdlib>
+
+#include "stencil.hpp"
+
+namespace topo {
+
+// ----------------------------------------------------------------------------------
+// Per-solve tables: alpha_e in both precisions, 1 / sum_{e ∋ n} alpha_e per node.
+// ----------------------------------------------------------------------------------
+__global__ void k_alpha(int ne, const double* __restrict__ rho, double E0, double Emin,
+                        double p, double* __restrict__ a64, float* __restrict__ a32) {
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t b = blockIdx.y;
+    if (e >= (size_t)ne) return;
+    const double a = simp_alpha(rho[b * ne + e], E0, Emin, p);
+    if (a64) a64[b * ne + e] = a;
+    if (a32) a32[b * ne + e] = (float)a;
+}
+
+__global__ void k_winv(Grid g, const double* __restrict__ a64, double* __restrict__ w64,
+                       float* __restrict__ w32) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= g.n_nodes) return;
+    int i, j, k;
+    node_ijk(g, n, i, j, k);
+    const double s = node_alpha_sum(g, i, j, k, a64);
+    const double w = s > 0.0 ? 1.0 / s : 0.0;
+    if (w64) w64[n] = w;
+    if (w32) w32[n] = (float)w;
+}
+
+// ----------------------------------------------------------------------------------
+// Public apply: y_b = K(rho_b) x_b, Dirichlet rows and columns eliminated.
+// ----------------------------------------------------------------------------------
+template <int DIM, typename T>
+__global__ __launch_bounds__(kBlock) void k_apply(Grid g, const T* __restrict__ alpha,
+                                                  const T* __restrict__ K,
+                                                  const uint8_t* __restrict__ mask,
+                                                  const T* __restrict__ x, T* __restrict__ y) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= g.n_nodes) return;
+    const size_t b = blockIdx.y;
+    const T* xb = x + b * g.n_dofs;
+    T* yb = y + b * g.n_dofs;
+    const T* ab = alpha + b * g.n_elems;
+    int i, j, k;
+    node_ijk(g, n, i, j, k);
+    FetchMasked<T> f{xb, mask, g.n_nodes};
+    T out[DIM];
+    if constexpr (DIM == 2) node_apply2<T>(g, i, j, ab, K, f, out);
+    else node_apply3<T>(g, i, j, k, ab, K, f, out);
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+        const size_t idx = (size_t)c * g.n_nodes + n;
+        yb[idx] = mask[idx] ? T(0) : out[c];
+    }
+}
+
+// ----------------------------------------------------------------------------------
+// Jacobi-PCG.  Two kernels per iteration; scalars live on the device and every
+// global reduction is finished, in a fixed order, by the last block of the kernel
+// that produced the partial sums (no floating-point atomics, bitwise reproducible).
+//   k_pcg_apply : p_new = z + beta p_old (fused into the stencil), q = K p_new,
+//                 pq partials -> alpha = rz / pq
+//   k_pcg_update: x += alpha p, r -= alpha q, z = D^{-1} r, rz / rr partials
+//                 -> beta, convergence flag
+// ----------------------------------------------------------------------------------
+struct PcgState {
+    double alpha, beta, rz, rr, bb, tol2, pq;
+    int done;   // 0 running, 1 converged, 2 iteration limit, 3 breakdown
+    int iters;
+    int maxit;
+    unsigned counter;
+};
+
+template <int DIM, typename T>
+__global__ __launch_bounds__(kBlock) void k_pcg_init(Grid g, const T* __restrict__ b,
+                                                     const T* __restrict__ winv, T ik0, T ik1,
+                                                     T ik2, T* __restrict__ x, T* __restrict__ r,
+                                                     T* __restrict__ z, T* __restrict__ p,
+                                                     double* __restrict__ part, PcgState* st,
+                                                     double tol, int maxit) {
+    __shared__ double lds[32];
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    double v[2] = {0.0, 0.0};
+    if (n < g.n_nodes) {
+        const T ik[3] = {ik0, ik1, ik2};
+        const T w = winv[n];
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            const size_t i = (size_t)c * g.n_nodes + n;
+            const T bi = b[i];
+            const T zi = bi * w * ik[c];
+            x[i] = T(0);
+            r[i] = bi;
+            z[i] = zi;
+            p[i] = T(0);
+            v[0] += (double)bi * (double)zi;
+            v[1] += (double)bi * (double)bi;
+        }
+    }
+    block_reduce<2>(v, lds);
+    const int nb = gridDim.x;
+    if (threadIdx.x == 0) {
+        part[nb + blockIdx.x] = v[0];
+        part[2 * nb + blockIdx.x] = v[1];
+    }
+    if (last_block(&st->counter)) {
+        const double rz = block_sum_array(part + nb, nb, lds);
+        const double rr = block_sum_array(part + 2 * nb, nb, lds);
+        if (threadIdx.x == 0) {
+            st->rz = rz;
+            st->rr = rr;
+            st->bb = rr;
+            st->tol2 = tol * tol * rr;
+            st->beta = 0.0;
+            st->alpha = 0.0;
+            st->iters = 0;
+            st->maxit = maxit;
+            st->done = (rr == 0.0) ? 1 : (maxit <= 0 ? 2 : 0);
+        }
+    }
+}
+
+template <int DIM, typename T>
+__global__ __launch_bounds__(kBlock) void k_pcg_apply(Grid g, const T* __restrict__ alpha,
+                                                      const T* __restrict__ K,
+                                                      const uint8_t* __restrict__ mask,
+                                                      const T* __restrict__ z,
+                                                      const T* __restrict__ p_old,
+                                                      T* __restrict__ p_new, T* __restrict__ q,
+                                                      double* __restrict__ part, PcgState* st) {
+    if (st->done) return;
+    __shared__ double lds[16];
+    const T beta = (T)st->beta;
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    double v[1] = {0.0};
+    if (n < g.n_nodes) {
+        int i, j, k;
+        node_ijk(g, n, i, j, k);
+        FetchDirection<T> f{z, p_old, beta, g.n_nodes};
+        T out[DIM];
+        if constexpr (DIM == 2) node_apply2<T>(g, i, j, alpha, K, f, out);
+        else node_apply3<T>(g, i, j, k, alpha, K, f, out);
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            const size_t idx = (size_t)c * g.n_nodes + n;
+            const T pn = z[idx] + beta * p_old[idx];
+            const T qv = mask[idx] ? T(0) : out[c];
+            p_new[idx] = pn;
+            q[idx] = qv;
+            v[0] += (double)pn * (double)qv;
+        }
+    }
+    block_reduce<1>(v, lds);
+    if (threadIdx.x == 0) part[blockIdx.x] = v[0];
+    if (last_block(&st->counter)) {
+        const double pq = block_sum_array(part, gridDim.x, lds);
+        if (threadIdx.x == 0) {
+            st->pq = pq;
+            if (!(pq > 0.0) || !isfinite(pq)) st->done = 3;
+            else st->alpha = st->rz / pq;
+        }
+    }
+}
+
+template <int DIM, typename T>
+__global__ __launch_bounds__(kBlock) void k_pcg_update(Grid g, const T* __restrict__ winv,
+                                                       T ik0, T ik1, T ik2, T* __restrict__ x,
+                                                       T* __restrict__ r, T* __restrict__ z,
+                                                       const T* __restrict__ p,
+                                                       const T* __restrict__ q,
+                                                       double* __restrict__ part, PcgState* st) {
+    if (st->done) return;
+    __shared__ double lds[32];
+    const T a = (T)st->alpha;
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    double v[2] = {0.0, 0.0};
+    if (n < g.n_nodes) {
+        const T ik[3] = {ik0, ik1, ik2};
+        const T w = winv[n];
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            const size_t i = (size_t)c * g.n_nodes + n;
+            x[i] += a * p[i];
+            const T ri = r[i] - a * q[i];
+            const T zi = ri * w * ik[c];
+            r[i] = ri;
+            z[i] = zi;
+            v[0] += (double)ri * (double)zi;
+            v[1] += (double)ri * (double)ri;
+        }
+    }
+    block_reduce<2>(v, lds);
+    const int nb = gridDim.x;
+    if (threadIdx.x == 0) {
+        part[nb + blockIdx.x] = v[0];
+        part[2 * nb + blockIdx.x] = v[1];
+    }
+    if (last_block(&st->counter)) {
+        const double rz = block_sum_array(part + nb, nb, lds);
+        const double rr = block_sum_array(part + 2 * nb, nb, lds);
+        if (threadIdx.x == 0) {
+            const int it = st->iters + 1;
+            st->iters = it;
+            st->beta = rz / st->rz;
+            st->rz = rz;
+            st->rr = rr;
+            if (rr <= st->tol2) st->done = 1;
+            else if (it >= st->maxit) st->done = 2;
+            else if (!isfinite(rr)) st->done = 3;
+        }
+    }
+}
+
+// ----------------------------------------------------------------------------------
+// float64 residual r = f - K u over free DOFs (u zero on Dirichlet DOFs), with
+// ||r||^2, f^T u and u^T r reduced per field (blockIdx.y) into out[4*b .. 4*b+2].
+// ----------------------------------------------------------------------------------
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_residual(Grid g, const double* __restrict__ alpha,
+                                                     const double* __restrict__ K,
+                                                     const uint8_t* __restrict__ mask,
+                                                     const double* __restrict__ u,
+                                                     const double* __restrict__ f,
+                                                     double* __restrict__ r,
+                                                     double* __restrict__ part,
+                                                     double* __restrict__ out,
+                                                     unsigned* __restrict__ counters) {
+    __shared__ double lds[48];
+    const size_t b = blockIdx.y;
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    const double* ub = u + b * g.n_dofs;
+    const double* ab = alpha + b * g.n_elems;
+    double v[3] = {0.0, 0.0, 0.0};
+    if (n < g.n_nodes) {
+        int i, j, k;
+        node_ijk(g, n, i, j, k);
+        FetchPlain<double> fe{ub, g.n_nodes};
+        double o[DIM];
+        if constexpr (DIM == 2) node_apply2<double>(g, i, j, ab, K, fe, o);
+        else node_apply3<double>(g, i, j, k, ab, K, fe, o);
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            const size_t idx = (size_t)c * g.n_nodes + n;
+            const bool fixed = mask[idx] != 0;
+            const double fi = fixed ? 0.0 : f[idx];
+            const double ui = ub[idx];
+            const double ri = fixed ? 0.0 : fi - o[c];
+            if (r) r[b * g.n_dofs + idx] = ri;
+            v[0] += ri * ri;
+            v[1] += fi * ui;
+            v[2] += ui * ri;
+        }
+    }
+    block_reduce<3>(v, lds);
+    const int nb = gridDim.x;
+    double* pb = part + b * 3 * nb;
+    if (threadIdx.x == 0) {
+        pb[blockIdx.x] = v[0];
+        pb[nb + blockIdx.x] = v[1];
+        pb[2 * nb + blockIdx.x] = v[2];
+    }
+    // per-field ticket: the last block of this field's row reduces it
+    __shared__ bool is_last;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned t = atomicAdd(&counters[b], 1u);
+        is_last = (t == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (is_last) {
+        __threadfence();
+        const double s0 = block_sum_array(pb, nb, lds);
+        const double s1 = block_sum_array(pb + nb, nb, lds);
+        const double s2 = block_sum_array(pb + 2 * nb, nb, lds);
+        if (threadIdx.x == 0) {
+            out[4 * b + 0] = s0;
+            out[4 * b + 1] = s1;
+            out[4 * b + 2] = s2;
+            atomicExch(&counters[b], 0u);
+        }
+    }
+}
+
+// rhs of a correction solve: b = s * r (cast to the inner precision)
+template <typename T>
+__global__ void k_scale_cast(long long n, const double* __restrict__ r, double s, T* __restrict__ b) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = (T)(s * r[i]);
+}
+
+// u += s * d
+template <typename T>
+__global__ void k_correct(long long n, double* __restrict__ u, const T* __restrict__ d, double s) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) u[i] += s * (double)d[i];
+}
+
+// ----------------------------------------------------------------------------------
+// Element sensitivity dc_e = -alpha'(rho_e) u_e^T K_e u_e   (float64)
+// ----------------------------------------------------------------------------------
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_gradient(Grid g, const double* __restrict__ rho,
+                                                     const double* __restrict__ K,
+                                                     const double* __restrict__ u, double E0,
+                                                     double Emin, double p,
+                                                     double* __restrict__ dc) {
+    constexpr int NEN = 1 << DIM;
+    constexpr int NE = DIM * NEN;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= g.n_elems) return;
+    const int ex = e % g.nx;
+    const int t = e / g.nx;
+    const int ey = t % g.ny;
+    const int ez = t / g.ny;
+    double ue[NE];
+#pragma unroll
+    for (int a = 0; a < NEN; ++a) {
+        const int n = ((ez + (a >> 2)) * g.ny1 + (ey + ((a >> 1) & 1))) * g.nx1 + ex + (a & 1);
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) ue[DIM * a + c] = u[(size_t)c * g.n_nodes + n];
+    }
+    // K_e annihilates rigid translations, so removing the element's mean displacement
+    // leaves u_e^T K_e u_e unchanged and avoids cancellation on near-rigid elements.
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+        double m = 0.0;
+#pragma unroll
+        for (int a = 0; a < NEN; ++a) m += ue[DIM * a + c];
+        m *= 1.0 / NEN;
+#pragma unroll
+        for (int a = 0; a < NEN; ++a) ue[DIM * a + c] -= m;
+    }
+    double qf = 0.0;
+#pragma unroll
+    for (int i = 0; i < NE; ++i) {
+        double s = 0.0;
+#pragma unroll
+        for (int j = 0; j < NE; ++j) s += K[i * NE + j] * ue[j];
+        qf += ue[i] * s;
+    }
+    const double r = rho[e];
+    double dp;  // d(rho^p)/d rho
+    if (p == 3.0) dp = 3.0 * r * r;
+    else if (p == 1.0) dp = 1.0;
+    else if (p == 2.0) dp = 2.0 * r;
+    else dp = p * pow(r, p - 1.0);
+    dc[e] = -(E0 - Emin) * dp * qf;
+}
+
+// ----------------------------------------------------------------------------------
+// Host drivers
+// ----------------------------------------------------------------------------------
+struct HdmBufs {
+    double* a64;
+    float* a32;
+    double* w64;
+    float* w32;
+};
+
+static int launch_tables(Ctx* ctx, const Grid& g, const topo_mesh& m, const double* rho,
+                         int B, double* a64, float* a32, double* w64, float* w32,
+                         hipStream_t s) {
+    dim3 ga(grid_blocks(g.n_elems), B);
+    hipLaunchKernelGGL(k_alpha, ga, dim3(kBlock), 0, s, g.n_elems, rho, m.E0, m.Emin, m.penal,
+                       a64, a32);
+    TOPO_CHECK_LAUNCH();
+    if (w64 || w32) {
+        hipLaunchKernelGGL(k_winv, dim3(grid_blocks(g.n_nodes)), dim3(kBlock), 0, s, g, a64, w64, w32);
+        TOPO_CHECK_LAUNCH();
+    }
+    return TOPO_OK;
+}
+
+// Inner PCG solve K x = b in precision T to ||r||/||b|| <= tol (recursive residual).
+template <int DIM, typename T>
+struct PcgRun {
+    const T* alpha;
+    const T* K;
+    const uint8_t* mask;
+    const T* winv;
+    T ik[3];
+    T *b, *x, *r, *z, *p0, *p1, *q;
+    double* part;
+    PcgState* st;
+};
+
+template <int DIM, typename T>
+static int pcg_run(Ctx* ctx, const Grid& g, PcgRun<DIM, T>& w, double tol, int maxit,
+                   hipStream_t s, PcgState* result) {
+    const int nb = grid_blocks(g.n_nodes);
+    hipLaunchKernelGGL((k_pcg_init<DIM, T>), dim3(nb), dim3(kBlock), 0, s, g, w.b, w.winv,
+                       w.ik[0], w.ik[1], w.ik[2], w.x, w.r, w.z, w.p0, w.part, w.st, tol, maxit);
+    TOPO_CHECK_LAUNCH();
+    void* pin = nullptr;
+    int rc = pinned_host(ctx, 2 * sizeof(PcgState), &pin);
+    if (rc) return rc;
+    PcgState* hs = (PcgState*)pin;
+    hipEvent_t ev[2];
+    TOPO_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+    TOPO_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+    bool pending[2] = {false, false};
+    long long issued = 0;
+    int chunk = 4;
+    int slot = 0;
+    const long long cap = (long long)maxit + 4096;
+    while (true) {
+        for (int c = 0; c < chunk; ++c, ++issued) {
+            T* pold = (issued & 1) ? w.p1 : w.p0;
+            T* pnew = (issued & 1) ? w.p0 : w.p1;
+            hipLaunchKernelGGL((k_pcg_apply<DIM, T>), dim3(nb), dim3(kBlock), 0, s, g, w.alpha,
+                               w.K, w.mask, w.z, pold, pnew, w.q, w.part, w.st);
+            hipLaunchKernelGGL((k_pcg_update<DIM, T>), dim3(nb), dim3(kBlock), 0, s, g, w.winv,
+                               w.ik[0], w.ik[1], w.ik[2], w.x, w.r, w.z, pnew, w.q, w.part, w.st);
+        }
+        TOPO_CHECK_LAUNCH();
+        TOPO_HIP(hipMemcpyAsync(&hs[slot], w.st, sizeof(PcgState), hipMemcpyDeviceToHost, s));
+        TOPO_HIP(hipEventRecord(ev[slot], s));
+        pending[slot] = true;
+        const int other = slot ^ 1;
+        bool stop = false;
+        if (pending[other]) {
+            TOPO_HIP(hipEventSynchronize(ev[other]));
+            pending[other] = false;
+            stop = hs[other].done != 0;
+        }
+        if (stop || issued >= cap) break;
+        slot = other;
+        if (chunk < 64) chunk *= 2;
+    }
+    TOPO_HIP(hipStreamSynchronize(s));
+    TOPO_HIP(hipEventDestroy(ev[0]));
+    TOPO_HIP(hipEventDestroy(ev[1]));
+    TOPO_HIP(hipMemcpy(result, w.st, sizeof(PcgState), hipMemcpyDeviceToHost));
+    return TOPO_OK;
+}
+
+static double mixed_inner_tol() {
+    static double v = [] {
+        const char* e = std::getenv("TOPO_MIXED_INNER_TOL");
+        double t = e ? std::atof(e) : 0.0;
+        return t > 0.0 ? t : 1e-5;
+    }();
+    return v;
+}
+
+template <int DIM, typename T>
+static int hdm_solve_impl(Ctx* ctx, const topo_mesh& m, const Grid& g, const ElemTables* tb,
+                          const double* rho, const uint8_t* mask, const double* f, double* u,
+                          double rtol, int maxit, bool mixed, double* compliance,
+                          topo_info* info, hipStream_t s) {
+    const long long N = g.n_dofs;
+    const int nb = grid_blocks(g.n_nodes);
+    Arena ar;
+    double *a64, *w64, *r64, *part, *rout;
+    T *ta, *tw, *b, *x, *r, *z, *p0, *p1, *q;
+    float *a32 = nullptr, *w32 = nullptr;
+    PcgState* st;
+    unsigned* counters;
+    ar.take(&a64, g.n_elems);
+    ar.take(&w64, g.n_nodes);
+    if (mixed) {
+        ar.take(&a32, g.n_elems);
+        ar.take(&w32, g.n_nodes);
+    }
+    ar.take(&r64, N);
+    ar.take(&part, 3 * (size_t)nb);
+    ar.take(&rout, 4);
+    ar.take(&st, 1);
+    ar.take(&counters, 64);
+    ar.take(&b, N);
+    ar.take(&x, N);
+    ar.take(&r, N);
+    ar.take(&z, N);
+    ar.take(&p0, N);
+    ar.take(&p1, N);
+    ar.take(&q, N);
+    int rc = ar.commit(ctx, s);
+    if (rc) return rc;
+    TOPO_HIP(hipMemsetAsync(st, 0, sizeof(PcgState), s));
+    TOPO_HIP(hipMemsetAsync(counters, 0, 64 * sizeof(unsigned), s));
+    rc = launch_tables(ctx, g, m, rho, 1, a64, a32, w64, w32, s);
+    if (rc) return rc;
+    if constexpr (sizeof(T) == 4) {
+        ta = (T*)a32;
+        tw = (T*)w32;
+    } else {
+        ta = (T*)a64;
+        tw = (T*)w64;
+    }
+    PcgRun<DIM, T> w;
+    w.alpha = ta;
+    w.K = sizeof(T) == 4 ? (const T*)tb->K32 : (const T*)tb->K64;
+    w.mask = mask;
+    w.winv = tw;
+    for (int c = 0; c < 3; ++c) w.ik[c] = c < DIM ? (T)(1.0 / tb->diag[c]) : T(0);
+    w.b = b;
+    w.x = x;
+    w.r = r;
+    w.z = z;
+    w.p0 = p0;
+    w.p1 = p1;
+    w.q = q;
+    w.part = part;
+    w.st = st;
+
+    TOPO_HIP(hipMemsetAsync(u, 0, N * sizeof(double), s));
+    void* pin = nullptr;
+    auto residual = [&](double out[3]) -> int {
+        hipLaunchKernelGGL((k_residual<DIM>), dim3(nb, 1), dim3(kBlock), 0, s, g, a64, tb->K64,
+                           mask, u, f, r64, part, rout, counters);
+        TOPO_CHECK_LAUNCH();
+        int rc2 = pinned_host(ctx, 4 * sizeof(double) + 2 * sizeof(PcgState), &pin);
+        if (rc2) return rc2;
+        double* h = (double*)((char*)pin + 2 * sizeof(PcgState));
+        TOPO_HIP(hipMemcpyAsync(h, rout, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+        TOPO_HIP(hipStreamSynchronize(s));
+        out[0] = h[0];
+        out[1] = h[1];
+        out[2] = h[2];
+        return TOPO_OK;
+    };
+    double res[3];
+    rc = residual(res);
+    if (rc) return rc;
+    const double nf = std::sqrt(res[0]);
+    int total = 0, outer = 0, status = TOPO_OK;
+    double rr = res[0], rr_prev = INFINITY;
+    const int max_outer = 40;
+    while (true) {
+        const double rel = nf > 0.0 ? std::sqrt(rr) / nf : 0.0;
+        if (rel <= rtol) break;
+        if (total >= maxit || outer >= max_outer) {
+            status = set_error(ctx, TOPO_ENOCONV, "no convergence: rel. residual %.3e after %d iterations",
+                               rel, total);
+            break;
+        }
+        if (outer > 0 && !(rr < 0.9 * rr_prev)) {
+            status = set_error(ctx, TOPO_ENOCONV, "refinement stagnated at rel. residual %.3e", rel);
+            break;
+        }
+        const double nr = std::sqrt(rr);
+        double tol_in = 0.5 * rtol * nf / nr;
+        if (mixed) tol_in = std::max(tol_in, mixed_inner_tol());
+        tol_in = std::max(tol_in, 1e-15);
+        const int bl = grid_blocks(N);
+        hipLaunchKernelGGL((k_scale_cast<T>), dim3(bl), dim3(kBlock), 0, s, N, r64, 1.0 / nr, b);
+        TOPO_CHECK_LAUNCH();
+        PcgState fin;
+        rc = pcg_run<DIM, T>(ctx, g, w, tol_in, maxit - total, s, &fin);
+        if (rc) return rc;
+        total += fin.iters;
+        if (fin.done == 3 && fin.iters == 0) {
+            status = set_error(ctx, TOPO_ENOTSPD, "CG breakdown: p^T K p <= 0");
+            break;
+        }
+        hipLaunchKernelGGL((k_correct<T>), dim3(bl), dim3(kBlock), 0, s, N, u, x, nr);
+        TOPO_CHECK_LAUNCH();
+        ++outer;
+        rr_prev = rr;
+        rc = residual(res);
+        if (rc) return rc;
+        rr = res[0];
+        if (fin.done == 3 && !(rr < rr_prev)) {
+            status = set_error(ctx, TOPO_ENOTSPD, "CG breakdown: p^T K p <= 0");
+            break;
+        }
+    }
+    if (info) {
+        info->iters = total;
+        info->refinements = outer;
+        info->rel_resid = nf > 0.0 ? std::sqrt(rr) / nf : 0.0;
+        info->compliance_raw = res[1];
+        info->compliance_corr = res[1] + res[2];
+    }
+    if (compliance) *compliance = res[1] + res[2];
+    return status;
+}
+
+}  // namespace topo
+
+using namespace topo;
+
+extern "C" {
+
+int topo_apply(topo_ctx* ctx, const topo_mesh* mesh, const double* rho, const uint8_t* mask,
+               const void* x, void* y, int32_t B, int32_t prec, void* stream) {
+    if (!ctx) return TOPO_EINVAL;
+    int rc = validate_mesh(ctx, mesh);
+    if (rc) return rc;
+    if (!rho || !mask || !x || !y) return set_error(ctx, TOPO_EINVAL, "null pointer argument");
+    if (B < 1) return set_error(ctx, TOPO_EINVAL, "B must be >= 1");
+    if (prec != TOPO_FP64 && prec != TOPO_MIXED) return set_error(ctx, TOPO_EINVAL, "bad precision");
+    TOPO_HIP(hipSetDevice(ctx->device));
+    const Grid g = make_grid(*mesh);
+    const ElemTables* tb = get_tables(ctx, *mesh);
+    if (!tb) return set_error(ctx, TOPO_EDEVICE, "element table upload failed");
+    hipStream_t s = (hipStream_t)stream;
+    Arena ar;
+    double* a64 = nullptr;
+    float* a32 = nullptr;
+    if (prec == TOPO_FP64) ar.take(&a64, (size_t)B * g.n_elems);
+    else ar.take(&a32, (size_t)B * g.n_elems);
+    rc = ar.commit(ctx, s);
+    if (rc) return rc;
+    rc = launch_tables(ctx, g, *mesh, rho, B, a64, a32, nullptr, nullptr, s);
+    if (rc) return rc;
+    dim3 grid(grid_blocks(g.n_nodes), B);
+    if (prec == TOPO_FP64) {
+        if (g.dim == 2)
+            hipLaunchKernelGGL((k_apply<2, double>), grid, dim3(kBlock), 0, s, g, a64, tb->K64, mask,
+                               (const double*)x, (double*)y);
+        else
+            hipLaunchKernelGGL((k_apply<3, double>), grid, dim3(kBlock), 0, s, g, a64, tb->K64, mask,
+                               (const double*)x, (double*)y);
+    } else {
+        if (g.dim == 2)
+            hipLaunchKernelGGL((k_apply<2, float>), grid, dim3(kBlock), 0, s, g, a32, tb->K32, mask,
+                               (const float*)x, (float*)y);
+        else
+            hipLaunchKernelGGL((k_apply<3, float>), grid, dim3(kBlock), 0, s, g, a32, tb->K32, mask,
+                               (const float*)x, (float*)y);
+    }
+    TOPO_CHECK_LAUNCH();
+    return TOPO_OK;
+}
+
+int topo_hdm_solve(topo_ctx* ctx, const topo_mesh* mesh, const double* rho, const uint8_t* mask,
+                   const double* f, double* u, double rtol, int32_t maxit, int32_t prec,
+                   double* compliance, topo_info* info, void* stream) {
+    if (!ctx) return TOPO_EINVAL;
+    int rc = validate_mesh(ctx, mesh);
+    if (rc) return rc;
+    if (!rho || !mask || !f || !u) return set_error(ctx, TOPO_EINVAL, "null pointer argument");
+    if (!(rtol > 0.0) || !(rtol < 1.0)) return set_error(ctx, TOPO_EINVAL, "rtol must lie in (0, 1)");
+    if (maxit < 1) return set_error(ctx, TOPO_EINVAL, "maxit must be >= 1");
+    if (prec != TOPO_FP64 && prec != TOPO_MIXED) return set_error(ctx, TOPO_EINVAL, "bad precision");
+    TOPO_HIP(hipSetDevice(ctx->device));
+    const Grid g = make_grid(*mesh);
+    const ElemTables* tb = get_tables(ctx, *mesh);
+    if (!tb) return set_error(ctx, TOPO_EDEVICE, "element table upload failed");
+    hipStream_t s = (hipStream_t)stream;
+    const bool mixed = prec == TOPO_MIXED;
+    if (g.dim == 2) {
+        if (mixed)
+            return hdm_solve_impl<2, float>(ctx, *mesh, g, tb, rho, mask, f, u, rtol, maxit, true,
+                                            compliance, info, s);
+        return hdm_solve_impl<2, double>(ctx, *mesh, g, tb, rho, mask, f, u, rtol, maxit, false,
+                                         compliance, info, s);
+    }
+    if (mixed)
+        return hdm_solve_impl<3, float>(ctx, *mesh, g, tb, rho, mask, f, u, rtol, maxit, true,
+                                        compliance, info, s);
+    return hdm_solve_impl<3, double>(ctx, *mesh, g, tb, rho, mask, f, u, rtol, maxit, false,
+                                     compliance, info, s);
+}
+
+int topo_hdm_gradient(topo_ctx* ctx, const topo_mesh* mesh, const double* rho, const double* u,
+                      double* dc, void* stream) {
+    if (!ctx) return TOPO_EINVAL;
+    int rc = validate_mesh(ctx, mesh);
+    if (rc) return rc;
+    if (!rho || !u || !dc) return set_error(ctx, TOPO_EINVAL, "null pointer argument");
+    TOPO_HIP(hipSetDevice(ctx->device));
+    const Grid g = make_grid(*mesh);
+    const ElemTables* tb = get_tables(ctx, *mesh);
+    if (!tb) return set_error(ctx, TOPO_EDEVICE, "element table upload failed");
+    hipStream_t s = (hipStream_t)stream;
+    if (g.dim == 2)
+        hipLaunchKernelGGL((k_gradient<2>), dim3(grid_blocks(g.n_elems)), dim3(kBlock), 0, s, g, rho,
+                           tb->K64, u, mesh->E0, mesh->Emin, mesh->penal, dc);
+    else
+        hipLaunchKernelGGL((k_gradient<3>), dim3(grid_blocks(g.n_elems)), dim3(kBlock), 0, s, g, rho,
+                           tb->K64, u, mesh->E0, mesh->Emin, mesh->penal, dc);
+    TOPO_CHECK_LAUNCH();
+    return TOPO_OK;
+}
+
+}  // extern "C"
+
+// Entry points shared with the ROM translation unit.
+namespace topo {
+
+int residual_fp64(Ctx* ctx, const Grid& g, const ElemTables* tb, const double* alpha64,
+                  const uint8_t* mask, const double* u, const double* f, double* r, int B,
+                  double* part, double* out, unsigned* counters, hipStream_t s) {
+    const int nb = grid_blocks(g.n_nodes);
+    if (g.dim == 2)
+        hipLaunchKernelGGL((k_residual<2>), dim3(nb, B), dim3(kBlock), 0, s, g, alpha64, tb->K64,
+                           mask, u, f, r, part, out, counters);
+    else
+        hipLaunchKernelGGL((k_residual<3>), dim3(nb, B), dim3(kBlock), 0, s, g, alpha64, tb->K64,
+                           mask, u, f, r, part, out, counters);
+    TOPO_CHECK_LAUNCH();
+    return TOPO_OK;
+}
+
+int alpha_tables(Ctx* ctx, const Grid& g, const topo_mesh& m, const double* rho, int B,
+                 double* a64, float* a32, hipStream_t s) {
+    return launch_tables(ctx, g, m, rho, B, a64, a32, nullptr, nullptr, s);
+}
+
+}  // namespace topo

@@ -1,0 +1,726 @@
+// Reduced-order model on the device (Sec. 3.1, 3.3, 3.4):
+//   K_hat[b] = sum_e alpha_be (P_e^T Phi)^T K_e (P_e^T Phi)  -- per-element contraction
+//              on the matrix cores (v_mfma 16x16x4, f32 or f64)
+//   f_hat    = Phi^T f
+//   y_hat    = K_hat^{-1} f_hat (float64 Cholesky), J_k = f_hat^T y_hat
+//   ||f - K(rho) Phi y_hat||  with optional float64 reduced refinement.
+#include <algorithm>
+#include <cmath>
+
+#include "stencil.hpp"
+
+namespace topo {
+
+int residual_fp64(Ctx* ctx, const Grid& g, const ElemTables* tb, const double* alpha64,
+                  const uint8_t* mask, const double* u, const double* f, double* r, int B,
+                  double* part, double* out, unsigned* counters, hipStream_t s);
+int alpha_tables(Ctx* ctx, const Grid& g, const topo_mesh& m, const double* rho, int B,
+                 double* a64, float* a32, hipStream_t s);
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Mfma;
+// Both 16x16x4 instructions take A[i][kk] from lane i + 16 kk and B[kk][j] from lane
+// j + 16 kk; they differ in where output element D[i][j] lands (j = lane % 16 in both):
+// f32 keeps four consecutive rows per lane, f64 interleaves rows with stride 4.
+template <> struct Mfma<float> {
+    typedef f32x4 acc_t;
+    static __device__ __forceinline__ acc_t run(float a, float b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+template <> struct Mfma<double> {
+    typedef f64x4 acc_t;
+    static __device__ __forceinline__ acc_t run(double a, double b, acc_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lane, int v) { return (lane >> 4) + 4 * v; }
+};
+
+// ----------------------------------------------------------------------------------
+// K_hat contraction.
+//   grid.x : element chunks (contiguous element ranges)
+//   grid.y : density fields b
+//   grid.z : groups of upper-triangle 16x16 tile pairs (I <= J)
+// Per sub-chunk of EC elements the block stages, in LDS, the element rows of the
+// basis A = P_e^T Phi (Dirichlet rows zeroed, columns zero-padded to KP) and
+// W = K_e A (element-local, density independent).  Each wave then owns TPW tile pairs
+// and accumulates K_hat_IJ += A_I^T (alpha W_J) over the rows with the matrix cores,
+// 4 rows per instruction.  Accumulators are flushed to float64 registers after every
+// sub-chunk, and each block writes one float64 partial per tile entry; a second
+// kernel sums the partials over chunks in a fixed order (deterministic).
+// ----------------------------------------------------------------------------------
+constexpr int TPW = 8;       // tile pairs per wave
+constexpr int WAVES = 4;     // waves per block
+constexpr int PAIRS_PER_GROUP = TPW * WAVES;
+
+__device__ __forceinline__ void pair_of(int p, int kt, int& I, int& J) {
+    // enumerate (I, J), I <= J, row by row
+    int i = 0;
+    while (p >= kt - i) {
+        p -= kt - i;
+        ++i;
+    }
+    I = i;
+    J = i + p;
+}
+
+template <int DIM, typename TP, typename TC>
+__global__ __launch_bounds__(WAVES * 64) void k_rom_contract(
+    Grid g, const TP* __restrict__ phi, int k, int ldphi, int KP, int LS,
+    const uint8_t* __restrict__ mask, const TC* __restrict__ alpha /*[B][Ne]*/,
+    const TC* __restrict__ Ke, int epw, int ec, double* __restrict__ partials) {
+    constexpr int NEN = 1 << DIM;
+    constexpr int NE = DIM * NEN;
+    extern __shared__ __align__(16) unsigned char smem[];
+    TC* sK = (TC*)smem;                       // [NE*NE]
+    TC* sA = sK + NE * NE;                    // [ec*NE][LS]
+    TC* sW = sA + (size_t)ec * NE * LS;       // [ec*NE][LS]
+    TC* sAl = sW + (size_t)ec * NE * LS;      // [ec]
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int b = blockIdx.y;
+    const int kt = KP / 16;
+    const int npairs = kt * (kt + 1) / 2;
+    const int e_begin = blockIdx.x * epw;
+    const int e_end = min(e_begin + epw, g.n_elems);
+    const TC* alpha_b = alpha + (size_t)b * g.n_elems;
+
+    for (int i = tid; i < NE * NE; i += blockDim.x) sK[i] = Ke[i];
+
+    // this wave's tile pairs
+    int myI[TPW], myJ[TPW];
+    int nmine = 0;
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+        const int p = blockIdx.z * PAIRS_PER_GROUP + wave + WAVES * t;
+        if (p < npairs) {
+            pair_of(p, kt, myI[t], myJ[t]);
+            nmine = t + 1;
+        } else {
+            myI[t] = myJ[t] = 0;
+        }
+    }
+    typedef typename Mfma<TC>::acc_t acc_t;
+    double acc64[TPW][4];
+#pragma unroll
+    for (int t = 0; t < TPW; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc64[t][v] = 0.0;
+
+    const int rows_full = ec * NE;
+    for (int e0 = e_begin; e0 < e_end; e0 += ec) {
+        const int ne_here = min(ec, e_end - e0);
+        const int rows = ne_here * NE;
+        __syncthreads();  // previous sub-chunk fully consumed
+        // stage A: rows (element, local dof), columns 0..KP-1 (zero beyond k)
+        for (int idx = tid; idx < rows_full * KP; idx += blockDim.x) {
+            const int row = idx / KP;
+            const int col = idx - row * KP;
+            TC v = TC(0);
+            if (row < rows && col < k) {
+                const int el = e0 + row / NE;
+                const int l = row % NE;
+                const int a = l / DIM, c = l % DIM;
+                const int ex = el % g.nx;
+                const int t2 = el / g.nx;
+                const int ey = t2 % g.ny;
+                const int ez = t2 / g.ny;
+                const int n = ((ez + (a >> 2)) * g.ny1 + (ey + ((a >> 1) & 1))) * g.nx1 + ex + (a & 1);
+                const size_t dof = (size_t)c * g.n_nodes + n;
+                if (!mask[dof]) v = (TC)phi[dof * (size_t)ldphi + col];
+            }
+            sA[(size_t)row * LS + col] = v;
+        }
+        for (int i = tid; i < ec; i += blockDim.x) sAl[i] = i < ne_here ? alpha_b[e0 + i] : TC(0);
+        __syncthreads();
+        // K_e annihilates rigid translations: subtract each element's mean per
+        // displacement component and column.  (A - T)^T K_e (A - T) = A^T K_e A exactly,
+        // with far less cancellation for smooth basis vectors.
+        for (int idx = tid; idx < ec * DIM * KP; idx += blockDim.x) {
+            const int col = idx % KP;
+            const int ec_c = idx / KP;
+            const int el = ec_c / DIM, c = ec_c % DIM;
+            TC* base = sA + (size_t)el * NE * LS + col;
+            TC m = TC(0);
+#pragma unroll
+            for (int a = 0; a < NEN; ++a) m += base[(size_t)(DIM * a + c) * LS];
+            m *= TC(1) / TC(NEN);
+#pragma unroll
+            for (int a = 0; a < NEN; ++a) base[(size_t)(DIM * a + c) * LS] -= m;
+        }
+        __syncthreads();
+        // W = K_e A per element (vector ALU)
+        for (int idx = tid; idx < rows_full * KP; idx += blockDim.x) {
+            const int row = idx / KP;
+            const int col = idx - row * KP;
+            const int el = row / NE;
+            const int l = row - el * NE;
+            const TC* Arow = sA + (size_t)el * NE * LS + col;
+            const TC* Krow = sK + l * NE;
+            TC s = TC(0);
+#pragma unroll
+            for (int m = 0; m < NE; ++m) s += Krow[m] * Arow[(size_t)m * LS];
+            sW[(size_t)row * LS + col] = s * sAl[el];
+        }
+        __syncthreads();
+        // matrix-core accumulation over the rows of this sub-chunk
+        acc_t acc[TPW];
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) acc[t] = acc_t{0, 0, 0, 0};
+        const int rsub = lane >> 4;   // row inside the 4-row step
+        const int csub = lane & 15;   // column inside the tile
+        for (int r0 = 0; r0 < rows; r0 += 4) {
+            const TC* arow = sA + (size_t)(r0 + rsub) * LS + csub;
+            const TC* wrow = sW + (size_t)(r0 + rsub) * LS + csub;
+#pragma unroll
+            for (int t = 0; t < TPW; ++t) {
+                if (t < nmine) {
+                    const TC av = arow[myI[t] * 16];
+                    const TC bv = wrow[myJ[t] * 16];
+                    acc[t] = Mfma<TC>::run(av, bv, acc[t]);
+                }
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < TPW; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc64[t][v] += (double)acc[t][v];
+    }
+    // write this block's partial tiles: partial[(b, chunk, pair)][16*16]
+    const size_t nchunks = gridDim.x;
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+        if (t < nmine) {
+            const int p = blockIdx.z * PAIRS_PER_GROUP + wave + WAVES * t;
+            double* dst = partials + (((size_t)b * nchunks + blockIdx.x) * npairs + p) * 256;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = Mfma<TC>::row(lane, v);  // row of the 16x16 output tile
+                const int j = lane & 15;            // column
+                dst[i * 16 + j] = acc64[t][v];
+            }
+        }
+    }
+}
+
+// Sum partial tiles over chunks (fixed order) and write the symmetric K_hat.
+__global__ void k_rom_reduce(int k, int KP, int nchunks, int B, const double* __restrict__ partials,
+                             double* __restrict__ Khat) {
+    const int kt = KP / 16;
+    const int npairs = kt * (kt + 1) / 2;
+    const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t total = (size_t)B * npairs * 256;
+    if (gid >= total) return;
+    const int e = gid % 256;
+    const size_t bp = gid / 256;
+    const int p = bp % npairs;
+    const int b = bp / npairs;
+    int I, J;
+    pair_of(p, kt, I, J);
+    const int i = I * 16 + e / 16;
+    const int j = J * 16 + e % 16;
+    if (i >= k || j >= k || i > j) return;  // keep the upper triangle only
+    double s = 0.0;
+    for (int c = 0; c < nchunks; ++c) s += partials[(((size_t)b * nchunks + c) * npairs + p) * 256 + e];
+    double* Kb = Khat + (size_t)b * k * k;
+    Kb[(size_t)i * k + j] = s;
+    Kb[(size_t)j * k + i] = s;
+}
+
+// ----------------------------------------------------------------------------------
+// out[b][j] = sum_i Phi[i][j] v[b][i] over free rows i (float64 accumulation).
+// grid.x: row chunks, grid.y: b.  Partials [b][chunk][k], reduced by k_colsum_reduce.
+// ----------------------------------------------------------------------------------
+template <typename TP>
+__global__ __launch_bounds__(256) void k_phit_v(long long nrows, const TP* __restrict__ phi, int k,
+                                                int ldphi, const uint8_t* __restrict__ mask,
+                                                const double* __restrict__ v, long long vstride,
+                                                int rows_per_chunk, double* __restrict__ partials) {
+    __shared__ double red[4][64];
+    const int lane = threadIdx.x & 63;
+    const int rg = threadIdx.x >> 6;
+    const int b = blockIdx.y;
+    const long long r0 = (long long)blockIdx.x * rows_per_chunk;
+    const long long r1 = min(r0 + rows_per_chunk, nrows);
+    const double* vb = v + (size_t)b * vstride;
+    double* dst = partials + ((size_t)b * gridDim.x + blockIdx.x) * k;
+    for (int c0 = 0; c0 < k; c0 += 64) {
+        const int col = c0 + lane;
+        double s = 0.0;
+        if (col < k) {
+            for (long long i = r0 + rg; i < r1; i += 4) {
+                if (mask[i]) continue;
+                s += (double)phi[(size_t)i * ldphi + col] * vb[i];
+            }
+        }
+        red[rg][lane] = s;
+        __syncthreads();
+        if (rg == 0 && col < k) dst[col] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+        __syncthreads();
+    }
+}
+
+__global__ void k_colsum_reduce(int k, int nchunks, int B, const double* __restrict__ partials,
+                                double* __restrict__ out) {
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= B * k) return;
+    const int b = gid / k, j = gid % k;
+    double s = 0.0;
+    for (int c = 0; c < nchunks; ++c) s += partials[((size_t)b * nchunks + c) * k + j];
+    out[gid] = s;
+}
+
+// u[b][i] = Phi[i][:] . y[b][:] on free rows, 0 on Dirichlet rows (float64 accumulation)
+template <typename TP>
+__global__ __launch_bounds__(256) void k_phi_y(long long nrows, const TP* __restrict__ phi, int k,
+                                               int ldphi, const uint8_t* __restrict__ mask,
+                                               const double* __restrict__ y, double* __restrict__ u) {
+    extern __shared__ double sy[];
+    const int b = blockIdx.y;
+    for (int j = threadIdx.x; j < k; j += blockDim.x) sy[j] = y[(size_t)b * k + j];
+    __syncthreads();
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nrows) return;
+    double s = 0.0;
+    if (!mask[i]) {
+        const TP* row = phi + (size_t)i * ldphi;
+        for (int j = 0; j < k; ++j) s += (double)row[j] * sy[j];
+    }
+    u[(size_t)b * nrows + i] = s;
+}
+
+// ----------------------------------------------------------------------------------
+// Batched float64 Cholesky K = L L^T (one block per matrix), in LDS when it fits,
+// otherwise in the global workspace copy.  status[b] = TOPO_ENOTSPD on a pivot that
+// is not positive relative to the original diagonal.
+// ----------------------------------------------------------------------------------
+constexpr int CHOL_LDS_MAX_K = 64;
+
+__global__ __launch_bounds__(256) void k_chol(int k, const double* __restrict__ Khat,
+                                              double* __restrict__ Lout, int* __restrict__ status) {
+    __shared__ double sm[CHOL_LDS_MAX_K * CHOL_LDS_MAX_K];
+    __shared__ int bad;
+    const int b = blockIdx.x;
+    const double* Kb = Khat + (size_t)b * k * k;
+    double* Lg = Lout + (size_t)b * k * k;
+    double* A = (k <= CHOL_LDS_MAX_K) ? sm : Lg;
+    for (int i = threadIdx.x; i < k * k; i += blockDim.x) {
+        const int r = i / k, c = i % k;
+        A[i] = (c <= r) ? Kb[(size_t)r * k + c] : 0.0;  // lower triangle
+    }
+    if (threadIdx.x == 0) bad = 0;
+    __syncthreads();
+    double maxdiag = 0.0;
+    for (int j = 0; j < k; ++j) maxdiag = fmax(maxdiag, fabs(A[j * k + j]));
+    const double tiny = 64.0 * k * 2.220446049250313e-16 * maxdiag;
+    for (int j = 0; j < k; ++j) {
+        if (threadIdx.x == 0) {
+            const double d = A[j * k + j];
+            if (!(d > tiny) || !isfinite(d)) {
+                bad = 1;
+                A[j * k + j] = 1.0;
+            } else {
+                A[j * k + j] = sqrt(d);
+            }
+        }
+        __syncthreads();
+        const double ljj = A[j * k + j];
+        for (int i = j + 1 + threadIdx.x; i < k; i += blockDim.x) A[i * k + j] /= ljj;
+        __syncthreads();
+        // trailing update of the lower triangle: A[i][l] -= A[i][j] A[l][j], j < l <= i
+        const int m = k - j - 1;
+        const int cnt = m * (m + 1) / 2;
+        for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
+            // t -> (i, l) with l <= i inside the trailing block
+            int ii = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+            while ((ii + 1) * (ii + 2) / 2 <= t) ++ii;
+            while (ii * (ii + 1) / 2 > t) --ii;
+            const int ll = t - ii * (ii + 1) / 2;
+            const int i = j + 1 + ii, l = j + 1 + ll;
+            A[i * k + l] -= A[i * k + j] * A[l * k + j];
+        }
+        __syncthreads();
+    }
+    if (A != Lg)
+        for (int i = threadIdx.x; i < k * k; i += blockDim.x) Lg[i] = A[i];
+    if (threadIdx.x == 0) status[b] = bad ? TOPO_ENOTSPD : 0;
+}
+
+// x[b] (+)= L^{-T} L^{-1} rhs[b]; optionally J[b] = c^T x[b]
+__global__ __launch_bounds__(256) void k_chol_solve(int k, const double* __restrict__ L,
+                                                    const double* __restrict__ rhs, long long rstride,
+                                                    double* __restrict__ x, int accumulate,
+                                                    const double* __restrict__ stepw,
+                                                    const double* __restrict__ cvec,
+                                                    double* __restrict__ J) {
+    extern __shared__ double sv[];  // [k]
+    __shared__ double lds[16];
+    const int b = blockIdx.x;
+    const double* Lb = L + (size_t)b * k * k;
+    const double* rb = rhs + (size_t)b * rstride;
+    for (int i = threadIdx.x; i < k; i += blockDim.x) sv[i] = rb[i];
+    __syncthreads();
+    // forward: L w = rhs (column-oriented)
+    for (int j = 0; j < k; ++j) {
+        if (threadIdx.x == 0) sv[j] /= Lb[(size_t)j * k + j];
+        __syncthreads();
+        const double wj = sv[j];
+        for (int i = j + 1 + threadIdx.x; i < k; i += blockDim.x) sv[i] -= Lb[(size_t)i * k + j] * wj;
+        __syncthreads();
+    }
+    // backward: L^T y = w
+    for (int j = k - 1; j >= 0; --j) {
+        if (threadIdx.x == 0) sv[j] /= Lb[(size_t)j * k + j];
+        __syncthreads();
+        const double yj = sv[j];
+        for (int i = threadIdx.x; i < j; i += blockDim.x) sv[i] -= Lb[(size_t)j * k + i] * yj;
+        __syncthreads();
+    }
+    double* xb = x + (size_t)b * k;
+    const double w = stepw ? stepw[b] : 1.0;
+    for (int i = threadIdx.x; i < k; i += blockDim.x) xb[i] = accumulate ? xb[i] + w * sv[i] : sv[i];
+    if (J) {
+        __syncthreads();
+        double s[1] = {0.0};
+        for (int i = threadIdx.x; i < k; i += blockDim.x) s[0] += cvec[i] * xb[i];
+        block_reduce<1>(s, lds);
+        if (threadIdx.x == 0) J[b] = s[0];
+    }
+}
+
+// resnorm[b] = sqrt(sum r^2), Jk[b] = f^T u  from the residual kernel's reductions
+__global__ void k_estimate_out(int B, const double* __restrict__ out, double* __restrict__ resnorm,
+                               double* __restrict__ Jk) {
+    for (int b = threadIdx.x; b < B; b += blockDim.x) {
+        resnorm[b] = sqrt(out[4 * b]);
+        if (Jk) Jk[b] = out[4 * b + 1];
+    }
+}
+
+// g2[b] = ||v[b]||^2 (one block per row, fixed order)
+__global__ void k_sqnorm_rows(int k, const double* __restrict__ v, double* __restrict__ g2) {
+    __shared__ double lds[16];
+    const int b = blockIdx.x;
+    double s[1] = {0.0};
+    for (int j = threadIdx.x; j < k; j += blockDim.x) s[0] += v[(size_t)b * k + j] * v[(size_t)b * k + j];
+    block_reduce<1>(s, lds);
+    if (threadIdx.x == 0) g2[b] = s[0];
+}
+
+// y[b] = ysave[b] where revert[b] != 0
+__global__ void k_restore_rows(int k, const int* __restrict__ revert, const double* __restrict__ ysave,
+                               double* __restrict__ y) {
+    const int b = blockIdx.x;
+    if (!revert[b]) return;
+    for (int j = threadIdx.x; j < k; j += blockDim.x) y[(size_t)b * k + j] = ysave[(size_t)b * k + j];
+}
+
+// ----------------------------------------------------------------------------------
+// Host side
+// ----------------------------------------------------------------------------------
+static int check_basis(Ctx* ctx, const Grid& g, const void* phi, int k, int ldphi) {
+    if (!phi) return set_error(ctx, TOPO_EINVAL, "phi is NULL");
+    if (k < 1) return set_error(ctx, TOPO_EINVAL, "k must be >= 1");
+    if ((long long)k > g.n_dofs) return set_error(ctx, TOPO_EINVAL, "k exceeds the number of DOFs");
+    if (ldphi < k) return set_error(ctx, TOPO_EINVAL, "ldphi < k");
+    return TOPO_OK;
+}
+
+static int phit_v(Ctx* ctx, const Grid& g, const void* phi, int fp32, int k, int ldphi,
+                  const uint8_t* mask, const double* v, long long vstride, int B, double* out,
+                  double* partials, int nchunks, hipStream_t s) {
+    const long long nrows = g.n_dofs;
+    const int rpc = (int)((nrows + nchunks - 1) / nchunks);
+    if (fp32)
+        hipLaunchKernelGGL((k_phit_v<float>), dim3(nchunks, B), dim3(256), 0, s, nrows,
+                           (const float*)phi, k, ldphi, mask, v, vstride, rpc, partials);
+    else
+        hipLaunchKernelGGL((k_phit_v<double>), dim3(nchunks, B), dim3(256), 0, s, nrows,
+                           (const double*)phi, k, ldphi, mask, v, vstride, rpc, partials);
+    TOPO_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_colsum_reduce, dim3(grid_blocks((long long)B * k)), dim3(kBlock), 0, s, k,
+                       nchunks, B, partials, out);
+    TOPO_CHECK_LAUNCH();
+    return TOPO_OK;
+}
+
+static int phit_chunks(const Grid& g) {
+    long long c = g.n_dofs / 2048;
+    return (int)std::max(1LL, std::min(c, 2048LL));
+}
+
+struct ContractPlan {
+    int KP, LS, kt, npairs, groups, ec, epw, nchunks;
+    size_t lds_bytes;
+};
+
+static ContractPlan plan_contract(const Grid& g, int k, int B, bool f64, int cu) {
+    ContractPlan p;
+    p.KP = (k + 15) / 16 * 16;
+    p.LS = p.KP + ((p.KP % 32 == 0) ? 4 : 0);
+    p.kt = p.KP / 16;
+    p.npairs = p.kt * (p.kt + 1) / 2;
+    p.groups = (p.npairs + PAIRS_PER_GROUP - 1) / PAIRS_PER_GROUP;
+    const int ne = g.dim * (1 << g.dim);
+    const size_t esz = f64 ? 8 : 4;
+    const size_t budget = 64 * 1024;
+    const size_t fixed = (size_t)ne * ne * esz;
+    int ec = (int)((budget - fixed) / (2 * (size_t)ne * p.LS * esz + esz));
+    ec = std::max(1, std::min(ec, 16));
+    p.ec = ec;
+    // aim at ~8 blocks per CU overall
+    const long long want_blocks = 8LL * cu;
+    long long per_field = std::max(1LL, want_blocks / ((long long)B * p.groups));
+    long long epw = (g.n_elems + per_field - 1) / per_field;
+    epw = std::max<long long>(epw, ec);
+    epw = (epw + ec - 1) / ec * ec;
+    p.epw = (int)epw;
+    p.nchunks = (int)((g.n_elems + epw - 1) / epw);
+    p.lds_bytes = fixed + 2 * (size_t)ec * ne * p.LS * esz + (size_t)ec * esz;
+    return p;
+}
+
+template <int DIM, typename TP, typename TC>
+static int launch_contract(Ctx* ctx, const Grid& g, const ContractPlan& p, const TP* phi, int k,
+                           int ldphi, const uint8_t* mask, const TC* alpha, const TC* Ke, int B,
+                           double* partials, hipStream_t s) {
+    auto kern = k_rom_contract<DIM, TP, TC>;
+    TOPO_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)p.lds_bytes));
+    hipLaunchKernelGGL(kern, dim3(p.nchunks, B, p.groups), dim3(WAVES * 64), p.lds_bytes, s, g, phi,
+                       k, ldphi, p.KP, p.LS, mask, alpha, Ke, p.epw, p.ec, partials);
+    TOPO_CHECK_LAUNCH();
+    return TOPO_OK;
+}
+
+}  // namespace topo
+
+using namespace topo;
+
+extern "C" {
+
+int topo_rom_build(topo_ctx* ctx, const topo_mesh* mesh, const void* phi, int32_t phi_fp32,
+                   int32_t k, int32_t ldphi, const uint8_t* mask, const double* f,
+                   const double* rho, int32_t B, double* Khat, double* fhat, int32_t prec,
+                   void* stream) {
+    if (!ctx) return TOPO_EINVAL;
+    int rc = validate_mesh(ctx, mesh);
+    if (rc) return rc;
+    const Grid g = make_grid(*mesh);
+    rc = check_basis(ctx, g, phi, k, ldphi);
+    if (rc) return rc;
+    if (!mask || !rho || !Khat || B < 1) return set_error(ctx, TOPO_EINVAL, "bad argument");
+    if (fhat && !f) return set_error(ctx, TOPO_EINVAL, "fhat requested without f");
+    if (prec != TOPO_FP64 && prec != TOPO_MIXED) return set_error(ctx, TOPO_EINVAL, "bad precision");
+    TOPO_HIP(hipSetDevice(ctx->device));
+    const ElemTables* tb = get_tables(ctx, *mesh);
+    if (!tb) return set_error(ctx, TOPO_EDEVICE, "element table upload failed");
+    hipStream_t s = (hipStream_t)stream;
+    const bool f64 = prec == TOPO_FP64;
+    const ContractPlan p = plan_contract(g, k, B, f64, ctx->cu_count);
+    if (p.lds_bytes > 64 * 1024)
+        return set_error(ctx, TOPO_EINVAL, "k = %d too large for the contraction tile (LDS)", k);
+    const int nc = phit_chunks(g);
+    Arena ar;
+    double* a64 = nullptr;
+    float* a32 = nullptr;
+    double *parts, *pf;
+    if (f64) ar.take(&a64, (size_t)B * g.n_elems);
+    else ar.take(&a32, (size_t)B * g.n_elems);
+    ar.take(&parts, (size_t)B * p.nchunks * p.npairs * 256);
+    ar.take(&pf, (size_t)nc * k);
+    rc = ar.commit(ctx, s);
+    if (rc) return rc;
+    rc = alpha_tables(ctx, g, *mesh, rho, B, a64, a32, s);
+    if (rc) return rc;
+    if (g.dim == 2) {
+        if (f64) {
+            rc = phi_fp32 ? launch_contract<2, float, double>(ctx, g, p, (const float*)phi, k, ldphi, mask, a64, tb->K64, B, parts, s)
+                          : launch_contract<2, double, double>(ctx, g, p, (const double*)phi, k, ldphi, mask, a64, tb->K64, B, parts, s);
+        } else {
+            rc = phi_fp32 ? launch_contract<2, float, float>(ctx, g, p, (const float*)phi, k, ldphi, mask, a32, tb->K32, B, parts, s)
+                          : launch_contract<2, double, float>(ctx, g, p, (const double*)phi, k, ldphi, mask, a32, tb->K32, B, parts, s);
+        }
+    } else {
+        if (f64) {
+            rc = phi_fp32 ? launch_contract<3, float, double>(ctx, g, p, (const float*)phi, k, ldphi, mask, a64, tb->K64, B, parts, s)
+                          : launch_contract<3, double, double>(ctx, g, p, (const double*)phi, k, ldphi, mask, a64, tb->K64, B, parts, s);
+        } else {
+            rc = phi_fp32 ? launch_contract<3, float, float>(ctx, g, p, (const float*)phi, k, ldphi, mask, a32, tb->K32, B, parts, s)
+                          : launch_contract<3, double, float>(ctx, g, p, (const double*)phi, k, ldphi, mask, a32, tb->K32, B, parts, s);
+        }
+    }
+    if (rc) return rc;
+    const size_t tot = (size_t)B * p.npairs * 256;
+    hipLaunchKernelGGL(k_rom_reduce, dim3(grid_blocks((long long)tot)), dim3(kBlock), 0, s, k, p.KP,
+                       p.nchunks, B, parts, Khat);
+    TOPO_CHECK_LAUNCH();
+    if (fhat) {
+        rc = phit_v(ctx, g, phi, phi_fp32, k, ldphi, mask, f, 0, 1, fhat, pf, nc, s);
+        if (rc) return rc;
+    }
+    return TOPO_OK;
+}
+
+int topo_rom_solve(topo_ctx* ctx, int32_t k, int32_t B, const double* Khat, const double* fhat,
+                   double* yhat, double* Jk, int32_t* status, void* stream) {
+    if (!ctx) return TOPO_EINVAL;
+    if (k < 1 || B < 1) return set_error(ctx, TOPO_EINVAL, "k and B must be >= 1");
+    if (!Khat || !fhat || !yhat || !Jk) return set_error(ctx, TOPO_EINVAL, "null pointer argument");
+    TOPO_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    Arena ar;
+    double* L;
+    int* st;
+    ar.take(&L, (size_t)B * k * k);
+    ar.take(&st, (size_t)B);
+    int rc = ar.commit(ctx, s);
+    if (rc) return rc;
+    int* stp = status ? (int*)status : st;
+    hipLaunchKernelGGL(k_chol, dim3(B), dim3(256), 0, s, k, Khat, L, stp);
+    TOPO_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_chol_solve, dim3(B), dim3(256), k * sizeof(double), s, k, L, fhat, 0LL, yhat,
+                       0, (const double*)nullptr, fhat, Jk);
+    TOPO_CHECK_LAUNCH();
+    if (!status) {
+        std::vector<int> h(B);
+        TOPO_HIP(hipMemcpyAsync(h.data(), st, B * sizeof(int), hipMemcpyDeviceToHost, s));
+        TOPO_HIP(hipStreamSynchronize(s));
+        for (int b = 0; b < B; ++b)
+            if (h[b] != 0) return set_error(ctx, TOPO_ENOTSPD, "reduced operator %d is not SPD", b);
+    }
+    return TOPO_OK;
+}
+
+int topo_rom_estimate(topo_ctx* ctx, const topo_mesh* mesh, const void* phi, int32_t phi_fp32,
+                      int32_t k, int32_t ldphi, const uint8_t* mask, const double* f,
+                      const double* rho, int32_t B, const double* Khat, double* yhat, double* Jk,
+                      double* resnorm, int32_t max_refine, void* stream) {
+    if (!ctx) return TOPO_EINVAL;
+    int rc = validate_mesh(ctx, mesh);
+    if (rc) return rc;
+    const Grid g = make_grid(*mesh);
+    rc = check_basis(ctx, g, phi, k, ldphi);
+    if (rc) return rc;
+    if (!mask || !f || !rho || !yhat || !resnorm || B < 1 || max_refine < 0)
+        return set_error(ctx, TOPO_EINVAL, "bad argument");
+    if (max_refine > 0 && !Khat) return set_error(ctx, TOPO_EINVAL, "refinement needs Khat");
+    TOPO_HIP(hipSetDevice(ctx->device));
+    const ElemTables* tb = get_tables(ctx, *mesh);
+    if (!tb) return set_error(ctx, TOPO_EDEVICE, "element table upload failed");
+    hipStream_t s = (hipStream_t)stream;
+    const long long N = g.n_dofs;
+    const int nb = grid_blocks(g.n_nodes);
+    const int nc = phit_chunks(g);
+    Arena ar;
+    double *a64, *u, *r, *part, *out, *rhat, *L = nullptr, *pc, *ybest, *g2, *stepw;
+    int *st = nullptr, *revert;
+    unsigned* counters;
+    ar.take(&a64, (size_t)B * g.n_elems);
+    ar.take(&u, (size_t)B * N);
+    ar.take(&r, (size_t)B * N);
+    ar.take(&part, (size_t)B * 3 * nb);
+    ar.take(&out, (size_t)4 * B);
+    ar.take(&counters, (size_t)B);
+    ar.take(&rhat, (size_t)B * k);
+    ar.take(&pc, (size_t)B * nc * k);
+    ar.take(&ybest, (size_t)B * k);
+    ar.take(&g2, (size_t)B);
+    ar.take(&stepw, (size_t)B);
+    ar.take(&revert, (size_t)B);
+    if (max_refine > 0) {
+        ar.take(&L, (size_t)B * k * k);
+        ar.take(&st, (size_t)B);
+    }
+    rc = ar.commit(ctx, s);
+    if (rc) return rc;
+    TOPO_HIP(hipMemsetAsync(counters, 0, B * sizeof(unsigned), s));
+    rc = alpha_tables(ctx, g, *mesh, rho, B, a64, nullptr, s);
+    if (rc) return rc;
+    // u = Phi y_hat, r = f - K u, ||r||^2 and f^T u per field
+    auto pass = [&]() -> int {
+        if (phi_fp32)
+            hipLaunchKernelGGL((k_phi_y<float>), dim3(grid_blocks(N), B), dim3(256), k * sizeof(double), s,
+                               N, (const float*)phi, k, ldphi, mask, yhat, u);
+        else
+            hipLaunchKernelGGL((k_phi_y<double>), dim3(grid_blocks(N), B), dim3(256), k * sizeof(double), s,
+                               N, (const double*)phi, k, ldphi, mask, yhat, u);
+        TOPO_CHECK_LAUNCH();
+        return residual_fp64(ctx, g, tb, a64, mask, u, f, r, B, part, out, counters, s);
+    };
+    // Galerkin residual r_hat = Phi^T r and its squared norm per field (read back)
+    auto galerkin = [&](std::vector<double>& gh) -> int {
+        int rc2 = phit_v(ctx, g, phi, phi_fp32, k, ldphi, mask, r, N, B, rhat, pc, nc, s);
+        if (rc2) return rc2;
+        hipLaunchKernelGGL(k_sqnorm_rows, dim3(B), dim3(64), 0, s, k, (const double*)rhat, g2);
+        TOPO_CHECK_LAUNCH();
+        gh.resize(B);
+        TOPO_HIP(hipMemcpyAsync(gh.data(), g2, B * sizeof(double), hipMemcpyDeviceToHost, s));
+        TOPO_HIP(hipStreamSynchronize(s));
+        return TOPO_OK;
+    };
+    rc = pass();
+    if (rc) return rc;
+    if (max_refine > 0) {
+        // Reduced iterative refinement: y += K_hat^{-1} Phi^T (f - K Phi y) with the
+        // float64 residual.  A field keeps a correction only while its Galerkin
+        // residual ||Phi^T r|| decreases; otherwise its previous y is restored.
+        hipLaunchKernelGGL(k_chol, dim3(B), dim3(256), 0, s, k, Khat, L, st);
+        TOPO_CHECK_LAUNCH();
+        std::vector<double> gcur, gnew;
+        rc = galerkin(gcur);
+        if (rc) return rc;
+        std::vector<int> active(B, 1), rev(B, 0);
+        std::vector<double> hstep(B);
+        for (int it = 0; it < max_refine; ++it) {
+            int nact = 0;
+            for (int b = 0; b < B; ++b) {
+                hstep[b] = active[b] ? 1.0 : 0.0;
+                nact += active[b];
+            }
+            if (!nact) break;
+            TOPO_HIP(hipMemcpyAsync(ybest, yhat, (size_t)B * k * sizeof(double), hipMemcpyDeviceToDevice, s));
+            TOPO_HIP(hipMemcpyAsync(stepw, hstep.data(), B * sizeof(double), hipMemcpyHostToDevice, s));
+            hipLaunchKernelGGL(k_chol_solve, dim3(B), dim3(256), k * sizeof(double), s, k, L, rhat,
+                               (long long)k, yhat, 1, (const double*)stepw, (const double*)nullptr,
+                               (double*)nullptr);
+            TOPO_CHECK_LAUNCH();
+            rc = pass();
+            if (rc) return rc;
+            rc = galerkin(gnew);
+            if (rc) return rc;
+            bool any = false;
+            for (int b = 0; b < B; ++b) {
+                rev[b] = 0;
+                if (active[b] && !(gnew[b] < gcur[b])) {
+                    rev[b] = 1;
+                    active[b] = 0;
+                    any = true;
+                }
+            }
+            if (any) {
+                TOPO_HIP(hipMemcpyAsync(revert, rev.data(), B * sizeof(int), hipMemcpyHostToDevice, s));
+                hipLaunchKernelGGL(k_restore_rows, dim3(B), dim3(64), 0, s, k, (const int*)revert,
+                                   (const double*)ybest, yhat);
+                TOPO_CHECK_LAUNCH();
+                rc = pass();
+                if (rc) return rc;
+                rc = galerkin(gnew);
+                if (rc) return rc;
+            }
+            gcur = gnew;
+        }
+    }
+    // ||r|| and J_k = f^T (Phi y_hat) of the final pass (reduced by the residual kernel)
+    hipLaunchKernelGGL(k_estimate_out, dim3(1), dim3(64), 0, s, B, (const double*)out, resnorm, Jk);
+    TOPO_CHECK_LAUNCH();
+    TOPO_HIP(hipStreamSynchronize(s));
+    return TOPO_OK;
+}
+
+}  // extern "C"

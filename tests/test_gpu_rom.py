@@ -1,0 +1,129 @@
+"""GPU parity of the ROM path (K_hat contraction on the matrix cores, f_hat, reduced
+Cholesky solve, residual error indicator with reduced refinement) against the FP64
+oracle, through the C ABI."""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from gpu_util import ctx, dev, host, problem_tensors, rel, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+CASES = [  # (problem, k) -- ragged k, several tiles, 2D and 3D
+    (W.mbb2d(13, 7), 5), (W.mbb2d(60, 20), 8), (W.cantilever2d(37, 11), 33),
+    (W.cantilever3d(7, 5, 3), 17), (W.bridge3d(6, 4, 5), 40), (W.mbb2d(1, 1), 3),
+]
+
+
+def _basis(p, k, dtype, seed=7):
+    return W.cosine_basis(p.mesh, p.mask, k, seed, dtype)
+
+
+def _rhos(p, B, seed=11):
+    rng = np.random.default_rng(seed)
+    return rng.uniform(0.05, 1.0, (B, p.mesh.n_elems))
+
+
+@pytest.mark.parametrize("p,k", CASES, ids=lambda v: getattr(v, "name", str(v)))
+@pytest.mark.parametrize("mode", ["fp64", "mixed"])
+def test_rom_build_matches_oracle(p, k, mode):
+    torch = torch_cuda()
+    from paper_2004_05756_amd import FP64, MIXED
+    phi = _basis(p, k, np.float32)
+    B = 3
+    rhos = _rhos(p, B)
+    Kh, fh = ctx().rom_build(p.mesh, dev(phi), k, dev(p.mask, torch.uint8), dev(p.f, torch.float64),
+                             dev(rhos, torch.float64), prec=FP64 if mode == "fp64" else MIXED)
+    Kh, fh = host(Kh), host(fh)
+    tol = 1e-13 if mode == "fp64" else 2e-6
+    for b in range(B):
+        ref = O.rom_operator(p.mesh, rhos[b], phi, p.mask)
+        assert np.array_equal(Kh[b], Kh[b].T)
+        assert np.abs(Kh[b] - ref).max() <= tol * np.abs(ref).max()
+    assert np.abs(fh - O.rom_load(phi, p.mask, p.f)).max() <= 1e-14 * max(np.abs(fh).max(), 1e-300) + 1e-300
+
+
+@pytest.mark.parametrize("p,k", CASES[:4], ids=lambda v: getattr(v, "name", str(v)))
+def test_rom_solve_and_estimate(p, k):
+    torch = torch_cuda()
+    from paper_2004_05756_amd import FP64, MIXED
+    phi = _basis(p, k, np.float32)
+    B = 2
+    rhos = _rhos(p, B, 5)
+    m = dev(p.mask, torch.uint8)
+    f = dev(p.f, torch.float64)
+    phid = dev(phi)
+    for mode, tolJ in (("fp64", 1e-10), ("mixed", 1e-8)):
+        prec = FP64 if mode == "fp64" else MIXED
+        r = dev(rhos, torch.float64)
+        Kh, fh = ctx().rom_build(p.mesh, phid, k, m, f, r, prec=prec)
+        y, J = ctx().rom_solve(Kh, fh)
+        y, J2, rn = ctx().rom_estimate(p.mesh, phid, k, m, f, r, Kh, y, max_refine=2)
+        y, J2, rn = host(y), host(J2), host(rn)
+        for b in range(B):
+            ev = O.rom_eval(p.mesh, rhos[b], phi, p.mask, p.f)
+            assert abs(J2[b] / ev["Jk"] - 1) <= tolJ
+            assert abs(rn[b] / ev["resnorm"] - 1) <= 1e-8
+            if mode == "fp64":
+                assert rel(y[b], ev["yhat"]) <= 1e-8
+
+
+def test_rom_solve_fp64_matches_cholesky():
+    torch = torch_cuda()
+    rng = np.random.default_rng(3)
+    for k in (1, 7, 64, 65, 130):
+        A = rng.standard_normal((k, k))
+        K = A @ A.T + k * np.eye(k)
+        fh = rng.standard_normal(k)
+        y, J = ctx().rom_solve(dev(K[None]), dev(fh))
+        yo, Jo = O.rom_solve(K, fh)
+        assert rel(host(y)[0], yo) <= 1e-12
+        assert abs(host(J)[0] / Jo - 1) <= 1e-12
+
+
+def test_estimate_zero_coefficients_is_load_norm():
+    torch = torch_cuda()
+    p, k = W.mbb2d(60, 20), 8
+    phi = _basis(p, k, np.float32)
+    rho = W.rho_jitter(p.mesh, 1000)
+    y = torch.zeros((1, k), dtype=torch.float64, device="cuda")
+    _, J, rn = ctx().rom_estimate(p.mesh, dev(phi), k, dev(p.mask, torch.uint8),
+                                  dev(p.f, torch.float64), dev(rho[None], torch.float64), None, y,
+                                  max_refine=0)
+    assert abs(host(rn)[0] / np.linalg.norm(p.f[p.mask == 0]) - 1) < 1e-15
+    assert host(J)[0] == 0.0
+
+
+def test_exactness_with_snapshot_in_basis():
+    """u*(rho) in span(Phi): J_k = J and the indicator vanishes (FP64 basis)."""
+    torch = torch_cuda()
+    from paper_2004_05756_amd import FP64
+    p = W.mbb2d(60, 20)
+    rho = W.rho_jitter(p.mesh, 1000)
+    u = O.solve_direct(p.mesh, rho, p.f, p.mask)
+    phi = np.column_stack([_basis(p, 7, np.float64), u])
+    k = phi.shape[1]
+    m, f, r = dev(p.mask, torch.uint8), dev(p.f, torch.float64), dev(rho[None], torch.float64)
+    Kh, fh = ctx().rom_build(p.mesh, dev(phi), k, m, f, r, prec=FP64)
+    y, J = ctx().rom_solve(Kh, fh)
+    y, J, rn = ctx().rom_estimate(p.mesh, dev(phi), k, m, f, r, Kh, y, max_refine=1)
+    assert abs(host(J)[0] / O.compliance(p.f, u) - 1) < 1e-11
+    assert host(rn)[0] / np.linalg.norm(p.f) < 1e-9
+
+
+def test_rank_deficient_basis_not_spd():
+    torch = torch_cuda()
+    from paper_2004_05756_amd import MIXED, TopoError, binding
+    p, k = W.mbb2d(30, 10), 6
+    phi = _basis(p, k, np.float32)
+    phi[:, 5] = phi[:, 2]
+    m, f = dev(p.mask, torch.uint8), dev(p.f, torch.float64)
+    r = dev(W.rho_jitter(p.mesh, 2)[None], torch.float64)
+    Kh, fh = ctx().rom_build(p.mesh, dev(phi), k, m, f, r, prec=MIXED)
+    with pytest.raises(TopoError) as ei:
+        ctx().rom_solve(Kh, fh)
+    assert ei.value.code == binding.TOPO_ENOTSPD
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ctx().rom_solve(Kh, fh, status=st)
+    assert int(st[0]) == binding.TOPO_ENOTSPD
