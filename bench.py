@@ -1,0 +1,247 @@
+#!/usr/bin/env python3
+"""Benchmark of the ROM-accelerated SIMP compliance hot path on one MI355X.
+
+One step = one pass of the whole hot path over one synthetic design:
+  HDM state solve (Jacobi-PCG, float32 inner / float64 refinement, rtol 1e-10)
+  -> compliance -> element sensitivity -> ROM build (K_hat by per-element MFMA
+  contraction, f_hat) -> reduced float64 Cholesky solve -> residual error indicator
+  with reduced refinement.
+Headline value: PCG DOF-iterations per second over the whole timed step
+(N_u x inner PCG iterations / wall time, ROM work included in the time).
+
+    python bench.py [--steps K] [--warmup W] [--workload cantilever2d_600x200]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+import numpy as np
+
+HBM_PEAK_GBS = 8000.0
+FP32_MFMA_PEAK_TFS = 157.3
+FP64_MFMA_PEAK_TFS = 78.6
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="cantilever2d_600x200")
+    ap.add_argument("--prec", choices=["mixed", "fp64"], default="mixed")
+    ap.add_argument("--rtol", type=float, default=None)
+    ap.add_argument("--k", type=int, default=None)
+    ap.add_argument("--max-refine", type=int, default=2)
+    ap.add_argument("--rom-evals", type=int, default=200, help="ROM evaluations per precision for evals/s and latency")
+    ap.add_argument("--timing-every", type=int, default=4, help="sample one launch in N of each hot kernel")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the ROM evals/s and FP64 comparison legs")
+    return ap.parse_args()
+
+
+def pcg_bytes(n_dofs, n_nodes, n_elems, word):
+    """Algorithmic HBM bytes of one launch of each PCG kernel (each array once).
+    apply : read z, p_old (stencil), alpha, mask; write p_new, q
+    update: read/write x, r; write z; read p, q, 1/sum(alpha) per node"""
+    return {
+        "pcg_apply": n_dofs * (4 * word + 1) + n_elems * word,
+        "pcg_update": n_dofs * 7 * word + n_nodes * word,
+    }
+
+
+def rom_contract_flops(n_elems, k, ne):
+    """Algorithmic flops of the per-element K_hat contraction for one density field
+    (operation count of the paper's cost analysis, Sec. 3.4)."""
+    return n_elems * (2 * k * ne * ne + 2 * k * k * ne)
+
+
+def cpu_baseline(cfg, phi_np, gpu_iters_per_step, n_dofs):
+    """The oracle as it stands, one full step on the same workload, 1 thread."""
+    import oracle as O
+    from threadpoolctl import threadpool_limits
+    p = cfg.problem
+    rho = cfg.rho(0)
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        u = O.solve_direct(p.mesh, rho, p.f, p.mask)
+        O.compliance(p.f, u)
+        O.sensitivity(p.mesh, rho, u)
+        O.rom_eval(p.mesh, rho, phi_np, p.mask, p.f)
+        dt = time.perf_counter() - t0
+    return {
+        "value": n_dofs * gpu_iters_per_step / dt,
+        "unit": "DOF-iter/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"one full oracle step on {cfg.name} (sparse direct solve, compliance, "
+                   f"sensitivity, assembled-matrix ROM eval k={phi_np.shape[1]}), single thread; "
+                   f"expressed as N_u x GPU PCG iterations per step / oracle step time"),
+        "seconds": dt,
+    }
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is "
+                                   "described in DESIGN.md but not built", "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    import workloads as W
+    from paper_2004_05756_amd import binding
+    from paper_2004_05756_amd.binding import FP64, MIXED
+
+    if not torch.cuda.is_available():
+        raise SystemExit("no GPU visible")
+    cfg = W.config(args.workload)
+    p = cfg.problem
+    m = p.mesh
+    k = args.k or cfg.k
+    rtol = args.rtol or cfg.rtol
+    prec = MIXED if args.prec == "mixed" else FP64
+    word = 4 if prec == MIXED else 8
+    dev = torch.device("cuda", 0)
+
+    rho_np = cfg.rho(0)
+    phi_np = W.cosine_basis(m, p.mask, k, cfg.basis_seed, np.float32)
+    rho = torch.as_tensor(rho_np).to(dev)
+    rho1 = rho.view(1, -1)
+    mask = torch.as_tensor(p.mask).to(dev)
+    f = torch.as_tensor(p.f).to(dev)
+    phi = torch.as_tensor(phi_np).to(dev)
+    u = torch.empty_like(f)
+    dc = torch.empty_like(rho)
+    Kh = torch.empty((1, k, k), dtype=torch.float64, device=dev)
+    fh = torch.empty(k, dtype=torch.float64, device=dev)
+    y = torch.empty((1, k), dtype=torch.float64, device=dev)
+    J = torch.empty(1, dtype=torch.float64, device=dev)
+    Je = torch.empty(1, dtype=torch.float64, device=dev)
+    rn = torch.empty(1, dtype=torch.float64, device=dev)
+    st = torch.empty(1, dtype=torch.int32, device=dev)
+
+    ctx = binding.Context(0)
+
+    def step():
+        _, info = ctx.hdm_solve(m, rho, mask, f, u=u, rtol=rtol, prec=prec)
+        ctx.hdm_gradient(m, rho, u, dc=dc)
+        ctx.rom_build(m, phi, k, mask, f, rho1, prec=prec, Khat=Kh, fhat=fh)
+        ctx.rom_solve(Kh, fh, status=st, yhat=y, Jk=J)
+        ctx.rom_estimate(m, phi, k, mask, f, rho1, Kh, y, max_refine=args.max_refine, Jk=Je, resnorm=rn)
+        return info
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    names = ["pcg_apply", "pcg_update", "residual", "rom_contract", "rom_reduce", "phit_v",
+             "phi_y", "chol", "chol_solve", "gradient"]
+    for nm in names:
+        ctx.kernel_time(nm, reset=True)
+    ctx.set_timing(args.timing_every)
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters = 0
+    infos = []
+    for _ in range(args.steps):
+        info = step()
+        iters += info["iters"]
+        infos.append(info)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.set_timing(0)
+    elapsed = t1 - t0
+    value = m.n_dofs * iters / elapsed
+
+    # live per-kernel durations from the sampled HIP events of the timed region
+    ktimes = {}
+    for nm in names:
+        n, ms = ctx.kernel_time(nm)
+        if n:
+            ktimes[nm] = {"samples": n, "avg_us": 1e3 * ms / n}
+    launches = {"pcg_apply": iters, "pcg_update": iters, "rom_contract": args.steps}
+    share = {nm: ktimes[nm]["avg_us"] * launches[nm] for nm in launches if nm in ktimes}
+    dominant = max(share, key=share.get) if share else None
+    pb = pcg_bytes(m.n_dofs, m.n_nodes, m.n_elems, word)
+    roofline = None
+    if dominant in pb:
+        avg_s = ktimes[dominant]["avg_us"] * 1e-6
+        gbs = pb[dominant] / avg_s / 1e9
+        roofline = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+                    "kernel": f"k_pcg_{dominant.split('_')[1]}<{m.dim},{'float' if word == 4 else 'double'}>",
+                    "bytes_per_launch": pb[dominant], "avg_us": ktimes[dominant]["avg_us"]}
+    elif dominant == "rom_contract":
+        ne = m.dim * 2 ** m.dim
+        fl = rom_contract_flops(m.n_elems, k, ne)
+        avg_s = ktimes[dominant]["avg_us"] * 1e-6
+        peak = FP32_MFMA_PEAK_TFS if word == 4 else FP64_MFMA_PEAK_TFS
+        tfs = fl / avg_s / 1e12
+        roofline = {"bound": "mfma", "achieved": tfs, "peak": peak, "unit": "TFLOP/s", "frac": tfs / peak,
+                    "traffic": None, "kernel": "k_rom_contract", "flops_per_launch": fl,
+                    "avg_us": ktimes[dominant]["avg_us"]}
+
+    out = {
+        "metric": "PCG DOF-iter/s (whole hot-path step; ROM build/solve/estimate included in the time)",
+        "value": value,
+        "unit": "DOF-iter/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if prec == MIXED else "f64",
+        "data": "synthetic",
+        "config": {"workload": cfg.name, "n_dofs": m.n_dofs, "n_elems": m.n_elems, "k": k, "rtol": rtol,
+                   "precision": args.prec, "max_refine": args.max_refine},
+        "roofline": roofline,
+        "pcg_iters_per_step": iters / args.steps,
+        "refinements_per_step": statistics.mean(i["refinements"] for i in infos),
+        "rel_resid": infos[-1]["rel_resid"],
+        "kernels": ktimes,
+    }
+
+    if not args.no_extra:
+        # HDM-only throughput in each precision, and ROM evals/s with latency percentiles
+        # (one eval = build + reduced solve + estimate), mixed vs plain FP64.
+        extra = {}
+        for name, pr in (("mixed", MIXED), ("fp64", FP64)):
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            _, inf = ctx.hdm_solve(m, rho, mask, f, u=u, rtol=rtol, prec=pr)
+            torch.cuda.synchronize()
+            tb = time.perf_counter() - ta
+            extra[f"hdm_{name}"] = {"ms": 1e3 * tb, "iters": inf["iters"],
+                                    "dof_iter_per_s": m.n_dofs * inf["iters"] / tb,
+                                    "compliance": inf["compliance_corr"]}
+            lat = []
+            for i in range(args.rom_evals):
+                ta = time.perf_counter()
+                ctx.rom_build(m, phi, k, mask, f, rho1, prec=pr, Khat=Kh, fhat=fh)
+                ctx.rom_solve(Kh, fh, status=st, yhat=y, Jk=J)
+                ctx.rom_estimate(m, phi, k, mask, f, rho1, Kh, y,
+                                 max_refine=args.max_refine if pr == MIXED else 0, Jk=Je, resnorm=rn)
+                torch.cuda.synchronize()
+                lat.append(time.perf_counter() - ta)
+            lat.sort()
+            extra[f"rom_{name}"] = {"evals_per_s": len(lat) / sum(lat),
+                                    "p50_ms": 1e3 * lat[len(lat) // 2],
+                                    "p99_ms": 1e3 * lat[min(len(lat) - 1, int(0.99 * len(lat)))],
+                                    "Jk": float(Je[0]), "resnorm": float(rn[0])}
+        out["extra"] = extra
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg, phi_np, iters / args.steps, m.n_dofs)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -98,6 +98,16 @@ const char* topo_strerror(int32_t code);
 /* Bytes of device workspace currently held by ctx (host scalar). */
 size_t topo_ctx_workspace_bytes(const topo_ctx* ctx);
 
+/* Instrumentation: bracket one launch in `every` (0 = off) of each hot kernel of ctx
+ * with a pair of HIP events on the stream it runs on. */
+int topo_ctx_set_timing(topo_ctx* ctx, int32_t every);
+/* Sampled launches and their summed device time in ms for one hot kernel: "apply",
+ * "pcg_apply", "pcg_update", "residual", "rom_contract", "rom_reduce", "phit_v",
+ * "phi_y", "chol", "chol_solve", "gradient".  Waits for pending samples (host
+ * outputs); reset != 0 clears the kernel's counters afterwards. */
+int topo_ctx_kernel_time(topo_ctx* ctx, const char* kernel, int64_t* samples,
+                         double* total_ms, int32_t reset);
+
 /* ---- element operator --------------------------------------------------------- */
 
 /* Unit-density element stiffness K_e of the mesh's element (Sec. 2.1), exact for the

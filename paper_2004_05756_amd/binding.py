@@ -22,6 +22,7 @@ EXPORTED = (
     "topo_ctx_create", "topo_ctx_destroy", "topo_last_error", "topo_strerror",
     "topo_ctx_workspace_bytes", "topo_element_stiffness", "topo_apply", "topo_hdm_solve",
     "topo_hdm_gradient", "topo_rom_build", "topo_rom_solve", "topo_rom_estimate",
+    "topo_ctx_set_timing", "topo_ctx_kernel_time",
 )
 
 
@@ -52,6 +53,9 @@ _SIGS = {
     "topo_last_error": (C.c_char_p, [_P]),
     "topo_strerror": (C.c_char_p, [C.c_int32]),
     "topo_ctx_workspace_bytes": (C.c_size_t, [_P]),
+    "topo_ctx_set_timing": (C.c_int, [_P, C.c_int32]),
+    "topo_ctx_kernel_time": (C.c_int, [_P, C.c_char_p, C.POINTER(C.c_int64), C.POINTER(C.c_double),
+                                       C.c_int32]),
     "topo_element_stiffness": (C.c_int, [C.POINTER(TopoMesh), C.POINTER(C.c_double)]),
     "topo_apply": (C.c_int, [_P, C.POINTER(TopoMesh), _P, _P, _P, _P, C.c_int32, C.c_int32, _P]),
     "topo_hdm_solve": (C.c_int, [_P, C.POINTER(TopoMesh), _P, _P, _P, _P, C.c_double, C.c_int32,
@@ -163,6 +167,18 @@ class Context:
 
     def workspace_bytes(self):
         return self.lib.topo_ctx_workspace_bytes(self.h)
+
+    def set_timing(self, every: int):
+        """Sample one launch in `every` of each hot kernel with HIP events (0 = off)."""
+        self._check(self.lib.topo_ctx_set_timing(self.h, int(every)), "set_timing")
+
+    def kernel_time(self, name: str, reset: bool = False):
+        """(sampled launches, summed device ms) of one hot kernel."""
+        n = C.c_int64()
+        ms = C.c_double()
+        rc = self.lib.topo_ctx_kernel_time(self.h, name.encode(), C.byref(n), C.byref(ms), int(reset))
+        self._check(rc, "kernel_time")
+        return int(n.value), float(ms.value)
 
     # -- full-order model -------------------------------------------------------------
     def apply(self, mesh, rho, mask, x, y=None, prec=FP64, stream=None):

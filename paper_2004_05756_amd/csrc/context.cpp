@@ -171,6 +171,59 @@ const ElemTables* get_tables(Ctx* ctx, const topo_mesh& m) {
     return &(ctx->tables[key] = t);
 }
 
+const char* const kKernelNames[KID_COUNT] = {
+    "apply", "pcg_apply", "pcg_update", "residual", "rom_contract", "rom_reduce",
+    "phit_v", "phi_y", "chol", "chol_solve", "gradient"};
+
+static hipEvent_t timing_event(Ctx* c) {
+    if (!c->timing.pool.empty()) {
+        hipEvent_t e = c->timing.pool.back();
+        c->timing.pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+TimedLaunch::TimedLaunch(Ctx* ctx, int k, hipStream_t st, int mode) : c(ctx), kid(k), s(st) {
+    if (!c || mode == kTimeOff) return;
+    Timing& t = c->timing;
+    if (t.every <= 0) return;
+    if (t.seen[kid]++ % t.every != 0 && mode != kTimeForced) return;
+    a = timing_event(c);
+    if (a && hipEventRecord(a, s) != hipSuccess) {
+        t.pool.push_back(a);
+        a = nullptr;
+    }
+}
+
+TimedLaunch::~TimedLaunch() {
+    if (!a) return;
+    hipEvent_t b = timing_event(c);
+    if (!b || hipEventRecord(b, s) != hipSuccess) {
+        c->timing.pool.push_back(a);
+        if (b) c->timing.pool.push_back(b);
+        return;
+    }
+    c->timing.pending.push_back({a, b, kid});
+    if (c->timing.pending.size() > 8192) timing_drain(c);
+}
+
+void timing_drain(Ctx* c) {
+    Timing& t = c->timing;
+    for (auto& r : t.pending) {
+        float ms = 0.f;
+        if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+            t.samples[r.kid] += 1;
+            t.total_ms[r.kid] += ms;
+        }
+        t.pool.push_back(r.a);
+        t.pool.push_back(r.b);
+    }
+    t.pending.clear();
+}
+
 int validate_mesh(Ctx* ctx, const topo_mesh* m) {
     if (!m) return set_error(ctx, TOPO_EINVAL, "mesh is NULL");
     if (m->dim != 2 && m->dim != 3) return set_error(ctx, TOPO_EINVAL, "dim must be 2 or 3");
@@ -220,6 +273,13 @@ int topo_ctx_destroy(topo_ctx* c) {
     if (!c) return TOPO_OK;
     (void)hipSetDevice(c->device);
     (void)hipDeviceSynchronize();
+    timing_drain(c);
+    for (hipEvent_t e : c->timing.pool) (void)hipEventDestroy(e);
+    for (auto& kv : c->graphs) {
+        if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+        if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
+    }
+    if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
     for (auto& kv : c->tables) {
         (void)hipFree(kv.second.K64);
         (void)hipFree(kv.second.K32);
@@ -245,6 +305,31 @@ const char* topo_strerror(int32_t code) {
         case TOPO_EAGAIN: return "TOPO_EAGAIN";
         default: return "TOPO_UNKNOWN";
     }
+}
+
+int topo_ctx_set_timing(topo_ctx* c, int32_t every) {
+    if (!c || every < 0) return TOPO_EINVAL;
+    c->timing.every = every;
+    return TOPO_OK;
+}
+
+int topo_ctx_kernel_time(topo_ctx* c, const char* kernel, int64_t* samples, double* total_ms,
+                         int32_t reset) {
+    if (!c || !kernel) return TOPO_EINVAL;
+    int kid = -1;
+    for (int i = 0; i < KID_COUNT; ++i)
+        if (std::strcmp(kernel, kKernelNames[i]) == 0) kid = i;
+    if (kid < 0) return set_error(c, TOPO_EINVAL, "unknown kernel name '%s'", kernel);
+    (void)hipSetDevice(c->device);
+    timing_drain(c);
+    if (samples) *samples = c->timing.samples[kid];
+    if (total_ms) *total_ms = c->timing.total_ms[kid];
+    if (reset) {
+        c->timing.samples[kid] = 0;
+        c->timing.total_ms[kid] = 0.0;
+        c->timing.seen[kid] = 0;
+    }
+    return TOPO_OK;
 }
 
 int topo_element_stiffness(const topo_mesh* mesh, double* K0) {

@@ -1,6 +1,13 @@
 // Full-order model on the device: matrix-free K(rho) apply, Jacobi-preconditioned CG
 // with float64 iterative refinement, compliance and element sensitivity
 // (Sec. 2.1 state equation, Sec. 2.3 compliance, Sec. 2.4 sensitivity).
+//
+// Global reductions never cross blocks inside a kernel: each kernel writes one
+// partial per block, and the consumer kernel (the next one in the stream) sums the
+// partials of its producer in a fixed order, redundantly in every block.  Kernel
+// boundaries provide the coherence between the XCDs' L2 caches, so no fences or
+// atomics are needed and every result is bitwise reproducible.
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 
@@ -61,21 +68,29 @@ __global__ __launch_bounds__(kBlock) void k_apply(Grid g, const T* __restrict__ 
 }
 
 // ----------------------------------------------------------------------------------
-// Jacobi-PCG.  Two kernels per iteration; scalars live on the device and every
-// global reduction is finished, in a fixed order, by the last block of the kernel
-// that produced the partial sums (no floating-point atomics, bitwise reproducible).
-//   k_pcg_apply : p_new = z + beta p_old (fused into the stencil), q = K p_new,
-//                 pq partials -> alpha = rz / pq
-//   k_pcg_update: x += alpha p, r -= alpha q, z = D^{-1} r, rz / rr partials
-//                 -> beta, convergence flag
+// Jacobi-PCG, two kernels per iteration:
+//   k_pcg_apply (iteration it): beta = rz_it / rz_{it-1}; p_new = z + beta p_old fused
+//                 into the stencil; q = K p_new; pq partials.  Also the stopping test
+//                 on rr = ||r_it||^2.
+//   k_pcg_update(iteration it): alpha = rz_it / pq; x += alpha p, r -= alpha q,
+//                 z = D^{-1} r; rz / rr partials of the next iteration.
+// Partials: part = [pq | rz(parity 0) | rz(parity 1) | rr(parity 0) | rr(parity 1)],
+// nb doubles each; iteration it writes rz/rr into parity it & 1 and reads the
+// current ones from parity (it + 1) & 1.  The PCG initialisation writes parity 1.
+// Block 0 alone writes the state record (done flag, iteration count, norms).
 // ----------------------------------------------------------------------------------
 struct PcgState {
-    double alpha, beta, rz, rr, bb, tol2, pq;
-    int done;   // 0 running, 1 converged, 2 iteration limit, 3 breakdown
-    int iters;
+    double bb;   // ||b||^2 (recorded by the first apply)
+    double rr;   // ||r||^2 at the last stopping test
+    int done;    // 0 running, 1 converged, 2 iteration limit, 3 breakdown
+    int iters;   // completed iterations
     int maxit;
-    unsigned counter;
+    int pad;
 };
+
+__device__ __forceinline__ const double* part_pq(const double* p, int) { return p; }
+__device__ __forceinline__ double* part_rz(double* p, int nb, int parity) { return p + (1 + parity) * nb; }
+__device__ __forceinline__ double* part_rr(double* p, int nb, int parity) { return p + (3 + parity) * nb; }
 
 template <int DIM, typename T>
 __global__ __launch_bounds__(kBlock) void k_pcg_init(Grid g, const T* __restrict__ b,
@@ -83,7 +98,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_init(Grid g, const T* __restrict
                                                      T ik2, T* __restrict__ x, T* __restrict__ r,
                                                      T* __restrict__ z, T* __restrict__ p,
                                                      double* __restrict__ part, PcgState* st,
-                                                     double tol, int maxit) {
+                                                     int maxit) {
     __shared__ double lds[32];
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     double v[2] = {0.0, 0.0};
@@ -106,22 +121,14 @@ __global__ __launch_bounds__(kBlock) void k_pcg_init(Grid g, const T* __restrict
     block_reduce<2>(v, lds);
     const int nb = gridDim.x;
     if (threadIdx.x == 0) {
-        part[nb + blockIdx.x] = v[0];
-        part[2 * nb + blockIdx.x] = v[1];
-    }
-    if (last_block(&st->counter)) {
-        const double rz = block_sum_array(part + nb, nb, lds);
-        const double rr = block_sum_array(part + 2 * nb, nb, lds);
-        if (threadIdx.x == 0) {
-            st->rz = rz;
-            st->rr = rr;
-            st->bb = rr;
-            st->tol2 = tol * tol * rr;
-            st->beta = 0.0;
-            st->alpha = 0.0;
+        part_rz(part, nb, 1)[blockIdx.x] = v[0];
+        part_rr(part, nb, 1)[blockIdx.x] = v[1];
+        if (blockIdx.x == 0) {
+            st->done = 0;
             st->iters = 0;
             st->maxit = maxit;
-            st->done = (rr == 0.0) ? 1 : (maxit <= 0 ? 2 : 0);
+            st->bb = 0.0;
+            st->rr = 0.0;
         }
     }
 }
@@ -133,39 +140,80 @@ __global__ __launch_bounds__(kBlock) void k_pcg_apply(Grid g, const T* __restric
                                                       const T* __restrict__ z,
                                                       const T* __restrict__ p_old,
                                                       T* __restrict__ p_new, T* __restrict__ q,
-                                                      double* __restrict__ part, PcgState* st) {
+                                                      double* __restrict__ part, PcgState* st,
+                                                      int parity, int first, double tol2) {
     if (st->done) return;
-    __shared__ double lds[16];
-    const T beta = (T)st->beta;
+    __shared__ double lds[48];
+    const int nb = gridDim.x;
+    const int cur = (parity + 1) & 1;
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool active = n < g.n_nodes;
+    int i = 0, j = 0, k = 0;
+    if (active) node_ijk(g, n, i, j, k);
+    // 2D: issue every load of this node before waiting on the scalar reduction
+    T zs[3][3][2], ps[3][3][2], al[2][2];
+    uint8_t mk[DIM];
+    if constexpr (DIM == 2) {
+        if (active) {
+            load_nbhd2(g, i, j, FetchPlain<T>{z, g.n_nodes}, zs);
+            load_nbhd2(g, i, j, FetchPlain<T>{p_old, g.n_nodes}, ps);
+            load_alpha2(g, i, j, alpha, al);
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) mk[c] = mask[(size_t)c * g.n_nodes + n];
+        }
+    }
+    // rr and rz of the current residual, rz of the previous one (one pass)
+    const double* arrs[3] = {part_rr(part, nb, cur), part_rz(part, nb, cur), part_rz(part, nb, parity)};
+    double red[3];
+    block_sum_arrays<3>(arrs, nb, red, lds);
+    const double rr = red[0];
+    const double bb = first ? rr : st->bb;
+    int code = 0;
+    if (!isfinite(rr)) code = 3;
+    else if (rr <= tol2 * bb) code = 1;
+    else if (st->iters >= st->maxit) code = 2;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (first) st->bb = rr;
+        st->rr = rr;
+        if (code) st->done = code;
+    }
+    if (code) return;
+    const T tb = first ? T(0) : (T)(red[1] / red[2]);
     double v[1] = {0.0};
-    if (n < g.n_nodes) {
-        int i, j, k;
-        node_ijk(g, n, i, j, k);
-        FetchDirection<T> f{z, p_old, beta, g.n_nodes};
-        T out[DIM];
-        if constexpr (DIM == 2) node_apply2<T>(g, i, j, alpha, K, f, out);
-        else node_apply3<T>(g, i, j, k, alpha, K, f, out);
+    if (active) {
+        T out[DIM], pn[DIM];
+        if constexpr (DIM == 2) {
+            T xs[3][3][2];
+#pragma unroll
+            for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+                for (int dx = 0; dx < 3; ++dx)
+#pragma unroll
+                    for (int c = 0; c < 2; ++c) xs[dy][dx][c] = zs[dy][dx][c] + tb * ps[dy][dx][c];
+            pn[0] = xs[1][1][0];
+            pn[1] = xs[1][1][1];
+            apply_nbhd2(K, xs, al, out);
+        } else {
+            FetchDirection<T> f{z, p_old, tb, g.n_nodes};
+            node_apply3<T>(g, i, j, k, alpha, K, f, out);
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) {
+                const size_t idx = (size_t)c * g.n_nodes + n;
+                pn[c] = z[idx] + tb * p_old[idx];
+                mk[c] = mask[idx];
+            }
+        }
 #pragma unroll
         for (int c = 0; c < DIM; ++c) {
             const size_t idx = (size_t)c * g.n_nodes + n;
-            const T pn = z[idx] + beta * p_old[idx];
-            const T qv = mask[idx] ? T(0) : out[c];
-            p_new[idx] = pn;
+            const T qv = mk[c] ? T(0) : out[c];
+            p_new[idx] = pn[c];
             q[idx] = qv;
-            v[0] += (double)pn * (double)qv;
+            v[0] += (double)pn[c] * (double)qv;
         }
     }
     block_reduce<1>(v, lds);
     if (threadIdx.x == 0) part[blockIdx.x] = v[0];
-    if (last_block(&st->counter)) {
-        const double pq = block_sum_array(part, gridDim.x, lds);
-        if (threadIdx.x == 0) {
-            st->pq = pq;
-            if (!(pq > 0.0) || !isfinite(pq)) st->done = 3;
-            else st->alpha = st->rz / pq;
-        }
-    }
 }
 
 template <int DIM, typename T>
@@ -174,20 +222,43 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(Grid g, const T* __restri
                                                        T* __restrict__ r, T* __restrict__ z,
                                                        const T* __restrict__ p,
                                                        const T* __restrict__ q,
-                                                       double* __restrict__ part, PcgState* st) {
+                                                       double* __restrict__ part, PcgState* st,
+                                                       int parity) {
     if (st->done) return;
     __shared__ double lds[32];
-    const T a = (T)st->alpha;
+    const int nb = gridDim.x;
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
-    double v[2] = {0.0, 0.0};
-    if (n < g.n_nodes) {
-        const T ik[3] = {ik0, ik1, ik2};
-        const T w = winv[n];
+    const bool active = n < g.n_nodes;
+    // issue this node's loads before waiting on the scalar reduction
+    T xv[DIM], rv[DIM], pv[DIM], qv[DIM], w = T(0);
+    if (active) {
+        w = winv[n];
 #pragma unroll
         for (int c = 0; c < DIM; ++c) {
             const size_t i = (size_t)c * g.n_nodes + n;
-            x[i] += a * p[i];
-            const T ri = r[i] - a * q[i];
+            xv[c] = x[i];
+            rv[c] = r[i];
+            pv[c] = p[i];
+            qv[c] = q[i];
+        }
+    }
+    const double* arrs[2] = {part, part_rz(part, nb, (parity + 1) & 1)};
+    double red[2];
+    block_sum_arrays<2>(arrs, nb, red, lds);
+    const double pq = red[0];
+    if (!(pq > 0.0) || !isfinite(pq)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) st->done = 3;
+        return;
+    }
+    const T a = (T)(red[1] / pq);
+    double v[2] = {0.0, 0.0};
+    if (active) {
+        const T ik[3] = {ik0, ik1, ik2};
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            const size_t i = (size_t)c * g.n_nodes + n;
+            x[i] = xv[c] + a * pv[c];
+            const T ri = rv[c] - a * qv[c];
             const T zi = ri * w * ik[c];
             r[i] = ri;
             z[i] = zi;
@@ -196,30 +267,17 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(Grid g, const T* __restri
         }
     }
     block_reduce<2>(v, lds);
-    const int nb = gridDim.x;
     if (threadIdx.x == 0) {
-        part[nb + blockIdx.x] = v[0];
-        part[2 * nb + blockIdx.x] = v[1];
-    }
-    if (last_block(&st->counter)) {
-        const double rz = block_sum_array(part + nb, nb, lds);
-        const double rr = block_sum_array(part + 2 * nb, nb, lds);
-        if (threadIdx.x == 0) {
-            const int it = st->iters + 1;
-            st->iters = it;
-            st->beta = rz / st->rz;
-            st->rz = rz;
-            st->rr = rr;
-            if (rr <= st->tol2) st->done = 1;
-            else if (it >= st->maxit) st->done = 2;
-            else if (!isfinite(rr)) st->done = 3;
-        }
+        part_rz(part, nb, parity)[blockIdx.x] = v[0];
+        part_rr(part, nb, parity)[blockIdx.x] = v[1];
+        if (blockIdx.x == 0) st->iters = st->iters + 1;
     }
 }
 
 // ----------------------------------------------------------------------------------
 // float64 residual r = f - K u over free DOFs (u zero on Dirichlet DOFs), with
-// ||r||^2, f^T u and u^T r reduced per field (blockIdx.y) into out[4*b .. 4*b+2].
+// per-block partials of ||r||^2, f^T u and u^T r for every field (blockIdx.y);
+// k_residual_sum reduces them (one block per field) into out[4*b .. 4*b+2].
 // ----------------------------------------------------------------------------------
 template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_residual(Grid g, const double* __restrict__ alpha,
@@ -228,9 +286,7 @@ __global__ __launch_bounds__(kBlock) void k_residual(Grid g, const double* __res
                                                      const double* __restrict__ u,
                                                      const double* __restrict__ f,
                                                      double* __restrict__ r,
-                                                     double* __restrict__ part,
-                                                     double* __restrict__ out,
-                                                     unsigned* __restrict__ counters) {
+                                                     double* __restrict__ part) {
     __shared__ double lds[48];
     const size_t b = blockIdx.y;
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
@@ -265,26 +321,20 @@ __global__ __launch_bounds__(kBlock) void k_residual(Grid g, const double* __res
         pb[nb + blockIdx.x] = v[1];
         pb[2 * nb + blockIdx.x] = v[2];
     }
-    // per-field ticket: the last block of this field's row reduces it
-    __shared__ bool is_last;
-    __threadfence();
-    __syncthreads();
+}
+
+__global__ __launch_bounds__(kBlock) void k_residual_sum(int nb, const double* __restrict__ part,
+                                                         double* __restrict__ out) {
+    __shared__ double lds[16];
+    const int b = blockIdx.x;
+    const double* pb = part + (size_t)b * 3 * nb;
+    const double s0 = block_sum_array(pb, nb, lds);
+    const double s1 = block_sum_array(pb + nb, nb, lds);
+    const double s2 = block_sum_array(pb + 2 * nb, nb, lds);
     if (threadIdx.x == 0) {
-        const unsigned t = atomicAdd(&counters[b], 1u);
-        is_last = (t == gridDim.x - 1);
-    }
-    __syncthreads();
-    if (is_last) {
-        __threadfence();
-        const double s0 = block_sum_array(pb, nb, lds);
-        const double s1 = block_sum_array(pb + nb, nb, lds);
-        const double s2 = block_sum_array(pb + 2 * nb, nb, lds);
-        if (threadIdx.x == 0) {
-            out[4 * b + 0] = s0;
-            out[4 * b + 1] = s1;
-            out[4 * b + 2] = s2;
-            atomicExch(&counters[b], 0u);
-        }
+        out[4 * b + 0] = s0;
+        out[4 * b + 1] = s1;
+        out[4 * b + 2] = s2;
     }
 }
 
@@ -357,13 +407,6 @@ __global__ __launch_bounds__(kBlock) void k_gradient(Grid g, const double* __res
 // ----------------------------------------------------------------------------------
 // Host drivers
 // ----------------------------------------------------------------------------------
-struct HdmBufs {
-    double* a64;
-    float* a32;
-    double* w64;
-    float* w32;
-};
-
 static int launch_tables(Ctx* ctx, const Grid& g, const topo_mesh& m, const double* rho,
                          int B, double* a64, float* a32, double* w64, float* w32,
                          hipStream_t s) {
@@ -391,34 +434,124 @@ struct PcgRun {
     PcgState* st;
 };
 
+static bool graphs_enabled() {
+    static const bool on = [] {
+        const char* e = std::getenv("TOPO_NO_GRAPH");
+        return !(e && e[0] && e[0] != '0');
+    }();
+    return on;
+}
+
+// One PCG iteration (apply + update) launched directly on stream s.
+template <int DIM, typename T>
+static void pcg_iteration(Ctx* ctx, const Grid& g, const PcgRun<DIM, T>& w, int nb, int parity,
+                          int first, double tol2, hipStream_t s, int timing) {
+    T* pold = parity ? w.p1 : w.p0;
+    T* pnew = parity ? w.p0 : w.p1;
+    {
+        TimedLaunch tl(ctx, KID_PCG_APPLY, s, timing);
+        hipLaunchKernelGGL((k_pcg_apply<DIM, T>), dim3(nb), dim3(kBlock), 0, s, g, w.alpha, w.K,
+                           w.mask, (const T*)w.z, (const T*)pold, pnew, w.q, w.part, w.st, parity,
+                           first, tol2);
+    }
+    {
+        TimedLaunch tl(ctx, KID_PCG_UPDATE, s, timing);
+        hipLaunchKernelGGL((k_pcg_update<DIM, T>), dim3(nb), dim3(kBlock), 0, s, g, w.winv, w.ik[0],
+                           w.ik[1], w.ik[2], w.x, w.r, w.z, (const T*)pnew, (const T*)w.q, w.part,
+                           w.st, parity);
+    }
+}
+
+// Graph of CH iterations starting at parity 1 (CH even, so every replay continues
+// the parity sequence), captured on the context's private stream.
+template <int DIM, typename T>
+static int pcg_graph(Ctx* ctx, const Grid& g, const PcgRun<DIM, T>& w, int nb, double tol2, int CH,
+                     hipGraphExec_t* out) {
+    std::vector<uintptr_t> key = {(uintptr_t)DIM, sizeof(T), (uintptr_t)nb, (uintptr_t)CH,
+                                  (uintptr_t)g.nx, (uintptr_t)g.ny, (uintptr_t)g.nz,
+                                  (uintptr_t)w.alpha, (uintptr_t)w.K, (uintptr_t)w.mask,
+                                  (uintptr_t)w.winv, (uintptr_t)w.x, (uintptr_t)w.r, (uintptr_t)w.z,
+                                  (uintptr_t)w.p0, (uintptr_t)w.p1, (uintptr_t)w.q, (uintptr_t)w.part,
+                                  (uintptr_t)w.st};
+    uint64_t tb;
+    std::memcpy(&tb, &tol2, sizeof tb);
+    key.push_back((uintptr_t)tb);
+    for (int c = 0; c < 3; ++c) {
+        double ikd = (double)w.ik[c];
+        uint64_t ib;
+        std::memcpy(&ib, &ikd, sizeof ib);
+        key.push_back((uintptr_t)ib);
+    }
+    auto it = ctx->graphs.find(key);
+    if (it != ctx->graphs.end()) {
+        *out = it->second.exec;
+        return TOPO_OK;
+    }
+    if (ctx->graphs.size() >= 16) {
+        for (auto& kv : ctx->graphs) {
+            (void)hipGraphExecDestroy(kv.second.exec);
+            (void)hipGraphDestroy(kv.second.graph);
+        }
+        ctx->graphs.clear();
+    }
+    if (!ctx->capture_stream) TOPO_HIP(hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
+    hipStream_t cs = ctx->capture_stream;
+    TOPO_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    for (int c = 0; c < CH; ++c) pcg_iteration<DIM, T>(ctx, g, w, nb, (1 + c) & 1, 0, tol2, cs, kTimeOff);
+    GraphEntry ge;
+    hipError_t e1 = hipStreamEndCapture(cs, &ge.graph);
+    if (e1 != hipSuccess) return set_error(ctx, TOPO_EDEVICE, "graph capture failed: %s", hipGetErrorString(e1));
+    TOPO_HIP(hipGraphInstantiateWithFlags(&ge.exec, ge.graph, 0));
+    ctx->graphs[key] = ge;
+    *out = ge.exec;
+    return TOPO_OK;
+}
+
 template <int DIM, typename T>
 static int pcg_run(Ctx* ctx, const Grid& g, PcgRun<DIM, T>& w, double tol, int maxit,
                    hipStream_t s, PcgState* result) {
     const int nb = grid_blocks(g.n_nodes);
+    const double tol2 = tol * tol;
     hipLaunchKernelGGL((k_pcg_init<DIM, T>), dim3(nb), dim3(kBlock), 0, s, g, w.b, w.winv,
-                       w.ik[0], w.ik[1], w.ik[2], w.x, w.r, w.z, w.p0, w.part, w.st, tol, maxit);
+                       w.ik[0], w.ik[1], w.ik[2], w.x, w.r, w.z, w.p0, w.part, w.st, maxit);
     TOPO_CHECK_LAUNCH();
     void* pin = nullptr;
     int rc = pinned_host(ctx, 2 * sizeof(PcgState), &pin);
     if (rc) return rc;
     PcgState* hs = (PcgState*)pin;
+    // iteration 0 (parity 0) records ||b||; the rest continue at parity 1
+    pcg_iteration<DIM, T>(ctx, g, w, nb, 0, 1, tol2, s, kTimeSampled);
+    TOPO_CHECK_LAUNCH();
+    constexpr int CH = 16;  // iterations per graph replay (even)
+    hipGraphExec_t exec = nullptr;
+    if (graphs_enabled()) {
+        rc = pcg_graph<DIM, T>(ctx, g, w, nb, tol2, CH, &exec);
+        if (rc) return rc;
+    }
     hipEvent_t ev[2];
     TOPO_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
     TOPO_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
     bool pending[2] = {false, false};
-    long long issued = 0;
+    long long issued = 1;
+    long long replays = 0;
     int chunk = 4;
     int slot = 0;
     const long long cap = (long long)maxit + 4096;
     while (true) {
-        for (int c = 0; c < chunk; ++c, ++issued) {
-            T* pold = (issued & 1) ? w.p1 : w.p0;
-            T* pnew = (issued & 1) ? w.p0 : w.p1;
-            hipLaunchKernelGGL((k_pcg_apply<DIM, T>), dim3(nb), dim3(kBlock), 0, s, g, w.alpha,
-                               w.K, w.mask, w.z, pold, pnew, w.q, w.part, w.st);
-            hipLaunchKernelGGL((k_pcg_update<DIM, T>), dim3(nb), dim3(kBlock), 0, s, g, w.winv,
-                               w.ik[0], w.ik[1], w.ik[2], w.x, w.r, w.z, pnew, w.q, w.part, w.st);
+        const int every = ctx->timing.every;
+        if (exec && !(every > 0 && replays % every == 0)) {
+            TOPO_HIP(hipGraphLaunch(exec, s));
+            issued += CH;
+        } else if (exec) {
+            // timing sample: two directly launched, timed iterations (keeps the parity)
+            for (int c = 0; c < 2; ++c, ++issued)
+                pcg_iteration<DIM, T>(ctx, g, w, nb, (int)(issued & 1), 0, tol2, s, kTimeForced);
+        } else {
+            for (int c = 0; c < chunk; ++c, ++issued)
+                pcg_iteration<DIM, T>(ctx, g, w, nb, (int)(issued & 1), 0, tol2, s, kTimeSampled);
+            if (chunk < 64) chunk *= 2;
         }
+        ++replays;
         TOPO_CHECK_LAUNCH();
         TOPO_HIP(hipMemcpyAsync(&hs[slot], w.st, sizeof(PcgState), hipMemcpyDeviceToHost, s));
         TOPO_HIP(hipEventRecord(ev[slot], s));
@@ -432,7 +565,6 @@ static int pcg_run(Ctx* ctx, const Grid& g, PcgRun<DIM, T>& w, double tol, int m
         }
         if (stop || issued >= cap) break;
         slot = other;
-        if (chunk < 64) chunk *= 2;
     }
     TOPO_HIP(hipStreamSynchronize(s));
     TOPO_HIP(hipEventDestroy(ev[0]));
@@ -450,6 +582,25 @@ static double mixed_inner_tol() {
     return v;
 }
 
+static int residual_launch(Ctx* ctx, const Grid& g, const double* K64, const double* alpha64,
+                           const uint8_t* mask, const double* u, const double* f, double* r, int B,
+                           double* part, double* out, hipStream_t s) {
+    const int nb = grid_blocks(g.n_nodes);
+    {
+        TimedLaunch tl(ctx, KID_RESIDUAL, s);
+        if (g.dim == 2)
+            hipLaunchKernelGGL((k_residual<2>), dim3(nb, B), dim3(kBlock), 0, s, g, alpha64, K64,
+                               mask, u, f, r, part);
+        else
+            hipLaunchKernelGGL((k_residual<3>), dim3(nb, B), dim3(kBlock), 0, s, g, alpha64, K64,
+                               mask, u, f, r, part);
+    }
+    TOPO_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_residual_sum, dim3(B), dim3(kBlock), 0, s, nb, (const double*)part, out);
+    TOPO_CHECK_LAUNCH();
+    return TOPO_OK;
+}
+
 template <int DIM, typename T>
 static int hdm_solve_impl(Ctx* ctx, const topo_mesh& m, const Grid& g, const ElemTables* tb,
                           const double* rho, const uint8_t* mask, const double* f, double* u,
@@ -458,11 +609,10 @@ static int hdm_solve_impl(Ctx* ctx, const topo_mesh& m, const Grid& g, const Ele
     const long long N = g.n_dofs;
     const int nb = grid_blocks(g.n_nodes);
     Arena ar;
-    double *a64, *w64, *r64, *part, *rout;
-    T *ta, *tw, *b, *x, *r, *z, *p0, *p1, *q;
+    double *a64, *w64, *r64, *part, *rpart, *rout;
+    T *b, *x, *r, *z, *p0, *p1, *q;
     float *a32 = nullptr, *w32 = nullptr;
     PcgState* st;
-    unsigned* counters;
     ar.take(&a64, g.n_elems);
     ar.take(&w64, g.n_nodes);
     if (mixed) {
@@ -470,10 +620,10 @@ static int hdm_solve_impl(Ctx* ctx, const topo_mesh& m, const Grid& g, const Ele
         ar.take(&w32, g.n_nodes);
     }
     ar.take(&r64, N);
-    ar.take(&part, 3 * (size_t)nb);
+    ar.take(&part, 5 * (size_t)nb);
+    ar.take(&rpart, 3 * (size_t)nb);
     ar.take(&rout, 4);
     ar.take(&st, 1);
-    ar.take(&counters, 64);
     ar.take(&b, N);
     ar.take(&x, N);
     ar.take(&r, N);
@@ -483,16 +633,16 @@ static int hdm_solve_impl(Ctx* ctx, const topo_mesh& m, const Grid& g, const Ele
     ar.take(&q, N);
     int rc = ar.commit(ctx, s);
     if (rc) return rc;
-    TOPO_HIP(hipMemsetAsync(st, 0, sizeof(PcgState), s));
-    TOPO_HIP(hipMemsetAsync(counters, 0, 64 * sizeof(unsigned), s));
     rc = launch_tables(ctx, g, m, rho, 1, a64, a32, w64, w32, s);
     if (rc) return rc;
+    const T* ta;
+    const T* tw;
     if constexpr (sizeof(T) == 4) {
-        ta = (T*)a32;
-        tw = (T*)w32;
+        ta = (const T*)a32;
+        tw = (const T*)w32;
     } else {
-        ta = (T*)a64;
-        tw = (T*)w64;
+        ta = (const T*)a64;
+        tw = (const T*)w64;
     }
     PcgRun<DIM, T> w;
     w.alpha = ta;
@@ -513,10 +663,9 @@ static int hdm_solve_impl(Ctx* ctx, const topo_mesh& m, const Grid& g, const Ele
     TOPO_HIP(hipMemsetAsync(u, 0, N * sizeof(double), s));
     void* pin = nullptr;
     auto residual = [&](double out[3]) -> int {
-        hipLaunchKernelGGL((k_residual<DIM>), dim3(nb, 1), dim3(kBlock), 0, s, g, a64, tb->K64,
-                           mask, u, f, r64, part, rout, counters);
-        TOPO_CHECK_LAUNCH();
-        int rc2 = pinned_host(ctx, 4 * sizeof(double) + 2 * sizeof(PcgState), &pin);
+        int rc2 = residual_launch(ctx, g, tb->K64, a64, mask, u, f, r64, 1, rpart, rout, s);
+        if (rc2) return rc2;
+        rc2 = pinned_host(ctx, 4 * sizeof(double) + 2 * sizeof(PcgState), &pin);
         if (rc2) return rc2;
         double* h = (double*)((char*)pin + 2 * sizeof(PcgState));
         TOPO_HIP(hipMemcpyAsync(h, rout, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -612,6 +761,7 @@ int topo_apply(topo_ctx* ctx, const topo_mesh* mesh, const double* rho, const ui
     rc = launch_tables(ctx, g, *mesh, rho, B, a64, a32, nullptr, nullptr, s);
     if (rc) return rc;
     dim3 grid(grid_blocks(g.n_nodes), B);
+    TimedLaunch tl(ctx, KID_APPLY, s);
     if (prec == TOPO_FP64) {
         if (g.dim == 2)
             hipLaunchKernelGGL((k_apply<2, double>), grid, dim3(kBlock), 0, s, g, a64, tb->K64, mask,
@@ -672,6 +822,7 @@ int topo_hdm_gradient(topo_ctx* ctx, const topo_mesh* mesh, const double* rho, c
     const ElemTables* tb = get_tables(ctx, *mesh);
     if (!tb) return set_error(ctx, TOPO_EDEVICE, "element table upload failed");
     hipStream_t s = (hipStream_t)stream;
+    TimedLaunch tl(ctx, KID_GRADIENT, s);
     if (g.dim == 2)
         hipLaunchKernelGGL((k_gradient<2>), dim3(grid_blocks(g.n_elems)), dim3(kBlock), 0, s, g, rho,
                            tb->K64, u, mesh->E0, mesh->Emin, mesh->penal, dc);
@@ -689,16 +840,8 @@ namespace topo {
 
 int residual_fp64(Ctx* ctx, const Grid& g, const ElemTables* tb, const double* alpha64,
                   const uint8_t* mask, const double* u, const double* f, double* r, int B,
-                  double* part, double* out, unsigned* counters, hipStream_t s) {
-    const int nb = grid_blocks(g.n_nodes);
-    if (g.dim == 2)
-        hipLaunchKernelGGL((k_residual<2>), dim3(nb, B), dim3(kBlock), 0, s, g, alpha64, tb->K64,
-                           mask, u, f, r, part, out, counters);
-    else
-        hipLaunchKernelGGL((k_residual<3>), dim3(nb, B), dim3(kBlock), 0, s, g, alpha64, tb->K64,
-                           mask, u, f, r, part, out, counters);
-    TOPO_CHECK_LAUNCH();
-    return TOPO_OK;
+                  double* part, double* out, hipStream_t s) {
+    return residual_launch(ctx, g, tb->K64, alpha64, mask, u, f, r, B, part, out, s);
 }
 
 int alpha_tables(Ctx* ctx, const Grid& g, const topo_mesh& m, const double* rho, int B,

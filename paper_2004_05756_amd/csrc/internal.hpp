@@ -44,10 +44,55 @@ struct ElemTables {
 void element_stiffness(const topo_mesh& m, std::vector<double>& K);
 
 // ----------------------------------------------------------------------------------
+// Sampled kernel timing (instrumentation): one launch in `every` of each hot kernel is
+// bracketed by a pair of HIP events on its own stream.
+// ----------------------------------------------------------------------------------
+enum KernelId {
+    KID_APPLY, KID_PCG_APPLY, KID_PCG_UPDATE, KID_RESIDUAL, KID_ROM_CONTRACT, KID_ROM_REDUCE,
+    KID_PHIT_V, KID_PHI_Y, KID_CHOL, KID_CHOL_SOLVE, KID_GRADIENT, KID_COUNT
+};
+extern const char* const kKernelNames[KID_COUNT];
+
+struct Timing {
+    int every = 0;
+    long long seen[KID_COUNT] = {};
+    long long samples[KID_COUNT] = {};
+    double total_ms[KID_COUNT] = {};
+    struct Rec { hipEvent_t a, b; int kid; };
+    std::vector<Rec> pending;
+    std::vector<hipEvent_t> pool;
+};
+
+struct Ctx;
+void timing_drain(Ctx* c);
+
+// mode: kTimeOff never records (e.g. during graph capture), kTimeSampled records one
+// launch in `every`, kTimeForced records whenever timing is enabled.
+enum { kTimeOff = 0, kTimeSampled = 1, kTimeForced = 2 };
+struct TimedLaunch {
+    Ctx* c;
+    int kid;
+    hipStream_t s;
+    hipEvent_t a = nullptr;
+    TimedLaunch(Ctx* ctx, int kid, hipStream_t s, int mode = kTimeSampled);
+    ~TimedLaunch();
+};
+
+// ----------------------------------------------------------------------------------
 // Context: device, element-table cache, grow-only workspace arena
 // ----------------------------------------------------------------------------------
+// Instantiated HIP graphs of launch-bound kernel sequences, keyed by every value baked
+// into their kernel arguments.
+struct GraphEntry {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
 struct Ctx {
     int device = 0;
+    Timing timing;
+    std::map<std::vector<uintptr_t>, GraphEntry> graphs;
+    hipStream_t capture_stream = nullptr;  // private stream used only for graph capture
     std::string err;
     std::map<std::tuple<int, double, double, double, double, int>, ElemTables> tables;
     void* ws = nullptr;        // device workspace
@@ -124,23 +169,16 @@ __device__ inline void block_reduce(double (&v)[NV], double* lds /* >= NV*16 */)
     __syncthreads();
 }
 
-// "Last block done" ticket: returns true in every thread of the block that arrives
-// last.  Partial results must have been written before the call.  The last block
-// resets the counter for the next use.
-__device__ inline bool last_block(unsigned* counter) {
-    __shared__ bool is_last;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned t = atomicAdd(counter, 1u);
-        is_last = (t == gridDim.x * gridDim.y * gridDim.z - 1);
-    }
-    __syncthreads();
-    if (is_last) {
-        __threadfence();
-        if (threadIdx.x == 0) atomicExch(counter, 0u);
-    }
-    return is_last;
+// Sum each of NV arrays of n doubles in one pass (fixed order; result in every thread).
+template <int NV>
+__device__ inline void block_sum_arrays(const double* const (&a)[NV], int n, double (&out)[NV],
+                                        double* lds /* >= NV*16 */) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) out[q] = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x)
+#pragma unroll
+        for (int q = 0; q < NV; ++q) out[q] += a[q][i];
+    block_reduce<NV>(out, lds);
 }
 
 // Sum n doubles with a fixed order inside one block (result in every thread).

@@ -13,7 +13,7 @@ namespace topo {
 
 int residual_fp64(Ctx* ctx, const Grid& g, const ElemTables* tb, const double* alpha64,
                   const uint8_t* mask, const double* u, const double* f, double* r, int B,
-                  double* part, double* out, unsigned* counters, hipStream_t s);
+                  double* part, double* out, hipStream_t s);
 int alpha_tables(Ctx* ctx, const Grid& g, const topo_mesh& m, const double* rho, int B,
                  double* a64, float* a32, hipStream_t s);
 
@@ -225,8 +225,16 @@ __global__ void k_rom_reduce(int k, int KP, int nchunks, int B, const double* __
     const int i = I * 16 + e / 16;
     const int j = J * 16 + e % 16;
     if (i >= k || j >= k || i > j) return;  // keep the upper triangle only
-    double s = 0.0;
-    for (int c = 0; c < nchunks; ++c) s += partials[(((size_t)b * nchunks + c) * npairs + p) * 256 + e];
+    // eight independent accumulators keep eight loads in flight; fixed combination order
+    const double* src = partials + ((size_t)b * nchunks * npairs + p) * 256 + e;
+    const size_t stride = (size_t)npairs * 256;
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int c = 0;
+    for (; c + 8 <= nchunks; c += 8)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc[q] += src[(size_t)(c + q) * stride];
+    for (; c < nchunks; ++c) acc[c & 7] += src[(size_t)c * stride];
+    const double s = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
     double* Kb = Khat + (size_t)b * k * k;
     Kb[(size_t)i * k + j] = s;
     Kb[(size_t)j * k + i] = s;
@@ -236,31 +244,44 @@ __global__ void k_rom_reduce(int k, int KP, int nchunks, int B, const double* __
 // out[b][j] = sum_i Phi[i][j] v[b][i] over free rows i (float64 accumulation).
 // grid.x: row chunks, grid.y: b.  Partials [b][chunk][k], reduced by k_colsum_reduce.
 // ----------------------------------------------------------------------------------
+// Threads form cw columns x (256 / cw) row phases (cw = k rounded up to a power of two,
+// at most 64), so small k still keeps every lane busy; two accumulators per thread.
 template <typename TP>
 __global__ __launch_bounds__(256) void k_phit_v(long long nrows, const TP* __restrict__ phi, int k,
                                                 int ldphi, const uint8_t* __restrict__ mask,
                                                 const double* __restrict__ v, long long vstride,
-                                                int rows_per_chunk, double* __restrict__ partials) {
-    __shared__ double red[4][64];
-    const int lane = threadIdx.x & 63;
-    const int rg = threadIdx.x >> 6;
+                                                int rows_per_chunk, int cw,
+                                                double* __restrict__ partials) {
+    __shared__ double red[256];
+    const int t = threadIdx.x;
+    const int cl = t % cw;
+    const int rp = t / cw;
+    const int nrp = 256 / cw;
     const int b = blockIdx.y;
     const long long r0 = (long long)blockIdx.x * rows_per_chunk;
     const long long r1 = min(r0 + rows_per_chunk, nrows);
     const double* vb = v + (size_t)b * vstride;
     double* dst = partials + ((size_t)b * gridDim.x + blockIdx.x) * k;
-    for (int c0 = 0; c0 < k; c0 += 64) {
-        const int col = c0 + lane;
-        double s = 0.0;
+    for (int c0 = 0; c0 < k; c0 += cw) {
+        const int col = c0 + cl;
+        double s0 = 0.0, s1 = 0.0;
         if (col < k) {
-            for (long long i = r0 + rg; i < r1; i += 4) {
-                if (mask[i]) continue;
-                s += (double)phi[(size_t)i * ldphi + col] * vb[i];
+            long long i = r0 + rp;
+            for (; i + nrp < r1; i += 2 * nrp) {
+                const double v0 = mask[i] ? 0.0 : vb[i];
+                const double v1 = mask[i + nrp] ? 0.0 : vb[i + nrp];
+                s0 += (double)phi[(size_t)i * ldphi + col] * v0;
+                s1 += (double)phi[(size_t)(i + nrp) * ldphi + col] * v1;
             }
+            if (i < r1) s0 += (double)phi[(size_t)i * ldphi + col] * (mask[i] ? 0.0 : vb[i]);
         }
-        red[rg][lane] = s;
+        red[t] = s0 + s1;
         __syncthreads();
-        if (rg == 0 && col < k) dst[col] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+        if (t < cw && c0 + t < k) {
+            double s = 0.0;
+            for (int q = 0; q < nrp; ++q) s += red[q * cw + t];
+            dst[c0 + t] = s;
+        }
         __syncthreads();
     }
 }
@@ -270,8 +291,14 @@ __global__ void k_colsum_reduce(int k, int nchunks, int B, const double* __restr
     const int gid = blockIdx.x * blockDim.x + threadIdx.x;
     if (gid >= B * k) return;
     const int b = gid / k, j = gid % k;
-    double s = 0.0;
-    for (int c = 0; c < nchunks; ++c) s += partials[((size_t)b * nchunks + c) * k + j];
+    const double* src = partials + (size_t)b * nchunks * k + j;
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int c = 0;
+    for (; c + 8 <= nchunks; c += 8)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc[q] += src[(size_t)(c + q) * k];
+    for (; c < nchunks; ++c) acc[c & 7] += src[(size_t)c * k];
+    const double s = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
     out[gid] = s;
 }
 
@@ -436,12 +463,17 @@ static int phit_v(Ctx* ctx, const Grid& g, const void* phi, int fp32, int k, int
                   double* partials, int nchunks, hipStream_t s) {
     const long long nrows = g.n_dofs;
     const int rpc = (int)((nrows + nchunks - 1) / nchunks);
-    if (fp32)
-        hipLaunchKernelGGL((k_phit_v<float>), dim3(nchunks, B), dim3(256), 0, s, nrows,
-                           (const float*)phi, k, ldphi, mask, v, vstride, rpc, partials);
-    else
-        hipLaunchKernelGGL((k_phit_v<double>), dim3(nchunks, B), dim3(256), 0, s, nrows,
-                           (const double*)phi, k, ldphi, mask, v, vstride, rpc, partials);
+    int cw = 1;
+    while (cw < k && cw < 64) cw *= 2;
+    {
+        TimedLaunch tl(ctx, KID_PHIT_V, s);
+        if (fp32)
+            hipLaunchKernelGGL((k_phit_v<float>), dim3(nchunks, B), dim3(256), 0, s, nrows,
+                               (const float*)phi, k, ldphi, mask, v, vstride, rpc, cw, partials);
+        else
+            hipLaunchKernelGGL((k_phit_v<double>), dim3(nchunks, B), dim3(256), 0, s, nrows,
+                               (const double*)phi, k, ldphi, mask, v, vstride, rpc, cw, partials);
+    }
     TOPO_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_colsum_reduce, dim3(grid_blocks((long long)B * k)), dim3(kBlock), 0, s, k,
                        nchunks, B, partials, out);
@@ -450,7 +482,7 @@ static int phit_v(Ctx* ctx, const Grid& g, const void* phi, int fp32, int k, int
 }
 
 static int phit_chunks(const Grid& g) {
-    long long c = g.n_dofs / 2048;
+    long long c = g.n_dofs / 256;
     return (int)std::max(1LL, std::min(c, 2048LL));
 }
 
@@ -473,8 +505,9 @@ static ContractPlan plan_contract(const Grid& g, int k, int B, bool f64, int cu)
     int ec = (int)((budget - fixed) / (2 * (size_t)ne * p.LS * esz + esz));
     ec = std::max(1, std::min(ec, 16));
     p.ec = ec;
-    // aim at ~8 blocks per CU overall
-    const long long want_blocks = 8LL * cu;
+    // aim at ~4 blocks per CU overall (each block writes npairs partial tiles, so more
+    // chunks only add reduction traffic)
+    const long long want_blocks = 4LL * cu;
     long long per_field = std::max(1LL, want_blocks / ((long long)B * p.groups));
     long long epw = (g.n_elems + per_field - 1) / per_field;
     epw = std::max<long long>(epw, ec);
@@ -492,6 +525,7 @@ static int launch_contract(Ctx* ctx, const Grid& g, const ContractPlan& p, const
     auto kern = k_rom_contract<DIM, TP, TC>;
     TOPO_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)p.lds_bytes));
+    TimedLaunch tl(ctx, KID_ROM_CONTRACT, s);
     hipLaunchKernelGGL(kern, dim3(p.nchunks, B, p.groups), dim3(WAVES * 64), p.lds_bytes, s, g, phi,
                        k, ldphi, p.KP, p.LS, mask, alpha, Ke, p.epw, p.ec, partials);
     TOPO_CHECK_LAUNCH();
@@ -557,8 +591,11 @@ int topo_rom_build(topo_ctx* ctx, const topo_mesh* mesh, const void* phi, int32_
     }
     if (rc) return rc;
     const size_t tot = (size_t)B * p.npairs * 256;
-    hipLaunchKernelGGL(k_rom_reduce, dim3(grid_blocks((long long)tot)), dim3(kBlock), 0, s, k, p.KP,
-                       p.nchunks, B, parts, Khat);
+    {
+        TimedLaunch tl(ctx, KID_ROM_REDUCE, s);
+        hipLaunchKernelGGL(k_rom_reduce, dim3(grid_blocks((long long)tot)), dim3(kBlock), 0, s, k, p.KP,
+                           p.nchunks, B, parts, Khat);
+    }
     TOPO_CHECK_LAUNCH();
     if (fhat) {
         rc = phit_v(ctx, g, phi, phi_fp32, k, ldphi, mask, f, 0, 1, fhat, pf, nc, s);
@@ -582,8 +619,12 @@ int topo_rom_solve(topo_ctx* ctx, int32_t k, int32_t B, const double* Khat, cons
     int rc = ar.commit(ctx, s);
     if (rc) return rc;
     int* stp = status ? (int*)status : st;
-    hipLaunchKernelGGL(k_chol, dim3(B), dim3(256), 0, s, k, Khat, L, stp);
+    {
+        TimedLaunch tl(ctx, KID_CHOL, s);
+        hipLaunchKernelGGL(k_chol, dim3(B), dim3(256), 0, s, k, Khat, L, stp);
+    }
     TOPO_CHECK_LAUNCH();
+    TimedLaunch tl(ctx, KID_CHOL_SOLVE, s);
     hipLaunchKernelGGL(k_chol_solve, dim3(B), dim3(256), k * sizeof(double), s, k, L, fhat, 0LL, yhat,
                        0, (const double*)nullptr, fhat, Jk);
     TOPO_CHECK_LAUNCH();
@@ -620,13 +661,11 @@ int topo_rom_estimate(topo_ctx* ctx, const topo_mesh* mesh, const void* phi, int
     Arena ar;
     double *a64, *u, *r, *part, *out, *rhat, *L = nullptr, *pc, *ybest, *g2, *stepw;
     int *st = nullptr, *revert;
-    unsigned* counters;
     ar.take(&a64, (size_t)B * g.n_elems);
     ar.take(&u, (size_t)B * N);
     ar.take(&r, (size_t)B * N);
     ar.take(&part, (size_t)B * 3 * nb);
     ar.take(&out, (size_t)4 * B);
-    ar.take(&counters, (size_t)B);
     ar.take(&rhat, (size_t)B * k);
     ar.take(&pc, (size_t)B * nc * k);
     ar.take(&ybest, (size_t)B * k);
@@ -639,11 +678,11 @@ int topo_rom_estimate(topo_ctx* ctx, const topo_mesh* mesh, const void* phi, int
     }
     rc = ar.commit(ctx, s);
     if (rc) return rc;
-    TOPO_HIP(hipMemsetAsync(counters, 0, B * sizeof(unsigned), s));
     rc = alpha_tables(ctx, g, *mesh, rho, B, a64, nullptr, s);
     if (rc) return rc;
     // u = Phi y_hat, r = f - K u, ||r||^2 and f^T u per field
     auto pass = [&]() -> int {
+        TimedLaunch tl(ctx, KID_PHI_Y, s);
         if (phi_fp32)
             hipLaunchKernelGGL((k_phi_y<float>), dim3(grid_blocks(N), B), dim3(256), k * sizeof(double), s,
                                N, (const float*)phi, k, ldphi, mask, yhat, u);
@@ -651,7 +690,7 @@ int topo_rom_estimate(topo_ctx* ctx, const topo_mesh* mesh, const void* phi, int
             hipLaunchKernelGGL((k_phi_y<double>), dim3(grid_blocks(N), B), dim3(256), k * sizeof(double), s,
                                N, (const double*)phi, k, ldphi, mask, yhat, u);
         TOPO_CHECK_LAUNCH();
-        return residual_fp64(ctx, g, tb, a64, mask, u, f, r, B, part, out, counters, s);
+        return residual_fp64(ctx, g, tb, a64, mask, u, f, r, B, part, out, s);
     };
     // Galerkin residual r_hat = Phi^T r and its squared norm per field (read back)
     auto galerkin = [&](std::vector<double>& gh) -> int {

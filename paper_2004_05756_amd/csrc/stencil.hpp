@@ -44,14 +44,12 @@ struct FetchDirection {
     }
 };
 
-// out[c] = (K(rho) x)(node (i,j,k), c) with x given by `fetch` (zero outside the grid)
-// and alpha_e read from `alpha` (zero outside the grid).
+// 2D building blocks, split so that a caller can issue every load before it waits on
+// anything else: the 3x3 neighbourhood of node (i,j) (zero outside the grid) and the
+// alpha of the 2x2 elements around it (zero outside the grid).
 template <typename T, typename Fetch>
-__device__ __forceinline__ void node_apply2(const Grid& g, int i, int j,
-                                            const T* __restrict__ alpha,
-                                            const T* __restrict__ K, const Fetch& fetch,
-                                            T (&out)[2]) {
-    T xs[3][3][2];
+__device__ __forceinline__ void load_nbhd2(const Grid& g, int i, int j, const Fetch& fetch,
+                                           T (&xs)[3][3][2]) {
 #pragma unroll
     for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
@@ -62,6 +60,25 @@ __device__ __forceinline__ void node_apply2(const Grid& g, int i, int j,
             xs[dy][dx][0] = ok ? fetch(n, 0) : T(0);
             xs[dy][dx][1] = ok ? fetch(n, 1) : T(0);
         }
+}
+
+template <typename T>
+__device__ __forceinline__ void load_alpha2(const Grid& g, int i, int j, const T* __restrict__ alpha,
+                                            T (&al)[2][2]) {
+#pragma unroll
+    for (int ey = 0; ey < 2; ++ey)
+#pragma unroll
+        for (int ex = 0; ex < 2; ++ex) {
+            const int exx = i - 1 + ex, eyy = j - 1 + ey;
+            const bool ok = (exx >= 0) & (exx < g.nx) & (eyy >= 0) & (eyy < g.ny);
+            al[ey][ex] = ok ? alpha[eyy * g.nx + exx] : T(0);
+        }
+}
+
+// out[c] = (K(rho) x)(node, c) from its loaded neighbourhood and element alphas.
+template <typename T>
+__device__ __forceinline__ void apply_nbhd2(const T* __restrict__ K, T (&xs)[3][3][2],
+                                            const T (&al)[2][2], T (&out)[2]) {
     // K_e rows sum to zero per component (rigid translations), so each element vector
     // may be taken relative to this node's value: exact, and free of cancellation when
     // x is smooth.  Out-of-grid entries only meet alpha = 0.
@@ -80,9 +97,6 @@ __device__ __forceinline__ void node_apply2(const Grid& g, int i, int j,
     for (int ey = 0; ey < 2; ++ey)
 #pragma unroll
         for (int ex = 0; ex < 2; ++ex) {
-            const int exx = i - 1 + ex, eyy = j - 1 + ey;
-            const bool ok = (exx >= 0) & (exx < g.nx) & (eyy >= 0) & (eyy < g.ny);
-            const T al = ok ? alpha[eyy * g.nx + exx] : T(0);
             const int a = (1 - ex) + 2 * (1 - ey);  // local index of this node in e
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
@@ -94,9 +108,23 @@ __device__ __forceinline__ void node_apply2(const Grid& g, int i, int j,
                     s += row[2 * b] * xs[ey + by][ex + bx][0];
                     s += row[2 * b + 1] * xs[ey + by][ex + bx][1];
                 }
-                out[c] += al * s;
+                out[c] += al[ey][ex] * s;
             }
         }
+}
+
+// out[c] = (K(rho) x)(node (i,j,k), c) with x given by `fetch` (zero outside the grid)
+// and alpha_e read from `alpha` (zero outside the grid).
+template <typename T, typename Fetch>
+__device__ __forceinline__ void node_apply2(const Grid& g, int i, int j,
+                                            const T* __restrict__ alpha,
+                                            const T* __restrict__ K, const Fetch& fetch,
+                                            T (&out)[2]) {
+    T xs[3][3][2];
+    T al[2][2];
+    load_nbhd2(g, i, j, fetch, xs);
+    load_alpha2(g, i, j, alpha, al);
+    apply_nbhd2(K, xs, al, out);
 }
 
 template <typename T, typename Fetch>
