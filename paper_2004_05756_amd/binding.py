@@ -297,3 +297,164 @@ def context(device: int = 0) -> Context:
 
 def lib():
     return load()
+
+
+# ----------------------------------------------------------------------------------
+# Request server (include/topo_serve.h)
+# ----------------------------------------------------------------------------------
+REQ_HDM, REQ_ROM = 0, 1
+
+SERVE_EXPORTED = (
+    "topo_server_create", "topo_server_destroy", "topo_server_register_mesh",
+    "topo_server_register_basis", "topo_server_submit", "topo_server_wait", "topo_server_poll",
+    "topo_server_stats", "topo_server_last_error",
+)
+
+
+class TopoRequest(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("mesh_id", C.c_int32), ("basis_id", C.c_int32), ("k", C.c_int32),
+                ("prec", C.c_int32), ("max_refine", C.c_int32), ("maxit", C.c_int32),
+                ("rho_on_device", C.c_int32), ("rtol", C.c_double), ("rho", C.c_void_p)]
+
+
+class TopoResult(C.Structure):
+    _fields_ = [("status", C.c_int32), ("kind", C.c_int32), ("iters", C.c_int32), ("batch", C.c_int32),
+                ("worker", C.c_int32), ("pad", C.c_int32), ("J", C.c_double), ("resnorm", C.c_double),
+                ("t_submit", C.c_double), ("t_start", C.c_double), ("t_done", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "pad"}
+
+
+class TopoServeStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64),
+                ("jobs", C.c_int64), ("rom_jobs", C.c_int64), ("hdm_jobs", C.c_int64),
+                ("mean_rom_batch", C.c_double), ("budget_bytes", C.c_size_t),
+                ("held_bytes", C.c_size_t), ("max_held_bytes", C.c_size_t),
+                ("p50_latency_s", C.c_double * 2), ("p99_latency_s", C.c_double * 2),
+                ("workers", C.c_int32), ("pad", C.c_int32)]
+
+
+_SERVE_SIGS = {
+    "topo_server_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.c_size_t, C.c_int32, C.c_int32]),
+    "topo_server_destroy": (C.c_int, [_P]),
+    "topo_server_register_mesh": (C.c_int, [_P, C.POINTER(TopoMesh), _P, _P, C.POINTER(C.c_int32)]),
+    "topo_server_register_basis": (C.c_int, [_P, C.c_int32, _P, C.c_int32, C.c_int32, C.c_int32,
+                                             C.POINTER(C.c_int32)]),
+    "topo_server_submit": (C.c_int, [_P, C.POINTER(TopoRequest), C.POINTER(C.c_uint64)]),
+    "topo_server_wait": (C.c_int, [_P, C.c_uint64, C.POINTER(TopoResult)]),
+    "topo_server_poll": (C.c_int, [_P, C.c_uint64, C.POINTER(TopoResult)]),
+    "topo_server_stats": (C.c_int, [_P, C.POINTER(TopoServeStats)]),
+    "topo_server_last_error": (C.c_char_p, [_P]),
+}
+
+
+def _load_serve():
+    lib = load()
+    if not getattr(lib, "_serve_declared", False):
+        for name, (res, args) in _SERVE_SIGS.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        lib._serve_declared = True
+    return lib
+
+
+class Server:
+    """Continuous-batching request server (worker streams, HBM-budget admission,
+    fused ROM batches).  Registration takes host (numpy) arrays."""
+
+    def __init__(self, device=0, budget_bytes=16 << 30, max_batch=16, workers=4):
+        import numpy as np  # noqa: F401
+        self.lib = _load_serve()
+        h = C.c_void_p()
+        rc = self.lib.topo_server_create(C.byref(h), device, int(budget_bytes), int(max_batch), int(workers))
+        if rc != TOPO_OK:
+            raise TopoError(rc, "server creation")
+        self.h = h
+        self._meshes = {}
+
+    def _check(self, rc, what):
+        if rc != TOPO_OK:
+            raise TopoError(rc, f"{what}: {self.lib.topo_server_last_error(self.h).decode()}")
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.topo_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def register_mesh(self, mesh, mask, f):
+        import numpy as np
+        m = make_mesh(mesh)
+        mask = np.ascontiguousarray(mask, dtype=np.uint8)
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        mid = C.c_int32()
+        rc = self.lib.topo_server_register_mesh(self.h, C.byref(m), mask.ctypes.data, f.ctypes.data, C.byref(mid))
+        self._check(rc, "register_mesh")
+        self._meshes[mid.value] = mesh
+        return mid.value
+
+    def register_basis(self, mesh_id, phi, kmax=None):
+        import numpy as np
+        phi = np.ascontiguousarray(phi)
+        fp32 = 1 if phi.dtype == np.float32 else 0
+        if not fp32:
+            phi = np.ascontiguousarray(phi, dtype=np.float64)
+        kmax = int(kmax or phi.shape[1])
+        bid = C.c_int32()
+        rc = self.lib.topo_server_register_basis(self.h, int(mesh_id), phi.ctypes.data, fp32, kmax,
+                                                 int(phi.shape[1]), C.byref(bid))
+        self._check(rc, "register_basis")
+        return bid.value
+
+    def _submit(self, req, rho):
+        import numpy as np
+        t = C.c_uint64()
+        if hasattr(rho, "is_cuda") and rho.is_cuda:
+            req.rho = _ptr(rho, None, "rho")
+            req.rho_on_device = 1
+            keep = rho
+        else:
+            keep = np.ascontiguousarray(rho, dtype=np.float64)
+            req.rho = keep.ctypes.data
+            req.rho_on_device = 0
+        rc = self.lib.topo_server_submit(self.h, C.byref(req), C.byref(t))
+        del keep  # host densities are copied during submit
+        self._check(rc, "submit")
+        return t.value
+
+    def submit_hdm(self, mesh_id, rho, rtol=1e-10, prec=MIXED, maxit=0):
+        r = TopoRequest(kind=REQ_HDM, mesh_id=int(mesh_id), basis_id=-1, k=0, prec=int(prec), max_refine=0,
+                        maxit=int(maxit), rtol=float(rtol))
+        return self._submit(r, rho)
+
+    def submit_rom(self, mesh_id, basis_id, k, rho, prec=MIXED, max_refine=2):
+        r = TopoRequest(kind=REQ_ROM, mesh_id=int(mesh_id), basis_id=int(basis_id), k=int(k), prec=int(prec),
+                        max_refine=int(max_refine), maxit=0, rtol=0.0)
+        return self._submit(r, rho)
+
+    def wait(self, ticket):
+        res = TopoResult()
+        self.lib.topo_server_wait(self.h, C.c_uint64(ticket), C.byref(res))
+        return res.as_dict()
+
+    def poll(self, ticket):
+        res = TopoResult()
+        rc = self.lib.topo_server_poll(self.h, C.c_uint64(ticket), C.byref(res))
+        if rc == TOPO_EAGAIN:
+            return None
+        return res.as_dict()
+
+    def stats(self):
+        st = TopoServeStats()
+        self._check(self.lib.topo_server_stats(self.h, C.byref(st)), "stats")
+        d = {f: getattr(st, f) for f, _ in st._fields_ if f not in ("pad", "p50_latency_s", "p99_latency_s")}
+        d["p50_latency_s"] = {"hdm": st.p50_latency_s[0], "rom": st.p50_latency_s[1]}
+        d["p99_latency_s"] = {"hdm": st.p99_latency_s[0], "rom": st.p99_latency_s[1]}
+        return d

@@ -111,8 +111,7 @@ int set_error(Ctx* c, int code, const char* fmt, ...) {
 }
 
 int Arena::commit(Ctx* ctx, hipStream_t s) {
-    size_t total = 0;
-    for (auto& r : reqs) total += (r.bytes + 255) & ~size_t(255);
+    const size_t total = this->total();
     if (total > ctx->ws_bytes) {
         if (ctx->ws) {
             TOPO_HIP(hipStreamSynchronize(s));
@@ -121,7 +120,7 @@ int Arena::commit(Ctx* ctx, hipStream_t s) {
             ctx->ws = nullptr;
             ctx->ws_bytes = 0;
         }
-        size_t want = total + total / 4 + (1 << 20);
+        const size_t want = grown(total);
         if (hipMalloc(&ctx->ws, want) != hipSuccess) {
             (void)hipGetLastError();
             ctx->ws = nullptr;

@@ -601,37 +601,66 @@ static int residual_launch(Ctx* ctx, const Grid& g, const double* K64, const dou
     return TOPO_OK;
 }
 
+template <typename T>
+struct HdmWs {
+    double *a64, *w64, *r64, *part, *rpart, *rout;
+    T *b, *x, *r, *z, *p0, *p1, *q;
+    float *a32 = nullptr, *w32 = nullptr;
+    PcgState* st;
+};
+
+template <typename T>
+static void hdm_takes(Arena& ar, const Grid& g, bool mixed, HdmWs<T>& w) {
+    const long long N = g.n_dofs;
+    const int nb = grid_blocks(g.n_nodes);
+    ar.take(&w.a64, g.n_elems);
+    ar.take(&w.w64, g.n_nodes);
+    if (mixed) {
+        ar.take(&w.a32, g.n_elems);
+        ar.take(&w.w32, g.n_nodes);
+    }
+    ar.take(&w.r64, N);
+    ar.take(&w.part, 5 * (size_t)nb);
+    ar.take(&w.rpart, 3 * (size_t)nb);
+    ar.take(&w.rout, 4);
+    ar.take(&w.st, 1);
+    ar.take(&w.b, N);
+    ar.take(&w.x, N);
+    ar.take(&w.r, N);
+    ar.take(&w.z, N);
+    ar.take(&w.p0, N);
+    ar.take(&w.p1, N);
+    ar.take(&w.q, N);
+}
+
+size_t ws_hdm_solve(const Grid& g, bool mixed) {
+    Arena ar;
+    if (mixed) {
+        HdmWs<float> w;
+        hdm_takes(ar, g, true, w);
+    } else {
+        HdmWs<double> w;
+        hdm_takes(ar, g, false, w);
+    }
+    return ar.total();
+}
+
 template <int DIM, typename T>
 static int hdm_solve_impl(Ctx* ctx, const topo_mesh& m, const Grid& g, const ElemTables* tb,
                           const double* rho, const uint8_t* mask, const double* f, double* u,
                           double rtol, int maxit, bool mixed, double* compliance,
                           topo_info* info, hipStream_t s) {
     const long long N = g.n_dofs;
-    const int nb = grid_blocks(g.n_nodes);
     Arena ar;
-    double *a64, *w64, *r64, *part, *rpart, *rout;
-    T *b, *x, *r, *z, *p0, *p1, *q;
-    float *a32 = nullptr, *w32 = nullptr;
-    PcgState* st;
-    ar.take(&a64, g.n_elems);
-    ar.take(&w64, g.n_nodes);
-    if (mixed) {
-        ar.take(&a32, g.n_elems);
-        ar.take(&w32, g.n_nodes);
-    }
-    ar.take(&r64, N);
-    ar.take(&part, 5 * (size_t)nb);
-    ar.take(&rpart, 3 * (size_t)nb);
-    ar.take(&rout, 4);
-    ar.take(&st, 1);
-    ar.take(&b, N);
-    ar.take(&x, N);
-    ar.take(&r, N);
-    ar.take(&z, N);
-    ar.take(&p0, N);
-    ar.take(&p1, N);
-    ar.take(&q, N);
+    HdmWs<T> ws;
+    hdm_takes(ar, g, mixed, ws);
     int rc = ar.commit(ctx, s);
+    if (rc) return rc;
+    double *a64 = ws.a64, *w64 = ws.w64, *r64 = ws.r64, *part = ws.part, *rpart = ws.rpart,
+           *rout = ws.rout;
+    T *b = ws.b, *x = ws.x, *r = ws.r, *z = ws.z, *p0 = ws.p0, *p1 = ws.p1, *q = ws.q;
+    float *a32 = ws.a32, *w32 = ws.w32;
+    PcgState* st = ws.st;
     if (rc) return rc;
     rc = launch_tables(ctx, g, m, rho, 1, a64, a32, w64, w32, s);
     if (rc) return rc;

@@ -113,7 +113,20 @@ struct Arena {
     template <typename T>
     void take(T** out, size_t count) { reqs.push_back({(void**)out, count * sizeof(T)}); }
     int commit(Ctx* c, hipStream_t s);
+    // bytes the pending requests need, and what the arena allocates when it must grow
+    size_t total() const {
+        size_t t = 0;
+        for (const auto& r : reqs) t += (r.bytes + 255) & ~size_t(255);
+        return t;
+    }
+    static size_t grown(size_t total) { return total + total / 4 + (size_t(1) << 20); }
 };
+
+// Device workspace (bytes, before the arena's growth margin) of each entry point.
+size_t ws_hdm_solve(const Grid& g, bool mixed);
+size_t ws_rom_build(const Grid& g, int k, int B, bool f64, int cu);
+size_t ws_rom_solve(int k, int B);
+size_t ws_rom_estimate(const Grid& g, int k, int B, int max_refine);
 
 int pinned_host(Ctx* c, size_t bytes, void** out);
 const ElemTables* get_tables(Ctx* c, const topo_mesh& m);

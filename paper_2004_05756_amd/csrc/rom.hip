@@ -507,8 +507,11 @@ static ContractPlan plan_contract(const Grid& g, int k, int B, bool f64, int cu)
     p.ec = ec;
     // aim at ~4 blocks per CU overall (each block writes npairs partial tiles, so more
     // chunks only add reduction traffic)
+    // The chunking depends on the mesh, k and precision only -- never on B -- so a
+    // field's K_hat is bitwise the same alone and inside a batch.
+    (void)B;
     const long long want_blocks = 4LL * cu;
-    long long per_field = std::max(1LL, want_blocks / ((long long)B * p.groups));
+    long long per_field = std::max(1LL, want_blocks / (long long)p.groups);
     long long epw = (g.n_elems + per_field - 1) / per_field;
     epw = std::max<long long>(epw, ec);
     epw = (epw + ec - 1) / ec * ec;
@@ -763,3 +766,56 @@ int topo_rom_estimate(topo_ctx* ctx, const topo_mesh* mesh, const void* phi, int
 }
 
 }  // extern "C"
+
+// Device workspace of the ROM entry points; each mirrors the take sequence of the
+// corresponding call above (keep them in step).
+namespace topo {
+
+size_t ws_rom_build(const Grid& g, int k, int B, bool f64, int cu) {
+    const ContractPlan p = plan_contract(g, k, B, f64, cu);
+    const int nc = phit_chunks(g);
+    Arena ar;
+    double *a64, *parts, *pf;
+    float* a32;
+    if (f64) ar.take(&a64, (size_t)B * g.n_elems);
+    else ar.take(&a32, (size_t)B * g.n_elems);
+    ar.take(&parts, (size_t)B * p.nchunks * p.npairs * 256);
+    ar.take(&pf, (size_t)nc * k);
+    return ar.total();
+}
+
+size_t ws_rom_solve(int k, int B) {
+    Arena ar;
+    double* L;
+    int* st;
+    ar.take(&L, (size_t)B * k * k);
+    ar.take(&st, (size_t)B);
+    return ar.total();
+}
+
+size_t ws_rom_estimate(const Grid& g, int k, int B, int max_refine) {
+    const long long N = g.n_dofs;
+    const int nb = grid_blocks(g.n_nodes);
+    const int nc = phit_chunks(g);
+    Arena ar;
+    double *a64, *u, *r, *part, *out, *rhat, *L, *pc, *ybest, *g2, *stepw;
+    int *st, *revert;
+    ar.take(&a64, (size_t)B * g.n_elems);
+    ar.take(&u, (size_t)B * N);
+    ar.take(&r, (size_t)B * N);
+    ar.take(&part, (size_t)B * 3 * nb);
+    ar.take(&out, (size_t)4 * B);
+    ar.take(&rhat, (size_t)B * k);
+    ar.take(&pc, (size_t)B * nc * k);
+    ar.take(&ybest, (size_t)B * k);
+    ar.take(&g2, (size_t)B);
+    ar.take(&stepw, (size_t)B);
+    ar.take(&revert, (size_t)B);
+    if (max_refine > 0) {
+        ar.take(&L, (size_t)B * k * k);
+        ar.take(&st, (size_t)B);
+    }
+    return ar.total();
+}
+
+}  // namespace topo
