@@ -83,6 +83,10 @@ typedef struct topo_info {
     double rel_resid;       /* final true ||f - K u||_2 / ||f||_2 over free DOFs      */
     double compliance_raw;  /* f^T u                                                   */
     double compliance_corr; /* f^T u + u^T r = c* - ||u - u*||_K^2 (second order)    */
+    int32_t fp64_fallback;  /* TOPO_MIXED only: 1 when a float32 correction failed to  */
+                            /* reduce the true residual and the solve was redone in   */
+                            /* float64 from u = 0 (iters counts both attempts)        */
+    int32_t reserved;
 } topo_info;
 
 /* ---- context ------------------------------------------------------------------ */

@@ -40,10 +40,11 @@ class TopoMesh(C.Structure):
 
 class TopoInfo(C.Structure):
     _fields_ = [("iters", C.c_int32), ("refinements", C.c_int32), ("rel_resid", C.c_double),
-                ("compliance_raw", C.c_double), ("compliance_corr", C.c_double)]
+                ("compliance_raw", C.c_double), ("compliance_corr", C.c_double),
+                ("fp64_fallback", C.c_int32), ("reserved", C.c_int32)]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_}
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
 
 
 _P = C.c_void_p

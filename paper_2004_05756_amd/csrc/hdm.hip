@@ -649,8 +649,9 @@ template <int DIM, typename T>
 static int hdm_solve_impl(Ctx* ctx, const topo_mesh& m, const Grid& g, const ElemTables* tb,
                           const double* rho, const uint8_t* mask, const double* f, double* u,
                           double rtol, int maxit, bool mixed, double* compliance,
-                          topo_info* info, hipStream_t s) {
+                          topo_info* info, hipStream_t s, bool* stagnated) {
     const long long N = g.n_dofs;
+    if (stagnated) *stagnated = false;
     Arena ar;
     HdmWs<T> ws;
     hdm_takes(ar, g, mixed, ws);
@@ -721,6 +722,7 @@ static int hdm_solve_impl(Ctx* ctx, const topo_mesh& m, const Grid& g, const Ele
         }
         if (outer > 0 && !(rr < 0.9 * rr_prev)) {
             status = set_error(ctx, TOPO_ENOCONV, "refinement stagnated at rel. residual %.3e", rel);
+            if (stagnated) *stagnated = true;
             break;
         }
         const double nr = std::sqrt(rr);
@@ -734,6 +736,10 @@ static int hdm_solve_impl(Ctx* ctx, const topo_mesh& m, const Grid& g, const Ele
         rc = pcg_run<DIM, T>(ctx, g, w, tol_in, maxit - total, s, &fin);
         if (rc) return rc;
         total += fin.iters;
+        if (std::getenv("TOPO_DEBUG_PCG"))
+            fprintf(stderr, "[pcg] outer %d: inner %d its, done %d, inner rel %.3e (tol %.1e), outer rel %.3e\n",
+                    outer, fin.iters, fin.done, std::sqrt(fin.rr / std::max(fin.bb, 1e-300)), tol_in,
+                    std::sqrt(rr) / nf);
         if (fin.done == 3 && fin.iters == 0) {
             status = set_error(ctx, TOPO_ENOTSPD, "CG breakdown: p^T K p <= 0");
             break;
@@ -825,19 +831,33 @@ int topo_hdm_solve(topo_ctx* ctx, const topo_mesh* mesh, const double* rho, cons
     const ElemTables* tb = get_tables(ctx, *mesh);
     if (!tb) return set_error(ctx, TOPO_EDEVICE, "element table upload failed");
     hipStream_t s = (hipStream_t)stream;
-    const bool mixed = prec == TOPO_MIXED;
-    if (g.dim == 2) {
-        if (mixed)
-            return hdm_solve_impl<2, float>(ctx, *mesh, g, tb, rho, mask, f, u, rtol, maxit, true,
-                                            compliance, info, s);
-        return hdm_solve_impl<2, double>(ctx, *mesh, g, tb, rho, mask, f, u, rtol, maxit, false,
-                                         compliance, info, s);
-    }
-    if (mixed)
-        return hdm_solve_impl<3, float>(ctx, *mesh, g, tb, rho, mask, f, u, rtol, maxit, true,
-                                        compliance, info, s);
-    return hdm_solve_impl<3, double>(ctx, *mesh, g, tb, rho, mask, f, u, rtol, maxit, false,
-                                     compliance, info, s);
+    topo_info local{};
+    topo_info* inf = info ? info : &local;
+    *inf = topo_info{};
+    if (prec == TOPO_FP64)
+        return g.dim == 2 ? hdm_solve_impl<2, double>(ctx, *mesh, g, tb, rho, mask, f, u, rtol, maxit,
+                                                      false, compliance, inf, s, nullptr)
+                          : hdm_solve_impl<3, double>(ctx, *mesh, g, tb, rho, mask, f, u, rtol, maxit,
+                                                      false, compliance, inf, s, nullptr);
+    // mixed: float32 inner solves; if a float32 correction fails to reduce the true
+    // residual (float32 rounding too coarse for this operator), redo the solve in float64
+    bool stagnated = false;
+    rc = g.dim == 2 ? hdm_solve_impl<2, float>(ctx, *mesh, g, tb, rho, mask, f, u, rtol, maxit, true,
+                                               compliance, inf, s, &stagnated)
+                    : hdm_solve_impl<3, float>(ctx, *mesh, g, tb, rho, mask, f, u, rtol, maxit, true,
+                                               compliance, inf, s, &stagnated);
+    if (rc != TOPO_ENOCONV || !stagnated) return rc;
+    const topo_info first = *inf;
+    const int left = maxit - first.iters;
+    if (left < 1) return rc;
+    rc = g.dim == 2 ? hdm_solve_impl<2, double>(ctx, *mesh, g, tb, rho, mask, f, u, rtol, left, false,
+                                                compliance, inf, s, nullptr)
+                    : hdm_solve_impl<3, double>(ctx, *mesh, g, tb, rho, mask, f, u, rtol, left, false,
+                                                compliance, inf, s, nullptr);
+    inf->iters += first.iters;
+    inf->refinements += first.refinements;
+    inf->fp64_fallback = 1;
+    return rc;
 }
 
 int topo_hdm_gradient(topo_ctx* ctx, const topo_mesh* mesh, const double* rho, const double* u,
