@@ -43,11 +43,11 @@ __global__ void k_winv(Grid g, const double* __restrict__ a64, double* __restric
 // ----------------------------------------------------------------------------------
 // Public apply: y_b = K(rho_b) x_b, Dirichlet rows and columns eliminated.
 // ----------------------------------------------------------------------------------
-template <int DIM, typename T>
-__global__ __launch_bounds__(kBlock) void k_apply(Grid g, const T* __restrict__ alpha,
-                                                  const T* __restrict__ K,
-                                                  const uint8_t* __restrict__ mask,
-                                                  const T* __restrict__ x, T* __restrict__ y) {
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_apply2(Grid g, const T* __restrict__ alpha,
+                                                   const T* __restrict__ K,
+                                                   const uint8_t* __restrict__ mask,
+                                                   const T* __restrict__ x, T* __restrict__ y) {
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= g.n_nodes) return;
     const size_t b = blockIdx.y;
@@ -57,11 +57,37 @@ __global__ __launch_bounds__(kBlock) void k_apply(Grid g, const T* __restrict__ 
     int i, j, k;
     node_ijk(g, n, i, j, k);
     FetchMasked<T> f{xb, mask, g.n_nodes};
-    T out[DIM];
-    if constexpr (DIM == 2) node_apply2<T>(g, i, j, ab, K, f, out);
-    else node_apply3<T>(g, i, j, k, ab, K, f, out);
+    T out[2];
+    node_apply2<T>(g, i, j, ab, K, f, out);
 #pragma unroll
-    for (int c = 0; c < DIM; ++c) {
+    for (int c = 0; c < 2; ++c) {
+        const size_t idx = (size_t)c * g.n_nodes + n;
+        yb[idx] = mask[idx] ? T(0) : out[c];
+    }
+}
+
+// 3D: one block per node tile (blockIdx.x), one field per blockIdx.y.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_apply3(Grid g, const T* __restrict__ alpha,
+                                                   const T* __restrict__ K,
+                                                   const uint8_t* __restrict__ mask,
+                                                   const T* __restrict__ x, T* __restrict__ y) {
+    __shared__ Tile3Lds<T> L;
+    const size_t b = blockIdx.y;
+    int i0, j0, k0, tx, ty, tz;
+    tile3_origin(g, blockIdx.x, i0, j0, k0);
+    tile3_thread(tx, ty, tz);
+    tile3_stage(g, i0, j0, k0, FetchMasked<T>{x + b * g.n_dofs, mask, g.n_nodes}, L);
+    tile3_load_alpha(g, i0, j0, k0, alpha + b * g.n_elems, L);
+    __syncthreads();
+    const int i = i0 + tx, j = j0 + ty, k = k0 + tz;
+    if (i >= g.nx1 || j >= g.ny1 || k >= g.nz1) return;
+    const int n = (k * g.ny1 + j) * g.nx1 + i;
+    T out[3];
+    tile3_compute(L, K, tx, ty, tz, out);
+    T* yb = y + b * g.n_dofs;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
         const size_t idx = (size_t)c * g.n_nodes + n;
         yb[idx] = mask[idx] ? T(0) : out[c];
     }
@@ -75,8 +101,10 @@ __global__ __launch_bounds__(kBlock) void k_apply(Grid g, const T* __restrict__ 
 //   k_pcg_update(iteration it): alpha = rz_it / pq; x += alpha p, r -= alpha q,
 //                 z = D^{-1} r; rz / rr partials of the next iteration.
 // Partials: part = [pq | rz(parity 0) | rz(parity 1) | rr(parity 0) | rr(parity 1)],
-// nb doubles each; iteration it writes rz/rr into parity it & 1 and reads the
-// current ones from parity (it + 1) & 1.  The PCG initialisation writes parity 1.
+// ps doubles apart; the apply writes one pq partial per stencil block (napp), the
+// initialisation and the update one rz / rr partial per node-linear block (nupd).
+// Iteration it writes rz/rr into parity it & 1 and reads the current ones from parity
+// (it + 1) & 1.  The PCG initialisation writes parity 1.
 // Block 0 alone writes the state record (done flag, iteration count, norms).
 // ----------------------------------------------------------------------------------
 struct PcgState {
@@ -88,9 +116,8 @@ struct PcgState {
     int pad;
 };
 
-__device__ __forceinline__ const double* part_pq(const double* p, int) { return p; }
-__device__ __forceinline__ double* part_rz(double* p, int nb, int parity) { return p + (1 + parity) * nb; }
-__device__ __forceinline__ double* part_rr(double* p, int nb, int parity) { return p + (3 + parity) * nb; }
+__device__ __forceinline__ double* part_rz(double* p, int ps, int parity) { return p + (1 + parity) * ps; }
+__device__ __forceinline__ double* part_rr(double* p, int ps, int parity) { return p + (3 + parity) * ps; }
 
 template <int DIM, typename T>
 __global__ __launch_bounds__(kBlock) void k_pcg_init(Grid g, const T* __restrict__ b,
@@ -98,7 +125,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_init(Grid g, const T* __restrict
                                                      T ik2, T* __restrict__ x, T* __restrict__ r,
                                                      T* __restrict__ z, T* __restrict__ p,
                                                      double* __restrict__ part, PcgState* st,
-                                                     int maxit) {
+                                                     int ps, int maxit) {
     __shared__ double lds[32];
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     double v[2] = {0.0, 0.0};
@@ -119,10 +146,9 @@ __global__ __launch_bounds__(kBlock) void k_pcg_init(Grid g, const T* __restrict
         }
     }
     block_reduce<2>(v, lds);
-    const int nb = gridDim.x;
     if (threadIdx.x == 0) {
-        part_rz(part, nb, 1)[blockIdx.x] = v[0];
-        part_rr(part, nb, 1)[blockIdx.x] = v[1];
+        part_rz(part, ps, 1)[blockIdx.x] = v[0];
+        part_rr(part, ps, 1)[blockIdx.x] = v[1];
         if (blockIdx.x == 0) {
             st->done = 0;
             st->iters = 0;
@@ -133,39 +159,17 @@ __global__ __launch_bounds__(kBlock) void k_pcg_init(Grid g, const T* __restrict
     }
 }
 
-template <int DIM, typename T>
-__global__ __launch_bounds__(kBlock) void k_pcg_apply(Grid g, const T* __restrict__ alpha,
-                                                      const T* __restrict__ K,
-                                                      const uint8_t* __restrict__ mask,
-                                                      const T* __restrict__ z,
-                                                      const T* __restrict__ p_old,
-                                                      T* __restrict__ p_new, T* __restrict__ q,
-                                                      double* __restrict__ part, PcgState* st,
-                                                      int parity, int first, double tol2) {
-    if (st->done) return;
-    __shared__ double lds[48];
-    const int nb = gridDim.x;
+// Stopping test and CG coefficient of an apply, from the update partials (every block
+// computes the same values).  Returns the done code; tb is beta.
+template <typename T>
+__device__ __forceinline__ int pcg_apply_scalars(double* part, PcgState* st, int ps, int nupd,
+                                                 int parity, int first, double tol2, T& tb,
+                                                 double* lds) {
     const int cur = (parity + 1) & 1;
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
-    const bool active = n < g.n_nodes;
-    int i = 0, j = 0, k = 0;
-    if (active) node_ijk(g, n, i, j, k);
-    // 2D: issue every load of this node before waiting on the scalar reduction
-    T zs[3][3][2], ps[3][3][2], al[2][2];
-    uint8_t mk[DIM];
-    if constexpr (DIM == 2) {
-        if (active) {
-            load_nbhd2(g, i, j, FetchPlain<T>{z, g.n_nodes}, zs);
-            load_nbhd2(g, i, j, FetchPlain<T>{p_old, g.n_nodes}, ps);
-            load_alpha2(g, i, j, alpha, al);
-#pragma unroll
-            for (int c = 0; c < DIM; ++c) mk[c] = mask[(size_t)c * g.n_nodes + n];
-        }
-    }
     // rr and rz of the current residual, rz of the previous one (one pass)
-    const double* arrs[3] = {part_rr(part, nb, cur), part_rz(part, nb, cur), part_rz(part, nb, parity)};
+    const double* arrs[3] = {part_rr(part, ps, cur), part_rz(part, ps, cur), part_rz(part, ps, parity)};
     double red[3];
-    block_sum_arrays<3>(arrs, nb, red, lds);
+    block_sum_arrays<3>(arrs, nupd, red, lds);
     const double rr = red[0];
     const double bb = first ? rr : st->bb;
     int code = 0;
@@ -177,39 +181,147 @@ __global__ __launch_bounds__(kBlock) void k_pcg_apply(Grid g, const T* __restric
         st->rr = rr;
         if (code) st->done = code;
     }
-    if (code) return;
-    const T tb = first ? T(0) : (T)(red[1] / red[2]);
+    tb = first ? T(0) : (T)(red[1] / red[2]);
+    return code;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_pcg_apply2(Grid g, const T* __restrict__ alpha,
+                                                       const T* __restrict__ K,
+                                                       const uint8_t* __restrict__ mask,
+                                                       const T* __restrict__ z,
+                                                       const T* __restrict__ p_old,
+                                                       T* __restrict__ p_new, T* __restrict__ q,
+                                                       double* __restrict__ part, PcgState* st,
+                                                       int ps, int nupd, int parity, int first,
+                                                       double tol2) {
+    if (st->done) return;
+    __shared__ double lds[48];
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool active = n < g.n_nodes;
+    int i = 0, j = 0, k = 0;
+    if (active) node_ijk(g, n, i, j, k);
+    // issue every load of this node before waiting on the scalar reduction
+    T zs[3][3][2], ps_[3][3][2], al[2][2];
+    uint8_t mk[2];
+    if (active) {
+        load_nbhd2(g, i, j, FetchPlain<T>{z, g.n_nodes}, zs);
+        load_nbhd2(g, i, j, FetchPlain<T>{p_old, g.n_nodes}, ps_);
+        load_alpha2(g, i, j, alpha, al);
+#pragma unroll
+        for (int c = 0; c < 2; ++c) mk[c] = mask[(size_t)c * g.n_nodes + n];
+    }
+    T tb;
+    if (pcg_apply_scalars(part, st, ps, nupd, parity, first, tol2, tb, lds)) return;
     double v[1] = {0.0};
     if (active) {
-        T out[DIM], pn[DIM];
-        if constexpr (DIM == 2) {
-            T xs[3][3][2];
+        T out[2], pn[2];
+        T xs[3][3][2];
 #pragma unroll
-            for (int dy = 0; dy < 3; ++dy)
+        for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
-                for (int dx = 0; dx < 3; ++dx)
+            for (int dx = 0; dx < 3; ++dx)
 #pragma unroll
-                    for (int c = 0; c < 2; ++c) xs[dy][dx][c] = zs[dy][dx][c] + tb * ps[dy][dx][c];
-            pn[0] = xs[1][1][0];
-            pn[1] = xs[1][1][1];
-            apply_nbhd2(K, xs, al, out);
-        } else {
-            FetchDirection<T> f{z, p_old, tb, g.n_nodes};
-            node_apply3<T>(g, i, j, k, alpha, K, f, out);
+                for (int c = 0; c < 2; ++c) xs[dy][dx][c] = zs[dy][dx][c] + tb * ps_[dy][dx][c];
+        pn[0] = xs[1][1][0];
+        pn[1] = xs[1][1][1];
+        apply_nbhd2(K, xs, al, out);
 #pragma unroll
-            for (int c = 0; c < DIM; ++c) {
-                const size_t idx = (size_t)c * g.n_nodes + n;
-                pn[c] = z[idx] + tb * p_old[idx];
-                mk[c] = mask[idx];
-            }
-        }
-#pragma unroll
-        for (int c = 0; c < DIM; ++c) {
+        for (int c = 0; c < 2; ++c) {
             const size_t idx = (size_t)c * g.n_nodes + n;
             const T qv = mk[c] ? T(0) : out[c];
             p_new[idx] = pn[c];
             q[idx] = qv;
             v[0] += (double)pn[c] * (double)qv;
+        }
+    }
+    block_reduce<1>(v, lds);
+    if (threadIdx.x == 0) part[blockIdx.x] = v[0];
+}
+
+// 3D: one block per node tile.  The tile's halo of z and p_old and its element alphas
+// are loaded into registers before the scalar reduction, then p_new = z + beta p_old is
+// formed once per halo node in LDS and the stencil runs from there.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_pcg_apply3(Grid g, const T* __restrict__ alpha,
+                                                       const T* __restrict__ K,
+                                                       const uint8_t* __restrict__ mask,
+                                                       const T* __restrict__ z,
+                                                       const T* __restrict__ p_old,
+                                                       T* __restrict__ p_new, T* __restrict__ q,
+                                                       double* __restrict__ part, PcgState* st,
+                                                       int ps, int nupd, int parity, int first,
+                                                       double tol2) {
+    if (st->done) return;
+    __shared__ Tile3Lds<T> L;
+    __shared__ double lds[48];
+    int i0, j0, k0, tx, ty, tz;
+    tile3_origin(g, blockIdx.x, i0, j0, k0);
+    tile3_thread(tx, ty, tz);
+    const int i = i0 + tx, j = j0 + ty, k = k0 + tz;
+    const bool active = (i < g.nx1) & (j < g.ny1) & (k < g.nz1);
+    const int n = active ? (k * g.ny1 + j) * g.nx1 + i : 0;
+    constexpr int RH = (H3N + kBlock - 1) / kBlock;
+    constexpr int RA = (E3N + kBlock - 1) / kBlock;
+    T zr[RH][3], pr[RH][3], ar[RA];
+    bool hv[RH];
+#pragma unroll
+    for (int r = 0; r < RH; ++r) {
+        const int qh = threadIdx.x + r * kBlock;
+        const int hn = qh < H3N ? tile3_halo_node(g, i0, j0, k0, qh) : -1;
+        hv[r] = hn >= 0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            zr[r][c] = hv[r] ? z[(size_t)c * g.n_nodes + hn] : T(0);
+            pr[r][c] = hv[r] ? p_old[(size_t)c * g.n_nodes + hn] : T(0);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < RA; ++r) {
+        const int qa = threadIdx.x + r * kBlock;
+        T a = T(0);
+        if (qa < E3N) {
+            const int ex = qa % E3X, ey = (qa / E3X) % E3Y, ez = qa / (E3X * E3Y);
+            const int exx = i0 - 1 + ex, eyy = j0 - 1 + ey, ezz = k0 - 1 + ez;
+            if ((exx >= 0) & (exx < g.nx) & (eyy >= 0) & (eyy < g.ny) & (ezz >= 0) & (ezz < g.nz))
+                a = alpha[((size_t)ezz * g.ny + eyy) * g.nx + exx];
+        }
+        ar[r] = a;
+    }
+    uint8_t mk[3] = {0, 0, 0};
+    if (active) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) mk[c] = mask[(size_t)c * g.n_nodes + n];
+    }
+    T tb;
+    if (pcg_apply_scalars(part, st, ps, nupd, parity, first, tol2, tb, lds)) return;
+#pragma unroll
+    for (int r = 0; r < RH; ++r) {
+        const int qh = threadIdx.x + r * kBlock;
+        if (qh < H3N) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) L.x[c][qh] = hv[r] ? zr[r][c] + tb * pr[r][c] : T(0);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < RA; ++r) {
+        const int qa = threadIdx.x + r * kBlock;
+        if (qa < E3N) L.al[qa] = ar[r];
+    }
+    __syncthreads();
+    double v[1] = {0.0};
+    if (active) {
+        T out[3];
+        tile3_compute(L, K, tx, ty, tz, out);
+        const int qc = ((tz + 1) * H3Y + (ty + 1)) * H3X + (tx + 1);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const size_t idx = (size_t)c * g.n_nodes + n;
+            const T pn = L.x[c][qc];
+            const T qv = mk[c] ? T(0) : out[c];
+            p_new[idx] = pn;
+            q[idx] = qv;
+            v[0] += (double)pn * (double)qv;
         }
     }
     block_reduce<1>(v, lds);
@@ -223,10 +335,9 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(Grid g, const T* __restri
                                                        const T* __restrict__ p,
                                                        const T* __restrict__ q,
                                                        double* __restrict__ part, PcgState* st,
-                                                       int parity) {
+                                                       int ps, int napp, int parity) {
     if (st->done) return;
     __shared__ double lds[32];
-    const int nb = gridDim.x;
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     const bool active = n < g.n_nodes;
     // issue this node's loads before waiting on the scalar reduction
@@ -242,9 +353,10 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(Grid g, const T* __restri
             qv[c] = q[i];
         }
     }
-    const double* arrs[2] = {part, part_rz(part, nb, (parity + 1) & 1)};
+    const double* arrs[2] = {part, part_rz(part, ps, (parity + 1) & 1)};
+    const int cnt[2] = {napp, (int)gridDim.x};
     double red[2];
-    block_sum_arrays<2>(arrs, nb, red, lds);
+    block_sum_arrays_n<2>(arrs, cnt, red, lds);
     const double pq = red[0];
     if (!(pq > 0.0) || !isfinite(pq)) {
         if (blockIdx.x == 0 && threadIdx.x == 0) st->done = 3;
@@ -268,8 +380,8 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(Grid g, const T* __restri
     }
     block_reduce<2>(v, lds);
     if (threadIdx.x == 0) {
-        part_rz(part, nb, parity)[blockIdx.x] = v[0];
-        part_rr(part, nb, parity)[blockIdx.x] = v[1];
+        part_rz(part, ps, parity)[blockIdx.x] = v[0];
+        part_rr(part, ps, parity)[blockIdx.x] = v[1];
         if (blockIdx.x == 0) st->iters = st->iters + 1;
     }
 }
@@ -279,40 +391,24 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(Grid g, const T* __restri
 // per-block partials of ||r||^2, f^T u and u^T r for every field (blockIdx.y);
 // k_residual_sum reduces them (one block per field) into out[4*b .. 4*b+2].
 // ----------------------------------------------------------------------------------
-template <int DIM>
-__global__ __launch_bounds__(kBlock) void k_residual(Grid g, const double* __restrict__ alpha,
-                                                     const double* __restrict__ K,
-                                                     const uint8_t* __restrict__ mask,
-                                                     const double* __restrict__ u,
-                                                     const double* __restrict__ f,
-                                                     double* __restrict__ r,
-                                                     double* __restrict__ part) {
-    __shared__ double lds[48];
-    const size_t b = blockIdx.y;
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
-    const double* ub = u + b * g.n_dofs;
-    const double* ab = alpha + b * g.n_elems;
-    double v[3] = {0.0, 0.0, 0.0};
-    if (n < g.n_nodes) {
-        int i, j, k;
-        node_ijk(g, n, i, j, k);
-        FetchPlain<double> fe{ub, g.n_nodes};
-        double o[DIM];
-        if constexpr (DIM == 2) node_apply2<double>(g, i, j, ab, K, fe, o);
-        else node_apply3<double>(g, i, j, k, ab, K, fe, o);
-#pragma unroll
-        for (int c = 0; c < DIM; ++c) {
-            const size_t idx = (size_t)c * g.n_nodes + n;
-            const bool fixed = mask[idx] != 0;
-            const double fi = fixed ? 0.0 : f[idx];
-            const double ui = ub[idx];
-            const double ri = fixed ? 0.0 : fi - o[c];
-            if (r) r[b * g.n_dofs + idx] = ri;
-            v[0] += ri * ri;
-            v[1] += fi * ui;
-            v[2] += ui * ri;
-        }
-    }
+// Residual, compliance and u^T r terms of one free DOF, accumulated into v.
+__device__ __forceinline__ double residual_dof(const uint8_t* __restrict__ mask,
+                                               const double* __restrict__ f,
+                                               const double* __restrict__ ub, double* rb,
+                                               size_t idx, double o, double (&v)[3]) {
+    const bool fixed = mask[idx] != 0;
+    const double fi = fixed ? 0.0 : f[idx];
+    const double ui = ub[idx];
+    const double ri = fixed ? 0.0 : fi - o;
+    if (rb) rb[idx] = ri;
+    v[0] += ri * ri;
+    v[1] += fi * ui;
+    v[2] += ui * ri;
+    return ri;
+}
+
+__device__ __forceinline__ void residual_partials(double (&v)[3], double* __restrict__ part,
+                                                  size_t b, double* lds) {
     block_reduce<3>(v, lds);
     const int nb = gridDim.x;
     double* pb = part + b * 3 * nb;
@@ -321,6 +417,61 @@ __global__ __launch_bounds__(kBlock) void k_residual(Grid g, const double* __res
         pb[nb + blockIdx.x] = v[1];
         pb[2 * nb + blockIdx.x] = v[2];
     }
+}
+
+__global__ __launch_bounds__(kBlock) void k_residual2(Grid g, const double* __restrict__ alpha,
+                                                      const double* __restrict__ K,
+                                                      const uint8_t* __restrict__ mask,
+                                                      const double* __restrict__ u,
+                                                      const double* __restrict__ f,
+                                                      double* __restrict__ r,
+                                                      double* __restrict__ part) {
+    __shared__ double lds[48];
+    const size_t b = blockIdx.y;
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    const double* ub = u + b * g.n_dofs;
+    double v[3] = {0.0, 0.0, 0.0};
+    if (n < g.n_nodes) {
+        int i, j, k;
+        node_ijk(g, n, i, j, k);
+        double o[2];
+        node_apply2<double>(g, i, j, alpha + b * g.n_elems, K, FetchPlain<double>{ub, g.n_nodes}, o);
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+            residual_dof(mask, f, ub, r ? r + b * g.n_dofs : nullptr, (size_t)c * g.n_nodes + n, o[c], v);
+    }
+    residual_partials(v, part, b, lds);
+}
+
+// 3D: one block per node tile.
+__global__ __launch_bounds__(kBlock) void k_residual3(Grid g, const double* __restrict__ alpha,
+                                                      const double* __restrict__ K,
+                                                      const uint8_t* __restrict__ mask,
+                                                      const double* __restrict__ u,
+                                                      const double* __restrict__ f,
+                                                      double* __restrict__ r,
+                                                      double* __restrict__ part) {
+    __shared__ Tile3Lds<double> L;
+    __shared__ double lds[48];
+    const size_t b = blockIdx.y;
+    const double* ub = u + b * g.n_dofs;
+    int i0, j0, k0, tx, ty, tz;
+    tile3_origin(g, blockIdx.x, i0, j0, k0);
+    tile3_thread(tx, ty, tz);
+    tile3_stage(g, i0, j0, k0, FetchPlain<double>{ub, g.n_nodes}, L);
+    tile3_load_alpha(g, i0, j0, k0, alpha + b * g.n_elems, L);
+    __syncthreads();
+    const int i = i0 + tx, j = j0 + ty, k = k0 + tz;
+    double v[3] = {0.0, 0.0, 0.0};
+    if (i < g.nx1 && j < g.ny1 && k < g.nz1) {
+        const int n = (k * g.ny1 + j) * g.nx1 + i;
+        double o[3];
+        tile3_compute(L, K, tx, ty, tz, o);
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            residual_dof(mask, f, ub, r ? r + b * g.n_dofs : nullptr, (size_t)c * g.n_nodes + n, o[c], v);
+    }
+    residual_partials(v, part, b, lds);
 }
 
 __global__ __launch_bounds__(kBlock) void k_residual_sum(int nb, const double* __restrict__ part,
@@ -442,32 +593,47 @@ static bool graphs_enabled() {
     return on;
 }
 
+// Launch geometry of the PCG kernels: node-linear blocks for the init / update, stencil
+// blocks for the apply, and the stride of the partial arrays.
+struct PcgGeom {
+    int nupd, napp, ps;
+};
+
+static PcgGeom pcg_geom(const Grid& g) {
+    return PcgGeom{grid_blocks(g.n_nodes), stencil_blocks(g), partial_stride(g)};
+}
+
 // One PCG iteration (apply + update) launched directly on stream s.
 template <int DIM, typename T>
-static void pcg_iteration(Ctx* ctx, const Grid& g, const PcgRun<DIM, T>& w, int nb, int parity,
-                          int first, double tol2, hipStream_t s, int timing) {
+static void pcg_iteration(Ctx* ctx, const Grid& g, const PcgRun<DIM, T>& w, const PcgGeom& pg,
+                          int parity, int first, double tol2, hipStream_t s, int timing) {
     T* pold = parity ? w.p1 : w.p0;
     T* pnew = parity ? w.p0 : w.p1;
     {
         TimedLaunch tl(ctx, KID_PCG_APPLY, s, timing);
-        hipLaunchKernelGGL((k_pcg_apply<DIM, T>), dim3(nb), dim3(kBlock), 0, s, g, w.alpha, w.K,
-                           w.mask, (const T*)w.z, (const T*)pold, pnew, w.q, w.part, w.st, parity,
-                           first, tol2);
+        if constexpr (DIM == 2)
+            hipLaunchKernelGGL((k_pcg_apply2<T>), dim3(pg.napp), dim3(kBlock), 0, s, g, w.alpha, w.K,
+                               w.mask, (const T*)w.z, (const T*)pold, pnew, w.q, w.part, w.st,
+                               pg.ps, pg.nupd, parity, first, tol2);
+        else
+            hipLaunchKernelGGL((k_pcg_apply3<T>), dim3(pg.napp), dim3(kBlock), 0, s, g, w.alpha, w.K,
+                               w.mask, (const T*)w.z, (const T*)pold, pnew, w.q, w.part, w.st,
+                               pg.ps, pg.nupd, parity, first, tol2);
     }
     {
         TimedLaunch tl(ctx, KID_PCG_UPDATE, s, timing);
-        hipLaunchKernelGGL((k_pcg_update<DIM, T>), dim3(nb), dim3(kBlock), 0, s, g, w.winv, w.ik[0],
-                           w.ik[1], w.ik[2], w.x, w.r, w.z, (const T*)pnew, (const T*)w.q, w.part,
-                           w.st, parity);
+        hipLaunchKernelGGL((k_pcg_update<DIM, T>), dim3(pg.nupd), dim3(kBlock), 0, s, g, w.winv,
+                           w.ik[0], w.ik[1], w.ik[2], w.x, w.r, w.z, (const T*)pnew, (const T*)w.q,
+                           w.part, w.st, pg.ps, pg.napp, parity);
     }
 }
 
 // Graph of CH iterations starting at parity 1 (CH even, so every replay continues
 // the parity sequence), captured on the context's private stream.
 template <int DIM, typename T>
-static int pcg_graph(Ctx* ctx, const Grid& g, const PcgRun<DIM, T>& w, int nb, double tol2, int CH,
-                     hipGraphExec_t* out) {
-    std::vector<uintptr_t> key = {(uintptr_t)DIM, sizeof(T), (uintptr_t)nb, (uintptr_t)CH,
+static int pcg_graph(Ctx* ctx, const Grid& g, const PcgRun<DIM, T>& w, const PcgGeom& pg,
+                     double tol2, int CH, hipGraphExec_t* out) {
+    std::vector<uintptr_t> key = {(uintptr_t)DIM, sizeof(T), (uintptr_t)pg.napp, (uintptr_t)CH,
                                   (uintptr_t)g.nx, (uintptr_t)g.ny, (uintptr_t)g.nz,
                                   (uintptr_t)w.alpha, (uintptr_t)w.K, (uintptr_t)w.mask,
                                   (uintptr_t)w.winv, (uintptr_t)w.x, (uintptr_t)w.r, (uintptr_t)w.z,
@@ -497,7 +663,7 @@ static int pcg_graph(Ctx* ctx, const Grid& g, const PcgRun<DIM, T>& w, int nb, d
     if (!ctx->capture_stream) TOPO_HIP(hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
     hipStream_t cs = ctx->capture_stream;
     TOPO_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-    for (int c = 0; c < CH; ++c) pcg_iteration<DIM, T>(ctx, g, w, nb, (1 + c) & 1, 0, tol2, cs, kTimeOff);
+    for (int c = 0; c < CH; ++c) pcg_iteration<DIM, T>(ctx, g, w, pg, (1 + c) & 1, 0, tol2, cs, kTimeOff);
     GraphEntry ge;
     hipError_t e1 = hipStreamEndCapture(cs, &ge.graph);
     if (e1 != hipSuccess) return set_error(ctx, TOPO_EDEVICE, "graph capture failed: %s", hipGetErrorString(e1));
@@ -510,22 +676,22 @@ static int pcg_graph(Ctx* ctx, const Grid& g, const PcgRun<DIM, T>& w, int nb, d
 template <int DIM, typename T>
 static int pcg_run(Ctx* ctx, const Grid& g, PcgRun<DIM, T>& w, double tol, int maxit,
                    hipStream_t s, PcgState* result) {
-    const int nb = grid_blocks(g.n_nodes);
+    const PcgGeom pg = pcg_geom(g);
     const double tol2 = tol * tol;
-    hipLaunchKernelGGL((k_pcg_init<DIM, T>), dim3(nb), dim3(kBlock), 0, s, g, w.b, w.winv,
-                       w.ik[0], w.ik[1], w.ik[2], w.x, w.r, w.z, w.p0, w.part, w.st, maxit);
+    hipLaunchKernelGGL((k_pcg_init<DIM, T>), dim3(pg.nupd), dim3(kBlock), 0, s, g, w.b, w.winv,
+                       w.ik[0], w.ik[1], w.ik[2], w.x, w.r, w.z, w.p0, w.part, w.st, pg.ps, maxit);
     TOPO_CHECK_LAUNCH();
     void* pin = nullptr;
     int rc = pinned_host(ctx, 2 * sizeof(PcgState), &pin);
     if (rc) return rc;
     PcgState* hs = (PcgState*)pin;
     // iteration 0 (parity 0) records ||b||; the rest continue at parity 1
-    pcg_iteration<DIM, T>(ctx, g, w, nb, 0, 1, tol2, s, kTimeSampled);
+    pcg_iteration<DIM, T>(ctx, g, w, pg, 0, 1, tol2, s, kTimeSampled);
     TOPO_CHECK_LAUNCH();
     constexpr int CH = 16;  // iterations per graph replay (even)
     hipGraphExec_t exec = nullptr;
     if (graphs_enabled()) {
-        rc = pcg_graph<DIM, T>(ctx, g, w, nb, tol2, CH, &exec);
+        rc = pcg_graph<DIM, T>(ctx, g, w, pg, tol2, CH, &exec);
         if (rc) return rc;
     }
     hipEvent_t ev[2];
@@ -545,10 +711,10 @@ static int pcg_run(Ctx* ctx, const Grid& g, PcgRun<DIM, T>& w, double tol, int m
         } else if (exec) {
             // timing sample: two directly launched, timed iterations (keeps the parity)
             for (int c = 0; c < 2; ++c, ++issued)
-                pcg_iteration<DIM, T>(ctx, g, w, nb, (int)(issued & 1), 0, tol2, s, kTimeForced);
+                pcg_iteration<DIM, T>(ctx, g, w, pg, (int)(issued & 1), 0, tol2, s, kTimeForced);
         } else {
             for (int c = 0; c < chunk; ++c, ++issued)
-                pcg_iteration<DIM, T>(ctx, g, w, nb, (int)(issued & 1), 0, tol2, s, kTimeSampled);
+                pcg_iteration<DIM, T>(ctx, g, w, pg, (int)(issued & 1), 0, tol2, s, kTimeSampled);
             if (chunk < 64) chunk *= 2;
         }
         ++replays;
@@ -585,15 +751,15 @@ static double mixed_inner_tol() {
 static int residual_launch(Ctx* ctx, const Grid& g, const double* K64, const double* alpha64,
                            const uint8_t* mask, const double* u, const double* f, double* r, int B,
                            double* part, double* out, hipStream_t s) {
-    const int nb = grid_blocks(g.n_nodes);
+    const int nb = stencil_blocks(g);
     {
         TimedLaunch tl(ctx, KID_RESIDUAL, s);
         if (g.dim == 2)
-            hipLaunchKernelGGL((k_residual<2>), dim3(nb, B), dim3(kBlock), 0, s, g, alpha64, K64,
-                               mask, u, f, r, part);
+            hipLaunchKernelGGL(k_residual2, dim3(nb, B), dim3(kBlock), 0, s, g, alpha64, K64, mask,
+                               u, f, r, part);
         else
-            hipLaunchKernelGGL((k_residual<3>), dim3(nb, B), dim3(kBlock), 0, s, g, alpha64, K64,
-                               mask, u, f, r, part);
+            hipLaunchKernelGGL(k_residual3, dim3(nb, B), dim3(kBlock), 0, s, g, alpha64, K64, mask,
+                               u, f, r, part);
     }
     TOPO_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_residual_sum, dim3(B), dim3(kBlock), 0, s, nb, (const double*)part, out);
@@ -612,7 +778,7 @@ struct HdmWs {
 template <typename T>
 static void hdm_takes(Arena& ar, const Grid& g, bool mixed, HdmWs<T>& w) {
     const long long N = g.n_dofs;
-    const int nb = grid_blocks(g.n_nodes);
+    const int nb = partial_stride(g);
     ar.take(&w.a64, g.n_elems);
     ar.take(&w.w64, g.n_nodes);
     if (mixed) {
@@ -795,21 +961,21 @@ int topo_apply(topo_ctx* ctx, const topo_mesh* mesh, const double* rho, const ui
     if (rc) return rc;
     rc = launch_tables(ctx, g, *mesh, rho, B, a64, a32, nullptr, nullptr, s);
     if (rc) return rc;
-    dim3 grid(grid_blocks(g.n_nodes), B);
+    dim3 grid(stencil_blocks(g), B);
     TimedLaunch tl(ctx, KID_APPLY, s);
     if (prec == TOPO_FP64) {
         if (g.dim == 2)
-            hipLaunchKernelGGL((k_apply<2, double>), grid, dim3(kBlock), 0, s, g, a64, tb->K64, mask,
+            hipLaunchKernelGGL((k_apply2<double>), grid, dim3(kBlock), 0, s, g, a64, tb->K64, mask,
                                (const double*)x, (double*)y);
         else
-            hipLaunchKernelGGL((k_apply<3, double>), grid, dim3(kBlock), 0, s, g, a64, tb->K64, mask,
+            hipLaunchKernelGGL((k_apply3<double>), grid, dim3(kBlock), 0, s, g, a64, tb->K64, mask,
                                (const double*)x, (double*)y);
     } else {
         if (g.dim == 2)
-            hipLaunchKernelGGL((k_apply<2, float>), grid, dim3(kBlock), 0, s, g, a32, tb->K32, mask,
+            hipLaunchKernelGGL((k_apply2<float>), grid, dim3(kBlock), 0, s, g, a32, tb->K32, mask,
                                (const float*)x, (float*)y);
         else
-            hipLaunchKernelGGL((k_apply<3, float>), grid, dim3(kBlock), 0, s, g, a32, tb->K32, mask,
+            hipLaunchKernelGGL((k_apply3<float>), grid, dim3(kBlock), 0, s, g, a32, tb->K32, mask,
                                (const float*)x, (float*)y);
     }
     TOPO_CHECK_LAUNCH();

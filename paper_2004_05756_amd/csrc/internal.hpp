@@ -206,6 +206,41 @@ inline int grid_blocks(long long n, int block = kBlock) {
     return (int)((n + block - 1) / block);
 }
 
+// 3D node tile of the stencil kernels: one block of kBlock threads per tile.
+constexpr int T3X = 16, T3Y = 4, T3Z = 4;
+static_assert(T3X * T3Y * T3Z == kBlock, "one thread per tile node");
+
+// Blocks of a node-stencil launch (apply, PCG apply, residual): one per node tile in
+// 3D, one per kBlock consecutive nodes in 2D.
+inline int stencil_blocks(const Grid& g) {
+    if (g.dim == 2) return grid_blocks(g.n_nodes);
+    return ((g.nx1 + T3X - 1) / T3X) * ((g.ny1 + T3Y - 1) / T3Y) * ((g.nz1 + T3Z - 1) / T3Z);
+}
+
+// Stride of the per-block partial arrays shared by the stencil and the node-linear
+// PCG kernels.
+inline int partial_stride(const Grid& g) {
+    const int a = stencil_blocks(g), b = grid_blocks(g.n_nodes);
+    return a > b ? a : b;
+}
+
+// Sum each of NV arrays (array q has n[q] doubles) in one pass, fixed order.
+template <int NV>
+__device__ inline void block_sum_arrays_n(const double* const (&a)[NV], const int (&n)[NV],
+                                          double (&out)[NV], double* lds /* >= NV*16 */) {
+    int nmax = 0;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        out[q] = 0.0;
+        nmax = n[q] > nmax ? n[q] : nmax;
+    }
+    for (int i = threadIdx.x; i < nmax; i += blockDim.x)
+#pragma unroll
+        for (int q = 0; q < NV; ++q)
+            if (i < n[q]) out[q] += a[q][i];
+    block_reduce<NV>(out, lds);
+}
+
 }  // namespace topo
 
 // The opaque handle of the C ABI is the context itself.

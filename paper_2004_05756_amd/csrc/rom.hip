@@ -659,7 +659,7 @@ int topo_rom_estimate(topo_ctx* ctx, const topo_mesh* mesh, const void* phi, int
     if (!tb) return set_error(ctx, TOPO_EDEVICE, "element table upload failed");
     hipStream_t s = (hipStream_t)stream;
     const long long N = g.n_dofs;
-    const int nb = grid_blocks(g.n_nodes);
+    const int nb = stencil_blocks(g);
     const int nc = phit_chunks(g);
     Arena ar;
     double *a64, *u, *r, *part, *out, *rhat, *L = nullptr, *pc, *ybest, *g2, *stepw;
@@ -795,7 +795,7 @@ size_t ws_rom_solve(int k, int B) {
 
 size_t ws_rom_estimate(const Grid& g, int k, int B, int max_refine) {
     const long long N = g.n_dofs;
-    const int nb = grid_blocks(g.n_nodes);
+    const int nb = stencil_blocks(g);
     const int nc = phit_chunks(g);
     Arena ar;
     double *a64, *u, *r, *part, *out, *rhat, *L, *pc, *ybest, *g2, *stepw;
