@@ -47,10 +47,10 @@ def parse():
 def pcg_bytes(n_dofs, n_nodes, n_elems, word):
     """Algorithmic HBM bytes of one launch of each PCG kernel (each array once).
     apply : read z, p_old (stencil), alpha, mask; write p_new, q
-    update: read/write x, r; write z; read p, q, 1/sum(alpha) per node"""
+    update: read/write x (float64), r; write z; read p, q, 1/sum(alpha) per node"""
     return {
         "pcg_apply": n_dofs * (4 * word + 1) + n_elems * word,
-        "pcg_update": n_dofs * 7 * word + n_nodes * word,
+        "pcg_update": n_dofs * (5 * word + 16) + n_nodes * word,
     }
 
 

@@ -379,6 +379,10 @@ class Server:
         if rc != TOPO_OK:
             raise TopoError(rc, f"{what}: {self.lib.topo_server_last_error(self.h).decode()}")
 
+    def last_error(self):
+        """Message of the last failed request or call ("" if none)."""
+        return self.lib.topo_server_last_error(self.h).decode()
+
     def close(self):
         if getattr(self, "h", None):
             self.lib.topo_server_destroy(self.h)

@@ -108,10 +108,12 @@ __global__ __launch_bounds__(kBlock) void k_apply3(Grid g, const T* __restrict__
 // Block 0 alone writes the state record (done flag, iteration count, norms).
 // ----------------------------------------------------------------------------------
 struct PcgState {
-    double bb;   // ||b||^2 (recorded by the first apply)
-    double rr;   // ||r||^2 at the last stopping test
-    int done;    // 0 running, 1 converged, 2 iteration limit, 3 breakdown
-    int iters;   // completed iterations
+    double bb;    // reference ||r||^2 of the stopping test (set by the first apply, or by
+                  // the host when a segment continues after a residual replacement)
+    double rr;    // ||r||^2 at the last stopping test
+    double tol2;  // the segment stops when rr <= tol2 * bb
+    int done;     // 0 running, 1 converged, 2 iteration limit, 3 breakdown
+    int iters;    // completed iterations (over all segments)
     int maxit;
     int pad;
 };
@@ -122,22 +124,21 @@ __device__ __forceinline__ double* part_rr(double* p, int ps, int parity) { retu
 template <int DIM, typename T>
 __global__ __launch_bounds__(kBlock) void k_pcg_init(Grid g, const T* __restrict__ b,
                                                      const T* __restrict__ winv, T ik0, T ik1,
-                                                     T ik2, T* __restrict__ x, T* __restrict__ r,
+                                                     T ik2, double* __restrict__ x, T* __restrict__ r,
                                                      T* __restrict__ z, T* __restrict__ p,
                                                      double* __restrict__ part, PcgState* st,
-                                                     int ps, int maxit) {
+                                                     int ps, int maxit, double tol2) {
     __shared__ double lds[32];
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
     double v[2] = {0.0, 0.0};
-    if (n < g.n_nodes) {
-        const T ik[3] = {ik0, ik1, ik2};
+    const T ik[3] = {ik0, ik1, ik2};
+    for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < g.n_nodes; n += gridDim.x * blockDim.x) {
         const T w = winv[n];
 #pragma unroll
         for (int c = 0; c < DIM; ++c) {
             const size_t i = (size_t)c * g.n_nodes + n;
             const T bi = b[i];
             const T zi = bi * w * ik[c];
-            x[i] = T(0);
+            x[i] = 0.0;
             r[i] = bi;
             z[i] = zi;
             p[i] = T(0);
@@ -155,6 +156,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_init(Grid g, const T* __restrict
             st->maxit = maxit;
             st->bb = 0.0;
             st->rr = 0.0;
+            st->tol2 = tol2;
         }
     }
 }
@@ -163,8 +165,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_init(Grid g, const T* __restrict
 // computes the same values).  Returns the done code; tb is beta.
 template <typename T>
 __device__ __forceinline__ int pcg_apply_scalars(double* part, PcgState* st, int ps, int nupd,
-                                                 int parity, int first, double tol2, T& tb,
-                                                 double* lds) {
+                                                 int parity, int first, T& tb, double* lds) {
     const int cur = (parity + 1) & 1;
     // rr and rz of the current residual, rz of the previous one (one pass)
     const double* arrs[3] = {part_rr(part, ps, cur), part_rz(part, ps, cur), part_rz(part, ps, parity)};
@@ -174,7 +175,7 @@ __device__ __forceinline__ int pcg_apply_scalars(double* part, PcgState* st, int
     const double bb = first ? rr : st->bb;
     int code = 0;
     if (!isfinite(rr)) code = 3;
-    else if (rr <= tol2 * bb) code = 1;
+    else if (rr <= st->tol2 * bb) code = 1;
     else if (st->iters >= st->maxit) code = 2;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         if (first) st->bb = rr;
@@ -185,6 +186,8 @@ __device__ __forceinline__ int pcg_apply_scalars(double* part, PcgState* st, int
     return code;
 }
 
+// 2D: grid-stride over nodes.  The loads of a thread's first node are issued before it
+// waits on the scalar reduction.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_pcg_apply2(Grid g, const T* __restrict__ alpha,
                                                        const T* __restrict__ K,
@@ -193,28 +196,27 @@ __global__ __launch_bounds__(kBlock) void k_pcg_apply2(Grid g, const T* __restri
                                                        const T* __restrict__ p_old,
                                                        T* __restrict__ p_new, T* __restrict__ q,
                                                        double* __restrict__ part, PcgState* st,
-                                                       int ps, int nupd, int parity, int first,
-                                                       double tol2) {
+                                                       int ps, int nupd, int parity, int first) {
     if (st->done) return;
     __shared__ double lds[48];
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
-    const bool active = n < g.n_nodes;
-    int i = 0, j = 0, k = 0;
-    if (active) node_ijk(g, n, i, j, k);
-    // issue every load of this node before waiting on the scalar reduction
+    const int stride = gridDim.x * blockDim.x;
+    int n = blockIdx.x * blockDim.x + threadIdx.x;
     T zs[3][3][2], ps_[3][3][2], al[2][2];
     uint8_t mk[2];
-    if (active) {
+    auto load = [&](int node) {
+        int i, j, k;
+        node_ijk(g, node, i, j, k);
         load_nbhd2(g, i, j, FetchPlain<T>{z, g.n_nodes}, zs);
         load_nbhd2(g, i, j, FetchPlain<T>{p_old, g.n_nodes}, ps_);
         load_alpha2(g, i, j, alpha, al);
 #pragma unroll
-        for (int c = 0; c < 2; ++c) mk[c] = mask[(size_t)c * g.n_nodes + n];
-    }
+        for (int c = 0; c < 2; ++c) mk[c] = mask[(size_t)c * g.n_nodes + node];
+    };
+    if (n < g.n_nodes) load(n);
     T tb;
-    if (pcg_apply_scalars(part, st, ps, nupd, parity, first, tol2, tb, lds)) return;
+    if (pcg_apply_scalars(part, st, ps, nupd, parity, first, tb, lds)) return;
     double v[1] = {0.0};
-    if (active) {
+    while (n < g.n_nodes) {
         T out[2], pn[2];
         T xs[3][3][2];
 #pragma unroll
@@ -234,6 +236,8 @@ __global__ __launch_bounds__(kBlock) void k_pcg_apply2(Grid g, const T* __restri
             q[idx] = qv;
             v[0] += (double)pn[c] * (double)qv;
         }
+        n += stride;
+        if (n < g.n_nodes) load(n);
     }
     block_reduce<1>(v, lds);
     if (threadIdx.x == 0) part[blockIdx.x] = v[0];
@@ -250,8 +254,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_apply3(Grid g, const T* __restri
                                                        const T* __restrict__ p_old,
                                                        T* __restrict__ p_new, T* __restrict__ q,
                                                        double* __restrict__ part, PcgState* st,
-                                                       int ps, int nupd, int parity, int first,
-                                                       double tol2) {
+                                                       int ps, int nrz, int parity, int first) {
     if (st->done) return;
     __shared__ Tile3Lds<T> L;
     __shared__ double lds[48];
@@ -294,7 +297,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_apply3(Grid g, const T* __restri
         for (int c = 0; c < 3; ++c) mk[c] = mask[(size_t)c * g.n_nodes + n];
     }
     T tb;
-    if (pcg_apply_scalars(part, st, ps, nupd, parity, first, tol2, tb, lds)) return;
+    if (pcg_apply_scalars(part, st, ps, nrz, parity, first, tb, lds)) return;
 #pragma unroll
     for (int r = 0; r < RH; ++r) {
         const int qh = threadIdx.x + r * kBlock;
@@ -330,31 +333,33 @@ __global__ __launch_bounds__(kBlock) void k_pcg_apply3(Grid g, const T* __restri
 
 template <int DIM, typename T>
 __global__ __launch_bounds__(kBlock) void k_pcg_update(Grid g, const T* __restrict__ winv,
-                                                       T ik0, T ik1, T ik2, T* __restrict__ x,
+                                                       T ik0, T ik1, T ik2, double* __restrict__ x,
                                                        T* __restrict__ r, T* __restrict__ z,
                                                        const T* __restrict__ p,
                                                        const T* __restrict__ q,
                                                        double* __restrict__ part, PcgState* st,
-                                                       int ps, int napp, int parity) {
+                                                       int ps, int npq, int nrz, int parity) {
     if (st->done) return;
     __shared__ double lds[32];
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
-    const bool active = n < g.n_nodes;
-    // issue this node's loads before waiting on the scalar reduction
-    T xv[DIM], rv[DIM], pv[DIM], qv[DIM], w = T(0);
-    if (active) {
-        w = winv[n];
+    const int stride = gridDim.x * blockDim.x;
+    int n = blockIdx.x * blockDim.x + threadIdx.x;
+    double xv[DIM];
+    T rv[DIM], pv[DIM], qv[DIM], w = T(0);
+    auto load = [&](int node) {
+        w = winv[node];
 #pragma unroll
         for (int c = 0; c < DIM; ++c) {
-            const size_t i = (size_t)c * g.n_nodes + n;
+            const size_t i = (size_t)c * g.n_nodes + node;
             xv[c] = x[i];
             rv[c] = r[i];
             pv[c] = p[i];
             qv[c] = q[i];
         }
-    }
+    };
+    // issue the first node's loads before waiting on the scalar reduction
+    if (n < g.n_nodes) load(n);
     const double* arrs[2] = {part, part_rz(part, ps, (parity + 1) & 1)};
-    const int cnt[2] = {napp, (int)gridDim.x};
+    const int cnt[2] = {npq, nrz};
     double red[2];
     block_sum_arrays_n<2>(arrs, cnt, red, lds);
     const double pq = red[0];
@@ -363,15 +368,85 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(Grid g, const T* __restri
         return;
     }
     const T a = (T)(red[1] / pq);
+    const T ik[3] = {ik0, ik1, ik2};
     double v[2] = {0.0, 0.0};
-    if (active) {
-        const T ik[3] = {ik0, ik1, ik2};
+    while (n < g.n_nodes) {
 #pragma unroll
         for (int c = 0; c < DIM; ++c) {
             const size_t i = (size_t)c * g.n_nodes + n;
-            x[i] = xv[c] + a * pv[c];
+            x[i] = xv[c] + (double)a * (double)pv[c];
             const T ri = rv[c] - a * qv[c];
             const T zi = ri * w * ik[c];
+            r[i] = ri;
+            z[i] = zi;
+            v[0] += (double)ri * (double)zi;
+            v[1] += (double)ri * (double)ri;
+        }
+        n += stride;
+        if (n < g.n_nodes) load(n);
+    }
+    block_reduce<2>(v, lds);
+    if (threadIdx.x == 0) {
+        part_rz(part, ps, parity)[blockIdx.x] = v[0];
+        part_rr(part, ps, parity)[blockIdx.x] = v[1];
+        if (blockIdx.x == 0) st->iters = st->iters + 1;
+    }
+}
+
+// In-place fixed-order sum of the per-block partials of large launches: a[0] = sum of
+// a[0..n), and likewise b when given (one block).  The consumer then reads 1 value
+// instead of every block summing all partials again.  Skipped once the recursion is
+// done: its producer did not run then, and summing again would count a[0] twice.
+__global__ __launch_bounds__(1024) void k_partials_sum(double* __restrict__ a,
+                                                       double* __restrict__ b, int n,
+                                                       const PcgState* st) {
+    if (st->done) return;
+    __shared__ double lds[32];
+    double v[2] = {0.0, 0.0};
+    constexpr int U = 8;  // loads in flight per thread
+    for (int i0 = threadIdx.x; i0 < n; i0 += U * blockDim.x) {
+        double ta[U], tb[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u * blockDim.x;
+            ta[u] = i < n ? a[i] : 0.0;
+            tb[u] = (b && i < n) ? b[i] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            v[0] += ta[u];
+            v[1] += tb[u];
+        }
+    }
+    block_reduce<2>(v, lds);
+    if (threadIdx.x == 0) {
+        a[0] = v[0];
+        if (b) b[0] = v[1];
+    }
+}
+
+// Residual replacement: the segment's correction has been added to u in float64 and
+// the true residual r64 = f - K u recomputed; the recursion continues from
+// r = scale * r64 (x restarts at 0, the search direction p is kept), so the Krylov
+// progress of the earlier segments is not lost.  Writes the rz / rr partials of the
+// replaced residual into parity `cur`, where the next apply reads them.
+template <int DIM, typename T>
+__global__ __launch_bounds__(kBlock) void k_pcg_replace(Grid g, const double* __restrict__ r64,
+                                                        double scale, const T* __restrict__ winv,
+                                                        T ik0, T ik1, T ik2, double* __restrict__ x,
+                                                        T* __restrict__ r, T* __restrict__ z,
+                                                        double* __restrict__ part, int ps, int cur) {
+    __shared__ double lds[32];
+    double v[2] = {0.0, 0.0};
+    const T ik[3] = {ik0, ik1, ik2};
+    for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < g.n_nodes; n += gridDim.x * blockDim.x) {
+        const T w = winv[n];
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            const size_t i = (size_t)c * g.n_nodes + n;
+            const T ri = (T)(scale * r64[i]);
+            const T zi = ri * w * ik[c];
+            x[i] = 0.0;
             r[i] = ri;
             z[i] = zi;
             v[0] += (double)ri * (double)zi;
@@ -380,9 +455,8 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(Grid g, const T* __restri
     }
     block_reduce<2>(v, lds);
     if (threadIdx.x == 0) {
-        part_rz(part, ps, parity)[blockIdx.x] = v[0];
-        part_rr(part, ps, parity)[blockIdx.x] = v[1];
-        if (blockIdx.x == 0) st->iters = st->iters + 1;
+        part_rz(part, ps, cur)[blockIdx.x] = v[0];
+        part_rr(part, ps, cur)[blockIdx.x] = v[1];
     }
 }
 
@@ -580,7 +654,8 @@ struct PcgRun {
     const uint8_t* mask;
     const T* winv;
     T ik[3];
-    T *b, *x, *r, *z, *p0, *p1, *q;
+    T *b, *r, *z, *p0, *p1, *q;
+    double* x;  // the segment's correction, accumulated in float64
     double* part;
     PcgState* st;
 };
@@ -594,19 +669,36 @@ static bool graphs_enabled() {
 }
 
 // Launch geometry of the PCG kernels: node-linear blocks for the init / update, stencil
-// blocks for the apply, and the stride of the partial arrays.
+// blocks for the apply, the stride of the partial arrays, and how many partials each
+// consumer sums (1 when a launch has more blocks than kPcgMaxBlocks: its partials are
+// then summed once by k_partials_sum).
 struct PcgGeom {
     int nupd, napp, ps;
+    int npq, nrz;  // partials read of the apply's pq and of the update's rz / rr
 };
 
 static PcgGeom pcg_geom(const Grid& g) {
-    return PcgGeom{grid_blocks(g.n_nodes), stencil_blocks(g), partial_stride(g)};
+    PcgGeom pg;
+    pg.nupd = grid_blocks(g.n_nodes);
+    pg.napp = stencil_blocks(g);
+    pg.ps = std::max(pg.nupd, pg.napp);
+    pg.npq = pg.napp > kPcgMaxBlocks ? 1 : pg.napp;
+    pg.nrz = pg.nupd > kPcgMaxBlocks ? 1 : pg.nupd;
+    return pg;
+}
+
+// Collapse the rz / rr partials of parity `par` written by a node-linear launch.
+static void pcg_sum_rz(const PcgGeom& pg, double* part, int par, const PcgState* st,
+                       hipStream_t s) {
+    if (pg.nrz == 1 && pg.nupd > 1)
+        hipLaunchKernelGGL(k_partials_sum, dim3(1), dim3(1024), 0, s, part + (1 + par) * (size_t)pg.ps,
+                           part + (3 + par) * (size_t)pg.ps, pg.nupd, st);
 }
 
 // One PCG iteration (apply + update) launched directly on stream s.
 template <int DIM, typename T>
 static void pcg_iteration(Ctx* ctx, const Grid& g, const PcgRun<DIM, T>& w, const PcgGeom& pg,
-                          int parity, int first, double tol2, hipStream_t s, int timing) {
+                          int parity, int first, hipStream_t s, int timing) {
     T* pold = parity ? w.p1 : w.p0;
     T* pnew = parity ? w.p0 : w.p1;
     {
@@ -614,34 +706,35 @@ static void pcg_iteration(Ctx* ctx, const Grid& g, const PcgRun<DIM, T>& w, cons
         if constexpr (DIM == 2)
             hipLaunchKernelGGL((k_pcg_apply2<T>), dim3(pg.napp), dim3(kBlock), 0, s, g, w.alpha, w.K,
                                w.mask, (const T*)w.z, (const T*)pold, pnew, w.q, w.part, w.st,
-                               pg.ps, pg.nupd, parity, first, tol2);
+                               pg.ps, pg.nrz, parity, first);
         else
             hipLaunchKernelGGL((k_pcg_apply3<T>), dim3(pg.napp), dim3(kBlock), 0, s, g, w.alpha, w.K,
                                w.mask, (const T*)w.z, (const T*)pold, pnew, w.q, w.part, w.st,
-                               pg.ps, pg.nupd, parity, first, tol2);
+                               pg.ps, pg.nrz, parity, first);
     }
+    if (pg.npq == 1 && pg.napp > 1)
+        hipLaunchKernelGGL(k_partials_sum, dim3(1), dim3(1024), 0, s, w.part, (double*)nullptr, pg.napp,
+                           (const PcgState*)w.st);
     {
         TimedLaunch tl(ctx, KID_PCG_UPDATE, s, timing);
         hipLaunchKernelGGL((k_pcg_update<DIM, T>), dim3(pg.nupd), dim3(kBlock), 0, s, g, w.winv,
                            w.ik[0], w.ik[1], w.ik[2], w.x, w.r, w.z, (const T*)pnew, (const T*)w.q,
-                           w.part, w.st, pg.ps, pg.napp, parity);
+                           w.part, w.st, pg.ps, pg.npq, pg.nrz, parity);
     }
+    pcg_sum_rz(pg, w.part, parity, w.st, s);
 }
 
 // Graph of CH iterations starting at parity 1 (CH even, so every replay continues
 // the parity sequence), captured on the context's private stream.
 template <int DIM, typename T>
 static int pcg_graph(Ctx* ctx, const Grid& g, const PcgRun<DIM, T>& w, const PcgGeom& pg,
-                     double tol2, int CH, hipGraphExec_t* out) {
+                     int CH, hipGraphExec_t* out) {
     std::vector<uintptr_t> key = {(uintptr_t)DIM, sizeof(T), (uintptr_t)pg.napp, (uintptr_t)CH,
                                   (uintptr_t)g.nx, (uintptr_t)g.ny, (uintptr_t)g.nz,
                                   (uintptr_t)w.alpha, (uintptr_t)w.K, (uintptr_t)w.mask,
                                   (uintptr_t)w.winv, (uintptr_t)w.x, (uintptr_t)w.r, (uintptr_t)w.z,
                                   (uintptr_t)w.p0, (uintptr_t)w.p1, (uintptr_t)w.q, (uintptr_t)w.part,
                                   (uintptr_t)w.st};
-    uint64_t tb;
-    std::memcpy(&tb, &tol2, sizeof tb);
-    key.push_back((uintptr_t)tb);
     for (int c = 0; c < 3; ++c) {
         double ikd = (double)w.ik[c];
         uint64_t ib;
@@ -663,7 +756,7 @@ static int pcg_graph(Ctx* ctx, const Grid& g, const PcgRun<DIM, T>& w, const Pcg
     if (!ctx->capture_stream) TOPO_HIP(hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
     hipStream_t cs = ctx->capture_stream;
     TOPO_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-    for (int c = 0; c < CH; ++c) pcg_iteration<DIM, T>(ctx, g, w, pg, (1 + c) & 1, 0, tol2, cs, kTimeOff);
+    for (int c = 0; c < CH; ++c) pcg_iteration<DIM, T>(ctx, g, w, pg, (1 + c) & 1, 0, cs, kTimeOff);
     GraphEntry ge;
     hipError_t e1 = hipStreamEndCapture(cs, &ge.graph);
     if (e1 != hipSuccess) return set_error(ctx, TOPO_EDEVICE, "graph capture failed: %s", hipGetErrorString(e1));
@@ -673,32 +766,46 @@ static int pcg_graph(Ctx* ctx, const Grid& g, const PcgRun<DIM, T>& w, const Pcg
     return TOPO_OK;
 }
 
+// Runs PCG iterations until the device state reports done.  fresh: initialise from
+// w.b (x = 0) with stopping tolerance tol and maxit, and run iteration 0 (which records
+// ||b||^2); otherwise continue a segment whose state (done = 0, bb, tol2) the host has
+// uploaded after a residual replacement, at iteration iters0.
 template <int DIM, typename T>
-static int pcg_run(Ctx* ctx, const Grid& g, PcgRun<DIM, T>& w, double tol, int maxit,
-                   hipStream_t s, PcgState* result) {
+static int pcg_run(Ctx* ctx, const Grid& g, PcgRun<DIM, T>& w, bool fresh, double tol, int maxit,
+                   int iters0, hipStream_t s, PcgState* result) {
     const PcgGeom pg = pcg_geom(g);
-    const double tol2 = tol * tol;
-    hipLaunchKernelGGL((k_pcg_init<DIM, T>), dim3(pg.nupd), dim3(kBlock), 0, s, g, w.b, w.winv,
-                       w.ik[0], w.ik[1], w.ik[2], w.x, w.r, w.z, w.p0, w.part, w.st, pg.ps, maxit);
-    TOPO_CHECK_LAUNCH();
     void* pin = nullptr;
     int rc = pinned_host(ctx, 2 * sizeof(PcgState), &pin);
     if (rc) return rc;
     PcgState* hs = (PcgState*)pin;
-    // iteration 0 (parity 0) records ||b||; the rest continue at parity 1
-    pcg_iteration<DIM, T>(ctx, g, w, pg, 0, 1, tol2, s, kTimeSampled);
+    long long issued;
+    if (fresh) {
+        hipLaunchKernelGGL((k_pcg_init<DIM, T>), dim3(pg.nupd), dim3(kBlock), 0, s, g, w.b, w.winv,
+                           w.ik[0], w.ik[1], w.ik[2], w.x, w.r, w.z, w.p0, w.part, w.st, pg.ps,
+                           maxit, tol * tol);
+        TOPO_CHECK_LAUNCH();
+        pcg_sum_rz(pg, w.part, 1, w.st, s);
+        // iteration 0 (parity 0) records ||b||; the rest continue at parity 1
+        pcg_iteration<DIM, T>(ctx, g, w, pg, 0, 1, s, kTimeSampled);
+        issued = 1;
+    } else {
+        issued = iters0;
+        if ((issued & 1) == 0) {  // graphs start at an odd iteration
+            pcg_iteration<DIM, T>(ctx, g, w, pg, 0, 0, s, kTimeSampled);
+            ++issued;
+        }
+    }
     TOPO_CHECK_LAUNCH();
     constexpr int CH = 16;  // iterations per graph replay (even)
     hipGraphExec_t exec = nullptr;
     if (graphs_enabled()) {
-        rc = pcg_graph<DIM, T>(ctx, g, w, pg, tol2, CH, &exec);
+        rc = pcg_graph<DIM, T>(ctx, g, w, pg, CH, &exec);
         if (rc) return rc;
     }
     hipEvent_t ev[2];
     TOPO_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
     TOPO_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
     bool pending[2] = {false, false};
-    long long issued = 1;
     long long replays = 0;
     int chunk = 4;
     int slot = 0;
@@ -711,10 +818,10 @@ static int pcg_run(Ctx* ctx, const Grid& g, PcgRun<DIM, T>& w, double tol, int m
         } else if (exec) {
             // timing sample: two directly launched, timed iterations (keeps the parity)
             for (int c = 0; c < 2; ++c, ++issued)
-                pcg_iteration<DIM, T>(ctx, g, w, pg, (int)(issued & 1), 0, tol2, s, kTimeForced);
+                pcg_iteration<DIM, T>(ctx, g, w, pg, (int)(issued & 1), 0, s, kTimeForced);
         } else {
             for (int c = 0; c < chunk; ++c, ++issued)
-                pcg_iteration<DIM, T>(ctx, g, w, pg, (int)(issued & 1), 0, tol2, s, kTimeSampled);
+                pcg_iteration<DIM, T>(ctx, g, w, pg, (int)(issued & 1), 0, s, kTimeSampled);
             if (chunk < 64) chunk *= 2;
         }
         ++replays;
@@ -739,11 +846,24 @@ static int pcg_run(Ctx* ctx, const Grid& g, PcgRun<DIM, T>& w, double tol, int m
     return TOPO_OK;
 }
 
-static double mixed_inner_tol() {
+// Largest ratio of true to recursive residual at the end of a segment for which the
+// recursion is continued after the residual replacement (else it restarts).
+static double replace_drift_max() {
     static double v = [] {
-        const char* e = std::getenv("TOPO_MIXED_INNER_TOL");
+        const char* e = std::getenv("TOPO_REPLACE_DRIFT");
+        return e ? std::atof(e) : 4.0;
+    }();
+    return v;
+}
+
+// Reduction of the residual a float32 segment aims for before its residual is replaced
+// by the float64 one (small enough to keep the replacements rare, large enough that the
+// float32 recursion has not drifted from the true residual).
+static double mixed_segment_tol() {
+    static double v = [] {
+        const char* e = std::getenv("TOPO_MIXED_SEGMENT_TOL");
         double t = e ? std::atof(e) : 0.0;
-        return t > 0.0 ? t : 1e-5;
+        return t > 0.0 ? t : 1e-2;
     }();
     return v;
 }
@@ -769,8 +889,8 @@ static int residual_launch(Ctx* ctx, const Grid& g, const double* K64, const dou
 
 template <typename T>
 struct HdmWs {
-    double *a64, *w64, *r64, *part, *rpart, *rout;
-    T *b, *x, *r, *z, *p0, *p1, *q;
+    double *a64, *w64, *r64, *part, *rpart, *rout, *x;
+    T *b, *r, *z, *p0, *p1, *q;
     float *a32 = nullptr, *w32 = nullptr;
     PcgState* st;
 };
@@ -825,7 +945,8 @@ static int hdm_solve_impl(Ctx* ctx, const topo_mesh& m, const Grid& g, const Ele
     if (rc) return rc;
     double *a64 = ws.a64, *w64 = ws.w64, *r64 = ws.r64, *part = ws.part, *rpart = ws.rpart,
            *rout = ws.rout;
-    T *b = ws.b, *x = ws.x, *r = ws.r, *z = ws.z, *p0 = ws.p0, *p1 = ws.p1, *q = ws.q;
+    T *b = ws.b, *r = ws.r, *z = ws.z, *p0 = ws.p0, *p1 = ws.p1, *q = ws.q;
+    double* x = ws.x;
     float *a32 = ws.a32, *w32 = ws.w32;
     PcgState* st = ws.st;
     if (rc) return rc;
@@ -857,13 +978,16 @@ static int hdm_solve_impl(Ctx* ctx, const topo_mesh& m, const Grid& g, const Ele
     w.st = st;
 
     TOPO_HIP(hipMemsetAsync(u, 0, N * sizeof(double), s));
+    // pinned host layout: [2 PcgState poll slots | 4 residual sums | PcgState upload]
+    const size_t pin_res = 2 * sizeof(PcgState);
+    const size_t pin_up = pin_res + 4 * sizeof(double);
     void* pin = nullptr;
+    rc = pinned_host(ctx, pin_up + sizeof(PcgState), &pin);
+    if (rc) return rc;
     auto residual = [&](double out[3]) -> int {
         int rc2 = residual_launch(ctx, g, tb->K64, a64, mask, u, f, r64, 1, rpart, rout, s);
         if (rc2) return rc2;
-        rc2 = pinned_host(ctx, 4 * sizeof(double) + 2 * sizeof(PcgState), &pin);
-        if (rc2) return rc2;
-        double* h = (double*)((char*)pin + 2 * sizeof(PcgState));
+        double* h = (double*)((char*)pin + pin_res);
         TOPO_HIP(hipMemcpyAsync(h, rout, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
         TOPO_HIP(hipStreamSynchronize(s));
         out[0] = h[0];
@@ -874,45 +998,74 @@ static int hdm_solve_impl(Ctx* ctx, const topo_mesh& m, const Grid& g, const Ele
     double res[3];
     rc = residual(res);
     if (rc) return rc;
+    // One Krylov recursion in precision T, cut into segments: each segment runs until
+    // its recursive residual has dropped by tol_seg, then its correction is added to u
+    // in float64, the true residual f - K u is recomputed in float64 and replaces the
+    // recursive one, and the recursion continues with the same search direction.  The
+    // inner system is scaled by 1 / ||f|| so that float32 values stay O(1).
     const double nf = std::sqrt(res[0]);
-    int total = 0, outer = 0, status = TOPO_OK;
+    const double scale = nf > 0.0 ? 1.0 / nf : 1.0;
+    const double seg_min = mixed ? mixed_segment_tol() : 0.0;
+    const PcgGeom pg = pcg_geom(g);
+    const int bl = grid_blocks(N);
+    const double drift_max = replace_drift_max();
+    int total = 0, base = 0, segments = 0, status = TOPO_OK;
+    bool fresh = true;
     double rr = res[0], rr_prev = INFINITY;
-    const int max_outer = 40;
+    PcgState fin{};
     while (true) {
         const double rel = nf > 0.0 ? std::sqrt(rr) / nf : 0.0;
         if (rel <= rtol) break;
-        if (total >= maxit || outer >= max_outer) {
+        if (total >= maxit || segments >= 400) {
             status = set_error(ctx, TOPO_ENOCONV, "no convergence: rel. residual %.3e after %d iterations",
                                rel, total);
             break;
         }
-        if (outer > 0 && !(rr < 0.9 * rr_prev)) {
-            status = set_error(ctx, TOPO_ENOCONV, "refinement stagnated at rel. residual %.3e", rel);
+        if (segments > 0 && !(rr < 0.5 * rr_prev)) {
+            status = set_error(ctx, TOPO_ENOCONV, "residual replacement stagnated at rel. residual %.3e", rel);
             if (stagnated) *stagnated = true;
             break;
         }
-        const double nr = std::sqrt(rr);
-        double tol_in = 0.5 * rtol * nf / nr;
-        if (mixed) tol_in = std::max(tol_in, mixed_inner_tol());
-        tol_in = std::max(tol_in, 1e-15);
-        const int bl = grid_blocks(N);
-        hipLaunchKernelGGL((k_scale_cast<T>), dim3(bl), dim3(kBlock), 0, s, N, r64, 1.0 / nr, b);
-        TOPO_CHECK_LAUNCH();
-        PcgState fin;
-        rc = pcg_run<DIM, T>(ctx, g, w, tol_in, maxit - total, s, &fin);
+        double tol_seg = std::max(0.5 * rtol * nf / std::sqrt(rr), seg_min);
+        tol_seg = std::min(std::max(tol_seg, 1e-15), 0.5);
+        if (fresh) {
+            hipLaunchKernelGGL((k_scale_cast<T>), dim3(bl), dim3(kBlock), 0, s, N, r64, scale, b);
+            TOPO_CHECK_LAUNCH();
+            base = total;
+            rc = pcg_run<DIM, T>(ctx, g, w, true, tol_seg, maxit - base, 0, s, &fin);
+        } else {
+            // state first (done = 0), so that the partial sums below are not skipped
+            PcgState* up = (PcgState*)((char*)pin + pin_up);
+            *up = PcgState{};
+            up->bb = rr * scale * scale;
+            up->rr = up->bb;
+            up->tol2 = tol_seg * tol_seg;
+            up->done = 0;
+            up->iters = fin.iters;
+            up->maxit = maxit - base;
+            TOPO_HIP(hipMemcpyAsync(st, up, sizeof(PcgState), hipMemcpyHostToDevice, s));
+            hipLaunchKernelGGL((k_pcg_replace<DIM, T>), dim3(pg.nupd), dim3(kBlock), 0, s, g,
+                               (const double*)r64, scale, w.winv, w.ik[0], w.ik[1], w.ik[2], x, r, z,
+                               part, pg.ps, (fin.iters + 1) & 1);
+            TOPO_CHECK_LAUNCH();
+            pcg_sum_rz(pg, part, (fin.iters + 1) & 1, st, s);
+            rc = pcg_run<DIM, T>(ctx, g, w, false, tol_seg, maxit - base, fin.iters, s, &fin);
+        }
         if (rc) return rc;
-        total += fin.iters;
+        const int seg_iters = base + fin.iters - total;
+        total = base + fin.iters;
         if (std::getenv("TOPO_DEBUG_PCG"))
-            fprintf(stderr, "[pcg] outer %d: inner %d its, done %d, inner rel %.3e (tol %.1e), outer rel %.3e\n",
-                    outer, fin.iters, fin.done, std::sqrt(fin.rr / std::max(fin.bb, 1e-300)), tol_in,
-                    std::sqrt(rr) / nf);
-        if (fin.done == 3 && fin.iters == 0) {
+            fprintf(stderr, "[pcg] segment %d (%s): %d its, done %d, recursive rel %.3e (tol %.1e), true rel before %.3e\n",
+                    segments, fresh ? "fresh" : "continued", seg_iters, fin.done,
+                    std::sqrt(fin.rr / std::max(fin.bb, 1e-300)), tol_seg, std::sqrt(rr) / nf);
+        if (fin.done == 3 && seg_iters == 0) {
             status = set_error(ctx, TOPO_ENOTSPD, "CG breakdown: p^T K p <= 0");
             break;
         }
-        hipLaunchKernelGGL((k_correct<T>), dim3(bl), dim3(kBlock), 0, s, N, u, x, nr);
+        hipLaunchKernelGGL((k_correct<double>), dim3(bl), dim3(kBlock), 0, s, N, u, (const double*)x,
+                           nf > 0.0 ? nf : 1.0);
         TOPO_CHECK_LAUNCH();
-        ++outer;
+        ++segments;
         rr_prev = rr;
         rc = residual(res);
         if (rc) return rc;
@@ -921,10 +1074,14 @@ static int hdm_solve_impl(Ctx* ctx, const topo_mesh& m, const Grid& g, const Ele
             status = set_error(ctx, TOPO_ENOTSPD, "CG breakdown: p^T K p <= 0");
             break;
         }
+        // continue the recursion only while it still tracks the true residual; a
+        // segment whose true residual drifted far from the recursive one restarts
+        const double drift = fin.rr > 0.0 ? std::sqrt(rr) * scale / std::sqrt(fin.rr) : INFINITY;
+        fresh = !(drift <= drift_max) || fin.done != 1;
     }
     if (info) {
         info->iters = total;
-        info->refinements = outer;
+        info->refinements = segments;
         info->rel_resid = nf > 0.0 ? std::sqrt(rr) / nf : 0.0;
         info->compliance_raw = res[1];
         info->compliance_corr = res[1] + res[2];

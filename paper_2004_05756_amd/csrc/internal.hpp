@@ -210,12 +210,21 @@ inline int grid_blocks(long long n, int block = kBlock) {
 constexpr int T3X = 16, T3Y = 4, T3Z = 4;
 static_assert(T3X * T3Y * T3Z == kBlock, "one thread per tile node");
 
+// Node tiles of a 3D grid.
+__host__ __device__ inline int stencil_tiles3(const Grid& g) {
+    return ((g.nx1 + T3X - 1) / T3X) * ((g.ny1 + T3Y - 1) / T3Y) * ((g.nz1 + T3Z - 1) / T3Z);
+}
+
 // Blocks of a node-stencil launch (apply, PCG apply, residual): one per node tile in
 // 3D, one per kBlock consecutive nodes in 2D.
 inline int stencil_blocks(const Grid& g) {
-    if (g.dim == 2) return grid_blocks(g.n_nodes);
-    return ((g.nx1 + T3X - 1) / T3X) * ((g.ny1 + T3Y - 1) / T3Y) * ((g.nz1 + T3Z - 1) / T3Z);
+    return g.dim == 2 ? grid_blocks(g.n_nodes) : stencil_tiles3(g);
 }
+
+// Largest block count of a PCG launch whose per-block partials every block of the next
+// kernel sums by itself; larger launches get one summing kernel in between, so that the
+// redundant sums never cost more than a few hundred kilobytes of cache reads per block.
+constexpr int kPcgMaxBlocks = 2048;
 
 // Stride of the per-block partial arrays shared by the stencil and the node-linear
 // PCG kernels.

@@ -57,13 +57,17 @@ def test_results_same_alone_and_in_the_mix():
     alone_srv = _server(max_batch=1, workers=1)
     recs, reqs = _setup(alone_srv)
     alone = _submit_all(alone_srv, recs, reqs)
+    errs = [alone_srv.last_error()]
     alone_srv.close()
     mix_srv = _server(max_batch=8, workers=4)
     recs2, _ = _setup(mix_srv)
     mix = _submit_all(mix_srv, recs2, reqs)
     st = mix_srv.stats()
+    errs.append(mix_srv.last_error())
     mix_srv.close()
-    assert all(r["status"] == 0 for r in alone + mix)
+    bad = [(i, req[0], req[4], a["status"], b["status"]) for i, (req, a, b) in enumerate(zip(reqs, alone, mix))
+           if a["status"] != 0 or b["status"] != 0]
+    assert not bad, (bad, errs)
     assert st["mean_rom_batch"] > 1.0  # fusion happened
     for (kind, which, rho, k, prec), a, b in zip(reqs, alone, mix):
         if kind == "hdm":
