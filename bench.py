@@ -41,6 +41,9 @@ def parse():
     ap.add_argument("--timing-every", type=int, default=4, help="sample one launch in N of each hot kernel")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the ROM evals/s and FP64 comparison legs")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving-stream leg")
+    ap.add_argument("--serving-requests", type=int, default=512)
+    ap.add_argument("--serving-workers", type=int, default=4)
     return ap.parse_args()
 
 
@@ -82,6 +85,137 @@ def cpu_baseline(cfg, phi_np, gpu_iters_per_step, n_dofs):
                    f"sensitivity, assembled-matrix ROM eval k={phi_np.shape[1]}), single thread; "
                    f"expressed as N_u x GPU PCG iterations per step / oracle step time"),
         "seconds": dt,
+    }
+
+
+def _pct(xs, q):
+    xs = sorted(xs)
+    return xs[min(len(xs) - 1, int(q * len(xs)))] if xs else None
+
+
+def serving_leg(args, torch, W, binding, FP64, MIXED):
+    """The serving workload: the seeded stream of ROM / HDM requests over four meshes,
+    (a) plain FP64 one request at a time through the context, (b) the continuous-
+    batching server in mixed precision with every request submitted at once
+    (saturation throughput), (c) the same server with Poisson arrivals at 0.7x the
+    FP64 sequential rate (latency under load).  Densities and bases are resident on
+    the device for (a); the server receives host densities (copied at submit)."""
+    dev = torch.device("cuda", 0)
+    cfgs = [W.config(nm) for nm in W.SERVING_MESHES]
+    kmax = 128
+    reqs = W.serving_stream(args.serving_requests, kmax=kmax)
+    pool = [[c.rho(i) for i in range(8)] for c in cfgs]
+    phis = [W.cosine_basis(c.problem.mesh, c.problem.mask, kmax, c.basis_seed, np.float32) for c in cfgs]
+    D = []
+    for c, phi, rp in zip(cfgs, phis, pool):
+        p = c.problem
+        D.append({"mask": torch.as_tensor(p.mask).to(dev), "f": torch.as_tensor(p.f).to(dev),
+                  "phi": torch.as_tensor(phi).to(dev),
+                  "rho": [torch.as_tensor(r).to(dev).view(1, -1) for r in rp]})
+
+    # (a) plain FP64, one at a time
+    ctx = binding.Context(0)
+
+    def run_fp64(q):
+        c, d = cfgs[q.mesh], D[q.mesh]
+        m = c.problem.mesh
+        rho = d["rho"][q.rho_id]
+        if q.kind == "hdm":
+            _, inf = ctx.hdm_solve(m, rho.view(-1), d["mask"], d["f"], rtol=c.rtol, prec=FP64)
+            return inf["compliance_corr"]
+        Kh, fh = ctx.rom_build(m, d["phi"], q.k, d["mask"], d["f"], rho, prec=FP64)
+        y, _ = ctx.rom_solve(Kh, fh)
+        _, J, _ = ctx.rom_estimate(m, d["phi"], q.k, d["mask"], d["f"], rho, Kh, y, max_refine=0)
+        return float(J[0])
+
+    seen = set()
+    for q in reqs:  # warm-up: one request of each (mesh, kind)
+        if (q.mesh, q.kind) not in seen:
+            seen.add((q.mesh, q.kind))
+            run_fp64(q)
+    torch.cuda.synchronize()
+    lat_a, J_a = [], []
+    for q in reqs:
+        t = time.perf_counter()
+        J_a.append(run_fp64(q))
+        torch.cuda.synchronize()
+        lat_a.append(time.perf_counter() - t)
+    fp64_rate = len(reqs) / sum(lat_a)
+    ctx.close()
+
+    # (b), (c) the server in mixed precision
+    srv = binding.Server(0, budget_bytes=32 << 30, max_batch=16, workers=args.serving_workers)
+    ids = []
+    for c, phi in zip(cfgs, phis):
+        p = c.problem
+        mid = srv.register_mesh(p.mesh, p.mask, p.f)
+        ids.append((mid, srv.register_basis(mid, phi)))
+
+    def submit(q):
+        c = cfgs[q.mesh]
+        mid, bid = ids[q.mesh]
+        rho = pool[q.mesh][q.rho_id]
+        if q.kind == "hdm":
+            return srv.submit_hdm(mid, rho, rtol=c.rtol, prec=MIXED)
+        return srv.submit_rom(mid, bid, q.k, rho, prec=MIXED, max_refine=2)
+
+    warm = []
+    seen = set()
+    for q in reqs:
+        if (q.mesh, q.kind) not in seen:
+            seen.add((q.mesh, q.kind))
+            warm.append(submit(q))
+    for t in warm:
+        srv.wait(t)
+    t0 = time.perf_counter()
+    res_b = [srv.wait(t) for t in [submit(q) for q in reqs]]
+    sat_s = time.perf_counter() - t0
+    arr = W.poisson_arrivals(len(reqs), 0.7 * fp64_rate)
+    tickets = []
+    t0 = time.perf_counter()
+    for q, ta in zip(reqs, arr):
+        dt = t0 + ta - time.perf_counter()
+        if dt > 0:
+            time.sleep(dt)
+        tickets.append(submit(q))
+    res_c = [srv.wait(t) for t in tickets]
+    st = srv.stats()
+    srv.close()
+
+    def lat(res, kind=None):
+        return [r["t_done"] - r["t_submit"] for r, q in zip(res, reqs) if kind in (None, q.kind)]
+
+    def rel_diff(kind):
+        d = [abs(r["J"] / ja - 1.0) for r, ja, q in zip(res_b, J_a, reqs) if q.kind == kind and ja != 0]
+        return max(d) if d else None
+
+    failed = sum(1 for r in res_b + res_c if r["status"] != 0)
+    # device-side overlap of the saturated run: summed job service time over makespan
+    busy = {kd: sum(r["t_done"] - r["t_start"] for r, q in zip(res_b, reqs) if q.kind == kd)
+            for kd in ("hdm", "rom")}
+    fp64_busy = {kd: sum(x for x, q in zip(lat_a, reqs) if q.kind == kd) for kd in ("hdm", "rom")}
+    ms = lambda x: None if x is None else 1e3 * x  # noqa: E731
+    return {
+        "requests": len(reqs),
+        "mix": {"meshes": list(W.SERVING_MESHES), "rom_frac": 0.8, "k": [8, kmax],
+                "hdm": sum(q.kind == "hdm" for q in reqs)},
+        "fp64_sequential": {"evals_per_s": fp64_rate, "p50_ms": ms(_pct(lat_a, 0.5)),
+                            "p99_ms": ms(_pct(lat_a, 0.99)), "service_s": fp64_busy},
+        "served_mixed_saturated": {"evals_per_s": len(reqs) / sat_s, "makespan_s": sat_s,
+                                   "p50_ms": ms(_pct(lat(res_b), 0.5)), "p99_ms": ms(_pct(lat(res_b), 0.99)),
+                                   "speedup_vs_fp64_sequential": (len(reqs) / sat_s) / fp64_rate,
+                                   "service_s": busy, "overlap": (busy["hdm"] + busy["rom"]) / sat_s},
+        "served_mixed_poisson": {"arrival_rate_per_s": 0.7 * fp64_rate,
+                                 "p50_ms": ms(_pct(lat(res_c), 0.5)), "p99_ms": ms(_pct(lat(res_c), 0.99)),
+                                 "p50_ms_rom": ms(_pct(lat(res_c, "rom"), 0.5)),
+                                 "p99_ms_rom": ms(_pct(lat(res_c, "rom"), 0.99)),
+                                 "p50_ms_hdm": ms(_pct(lat(res_c, "hdm"), 0.5)),
+                                 "p99_ms_hdm": ms(_pct(lat(res_c, "hdm"), 0.99))},
+        "max_rel_diff_vs_fp64": {"hdm_J": rel_diff("hdm"), "rom_Jk": rel_diff("rom")},
+        "mean_rom_batch": st["mean_rom_batch"],
+        "max_held_gb": st["max_held_bytes"] / 2**30,
+        "failed": failed,
+        "workers": args.serving_workers,
     }
 
 
@@ -237,6 +371,9 @@ def main():
                                     "p99_ms": 1e3 * lat[min(len(lat) - 1, int(0.99 * len(lat)))],
                                     "Jk": float(Je[0]), "resnorm": float(rn[0])}
         out["extra"] = extra
+
+    if not args.no_serving:
+        out["serving"] = serving_leg(args, torch, W, binding, FP64, MIXED)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, phi_np, iters / args.steps, m.n_dofs)

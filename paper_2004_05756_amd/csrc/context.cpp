@@ -278,7 +278,6 @@ int topo_ctx_destroy(topo_ctx* c) {
         if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
         if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
     }
-    if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
     for (auto& kv : c->tables) {
         (void)hipFree(kv.second.K64);
         (void)hipFree(kv.second.K32);

@@ -687,45 +687,73 @@ static PcgGeom pcg_geom(const Grid& g) {
     return pg;
 }
 
+
+// Where kernel launches go: directly onto a stream, or appended as kernel nodes (each
+// depending on the previous one) to a graph under construction.  Graphs are built
+// node by node rather than by stream capture, so that building one never interferes
+// with launches that other threads make at the same time.  Argument types must match
+// the kernel's parameters exactly.
+struct LaunchSink {
+    hipStream_t s = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphNode_t last = nullptr;
+    hipError_t err = hipSuccess;
+    template <typename... A>
+    void operator()(const void* fn, dim3 grid, dim3 block, A... args) {
+        void* ptrs[] = {(void*)&args...};
+        hipError_t e;
+        if (!graph) {
+            e = hipLaunchKernel(fn, grid, block, ptrs, 0, s);
+        } else {
+            hipKernelNodeParams kp{};
+            kp.func = const_cast<void*>(fn);
+            kp.gridDim = grid;
+            kp.blockDim = block;
+            kp.sharedMemBytes = 0;
+            kp.kernelParams = ptrs;
+            kp.extra = nullptr;
+            hipGraphNode_t node = nullptr;
+            e = hipGraphAddKernelNode(&node, graph, last ? &last : nullptr, last ? 1 : 0, &kp);
+            if (e == hipSuccess) last = node;
+        }
+        if (e != hipSuccess && err == hipSuccess) err = e;
+    }
+};
+
 // Collapse the rz / rr partials of parity `par` written by a node-linear launch.
-static void pcg_sum_rz(const PcgGeom& pg, double* part, int par, const PcgState* st,
-                       hipStream_t s) {
+static void pcg_sum_rz(const PcgGeom& pg, double* part, int par, const PcgState* st, LaunchSink& L) {
     if (pg.nrz == 1 && pg.nupd > 1)
-        hipLaunchKernelGGL(k_partials_sum, dim3(1), dim3(1024), 0, s, part + (1 + par) * (size_t)pg.ps,
-                           part + (3 + par) * (size_t)pg.ps, pg.nupd, st);
+        L((const void*)k_partials_sum, dim3(1), dim3(1024), part + (1 + par) * (size_t)pg.ps,
+          part + (3 + par) * (size_t)pg.ps, (int)pg.nupd, st);
 }
 
-// One PCG iteration (apply + update) launched directly on stream s.
+// One PCG iteration (apply + update).
 template <int DIM, typename T>
 static void pcg_iteration(Ctx* ctx, const Grid& g, const PcgRun<DIM, T>& w, const PcgGeom& pg,
-                          int parity, int first, hipStream_t s, int timing) {
-    T* pold = parity ? w.p1 : w.p0;
+                          int parity, int first, LaunchSink& L, int timing) {
+    const T* pold = parity ? w.p1 : w.p0;
     T* pnew = parity ? w.p0 : w.p1;
+    const T* zc = w.z;
     {
-        TimedLaunch tl(ctx, KID_PCG_APPLY, s, timing);
-        if constexpr (DIM == 2)
-            hipLaunchKernelGGL((k_pcg_apply2<T>), dim3(pg.napp), dim3(kBlock), 0, s, g, w.alpha, w.K,
-                               w.mask, (const T*)w.z, (const T*)pold, pnew, w.q, w.part, w.st,
-                               pg.ps, pg.nrz, parity, first);
-        else
-            hipLaunchKernelGGL((k_pcg_apply3<T>), dim3(pg.napp), dim3(kBlock), 0, s, g, w.alpha, w.K,
-                               w.mask, (const T*)w.z, (const T*)pold, pnew, w.q, w.part, w.st,
-                               pg.ps, pg.nrz, parity, first);
+        TimedLaunch tl(ctx, KID_PCG_APPLY, L.s, L.graph ? kTimeOff : timing);
+        const void* fn = DIM == 2 ? (const void*)k_pcg_apply2<T> : (const void*)k_pcg_apply3<T>;
+        L(fn, dim3(pg.napp), dim3(kBlock), g, w.alpha, w.K, w.mask, zc, pold, pnew, w.q, w.part, w.st,
+          (int)pg.ps, (int)pg.nrz, parity, first);
     }
     if (pg.npq == 1 && pg.napp > 1)
-        hipLaunchKernelGGL(k_partials_sum, dim3(1), dim3(1024), 0, s, w.part, (double*)nullptr, pg.napp,
-                           (const PcgState*)w.st);
+        L((const void*)k_partials_sum, dim3(1), dim3(1024), w.part, (double*)nullptr, (int)pg.napp,
+          (const PcgState*)w.st);
     {
-        TimedLaunch tl(ctx, KID_PCG_UPDATE, s, timing);
-        hipLaunchKernelGGL((k_pcg_update<DIM, T>), dim3(pg.nupd), dim3(kBlock), 0, s, g, w.winv,
-                           w.ik[0], w.ik[1], w.ik[2], w.x, w.r, w.z, (const T*)pnew, (const T*)w.q,
-                           w.part, w.st, pg.ps, pg.npq, pg.nrz, parity);
+        TimedLaunch tl(ctx, KID_PCG_UPDATE, L.s, L.graph ? kTimeOff : timing);
+        L((const void*)k_pcg_update<DIM, T>, dim3(pg.nupd), dim3(kBlock), g, w.winv, w.ik[0], w.ik[1],
+          w.ik[2], w.x, w.r, w.z, (const T*)pnew, (const T*)w.q, w.part, w.st, (int)pg.ps, (int)pg.npq,
+          (int)pg.nrz, parity);
     }
-    pcg_sum_rz(pg, w.part, parity, w.st, s);
+    pcg_sum_rz(pg, w.part, parity, w.st, L);
 }
 
 // Graph of CH iterations starting at parity 1 (CH even, so every replay continues
-// the parity sequence), captured on the context's private stream.
+// the parity sequence).
 template <int DIM, typename T>
 static int pcg_graph(Ctx* ctx, const Grid& g, const PcgRun<DIM, T>& w, const PcgGeom& pg,
                      int CH, hipGraphExec_t* out) {
@@ -753,14 +781,20 @@ static int pcg_graph(Ctx* ctx, const Grid& g, const PcgRun<DIM, T>& w, const Pcg
         }
         ctx->graphs.clear();
     }
-    if (!ctx->capture_stream) TOPO_HIP(hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
-    hipStream_t cs = ctx->capture_stream;
-    TOPO_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-    for (int c = 0; c < CH; ++c) pcg_iteration<DIM, T>(ctx, g, w, pg, (1 + c) & 1, 0, cs, kTimeOff);
     GraphEntry ge;
-    hipError_t e1 = hipStreamEndCapture(cs, &ge.graph);
-    if (e1 != hipSuccess) return set_error(ctx, TOPO_EDEVICE, "graph capture failed: %s", hipGetErrorString(e1));
-    TOPO_HIP(hipGraphInstantiateWithFlags(&ge.exec, ge.graph, 0));
+    TOPO_HIP(hipGraphCreate(&ge.graph, 0));
+    LaunchSink L;
+    L.graph = ge.graph;
+    for (int c = 0; c < CH; ++c) pcg_iteration<DIM, T>(ctx, g, w, pg, (1 + c) & 1, 0, L, kTimeOff);
+    if (L.err != hipSuccess) {
+        (void)hipGraphDestroy(ge.graph);
+        return set_error(ctx, TOPO_EDEVICE, "graph construction failed: %s", hipGetErrorString(L.err));
+    }
+    const hipError_t e1 = hipGraphInstantiateWithFlags(&ge.exec, ge.graph, 0);
+    if (e1 != hipSuccess) {
+        (void)hipGraphDestroy(ge.graph);
+        return set_error(ctx, TOPO_EDEVICE, "graph instantiation failed: %s", hipGetErrorString(e1));
+    }
     ctx->graphs[key] = ge;
     *out = ge.exec;
     return TOPO_OK;
@@ -778,24 +812,27 @@ static int pcg_run(Ctx* ctx, const Grid& g, PcgRun<DIM, T>& w, bool fresh, doubl
     int rc = pinned_host(ctx, 2 * sizeof(PcgState), &pin);
     if (rc) return rc;
     PcgState* hs = (PcgState*)pin;
+    LaunchSink L;
+    L.s = s;
     long long issued;
     if (fresh) {
         hipLaunchKernelGGL((k_pcg_init<DIM, T>), dim3(pg.nupd), dim3(kBlock), 0, s, g, w.b, w.winv,
                            w.ik[0], w.ik[1], w.ik[2], w.x, w.r, w.z, w.p0, w.part, w.st, pg.ps,
                            maxit, tol * tol);
         TOPO_CHECK_LAUNCH();
-        pcg_sum_rz(pg, w.part, 1, w.st, s);
+        pcg_sum_rz(pg, w.part, 1, w.st, L);
         // iteration 0 (parity 0) records ||b||; the rest continue at parity 1
-        pcg_iteration<DIM, T>(ctx, g, w, pg, 0, 1, s, kTimeSampled);
+        pcg_iteration<DIM, T>(ctx, g, w, pg, 0, 1, L, kTimeSampled);
         issued = 1;
     } else {
         issued = iters0;
         if ((issued & 1) == 0) {  // graphs start at an odd iteration
-            pcg_iteration<DIM, T>(ctx, g, w, pg, 0, 0, s, kTimeSampled);
+            pcg_iteration<DIM, T>(ctx, g, w, pg, 0, 0, L, kTimeSampled);
             ++issued;
         }
     }
     TOPO_CHECK_LAUNCH();
+    TOPO_HIP(L.err);
     constexpr int CH = 16;  // iterations per graph replay (even)
     hipGraphExec_t exec = nullptr;
     if (graphs_enabled()) {
@@ -818,14 +855,15 @@ static int pcg_run(Ctx* ctx, const Grid& g, PcgRun<DIM, T>& w, bool fresh, doubl
         } else if (exec) {
             // timing sample: two directly launched, timed iterations (keeps the parity)
             for (int c = 0; c < 2; ++c, ++issued)
-                pcg_iteration<DIM, T>(ctx, g, w, pg, (int)(issued & 1), 0, s, kTimeForced);
+                pcg_iteration<DIM, T>(ctx, g, w, pg, (int)(issued & 1), 0, L, kTimeForced);
         } else {
             for (int c = 0; c < chunk; ++c, ++issued)
-                pcg_iteration<DIM, T>(ctx, g, w, pg, (int)(issued & 1), 0, s, kTimeSampled);
+                pcg_iteration<DIM, T>(ctx, g, w, pg, (int)(issued & 1), 0, L, kTimeSampled);
             if (chunk < 64) chunk *= 2;
         }
         ++replays;
         TOPO_CHECK_LAUNCH();
+        TOPO_HIP(L.err);
         TOPO_HIP(hipMemcpyAsync(&hs[slot], w.st, sizeof(PcgState), hipMemcpyDeviceToHost, s));
         TOPO_HIP(hipEventRecord(ev[slot], s));
         pending[slot] = true;
@@ -842,7 +880,9 @@ static int pcg_run(Ctx* ctx, const Grid& g, PcgRun<DIM, T>& w, bool fresh, doubl
     TOPO_HIP(hipStreamSynchronize(s));
     TOPO_HIP(hipEventDestroy(ev[0]));
     TOPO_HIP(hipEventDestroy(ev[1]));
-    TOPO_HIP(hipMemcpy(result, w.st, sizeof(PcgState), hipMemcpyDeviceToHost));
+    TOPO_HIP(hipMemcpyAsync(&hs[0], w.st, sizeof(PcgState), hipMemcpyDeviceToHost, s));
+    TOPO_HIP(hipStreamSynchronize(s));
+    *result = hs[0];
     return TOPO_OK;
 }
 
@@ -1048,7 +1088,10 @@ static int hdm_solve_impl(Ctx* ctx, const topo_mesh& m, const Grid& g, const Ele
                                (const double*)r64, scale, w.winv, w.ik[0], w.ik[1], w.ik[2], x, r, z,
                                part, pg.ps, (fin.iters + 1) & 1);
             TOPO_CHECK_LAUNCH();
-            pcg_sum_rz(pg, part, (fin.iters + 1) & 1, st, s);
+            LaunchSink L;
+            L.s = s;
+            pcg_sum_rz(pg, part, (fin.iters + 1) & 1, st, L);
+            TOPO_HIP(L.err);
             rc = pcg_run<DIM, T>(ctx, g, w, false, tol_seg, maxit - base, fin.iters, s, &fin);
         }
         if (rc) return rc;

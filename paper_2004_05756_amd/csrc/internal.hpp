@@ -92,7 +92,6 @@ struct Ctx {
     int device = 0;
     Timing timing;
     std::map<std::vector<uintptr_t>, GraphEntry> graphs;
-    hipStream_t capture_stream = nullptr;  // private stream used only for graph capture
     std::string err;
     std::map<std::tuple<int, double, double, double, double, int>, ElemTables> tables;
     void* ws = nullptr;        // device workspace

@@ -27,7 +27,7 @@ __all__ = [
     "Mesh", "Problem", "mbb2d", "cantilever2d", "cantilever3d", "bridge3d",
     "paper_mbb", "paper_cantilever", "paper_ssbeam",
     "rho_jitter", "rho_smoothed", "rho_batch", "cosine_basis", "orthonormalize",
-    "config", "CONFIG_NAMES",
+    "config", "CONFIG_NAMES", "SERVING_MESHES", "ServingRequest", "serving_stream", "poisson_arrivals",
 ]
 
 
@@ -302,6 +302,43 @@ def orthonormalize(cols: np.ndarray, mask: np.ndarray, dtype=np.float64):
     a[mask.astype(bool), :] = 0.0
     q, _ = np.linalg.qr(a)
     return q.astype(dtype)
+
+
+# ---------------------------------------------------------------------------------
+# Request stream of the serving workload
+# ---------------------------------------------------------------------------------
+
+SERVING_MESHES = ("mbb2d_60x20", "cantilever2d_600x200", "cantilever3d_48x24x24",
+                  "cantilever3d_96x48x48")
+
+
+@dataclass
+class ServingRequest:
+    mesh: int     # index into SERVING_MESHES
+    kind: str     # "rom" or "hdm"
+    k: int        # ROM basis size (0 for HDM)
+    rho_id: int   # index into the per-mesh pool of density fields
+
+
+def serving_stream(n: int = 512, seed: int = 5150, rom_frac: float = 0.8, kmin: int = 8,
+                   kmax: int = 128, rho_pool: int = 8):
+    """Seeded request mix: mesh uniform over SERVING_MESHES, ROM with probability
+    rom_frac (k uniform in [kmin, kmax]), else HDM; densities drawn from a pool of
+    rho_pool smoothed fields per mesh."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        mesh = int(rng.integers(0, len(SERVING_MESHES)))
+        rom = bool(rng.random() < rom_frac)
+        k = int(rng.integers(kmin, kmax + 1)) if rom else 0
+        out.append(ServingRequest(mesh, "rom" if rom else "hdm", k, int(rng.integers(0, rho_pool))))
+    return out
+
+
+def poisson_arrivals(n: int, rate: float, seed: int = 5151):
+    """Arrival times (seconds from 0) of a Poisson process of the given rate."""
+    rng = np.random.default_rng(seed)
+    return np.cumsum(rng.exponential(1.0 / rate, n))
 
 
 # ---------------------------------------------------------------------------------
