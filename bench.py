@@ -22,6 +22,7 @@ import time
 
 import numpy as np
 
+ROOT = os.path.dirname(os.path.abspath(__file__))
 HBM_PEAK_GBS = 8000.0
 FP32_MFMA_PEAK_TFS = 157.3
 FP64_MFMA_PEAK_TFS = 78.6
@@ -44,6 +45,9 @@ def parse():
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-stream leg")
     ap.add_argument("--serving-requests", type=int, default=512)
     ap.add_argument("--serving-workers", type=int, default=4)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES bytes (5 times), the "
+                         "reference kernel that scales the HBM byte counters")
     return ap.parse_args()
 
 
@@ -55,6 +59,37 @@ def pcg_bytes(n_dofs, n_nodes, n_elems, word):
         "pcg_apply": n_dofs * (4 * word + 1) + n_elems * word,
         "pcg_update": n_dofs * (5 * word + 16) + n_nodes * word,
     }
+
+
+# Device sources of the PCG kernels: measured HBM traffic recorded under profiles/ is
+# used only while these files are unchanged since the counters were taken.
+KERNEL_SOURCES = ("paper_2004_05756_amd/csrc/hdm.hip", "paper_2004_05756_amd/csrc/stencil.hpp",
+                  "paper_2004_05756_amd/csrc/internal.hpp")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch of `kernel` from the rocprofv3 FETCH_SIZE / WRITE_SIZE
+    summary under profiles/ (each counter scaled by what it reads for a plain copy of
+    known size), or None when there is none or the kernel sources changed since."""
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("traffic-json: "):
+                rec = json.loads(line[len("traffic-json: "):]).get(kernel)
+                if rec and rec.get("source_hash") == kernel_source_hash():
+                    return rec["bytes_per_launch"]
+    return None
 
 
 def rom_contract_flops(n_elems, k, ne):
@@ -234,6 +269,15 @@ def main():
 
     if not torch.cuda.is_available():
         raise SystemExit("no GPU visible")
+    if args.calibrate_copy:
+        n = args.calibrate_copy // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": 4 * n, "launches": 5}))
+        return
     cfg = W.config(args.workload)
     p = cfg.problem
     m = p.mesh
@@ -307,10 +351,11 @@ def main():
     if dominant in pb:
         avg_s = ktimes[dominant]["avg_us"] * 1e-6
         gbs = pb[dominant] / avg_s / 1e9
+        kname = f"k_pcg_{dominant.split('_')[1]}{m.dim if dominant == 'pcg_apply' else ''}" \
+                f"<{'' if dominant == 'pcg_apply' else str(m.dim) + ','}{'float' if word == 4 else 'double'}>"
         roofline = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": gbs / HBM_PEAK_GBS, "traffic": None,
-                    "kernel": f"k_pcg_{dominant.split('_')[1]}<{m.dim},{'float' if word == 4 else 'double'}>",
-                    "bytes_per_launch": pb[dominant], "avg_us": ktimes[dominant]["avg_us"]}
+                    "frac": gbs / HBM_PEAK_GBS, "traffic": measured_traffic(cfg.name, kname),
+                    "kernel": kname, "bytes_per_launch": pb[dominant], "avg_us": ktimes[dominant]["avg_us"]}
     elif dominant == "rom_contract":
         ne = m.dim * 2 ** m.dim
         fl = rom_contract_flops(m.n_elems, k, ne)

@@ -185,13 +185,23 @@ static hipEvent_t timing_event(Ctx* c) {
     return e;
 }
 
-TimedLaunch::TimedLaunch(Ctx* ctx, int k, hipStream_t st, int mode) : c(ctx), kid(k), s(st) {
+TimedLaunch::TimedLaunch(Ctx* ctx, int k, hipStream_t st, int mode, bool ik)
+    : c(ctx), kid(k), s(st), in_kernel(ik) {
     if (!c || mode == kTimeOff) return;
     Timing& t = c->timing;
     if (t.every <= 0) return;
     if (t.seen[kid]++ % t.every != 0 && mode != kTimeForced) return;
     a = timing_event(c);
-    if (a && hipEventRecord(a, s) != hipSuccess) {
+    if (!a) return;
+    if (in_kernel) {
+        b = timing_event(c);
+        if (!b) {
+            t.pool.push_back(a);
+            a = nullptr;
+        }
+        return;
+    }
+    if (hipEventRecord(a, s) != hipSuccess) {
         t.pool.push_back(a);
         a = nullptr;
     }
@@ -199,11 +209,13 @@ TimedLaunch::TimedLaunch(Ctx* ctx, int k, hipStream_t st, int mode) : c(ctx), ki
 
 TimedLaunch::~TimedLaunch() {
     if (!a) return;
-    hipEvent_t b = timing_event(c);
-    if (!b || hipEventRecord(b, s) != hipSuccess) {
-        c->timing.pool.push_back(a);
-        if (b) c->timing.pool.push_back(b);
-        return;
+    if (!in_kernel) {
+        b = timing_event(c);
+        if (!b || hipEventRecord(b, s) != hipSuccess) {
+            c->timing.pool.push_back(a);
+            if (b) c->timing.pool.push_back(b);
+            return;
+        }
     }
     c->timing.pending.push_back({a, b, kid});
     if (c->timing.pending.size() > 8192) timing_drain(c);

@@ -11,6 +11,8 @@
 #include <cmath>
 #include <cstdlib>
 
+#include <hip/hip_ext.h>
+
 #include "stencil.hpp"
 
 namespace topo {
@@ -48,7 +50,7 @@ __global__ __launch_bounds__(kBlock) void k_apply2(Grid g, const T* __restrict__
                                                    const T* __restrict__ K,
                                                    const uint8_t* __restrict__ mask,
                                                    const T* __restrict__ x, T* __restrict__ y) {
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    const int n = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (n >= g.n_nodes) return;
     const size_t b = blockIdx.y;
     const T* xb = x + b * g.n_dofs;
@@ -75,7 +77,7 @@ __global__ __launch_bounds__(kBlock) void k_apply3(Grid g, const T* __restrict__
     __shared__ Tile3Lds<T> L;
     const size_t b = blockIdx.y;
     int i0, j0, k0, tx, ty, tz;
-    tile3_origin(g, blockIdx.x, i0, j0, k0);
+    tile3_origin(g, xcd_block(blockIdx.x, gridDim.x), i0, j0, k0);
     tile3_thread(tx, ty, tz);
     tile3_stage(g, i0, j0, k0, FetchMasked<T>{x + b * g.n_dofs, mask, g.n_nodes}, L);
     tile3_load_alpha(g, i0, j0, k0, alpha + b * g.n_elems, L);
@@ -200,7 +202,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_apply2(Grid g, const T* __restri
     if (st->done) return;
     __shared__ double lds[48];
     const int stride = gridDim.x * blockDim.x;
-    int n = blockIdx.x * blockDim.x + threadIdx.x;
+    int n = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     T zs[3][3][2], ps_[3][3][2], al[2][2];
     uint8_t mk[2];
     auto load = [&](int node) {
@@ -259,7 +261,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_apply3(Grid g, const T* __restri
     __shared__ Tile3Lds<T> L;
     __shared__ double lds[48];
     int i0, j0, k0, tx, ty, tz;
-    tile3_origin(g, blockIdx.x, i0, j0, k0);
+    tile3_origin(g, xcd_block(blockIdx.x, gridDim.x), i0, j0, k0);
     tile3_thread(tx, ty, tz);
     const int i = i0 + tx, j = j0 + ty, k = k0 + tz;
     const bool active = (i < g.nx1) & (j < g.ny1) & (k < g.nz1);
@@ -502,7 +504,7 @@ __global__ __launch_bounds__(kBlock) void k_residual2(Grid g, const double* __re
                                                       double* __restrict__ part) {
     __shared__ double lds[48];
     const size_t b = blockIdx.y;
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    const int n = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     const double* ub = u + b * g.n_dofs;
     double v[3] = {0.0, 0.0, 0.0};
     if (n < g.n_nodes) {
@@ -530,7 +532,7 @@ __global__ __launch_bounds__(kBlock) void k_residual3(Grid g, const double* __re
     const size_t b = blockIdx.y;
     const double* ub = u + b * g.n_dofs;
     int i0, j0, k0, tx, ty, tz;
-    tile3_origin(g, blockIdx.x, i0, j0, k0);
+    tile3_origin(g, xcd_block(blockIdx.x, gridDim.x), i0, j0, k0);
     tile3_thread(tx, ty, tz);
     tile3_stage(g, i0, j0, k0, FetchPlain<double>{ub, g.n_nodes}, L);
     tile3_load_alpha(g, i0, j0, k0, alpha + b * g.n_elems, L);
@@ -588,7 +590,7 @@ __global__ __launch_bounds__(kBlock) void k_gradient(Grid g, const double* __res
                                                      double* __restrict__ dc) {
     constexpr int NEN = 1 << DIM;
     constexpr int NE = DIM * NEN;
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    const int e = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (e >= g.n_elems) return;
     const int ex = e % g.nx;
     const int t = e / g.nx;
@@ -698,12 +700,17 @@ struct LaunchSink {
     hipGraph_t graph = nullptr;
     hipGraphNode_t last = nullptr;
     hipError_t err = hipSuccess;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;  // kernel start / end stamps of the next launch
     template <typename... A>
     void operator()(const void* fn, dim3 grid, dim3 block, A... args) {
         void* ptrs[] = {(void*)&args...};
         hipError_t e;
         if (!graph) {
-            e = hipLaunchKernel(fn, grid, block, ptrs, 0, s);
+            if (ev0)
+                e = hipExtLaunchKernel(fn, grid, block, ptrs, 0, s, ev0, ev1, 0);
+            else
+                e = hipLaunchKernel(fn, grid, block, ptrs, 0, s);
+            ev0 = ev1 = nullptr;
         } else {
             hipKernelNodeParams kp{};
             kp.func = const_cast<void*>(fn);
@@ -735,7 +742,9 @@ static void pcg_iteration(Ctx* ctx, const Grid& g, const PcgRun<DIM, T>& w, cons
     T* pnew = parity ? w.p0 : w.p1;
     const T* zc = w.z;
     {
-        TimedLaunch tl(ctx, KID_PCG_APPLY, L.s, L.graph ? kTimeOff : timing);
+        TimedLaunch tl(ctx, KID_PCG_APPLY, L.s, L.graph ? kTimeOff : timing, true);
+        L.ev0 = tl.a;
+        L.ev1 = tl.b;
         const void* fn = DIM == 2 ? (const void*)k_pcg_apply2<T> : (const void*)k_pcg_apply3<T>;
         L(fn, dim3(pg.napp), dim3(kBlock), g, w.alpha, w.K, w.mask, zc, pold, pnew, w.q, w.part, w.st,
           (int)pg.ps, (int)pg.nrz, parity, first);
@@ -744,7 +753,9 @@ static void pcg_iteration(Ctx* ctx, const Grid& g, const PcgRun<DIM, T>& w, cons
         L((const void*)k_partials_sum, dim3(1), dim3(1024), w.part, (double*)nullptr, (int)pg.napp,
           (const PcgState*)w.st);
     {
-        TimedLaunch tl(ctx, KID_PCG_UPDATE, L.s, L.graph ? kTimeOff : timing);
+        TimedLaunch tl(ctx, KID_PCG_UPDATE, L.s, L.graph ? kTimeOff : timing, true);
+        L.ev0 = tl.a;
+        L.ev1 = tl.b;
         L((const void*)k_pcg_update<DIM, T>, dim3(pg.nupd), dim3(kBlock), g, w.winv, w.ik[0], w.ik[1],
           w.ik[2], w.x, w.r, w.z, (const T*)pnew, (const T*)w.q, w.part, w.st, (int)pg.ps, (int)pg.npq,
           (int)pg.nrz, parity);

@@ -66,15 +66,19 @@ struct Timing {
 struct Ctx;
 void timing_drain(Ctx* c);
 
-// mode: kTimeOff never records (e.g. during graph capture), kTimeSampled records one
-// launch in `every`, kTimeForced records whenever timing is enabled.
+// mode: kTimeOff never records (e.g. while building a graph), kTimeSampled records one
+// launch in `every`, kTimeForced records whenever timing is enabled.  With in_kernel,
+// a sampled launch gets the event pair (a, b) to pass to hipExtLaunchKernel, which
+// stamps them when the kernel itself starts and ends (no marker packets around it);
+// otherwise a and b are recorded on the stream before and after the launch.
 enum { kTimeOff = 0, kTimeSampled = 1, kTimeForced = 2 };
 struct TimedLaunch {
     Ctx* c;
     int kid;
     hipStream_t s;
-    hipEvent_t a = nullptr;
-    TimedLaunch(Ctx* ctx, int kid, hipStream_t s, int mode = kTimeSampled);
+    bool in_kernel;
+    hipEvent_t a = nullptr, b = nullptr;
+    TimedLaunch(Ctx* ctx, int kid, hipStream_t s, int mode = kTimeSampled, bool in_kernel = false);
     ~TimedLaunch();
 };
 
@@ -203,6 +207,16 @@ __device__ inline double block_sum_array(const double* a, int n, double* lds) {
 
 inline int grid_blocks(long long n, int block = kBlock) {
     return (int)((n + block - 1) / block);
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs (block b runs on XCD b % 8),
+// and each XCD has its own L2.  Stencil kernels therefore map block b to the logical
+// tile / node range xcd_block(b, nb), which gives every XCD one contiguous eighth of
+// the grid, so that the halo rows a block re-reads are mostly in its own L2.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+    const int x = b % kXcds, q = nb / kXcds, r = nb % kXcds;
+    return x * q + (x < r ? x : r) + b / kXcds;
 }
 
 // 3D node tile of the stencil kernels: one block of kBlock threads per tile.
