@@ -1,4 +1,5 @@
 // Context, workspace arena, element tables and argument validation.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 
@@ -98,6 +99,95 @@ void element_stiffness(const topo_mesh& m, std::vector<double>& K) {
     }
 }
 
+bool element_factor(const topo_mesh& m, const std::vector<double>& K, std::vector<double>& F) {
+    const int dim = m.dim, nen = 1 << dim, ne = dim * nen;
+    auto H = [](int mm, int a) { return (__builtin_popcount(mm & a) & 1) ? -1.0 : 1.0; };
+    // Kt[(mm,c),(mp,d)] = nen^-2 sum_ab H[mm][a] K[(a,c),(b,d)] H[mp][b]
+    auto Kt = [&](int mm, int c, int mp, int d) {
+        double s = 0.0;
+        for (int a = 0; a < nen; ++a)
+            for (int b = 0; b < nen; ++b) s += H(mm, a) * K[(size_t)(dim * a + c) * ne + dim * b + d] * H(mp, b);
+        return s / (double)(nen * nen);
+    };
+    F.assign(kFacSize, 0.0);
+    for (int c = 0; c < dim; ++c) F[kFacH + c] = m.h[c];
+    // R rows, for the reconstruction check
+    std::vector<std::vector<double>> R;
+    for (int n = 0; n < nen; ++n) {
+        // block entries (n ^ e_c, c); reduction rows G (r x dim) over them
+        double B[3][3];
+        for (int c = 0; c < dim; ++c)
+            for (int d = 0; d < dim; ++d) B[c][d] = Kt(n ^ (1 << c), c, n ^ (1 << d), d);
+        double G[3][3] = {};
+        int r = 0;
+        const int pc = __builtin_popcount(n);
+        if (pc == 1) {  // a rigid translation: drop its component
+            for (int c = 0; c < dim; ++c)
+                if (n != (1 << c)) G[r++][c] = 1.0;
+        } else if (pc == 2) {  // a rigid rotation in the plane of the two set axes
+            int cd[2], q = 0;
+            for (int c = 0; c < dim; ++c)
+                if ((n >> c) & 1) cd[q++] = c;
+            G[r][cd[0]] = m.h[cd[0]];
+            G[r][cd[1]] = m.h[cd[1]];
+            ++r;
+            for (int c = 0; c < dim; ++c)
+                if (!((n >> c) & 1)) G[r++][c] = 1.0;
+        } else {
+            for (int c = 0; c < dim; ++c) G[r++][c] = 1.0;
+        }
+        // M = (G G^T)^-1 G B G^T (G G^T)^-1 (rows of G are orthogonal)
+        double gg[3], Mb[3][3];
+        for (int i = 0; i < r; ++i) {
+            gg[i] = 0.0;
+            for (int c = 0; c < dim; ++c) gg[i] += G[i][c] * G[i][c];
+        }
+        for (int i = 0; i < r; ++i)
+            for (int j = 0; j < r; ++j) {
+                double s = 0.0;
+                for (int c = 0; c < dim; ++c)
+                    for (int d = 0; d < dim; ++d) s += G[i][c] * B[c][d] * G[j][d];
+                Mb[i][j] = s / (gg[i] * gg[j]);
+            }
+        // Cholesky M = L L^T
+        double L[3][3] = {};
+        for (int i = 0; i < r; ++i)
+            for (int j = 0; j <= i; ++j) {
+                double s = Mb[i][j];
+                for (int q = 0; q < j; ++q) s -= L[i][q] * L[j][q];
+                if (i == j) {
+                    if (!(s > 0.0)) return false;
+                    L[i][i] = std::sqrt(s);
+                } else {
+                    L[i][j] = s / L[j][j];
+                }
+            }
+        const int slot[3][3] = {{0, 1, 2}, {-1, 3, 4}, {-1, -1, 5}};
+        for (int i = 0; i < r; ++i)
+            for (int j = i; j < r; ++j) F[6 * n + slot[i][j]] = L[j][i];  // (L^T)[i][j]
+        // rows of R: (L^T G)[i][c] times H[n ^ e_c][a] on DOF (a, c)
+        for (int i = 0; i < r; ++i) {
+            std::vector<double> row(ne, 0.0);
+            for (int c = 0; c < dim; ++c) {
+                double w = 0.0;
+                for (int j = i; j < r; ++j) w += L[j][i] * G[j][c];
+                for (int a = 0; a < nen; ++a) row[dim * a + c] += w * H(n ^ (1 << c), a);
+            }
+            R.push_back(row);
+        }
+    }
+    // K must equal R^T R, and every block must be closed under the reflections
+    double kmax = 0.0, err = 0.0;
+    for (int i = 0; i < ne * ne; ++i) kmax = std::max(kmax, std::fabs(K[i]));
+    for (int i = 0; i < ne; ++i)
+        for (int j = 0; j < ne; ++j) {
+            double s = 0.0;
+            for (auto& row : R) s += row[i] * row[j];
+            err = std::max(err, std::fabs(s - K[(size_t)i * ne + j]));
+        }
+    return err <= 1e-12 * kmax && (int)R.size() == (dim == 2 ? 5 : 18);
+}
+
 int set_error(Ctx* c, int code, const char* fmt, ...) {
     if (c) {
         char buf[1024];
@@ -166,6 +256,15 @@ const ElemTables* get_tables(Ctx* ctx, const topo_mesh& m) {
     if (hipMemcpy(t.K64, t.host.data(), n * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
         return nullptr;
     if (hipMemcpy(t.K32, k32.data(), n * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
+        return nullptr;
+    std::vector<double> fac;
+    if (!element_factor(m, t.host, fac)) return nullptr;
+    std::vector<float> fac32(fac.begin(), fac.end());
+    if (hipMalloc(&t.F64, kFacSize * sizeof(double)) != hipSuccess) return nullptr;
+    if (hipMalloc(&t.F32, kFacSize * sizeof(float)) != hipSuccess) return nullptr;
+    if (hipMemcpy(t.F64, fac.data(), kFacSize * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+        return nullptr;
+    if (hipMemcpy(t.F32, fac32.data(), kFacSize * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
         return nullptr;
     return &(ctx->tables[key] = t);
 }
@@ -293,6 +392,8 @@ int topo_ctx_destroy(topo_ctx* c) {
     for (auto& kv : c->tables) {
         (void)hipFree(kv.second.K64);
         (void)hipFree(kv.second.K32);
+        (void)hipFree(kv.second.F64);
+        (void)hipFree(kv.second.F32);
     }
     if (c->ws) (void)hipFree(c->ws);
     if (c->pinned) (void)hipHostFree(c->pinned);

@@ -31,17 +31,33 @@ struct Grid {
 
 Grid make_grid(const topo_mesh& m);
 
+// Symmetry-blocked factor K_e = R^T R of the box element (R has 5 rows for Q4, 18 for
+// H8).  The reflections of the box commute with K_e, so in the Walsh-Hadamard basis of
+// the nodal values (per displacement component) K_e splits into one small block per
+// reflection character.  The rigid translations and rotations occupy fixed directions
+// of these blocks and are dropped exactly; each remaining block is SPD and stored as
+// its upper-triangular Cholesky factor.  Table layout: 8 blocks x 6 slots
+// (L00 L01 L02 L11 L12 L22 of the block's transposed factor), then h[0..2].
+constexpr int kFacSize = 51;
+constexpr int kFacH = 48;
+
 // Element tables of one (dim, h, nu, plane) combination, resident on the device.
 struct ElemTables {
     int ne;            // element DOFs: 8 (Q4) or 24 (H8)
     double* K64;       // device [ne*ne]
     float* K32;        // device [ne*ne]
+    double* F64 = nullptr;  // device [kFacSize] symmetry-blocked factor
+    float* F32 = nullptr;   // device [kFacSize]
     double diag[3];    // K_e diagonal per displacement component (host copy)
     std::vector<double> host;  // host copy of K64
 };
 
 // Exact element stiffness of the rectangular Q4 / H8 element (host).
 void element_stiffness(const topo_mesh& m, std::vector<double>& K);
+
+// The symmetry-blocked factor of K (kFacSize values); false if K does not have the
+// block structure of a box element or a block is not positive definite.
+bool element_factor(const topo_mesh& m, const std::vector<double>& K, std::vector<double>& F);
 
 // ----------------------------------------------------------------------------------
 // Sampled kernel timing (instrumentation): one launch in `every` of each hot kernel is

@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cmath>
 
+#include "elemfac.hpp"
 #include "stencil.hpp"
 
 namespace topo {
@@ -40,17 +41,19 @@ template <> struct Mfma<double> {
 };
 
 // ----------------------------------------------------------------------------------
-// K_hat contraction.
+// K_hat contraction.  With K_e = R^T R (symmetry-blocked factor, elemfac.hpp),
+//   K_hat = sum_e alpha_e (R P_e^T Phi)^T (R P_e^T Phi) = D^T D,
+// D stacking the rows sqrt(alpha_e) R P_e^T Phi of every element (5 per Q4, 18 per H8;
+// Dirichlet rows of Phi zeroed, columns zero-padded to KP).
 //   grid.x : element chunks (contiguous element ranges)
 //   grid.y : density fields b
 //   grid.z : groups of upper-triangle 16x16 tile pairs (I <= J)
-// Per sub-chunk of EC elements the block stages, in LDS, the element rows of the
-// basis A = P_e^T Phi (Dirichlet rows zeroed, columns zero-padded to KP) and
-// W = K_e A (element-local, density independent).  Each wave then owns TPW tile pairs
-// and accumulates K_hat_IJ += A_I^T (alpha W_J) over the rows with the matrix cores,
+// Per sub-chunk of ec elements the block stages D in LDS (one thread per element and
+// column: 2^dim gathered basis rows, edge differences, the small triangular blocks),
+// then each wave accumulates its tile pairs K_hat_IJ += D_I^T D_J on the matrix cores,
 // 4 rows per instruction.  Accumulators are flushed to float64 registers after every
-// sub-chunk, and each block writes one float64 partial per tile entry; a second
-// kernel sums the partials over chunks in a fixed order (deterministic).
+// sub-chunk, and each block writes one float64 partial per tile entry; a second kernel
+// sums the partials over chunks in a fixed order (deterministic).
 // ----------------------------------------------------------------------------------
 constexpr int TPW = 8;       // tile pairs per wave
 constexpr int WAVES = 4;     // waves per block
@@ -71,14 +74,15 @@ template <int DIM, typename TP, typename TC>
 __global__ __launch_bounds__(WAVES * 64) void k_rom_contract(
     Grid g, const TP* __restrict__ phi, int k, int ldphi, int KP, int LS,
     const uint8_t* __restrict__ mask, const TC* __restrict__ alpha /*[B][Ne]*/,
-    const TC* __restrict__ Ke, int epw, int ec, double* __restrict__ partials) {
+    const TC* __restrict__ F, int epw, int ec, double* __restrict__ partials) {
     constexpr int NEN = 1 << DIM;
-    constexpr int NE = DIM * NEN;
+    constexpr int NR = DIM == 2 ? kRows2 : kRows3;
     extern __shared__ __align__(16) unsigned char smem[];
-    TC* sK = (TC*)smem;                       // [NE*NE]
-    TC* sA = sK + NE * NE;                    // [ec*NE][LS]
-    TC* sW = sA + (size_t)ec * NE * LS;       // [ec*NE][LS]
-    TC* sAl = sW + (size_t)ec * NE * LS;      // [ec]
+    TC* sD = (TC*)smem;  // [round_up(ec * NR, 4)][LS]
+    __shared__ TC sF[kFacSize];
+    __shared__ int sNode[64][NEN];       // node of each local node of the sub-chunk's elements
+    __shared__ uint32_t sFree[64];       // bit DIM*a+c set: DOF (a, c) is free
+    __shared__ TC sSa[64];               // sqrt(alpha_e)
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -86,11 +90,14 @@ __global__ __launch_bounds__(WAVES * 64) void k_rom_contract(
     const int b = blockIdx.y;
     const int kt = KP / 16;
     const int npairs = kt * (kt + 1) / 2;
-    const int e_begin = blockIdx.x * epw;
+    const int e_begin = xcd_block(blockIdx.x, gridDim.x) * epw;
     const int e_end = min(e_begin + epw, g.n_elems);
     const TC* alpha_b = alpha + (size_t)b * g.n_elems;
+    const int rows_full = ec * NR;
+    const int rows_alloc = (rows_full + 3) & ~3;
 
-    for (int i = tid; i < NE * NE; i += blockDim.x) sK[i] = Ke[i];
+    for (int i = tid; i < kFacSize; i += blockDim.x) sF[i] = F[i];
+    for (int i = rows_full * LS + tid; i < rows_alloc * LS; i += blockDim.x) sD[i] = TC(0);
 
     // this wave's tile pairs
     int myI[TPW], myJ[TPW];
@@ -112,60 +119,64 @@ __global__ __launch_bounds__(WAVES * 64) void k_rom_contract(
 #pragma unroll
         for (int v = 0; v < 4; ++v) acc64[t][v] = 0.0;
 
-    const int rows_full = ec * NE;
     for (int e0 = e_begin; e0 < e_end; e0 += ec) {
         const int ne_here = min(ec, e_end - e0);
-        const int rows = ne_here * NE;
-        __syncthreads();  // previous sub-chunk fully consumed
-        // stage A: rows (element, local dof), columns 0..KP-1 (zero beyond k)
-        for (int idx = tid; idx < rows_full * KP; idx += blockDim.x) {
-            const int row = idx / KP;
-            const int col = idx - row * KP;
-            TC v = TC(0);
-            if (row < rows && col < k) {
-                const int el = e0 + row / NE;
-                const int l = row % NE;
-                const int a = l / DIM, c = l % DIM;
-                const int ex = el % g.nx;
-                const int t2 = el / g.nx;
+        __syncthreads();  // previous sub-chunk fully consumed (and sF staged)
+        // element geometry of the sub-chunk: node indices, free-DOF bits, sqrt(alpha)
+        for (int idx = tid; idx < ec * NEN; idx += blockDim.x) {
+            const int el = idx / NEN, a = idx - el * NEN;
+            int n = 0;
+            uint32_t bits = 0;
+            if (el < ne_here) {
+                const int e = e0 + el;
+                const int ex = e % g.nx;
+                const int t2 = e / g.nx;
                 const int ey = t2 % g.ny;
                 const int ez = t2 / g.ny;
-                const int n = ((ez + (a >> 2)) * g.ny1 + (ey + ((a >> 1) & 1))) * g.nx1 + ex + (a & 1);
-                const size_t dof = (size_t)c * g.n_nodes + n;
-                if (!mask[dof]) v = (TC)phi[dof * (size_t)ldphi + col];
+                n = ((ez + (a >> 2)) * g.ny1 + (ey + ((a >> 1) & 1))) * g.nx1 + ex + (a & 1);
+#pragma unroll
+                for (int c = 0; c < DIM; ++c)
+                    if (!mask[(size_t)c * g.n_nodes + n]) bits |= 1u << (DIM * a + c);
             }
-            sA[(size_t)row * LS + col] = v;
-        }
-        for (int i = tid; i < ec; i += blockDim.x) sAl[i] = i < ne_here ? alpha_b[e0 + i] : TC(0);
-        __syncthreads();
-        // K_e annihilates rigid translations: subtract each element's mean per
-        // displacement component and column.  (A - T)^T K_e (A - T) = A^T K_e A exactly,
-        // with far less cancellation for smooth basis vectors.
-        for (int idx = tid; idx < ec * DIM * KP; idx += blockDim.x) {
-            const int col = idx % KP;
-            const int ec_c = idx / KP;
-            const int el = ec_c / DIM, c = ec_c % DIM;
-            TC* base = sA + (size_t)el * NE * LS + col;
-            TC m = TC(0);
+            sNode[el][a] = n;
+            // combine the bits of the element's nodes (NEN consecutive lanes)
 #pragma unroll
-            for (int a = 0; a < NEN; ++a) m += base[(size_t)(DIM * a + c) * LS];
-            m *= TC(1) / TC(NEN);
-#pragma unroll
-            for (int a = 0; a < NEN; ++a) base[(size_t)(DIM * a + c) * LS] -= m;
+            for (int off = 1; off < NEN; off <<= 1) bits |= __shfl_xor(bits, off, 64);
+            if (a == 0) {
+                sFree[el] = bits;
+                sSa[el] = el < ne_here ? (TC)sqrt(alpha_b[e0 + el]) : TC(0);
+            }
         }
         __syncthreads();
-        // W = K_e A per element (vector ALU)
-        for (int idx = tid; idx < rows_full * KP; idx += blockDim.x) {
-            const int row = idx / KP;
-            const int col = idx - row * KP;
-            const int el = row / NE;
-            const int l = row - el * NE;
-            const TC* Arow = sA + (size_t)el * NE * LS + col;
-            const TC* Krow = sK + l * NE;
-            TC s = TC(0);
+        for (int idx = tid; idx < ec * KP; idx += blockDim.x) {
+            const int el = idx / KP;
+            const int col = idx - el * KP;
+            TC D[NR];
+            if (el < ne_here && col < k) {
+                // every load issued unconditionally (basis rows exist for fixed DOFs too)
+                const uint32_t fr = sFree[el];
+                TP v[NEN][DIM];
 #pragma unroll
-            for (int m = 0; m < NE; ++m) s += Krow[m] * Arow[(size_t)m * LS];
-            sW[(size_t)row * LS + col] = s * sAl[el];
+                for (int a = 0; a < NEN; ++a) {
+                    const size_t n = (size_t)sNode[el][a];
+#pragma unroll
+                    for (int c = 0; c < DIM; ++c)
+                        v[a][c] = phi[((size_t)c * g.n_nodes + n) * (size_t)ldphi + col];
+                }
+                TC A[NEN][DIM];
+#pragma unroll
+                for (int a = 0; a < NEN; ++a)
+#pragma unroll
+                    for (int c = 0; c < DIM; ++c)
+                        A[a][c] = ((fr >> (DIM * a + c)) & 1u) ? (TC)v[a][c] : TC(0);
+                if constexpr (DIM == 2) elem_rows2(A, sF, sSa[el], D);
+                else elem_rows3(A, sF, sSa[el], D);
+            } else {
+#pragma unroll
+                for (int r = 0; r < NR; ++r) D[r] = TC(0);
+            }
+#pragma unroll
+            for (int r = 0; r < NR; ++r) sD[(size_t)(el * NR + r) * LS + col] = D[r];
         }
         __syncthreads();
         // matrix-core accumulation over the rows of this sub-chunk
@@ -174,14 +185,14 @@ __global__ __launch_bounds__(WAVES * 64) void k_rom_contract(
         for (int t = 0; t < TPW; ++t) acc[t] = acc_t{0, 0, 0, 0};
         const int rsub = lane >> 4;   // row inside the 4-row step
         const int csub = lane & 15;   // column inside the tile
+        const int rows = ne_here * NR;
         for (int r0 = 0; r0 < rows; r0 += 4) {
-            const TC* arow = sA + (size_t)(r0 + rsub) * LS + csub;
-            const TC* wrow = sW + (size_t)(r0 + rsub) * LS + csub;
+            const TC* drow = sD + (size_t)(r0 + rsub) * LS + csub;
 #pragma unroll
             for (int t = 0; t < TPW; ++t) {
                 if (t < nmine) {
-                    const TC av = arow[myI[t] * 16];
-                    const TC bv = wrow[myJ[t] * 16];
+                    const TC av = drow[myI[t] * 16];
+                    const TC bv = drow[myJ[t] * 16];
                     acc[t] = Mfma<TC>::run(av, bv, acc[t]);
                 }
             }
@@ -494,16 +505,18 @@ struct ContractPlan {
 static ContractPlan plan_contract(const Grid& g, int k, int B, bool f64, int cu) {
     ContractPlan p;
     p.KP = (k + 15) / 16 * 16;
-    p.LS = p.KP + ((p.KP % 32 == 0) ? 4 : 0);
+    // an odd number of 16-column groups per row: the 4 rows of one matrix-core step fall
+    // on different LDS banks
+    p.LS = p.KP + ((p.KP / 16) % 2 == 0 ? 16 : 0);
     p.kt = p.KP / 16;
     p.npairs = p.kt * (p.kt + 1) / 2;
     p.groups = (p.npairs + PAIRS_PER_GROUP - 1) / PAIRS_PER_GROUP;
-    const int ne = g.dim * (1 << g.dim);
+    const int nr = g.dim == 2 ? kRows2 : kRows3;
     const size_t esz = f64 ? 8 : 4;
     const size_t budget = 64 * 1024;
-    const size_t fixed = (size_t)ne * ne * esz;
-    int ec = (int)((budget - fixed) / (2 * (size_t)ne * p.LS * esz + esz));
-    ec = std::max(1, std::min(ec, 16));
+    auto bytes = [&](int e) { return (size_t)((e * nr + 3) & ~3) * p.LS * esz; };
+    int ec = 64;
+    while (ec > 1 && bytes(ec) > budget) --ec;
     p.ec = ec;
     // aim at ~4 blocks per CU overall (each block writes npairs partial tiles, so more
     // chunks only add reduction traffic)
@@ -517,20 +530,20 @@ static ContractPlan plan_contract(const Grid& g, int k, int B, bool f64, int cu)
     epw = (epw + ec - 1) / ec * ec;
     p.epw = (int)epw;
     p.nchunks = (int)((g.n_elems + epw - 1) / epw);
-    p.lds_bytes = fixed + 2 * (size_t)ec * ne * p.LS * esz + (size_t)ec * esz;
+    p.lds_bytes = bytes(ec);
     return p;
 }
 
 template <int DIM, typename TP, typename TC>
 static int launch_contract(Ctx* ctx, const Grid& g, const ContractPlan& p, const TP* phi, int k,
-                           int ldphi, const uint8_t* mask, const TC* alpha, const TC* Ke, int B,
+                           int ldphi, const uint8_t* mask, const TC* alpha, const TC* F, int B,
                            double* partials, hipStream_t s) {
     auto kern = k_rom_contract<DIM, TP, TC>;
     TOPO_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)p.lds_bytes));
     TimedLaunch tl(ctx, KID_ROM_CONTRACT, s);
     hipLaunchKernelGGL(kern, dim3(p.nchunks, B, p.groups), dim3(WAVES * 64), p.lds_bytes, s, g, phi,
-                       k, ldphi, p.KP, p.LS, mask, alpha, Ke, p.epw, p.ec, partials);
+                       k, ldphi, p.KP, p.LS, mask, alpha, F, p.epw, p.ec, partials);
     TOPO_CHECK_LAUNCH();
     return TOPO_OK;
 }
@@ -577,19 +590,19 @@ int topo_rom_build(topo_ctx* ctx, const topo_mesh* mesh, const void* phi, int32_
     if (rc) return rc;
     if (g.dim == 2) {
         if (f64) {
-            rc = phi_fp32 ? launch_contract<2, float, double>(ctx, g, p, (const float*)phi, k, ldphi, mask, a64, tb->K64, B, parts, s)
-                          : launch_contract<2, double, double>(ctx, g, p, (const double*)phi, k, ldphi, mask, a64, tb->K64, B, parts, s);
+            rc = phi_fp32 ? launch_contract<2, float, double>(ctx, g, p, (const float*)phi, k, ldphi, mask, a64, tb->F64, B, parts, s)
+                          : launch_contract<2, double, double>(ctx, g, p, (const double*)phi, k, ldphi, mask, a64, tb->F64, B, parts, s);
         } else {
-            rc = phi_fp32 ? launch_contract<2, float, float>(ctx, g, p, (const float*)phi, k, ldphi, mask, a32, tb->K32, B, parts, s)
-                          : launch_contract<2, double, float>(ctx, g, p, (const double*)phi, k, ldphi, mask, a32, tb->K32, B, parts, s);
+            rc = phi_fp32 ? launch_contract<2, float, float>(ctx, g, p, (const float*)phi, k, ldphi, mask, a32, tb->F32, B, parts, s)
+                          : launch_contract<2, double, float>(ctx, g, p, (const double*)phi, k, ldphi, mask, a32, tb->F32, B, parts, s);
         }
     } else {
         if (f64) {
-            rc = phi_fp32 ? launch_contract<3, float, double>(ctx, g, p, (const float*)phi, k, ldphi, mask, a64, tb->K64, B, parts, s)
-                          : launch_contract<3, double, double>(ctx, g, p, (const double*)phi, k, ldphi, mask, a64, tb->K64, B, parts, s);
+            rc = phi_fp32 ? launch_contract<3, float, double>(ctx, g, p, (const float*)phi, k, ldphi, mask, a64, tb->F64, B, parts, s)
+                          : launch_contract<3, double, double>(ctx, g, p, (const double*)phi, k, ldphi, mask, a64, tb->F64, B, parts, s);
         } else {
-            rc = phi_fp32 ? launch_contract<3, float, float>(ctx, g, p, (const float*)phi, k, ldphi, mask, a32, tb->K32, B, parts, s)
-                          : launch_contract<3, double, float>(ctx, g, p, (const double*)phi, k, ldphi, mask, a32, tb->K32, B, parts, s);
+            rc = phi_fp32 ? launch_contract<3, float, float>(ctx, g, p, (const float*)phi, k, ldphi, mask, a32, tb->F32, B, parts, s)
+                          : launch_contract<3, double, float>(ctx, g, p, (const double*)phi, k, ldphi, mask, a32, tb->F32, B, parts, s);
         }
     }
     if (rc) return rc;
