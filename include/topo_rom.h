@@ -28,9 +28,10 @@
  *    zero), u = 0 and r = 0 there, and every norm / dot product runs over free DOFs.
  *  - Material law (Sec. 2.1): alpha(rho) = Emin + (E0 - Emin) rho^penal; the paper's
  *    law is the case E0 = 1, Emin = rho_l.
- *  - Basis Phi: row-major [N_u][ldphi], rows indexed like DOF vectors; the first k
- *    columns are used.  float32 when phi_fp32 != 0, float64 otherwise.  Phi must
- *    have full column rank on the free DOFs (orthonormality is not required).
+ *  - Basis Phi: row-major [N_u][ldphi] (k <= ldphi <= 1024), rows indexed like DOF
+ *    vectors; the first k columns are used.  float32 when phi_fp32 != 0, float64
+ *    otherwise.  Phi must have full column rank on the free DOFs (orthonormality is
+ *    not required).
  *  - stream: a hipStream_t (NULL = the null stream).  Work is stream-ordered.  Calls
  *    that need a convergence or pivot decision (hdm_solve, rom_estimate with
  *    max_refine > 0, rom_solve with status == NULL) synchronise that stream and
@@ -160,8 +161,11 @@ int topo_hdm_gradient(topo_ctx* ctx, const topo_mesh* mesh, const double* rho,
  *   Khat[b] = sum_e alpha(rho_be) (P_e^T Phi)^T K_e (P_e^T Phi)   [B][k][k] f64 out,
  *   fhat    = Phi^T f                                             [k] f64 out (may
  *             be NULL; it depends on the basis only).
- * TOPO_MIXED contracts float32 Phi on float32 matrix cores with float64 cross-tile
- * sums; TOPO_FP64 contracts in float64 (Phi promoted when phi_fp32 != 0).
+ * Evaluated as K_hat = D^T D with D stacking sqrt(alpha_e) R P_e^T Phi per element,
+ * K_e = R^T R being the element operator's symmetry-blocked factor (5 rows per Q4,
+ * 18 per H8, rigid modes dropped exactly).  TOPO_MIXED contracts in float32 on the
+ * matrix cores with float64 cross-tile sums; TOPO_FP64 contracts in float64 (Phi
+ * promoted when phi_fp32 != 0).
  *   rho: [B][n_elems] f64. */
 int topo_rom_build(topo_ctx* ctx, const topo_mesh* mesh, const void* phi,
                    int32_t phi_fp32, int32_t k, int32_t ldphi, const uint8_t* mask,
@@ -183,8 +187,9 @@ int topo_rom_solve(topo_ctx* ctx, int32_t k, int32_t B, const double* Khat,
  *   u_b = Phi yhat[b] (float64 accumulation), r_b = f - K(rho_b) u_b on free DOFs in
  *   float64, resnorm[b] = ||r_b||_2.
  * With max_refine > 0 the reduced coefficients are refined in float64, up to
- * max_refine times: yhat += K_hat^{-1} Phi^T r (stopping early when ||r|| no longer
- * decreases), recovering float64 accuracy of a float32 K_hat; then
+ * max_refine times: yhat += K_hat^{-1} Phi^T r (a step is kept only while the
+ * Galerkin residual ||Phi^T r|| of that field decreases), recovering float64 accuracy
+ * of a float32 K_hat; then
  * Jk[b] = f^T Phi yhat[b] and resnorm are those of the refined yhat.
  *   yhat [B][k] f64 in/out, Jk [B] f64 out (may be NULL), resnorm [B] f64 out,
  *   Khat [B][k][k] f64 (only read when max_refine > 0). */

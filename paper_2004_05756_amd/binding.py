@@ -262,7 +262,7 @@ class Context:
         self._check(rc, "rom_solve")
         return yhat, Jk
 
-    def rom_estimate(self, mesh, phi, k, mask, f, rho, Khat, yhat, max_refine=2, stream=None,
+    def rom_estimate(self, mesh, phi, k, mask, f, rho, Khat, yhat, max_refine=1, stream=None,
                      Jk=None, resnorm=None):
         import torch
         if rho.dim() == 1:
@@ -439,7 +439,7 @@ class Server:
                         maxit=int(maxit), rtol=float(rtol))
         return self._submit(r, rho)
 
-    def submit_rom(self, mesh_id, basis_id, k, rho, prec=MIXED, max_refine=2):
+    def submit_rom(self, mesh_id, basis_id, k, rho, prec=MIXED, max_refine=1):
         r = TopoRequest(kind=REQ_ROM, mesh_id=int(mesh_id), basis_id=int(basis_id), k=int(k), prec=int(prec),
                         max_refine=int(max_refine), maxit=0, rtol=0.0)
         return self._submit(r, rho)

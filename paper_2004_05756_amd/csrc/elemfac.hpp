@@ -74,6 +74,65 @@ __device__ __forceinline__ void elem_rows3(const T (&A)[8][3], const T* __restri
     for (int r = 0; r < kRows3; ++r) D[r] *= s;
 }
 
+// Y = alpha K_e A for one element (H8): D = -alpha R A by elem_rows3, then
+// Y = R^T (-D) = H G^T L (-D) with the fast Walsh-Hadamard transform.  The transformed
+// translation entries are zero, so every Y sums to zero over the nodes (per component)
+// and a rigid motion gives Y = 0 exactly.
+template <typename T>
+__device__ __forceinline__ void elem_apply3(const T (&A)[8][3], const T* __restrict__ F, T alpha,
+                                            T (&Y)[8][3]) {
+    T D[kRows3];
+    elem_rows3(A, F, alpha, D);
+    // u = -L D per block (L = Lt^T, lower triangular), scattered to V[m][c] by G^T
+    T V[8][3];
+    const T h0 = F[kFacH], h1 = F[kFacH + 1], h2 = F[kFacH + 2];
+    auto lo3 = [&](int n, const T* d, T& u0, T& u1, T& u2) {
+        u0 = -(F[6 * n + 0] * d[0]);
+        u1 = -(F[6 * n + 1] * d[0] + F[6 * n + 3] * d[1]);
+        u2 = -(F[6 * n + 2] * d[0] + F[6 * n + 4] * d[1] + F[6 * n + 5] * d[2]);
+    };
+    auto lo2 = [&](int n, const T* d, T& u0, T& u1) {
+        u0 = -(F[6 * n + 0] * d[0]);
+        u1 = -(F[6 * n + 1] * d[0] + F[6 * n + 3] * d[1]);
+    };
+    T u0, u1, u2;
+    V[0][0] = V[0][1] = V[0][2] = T(0);
+    lo3(0, D + 0, u0, u1, u2);
+    V[1][0] = u0; V[2][1] = u1; V[4][2] = u2;
+    lo2(1, D + 3, u0, u1);
+    V[3][1] = u0; V[5][2] = u1;
+    lo2(2, D + 5, u0, u1);
+    V[3][0] = u0; V[6][2] = u1;
+    lo2(3, D + 7, u0, u1);
+    V[2][0] = h0 * u0; V[1][1] = h1 * u0; V[7][2] = u1;
+    lo2(4, D + 9, u0, u1);
+    V[5][0] = u0; V[6][1] = u1;
+    lo2(5, D + 11, u0, u1);
+    V[4][0] = h0 * u0; V[1][2] = h2 * u0; V[7][1] = u1;
+    lo2(6, D + 13, u0, u1);
+    V[4][1] = h1 * u0; V[2][2] = h2 * u0; V[7][0] = u1;
+    lo3(7, D + 15, u0, u1, u2);
+    V[6][0] = u0; V[5][1] = u1; V[3][2] = u2;
+    // Y[a][c] = sum_m (-1)^{m.a} V[m][c]
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        T w[8];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) w[m] = V[m][c];
+#pragma unroll
+        for (int bit = 1; bit < 8; bit <<= 1)
+#pragma unroll
+            for (int m = 0; m < 8; ++m)
+                if (!(m & bit)) {
+                    const T x0 = w[m], x1 = w[m | bit];
+                    w[m] = x0 + x1;
+                    w[m | bit] = x0 - x1;
+                }
+#pragma unroll
+        for (int a = 0; a < 8; ++a) Y[a][c] = w[a];
+    }
+}
+
 // D = s * R A for one column of the Q4 element (a = ax + 2 ay).
 template <typename T>
 __device__ __forceinline__ void elem_rows2(const T (&A)[4][2], const T* __restrict__ F, T s,

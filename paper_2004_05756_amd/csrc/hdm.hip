@@ -13,6 +13,7 @@
 
 #include <hip/hip_ext.h>
 
+#include "march3.hpp"
 #include "stencil.hpp"
 
 namespace topo {
@@ -68,31 +69,91 @@ __global__ __launch_bounds__(kBlock) void k_apply2(Grid g, const T* __restrict__
     }
 }
 
-// 3D: one block per node tile (blockIdx.x), one field per blockIdx.y.
+// Sources of the 3D march (march3.hpp): the values of node planes, fetched two slots
+// per thread, loads issued without waiting.
+template <typename T>
+struct SrcMasked {  // x with Dirichlet DOFs zeroed
+    const T* __restrict__ x;
+    const uint8_t* __restrict__ mask;
+    int nn;
+    T v[4][3];
+    __device__ __forceinline__ void fetch(int slot, int node) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            T xv = T(0);
+            uint8_t mk = 1;
+            if (node >= 0) {
+                xv = x[(size_t)c * nn + node];
+                mk = mask[(size_t)c * nn + node];
+            }
+            v[slot][c] = mk ? T(0) : xv;
+        }
+    }
+    __device__ __forceinline__ T value(int slot, int c) const { return v[slot][c]; }
+};
+
+template <typename T>
+struct SrcPlain {
+    const T* __restrict__ x;
+    int nn;
+    T v[4][3];
+    __device__ __forceinline__ void fetch(int slot, int node) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) v[slot][c] = node >= 0 ? x[(size_t)c * nn + node] : T(0);
+    }
+    __device__ __forceinline__ T value(int slot, int c) const { return v[slot][c]; }
+};
+
+template <typename T>
+struct SrcDirection {  // p_new = z + beta p_old
+    const T* __restrict__ z;
+    const T* __restrict__ p;
+    T beta;
+    int nn;
+    T zv[4][3], pv[4][3];
+    __device__ __forceinline__ void fetch(int slot, int node) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            zv[slot][c] = node >= 0 ? z[(size_t)c * nn + node] : T(0);
+            pv[slot][c] = node >= 0 ? p[(size_t)c * nn + node] : T(0);
+        }
+    }
+    __device__ __forceinline__ T value(int slot, int c) const { return zv[slot][c] + beta * pv[slot][c]; }
+};
+
+// Fetch the two prologue planes k0 - 1 (slots 0, 1) and k0 (slots 2, 3).
+template <typename Src>
+__device__ __forceinline__ void march3_prologue(const Grid& g, const MarchBlock& m, Src& src) {
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const int q = threadIdx.x + r * kBlock;
+        src.fetch(r, q < MPN ? march3_node(g, m, q, m.k0 - 1) : -1);
+        src.fetch(2 + r, q < MPN ? march3_node(g, m, q, m.k0) : -1);
+    }
+}
+
+// 3D: one block per march column (blockIdx.x), one field per blockIdx.y.  F is the
+// element factor table.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_apply3(Grid g, const T* __restrict__ alpha,
-                                                   const T* __restrict__ K,
+                                                   const T* __restrict__ F,
                                                    const uint8_t* __restrict__ mask,
                                                    const T* __restrict__ x, T* __restrict__ y) {
-    __shared__ Tile3Lds<T> L;
+    __shared__ MarchLds<T> L;
     const size_t b = blockIdx.y;
-    int i0, j0, k0, tx, ty, tz;
-    tile3_origin(g, xcd_block(blockIdx.x, gridDim.x), i0, j0, k0);
-    tile3_thread(tx, ty, tz);
-    tile3_stage(g, i0, j0, k0, FetchMasked<T>{x + b * g.n_dofs, mask, g.n_nodes}, L);
-    tile3_load_alpha(g, i0, j0, k0, alpha + b * g.n_elems, L);
-    __syncthreads();
-    const int i = i0 + tx, j = j0 + ty, k = k0 + tz;
-    if (i >= g.nx1 || j >= g.ny1 || k >= g.nz1) return;
-    const int n = (k * g.ny1 + j) * g.nx1 + i;
-    T out[3];
-    tile3_compute(L, K, tx, ty, tz, out);
+    const MarchBlock m = march3_block(g, xcd_block(blockIdx.x, gridDim.x));
+    for (int i = threadIdx.x; i < kFacSize; i += blockDim.x) L.F[i] = F[i];
+    SrcMasked<T> src{x + b * g.n_dofs, mask, g.n_nodes};
+    march3_prologue(g, m, src);
     T* yb = y + b * g.n_dofs;
+    auto emit = [&](int n, const T (&out)[3], const T (&)[3]) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        const size_t idx = (size_t)c * g.n_nodes + n;
-        yb[idx] = mask[idx] ? T(0) : out[c];
-    }
+        for (int c = 0; c < 3; ++c) {
+            const size_t idx = (size_t)c * g.n_nodes + n;
+            yb[idx] = mask[idx] ? T(0) : out[c];
+        }
+    };
+    march3_run(g, m, alpha + b * g.n_elems, L, src, emit);
 }
 
 // ----------------------------------------------------------------------------------
@@ -245,12 +306,13 @@ __global__ __launch_bounds__(kBlock) void k_pcg_apply2(Grid g, const T* __restri
     if (threadIdx.x == 0) part[blockIdx.x] = v[0];
 }
 
-// 3D: one block per node tile.  The tile's halo of z and p_old and its element alphas
-// are loaded into registers before the scalar reduction, then p_new = z + beta p_old is
-// formed once per halo node in LDS and the stencil runs from there.
+// 3D: one block per march column.  The first two node planes of z and p_old are
+// fetched before the scalar reduction; p_new = z + beta p_old is formed per node as
+// the planes are staged, and the element march runs from LDS.  K is the element factor
+// table here.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_pcg_apply3(Grid g, const T* __restrict__ alpha,
-                                                       const T* __restrict__ K,
+                                                       const T* __restrict__ F,
                                                        const uint8_t* __restrict__ mask,
                                                        const T* __restrict__ z,
                                                        const T* __restrict__ p_old,
@@ -258,77 +320,27 @@ __global__ __launch_bounds__(kBlock) void k_pcg_apply3(Grid g, const T* __restri
                                                        double* __restrict__ part, PcgState* st,
                                                        int ps, int nrz, int parity, int first) {
     if (st->done) return;
-    __shared__ Tile3Lds<T> L;
+    __shared__ MarchLds<T> L;
     __shared__ double lds[48];
-    int i0, j0, k0, tx, ty, tz;
-    tile3_origin(g, xcd_block(blockIdx.x, gridDim.x), i0, j0, k0);
-    tile3_thread(tx, ty, tz);
-    const int i = i0 + tx, j = j0 + ty, k = k0 + tz;
-    const bool active = (i < g.nx1) & (j < g.ny1) & (k < g.nz1);
-    const int n = active ? (k * g.ny1 + j) * g.nx1 + i : 0;
-    constexpr int RH = (H3N + kBlock - 1) / kBlock;
-    constexpr int RA = (E3N + kBlock - 1) / kBlock;
-    T zr[RH][3], pr[RH][3], ar[RA];
-    bool hv[RH];
-#pragma unroll
-    for (int r = 0; r < RH; ++r) {
-        const int qh = threadIdx.x + r * kBlock;
-        const int hn = qh < H3N ? tile3_halo_node(g, i0, j0, k0, qh) : -1;
-        hv[r] = hn >= 0;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            zr[r][c] = hv[r] ? z[(size_t)c * g.n_nodes + hn] : T(0);
-            pr[r][c] = hv[r] ? p_old[(size_t)c * g.n_nodes + hn] : T(0);
-        }
-    }
-#pragma unroll
-    for (int r = 0; r < RA; ++r) {
-        const int qa = threadIdx.x + r * kBlock;
-        T a = T(0);
-        if (qa < E3N) {
-            const int ex = qa % E3X, ey = (qa / E3X) % E3Y, ez = qa / (E3X * E3Y);
-            const int exx = i0 - 1 + ex, eyy = j0 - 1 + ey, ezz = k0 - 1 + ez;
-            if ((exx >= 0) & (exx < g.nx) & (eyy >= 0) & (eyy < g.ny) & (ezz >= 0) & (ezz < g.nz))
-                a = alpha[((size_t)ezz * g.ny + eyy) * g.nx + exx];
-        }
-        ar[r] = a;
-    }
-    uint8_t mk[3] = {0, 0, 0};
-    if (active) {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) mk[c] = mask[(size_t)c * g.n_nodes + n];
-    }
+    const MarchBlock m = march3_block(g, xcd_block(blockIdx.x, gridDim.x));
+    for (int i = threadIdx.x; i < kFacSize; i += blockDim.x) L.F[i] = F[i];
+    SrcDirection<T> src{z, p_old, T(0), g.n_nodes};
+    march3_prologue(g, m, src);
     T tb;
     if (pcg_apply_scalars(part, st, ps, nrz, parity, first, tb, lds)) return;
-#pragma unroll
-    for (int r = 0; r < RH; ++r) {
-        const int qh = threadIdx.x + r * kBlock;
-        if (qh < H3N) {
-#pragma unroll
-            for (int c = 0; c < 3; ++c) L.x[c][qh] = hv[r] ? zr[r][c] + tb * pr[r][c] : T(0);
-        }
-    }
-#pragma unroll
-    for (int r = 0; r < RA; ++r) {
-        const int qa = threadIdx.x + r * kBlock;
-        if (qa < E3N) L.al[qa] = ar[r];
-    }
-    __syncthreads();
+    src.beta = tb;
     double v[1] = {0.0};
-    if (active) {
-        T out[3];
-        tile3_compute(L, K, tx, ty, tz, out);
-        const int qc = ((tz + 1) * H3Y + (ty + 1)) * H3X + (tx + 1);
+    auto emit = [&](int n, const T (&out)[3], const T (&pn)[3]) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const size_t idx = (size_t)c * g.n_nodes + n;
-            const T pn = L.x[c][qc];
-            const T qv = mk[c] ? T(0) : out[c];
-            p_new[idx] = pn;
+            const T qv = mask[idx] ? T(0) : out[c];
+            p_new[idx] = pn[c];
             q[idx] = qv;
-            v[0] += (double)pn * (double)qv;
+            v[0] += (double)pn[c] * (double)qv;
         }
-    }
+    };
+    march3_run(g, m, alpha, L, src, emit);
     block_reduce<1>(v, lds);
     if (threadIdx.x == 0) part[blockIdx.x] = v[0];
 }
@@ -519,34 +531,29 @@ __global__ __launch_bounds__(kBlock) void k_residual2(Grid g, const double* __re
     residual_partials(v, part, b, lds);
 }
 
-// 3D: one block per node tile.
+// 3D: one block per march column; F is the element factor table.
 __global__ __launch_bounds__(kBlock) void k_residual3(Grid g, const double* __restrict__ alpha,
-                                                      const double* __restrict__ K,
+                                                      const double* __restrict__ F,
                                                       const uint8_t* __restrict__ mask,
                                                       const double* __restrict__ u,
                                                       const double* __restrict__ f,
                                                       double* __restrict__ r,
                                                       double* __restrict__ part) {
-    __shared__ Tile3Lds<double> L;
+    __shared__ MarchLds<double> L;
     __shared__ double lds[48];
     const size_t b = blockIdx.y;
     const double* ub = u + b * g.n_dofs;
-    int i0, j0, k0, tx, ty, tz;
-    tile3_origin(g, xcd_block(blockIdx.x, gridDim.x), i0, j0, k0);
-    tile3_thread(tx, ty, tz);
-    tile3_stage(g, i0, j0, k0, FetchPlain<double>{ub, g.n_nodes}, L);
-    tile3_load_alpha(g, i0, j0, k0, alpha + b * g.n_elems, L);
-    __syncthreads();
-    const int i = i0 + tx, j = j0 + ty, k = k0 + tz;
+    const MarchBlock m = march3_block(g, xcd_block(blockIdx.x, gridDim.x));
+    for (int i = threadIdx.x; i < kFacSize; i += blockDim.x) L.F[i] = F[i];
+    SrcPlain<double> src{ub, g.n_nodes};
+    march3_prologue(g, m, src);
     double v[3] = {0.0, 0.0, 0.0};
-    if (i < g.nx1 && j < g.ny1 && k < g.nz1) {
-        const int n = (k * g.ny1 + j) * g.nx1 + i;
-        double o[3];
-        tile3_compute(L, K, tx, ty, tz, o);
+    double* rb = r ? r + b * g.n_dofs : nullptr;
+    auto emit = [&](int n, const double (&o)[3], const double (&)[3]) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
-            residual_dof(mask, f, ub, r ? r + b * g.n_dofs : nullptr, (size_t)c * g.n_nodes + n, o[c], v);
-    }
+        for (int c = 0; c < 3; ++c) residual_dof(mask, f, ub, rb, (size_t)c * g.n_nodes + n, o[c], v);
+    };
+    march3_run(g, m, alpha + b * g.n_elems, L, src, emit);
     residual_partials(v, part, b, lds);
 }
 
@@ -919,6 +926,7 @@ static double mixed_segment_tol() {
     return v;
 }
 
+// K64: the dense element matrix in 2D, the element factor table in 3D.
 static int residual_launch(Ctx* ctx, const Grid& g, const double* K64, const double* alpha64,
                            const uint8_t* mask, const double* u, const double* f, double* r, int B,
                            double* part, double* out, hipStream_t s) {
@@ -1014,7 +1022,9 @@ static int hdm_solve_impl(Ctx* ctx, const topo_mesh& m, const Grid& g, const Ele
     }
     PcgRun<DIM, T> w;
     w.alpha = ta;
-    w.K = sizeof(T) == 4 ? (const T*)tb->K32 : (const T*)tb->K64;
+    // 2D: the dense element matrix; 3D: the symmetry-blocked factor table
+    if constexpr (DIM == 2) w.K = sizeof(T) == 4 ? (const T*)tb->K32 : (const T*)tb->K64;
+    else w.K = sizeof(T) == 4 ? (const T*)tb->F32 : (const T*)tb->F64;
     w.mask = mask;
     w.winv = tw;
     for (int c = 0; c < 3; ++c) w.ik[c] = c < DIM ? (T)(1.0 / tb->diag[c]) : T(0);
@@ -1036,7 +1046,7 @@ static int hdm_solve_impl(Ctx* ctx, const topo_mesh& m, const Grid& g, const Ele
     rc = pinned_host(ctx, pin_up + sizeof(PcgState), &pin);
     if (rc) return rc;
     auto residual = [&](double out[3]) -> int {
-        int rc2 = residual_launch(ctx, g, tb->K64, a64, mask, u, f, r64, 1, rpart, rout, s);
+        int rc2 = residual_launch(ctx, g, g.dim == 2 ? tb->K64 : tb->F64, a64, mask, u, f, r64, 1, rpart, rout, s);
         if (rc2) return rc2;
         double* h = (double*)((char*)pin + pin_res);
         TOPO_HIP(hipMemcpyAsync(h, rout, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -1179,14 +1189,14 @@ int topo_apply(topo_ctx* ctx, const topo_mesh* mesh, const double* rho, const ui
             hipLaunchKernelGGL((k_apply2<double>), grid, dim3(kBlock), 0, s, g, a64, tb->K64, mask,
                                (const double*)x, (double*)y);
         else
-            hipLaunchKernelGGL((k_apply3<double>), grid, dim3(kBlock), 0, s, g, a64, tb->K64, mask,
+            hipLaunchKernelGGL((k_apply3<double>), grid, dim3(kBlock), 0, s, g, a64, tb->F64, mask,
                                (const double*)x, (double*)y);
     } else {
         if (g.dim == 2)
             hipLaunchKernelGGL((k_apply2<float>), grid, dim3(kBlock), 0, s, g, a32, tb->K32, mask,
                                (const float*)x, (float*)y);
         else
-            hipLaunchKernelGGL((k_apply3<float>), grid, dim3(kBlock), 0, s, g, a32, tb->K32, mask,
+            hipLaunchKernelGGL((k_apply3<float>), grid, dim3(kBlock), 0, s, g, a32, tb->F32, mask,
                                (const float*)x, (float*)y);
     }
     TOPO_CHECK_LAUNCH();
@@ -1267,7 +1277,7 @@ namespace topo {
 int residual_fp64(Ctx* ctx, const Grid& g, const ElemTables* tb, const double* alpha64,
                   const uint8_t* mask, const double* u, const double* f, double* r, int B,
                   double* part, double* out, hipStream_t s) {
-    return residual_launch(ctx, g, tb->K64, alpha64, mask, u, f, r, B, part, out, s);
+    return residual_launch(ctx, g, g.dim == 2 ? tb->K64 : tb->F64, alpha64, mask, u, f, r, B, part, out, s);
 }
 
 int alpha_tables(Ctx* ctx, const Grid& g, const topo_mesh& m, const double* rho, int B,

@@ -244,10 +244,27 @@ __host__ __device__ inline int stencil_tiles3(const Grid& g) {
     return ((g.nx1 + T3X - 1) / T3X) * ((g.ny1 + T3Y - 1) / T3Y) * ((g.nz1 + T3Z - 1) / T3Z);
 }
 
-// Blocks of a node-stencil launch (apply, PCG apply, residual): one per node tile in
-// 3D, one per kBlock consecutive nodes in 2D.
+// 3D element-centric march: a block owns 31 x 7 node columns (a 32 x 8 tile of element
+// columns) over KZ node planes, with KZ chosen for about four blocks per CU.
+constexpr int MEX = 32, MEY = 8;             // element tile (one thread each)
+constexpr int MOX = MEX - 1, MOY = MEY - 1;  // owned node columns
+__host__ __device__ inline int march3_tiles_x(const Grid& g) { return (g.nx1 + MOX - 1) / MOX; }
+__host__ __device__ inline int march3_tiles_y(const Grid& g) { return (g.ny1 + MOY - 1) / MOY; }
+__host__ __device__ inline int march3_kz(const Grid& g) {
+    const int xy = march3_tiles_x(g) * march3_tiles_y(g);
+    const int chunks = (1024 + xy - 1) / xy;
+    const int kz = (g.nz1 + chunks - 1) / chunks;
+    return kz < 2 ? 2 : kz;
+}
+__host__ __device__ inline int march3_blocks(const Grid& g) {
+    const int kz = march3_kz(g);
+    return march3_tiles_x(g) * march3_tiles_y(g) * ((g.nz1 + kz - 1) / kz);
+}
+
+// Blocks of a node-stencil launch (apply, PCG apply, residual): one per march column
+// in 3D, one per kBlock consecutive nodes in 2D.
 inline int stencil_blocks(const Grid& g) {
-    return g.dim == 2 ? grid_blocks(g.n_nodes) : stencil_tiles3(g);
+    return g.dim == 2 ? grid_blocks(g.n_nodes) : march3_blocks(g);
 }
 
 // Largest block count of a PCG launch whose per-block partials every block of the next

@@ -255,45 +255,94 @@ __global__ void k_rom_reduce(int k, int KP, int nchunks, int B, const double* __
 // out[b][j] = sum_i Phi[i][j] v[b][i] over free rows i (float64 accumulation).
 // grid.x: row chunks, grid.y: b.  Partials [b][chunk][k], reduced by k_colsum_reduce.
 // ----------------------------------------------------------------------------------
-// Threads form cw columns x (256 / cw) row phases (cw = k rounded up to a power of two,
-// at most 64), so small k still keeps every lane busy; two accumulators per thread.
+// Phi is row-major, so a tile of rb consecutive rows is one contiguous stretch of
+// memory: the block copies it into LDS with coalesced loads (rows padded to an odd
+// stride), then thread j accumulates column j over the tile's rows.
+template <typename TP>
+__device__ __forceinline__ void stage_rows(const TP* __restrict__ phi, int ldphi, long long r0,
+                                           int nr, int lds_ld, TP* __restrict__ tile) {
+    const TP* src = phi + (size_t)r0 * ldphi;
+    const int n = nr * ldphi;
+    constexpr int V = 16 / sizeof(TP);  // elements per 16-byte load
+    constexpr int U = 4;                // 16-byte loads in flight per thread
+    if (((uintptr_t)src & 15) == 0) {
+        const int nv = n / V;
+        const uint4* s4 = (const uint4*)src;
+        for (int q0 = threadIdx.x; q0 < nv; q0 += U * blockDim.x) {
+            uint4 w[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int q = q0 + u * blockDim.x;
+                if (q < nv) w[u] = s4[q];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int q = q0 + u * blockDim.x;
+                if (q < nv) {
+                    const TP* e = (const TP*)&w[u];
+#pragma unroll
+                    for (int v = 0; v < V; ++v) {
+                        const int idx = q * V + v;
+                        const int r = idx / ldphi, c = idx - r * ldphi;
+                        tile[r * lds_ld + c] = e[v];
+                    }
+                }
+            }
+        }
+        for (int idx = nv * V + threadIdx.x; idx < n; idx += blockDim.x) {
+            const int r = idx / ldphi, c = idx - r * ldphi;
+            tile[r * lds_ld + c] = src[idx];
+        }
+    } else {
+        for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
+            const int r = idx / ldphi, c = idx - r * ldphi;
+            tile[r * lds_ld + c] = src[idx];
+        }
+    }
+}
+
 template <typename TP>
 __global__ __launch_bounds__(256) void k_phit_v(long long nrows, const TP* __restrict__ phi, int k,
                                                 int ldphi, const uint8_t* __restrict__ mask,
                                                 const double* __restrict__ v, long long vstride,
-                                                int rows_per_chunk, int cw,
+                                                int rows_per_chunk, int rb,
                                                 double* __restrict__ partials) {
-    __shared__ double red[256];
-    const int t = threadIdx.x;
-    const int cl = t % cw;
-    const int rp = t / cw;
-    const int nrp = 256 / cw;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int lds_ld = ldphi | 1;
+    TP* tile = (TP*)smem;                                  // [rb][lds_ld]
+    double* sv = (double*)(smem + (((size_t)rb * lds_ld * sizeof(TP) + 15) & ~(size_t)15));  // [rb]
     const int b = blockIdx.y;
     const long long r0 = (long long)blockIdx.x * rows_per_chunk;
     const long long r1 = min(r0 + rows_per_chunk, nrows);
     const double* vb = v + (size_t)b * vstride;
     double* dst = partials + ((size_t)b * gridDim.x + blockIdx.x) * k;
-    for (int c0 = 0; c0 < k; c0 += cw) {
-        const int col = c0 + cl;
-        double s0 = 0.0, s1 = 0.0;
-        if (col < k) {
-            long long i = r0 + rp;
-            for (; i + nrp < r1; i += 2 * nrp) {
-                const double v0 = mask[i] ? 0.0 : vb[i];
-                const double v1 = mask[i + nrp] ? 0.0 : vb[i + nrp];
-                s0 += (double)phi[(size_t)i * ldphi + col] * v0;
-                s1 += (double)phi[(size_t)(i + nrp) * ldphi + col] * v1;
+    constexpr int CMAX = 4;  // columns per thread (k <= 1024)
+    double acc[CMAX] = {0.0, 0.0, 0.0, 0.0};
+    for (long long t0 = r0; t0 < r1; t0 += rb) {
+        const int nr = (int)min((long long)rb, r1 - t0);
+        __syncthreads();
+        stage_rows(phi, ldphi, t0, nr, lds_ld, tile);
+        for (int r = threadIdx.x; r < nr; r += blockDim.x) sv[r] = mask[t0 + r] ? 0.0 : vb[t0 + r];
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < CMAX; ++q) {
+            const int j = threadIdx.x + q * blockDim.x;
+            if (j < k) {
+                double s0 = 0.0, s1 = 0.0;
+                int r = 0;
+                for (; r + 1 < nr; r += 2) {
+                    s0 += (double)tile[r * lds_ld + j] * sv[r];
+                    s1 += (double)tile[(r + 1) * lds_ld + j] * sv[r + 1];
+                }
+                if (r < nr) s0 += (double)tile[r * lds_ld + j] * sv[r];
+                acc[q] += s0 + s1;
             }
-            if (i < r1) s0 += (double)phi[(size_t)i * ldphi + col] * (mask[i] ? 0.0 : vb[i]);
         }
-        red[t] = s0 + s1;
-        __syncthreads();
-        if (t < cw && c0 + t < k) {
-            double s = 0.0;
-            for (int q = 0; q < nrp; ++q) s += red[q * cw + t];
-            dst[c0 + t] = s;
-        }
-        __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < CMAX; ++q) {
+        const int j = threadIdx.x + q * blockDim.x;
+        if (j < k) dst[j] = acc[q];
     }
 }
 
@@ -313,79 +362,91 @@ __global__ void k_colsum_reduce(int k, int nchunks, int B, const double* __restr
     out[gid] = s;
 }
 
-// u[b][i] = Phi[i][:] . y[b][:] on free rows, 0 on Dirichlet rows (float64 accumulation)
+// u[b][i] = Phi[i][:] . y[b][:] on free rows, 0 on Dirichlet rows (float64 accumulation).
+// A block handles a contiguous tile of rb rows (staged in LDS with coalesced loads);
+// 256 / rb threads share a row and combine their column sums with lane shuffles.
 template <typename TP>
 __global__ __launch_bounds__(256) void k_phi_y(long long nrows, const TP* __restrict__ phi, int k,
                                                int ldphi, const uint8_t* __restrict__ mask,
-                                               const double* __restrict__ y, double* __restrict__ u) {
-    extern __shared__ double sy[];
+                                               const double* __restrict__ y, int rb,
+                                               double* __restrict__ u) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int lds_ld = ldphi | 1;
+    double* sy = (double*)smem;                 // [k]
+    TP* tile = (TP*)(sy + ((k + 1) & ~1));      // [rb][lds_ld]
     const int b = blockIdx.y;
     for (int j = threadIdx.x; j < k; j += blockDim.x) sy[j] = y[(size_t)b * k + j];
+    const long long r0 = (long long)blockIdx.x * rb;
+    const int nr = (int)min((long long)rb, nrows - r0);
+    stage_rows(phi, ldphi, r0, nr, lds_ld, tile);
     __syncthreads();
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nrows) return;
+    const int tpr = blockDim.x / rb;            // threads per row (power of two <= 64)
+    const int r = threadIdx.x / tpr, q = threadIdx.x - r * tpr;
     double s = 0.0;
-    if (!mask[i]) {
-        const TP* row = phi + (size_t)i * ldphi;
-        for (int j = 0; j < k; ++j) s += (double)row[j] * sy[j];
-    }
-    u[(size_t)b * nrows + i] = s;
+    if (r < nr)
+        for (int j = q; j < k; j += tpr) s += (double)tile[r * lds_ld + j] * sy[j];
+    for (int off = tpr >> 1; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (q == 0 && r < nr) u[(size_t)b * nrows + r0 + r] = mask[r0 + r] ? 0.0 : s;
 }
 
 // ----------------------------------------------------------------------------------
-// Batched float64 Cholesky K = L L^T (one block per matrix), in LDS when it fits,
-// otherwise in the global workspace copy.  status[b] = TOPO_ENOTSPD on a pivot that
-// is not positive relative to the original diagonal.
+// Batched float64 Cholesky K = L L^T (one block per matrix, right-looking by column).
+// The lower triangle is kept packed in LDS when it fits (k <= CHOL_LDS_MAX_K),
+// otherwise in the global workspace copy.  The trailing update of each step runs on
+// a 16 x 16 thread grid (rows by ty, columns by tx), with no index decoding.  status[b] = TOPO_ENOTSPD on
+// a pivot that is not positive relative to the largest original diagonal entry.
 // ----------------------------------------------------------------------------------
-constexpr int CHOL_LDS_MAX_K = 64;
+constexpr int CHOL_LDS_MAX_K = 127;
+
+__device__ __forceinline__ int tri_idx(int i, int l) { return i * (i + 1) / 2 + l; }
 
 __global__ __launch_bounds__(256) void k_chol(int k, const double* __restrict__ Khat,
                                               double* __restrict__ Lout, int* __restrict__ status) {
-    __shared__ double sm[CHOL_LDS_MAX_K * CHOL_LDS_MAX_K];
+    __shared__ double sm[CHOL_LDS_MAX_K * (CHOL_LDS_MAX_K + 1) / 2];
     __shared__ int bad;
     const int b = blockIdx.x;
     const double* Kb = Khat + (size_t)b * k * k;
     double* Lg = Lout + (size_t)b * k * k;
-    double* A = (k <= CHOL_LDS_MAX_K) ? sm : Lg;
-    for (int i = threadIdx.x; i < k * k; i += blockDim.x) {
-        const int r = i / k, c = i % k;
-        A[i] = (c <= r) ? Kb[(size_t)r * k + c] : 0.0;  // lower triangle
+    const bool packed = k <= CHOL_LDS_MAX_K;
+    // element (i, l), l <= i, of the working lower triangle
+    auto at = [&](int i, int l) -> double& { return packed ? sm[tri_idx(i, l)] : Lg[(size_t)i * k + l]; };
+    for (int q = threadIdx.x; q < k * k; q += blockDim.x) {
+        const int i = q / k, l = q - i * k;
+        if (l <= i) at(i, l) = Kb[(size_t)i * k + l];
+        else if (!packed) Lg[q] = 0.0;
     }
     if (threadIdx.x == 0) bad = 0;
     __syncthreads();
     double maxdiag = 0.0;
-    for (int j = 0; j < k; ++j) maxdiag = fmax(maxdiag, fabs(A[j * k + j]));
+    for (int j = 0; j < k; ++j) maxdiag = fmax(maxdiag, fabs(at(j, j)));
     const double tiny = 64.0 * k * 2.220446049250313e-16 * maxdiag;
+    const int ty = threadIdx.x / 16, tx = threadIdx.x % 16;  // blockDim.x == 256
     for (int j = 0; j < k; ++j) {
         if (threadIdx.x == 0) {
-            const double d = A[j * k + j];
+            const double d = at(j, j);
             if (!(d > tiny) || !isfinite(d)) {
                 bad = 1;
-                A[j * k + j] = 1.0;
+                at(j, j) = 1.0;
             } else {
-                A[j * k + j] = sqrt(d);
+                at(j, j) = sqrt(d);
             }
         }
         __syncthreads();
-        const double ljj = A[j * k + j];
-        for (int i = j + 1 + threadIdx.x; i < k; i += blockDim.x) A[i * k + j] /= ljj;
+        const double inv = 1.0 / at(j, j);
+        for (int i = j + 1 + threadIdx.x; i < k; i += blockDim.x) at(i, j) *= inv;
         __syncthreads();
-        // trailing update of the lower triangle: A[i][l] -= A[i][j] A[l][j], j < l <= i
-        const int m = k - j - 1;
-        const int cnt = m * (m + 1) / 2;
-        for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
-            // t -> (i, l) with l <= i inside the trailing block
-            int ii = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
-            while ((ii + 1) * (ii + 2) / 2 <= t) ++ii;
-            while (ii * (ii + 1) / 2 > t) --ii;
-            const int ll = t - ii * (ii + 1) / 2;
-            const int i = j + 1 + ii, l = j + 1 + ll;
-            A[i * k + l] -= A[i * k + j] * A[l * k + j];
+        // A[i][l] -= L[i][j] L[l][j] for j < l <= i, on a 16 x 16 thread grid
+        for (int i = j + 1 + ty; i < k; i += 16) {
+            const double lij = at(i, j);
+            for (int l = j + 1 + tx; l <= i; l += 16) at(i, l) -= lij * at(l, j);
         }
         __syncthreads();
     }
-    if (A != Lg)
-        for (int i = threadIdx.x; i < k * k; i += blockDim.x) Lg[i] = A[i];
+    if (packed)
+        for (int q = threadIdx.x; q < k * k; q += blockDim.x) {
+            const int i = q / k, l = q - i * k;
+            Lg[q] = l <= i ? sm[tri_idx(i, l)] : 0.0;
+        }
     if (threadIdx.x == 0) status[b] = bad ? TOPO_ENOTSPD : 0;
 }
 
@@ -466,24 +527,41 @@ static int check_basis(Ctx* ctx, const Grid& g, const void* phi, int k, int ldph
     if (k < 1) return set_error(ctx, TOPO_EINVAL, "k must be >= 1");
     if ((long long)k > g.n_dofs) return set_error(ctx, TOPO_EINVAL, "k exceeds the number of DOFs");
     if (ldphi < k) return set_error(ctx, TOPO_EINVAL, "ldphi < k");
+    if (ldphi > 1024) return set_error(ctx, TOPO_EINVAL, "ldphi > 1024 is not supported");
     return TOPO_OK;
+}
+
+// Rows per LDS tile of the basis-streaming kernels: as many as fit in 48 KB (a power of
+// two between 1 and 256).
+static int tile_rows(int ldphi, size_t esz) {
+    const size_t row = (size_t)(ldphi | 1) * esz;
+    int rb = 256;
+    while (rb > 1 && (size_t)rb * row > 48 * 1024) rb >>= 1;
+    return rb;
+}
+
+static size_t tile_bytes(int rb, int ldphi, size_t esz) {
+    return (((size_t)rb * (ldphi | 1) * esz + 15) & ~(size_t)15);
 }
 
 static int phit_v(Ctx* ctx, const Grid& g, const void* phi, int fp32, int k, int ldphi,
                   const uint8_t* mask, const double* v, long long vstride, int B, double* out,
                   double* partials, int nchunks, hipStream_t s) {
     const long long nrows = g.n_dofs;
-    const int rpc = (int)((nrows + nchunks - 1) / nchunks);
-    int cw = 1;
-    while (cw < k && cw < 64) cw *= 2;
+    // rows per chunk a multiple of 4: every tile starts 16-byte aligned in the basis
+    const int rpc = (int)((nrows + nchunks - 1) / nchunks + 3) & ~3;
+    const size_t esz = fp32 ? 4 : 8;
+    const int rb = tile_rows(ldphi, esz);
+    const size_t lds = tile_bytes(rb, ldphi, esz) + (size_t)rb * sizeof(double);
+    if (k > 1024) return set_error(ctx, TOPO_EINVAL, "k > 1024 not supported by the projection kernel");
     {
         TimedLaunch tl(ctx, KID_PHIT_V, s);
         if (fp32)
-            hipLaunchKernelGGL((k_phit_v<float>), dim3(nchunks, B), dim3(256), 0, s, nrows,
-                               (const float*)phi, k, ldphi, mask, v, vstride, rpc, cw, partials);
+            hipLaunchKernelGGL((k_phit_v<float>), dim3(nchunks, B), dim3(256), lds, s, nrows,
+                               (const float*)phi, k, ldphi, mask, v, vstride, rpc, rb, partials);
         else
-            hipLaunchKernelGGL((k_phit_v<double>), dim3(nchunks, B), dim3(256), 0, s, nrows,
-                               (const double*)phi, k, ldphi, mask, v, vstride, rpc, cw, partials);
+            hipLaunchKernelGGL((k_phit_v<double>), dim3(nchunks, B), dim3(256), lds, s, nrows,
+                               (const double*)phi, k, ldphi, mask, v, vstride, rpc, rb, partials);
     }
     TOPO_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_colsum_reduce, dim3(grid_blocks((long long)B * k)), dim3(kBlock), 0, s, k,
@@ -699,12 +777,15 @@ int topo_rom_estimate(topo_ctx* ctx, const topo_mesh* mesh, const void* phi, int
     // u = Phi y_hat, r = f - K u, ||r||^2 and f^T u per field
     auto pass = [&]() -> int {
         TimedLaunch tl(ctx, KID_PHI_Y, s);
+        const size_t esz = phi_fp32 ? 4 : 8;
+        const int rb = tile_rows(ldphi, esz);
+        const size_t lds = (size_t)((k + 1) & ~1) * sizeof(double) + tile_bytes(rb, ldphi, esz);
         if (phi_fp32)
-            hipLaunchKernelGGL((k_phi_y<float>), dim3(grid_blocks(N), B), dim3(256), k * sizeof(double), s,
-                               N, (const float*)phi, k, ldphi, mask, yhat, u);
+            hipLaunchKernelGGL((k_phi_y<float>), dim3(grid_blocks(N, rb), B), dim3(256), lds, s,
+                               N, (const float*)phi, k, ldphi, mask, yhat, rb, u);
         else
-            hipLaunchKernelGGL((k_phi_y<double>), dim3(grid_blocks(N), B), dim3(256), k * sizeof(double), s,
-                               N, (const double*)phi, k, ldphi, mask, yhat, u);
+            hipLaunchKernelGGL((k_phi_y<double>), dim3(grid_blocks(N, rb), B), dim3(256), lds, s,
+                               N, (const double*)phi, k, ldphi, mask, yhat, rb, u);
         TOPO_CHECK_LAUNCH();
         return residual_fp64(ctx, g, tb, a64, mask, u, f, r, B, part, out, s);
     };

@@ -197,12 +197,21 @@ __device__ __forceinline__ void node_apply3(const Grid& g, int i, int j, int k,
 // ----------------------------------------------------------------------------------
 constexpr int H3X = T3X + 2, H3Y = T3Y + 2, H3Z = T3Z + 2;
 constexpr int H3N = H3X * H3Y * H3Z;                    // halo nodes per tile
+// LDS row stride of the halo: for float, 16 (mod 32) words, so that the two y-rows of
+// nodes a half-wave reads fall on disjoint banks; double keeps the dense stride (the
+// larger tile would cost occupancy)
+template <typename T> struct Tile3Stride { static constexpr int X = sizeof(T) == 4 ? 48 : H3X; };
+template <typename T>
+__host__ __device__ constexpr int tile3_slot(int q) {
+    return q + (q / H3X) * (Tile3Stride<T>::X - H3X);
+}
 constexpr int E3X = T3X + 1, E3Y = T3Y + 1, E3Z = T3Z + 1;
 constexpr int E3N = E3X * E3Y * E3Z;                    // element alphas per tile
 
 template <typename T>
 struct Tile3Lds {
-    T x[3][H3N];
+    static constexpr int SX = Tile3Stride<T>::X;
+    T x[3][SX * H3Y * H3Z];
     T al[E3N];
 };
 
@@ -248,7 +257,7 @@ __device__ __forceinline__ void tile3_stage(const Grid& g, int i0, int j0, int k
     for (int q = threadIdx.x; q < H3N; q += blockDim.x) {
         const int n = tile3_halo_node(g, i0, j0, k0, q);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) L.x[c][q] = n >= 0 ? fetch(n, c) : T(0);
+        for (int c = 0; c < 3; ++c) L.x[c][tile3_slot<T>(q)] = n >= 0 ? fetch(n, c) : T(0);
     }
 }
 
@@ -263,7 +272,7 @@ __device__ __forceinline__ void tile3_compute(const Tile3Lds<T>& L, const T* __r
         for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
             for (int dx = 0; dx < 3; ++dx) {
-                const int q = ((tz + dz) * H3Y + (ty + dy)) * H3X + (tx + dx);
+                const int q = ((tz + dz) * H3Y + (ty + dy)) * Tile3Lds<T>::SX + (tx + dx);
 #pragma unroll
                 for (int c = 0; c < 3; ++c) xs[dz][dy][dx][c] = L.x[c][q];
             }
