@@ -55,12 +55,10 @@ __device__ __forceinline__ void tri2(const T* F, int n, T z0, T z1, T* D) {
     D[1] = F[6 * n + 3] * z1;
 }
 
-// D = s * R A for one column: A[a][c] nodal values of the H8 element, F its factor.
+// D = s * L^T G N (= -s R A when N = neg_wht3(A)).
 template <typename T>
-__device__ __forceinline__ void elem_rows3(const T (&A)[8][3], const T* __restrict__ F, T s,
-                                           T (&D)[kRows3]) {
-    T N[8][3];
-    neg_wht3(A, N);
+__device__ __forceinline__ void rows3_from_n(const T (&N)[8][3], const T* __restrict__ F, T s,
+                                             T (&D)[kRows3]) {
     const T h0 = F[kFacH], h1 = F[kFacH + 1], h2 = F[kFacH + 2];
     tri3(F, 0, N[1][0], N[2][1], N[4][2], D + 0);              // normal strains
     tri2(F, 1, N[3][1], N[5][2], D + 3);                       // x translation dropped
@@ -74,15 +72,21 @@ __device__ __forceinline__ void elem_rows3(const T (&A)[8][3], const T* __restri
     for (int r = 0; r < kRows3; ++r) D[r] *= s;
 }
 
-// Y = alpha K_e A for one element (H8): D = -alpha R A by elem_rows3, then
+// D = s * R A for one column: A[a][c] nodal values of the H8 element, F its factor.
+template <typename T>
+__device__ __forceinline__ void elem_rows3(const T (&A)[8][3], const T* __restrict__ F, T s,
+                                           T (&D)[kRows3]) {
+    T N[8][3];
+    neg_wht3(A, N);
+    rows3_from_n(N, F, s, D);
+}
+
 // Y = R^T (-D) = H G^T L (-D) with the fast Walsh-Hadamard transform.  The transformed
 // translation entries are zero, so every Y sums to zero over the nodes (per component)
 // and a rigid motion gives Y = 0 exactly.
 template <typename T>
-__device__ __forceinline__ void elem_apply3(const T (&A)[8][3], const T* __restrict__ F, T alpha,
-                                            T (&Y)[8][3]) {
-    T D[kRows3];
-    elem_rows3(A, F, alpha, D);
+__device__ __forceinline__ void apply3_from_d(const T (&D)[kRows3], const T* __restrict__ F,
+                                              T (&Y)[8][3]) {
     // u = -L D per block (L = Lt^T, lower triangular), scattered to V[m][c] by G^T
     T V[8][3];
     const T h0 = F[kFacH], h1 = F[kFacH + 1], h2 = F[kFacH + 2];
@@ -131,6 +135,15 @@ __device__ __forceinline__ void elem_apply3(const T (&A)[8][3], const T* __restr
 #pragma unroll
         for (int a = 0; a < 8; ++a) Y[a][c] = w[a];
     }
+}
+
+// Y = alpha K_e A for one element (H8).
+template <typename T>
+__device__ __forceinline__ void elem_apply3(const T (&A)[8][3], const T* __restrict__ F, T alpha,
+                                            T (&Y)[8][3]) {
+    T D[kRows3];
+    elem_rows3(A, F, alpha, D);
+    apply3_from_d(D, F, Y);
 }
 
 // D = s * R A for one column of the Q4 element (a = ax + 2 ay).

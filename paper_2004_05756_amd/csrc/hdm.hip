@@ -70,7 +70,8 @@ __global__ __launch_bounds__(kBlock) void k_apply2(Grid g, const T* __restrict__
 }
 
 // Sources of the 3D march (march3.hpp): the values of node planes, fetched two slots
-// per thread, loads issued without waiting.
+// per thread with every load issued unconditionally (an invalid node reads node 0 and
+// is zeroed afterwards).
 template <typename T>
 struct SrcMasked {  // x with Dirichlet DOFs zeroed
     const T* __restrict__ x;
@@ -78,15 +79,12 @@ struct SrcMasked {  // x with Dirichlet DOFs zeroed
     int nn;
     T v[4][3];
     __device__ __forceinline__ void fetch(int slot, int node) {
+        const int n = node >= 0 ? node : 0;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            T xv = T(0);
-            uint8_t mk = 1;
-            if (node >= 0) {
-                xv = x[(size_t)c * nn + node];
-                mk = mask[(size_t)c * nn + node];
-            }
-            v[slot][c] = mk ? T(0) : xv;
+            const T xv = x[c * nn + n];
+            const uint8_t mk = mask[c * nn + n];
+            v[slot][c] = (node < 0 || mk) ? T(0) : xv;
         }
     }
     __device__ __forceinline__ T value(int slot, int c) const { return v[slot][c]; }
@@ -98,8 +96,12 @@ struct SrcPlain {
     int nn;
     T v[4][3];
     __device__ __forceinline__ void fetch(int slot, int node) {
+        const int n = node >= 0 ? node : 0;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) v[slot][c] = node >= 0 ? x[(size_t)c * nn + node] : T(0);
+        for (int c = 0; c < 3; ++c) {
+            const T xv = x[c * nn + n];
+            v[slot][c] = node >= 0 ? xv : T(0);
+        }
     }
     __device__ __forceinline__ T value(int slot, int c) const { return v[slot][c]; }
 };
@@ -112,10 +114,12 @@ struct SrcDirection {  // p_new = z + beta p_old
     int nn;
     T zv[4][3], pv[4][3];
     __device__ __forceinline__ void fetch(int slot, int node) {
+        const int n = node >= 0 ? node : 0;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            zv[slot][c] = node >= 0 ? z[(size_t)c * nn + node] : T(0);
-            pv[slot][c] = node >= 0 ? p[(size_t)c * nn + node] : T(0);
+            const T a = z[c * nn + n], b = p[c * nn + n];
+            zv[slot][c] = node >= 0 ? a : T(0);
+            pv[slot][c] = node >= 0 ? b : T(0);
         }
     }
     __device__ __forceinline__ T value(int slot, int c) const { return zv[slot][c] + beta * pv[slot][c]; }
@@ -123,12 +127,12 @@ struct SrcDirection {  // p_new = z + beta p_old
 
 // Fetch the two prologue planes k0 - 1 (slots 0, 1) and k0 (slots 2, 3).
 template <typename Src>
-__device__ __forceinline__ void march3_prologue(const Grid& g, const MarchBlock& m, Src& src) {
+__device__ __forceinline__ void march3_prologue(const Grid& g, const MarchBlock& m,
+                                                const MarchSlots& sl, Src& src) {
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
-        const int q = threadIdx.x + r * kBlock;
-        src.fetch(r, q < MPN ? march3_node(g, m, q, m.k0 - 1) : -1);
-        src.fetch(2 + r, q < MPN ? march3_node(g, m, q, m.k0) : -1);
+        src.fetch(r, march3_node(g, sl, r, m.k0 - 1));
+        src.fetch(2 + r, march3_node(g, sl, r, m.k0));
     }
 }
 
@@ -143,8 +147,9 @@ __global__ __launch_bounds__(kBlock) void k_apply3(Grid g, const T* __restrict__
     const size_t b = blockIdx.y;
     const MarchBlock m = march3_block(g, xcd_block(blockIdx.x, gridDim.x));
     for (int i = threadIdx.x; i < kFacSize; i += blockDim.x) L.F[i] = F[i];
+    const MarchSlots sl = march3_slots(g, m);
     SrcMasked<T> src{x + b * g.n_dofs, mask, g.n_nodes};
-    march3_prologue(g, m, src);
+    march3_prologue(g, m, sl, src);
     T* yb = y + b * g.n_dofs;
     auto emit = [&](int n, const T (&out)[3], const T (&)[3]) {
 #pragma unroll
@@ -153,7 +158,7 @@ __global__ __launch_bounds__(kBlock) void k_apply3(Grid g, const T* __restrict__
             yb[idx] = mask[idx] ? T(0) : out[c];
         }
     };
-    march3_run(g, m, alpha + b * g.n_elems, L, src, emit);
+    march3_run(g, m, sl, alpha + b * g.n_elems, L, src, emit);
 }
 
 // ----------------------------------------------------------------------------------
@@ -324,8 +329,9 @@ __global__ __launch_bounds__(kBlock) void k_pcg_apply3(Grid g, const T* __restri
     __shared__ double lds[48];
     const MarchBlock m = march3_block(g, xcd_block(blockIdx.x, gridDim.x));
     for (int i = threadIdx.x; i < kFacSize; i += blockDim.x) L.F[i] = F[i];
+    const MarchSlots sl = march3_slots(g, m);
     SrcDirection<T> src{z, p_old, T(0), g.n_nodes};
-    march3_prologue(g, m, src);
+    march3_prologue(g, m, sl, src);
     T tb;
     if (pcg_apply_scalars(part, st, ps, nrz, parity, first, tb, lds)) return;
     src.beta = tb;
@@ -340,7 +346,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_apply3(Grid g, const T* __restri
             v[0] += (double)pn[c] * (double)qv;
         }
     };
-    march3_run(g, m, alpha, L, src, emit);
+    march3_run(g, m, sl, alpha, L, src, emit);
     block_reduce<1>(v, lds);
     if (threadIdx.x == 0) part[blockIdx.x] = v[0];
 }
@@ -545,15 +551,16 @@ __global__ __launch_bounds__(kBlock) void k_residual3(Grid g, const double* __re
     const double* ub = u + b * g.n_dofs;
     const MarchBlock m = march3_block(g, xcd_block(blockIdx.x, gridDim.x));
     for (int i = threadIdx.x; i < kFacSize; i += blockDim.x) L.F[i] = F[i];
+    const MarchSlots sl = march3_slots(g, m);
     SrcPlain<double> src{ub, g.n_nodes};
-    march3_prologue(g, m, src);
+    march3_prologue(g, m, sl, src);
     double v[3] = {0.0, 0.0, 0.0};
     double* rb = r ? r + b * g.n_dofs : nullptr;
     auto emit = [&](int n, const double (&o)[3], const double (&)[3]) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) residual_dof(mask, f, ub, rb, (size_t)c * g.n_nodes + n, o[c], v);
     };
-    march3_run(g, m, alpha + b * g.n_elems, L, src, emit);
+    march3_run(g, m, sl, alpha + b * g.n_elems, L, src, emit);
     residual_partials(v, part, b, lds);
 }
 

@@ -38,29 +38,88 @@ struct MarchLds {
     T F[kFacSize];
 };
 
-// Node of plane slot q at node plane k, or -1 outside the grid.
-__device__ __forceinline__ int march3_node(const Grid& g, const MarchBlock& m, int q, int k) {
-    const int px = q % MPX, py = q / MPX;
-    const int i = m.i0 - 1 + px, j = m.j0 - 1 + py;
-    const bool ok = (i >= 0) & (i < g.nx1) & (j >= 0) & (j < g.ny1) & (k >= 0) & (k < g.nz1);
-    return ok ? (k * g.ny1 + j) * g.nx1 + i : -1;
+// Plane slots of this thread (q = tid and tid + kBlock): the node index at plane 0
+// (or -1 when the column lies outside the grid); plane k adds k * (nx1 * ny1).
+struct MarchSlots {
+    int base[2];
+    int pstride;
+};
+
+__device__ __forceinline__ MarchSlots march3_slots(const Grid& g, const MarchBlock& m) {
+    MarchSlots sl;
+    sl.pstride = g.nx1 * g.ny1;
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const int q = threadIdx.x + r * kBlock;
+        const int px = q % MPX, py = q / MPX;
+        const int i = m.i0 - 1 + px, j = m.j0 - 1 + py;
+        const bool ok = (q < MPN) & (i >= 0) & (i < g.nx1) & (j >= 0) & (j < g.ny1);
+        sl.base[r] = ok ? j * g.nx1 + i : -1;
+    }
+    return sl;
 }
 
-// The march.  Src (per plane slot, this thread's two slots):
+// Node of slot r at node plane k, or -1.
+__device__ __forceinline__ int march3_node(const Grid& g, const MarchSlots& sl, int r, int k) {
+    return (sl.base[r] >= 0 && k >= 0 && k < g.nz1) ? sl.base[r] + k * sl.pstride : -1;
+}
+
+// Per face (the 4 nodes f = fx + 2 fy of one z level of an element) and component:
+// the sum and the y-alternating difference of its two x-edge differences, and the sum
+// of its two y-edge differences.  Shared by the element below and the one above.
+template <typename T>
+struct FaceSums {
+    T X[3], Xs[3], Y[3];
+};
+
+template <typename T>
+__device__ __forceinline__ void face_sums(const T (&a)[4][3], FaceSums<T>& f) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const T dx0 = a[1][c] - a[0][c], dx1 = a[3][c] - a[2][c];
+        const T dy0 = a[2][c] - a[0][c], dy1 = a[3][c] - a[1][c];
+        f.X[c] = dx0 + dx1;
+        f.Xs[c] = dx0 - dx1;
+        f.Y[c] = dy0 + dy1;
+    }
+}
+
+// N = neg_wht3 of the element from its bottom (b) and top (t) faces.
+template <typename T>
+__device__ __forceinline__ void neg_wht3_faces(const T (&ab)[4][3], const T (&at)[4][3],
+                                               const FaceSums<T>& fb, const FaceSums<T>& ft,
+                                               T (&N)[8][3]) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        N[0][c] = T(0);
+        N[1][c] = fb.X[c] + ft.X[c];
+        N[3][c] = fb.Xs[c] + ft.Xs[c];
+        N[5][c] = fb.X[c] - ft.X[c];
+        N[7][c] = fb.Xs[c] - ft.Xs[c];
+        N[2][c] = fb.Y[c] + ft.Y[c];
+        N[6][c] = fb.Y[c] - ft.Y[c];
+        N[4][c] = ((at[0][c] - ab[0][c]) + (at[1][c] - ab[1][c])) +
+                  ((at[2][c] - ab[2][c]) + (at[3][c] - ab[3][c]));
+    }
+}
+
+// The march.  Src (this thread's two plane slots):
 //   fetch(int slot_index, int node)  issue the loads of node (node may be -1: zero)
 //   value(int slot_index, int c)     the fetched value
 // Emit (owned nodes, in node-plane order):
 //   emit(int node, const T (&y)[3], const T (&xn)[3])  y = (K x)(node), xn = x(node)
-// The caller has fetched planes k0-1 (set 0) and k0 (set 1) and calls with them.
+// The caller has fetched planes k0-1 (slots 0, 1) and k0 (slots 2, 3).
 template <typename T, typename Src, typename Emit>
 __device__ __forceinline__ void march3_run(const Grid& g, const MarchBlock& m,
-                                           const T* __restrict__ alpha, MarchLds<T>& L,
-                                           Src& src, Emit& emit) {
+                                           const MarchSlots& sl, const T* __restrict__ alpha,
+                                           MarchLds<T>& L, Src& src, Emit& emit) {
     const int tid = threadIdx.x;
     const int tx = tid % MEX, ty = tid / MEX;
     const int ex = m.i0 - 1 + tx, ey = m.j0 - 1 + ty;
     const bool exy = (ex >= 0) & (ex < g.nx) & (ey >= 0) & (ey < g.ny);
-    // commit the two prologue planes (src sets 0, 1) to LDS buffers 0, 1
+    const int abase = exy ? ey * g.nx + ex : 0;
+    const int astride = g.nx * g.ny;
+    // commit the two prologue planes to LDS buffers 0, 1
 #pragma unroll
     for (int set = 0; set < 2; ++set)
 #pragma unroll
@@ -74,11 +133,14 @@ __device__ __forceinline__ void march3_run(const Grid& g, const MarchBlock& m,
     T top[4][3];
 #pragma unroll
     for (int v = 0; v < 4; ++v) top[v][0] = top[v][1] = top[v][2] = T(0);
-    T al_next = T(0);
-    {
-        const int ez = m.k0 - 1;
-        if (exy && ez >= 0 && ez < g.nz) al_next = alpha[((size_t)ez * g.ny + ey) * g.nx + ex];
-    }
+    auto alpha_at = [&](int ez) -> T {
+        const bool ok = exy && ez >= 0 && ez < g.nz;
+        const T a = alpha[ok ? (size_t)ez * astride + abase : 0];
+        return ok ? a : T(0);
+    };
+    T al_next = alpha_at(m.k0 - 1);
+    T ab[4][3];        // bottom face of the current element (carried from the step before)
+    FaceSums<T> fb;
     for (int s = 0; s <= K; ++s) {
         const int ez = m.k0 - 1 + s;  // element layer between node planes ez and ez + 1
         const int bot = s & 1, topb = (s + 1) & 1;
@@ -97,32 +159,37 @@ __device__ __forceinline__ void march3_run(const Grid& g, const MarchBlock& m,
         const T al = al_next;
         if (s < K) {
 #pragma unroll
-            for (int r = 0; r < 2; ++r) {
-                const int q = tid + r * kBlock;
-                src.fetch(r, q < MPN ? march3_node(g, m, q, ez + 2) : -1);
+            for (int r = 0; r < 2; ++r) src.fetch(r, march3_node(g, sl, r, ez + 2));
+            al_next = alpha_at(ez + 1);
+        }
+        if (s == 0) {
+#pragma unroll
+            for (int f = 0; f < 4; ++f) {
+                const int q = (ty + (f >> 1)) * MPX + tx + (f & 1);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) ab[f][c] = L.plane[bot][c][q];
             }
-            const int ezn = ez + 1;
-            al_next = (exy && ezn < g.nz) ? alpha[((size_t)ezn * g.ny + ey) * g.nx + ex] : T(0);
+            face_sums(ab, fb);
         }
-        // this thread's element: nodes a = ax + 2 ay + 4 az
-        T A[8][3], Y[8][3];
+        T at[4][3];
 #pragma unroll
-        for (int a = 0; a < 8; ++a) {
-            const int q = (ty + ((a >> 1) & 1)) * MPX + tx + (a & 1);
-            const int buf = (a >> 2) ? topb : bot;
+        for (int f = 0; f < 4; ++f) {
+            const int q = (ty + (f >> 1)) * MPX + tx + (f & 1);
 #pragma unroll
-            for (int c = 0; c < 3; ++c) A[a][c] = L.plane[buf][c][q];
+            for (int c = 0; c < 3; ++c) at[f][c] = L.plane[topb][c][q];
         }
-        elem_apply3(A, L.F, al, Y);
+        FaceSums<T> ft;
+        face_sums(at, ft);
+        T N[8][3], D[kRows3], Y[8][3];
+        neg_wht3_faces(ab, at, fb, ft, N);
+        rows3_from_n(N, L.F, al, D);
+        apply3_from_d(D, L.F, Y);
         // node plane ez: corner sums of the layer below (top) and this layer (bottom)
-        T xn[3];
         if (s >= 1) {
 #pragma unroll
             for (int v = 0; v < 4; ++v)
 #pragma unroll
                 for (int c = 0; c < 3; ++c) L.xch[c][v][tid] = top[v][c] + Y[v][c];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) xn[c] = L.plane[bot][c][ty * MPX + tx];
         }
         __syncthreads();
         if (s >= 1 && tx >= 1 && ty >= 1) {
@@ -133,13 +200,17 @@ __device__ __forceinline__ void march3_run(const Grid& g, const MarchBlock& m,
                 for (int c = 0; c < 3; ++c)
                     y[c] = (L.xch[c][3][tid - MEX - 1] + L.xch[c][2][tid - MEX]) +
                            (L.xch[c][1][tid - 1] + L.xch[c][0][tid]);
-                emit((ez * g.ny1 + j) * g.nx1 + i, y, xn);
+                emit((ez * g.ny1 + j) * g.nx1 + i, y, ab[0]);
             }
         }
 #pragma unroll
         for (int v = 0; v < 4; ++v)
 #pragma unroll
-            for (int c = 0; c < 3; ++c) top[v][c] = Y[v + 4][c];
+            for (int c = 0; c < 3; ++c) {
+                top[v][c] = Y[v + 4][c];
+                ab[v][c] = at[v][c];
+            }
+        fb = ft;
     }
 }
 
