@@ -37,7 +37,7 @@ def parse():
     ap.add_argument("--prec", choices=["mixed", "fp64"], default="mixed")
     ap.add_argument("--rtol", type=float, default=None)
     ap.add_argument("--k", type=int, default=None)
-    ap.add_argument("--max-refine", type=int, default=2)
+    ap.add_argument("--max-refine", type=int, default=1)
     ap.add_argument("--rom-evals", type=int, default=200, help="ROM evaluations per precision for evals/s and latency")
     ap.add_argument("--timing-every", type=int, default=4, help="sample one launch in N of each hot kernel")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-stream leg")
     ap.add_argument("--serving-requests", type=int, default=512)
     ap.add_argument("--serving-workers", type=int, default=4)
+    ap.add_argument("--no-bridge", action="store_true",
+                    help="skip the 192x96x96 leg (16-field batched apply, one HDM solve per precision)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes (5 times), the "
                          "reference kernel that scales the HBM byte counters")
@@ -192,7 +194,7 @@ def serving_leg(args, torch, W, binding, FP64, MIXED):
         rho = pool[q.mesh][q.rho_id]
         if q.kind == "hdm":
             return srv.submit_hdm(mid, rho, rtol=c.rtol, prec=MIXED)
-        return srv.submit_rom(mid, bid, q.k, rho, prec=MIXED, max_refine=2)
+        return srv.submit_rom(mid, bid, q.k, rho, prec=MIXED, max_refine=1)
 
     warm = []
     seen = set()
@@ -252,6 +254,55 @@ def serving_leg(args, torch, W, binding, FP64, MIXED):
         "failed": failed,
         "workers": args.serving_workers,
     }
+
+
+def bridge_leg(torch, W, binding, FP64, MIXED):
+    """The 192x96x96 bridge: the 16-field batched apply in both precisions (kernel time
+    from the library's sampled events, algorithmic bytes, HBM fraction) and one HDM
+    solve per precision to the workload's tolerance.  The 16 density fields are four
+    seeded smoothed fields, each used four times (the smoothing of 16 fields on the host
+    would dominate the leg; the apply's cost does not depend on the values)."""
+    cfg = W.config("bridge3d_192x96x96")
+    p, m = cfg.problem, cfg.problem.mesh
+    dev = torch.device("cuda", 0)
+    base = [cfg.rho(i) for i in range(4)]
+    rhos = torch.as_tensor(np.stack([base[i % 4] for i in range(cfg.batch)])).to(dev)
+    mask = torch.as_tensor(p.mask).to(dev)
+    f = torch.as_tensor(p.f).to(dev)
+    ctx = binding.Context(0)
+    out = {"workload": cfg.name, "n_dofs": m.n_dofs, "fields": cfg.batch}
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(7)
+    for name, pr, dt in (("mixed", MIXED, torch.float32), ("fp64", FP64, torch.float64)):
+        w = 4 if pr == MIXED else 8
+        x = torch.randn(cfg.batch, m.n_dofs, device=dev, dtype=dt, generator=gen)
+        y = torch.empty_like(x)
+        for _ in range(2):
+            ctx.apply(m, rhos, mask, x, y=y, prec=pr)
+        torch.cuda.synchronize()
+        ctx.kernel_time("apply", reset=True)
+        ctx.set_timing(1)
+        reps = 10
+        for _ in range(reps):
+            ctx.apply(m, rhos, mask, x, y=y, prec=pr)
+        torch.cuda.synchronize()
+        ctx.set_timing(0)
+        n, ms = ctx.kernel_time("apply", reset=True)
+        us = 1e3 * ms / max(n, 1)
+        nbytes = cfg.batch * (m.n_dofs * (2 * w + 1) + m.n_elems * w)
+        gbs = nbytes / (us * 1e-6) / 1e9
+        out[f"apply_{name}"] = {"kernel_us": us, "bytes_per_launch": nbytes, "GB_s": gbs,
+                                "hbm_frac": gbs / HBM_PEAK_GBS}
+        del x, y
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, inf = ctx.hdm_solve(m, rhos[0], mask, f, rtol=cfg.rtol, prec=pr)
+        torch.cuda.synchronize()
+        dt_s = time.perf_counter() - t0
+        out[f"hdm_{name}"] = {"ms": 1e3 * dt_s, "iters": inf["iters"], "fp64_fallback": inf["fp64_fallback"],
+                              "rel_resid": inf["rel_resid"], "dof_iter_per_s": m.n_dofs * inf["iters"] / dt_s}
+    ctx.close()
+    return out
 
 
 def main():
@@ -419,6 +470,9 @@ def main():
 
     if not args.no_serving:
         out["serving"] = serving_leg(args, torch, W, binding, FP64, MIXED)
+
+    if not args.no_bridge:
+        out["bridge"] = bridge_leg(torch, W, binding, FP64, MIXED)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, phi_np, iters / args.steps, m.n_dofs)

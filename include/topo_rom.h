@@ -120,6 +120,19 @@ int topo_ctx_kernel_time(topo_ctx* ctx, const char* kernel, int64_t* samples,
  * a = ax + 2*ay (+ 4*az).  K0: HOST array of (dim*2^dim)^2 doubles, row-major. */
 int topo_element_stiffness(const topo_mesh* mesh, double* K0);
 
+/* Symmetry-blocked factor K_e = R^T R that the apply, the residual and the K_hat
+ * contraction evaluate (R: 5 rows for Q4, 18 for H8).  In the Walsh-Hadamard basis
+ * N[m][c] = -sum_a (-1)^{popcount(m & a)} x[a][c] of an element vector x, K_e splits
+ * into one block per reflection character n (entries (n ^ 2^c, c), c < dim).  Blocks
+ * with one set bit drop their rigid translation entry; blocks with two set bits c < d
+ * combine h[c] N[n^2^c][c] + h[d] N[n^2^d][d] (which annihilates the rotation in that
+ * plane) followed by the remaining entry; blocks 0 and 7 keep all three entries.  F:
+ * HOST array of 51 doubles: per block n (0 .. 2^dim - 1) six slots holding the upper-
+ * triangular transposed Cholesky factor of the reduced block (L00 L01 L02 L11 L12 L22,
+ * unused slots zero), then h[0..2] at 48..50.  TOPO_EINVAL for a mesh whose element
+ * operator does not have that structure (not produced by valid meshes). */
+int topo_element_factor(const topo_mesh* mesh, double* F);
+
 /* ---- full-order model ----------------------------------------------------------- */
 
 /* Matrix-free operator apply y_b = K(rho_b) x_b for B fields (Sec. 2.1,

@@ -20,7 +20,8 @@ FP64, MIXED = 0, 1
 # every symbol the public headers declare
 EXPORTED = (
     "topo_ctx_create", "topo_ctx_destroy", "topo_last_error", "topo_strerror",
-    "topo_ctx_workspace_bytes", "topo_element_stiffness", "topo_apply", "topo_hdm_solve",
+    "topo_ctx_workspace_bytes", "topo_element_stiffness", "topo_element_factor", "topo_apply",
+    "topo_hdm_solve",
     "topo_hdm_gradient", "topo_rom_build", "topo_rom_solve", "topo_rom_estimate",
     "topo_ctx_set_timing", "topo_ctx_kernel_time",
 )
@@ -58,6 +59,7 @@ _SIGS = {
     "topo_ctx_kernel_time": (C.c_int, [_P, C.c_char_p, C.POINTER(C.c_int64), C.POINTER(C.c_double),
                                        C.c_int32]),
     "topo_element_stiffness": (C.c_int, [C.POINTER(TopoMesh), C.POINTER(C.c_double)]),
+    "topo_element_factor": (C.c_int, [C.POINTER(TopoMesh), C.POINTER(C.c_double)]),
     "topo_apply": (C.c_int, [_P, C.POINTER(TopoMesh), _P, _P, _P, _P, C.c_int32, C.c_int32, _P]),
     "topo_hdm_solve": (C.c_int, [_P, C.POINTER(TopoMesh), _P, _P, _P, _P, C.c_double, C.c_int32,
                                  C.c_int32, C.POINTER(C.c_double), C.POINTER(TopoInfo), _P]),
@@ -118,6 +120,17 @@ def element_stiffness(mesh):
     if rc != TOPO_OK:
         raise TopoError(rc, "element stiffness")
     return np.frombuffer(out, dtype=np.float64).reshape(ne, ne).copy()
+
+
+def element_factor(mesh):
+    """The 51-entry symmetry-blocked factor table of the element operator."""
+    import numpy as np
+    m = make_mesh(mesh)
+    out = (C.c_double * 51)()
+    rc = load().topo_element_factor(C.byref(m), out)
+    if rc != TOPO_OK:
+        raise TopoError(rc, "element factor")
+    return np.frombuffer(out, dtype=np.float64).copy()
 
 
 def _ptr(t, dtype=None, name="tensor"):

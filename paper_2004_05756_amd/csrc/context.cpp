@@ -453,4 +453,15 @@ int topo_element_stiffness(const topo_mesh* mesh, double* K0) {
     return TOPO_OK;
 }
 
+int topo_element_factor(const topo_mesh* mesh, double* F) {
+    if (!F) return TOPO_EINVAL;
+    int rc = validate_mesh(nullptr, mesh);
+    if (rc) return rc;
+    std::vector<double> K, fac;
+    element_stiffness(*mesh, K);
+    if (!element_factor(*mesh, K, fac)) return TOPO_EINVAL;
+    std::memcpy(F, fac.data(), fac.size() * sizeof(double));
+    return TOPO_OK;
+}
+
 }  // extern "C"

@@ -235,15 +235,6 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
     return x * q + (x < r ? x : r) + b / kXcds;
 }
 
-// 3D node tile of the stencil kernels: one block of kBlock threads per tile.
-constexpr int T3X = 16, T3Y = 4, T3Z = 4;
-static_assert(T3X * T3Y * T3Z == kBlock, "one thread per tile node");
-
-// Node tiles of a 3D grid.
-__host__ __device__ inline int stencil_tiles3(const Grid& g) {
-    return ((g.nx1 + T3X - 1) / T3X) * ((g.ny1 + T3Y - 1) / T3Y) * ((g.nz1 + T3Z - 1) / T3Z);
-}
-
 // 3D element-centric march: a block owns 31 x 7 node columns (a 32 x 8 tile of element
 // columns) over KZ node planes, with KZ chosen for about four blocks per CU.
 constexpr int MEX = 32, MEY = 8;             // element tile (one thread each)

@@ -75,3 +75,64 @@ def test_null_context_is_einval(lib):
     m = binding.make_mesh(W.Mesh((4, 3)))
     assert lib.topo_hdm_gradient(None, C.byref(m), None, None, None, None) == binding.TOPO_EINVAL
     assert lib.topo_rom_solve(None, 4, 1, None, None, None, None, None, None) == binding.TOPO_EINVAL
+
+
+def _reconstruct_from_factor(F, dim, h):
+    """K = R^T R from the documented factor layout (written here from the header's
+    description, independently of the library)."""
+    nen = 1 << dim
+    ne = dim * nen
+    Hs = np.array([[(-1.0) ** bin(m & a).count("1") for a in range(nen)] for m in range(nen)])
+    rows = []
+    for n in range(nen):
+        bits = [c for c in range(dim) if (n >> c) & 1]
+        # reduced coordinates as combinations g[(m, c)] of the N entries
+        if len(bits) == 1:
+            coords = [{(n ^ (1 << c), c): 1.0} for c in range(dim) if c != bits[0]]
+        elif len(bits) == 2:
+            c, d = bits
+            coords = [{(n ^ (1 << c), c): h[c], (n ^ (1 << d), d): h[d]}]
+            coords += [{(n ^ (1 << k), k): 1.0} for k in range(dim) if k not in bits]
+        else:
+            coords = [{(n ^ (1 << c), c): 1.0} for c in range(dim)]
+        r = len(coords)
+        slot = {(0, 0): 0, (0, 1): 1, (0, 2): 2, (1, 1): 3, (1, 2): 4, (2, 2): 5}
+        Lt = np.zeros((r, r))
+        for i in range(r):
+            for j in range(i, r):
+                Lt[i, j] = F[6 * n + slot[(i, j)]]
+        # z_j as a row vector over DOFs (a, c): N[m][c] = -sum_a H[m][a] x[a][c]
+        Z = np.zeros((r, ne))
+        for j, comb in enumerate(coords):
+            for (m, c), w in comb.items():
+                for a in range(nen):
+                    Z[j, dim * a + c] -= w * Hs[m, a]
+        rows.append(Lt @ Z)
+    R = np.vstack(rows)
+    return R
+
+
+@pytest.mark.parametrize("dim,h", [(2, (1.0, 1.0, 1.0)), (2, (1.0, 0.5, 1.0)), (3, (1.0, 1.0, 1.0)),
+                                   (3, (1.0, 0.7, 1.3)), (3, (2.0, 2.0, 2.0))])
+def test_element_factor_reconstructs_oracle_Ke(dim, h):
+    """The symmetry-blocked factor the kernels use gives back the oracle's K_e (R^T R),
+    has the element's rank (5 / 18 rows) and annihilates the rigid motions."""
+    from paper_2004_05756_amd import binding
+    nel = (4, 3, 2) if dim == 3 else (4, 3)
+    m = W.Mesh(nel=nel, h=tuple(h[:dim]))
+    F = binding.element_factor(m)
+    R = _reconstruct_from_factor(F, dim, h)
+    assert R.shape[0] == (5 if dim == 2 else 18)
+    Ke = O.element_stiffness(dim, np.array(h[:dim]), 1.0, 0.3, True)
+    assert np.abs(R.T @ R - Ke).max() <= 1e-13 * np.abs(Ke).max()
+    # rigid translations and rotations are exactly in the null space of R
+    nen = 1 << dim
+    coords = np.array([[(a >> c) & 1 for c in range(dim)] for a in range(nen)], float) * np.array(h[:dim])
+    modes = []
+    for c in range(dim):
+        v = np.zeros((nen, dim)); v[:, c] = 1.0; modes.append(v)
+    for c in range(dim):
+        for d in range(c + 1, dim):
+            v = np.zeros((nen, dim)); v[:, c] = -coords[:, d]; v[:, d] = coords[:, c]; modes.append(v)
+    for v in modes:
+        assert np.abs(R @ v.reshape(-1)).max() <= 1e-13 * np.abs(R).max() * np.abs(v).max()
