@@ -219,41 +219,83 @@ __global__ __launch_bounds__(WAVES * 64) void k_rom_contract(
     }
 }
 
-// Sum partial tiles over chunks (fixed order) and write the symmetric K_hat.
-__global__ void k_rom_reduce(int k, int KP, int nchunks, int B, const double* __restrict__ partials,
-                             double* __restrict__ Khat) {
-    const int kt = KP / 16;
-    const int npairs = kt * (kt + 1) / 2;
-    const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const size_t total = (size_t)B * npairs * 256;
-    if (gid >= total) return;
-    const int e = gid % 256;
-    const size_t bp = gid / 256;
-    const int p = bp % npairs;
-    const int b = bp / npairs;
-    int I, J;
-    pair_of(p, kt, I, J);
-    const int i = I * 16 + e / 16;
-    const int j = J * 16 + e % 16;
-    if (i >= k || j >= k || i > j) return;  // keep the upper triangle only
-    // eight independent accumulators keep eight loads in flight; fixed combination order
-    const double* src = partials + ((size_t)b * nchunks * npairs + p) * 256 + e;
-    const size_t stride = (size_t)npairs * 256;
+// ----------------------------------------------------------------------------------
+// Sum of per-chunk partials: out(b, e) = sum_c partials[b][c][e] for e < m.  A block of
+// 1024 threads covers CW = 1024 / S consecutive entries with S chunk slices; slice s
+// sums chunks s, s + S, ... (eight loads in flight), and the S slice sums are combined
+// by a pairwise tree in LDS.  The order depends on nchunks and S only, and S on
+// nchunks only, so a field's result is bitwise the same alone and inside a batch.
+// ----------------------------------------------------------------------------------
+constexpr int kSumBlock = 1024;
+
+static int chunk_slices(int nchunks) {
+    int S = 1;
+    while (S < 32 && (nchunks + S - 1) / S > 32) S *= 2;
+    return S;
+}
+
+template <typename Epi>
+__global__ __launch_bounds__(kSumBlock) void k_chunk_sum(int m, int nchunks, int S,
+                                                         const double* __restrict__ partials, Epi epi) {
+    __shared__ double red[kSumBlock];
+    const int CW = kSumBlock / S;
+    const int col = threadIdx.x % CW, sl = threadIdx.x / CW;
+    const int e = blockIdx.x * CW + col;
+    const int b = blockIdx.y;
     double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    int c = 0;
-    for (; c + 8 <= nchunks; c += 8)
+    if (e < m) {
+        const double* src = partials + (size_t)b * nchunks * m + e;
+        int c = sl;
+        for (; c + 7 * S < nchunks; c += 8 * S)
 #pragma unroll
-        for (int q = 0; q < 8; ++q) acc[q] += src[(size_t)(c + q) * stride];
-    for (; c < nchunks; ++c) acc[c & 7] += src[(size_t)c * stride];
-    const double s = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
-    double* Kb = Khat + (size_t)b * k * k;
-    Kb[(size_t)i * k + j] = s;
-    Kb[(size_t)j * k + i] = s;
+            for (int q = 0; q < 8; ++q) acc[q] += src[(size_t)(c + q * S) * m];
+#pragma unroll
+        for (int q = 0; q < 7; ++q)
+            if (c + q * S < nchunks) acc[q] += src[(size_t)(c + q * S) * m];
+    }
+    red[threadIdx.x] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+    __syncthreads();
+    for (int h = S >> 1; h > 0; h >>= 1) {
+        if (sl < h) red[threadIdx.x] += red[threadIdx.x + h * CW];
+        __syncthreads();
+    }
+    if (sl == 0 && e < m) epi(b, e, red[threadIdx.x]);
+}
+
+// Column sums: out[b][j], m = k.
+struct ColsumOut {
+    int k;
+    double* out;
+    __device__ void operator()(int b, int j, double s) const { out[(size_t)b * k + j] = s; }
+};
+
+// Partial 16 x 16 tiles of K_hat (npairs upper-triangle tile pairs): write the
+// symmetric matrix from its upper triangle.
+struct KhatOut {
+    int k, kt;
+    double* Khat;
+    __device__ void operator()(int b, int e, double s) const {
+        int I, J;
+        pair_of(e / 256, kt, I, J);
+        const int i = I * 16 + (e % 256) / 16, j = J * 16 + e % 16;
+        if (i >= k || j >= k || i > j) return;
+        double* Kb = Khat + (size_t)b * k * k;
+        Kb[(size_t)i * k + j] = s;
+        Kb[(size_t)j * k + i] = s;
+    }
+};
+
+template <typename Epi>
+static void launch_chunk_sum(int m, int nchunks, int B, const double* partials, Epi epi, hipStream_t s) {
+    const int S = chunk_slices(nchunks);
+    const int CW = kSumBlock / S;
+    hipLaunchKernelGGL((k_chunk_sum<Epi>), dim3((m + CW - 1) / CW, B), dim3(kSumBlock), 0, s, m, nchunks, S,
+                       partials, epi);
 }
 
 // ----------------------------------------------------------------------------------
 // out[b][j] = sum_i Phi[i][j] v[b][i] over free rows i (float64 accumulation).
-// grid.x: row chunks, grid.y: b.  Partials [b][chunk][k], reduced by k_colsum_reduce.
+// grid.x: row chunks, grid.y: b.  Partials [b][chunk][k], summed by k_chunk_sum.
 // ----------------------------------------------------------------------------------
 // Phi is row-major, so a tile of rb consecutive rows is one contiguous stretch of
 // memory: the block copies it into LDS with coalesced loads (rows padded to an odd
@@ -346,22 +388,6 @@ __global__ __launch_bounds__(256) void k_phit_v(long long nrows, const TP* __res
     }
 }
 
-__global__ void k_colsum_reduce(int k, int nchunks, int B, const double* __restrict__ partials,
-                                double* __restrict__ out) {
-    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid >= B * k) return;
-    const int b = gid / k, j = gid % k;
-    const double* src = partials + (size_t)b * nchunks * k + j;
-    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    int c = 0;
-    for (; c + 8 <= nchunks; c += 8)
-#pragma unroll
-        for (int q = 0; q < 8; ++q) acc[q] += src[(size_t)(c + q) * k];
-    for (; c < nchunks; ++c) acc[c & 7] += src[(size_t)c * k];
-    const double s = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
-    out[gid] = s;
-}
-
 // u[b][i] = Phi[i][:] . y[b][:] on free rows, 0 on Dirichlet rows (float64 accumulation).
 // A block handles a contiguous tile of rb rows (staged in LDS with coalesced loads);
 // 256 / rb threads share a row and combine their column sums with lane shuffles.
@@ -390,81 +416,256 @@ __global__ __launch_bounds__(256) void k_phi_y(long long nrows, const TP* __rest
 }
 
 // ----------------------------------------------------------------------------------
-// Batched float64 Cholesky K = L L^T (one block per matrix, right-looking by column).
-// The lower triangle is kept packed in LDS when it fits (k <= CHOL_LDS_MAX_K),
-// otherwise in the global workspace copy.  The trailing update of each step runs on
-// a 16 x 16 thread grid (rows by ty, columns by tx), with no index decoding.  status[b] = TOPO_ENOTSPD on
-// a pivot that is not positive relative to the largest original diagonal entry.
+// Batched float64 Cholesky K = L L^T (one block of 256 threads per matrix,
+// right-looking by column).  Column j is left unscaled at step j: the trailing update
+// subtracts A[i][j] A[l][j] / A[j][j], and the output divides each column by the
+// square root of its pivot.  status[b] = TOPO_ENOTSPD on a pivot that is not positive
+// relative to the largest original diagonal entry (that pivot is then taken as 1).
+//
+// k <= CHOL_REG_MAX_K: the lower triangle lives in registers on a 16 x 16 thread grid
+// (thread (ty, tx) holds rows ty + 16 r, columns tx + 16 c, c <= r).  At step j the 16
+// threads holding column j publish it through a double-buffered LDS vector, and after
+// one barrier every thread updates its own entries.  Larger k works on the global
+// workspace copy in the same order.
 // ----------------------------------------------------------------------------------
-constexpr int CHOL_LDS_MAX_K = 127;
+constexpr int CHOL_REG_MAX_K = 128;
+constexpr int CHOL_LDS_MAX_K = 127;  // packed factor of the substitution kernel
 
 __device__ __forceinline__ int tri_idx(int i, int l) { return i * (i + 1) / 2 + l; }
 
+__device__ __forceinline__ double chol_pivot(double d, double tiny) {
+    return (d > tiny && isfinite(d)) ? d : 1.0;
+}
+
 __global__ __launch_bounds__(256) void k_chol(int k, const double* __restrict__ Khat,
                                               double* __restrict__ Lout, int* __restrict__ status) {
-    __shared__ double sm[CHOL_LDS_MAX_K * (CHOL_LDS_MAX_K + 1) / 2];
+    __shared__ double col[2][CHOL_REG_MAX_K];
+    __shared__ double piv[CHOL_REG_MAX_K];
+    __shared__ double dmax[256];
     __shared__ int bad;
     const int b = blockIdx.x;
     const double* Kb = Khat + (size_t)b * k * k;
     double* Lg = Lout + (size_t)b * k * k;
-    const bool packed = k <= CHOL_LDS_MAX_K;
-    // element (i, l), l <= i, of the working lower triangle
-    auto at = [&](int i, int l) -> double& { return packed ? sm[tri_idx(i, l)] : Lg[(size_t)i * k + l]; };
-    for (int q = threadIdx.x; q < k * k; q += blockDim.x) {
-        const int i = q / k, l = q - i * k;
-        if (l <= i) at(i, l) = Kb[(size_t)i * k + l];
-        else if (!packed) Lg[q] = 0.0;
-    }
-    if (threadIdx.x == 0) bad = 0;
-    __syncthreads();
-    double maxdiag = 0.0;
-    for (int j = 0; j < k; ++j) maxdiag = fmax(maxdiag, fabs(at(j, j)));
-    const double tiny = 64.0 * k * 2.220446049250313e-16 * maxdiag;
     const int ty = threadIdx.x / 16, tx = threadIdx.x % 16;  // blockDim.x == 256
-    for (int j = 0; j < k; ++j) {
-        if (threadIdx.x == 0) {
-            const double d = at(j, j);
-            if (!(d > tiny) || !isfinite(d)) {
-                bad = 1;
-                at(j, j) = 1.0;
-            } else {
-                at(j, j) = sqrt(d);
+    if (threadIdx.x == 0) bad = 0;
+    // largest original diagonal entry (fixed-order tree)
+    dmax[threadIdx.x] = threadIdx.x < k ? fabs(Kb[(size_t)threadIdx.x * k + threadIdx.x]) : 0.0;
+    for (int q = 256 + threadIdx.x; q < k; q += 256) dmax[threadIdx.x] = fmax(dmax[threadIdx.x], fabs(Kb[(size_t)q * k + q]));
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) dmax[threadIdx.x] = fmax(dmax[threadIdx.x], dmax[threadIdx.x + h]);
+        __syncthreads();
+    }
+    const double tiny = 64.0 * k * 2.220446049250313e-16 * dmax[0];
+    if (k <= CHOL_REG_MAX_K) {
+        constexpr int RM = CHOL_REG_MAX_K / 16;
+        double a[RM][RM];
+#pragma unroll
+        for (int r = 0; r < RM; ++r)
+#pragma unroll
+            for (int c = 0; c <= r; ++c) {
+                const int i = ty + 16 * r, l = tx + 16 * c;
+                a[r][c] = (i < k && l <= i) ? Kb[(size_t)i * k + l] : 0.0;
+            }
+#pragma unroll
+        for (int c0 = 0; c0 < RM; ++c0) {
+            if (16 * c0 >= k) break;
+            const int jn = min(16, k - 16 * c0);
+            for (int jj = 0; jj < jn; ++jj) {
+                const int j = 16 * c0 + jj;
+                double* cv = col[j & 1];
+                if (tx == jj) {
+#pragma unroll
+                    for (int r = c0; r < RM; ++r) {
+                        const int i = ty + 16 * r;
+                        if (i >= j && i < k) cv[i] = a[r][c0];
+                    }
+                }
+                __syncthreads();
+                const double d = cv[j];
+                const double p = chol_pivot(d, tiny);
+                if (threadIdx.x == 0) {
+                    piv[j] = p;
+                    if (p != d) bad = 1;
+                }
+                const double inv = 1.0 / p;
+                double li[RM], lc[RM];
+#pragma unroll
+                for (int r = c0; r < RM; ++r) {
+                    const int i = ty + 16 * r, l = tx + 16 * r;
+                    li[r] = (i > j && i < k) ? cv[i] * inv : 0.0;
+                    lc[r] = (l > j && l < k) ? cv[l] : 0.0;
+                }
+                // entries with l <= j or i >= k meet a zero factor; those with l > i
+                // (upper part of the diagonal tiles) are never written out
+#pragma unroll
+                for (int r = c0; r < RM; ++r)
+#pragma unroll
+                    for (int c = c0; c <= r; ++c) a[r][c] -= li[r] * lc[c];
             }
         }
         __syncthreads();
-        const double inv = 1.0 / at(j, j);
-        for (int i = j + 1 + threadIdx.x; i < k; i += blockDim.x) at(i, j) *= inv;
-        __syncthreads();
-        // A[i][l] -= L[i][j] L[l][j] for j < l <= i, on a 16 x 16 thread grid
-        for (int i = j + 1 + ty; i < k; i += 16) {
-            const double lij = at(i, j);
-            for (int l = j + 1 + tx; l <= i; l += 16) at(i, l) -= lij * at(l, j);
-        }
-        __syncthreads();
-    }
-    if (packed)
+        // L[i][l] = A[i][l] / sqrt(pivot l), L[l][l] = sqrt(pivot l), 0 above
+#pragma unroll
+        for (int r = 0; r < RM; ++r)
+#pragma unroll
+            for (int c = 0; c <= r; ++c) {
+                const int i = ty + 16 * r, l = tx + 16 * c;
+                if (i < k && l <= i) {
+                    const double sp = sqrt(piv[l]);
+                    Lg[(size_t)i * k + l] = l < i ? a[r][c] / sp : sp;
+                }
+            }
         for (int q = threadIdx.x; q < k * k; q += blockDim.x) {
             const int i = q / k, l = q - i * k;
-            Lg[q] = l <= i ? sm[tri_idx(i, l)] : 0.0;
+            if (l > i) Lg[q] = 0.0;
         }
+    } else {
+        auto at = [&](int i, int l) -> double& { return Lg[(size_t)i * k + l]; };
+        for (int q = threadIdx.x; q < k * k; q += blockDim.x) {
+            const int i = q / k, l = q - i * k;
+            Lg[q] = l <= i ? Kb[q] : 0.0;
+        }
+        __syncthreads();
+        for (int j = 0; j < k; ++j) {
+            const double d = at(j, j);
+            const double p = chol_pivot(d, tiny);
+            if (threadIdx.x == 0 && p != d) bad = 1;
+            const double inv = 1.0 / p;
+            for (int i = j + 1 + ty; i < k; i += 16) {
+                const double lij = at(i, j) * inv;
+                for (int l = j + 1 + tx; l <= i; l += 16) at(i, l) -= lij * at(l, j);
+            }
+            __syncthreads();
+        }
+        for (int q = threadIdx.x; q < k * k; q += blockDim.x) {
+            const int i = q / k, l = q - i * k;
+            if (l < i) Lg[q] /= sqrt(chol_pivot(Lg[(size_t)l * k + l], tiny));
+        }
+        __syncthreads();
+        for (int l = threadIdx.x; l < k; l += blockDim.x)
+            Lg[(size_t)l * k + l] = sqrt(chol_pivot(Lg[(size_t)l * k + l], tiny));
+    }
+    __syncthreads();
     if (threadIdx.x == 0) status[b] = bad ? TOPO_ENOTSPD : 0;
 }
 
-// x[b] (+)= L^{-T} L^{-1} rhs[b]; optionally J[b] = c^T x[b]
+// Forward and back substitution L L^T x = rhs (one block per system) with the packed
+// factor in LDS, run by the first wavefront alone: lane l owns rows l and l + 64, the
+// value of the pivot row is broadcast with v_readlane, so no step waits on a barrier.
+// Reciprocal pivots are formed once, up front.
+template <int RM>
+__device__ __forceinline__ void wave_trsv(int k, const double* __restrict__ sl, double (&v)[RM]) {
+    const int lane = threadIdx.x;
+    double rd[RM];
+#pragma unroll
+    for (int r = 0; r < RM; ++r) {
+        const int i = lane + 64 * r;
+        rd[r] = i < k ? 1.0 / sl[tri_idx(i, i)] : 0.0;
+    }
+    auto bcast = [](double x, int src) -> double {
+        const long long u = __double_as_longlong(x);
+        const int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffLL), src);
+        const int hi = __builtin_amdgcn_readlane((int)(u >> 32), src);
+        return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+    };
+    // forward, L w = rhs: after w_j is known, rows i > j drop L[i][j] w_j
+#pragma unroll
+    for (int R = 0; R < RM; ++R) {
+        const int jn = min(64, k - 64 * R);
+        for (int jj = 0; jj < jn; ++jj) {
+            const int j = 64 * R + jj;
+            const double wj = bcast(v[R], jj) * bcast(rd[R], jj);
+            if (lane == jj) v[R] = wj;
+#pragma unroll
+            for (int r = R; r < RM; ++r) {
+                const int i = lane + 64 * r;
+                if (i > j && i < k) v[r] -= sl[tri_idx(i, j)] * wj;
+            }
+        }
+    }
+    // backward, L^T y = w: after y_j is known, rows i < j drop L[j][i] y_j
+#pragma unroll
+    for (int R = RM - 1; R >= 0; --R) {
+        const int jn = min(64, k - 64 * R);
+        for (int jj = jn - 1; jj >= 0; --jj) {
+            const int j = 64 * R + jj;
+            const double yj = bcast(v[R], jj) * bcast(rd[R], jj);
+            if (lane == jj) v[R] = yj;
+#pragma unroll
+            for (int r = 0; r <= R; ++r) {
+                const int i = lane + 64 * r;
+                if (i < j) v[r] -= sl[tri_idx(j, i)] * yj;
+            }
+        }
+    }
+}
+
+// x[b] = L^{-T} L^{-1} rhs[b] (or x[b] += stepw[b] * that when accumulate), and J[b] =
+// c^T x[b] when J is given.
 __global__ __launch_bounds__(256) void k_chol_solve(int k, const double* __restrict__ L,
                                                     const double* __restrict__ rhs, long long rstride,
                                                     double* __restrict__ x, int accumulate,
                                                     const double* __restrict__ stepw,
                                                     const double* __restrict__ cvec,
                                                     double* __restrict__ J) {
-    extern __shared__ double sv[];  // [k]
+    __shared__ double sm[CHOL_LDS_MAX_K * (CHOL_LDS_MAX_K + 1) / 2];
     __shared__ double lds[16];
     const int b = blockIdx.x;
     const double* Lb = L + (size_t)b * k * k;
     const double* rb = rhs + (size_t)b * rstride;
+    double* xb = x + (size_t)b * k;
+    const double w = stepw ? stepw[b] : 1.0;
+    if (k <= CHOL_LDS_MAX_K) {
+        // eight loads in flight per thread
+        const int kk = k * k;
+        for (int q0 = threadIdx.x; q0 < kk; q0 += 8 * 256) {
+            double t[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int q = q0 + 256 * u;
+                t[u] = q < kk ? Lb[q] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int q = q0 + 256 * u;
+                const int i = q / k, l = q - i * k;
+                if (q < kk && l <= i) sm[tri_idx(i, l)] = t[u];
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x >= 64) return;
+        const int lane = threadIdx.x;
+        double v[2];
+        v[0] = lane < k ? rb[lane] : 0.0;
+        v[1] = lane + 64 < k ? rb[lane + 64] : 0.0;
+        if (k <= 64) {
+            double v1[1] = {v[0]};
+            wave_trsv<1>(k, sm, v1);
+            v[0] = v1[0];
+        } else {
+            wave_trsv<2>(k, sm, v);
+        }
+        double jsum = 0.0;
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const int i = lane + 64 * r;
+            if (i < k) {
+                const double xi = accumulate ? xb[i] + w * v[r] : v[r];
+                xb[i] = xi;
+                if (J) jsum += cvec[i] * xi;
+            }
+        }
+        if (J) {
+            for (int off = 32; off > 0; off >>= 1) jsum += __shfl_xor(jsum, off, 64);
+            if (lane == 0) J[b] = jsum;
+        }
+        return;
+    }
+    // larger k: the vector in LDS, column-oriented substitution by the whole block
+    double* sv = sm;  // [k], k <= 1024
     for (int i = threadIdx.x; i < k; i += blockDim.x) sv[i] = rb[i];
     __syncthreads();
-    // forward: L w = rhs (column-oriented)
     for (int j = 0; j < k; ++j) {
         if (threadIdx.x == 0) sv[j] /= Lb[(size_t)j * k + j];
         __syncthreads();
@@ -472,7 +673,6 @@ __global__ __launch_bounds__(256) void k_chol_solve(int k, const double* __restr
         for (int i = j + 1 + threadIdx.x; i < k; i += blockDim.x) sv[i] -= Lb[(size_t)i * k + j] * wj;
         __syncthreads();
     }
-    // backward: L^T y = w
     for (int j = k - 1; j >= 0; --j) {
         if (threadIdx.x == 0) sv[j] /= Lb[(size_t)j * k + j];
         __syncthreads();
@@ -480,8 +680,6 @@ __global__ __launch_bounds__(256) void k_chol_solve(int k, const double* __restr
         for (int i = threadIdx.x; i < j; i += blockDim.x) sv[i] -= Lb[(size_t)j * k + i] * yj;
         __syncthreads();
     }
-    double* xb = x + (size_t)b * k;
-    const double w = stepw ? stepw[b] : 1.0;
     for (int i = threadIdx.x; i < k; i += blockDim.x) xb[i] = accumulate ? xb[i] + w * sv[i] : sv[i];
     if (J) {
         __syncthreads();
@@ -564,8 +762,7 @@ static int phit_v(Ctx* ctx, const Grid& g, const void* phi, int fp32, int k, int
                                (const double*)phi, k, ldphi, mask, v, vstride, rpc, rb, partials);
     }
     TOPO_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_colsum_reduce, dim3(grid_blocks((long long)B * k)), dim3(kBlock), 0, s, k,
-                       nchunks, B, partials, out);
+    launch_chunk_sum(k, nchunks, B, partials, ColsumOut{k, out}, s);
     TOPO_CHECK_LAUNCH();
     return TOPO_OK;
 }
@@ -684,11 +881,9 @@ int topo_rom_build(topo_ctx* ctx, const topo_mesh* mesh, const void* phi, int32_
         }
     }
     if (rc) return rc;
-    const size_t tot = (size_t)B * p.npairs * 256;
     {
         TimedLaunch tl(ctx, KID_ROM_REDUCE, s);
-        hipLaunchKernelGGL(k_rom_reduce, dim3(grid_blocks((long long)tot)), dim3(kBlock), 0, s, k, p.KP,
-                           p.nchunks, B, parts, Khat);
+        launch_chunk_sum(p.npairs * 256, p.nchunks, B, parts, KhatOut{k, p.kt, Khat}, s);
     }
     TOPO_CHECK_LAUNCH();
     if (fhat) {
@@ -719,7 +914,7 @@ int topo_rom_solve(topo_ctx* ctx, int32_t k, int32_t B, const double* Khat, cons
     }
     TOPO_CHECK_LAUNCH();
     TimedLaunch tl(ctx, KID_CHOL_SOLVE, s);
-    hipLaunchKernelGGL(k_chol_solve, dim3(B), dim3(256), k * sizeof(double), s, k, L, fhat, 0LL, yhat,
+    hipLaunchKernelGGL(k_chol_solve, dim3(B), dim3(256), 0, s, k, L, fhat, 0LL, yhat,
                        0, (const double*)nullptr, fhat, Jk);
     TOPO_CHECK_LAUNCH();
     if (!status) {
@@ -822,7 +1017,7 @@ int topo_rom_estimate(topo_ctx* ctx, const topo_mesh* mesh, const void* phi, int
             if (!nact) break;
             TOPO_HIP(hipMemcpyAsync(ybest, yhat, (size_t)B * k * sizeof(double), hipMemcpyDeviceToDevice, s));
             TOPO_HIP(hipMemcpyAsync(stepw, hstep.data(), B * sizeof(double), hipMemcpyHostToDevice, s));
-            hipLaunchKernelGGL(k_chol_solve, dim3(B), dim3(256), k * sizeof(double), s, k, L, rhat,
+            hipLaunchKernelGGL(k_chol_solve, dim3(B), dim3(256), 0, s, k, L, rhat,
                                (long long)k, yhat, 1, (const double*)stepw, (const double*)nullptr,
                                (double*)nullptr);
             TOPO_CHECK_LAUNCH();
