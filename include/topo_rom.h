@@ -33,11 +33,13 @@
  *    otherwise.  Phi must have full column rank on the free DOFs (orthonormality is
  *    not required).
  *  - stream: a hipStream_t (NULL = the null stream).  Work is stream-ordered.  Calls
- *    that need a convergence or pivot decision (hdm_solve, rom_estimate with
- *    max_refine > 0, rom_solve with status == NULL) synchronise that stream and
- *    return the outcome synchronously.
+ *    that report a convergence or pivot outcome to the host (hdm_solve, rom_solve
+ *    with status == NULL) synchronise that stream and return it synchronously; the
+ *    others (rom_build, rom_estimate, hdm_gradient, ...) only enqueue work.
  *  - Threading: a context is used by one host thread at a time; distinct contexts
- *    may run concurrently on distinct streams.
+ *    may run concurrently on distinct streams.  The calls of one context share its
+ *    device workspace, so when they go to different streams the caller orders them
+ *    (for example by synchronising the first stream before the next call).
  *  - Errors: a negative TOPO_E* code; topo_last_error(ctx) gives a message.
  */
 #ifndef TOPO_ROM_H
@@ -201,9 +203,10 @@ int topo_rom_solve(topo_ctx* ctx, int32_t k, int32_t B, const double* Khat,
  *   float64, resnorm[b] = ||r_b||_2.
  * With max_refine > 0 the reduced coefficients are refined in float64, up to
  * max_refine times: yhat += K_hat^{-1} Phi^T r (a step is kept only while the
- * Galerkin residual ||Phi^T r|| of that field decreases), recovering float64 accuracy
- * of a float32 K_hat; then
- * Jk[b] = f^T Phi yhat[b] and resnorm are those of the refined yhat.
+ * Galerkin residual ||Phi^T r|| of that field decreases, and only when K_hat[b]
+ * factors), recovering float64 accuracy of a float32 K_hat; then
+ * Jk[b] = f^T Phi yhat[b] and resnorm are those of the refined yhat.  Every decision is
+ * taken on the device: the call does not synchronise the stream.
  *   yhat [B][k] f64 in/out, Jk [B] f64 out (may be NULL), resnorm [B] f64 out,
  *   Khat [B][k][k] f64 (only read when max_refine > 0). */
 int topo_rom_estimate(topo_ctx* ctx, const topo_mesh* mesh, const void* phi,

@@ -50,14 +50,15 @@ template <> struct Mfma<double> {
 //   grid.z : groups of upper-triangle 16x16 tile pairs (I <= J)
 // Per sub-chunk of ec elements the block stages D in LDS (one thread per element and
 // column: 2^dim gathered basis rows, edge differences, the small triangular blocks),
-// then each wave accumulates its tile pairs K_hat_IJ += D_I^T D_J on the matrix cores,
-// 4 rows per instruction.  Accumulators are flushed to float64 registers after every
-// sub-chunk, and each block writes one float64 partial per tile entry; a second kernel
-// sums the partials over chunks in a fixed order (deterministic).
+// then each wave accumulates its NT tile pairs K_hat_IJ += D_I^T D_J on the matrix
+// cores, 4 rows per instruction.  NT is a template parameter so that a wave's
+// accumulators stay in place over the row loop (no per-pair branch).  Float32
+// accumulators are flushed to float64 registers after every sub-chunk, and each block
+// writes one float64 partial per tile entry; a second kernel sums the partials over
+// chunks in a fixed order (deterministic).
 // ----------------------------------------------------------------------------------
-constexpr int TPW = 8;       // tile pairs per wave
 constexpr int WAVES = 4;     // waves per block
-constexpr int PAIRS_PER_GROUP = TPW * WAVES;
+constexpr int MAX_NT = 8;    // tile pairs per wave (template NT: 1, 2, 4 or 8)
 
 __device__ __forceinline__ void pair_of(int p, int kt, int& I, int& J) {
     // enumerate (I, J), I <= J, row by row
@@ -70,7 +71,7 @@ __device__ __forceinline__ void pair_of(int p, int kt, int& I, int& J) {
     J = i + p;
 }
 
-template <int DIM, typename TP, typename TC>
+template <int DIM, typename TP, typename TC, int NT>
 __global__ __launch_bounds__(WAVES * 64) void k_rom_contract(
     Grid g, const TP* __restrict__ phi, int k, int ldphi, int KP, int LS,
     const uint8_t* __restrict__ mask, const TC* __restrict__ alpha /*[B][Ne]*/,
@@ -99,25 +100,29 @@ __global__ __launch_bounds__(WAVES * 64) void k_rom_contract(
     for (int i = tid; i < kFacSize; i += blockDim.x) sF[i] = F[i];
     for (int i = rows_full * LS + tid; i < rows_alloc * LS; i += blockDim.x) sD[i] = TC(0);
 
-    // this wave's tile pairs
-    int myI[TPW], myJ[TPW];
-    int nmine = 0;
+    // this wave's NT tile pairs (p = group * NT * WAVES + wave + WAVES t); past the last
+    // pair a wave repeats tile (0, 0) and drops the result
+    int myI[NT], myJ[NT];
+    const int pbase = blockIdx.z * NT * WAVES + wave;
+    const bool any = pbase < npairs;  // wave-uniform
 #pragma unroll
-    for (int t = 0; t < TPW; ++t) {
-        const int p = blockIdx.z * PAIRS_PER_GROUP + wave + WAVES * t;
-        if (p < npairs) {
-            pair_of(p, kt, myI[t], myJ[t]);
-            nmine = t + 1;
-        } else {
-            myI[t] = myJ[t] = 0;
-        }
+    for (int t = 0; t < NT; ++t) {
+        const int p = pbase + WAVES * t;
+        if (p < npairs) pair_of(p, kt, myI[t], myJ[t]);
+        else myI[t] = myJ[t] = 0;
     }
+    // float64 sums of the tiles: float32 matrix-core sums are flushed into acc64 after
+    // every sub-chunk; float64 ones accumulate in acc over the whole chunk
     typedef typename Mfma<TC>::acc_t acc_t;
-    double acc64[TPW][4];
+    constexpr bool F32 = sizeof(TC) == 4;
+    double acc64[NT][4];
+    acc_t acc[NT];
 #pragma unroll
-    for (int t = 0; t < TPW; ++t)
+    for (int t = 0; t < NT; ++t) {
+        acc[t] = acc_t{0, 0, 0, 0};
 #pragma unroll
         for (int v = 0; v < 4; ++v) acc64[t][v] = 0.0;
+    }
 
     for (int e0 = e_begin; e0 < e_end; e0 += ec) {
         const int ne_here = min(ec, e_end - e0);
@@ -148,72 +153,92 @@ __global__ __launch_bounds__(WAVES * 64) void k_rom_contract(
             }
         }
         __syncthreads();
-        for (int idx = tid; idx < ec * KP; idx += blockDim.x) {
-            const int el = idx / KP;
-            const int col = idx - el * KP;
-            TC D[NR];
-            if (el < ne_here && col < k) {
-                // every load issued unconditionally (basis rows exist for fixed DOFs too)
-                const uint32_t fr = sFree[el];
-                TP v[NEN][DIM];
+        // U items (element, column) per thread per batch: all their basis loads are in
+        // flight before the first is used.  Indices past the sub-chunk or past k are
+        // clamped to a valid row / column and their D rows are zero.
+        constexpr int U = DIM == 2 ? 4 : 1;
+        const int nitems = ec * KP;
+        for (int idx0 = tid; idx0 < nitems; idx0 += U * blockDim.x) {
+            TP v[U][NEN][DIM];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int idx = idx0 + u * blockDim.x;
+                const int el = min(idx / KP, ec - 1);
+                const int col = min(idx % KP, k - 1);
 #pragma unroll
                 for (int a = 0; a < NEN; ++a) {
                     const size_t n = (size_t)sNode[el][a];
 #pragma unroll
                     for (int c = 0; c < DIM; ++c)
-                        v[a][c] = phi[((size_t)c * g.n_nodes + n) * (size_t)ldphi + col];
+                        v[u][a][c] = phi[((size_t)c * g.n_nodes + n) * (size_t)ldphi + col];
                 }
-                TC A[NEN][DIM];
-#pragma unroll
-                for (int a = 0; a < NEN; ++a)
-#pragma unroll
-                    for (int c = 0; c < DIM; ++c)
-                        A[a][c] = ((fr >> (DIM * a + c)) & 1u) ? (TC)v[a][c] : TC(0);
-                if constexpr (DIM == 2) elem_rows2(A, sF, sSa[el], D);
-                else elem_rows3(A, sF, sSa[el], D);
-            } else {
-#pragma unroll
-                for (int r = 0; r < NR; ++r) D[r] = TC(0);
             }
 #pragma unroll
-            for (int r = 0; r < NR; ++r) sD[(size_t)(el * NR + r) * LS + col] = D[r];
+            for (int u = 0; u < U; ++u) {
+                const int idx = idx0 + u * blockDim.x;
+                const int el = idx / KP;
+                const int col = idx % KP;
+                if (idx < nitems) {
+                    TC D[NR];
+                    if (el < ne_here && col < k) {
+                        const uint32_t fr = sFree[el];
+                        TC A[NEN][DIM];
+#pragma unroll
+                        for (int a = 0; a < NEN; ++a)
+#pragma unroll
+                            for (int c = 0; c < DIM; ++c)
+                                A[a][c] = ((fr >> (DIM * a + c)) & 1u) ? (TC)v[u][a][c] : TC(0);
+                        if constexpr (DIM == 2) elem_rows2(A, sF, sSa[el], D);
+                        else elem_rows3(A, sF, sSa[el], D);
+                    } else {
+#pragma unroll
+                        for (int r = 0; r < NR; ++r) D[r] = TC(0);
+                    }
+#pragma unroll
+                    for (int r = 0; r < NR; ++r) sD[(size_t)(el * NR + r) * LS + col] = D[r];
+                }
+            }
         }
         __syncthreads();
-        // matrix-core accumulation over the rows of this sub-chunk
-        acc_t acc[TPW];
+        // matrix-core accumulation over the rows of this sub-chunk: every operand of a
+        // 4-row step is loaded before its NT instructions
+        if (any) {
+            const int rsub = lane >> 4;   // row inside the 4-row step
+            const int csub = lane & 15;   // column inside the tile
+            const int rows = ne_here * NR;
+            const TC* drow = sD + (size_t)rsub * LS + csub;
+            for (int r0 = 0; r0 < rows; r0 += 4) {
+                TC av[NT], bv[NT];
 #pragma unroll
-        for (int t = 0; t < TPW; ++t) acc[t] = acc_t{0, 0, 0, 0};
-        const int rsub = lane >> 4;   // row inside the 4-row step
-        const int csub = lane & 15;   // column inside the tile
-        const int rows = ne_here * NR;
-        for (int r0 = 0; r0 < rows; r0 += 4) {
-            const TC* drow = sD + (size_t)(r0 + rsub) * LS + csub;
+                for (int t = 0; t < NT; ++t) {
+                    av[t] = drow[(size_t)r0 * LS + myI[t] * 16];
+                    bv[t] = drow[(size_t)r0 * LS + myJ[t] * 16];
+                }
 #pragma unroll
-            for (int t = 0; t < TPW; ++t) {
-                if (t < nmine) {
-                    const TC av = drow[myI[t] * 16];
-                    const TC bv = drow[myJ[t] * 16];
-                    acc[t] = Mfma<TC>::run(av, bv, acc[t]);
+                for (int t = 0; t < NT; ++t) acc[t] = Mfma<TC>::run(av[t], bv[t], acc[t]);
+            }
+            if constexpr (F32) {
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) acc64[t][v] += (double)acc[t][v];
+                    acc[t] = acc_t{0, 0, 0, 0};
                 }
             }
         }
-#pragma unroll
-        for (int t = 0; t < TPW; ++t)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) acc64[t][v] += (double)acc[t][v];
     }
     // write this block's partial tiles: partial[(b, chunk, pair)][16*16]
     const size_t nchunks = gridDim.x;
 #pragma unroll
-    for (int t = 0; t < TPW; ++t) {
-        if (t < nmine) {
-            const int p = blockIdx.z * PAIRS_PER_GROUP + wave + WAVES * t;
+    for (int t = 0; t < NT; ++t) {
+        const int p = pbase + WAVES * t;
+        if (p < npairs) {
             double* dst = partials + (((size_t)b * nchunks + blockIdx.x) * npairs + p) * 256;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int i = Mfma<TC>::row(lane, v);  // row of the 16x16 output tile
                 const int j = lane & 15;            // column
-                dst[i * 16 + j] = acc64[t][v];
+                dst[i * 16 + j] = F32 ? acc64[t][v] : (double)acc[t][v];
             }
         }
     }
@@ -616,6 +641,7 @@ __global__ __launch_bounds__(256) void k_chol_solve(int k, const double* __restr
     const double* rb = rhs + (size_t)b * rstride;
     double* xb = x + (size_t)b * k;
     const double w = stepw ? stepw[b] : 1.0;
+    if (accumulate && w == 0.0) return;  // x unchanged (whatever the factor holds)
     if (k <= CHOL_LDS_MAX_K) {
         // eight loads in flight per thread
         const int kk = k * k;
@@ -709,12 +735,40 @@ __global__ void k_sqnorm_rows(int k, const double* __restrict__ v, double* __res
     if (threadIdx.x == 0) g2[b] = s[0];
 }
 
-// y[b] = ysave[b] where revert[b] != 0
-__global__ void k_restore_rows(int k, const int* __restrict__ revert, const double* __restrict__ ysave,
-                               double* __restrict__ y) {
+// Reduced refinement bookkeeping (one entry per field).  A field refines while its
+// factor is valid and each step lowers its Galerkin residual ||Phi^T r||; `keep` holds
+// the residual-kernel sums (||r||^2, f^T u) of the last accepted y.
+__global__ void k_refine_begin(int B, const int* __restrict__ st, const double* __restrict__ out,
+                               int* __restrict__ active, double* __restrict__ stepw,
+                               double* __restrict__ keep) {
+    for (int b = threadIdx.x; b < B; b += blockDim.x) {
+        active[b] = st[b] == 0;
+        stepw[b] = st[b] == 0 ? 1.0 : 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) keep[4 * b + q] = out[4 * b + q];
+    }
+}
+
+// After a step: accept it (new sums kept) when the Galerkin residual dropped, else
+// restore y from ysave and stop refining that field.  One block per field.
+__global__ void k_refine_select(int k, const double* __restrict__ g2new, double* __restrict__ g2cur,
+                                int* __restrict__ active, double* __restrict__ stepw,
+                                const double* __restrict__ out, double* __restrict__ keep,
+                                const double* __restrict__ ysave, double* __restrict__ y) {
     const int b = blockIdx.x;
-    if (!revert[b]) return;
-    for (int j = threadIdx.x; j < k; j += blockDim.x) y[(size_t)b * k + j] = ysave[(size_t)b * k + j];
+    if (!active[b]) return;
+    const bool ok = g2new[b] < g2cur[b];
+    __syncthreads();
+    if (ok) {
+        if (threadIdx.x < 4) keep[4 * b + threadIdx.x] = out[4 * b + threadIdx.x];
+        if (threadIdx.x == 0) g2cur[b] = g2new[b];
+    } else {
+        for (int j = threadIdx.x; j < k; j += blockDim.x) y[(size_t)b * k + j] = ysave[(size_t)b * k + j];
+        if (threadIdx.x == 0) {
+            active[b] = 0;
+            stepw[b] = 0.0;
+        }
+    }
 }
 
 // ----------------------------------------------------------------------------------
@@ -773,7 +827,7 @@ static int phit_chunks(const Grid& g) {
 }
 
 struct ContractPlan {
-    int KP, LS, kt, npairs, groups, ec, epw, nchunks;
+    int KP, LS, kt, npairs, nt, groups, ec, epw, nchunks;
     size_t lds_bytes;
 };
 
@@ -785,7 +839,11 @@ static ContractPlan plan_contract(const Grid& g, int k, int B, bool f64, int cu)
     p.LS = p.KP + ((p.KP / 16) % 2 == 0 ? 16 : 0);
     p.kt = p.KP / 16;
     p.npairs = p.kt * (p.kt + 1) / 2;
-    p.groups = (p.npairs + PAIRS_PER_GROUP - 1) / PAIRS_PER_GROUP;
+    // tile pairs per wave: enough for all pairs in one group when possible (the basis
+    // rows are staged once per group)
+    p.nt = 1;
+    while (p.nt < MAX_NT && p.nt * WAVES < p.npairs) p.nt *= 2;
+    p.groups = (p.npairs + p.nt * WAVES - 1) / (p.nt * WAVES);
     const int nr = g.dim == 2 ? kRows2 : kRows3;
     const size_t esz = f64 ? 8 : 4;
     const size_t budget = 64 * 1024;
@@ -809,11 +867,11 @@ static ContractPlan plan_contract(const Grid& g, int k, int B, bool f64, int cu)
     return p;
 }
 
-template <int DIM, typename TP, typename TC>
-static int launch_contract(Ctx* ctx, const Grid& g, const ContractPlan& p, const TP* phi, int k,
-                           int ldphi, const uint8_t* mask, const TC* alpha, const TC* F, int B,
-                           double* partials, hipStream_t s) {
-    auto kern = k_rom_contract<DIM, TP, TC>;
+template <int DIM, typename TP, typename TC, int NT>
+static int launch_contract_nt(Ctx* ctx, const Grid& g, const ContractPlan& p, const TP* phi, int k,
+                              int ldphi, const uint8_t* mask, const TC* alpha, const TC* F, int B,
+                              double* partials, hipStream_t s) {
+    auto kern = k_rom_contract<DIM, TP, TC, NT>;
     TOPO_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)p.lds_bytes));
     TimedLaunch tl(ctx, KID_ROM_CONTRACT, s);
@@ -821,6 +879,18 @@ static int launch_contract(Ctx* ctx, const Grid& g, const ContractPlan& p, const
                        k, ldphi, p.KP, p.LS, mask, alpha, F, p.epw, p.ec, partials);
     TOPO_CHECK_LAUNCH();
     return TOPO_OK;
+}
+
+template <int DIM, typename TP, typename TC>
+static int launch_contract(Ctx* ctx, const Grid& g, const ContractPlan& p, const TP* phi, int k,
+                           int ldphi, const uint8_t* mask, const TC* alpha, const TC* F, int B,
+                           double* partials, hipStream_t s) {
+    switch (p.nt) {
+    case 1: return launch_contract_nt<DIM, TP, TC, 1>(ctx, g, p, phi, k, ldphi, mask, alpha, F, B, partials, s);
+    case 2: return launch_contract_nt<DIM, TP, TC, 2>(ctx, g, p, phi, k, ldphi, mask, alpha, F, B, partials, s);
+    case 4: return launch_contract_nt<DIM, TP, TC, 4>(ctx, g, p, phi, k, ldphi, mask, alpha, F, B, partials, s);
+    default: return launch_contract_nt<DIM, TP, TC, 8>(ctx, g, p, phi, k, ldphi, mask, alpha, F, B, partials, s);
+    }
 }
 
 }  // namespace topo
@@ -948,8 +1018,9 @@ int topo_rom_estimate(topo_ctx* ctx, const topo_mesh* mesh, const void* phi, int
     const int nb = stencil_blocks(g);
     const int nc = phit_chunks(g);
     Arena ar;
-    double *a64, *u, *r, *part, *out, *rhat, *L = nullptr, *pc, *ybest, *g2, *stepw;
-    int *st = nullptr, *revert;
+    double *a64, *u, *r, *part, *out, *keep = nullptr, *rhat, *L = nullptr, *pc, *ybest = nullptr;
+    double *g2cur = nullptr, *g2new = nullptr, *stepw = nullptr;
+    int *st = nullptr, *active = nullptr;
     ar.take(&a64, (size_t)B * g.n_elems);
     ar.take(&u, (size_t)B * N);
     ar.take(&r, (size_t)B * N);
@@ -957,13 +1028,15 @@ int topo_rom_estimate(topo_ctx* ctx, const topo_mesh* mesh, const void* phi, int
     ar.take(&out, (size_t)4 * B);
     ar.take(&rhat, (size_t)B * k);
     ar.take(&pc, (size_t)B * nc * k);
-    ar.take(&ybest, (size_t)B * k);
-    ar.take(&g2, (size_t)B);
-    ar.take(&stepw, (size_t)B);
-    ar.take(&revert, (size_t)B);
     if (max_refine > 0) {
+        ar.take(&keep, (size_t)4 * B);
+        ar.take(&ybest, (size_t)B * k);
+        ar.take(&g2cur, (size_t)B);
+        ar.take(&g2new, (size_t)B);
+        ar.take(&stepw, (size_t)B);
         ar.take(&L, (size_t)B * k * k);
         ar.take(&st, (size_t)B);
+        ar.take(&active, (size_t)B);
     }
     rc = ar.commit(ctx, s);
     if (rc) return rc;
@@ -984,73 +1057,46 @@ int topo_rom_estimate(topo_ctx* ctx, const topo_mesh* mesh, const void* phi, int
         TOPO_CHECK_LAUNCH();
         return residual_fp64(ctx, g, tb, a64, mask, u, f, r, B, part, out, s);
     };
-    // Galerkin residual r_hat = Phi^T r and its squared norm per field (read back)
-    auto galerkin = [&](std::vector<double>& gh) -> int {
+    // Galerkin residual r_hat = Phi^T r and its squared norm per field
+    auto galerkin = [&](double* g2) -> int {
         int rc2 = phit_v(ctx, g, phi, phi_fp32, k, ldphi, mask, r, N, B, rhat, pc, nc, s);
         if (rc2) return rc2;
         hipLaunchKernelGGL(k_sqnorm_rows, dim3(B), dim3(64), 0, s, k, (const double*)rhat, g2);
         TOPO_CHECK_LAUNCH();
-        gh.resize(B);
-        TOPO_HIP(hipMemcpyAsync(gh.data(), g2, B * sizeof(double), hipMemcpyDeviceToHost, s));
-        TOPO_HIP(hipStreamSynchronize(s));
         return TOPO_OK;
     };
     rc = pass();
     if (rc) return rc;
     if (max_refine > 0) {
         // Reduced iterative refinement: y += K_hat^{-1} Phi^T (f - K Phi y) with the
-        // float64 residual.  A field keeps a correction only while its Galerkin
-        // residual ||Phi^T r|| decreases; otherwise its previous y is restored.
+        // float64 residual, every decision taken on the device (no host round trip).
         hipLaunchKernelGGL(k_chol, dim3(B), dim3(256), 0, s, k, Khat, L, st);
         TOPO_CHECK_LAUNCH();
-        std::vector<double> gcur, gnew;
-        rc = galerkin(gcur);
+        rc = galerkin(g2cur);
         if (rc) return rc;
-        std::vector<int> active(B, 1), rev(B, 0);
-        std::vector<double> hstep(B);
+        hipLaunchKernelGGL(k_refine_begin, dim3(1), dim3(64), 0, s, B, (const int*)st,
+                           (const double*)out, active, stepw, keep);
+        TOPO_CHECK_LAUNCH();
         for (int it = 0; it < max_refine; ++it) {
-            int nact = 0;
-            for (int b = 0; b < B; ++b) {
-                hstep[b] = active[b] ? 1.0 : 0.0;
-                nact += active[b];
-            }
-            if (!nact) break;
             TOPO_HIP(hipMemcpyAsync(ybest, yhat, (size_t)B * k * sizeof(double), hipMemcpyDeviceToDevice, s));
-            TOPO_HIP(hipMemcpyAsync(stepw, hstep.data(), B * sizeof(double), hipMemcpyHostToDevice, s));
             hipLaunchKernelGGL(k_chol_solve, dim3(B), dim3(256), 0, s, k, L, rhat,
                                (long long)k, yhat, 1, (const double*)stepw, (const double*)nullptr,
                                (double*)nullptr);
             TOPO_CHECK_LAUNCH();
             rc = pass();
             if (rc) return rc;
-            rc = galerkin(gnew);
+            rc = galerkin(g2new);
             if (rc) return rc;
-            bool any = false;
-            for (int b = 0; b < B; ++b) {
-                rev[b] = 0;
-                if (active[b] && !(gnew[b] < gcur[b])) {
-                    rev[b] = 1;
-                    active[b] = 0;
-                    any = true;
-                }
-            }
-            if (any) {
-                TOPO_HIP(hipMemcpyAsync(revert, rev.data(), B * sizeof(int), hipMemcpyHostToDevice, s));
-                hipLaunchKernelGGL(k_restore_rows, dim3(B), dim3(64), 0, s, k, (const int*)revert,
-                                   (const double*)ybest, yhat);
-                TOPO_CHECK_LAUNCH();
-                rc = pass();
-                if (rc) return rc;
-                rc = galerkin(gnew);
-                if (rc) return rc;
-            }
-            gcur = gnew;
+            hipLaunchKernelGGL(k_refine_select, dim3(B), dim3(64), 0, s, k, (const double*)g2new,
+                               g2cur, active, stepw, (const double*)out, keep,
+                               (const double*)ybest, yhat);
+            TOPO_CHECK_LAUNCH();
         }
     }
-    // ||r|| and J_k = f^T (Phi y_hat) of the final pass (reduced by the residual kernel)
-    hipLaunchKernelGGL(k_estimate_out, dim3(1), dim3(64), 0, s, B, (const double*)out, resnorm, Jk);
+    // ||r|| and J_k = f^T (Phi y_hat) of the returned y (reduced by the residual kernel)
+    hipLaunchKernelGGL(k_estimate_out, dim3(1), dim3(64), 0, s, B,
+                       (const double*)(max_refine > 0 ? keep : out), resnorm, Jk);
     TOPO_CHECK_LAUNCH();
-    TOPO_HIP(hipStreamSynchronize(s));
     return TOPO_OK;
 }
 
@@ -1087,8 +1133,8 @@ size_t ws_rom_estimate(const Grid& g, int k, int B, int max_refine) {
     const int nb = stencil_blocks(g);
     const int nc = phit_chunks(g);
     Arena ar;
-    double *a64, *u, *r, *part, *out, *rhat, *L, *pc, *ybest, *g2, *stepw;
-    int *st, *revert;
+    double *a64, *u, *r, *part, *out, *keep, *rhat, *L, *pc, *ybest, *g2cur, *g2new, *stepw;
+    int *st, *active;
     ar.take(&a64, (size_t)B * g.n_elems);
     ar.take(&u, (size_t)B * N);
     ar.take(&r, (size_t)B * N);
@@ -1096,13 +1142,15 @@ size_t ws_rom_estimate(const Grid& g, int k, int B, int max_refine) {
     ar.take(&out, (size_t)4 * B);
     ar.take(&rhat, (size_t)B * k);
     ar.take(&pc, (size_t)B * nc * k);
-    ar.take(&ybest, (size_t)B * k);
-    ar.take(&g2, (size_t)B);
-    ar.take(&stepw, (size_t)B);
-    ar.take(&revert, (size_t)B);
     if (max_refine > 0) {
+        ar.take(&keep, (size_t)4 * B);
+        ar.take(&ybest, (size_t)B * k);
+        ar.take(&g2cur, (size_t)B);
+        ar.take(&g2new, (size_t)B);
+        ar.take(&stepw, (size_t)B);
         ar.take(&L, (size_t)B * k * k);
         ar.take(&st, (size_t)B);
+        ar.take(&active, (size_t)B);
     }
     return ar.total();
 }

@@ -127,3 +127,34 @@ def test_rank_deficient_basis_not_spd():
     st = torch.zeros(1, dtype=torch.int32, device="cuda")
     ctx().rom_solve(Kh, fh, status=st)
     assert int(st[0]) == binding.TOPO_ENOTSPD
+
+
+def test_refinement_accepts_and_reverts_per_field():
+    """Device-side refinement decisions in one batch: field 0 gets a good K_hat (step
+    kept, FP64-accurate J), field 1 a K_hat scaled by 0.1 (the step overshoots, the
+    Galerkin residual grows, y is restored), field 2 a K_hat that does not factor (no
+    step).  Fields 1 and 2 must report exactly what max_refine=0 reports for their y."""
+    torch = torch_cuda()
+    from paper_2004_05756_amd import MIXED
+    p, k = W.cantilever2d(37, 11), 12
+    phi = _basis(p, k, np.float32)
+    rhos = _rhos(p, 3, 21)
+    m, f, phid = dev(p.mask, torch.uint8), dev(p.f, torch.float64), dev(phi)
+    r = dev(rhos, torch.float64)
+    Kh, fh = ctx().rom_build(p.mesh, phid, k, m, f, r, prec=MIXED)
+    st = torch.zeros(3, dtype=torch.int32, device="cuda")
+    y0, _ = ctx().rom_solve(Kh, fh, status=st)
+    Kbad = Kh.clone()
+    Kbad[1] *= 0.1
+    Kbad[2] = -torch.eye(k, dtype=torch.float64, device="cuda")
+    y = y0.clone()
+    _, J, rn = ctx().rom_estimate(p.mesh, phid, k, m, f, r, Kbad, y, max_refine=2)
+    y_ref = y0.clone()
+    _, J0, rn0 = ctx().rom_estimate(p.mesh, phid, k, m, f, r, None, y_ref, max_refine=0)
+    y, J, rn, J0, rn0, y0 = host(y), host(J), host(rn), host(J0), host(rn0), host(y0)
+    ev = O.rom_eval(p.mesh, rhos[0], phi, p.mask, p.f)
+    assert abs(J[0] / ev["Jk"] - 1) <= 1e-8
+    assert not np.array_equal(y[0], y0[0])
+    for b in (1, 2):
+        assert np.array_equal(y[b], y0[b])
+        assert J[b] == J0[b] and rn[b] == rn0[b]
