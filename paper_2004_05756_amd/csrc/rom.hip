@@ -81,7 +81,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_rom_contract(
     extern __shared__ __align__(16) unsigned char smem[];
     TC* sD = (TC*)smem;  // [round_up(ec * NR, 4)][LS]
     __shared__ TC sF[kFacSize];
-    __shared__ int sNode[64][NEN];       // node of each local node of the sub-chunk's elements
+    __shared__ int sNode0[64];           // node of local node 0 of the sub-chunk's elements
     __shared__ uint32_t sFree[64];       // bit DIM*a+c set: DOF (a, c) is free
     __shared__ TC sSa[64];               // sqrt(alpha_e)
 
@@ -124,6 +124,17 @@ __global__ __launch_bounds__(WAVES * 64) void k_rom_contract(
         for (int v = 0; v < 4; ++v) acc64[t][v] = 0.0;
     }
 
+    // basis offsets (in elements) of local node a and component c from local node 0
+    size_t aoff[NEN];
+#pragma unroll
+    for (int a = 0; a < NEN; ++a)
+        aoff[a] = ((size_t)(a & 1) + (size_t)((a >> 1) & 1) * g.nx1 +
+                   (size_t)(a >> 2) * g.nx1 * g.ny1) * (size_t)ldphi;
+    const size_t coff = (size_t)g.n_nodes * ldphi;
+    constexpr uint32_t kAllFree = (1u << (DIM * NEN)) - 1u;
+    const int q_el = blockDim.x / KP, q_col = blockDim.x % KP;
+    const int el_t0 = tid / KP, col_t0 = tid % KP;
+
     for (int e0 = e_begin; e0 < e_end; e0 += ec) {
         const int ne_here = min(ec, e_end - e0);
         __syncthreads();  // previous sub-chunk fully consumed (and sF staged)
@@ -143,7 +154,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_rom_contract(
                 for (int c = 0; c < DIM; ++c)
                     if (!mask[(size_t)c * g.n_nodes + n]) bits |= 1u << (DIM * a + c);
             }
-            sNode[el][a] = n;
+            if (a == 0) sNode0[el] = n;
             // combine the bits of the element's nodes (NEN consecutive lanes)
 #pragma unroll
             for (int off = 1; off < NEN; off <<= 1) bits |= __shfl_xor(bits, off, 64);
@@ -155,30 +166,34 @@ __global__ __launch_bounds__(WAVES * 64) void k_rom_contract(
         __syncthreads();
         // U items (element, column) per thread per batch: all their basis loads are in
         // flight before the first is used.  Indices past the sub-chunk or past k are
-        // clamped to a valid row / column and their D rows are zero.
+        // clamped to a valid row / column and their D rows are zero.  The item cursor
+        // (el, col) advances by blockDim.x = q_el * KP + q_col items per step.
         constexpr int U = DIM == 2 ? 4 : 1;
         const int nitems = ec * KP;
+        int el_c = el_t0, col_c = col_t0;
         for (int idx0 = tid; idx0 < nitems; idx0 += U * blockDim.x) {
             TP v[U][NEN][DIM];
+            int elu[U], colu[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const int idx = idx0 + u * blockDim.x;
-                const int el = min(idx / KP, ec - 1);
-                const int col = min(idx % KP, k - 1);
-#pragma unroll
-                for (int a = 0; a < NEN; ++a) {
-                    const size_t n = (size_t)sNode[el][a];
-#pragma unroll
-                    for (int c = 0; c < DIM; ++c)
-                        v[u][a][c] = phi[((size_t)c * g.n_nodes + n) * (size_t)ldphi + col];
+                elu[u] = el_c;
+                colu[u] = col_c;
+                el_c += q_el;
+                col_c += q_col;
+                if (col_c >= KP) {
+                    col_c -= KP;
+                    ++el_c;
                 }
+                const TP* pe = phi + (size_t)sNode0[min(elu[u], ec - 1)] * ldphi + min(colu[u], k - 1);
+#pragma unroll
+                for (int a = 0; a < NEN; ++a)
+#pragma unroll
+                    for (int c = 0; c < DIM; ++c) v[u][a][c] = pe[aoff[a] + c * coff];
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const int idx = idx0 + u * blockDim.x;
-                const int el = idx / KP;
-                const int col = idx % KP;
-                if (idx < nitems) {
+                const int el = elu[u], col = colu[u];
+                if (idx0 + u * blockDim.x < nitems) {
                     TC D[NR];
                     if (el < ne_here && col < k) {
                         const uint32_t fr = sFree[el];
@@ -186,8 +201,14 @@ __global__ __launch_bounds__(WAVES * 64) void k_rom_contract(
 #pragma unroll
                         for (int a = 0; a < NEN; ++a)
 #pragma unroll
-                            for (int c = 0; c < DIM; ++c)
-                                A[a][c] = ((fr >> (DIM * a + c)) & 1u) ? (TC)v[u][a][c] : TC(0);
+                            for (int c = 0; c < DIM; ++c) A[a][c] = (TC)v[u][a][c];
+                        if (fr != kAllFree) {  // element touching the Dirichlet boundary
+#pragma unroll
+                            for (int a = 0; a < NEN; ++a)
+#pragma unroll
+                                for (int c = 0; c < DIM; ++c)
+                                    if (!((fr >> (DIM * a + c)) & 1u)) A[a][c] = TC(0);
+                        }
                         if constexpr (DIM == 2) elem_rows2(A, sF, sSa[el], D);
                         else elem_rows3(A, sF, sSa[el], D);
                     } else {
