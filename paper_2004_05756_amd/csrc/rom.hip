@@ -58,7 +58,7 @@ template <> struct Mfma<double> {
 // chunks in a fixed order (deterministic).
 // ----------------------------------------------------------------------------------
 constexpr int WAVES = 4;     // waves per block
-constexpr int MAX_NT = 8;    // tile pairs per wave (template NT: 1, 2, 4 or 8)
+constexpr int MAX_NT = 8;    // most tile pairs per wave (template NT: 1 .. 8)
 
 __device__ __forceinline__ void pair_of(int p, int kt, int& I, int& J) {
     // enumerate (I, J), I <= J, row by row
@@ -860,11 +860,10 @@ static ContractPlan plan_contract(const Grid& g, int k, int B, bool f64, int cu)
     p.LS = p.KP + ((p.KP / 16) % 2 == 0 ? 16 : 0);
     p.kt = p.KP / 16;
     p.npairs = p.kt * (p.kt + 1) / 2;
-    // tile pairs per wave: enough for all pairs in one group when possible (the basis
-    // rows are staged once per group)
-    p.nt = 1;
-    while (p.nt < MAX_NT && p.nt * WAVES < p.npairs) p.nt *= 2;
-    p.groups = (p.npairs + p.nt * WAVES - 1) / (p.nt * WAVES);
+    // tile pairs per wave: as few groups as possible (the basis rows are staged once per
+    // group), then the pairs spread evenly over the group's waves
+    p.groups = (p.npairs + MAX_NT * WAVES - 1) / (MAX_NT * WAVES);
+    p.nt = (p.npairs + p.groups * WAVES - 1) / (p.groups * WAVES);
     const int nr = g.dim == 2 ? kRows2 : kRows3;
     const size_t esz = f64 ? 8 : 4;
     const size_t budget = 64 * 1024;
@@ -907,9 +906,11 @@ static int launch_contract(Ctx* ctx, const Grid& g, const ContractPlan& p, const
                            int ldphi, const uint8_t* mask, const TC* alpha, const TC* F, int B,
                            double* partials, hipStream_t s) {
     switch (p.nt) {
-    case 1: return launch_contract_nt<DIM, TP, TC, 1>(ctx, g, p, phi, k, ldphi, mask, alpha, F, B, partials, s);
-    case 2: return launch_contract_nt<DIM, TP, TC, 2>(ctx, g, p, phi, k, ldphi, mask, alpha, F, B, partials, s);
-    case 4: return launch_contract_nt<DIM, TP, TC, 4>(ctx, g, p, phi, k, ldphi, mask, alpha, F, B, partials, s);
+#define TOPO_NT_CASE(n) \
+    case n: return launch_contract_nt<DIM, TP, TC, n>(ctx, g, p, phi, k, ldphi, mask, alpha, F, B, partials, s);
+    TOPO_NT_CASE(1) TOPO_NT_CASE(2) TOPO_NT_CASE(3) TOPO_NT_CASE(4)
+    TOPO_NT_CASE(5) TOPO_NT_CASE(6) TOPO_NT_CASE(7)
+#undef TOPO_NT_CASE
     default: return launch_contract_nt<DIM, TP, TC, 8>(ctx, g, p, phi, k, ldphi, mask, alpha, F, B, partials, s);
     }
 }
@@ -1004,9 +1005,11 @@ int topo_rom_solve(topo_ctx* ctx, int32_t k, int32_t B, const double* Khat, cons
         hipLaunchKernelGGL(k_chol, dim3(B), dim3(256), 0, s, k, Khat, L, stp);
     }
     TOPO_CHECK_LAUNCH();
-    TimedLaunch tl(ctx, KID_CHOL_SOLVE, s);
-    hipLaunchKernelGGL(k_chol_solve, dim3(B), dim3(256), 0, s, k, L, fhat, 0LL, yhat,
-                       0, (const double*)nullptr, fhat, Jk);
+    {
+        TimedLaunch tl(ctx, KID_CHOL_SOLVE, s);
+        hipLaunchKernelGGL(k_chol_solve, dim3(B), dim3(256), 0, s, k, L, fhat, 0LL, yhat,
+                           0, (const double*)nullptr, fhat, Jk);
+    }
     TOPO_CHECK_LAUNCH();
     if (!status) {
         std::vector<int> h(B);
@@ -1065,16 +1068,18 @@ int topo_rom_estimate(topo_ctx* ctx, const topo_mesh* mesh, const void* phi, int
     if (rc) return rc;
     // u = Phi y_hat, r = f - K u, ||r||^2 and f^T u per field
     auto pass = [&]() -> int {
-        TimedLaunch tl(ctx, KID_PHI_Y, s);
         const size_t esz = phi_fp32 ? 4 : 8;
         const int rb = tile_rows(ldphi, esz);
         const size_t lds = (size_t)((k + 1) & ~1) * sizeof(double) + tile_bytes(rb, ldphi, esz);
-        if (phi_fp32)
-            hipLaunchKernelGGL((k_phi_y<float>), dim3(grid_blocks(N, rb), B), dim3(256), lds, s,
-                               N, (const float*)phi, k, ldphi, mask, yhat, rb, u);
-        else
-            hipLaunchKernelGGL((k_phi_y<double>), dim3(grid_blocks(N, rb), B), dim3(256), lds, s,
-                               N, (const double*)phi, k, ldphi, mask, yhat, rb, u);
+        {
+            TimedLaunch tl(ctx, KID_PHI_Y, s);
+            if (phi_fp32)
+                hipLaunchKernelGGL((k_phi_y<float>), dim3(grid_blocks(N, rb), B), dim3(256), lds, s,
+                                   N, (const float*)phi, k, ldphi, mask, yhat, rb, u);
+            else
+                hipLaunchKernelGGL((k_phi_y<double>), dim3(grid_blocks(N, rb), B), dim3(256), lds, s,
+                                   N, (const double*)phi, k, ldphi, mask, yhat, rb, u);
+        }
         TOPO_CHECK_LAUNCH();
         return residual_fp64(ctx, g, tb, a64, mask, u, f, r, B, part, out, s);
     };

@@ -158,3 +158,23 @@ def test_refinement_accepts_and_reverts_per_field():
     for b in (1, 2):
         assert np.array_equal(y[b], y0[b])
         assert J[b] == J0[b] and rn[b] == rn0[b]
+
+
+@pytest.mark.parametrize("k", [64, 80, 96, 112, 128, 144, 200])
+@pytest.mark.parametrize("mode", ["fp64", "mixed"])
+def test_rom_build_tile_pair_layouts(k, mode):
+    """k = 64..200 puts 3 to 8 tile pairs on each wave, in one to three pair groups:
+    every layout of the contraction against the oracle's K_hat (3D, batch of 2)."""
+    torch = torch_cuda()
+    from paper_2004_05756_amd import FP64, MIXED
+    p = W.cantilever3d(7, 5, 3)
+    phi = _basis(p, k, np.float32, seed=3)
+    rhos = _rhos(p, 2, 17)
+    Kh, _ = ctx().rom_build(p.mesh, dev(phi), k, dev(p.mask, torch.uint8), dev(p.f, torch.float64),
+                            dev(rhos, torch.float64), prec=FP64 if mode == "fp64" else MIXED)
+    Kh = host(Kh)
+    tol = 1e-13 if mode == "fp64" else 2e-6
+    for b in range(2):
+        ref = O.rom_operator(p.mesh, rhos[b], phi, p.mask)
+        assert np.array_equal(Kh[b], Kh[b].T)
+        assert np.abs(Kh[b] - ref).max() <= tol * np.abs(ref).max()
