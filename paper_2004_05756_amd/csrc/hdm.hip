@@ -172,14 +172,17 @@ __global__ __launch_bounds__(kBlock) void k_apply3(Grid g, const T* __restrict__
 // ps doubles apart; the apply writes one pq partial per stencil block (napp), the
 // initialisation and the update one rz / rr partial per node-linear block (nupd).
 // Iteration it writes rz/rr into parity it & 1 and reads the current ones from parity
-// (it + 1) & 1.  The PCG initialisation writes parity 1.
-// Block 0 alone writes the state record (done flag, iteration count, norms).
+// (it + 1) & 1.  The PCG initialisation writes parity 1.  The apply of iteration it
+// records its summed rz_it in the state by parity (rz[it & 1]): the update of the same
+// iteration and the next apply read it there instead of summing its partials again.
+// Block 0 alone writes the state record (done flag, iteration count, norms, rz).
 // ----------------------------------------------------------------------------------
 struct PcgState {
     double bb;    // reference ||r||^2 of the stopping test (set by the first apply, or by
                   // the host when a segment continues after a residual replacement)
     double rr;    // ||r||^2 at the last stopping test
     double tol2;  // the segment stops when rr <= tol2 * bb
+    double rz[2]; // summed r.z of the last two applies, by iteration parity
     int done;     // 0 running, 1 converged, 2 iteration limit, 3 breakdown
     int iters;    // completed iterations (over all segments)
     int maxit;
@@ -189,8 +192,13 @@ struct PcgState {
 __device__ __forceinline__ double* part_rz(double* p, int ps, int parity) { return p + (1 + parity) * ps; }
 __device__ __forceinline__ double* part_rr(double* p, int ps, int parity) { return p + (3 + parity) * ps; }
 
+// Block size of the node-linear PCG kernels and of the 2D apply: fewer, larger blocks
+// leave fewer partial sums for the next kernel's prologue (measured at 241k DOF: 8 %
+// shorter kernels than with 256 threads; 1024 threads were slower again).
+constexpr int kPcgBlock = 512;
+
 template <int DIM, typename T>
-__global__ __launch_bounds__(kBlock) void k_pcg_init(Grid g, const T* __restrict__ b,
+__global__ __launch_bounds__(kPcgBlock) void k_pcg_init(Grid g, const T* __restrict__ b,
                                                      const T* __restrict__ winv, T ik0, T ik1,
                                                      T ik2, double* __restrict__ x, T* __restrict__ r,
                                                      T* __restrict__ z, T* __restrict__ p,
@@ -235,10 +243,10 @@ template <typename T>
 __device__ __forceinline__ int pcg_apply_scalars(double* part, PcgState* st, int ps, int nupd,
                                                  int parity, int first, T& tb, double* lds) {
     const int cur = (parity + 1) & 1;
-    // rr and rz of the current residual, rz of the previous one (one pass)
-    const double* arrs[3] = {part_rr(part, ps, cur), part_rz(part, ps, cur), part_rz(part, ps, parity)};
-    double red[3];
-    block_sum_arrays<3>(arrs, nupd, red, lds);
+    // rr and rz of the current residual (one pass); rz of the previous apply from the state
+    const double* arrs[2] = {part_rr(part, ps, cur), part_rz(part, ps, cur)};
+    double red[2];
+    block_sum_arrays<2>(arrs, nupd, red, lds);
     const double rr = red[0];
     const double bb = first ? rr : st->bb;
     int code = 0;
@@ -249,15 +257,16 @@ __device__ __forceinline__ int pcg_apply_scalars(double* part, PcgState* st, int
         if (first) st->bb = rr;
         st->rr = rr;
         if (code) st->done = code;
+        else st->rz[parity] = red[1];
     }
-    tb = first ? T(0) : (T)(red[1] / red[2]);
+    tb = first ? T(0) : (T)(red[1] / st->rz[cur]);
     return code;
 }
 
 // 2D: grid-stride over nodes.  The loads of a thread's first node are issued before it
 // waits on the scalar reduction.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_pcg_apply2(Grid g, const T* __restrict__ alpha,
+__global__ __launch_bounds__(kPcgBlock) void k_pcg_apply2(Grid g, const T* __restrict__ alpha,
                                                        const T* __restrict__ K,
                                                        const uint8_t* __restrict__ mask,
                                                        const T* __restrict__ z,
@@ -352,13 +361,13 @@ __global__ __launch_bounds__(kBlock) void k_pcg_apply3(Grid g, const T* __restri
 }
 
 template <int DIM, typename T>
-__global__ __launch_bounds__(kBlock) void k_pcg_update(Grid g, const T* __restrict__ winv,
+__global__ __launch_bounds__(kPcgBlock) void k_pcg_update(Grid g, const T* __restrict__ winv,
                                                        T ik0, T ik1, T ik2, double* __restrict__ x,
                                                        T* __restrict__ r, T* __restrict__ z,
                                                        const T* __restrict__ p,
                                                        const T* __restrict__ q,
                                                        double* __restrict__ part, PcgState* st,
-                                                       int ps, int npq, int nrz, int parity) {
+                                                       int ps, int npq, int parity) {
     if (st->done) return;
     __shared__ double lds[32];
     const int stride = gridDim.x * blockDim.x;
@@ -378,16 +387,12 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(Grid g, const T* __restri
     };
     // issue the first node's loads before waiting on the scalar reduction
     if (n < g.n_nodes) load(n);
-    const double* arrs[2] = {part, part_rz(part, ps, (parity + 1) & 1)};
-    const int cnt[2] = {npq, nrz};
-    double red[2];
-    block_sum_arrays_n<2>(arrs, cnt, red, lds);
-    const double pq = red[0];
+    const double pq = block_sum_array(part, npq, lds);
     if (!(pq > 0.0) || !isfinite(pq)) {
         if (blockIdx.x == 0 && threadIdx.x == 0) st->done = 3;
         return;
     }
-    const T a = (T)(red[1] / pq);
+    const T a = (T)(st->rz[parity] / pq);
     const T ik[3] = {ik0, ik1, ik2};
     double v[2] = {0.0, 0.0};
     while (n < g.n_nodes) {
@@ -451,7 +456,7 @@ __global__ __launch_bounds__(1024) void k_partials_sum(double* __restrict__ a,
 // progress of the earlier segments is not lost.  Writes the rz / rr partials of the
 // replaced residual into parity `cur`, where the next apply reads them.
 template <int DIM, typename T>
-__global__ __launch_bounds__(kBlock) void k_pcg_replace(Grid g, const double* __restrict__ r64,
+__global__ __launch_bounds__(kPcgBlock) void k_pcg_replace(Grid g, const double* __restrict__ r64,
                                                         double scale, const T* __restrict__ winv,
                                                         T ik0, T ik1, T ik2, double* __restrict__ x,
                                                         T* __restrict__ r, T* __restrict__ z,
@@ -695,8 +700,8 @@ struct PcgGeom {
 
 static PcgGeom pcg_geom(const Grid& g) {
     PcgGeom pg;
-    pg.nupd = grid_blocks(g.n_nodes);
-    pg.napp = stencil_blocks(g);
+    pg.nupd = grid_blocks(g.n_nodes, kPcgBlock);
+    pg.napp = g.dim == 2 ? grid_blocks(g.n_nodes, kPcgBlock) : stencil_blocks(g);
     pg.ps = std::max(pg.nupd, pg.napp);
     pg.npq = pg.napp > kPcgMaxBlocks ? 1 : pg.napp;
     pg.nrz = pg.nupd > kPcgMaxBlocks ? 1 : pg.nupd;
@@ -760,7 +765,7 @@ static void pcg_iteration(Ctx* ctx, const Grid& g, const PcgRun<DIM, T>& w, cons
         L.ev0 = tl.a;
         L.ev1 = tl.b;
         const void* fn = DIM == 2 ? (const void*)k_pcg_apply2<T> : (const void*)k_pcg_apply3<T>;
-        L(fn, dim3(pg.napp), dim3(kBlock), g, w.alpha, w.K, w.mask, zc, pold, pnew, w.q, w.part, w.st,
+        L(fn, dim3(pg.napp), dim3(DIM == 2 ? kPcgBlock : kBlock), g, w.alpha, w.K, w.mask, zc, pold, pnew, w.q, w.part, w.st,
           (int)pg.ps, (int)pg.nrz, parity, first);
     }
     if (pg.npq == 1 && pg.napp > 1)
@@ -770,9 +775,9 @@ static void pcg_iteration(Ctx* ctx, const Grid& g, const PcgRun<DIM, T>& w, cons
         TimedLaunch tl(ctx, KID_PCG_UPDATE, L.s, L.graph ? kTimeOff : timing, true);
         L.ev0 = tl.a;
         L.ev1 = tl.b;
-        L((const void*)k_pcg_update<DIM, T>, dim3(pg.nupd), dim3(kBlock), g, w.winv, w.ik[0], w.ik[1],
+        L((const void*)k_pcg_update<DIM, T>, dim3(pg.nupd), dim3(kPcgBlock), g, w.winv, w.ik[0], w.ik[1],
           w.ik[2], w.x, w.r, w.z, (const T*)pnew, (const T*)w.q, w.part, w.st, (int)pg.ps, (int)pg.npq,
-          (int)pg.nrz, parity);
+          parity);
     }
     pcg_sum_rz(pg, w.part, parity, w.st, L);
 }
@@ -841,7 +846,7 @@ static int pcg_run(Ctx* ctx, const Grid& g, PcgRun<DIM, T>& w, bool fresh, doubl
     L.s = s;
     long long issued;
     if (fresh) {
-        hipLaunchKernelGGL((k_pcg_init<DIM, T>), dim3(pg.nupd), dim3(kBlock), 0, s, g, w.b, w.winv,
+        hipLaunchKernelGGL((k_pcg_init<DIM, T>), dim3(pg.nupd), dim3(kPcgBlock), 0, s, g, w.b, w.winv,
                            w.ik[0], w.ik[1], w.ik[2], w.x, w.r, w.z, w.p0, w.part, w.st, pg.ps,
                            maxit, tol * tol);
         TOPO_CHECK_LAUNCH();
@@ -1111,8 +1116,11 @@ static int hdm_solve_impl(Ctx* ctx, const topo_mesh& m, const Grid& g, const Ele
             up->done = 0;
             up->iters = fin.iters;
             up->maxit = maxit - base;
+            // the replaced residual's apply takes beta against the last recursive rz
+            up->rz[0] = fin.rz[0];
+            up->rz[1] = fin.rz[1];
             TOPO_HIP(hipMemcpyAsync(st, up, sizeof(PcgState), hipMemcpyHostToDevice, s));
-            hipLaunchKernelGGL((k_pcg_replace<DIM, T>), dim3(pg.nupd), dim3(kBlock), 0, s, g,
+            hipLaunchKernelGGL((k_pcg_replace<DIM, T>), dim3(pg.nupd), dim3(kPcgBlock), 0, s, g,
                                (const double*)r64, scale, w.winv, w.ik[0], w.ik[1], w.ik[2], x, r, z,
                                part, pg.ps, (fin.iters + 1) & 1);
             TOPO_CHECK_LAUNCH();
