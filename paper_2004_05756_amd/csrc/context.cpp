@@ -99,7 +99,8 @@ void element_stiffness(const topo_mesh& m, std::vector<double>& K) {
     }
 }
 
-bool element_factor(const topo_mesh& m, const std::vector<double>& K, std::vector<double>& F) {
+bool element_factor(const topo_mesh& m, const std::vector<double>& K, std::vector<double>& F,
+                    std::vector<double>* Mt) {
     const int dim = m.dim, nen = 1 << dim, ne = dim * nen;
     auto H = [](int mm, int a) { return (__builtin_popcount(mm & a) & 1) ? -1.0 : 1.0; };
     // Kt[(mm,c),(mp,d)] = nen^-2 sum_ab H[mm][a] K[(a,c),(b,d)] H[mp][b]
@@ -111,6 +112,10 @@ bool element_factor(const topo_mesh& m, const std::vector<double>& K, std::vecto
     };
     F.assign(kFacSize, 0.0);
     for (int c = 0; c < dim; ++c) F[kFacH + c] = m.h[c];
+    if (Mt) {
+        Mt->assign(kFacSize, 0.0);
+        for (int c = 0; c < dim; ++c) (*Mt)[kFacH + c] = m.h[c];
+    }
     // R rows, for the reconstruction check
     std::vector<std::vector<double>> R;
     for (int n = 0; n < nen; ++n) {
@@ -164,7 +169,10 @@ bool element_factor(const topo_mesh& m, const std::vector<double>& K, std::vecto
             }
         const int slot[3][3] = {{0, 1, 2}, {-1, 3, 4}, {-1, -1, 5}};
         for (int i = 0; i < r; ++i)
-            for (int j = i; j < r; ++j) F[6 * n + slot[i][j]] = L[j][i];  // (L^T)[i][j]
+            for (int j = i; j < r; ++j) {
+                F[6 * n + slot[i][j]] = L[j][i];  // (L^T)[i][j]
+                if (Mt) (*Mt)[6 * n + slot[i][j]] = Mb[i][j];
+            }
         // rows of R: (L^T G)[i][c] times H[n ^ e_c][a] on DOF (a, c)
         for (int i = 0; i < r; ++i) {
             std::vector<double> row(ne, 0.0);
@@ -257,14 +265,17 @@ const ElemTables* get_tables(Ctx* ctx, const topo_mesh& m) {
         return nullptr;
     if (hipMemcpy(t.K32, k32.data(), n * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
         return nullptr;
-    std::vector<double> fac;
-    if (!element_factor(m, t.host, fac)) return nullptr;
-    std::vector<float> fac32(fac.begin(), fac.end());
+    std::vector<double> fac, mblk;
+    if (!element_factor(m, t.host, fac, &mblk)) return nullptr;
+    std::vector<float> fac32(fac.begin(), fac.end()), mblk32(mblk.begin(), mblk.end());
     if (hipMalloc(&t.F64, kFacSize * sizeof(double)) != hipSuccess) return nullptr;
     if (hipMalloc(&t.F32, kFacSize * sizeof(float)) != hipSuccess) return nullptr;
-    if (hipMemcpy(t.F64, fac.data(), kFacSize * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
-        return nullptr;
-    if (hipMemcpy(t.F32, fac32.data(), kFacSize * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
+    if (hipMalloc(&t.M64, kFacSize * sizeof(double)) != hipSuccess) return nullptr;
+    if (hipMalloc(&t.M32, kFacSize * sizeof(float)) != hipSuccess) return nullptr;
+    if (hipMemcpy(t.F64, fac.data(), kFacSize * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(t.F32, fac32.data(), kFacSize * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(t.M64, mblk.data(), kFacSize * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(t.M32, mblk32.data(), kFacSize * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
         return nullptr;
     return &(ctx->tables[key] = t);
 }
@@ -394,6 +405,8 @@ int topo_ctx_destroy(topo_ctx* c) {
         (void)hipFree(kv.second.K32);
         (void)hipFree(kv.second.F64);
         (void)hipFree(kv.second.F32);
+        (void)hipFree(kv.second.M64);
+        (void)hipFree(kv.second.M32);
     }
     if (c->ws) (void)hipFree(c->ws);
     if (c->pinned) (void)hipHostFree(c->pinned);

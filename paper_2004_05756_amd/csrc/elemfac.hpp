@@ -81,41 +81,47 @@ __device__ __forceinline__ void elem_rows3(const T (&A)[8][3], const T* __restri
     rows3_from_n(N, F, s, D);
 }
 
-// Y = R^T (-D) = H G^T L (-D) with the fast Walsh-Hadamard transform.  The transformed
-// translation entries are zero, so every Y sums to zero over the nodes (per component)
-// and a rigid motion gives Y = 0 exactly.
+// Y = s K_e A for one element from N = neg_wht3(A), with the reduced blocks M = L L^T
+// (table Mt: upper triangles in the factor's slots, element sizes at kFacH):
+// z = G N, u = -s M z, V = G^T u, Y = H V.  The same product as applying R^T after R,
+// with one symmetric block product in place of the two triangular ones.
 template <typename T>
-__device__ __forceinline__ void apply3_from_d(const T (&D)[kRows3], const T* __restrict__ F,
+__device__ __forceinline__ void apply3_from_n(const T (&N)[8][3], const T* __restrict__ Mt, T s,
                                               T (&Y)[8][3]) {
-    // u = -L D per block (L = Lt^T, lower triangular), scattered to V[m][c] by G^T
+    const T h0 = Mt[kFacH], h1 = Mt[kFacH + 1], h2 = Mt[kFacH + 2];
+    const T ns = -s;
+    auto sym3 = [&](int n, T z0, T z1, T z2, T& u0, T& u1, T& u2) {
+        z0 *= ns;
+        z1 *= ns;
+        z2 *= ns;
+        u0 = Mt[6 * n + 0] * z0 + Mt[6 * n + 1] * z1 + Mt[6 * n + 2] * z2;
+        u1 = Mt[6 * n + 1] * z0 + Mt[6 * n + 3] * z1 + Mt[6 * n + 4] * z2;
+        u2 = Mt[6 * n + 2] * z0 + Mt[6 * n + 4] * z1 + Mt[6 * n + 5] * z2;
+    };
+    auto sym2 = [&](int n, T z0, T z1, T& u0, T& u1) {
+        z0 *= ns;
+        z1 *= ns;
+        u0 = Mt[6 * n + 0] * z0 + Mt[6 * n + 1] * z1;
+        u1 = Mt[6 * n + 1] * z0 + Mt[6 * n + 3] * z1;
+    };
     T V[8][3];
-    const T h0 = F[kFacH], h1 = F[kFacH + 1], h2 = F[kFacH + 2];
-    auto lo3 = [&](int n, const T* d, T& u0, T& u1, T& u2) {
-        u0 = -(F[6 * n + 0] * d[0]);
-        u1 = -(F[6 * n + 1] * d[0] + F[6 * n + 3] * d[1]);
-        u2 = -(F[6 * n + 2] * d[0] + F[6 * n + 4] * d[1] + F[6 * n + 5] * d[2]);
-    };
-    auto lo2 = [&](int n, const T* d, T& u0, T& u1) {
-        u0 = -(F[6 * n + 0] * d[0]);
-        u1 = -(F[6 * n + 1] * d[0] + F[6 * n + 3] * d[1]);
-    };
     T u0, u1, u2;
     V[0][0] = V[0][1] = V[0][2] = T(0);
-    lo3(0, D + 0, u0, u1, u2);
+    sym3(0, N[1][0], N[2][1], N[4][2], u0, u1, u2);                 // normal strains
     V[1][0] = u0; V[2][1] = u1; V[4][2] = u2;
-    lo2(1, D + 3, u0, u1);
+    sym2(1, N[3][1], N[5][2], u0, u1);                              // x translation dropped
     V[3][1] = u0; V[5][2] = u1;
-    lo2(2, D + 5, u0, u1);
+    sym2(2, N[3][0], N[6][2], u0, u1);                              // y translation dropped
     V[3][0] = u0; V[6][2] = u1;
-    lo2(3, D + 7, u0, u1);
+    sym2(3, h0 * N[2][0] + h1 * N[1][1], N[7][2], u0, u1);          // rotation about z dropped
     V[2][0] = h0 * u0; V[1][1] = h1 * u0; V[7][2] = u1;
-    lo2(4, D + 9, u0, u1);
+    sym2(4, N[5][0], N[6][1], u0, u1);                              // z translation dropped
     V[5][0] = u0; V[6][1] = u1;
-    lo2(5, D + 11, u0, u1);
+    sym2(5, h0 * N[4][0] + h2 * N[1][2], N[7][1], u0, u1);          // rotation about y dropped
     V[4][0] = h0 * u0; V[1][2] = h2 * u0; V[7][1] = u1;
-    lo2(6, D + 13, u0, u1);
+    sym2(6, h1 * N[4][1] + h2 * N[2][2], N[7][0], u0, u1);          // rotation about x dropped
     V[4][1] = h1 * u0; V[2][2] = h2 * u0; V[7][0] = u1;
-    lo3(7, D + 15, u0, u1, u2);
+    sym3(7, N[6][0], N[5][1], N[3][2], u0, u1, u2);
     V[6][0] = u0; V[5][1] = u1; V[3][2] = u2;
     // Y[a][c] = sum_m (-1)^{m.a} V[m][c]
 #pragma unroll
@@ -135,15 +141,6 @@ __device__ __forceinline__ void apply3_from_d(const T (&D)[kRows3], const T* __r
 #pragma unroll
         for (int a = 0; a < 8; ++a) Y[a][c] = w[a];
     }
-}
-
-// Y = alpha K_e A for one element (H8).
-template <typename T>
-__device__ __forceinline__ void elem_apply3(const T (&A)[8][3], const T* __restrict__ F, T alpha,
-                                            T (&Y)[8][3]) {
-    T D[kRows3];
-    elem_rows3(A, F, alpha, D);
-    apply3_from_d(D, F, Y);
 }
 
 // D = s * R A for one column of the Q4 element (a = ax + 2 ay).

@@ -136,17 +136,17 @@ __device__ __forceinline__ void march3_prologue(const Grid& g, const MarchBlock&
     }
 }
 
-// 3D: one block per march column (blockIdx.x), one field per blockIdx.y.  F is the
-// element factor table.
+// 3D: one block per march column (blockIdx.x), one field per blockIdx.y.  M is the
+// table of reduced element blocks (apply3_from_n).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_apply3(Grid g, const T* __restrict__ alpha,
-                                                   const T* __restrict__ F,
+                                                   const T* __restrict__ M,
                                                    const uint8_t* __restrict__ mask,
                                                    const T* __restrict__ x, T* __restrict__ y) {
     __shared__ MarchLds<T> L;
     const size_t b = blockIdx.y;
     const MarchBlock m = march3_block(g, xcd_block(blockIdx.x, gridDim.x));
-    for (int i = threadIdx.x; i < kFacSize; i += blockDim.x) L.F[i] = F[i];
+    for (int i = threadIdx.x; i < kFacSize; i += blockDim.x) L.M[i] = M[i];
     const MarchSlots sl = march3_slots(g, m);
     SrcMasked<T> src{x + b * g.n_dofs, mask, g.n_nodes};
     march3_prologue(g, m, sl, src);
@@ -322,11 +322,11 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_apply2(Grid g, const T* __res
 
 // 3D: one block per march column.  The first two node planes of z and p_old are
 // fetched before the scalar reduction; p_new = z + beta p_old is formed per node as
-// the planes are staged, and the element march runs from LDS.  K is the element factor
-// table here.
+// the planes are staged, and the element march runs from LDS.  M is the table of
+// reduced element blocks.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_pcg_apply3(Grid g, const T* __restrict__ alpha,
-                                                       const T* __restrict__ F,
+                                                       const T* __restrict__ M,
                                                        const uint8_t* __restrict__ mask,
                                                        const T* __restrict__ z,
                                                        const T* __restrict__ p_old,
@@ -337,7 +337,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_apply3(Grid g, const T* __restri
     __shared__ MarchLds<T> L;
     __shared__ double lds[48];
     const MarchBlock m = march3_block(g, xcd_block(blockIdx.x, gridDim.x));
-    for (int i = threadIdx.x; i < kFacSize; i += blockDim.x) L.F[i] = F[i];
+    for (int i = threadIdx.x; i < kFacSize; i += blockDim.x) L.M[i] = M[i];
     const MarchSlots sl = march3_slots(g, m);
     SrcDirection<T> src{z, p_old, T(0), g.n_nodes};
     march3_prologue(g, m, sl, src);
@@ -542,9 +542,9 @@ __global__ __launch_bounds__(kBlock) void k_residual2(Grid g, const double* __re
     residual_partials(v, part, b, lds);
 }
 
-// 3D: one block per march column; F is the element factor table.
+// 3D: one block per march column; M is the table of reduced element blocks.
 __global__ __launch_bounds__(kBlock) void k_residual3(Grid g, const double* __restrict__ alpha,
-                                                      const double* __restrict__ F,
+                                                      const double* __restrict__ M,
                                                       const uint8_t* __restrict__ mask,
                                                       const double* __restrict__ u,
                                                       const double* __restrict__ f,
@@ -555,7 +555,7 @@ __global__ __launch_bounds__(kBlock) void k_residual3(Grid g, const double* __re
     const size_t b = blockIdx.y;
     const double* ub = u + b * g.n_dofs;
     const MarchBlock m = march3_block(g, xcd_block(blockIdx.x, gridDim.x));
-    for (int i = threadIdx.x; i < kFacSize; i += blockDim.x) L.F[i] = F[i];
+    for (int i = threadIdx.x; i < kFacSize; i += blockDim.x) L.M[i] = M[i];
     const MarchSlots sl = march3_slots(g, m);
     SrcPlain<double> src{ub, g.n_nodes};
     march3_prologue(g, m, sl, src);
@@ -938,7 +938,7 @@ static double mixed_segment_tol() {
     return v;
 }
 
-// K64: the dense element matrix in 2D, the element factor table in 3D.
+// K64: the dense element matrix in 2D, the reduced element blocks in 3D.
 static int residual_launch(Ctx* ctx, const Grid& g, const double* K64, const double* alpha64,
                            const uint8_t* mask, const double* u, const double* f, double* r, int B,
                            double* part, double* out, hipStream_t s) {
@@ -1034,9 +1034,9 @@ static int hdm_solve_impl(Ctx* ctx, const topo_mesh& m, const Grid& g, const Ele
     }
     PcgRun<DIM, T> w;
     w.alpha = ta;
-    // 2D: the dense element matrix; 3D: the symmetry-blocked factor table
+    // 2D: the dense element matrix; 3D: the reduced blocks of the symmetry-blocked form
     if constexpr (DIM == 2) w.K = sizeof(T) == 4 ? (const T*)tb->K32 : (const T*)tb->K64;
-    else w.K = sizeof(T) == 4 ? (const T*)tb->F32 : (const T*)tb->F64;
+    else w.K = sizeof(T) == 4 ? (const T*)tb->M32 : (const T*)tb->M64;
     w.mask = mask;
     w.winv = tw;
     for (int c = 0; c < 3; ++c) w.ik[c] = c < DIM ? (T)(1.0 / tb->diag[c]) : T(0);
@@ -1058,7 +1058,7 @@ static int hdm_solve_impl(Ctx* ctx, const topo_mesh& m, const Grid& g, const Ele
     rc = pinned_host(ctx, pin_up + sizeof(PcgState), &pin);
     if (rc) return rc;
     auto residual = [&](double out[3]) -> int {
-        int rc2 = residual_launch(ctx, g, g.dim == 2 ? tb->K64 : tb->F64, a64, mask, u, f, r64, 1, rpart, rout, s);
+        int rc2 = residual_launch(ctx, g, g.dim == 2 ? tb->K64 : tb->M64, a64, mask, u, f, r64, 1, rpart, rout, s);
         if (rc2) return rc2;
         double* h = (double*)((char*)pin + pin_res);
         TOPO_HIP(hipMemcpyAsync(h, rout, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -1204,14 +1204,14 @@ int topo_apply(topo_ctx* ctx, const topo_mesh* mesh, const double* rho, const ui
             hipLaunchKernelGGL((k_apply2<double>), grid, dim3(kBlock), 0, s, g, a64, tb->K64, mask,
                                (const double*)x, (double*)y);
         else
-            hipLaunchKernelGGL((k_apply3<double>), grid, dim3(kBlock), 0, s, g, a64, tb->F64, mask,
+            hipLaunchKernelGGL((k_apply3<double>), grid, dim3(kBlock), 0, s, g, a64, tb->M64, mask,
                                (const double*)x, (double*)y);
     } else {
         if (g.dim == 2)
             hipLaunchKernelGGL((k_apply2<float>), grid, dim3(kBlock), 0, s, g, a32, tb->K32, mask,
                                (const float*)x, (float*)y);
         else
-            hipLaunchKernelGGL((k_apply3<float>), grid, dim3(kBlock), 0, s, g, a32, tb->F32, mask,
+            hipLaunchKernelGGL((k_apply3<float>), grid, dim3(kBlock), 0, s, g, a32, tb->M32, mask,
                                (const float*)x, (float*)y);
     }
     TOPO_CHECK_LAUNCH();
@@ -1292,7 +1292,7 @@ namespace topo {
 int residual_fp64(Ctx* ctx, const Grid& g, const ElemTables* tb, const double* alpha64,
                   const uint8_t* mask, const double* u, const double* f, double* r, int B,
                   double* part, double* out, hipStream_t s) {
-    return residual_launch(ctx, g, g.dim == 2 ? tb->K64 : tb->F64, alpha64, mask, u, f, r, B, part, out, s);
+    return residual_launch(ctx, g, g.dim == 2 ? tb->K64 : tb->M64, alpha64, mask, u, f, r, B, part, out, s);
 }
 
 int alpha_tables(Ctx* ctx, const Grid& g, const topo_mesh& m, const double* rho, int B,

@@ -48,6 +48,8 @@ struct ElemTables {
     float* K32;        // device [ne*ne]
     double* F64 = nullptr;  // device [kFacSize] symmetry-blocked factor
     float* F32 = nullptr;   // device [kFacSize]
+    double* M64 = nullptr;  // device [kFacSize] the reduced blocks M = L L^T themselves
+    float* M32 = nullptr;   // device [kFacSize]
     double diag[3];    // K_e diagonal per displacement component (host copy)
     std::vector<double> host;  // host copy of K64
 };
@@ -55,9 +57,12 @@ struct ElemTables {
 // Exact element stiffness of the rectangular Q4 / H8 element (host).
 void element_stiffness(const topo_mesh& m, std::vector<double>& K);
 
-// The symmetry-blocked factor of K (kFacSize values); false if K does not have the
-// block structure of a box element or a block is not positive definite.
-bool element_factor(const topo_mesh& m, const std::vector<double>& K, std::vector<double>& F);
+// The symmetry-blocked factor of K (kFacSize values) and, when Mt is given, the reduced
+// blocks M = L L^T in the same slots (upper triangles; element sizes at kFacH); false if
+// K does not have the block structure of a box element or a block is not positive
+// definite.
+bool element_factor(const topo_mesh& m, const std::vector<double>& K, std::vector<double>& F,
+                    std::vector<double>* Mt = nullptr);
 
 // ----------------------------------------------------------------------------------
 // Sampled kernel timing (instrumentation): one launch in `every` of each hot kernel is

@@ -3,8 +3,9 @@
 // element columns, one element per thread, the extra row and column being the
 // neighbours the owned nodes also touch) over KZ node planes.  For each element layer
 // it stages the next node plane (33 x 9 nodes) in LDS, every thread evaluates its
-// element with the symmetry-blocked factor (about 210 operations instead of the 576
-// multiply-adds of the dense element rows), and each owned node sums the four corner
+// element in the symmetry-blocked form (edge differences, one symmetric product per
+// reflection block, the Walsh-Hadamard transform back: under 200 operations instead of
+// the 576 multiply-adds of the dense element rows), and each owned node sums the four corner
 // contributions of the layer below and the four of the layer above in a fixed order
 // (deterministic, no atomics).
 #pragma once
@@ -35,7 +36,7 @@ template <typename T>
 struct MarchLds {
     T plane[2][3][MPN];   // node planes, double-buffered
     T xch[3][4][kBlock];  // corner sums of the current node plane [c][corner][thread]
-    T F[kFacSize];
+    T M[kFacSize];  // reduced blocks of the element operator (apply3_from_n)
 };
 
 // Plane slots of this thread (q = tid and tid + kBlock): the node index at plane 0
@@ -180,10 +181,9 @@ __device__ __forceinline__ void march3_run(const Grid& g, const MarchBlock& m,
         }
         FaceSums<T> ft;
         face_sums(at, ft);
-        T N[8][3], D[kRows3], Y[8][3];
+        T N[8][3], Y[8][3];
         neg_wht3_faces(ab, at, fb, ft, N);
-        rows3_from_n(N, L.F, al, D);
-        apply3_from_d(D, L.F, Y);
+        apply3_from_n(N, L.M, al, Y);
         // node plane ez: corner sums of the layer below (top) and this layer (bottom)
         if (s >= 1) {
 #pragma unroll
