@@ -483,6 +483,17 @@ __device__ __forceinline__ double chol_pivot(double d, double tiny) {
     return (d > tiny && isfinite(d)) ? d : 1.0;
 }
 
+// 1 / p for a positive finite pivot: the hardware reciprocal refined by two Newton steps
+// (a few dependent operations on the critical path of a column step, within an ulp).
+__device__ __forceinline__ double chol_recip(double p) {
+    double r = __builtin_amdgcn_rcp(p);
+    r = fma(r, fma(-p, r, 1.0), r);
+    return fma(r, fma(-p, r, 1.0), r);
+}
+
+// RM > 0: the register path for 16 (RM - 1) < k <= 16 RM (only the RM row blocks that
+// exist are unrolled); RM = 0: the global-memory path for k > CHOL_REG_MAX_K.
+template <int RM>
 __global__ __launch_bounds__(256) void k_chol(int k, const double* __restrict__ Khat,
                                               double* __restrict__ Lout, int* __restrict__ status) {
     __shared__ double col[2][CHOL_REG_MAX_K];
@@ -503,8 +514,7 @@ __global__ __launch_bounds__(256) void k_chol(int k, const double* __restrict__ 
         __syncthreads();
     }
     const double tiny = 64.0 * k * 2.220446049250313e-16 * dmax[0];
-    if (k <= CHOL_REG_MAX_K) {
-        constexpr int RM = CHOL_REG_MAX_K / 16;
+    if constexpr (RM > 0) {
         double a[RM][RM];
 #pragma unroll
         for (int r = 0; r < RM; ++r)
@@ -534,7 +544,7 @@ __global__ __launch_bounds__(256) void k_chol(int k, const double* __restrict__ 
                     piv[j] = p;
                     if (p != d) bad = 1;
                 }
-                const double inv = 1.0 / p;
+                const double inv = chol_recip(p);
                 double li[RM], lc[RM];
 #pragma unroll
                 for (int r = c0; r < RM; ++r) {
@@ -734,6 +744,18 @@ __global__ __launch_bounds__(256) void k_chol_solve(int k, const double* __restr
         for (int i = threadIdx.x; i < k; i += blockDim.x) s[0] += cvec[i] * xb[i];
         block_reduce<1>(s, lds);
         if (threadIdx.x == 0) J[b] = s[0];
+    }
+}
+
+static void launch_chol(int k, int B, const double* Khat, double* L, int* st, hipStream_t s) {
+    const int rm = k <= CHOL_REG_MAX_K ? (k + 15) / 16 : 0;
+    switch (rm) {
+#define TOPO_CHOL_CASE(n) \
+    case n: hipLaunchKernelGGL(k_chol<n>, dim3(B), dim3(256), 0, s, k, Khat, L, st); break;
+    TOPO_CHOL_CASE(1) TOPO_CHOL_CASE(2) TOPO_CHOL_CASE(3) TOPO_CHOL_CASE(4)
+    TOPO_CHOL_CASE(5) TOPO_CHOL_CASE(6) TOPO_CHOL_CASE(7) TOPO_CHOL_CASE(8)
+#undef TOPO_CHOL_CASE
+    default: hipLaunchKernelGGL(k_chol<0>, dim3(B), dim3(256), 0, s, k, Khat, L, st);
     }
 }
 
@@ -1002,7 +1024,7 @@ int topo_rom_solve(topo_ctx* ctx, int32_t k, int32_t B, const double* Khat, cons
     int* stp = status ? (int*)status : st;
     {
         TimedLaunch tl(ctx, KID_CHOL, s);
-        hipLaunchKernelGGL(k_chol, dim3(B), dim3(256), 0, s, k, Khat, L, stp);
+        launch_chol(k, B, Khat, L, stp, s);
     }
     TOPO_CHECK_LAUNCH();
     {
@@ -1096,7 +1118,7 @@ int topo_rom_estimate(topo_ctx* ctx, const topo_mesh* mesh, const void* phi, int
     if (max_refine > 0) {
         // Reduced iterative refinement: y += K_hat^{-1} Phi^T (f - K Phi y) with the
         // float64 residual, every decision taken on the device (no host round trip).
-        hipLaunchKernelGGL(k_chol, dim3(B), dim3(256), 0, s, k, Khat, L, st);
+        launch_chol(k, B, Khat, L, st, s);
         TOPO_CHECK_LAUNCH();
         rc = galerkin(g2cur);
         if (rc) return rc;

@@ -72,7 +72,8 @@ def test_rom_solve_and_estimate(p, k):
 def test_rom_solve_fp64_matches_cholesky():
     torch = torch_cuda()
     rng = np.random.default_rng(3)
-    for k in (1, 7, 64, 65, 130):
+    # register / packed-LDS / global-memory paths of the factorisation and substitution
+    for k in (1, 7, 16, 17, 40, 64, 65, 96, 100, 127, 128, 129, 130, 257):
         A = rng.standard_normal((k, k))
         K = A @ A.T + k * np.eye(k)
         fh = rng.standard_normal(k)
@@ -178,3 +179,22 @@ def test_rom_build_tile_pair_layouts(k, mode):
         ref = O.rom_operator(p.mesh, rhos[b], phi, p.mask)
         assert np.array_equal(Kh[b], Kh[b].T)
         assert np.abs(Kh[b] - ref).max() <= tol * np.abs(ref).max()
+
+
+def test_rom_build_mid_size_chunk_slices():
+    """A 120x40 mesh: 75 contraction chunks and 38 projection chunks, so the partial sums
+    run with 4 and 2 chunk slices (the small cases use 1, the benchmark meshes 32)."""
+    torch = torch_cuda()
+    from paper_2004_05756_amd import FP64, MIXED
+    p, k = W.cantilever2d(120, 40), 24
+    phi = _basis(p, k, np.float32, seed=9)
+    rhos = _rhos(p, 2, 23)
+    for prec, tol in ((FP64, 1e-13), (MIXED, 2e-6)):
+        Kh, fh = ctx().rom_build(p.mesh, dev(phi), k, dev(p.mask, torch.uint8), dev(p.f, torch.float64),
+                                 dev(rhos, torch.float64), prec=prec)
+        Kh, fh = host(Kh), host(fh)
+        for b in range(2):
+            ref = O.rom_operator(p.mesh, rhos[b], phi, p.mask)
+            assert np.abs(Kh[b] - ref).max() <= tol * np.abs(ref).max()
+        ref_f = O.rom_load(phi, p.mask, p.f)
+        assert np.abs(fh - ref_f).max() <= 1e-14 * np.abs(ref_f).max()
