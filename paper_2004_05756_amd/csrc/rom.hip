@@ -625,33 +625,58 @@ __device__ __forceinline__ void wave_trsv(int k, const double* __restrict__ sl, 
         const int hi = __builtin_amdgcn_readlane((int)(u >> 32), src);
         return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
     };
-    // forward, L w = rhs: after w_j is known, rows i > j drop L[i][j] w_j
+    // forward, L w = rhs: after w_j is known, rows i > j drop L[i][j] w_j.  The factor
+    // entries of step j + 1 are loaded during step j (they do not depend on w).
+    auto fwd_load = [&](int j, double (&lv)[RM]) {
 #pragma unroll
-    for (int R = 0; R < RM; ++R) {
-        const int jn = min(64, k - 64 * R);
-        for (int jj = 0; jj < jn; ++jj) {
-            const int j = 64 * R + jj;
-            const double wj = bcast(v[R], jj) * bcast(rd[R], jj);
-            if (lane == jj) v[R] = wj;
+        for (int r = 0; r < RM; ++r) {
+            const int i = lane + 64 * r;
+            lv[r] = (i > j && i < k) ? sl[tri_idx(i, j)] : 0.0;
+        }
+    };
+    {
+        double nxt[RM];
+        fwd_load(0, nxt);
 #pragma unroll
-            for (int r = R; r < RM; ++r) {
-                const int i = lane + 64 * r;
-                if (i > j && i < k) v[r] -= sl[tri_idx(i, j)] * wj;
+        for (int R = 0; R < RM; ++R) {
+            const int jn = min(64, k - 64 * R);
+            for (int jj = 0; jj < jn; ++jj) {
+                const int j = 64 * R + jj;
+                double cur[RM];
+#pragma unroll
+                for (int r = 0; r < RM; ++r) cur[r] = nxt[r];
+                if (j + 1 < k) fwd_load(j + 1, nxt);
+                const double wj = bcast(v[R], jj) * bcast(rd[R], jj);
+                if (lane == jj) v[R] = wj;
+#pragma unroll
+                for (int r = R; r < RM; ++r) v[r] -= cur[r] * wj;  // zero where i <= j or i >= k
             }
         }
     }
     // backward, L^T y = w: after y_j is known, rows i < j drop L[j][i] y_j
+    auto bwd_load = [&](int j, double (&lv)[RM]) {
 #pragma unroll
-    for (int R = RM - 1; R >= 0; --R) {
-        const int jn = min(64, k - 64 * R);
-        for (int jj = jn - 1; jj >= 0; --jj) {
-            const int j = 64 * R + jj;
-            const double yj = bcast(v[R], jj) * bcast(rd[R], jj);
-            if (lane == jj) v[R] = yj;
+        for (int r = 0; r < RM; ++r) {
+            const int i = lane + 64 * r;
+            lv[r] = i < j ? sl[tri_idx(j, i)] : 0.0;
+        }
+    };
+    {
+        double nxt[RM];
+        bwd_load(k - 1, nxt);
 #pragma unroll
-            for (int r = 0; r <= R; ++r) {
-                const int i = lane + 64 * r;
-                if (i < j) v[r] -= sl[tri_idx(j, i)] * yj;
+        for (int R = RM - 1; R >= 0; --R) {
+            const int jn = min(64, k - 64 * R);
+            for (int jj = jn - 1; jj >= 0; --jj) {
+                const int j = 64 * R + jj;
+                double cur[RM];
+#pragma unroll
+                for (int r = 0; r < RM; ++r) cur[r] = nxt[r];
+                if (j > 0) bwd_load(j - 1, nxt);
+                const double yj = bcast(v[R], jj) * bcast(rd[R], jj);
+                if (lane == jj) v[R] = yj;
+#pragma unroll
+                for (int r = 0; r <= R; ++r) v[r] -= cur[r] * yj;  // zero where i >= j
             }
         }
     }
