@@ -22,6 +22,16 @@ Grid make_grid(const topo_mesh& m) {
     return g;
 }
 
+int march3_target(const Ctx* ctx, const void* kernel) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0) != hipSuccess ||
+        per_cu < 1 || ctx->cu_count < 1) {
+        (void)hipGetLastError();
+        return 1024;
+    }
+    return per_cu * ctx->cu_count;
+}
+
 // Element stiffness of the rectangular bilinear / trilinear element written as sums
 // of tensor products of exact 1D integrals of the linear shape functions
 // f0 = 1 - x/h, f1 = x/h on [0, h]:

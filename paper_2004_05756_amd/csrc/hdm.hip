@@ -939,9 +939,13 @@ static double mixed_segment_tol() {
 }
 
 // K64: the dense element matrix in 2D, the reduced element blocks in 3D.
-static int residual_launch(Ctx* ctx, const Grid& g, const double* K64, const double* alpha64,
+static int residual_launch(Ctx* ctx, const Grid& g0, const double* K64, const double* alpha64,
                            const uint8_t* mask, const double* u, const double* f, double* r, int B,
                            double* part, double* out, hipStream_t s) {
+    // the residual march fits its own resident wave (never more blocks than a grid with
+    // the default target, which sized the caller's partial arrays)
+    Grid g = g0;
+    if (g.dim == 3) g.mtarget = std::min(march3_target(ctx, (const void*)k_residual3), g0.mtarget > 0 ? g0.mtarget : 1024);
     const int nb = stencil_blocks(g);
     {
         TimedLaunch tl(ctx, KID_RESIDUAL, s);
@@ -1003,10 +1007,12 @@ size_t ws_hdm_solve(const Grid& g, bool mixed) {
 }
 
 template <int DIM, typename T>
-static int hdm_solve_impl(Ctx* ctx, const topo_mesh& m, const Grid& g, const ElemTables* tb,
+static int hdm_solve_impl(Ctx* ctx, const topo_mesh& m, const Grid& g0, const ElemTables* tb,
                           const double* rho, const uint8_t* mask, const double* f, double* u,
                           double rtol, int maxit, bool mixed, double* compliance,
                           topo_info* info, hipStream_t s, bool* stagnated) {
+    Grid g = g0;
+    if constexpr (DIM == 3) g.mtarget = march3_target(ctx, (const void*)k_pcg_apply3<T>);
     const long long N = g.n_dofs;
     if (stagnated) *stagnated = false;
     Arena ar;
@@ -1184,7 +1190,9 @@ int topo_apply(topo_ctx* ctx, const topo_mesh* mesh, const double* rho, const ui
     if (B < 1) return set_error(ctx, TOPO_EINVAL, "B must be >= 1");
     if (prec != TOPO_FP64 && prec != TOPO_MIXED) return set_error(ctx, TOPO_EINVAL, "bad precision");
     TOPO_HIP(hipSetDevice(ctx->device));
-    const Grid g = make_grid(*mesh);
+    Grid g = make_grid(*mesh);
+    if (g.dim == 3)
+        g.mtarget = march3_target(ctx, prec == TOPO_FP64 ? (const void*)k_apply3<double> : (const void*)k_apply3<float>);
     const ElemTables* tb = get_tables(ctx, *mesh);
     if (!tb) return set_error(ctx, TOPO_EDEVICE, "element table upload failed");
     hipStream_t s = (hipStream_t)stream;

@@ -27,6 +27,7 @@ struct Grid {
     int n_nodes;
     int n_elems;
     long long n_dofs;
+    int mtarget = 0;    // 3D march: resident blocks of the kernel per field (0: 1024)
 };
 
 Grid make_grid(const topo_mesh& m);
@@ -241,14 +242,17 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
 }
 
 // 3D element-centric march: a block owns 31 x 7 node columns (a 32 x 8 tile of element
-// columns) over KZ node planes, with KZ chosen for about four blocks per CU.
+// columns) over KZ node planes, with KZ chosen so that a field's blocks fit in one
+// resident wave of the kernel (mtarget blocks, from its occupancy): a partial second
+// wave of long marches left most of the chip idle (96x48x48 float64: 49 -> 42 ms).
 constexpr int MEX = 32, MEY = 8;             // element tile (one thread each)
 constexpr int MOX = MEX - 1, MOY = MEY - 1;  // owned node columns
 __host__ __device__ inline int march3_tiles_x(const Grid& g) { return (g.nx1 + MOX - 1) / MOX; }
 __host__ __device__ inline int march3_tiles_y(const Grid& g) { return (g.ny1 + MOY - 1) / MOY; }
 __host__ __device__ inline int march3_kz(const Grid& g) {
     const int xy = march3_tiles_x(g) * march3_tiles_y(g);
-    const int chunks = (1024 + xy - 1) / xy;
+    const int target = g.mtarget > 0 ? g.mtarget : 1024;
+    const int chunks = target > xy ? target / xy : 1;
     const int kz = (g.nz1 + chunks - 1) / chunks;
     return kz < 2 ? 2 : kz;
 }
@@ -256,6 +260,10 @@ __host__ __device__ inline int march3_blocks(const Grid& g) {
     const int kz = march3_kz(g);
     return march3_tiles_x(g) * march3_tiles_y(g) * ((g.nz1 + kz - 1) / kz);
 }
+
+// Resident blocks of a 256-thread kernel on the whole device (its occupancy times the
+// CU count); 1024 when the runtime cannot tell.
+int march3_target(const Ctx* ctx, const void* kernel);
 
 // Blocks of a node-stencil launch (apply, PCG apply, residual): one per march column
 // in 3D, one per kBlock consecutive nodes in 2D.
