@@ -309,8 +309,8 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is "
-                                   "described in DESIGN.md but not built", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "the benchmark runs on one GPU only: sharding across GPUs "
+                                   "is designed but not implemented", "n_gpus": args.gpus}))
         sys.exit(2)
 
     import torch
@@ -418,7 +418,11 @@ def main():
                     "avg_us": ktimes[dominant]["avg_us"]}
 
     out = {
-        "metric": "PCG DOF-iter/s (whole hot-path step; ROM build/solve/estimate included in the time)",
+        "metric": "PCG DOF-iter/s (%HBM peak); ROM evals/s + p99 latency, mixed vs plain FP64",
+        "value_definition": "PCG DOF-iterations per second of the whole hot-path step (HDM solve, "
+                            "sensitivity, ROM build, reduced solve and estimate inside the timed "
+                            "region); the %HBM peak is roofline.frac, the ROM evals/s and p99 "
+                            "latencies in each precision are under rom",
         "value": value,
         "unit": "DOF-iter/s",
         "n_gpus": 1,
@@ -467,6 +471,8 @@ def main():
                                     "p99_ms": 1e3 * lat[min(len(lat) - 1, int(0.99 * len(lat)))],
                                     "Jk": float(Je[0]), "resnorm": float(rn[0])}
         out["extra"] = extra
+        out["rom"] = {nm: {q: extra[f"rom_{nm}"][q] for q in ("evals_per_s", "p50_ms", "p99_ms")}
+                      for nm in ("mixed", "fp64")}
 
     if not args.no_serving:
         out["serving"] = serving_leg(args, torch, W, binding, FP64, MIXED)
