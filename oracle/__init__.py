@@ -17,11 +17,11 @@ closed forms, invariants, brute force or textbook results (see the test modules
 from .fem import (element_stiffness, constitutive, element_dofs, simp_alpha,
                   simp_alpha_prime, assemble, apply_masked, apply_rows, solve_direct,
                   solve_cg, compliance, sensitivity, free_dofs)
-from .rom import rom_operator, rom_load, rom_solve, rom_residual, rom_eval
+from .rom import rom_operator, rom_load, rom_solve, rom_residual, rom_eval, rom_gradient
 
 __all__ = [
     "element_stiffness", "constitutive", "element_dofs", "simp_alpha", "simp_alpha_prime",
     "assemble", "apply_masked", "apply_rows", "solve_direct", "solve_cg", "compliance",
     "sensitivity", "free_dofs", "rom_operator", "rom_load", "rom_solve", "rom_residual",
-    "rom_eval",
+    "rom_eval", "rom_gradient",
 ]

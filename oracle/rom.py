@@ -16,7 +16,7 @@ from __future__ import annotations
 import numpy as np
 import scipy.linalg as sla
 
-from .fem import assemble
+from .fem import assemble, sensitivity
 
 
 def _masked(phi, mask):
@@ -66,3 +66,14 @@ def rom_eval(mesh, rho, phi, mask, f, plane_stress=True):
     y, J = rom_solve(Kh, fh)
     _, rn, _ = rom_residual(mesh, rho, phi, mask, f, y, plane_stress)
     return dict(Khat=Kh, fhat=fh, yhat=y, Jk=J, resnorm=rn)
+
+
+def rom_gradient(mesh, rho, phi, mask, f, plane_stress=True):
+    """Sensitivity of the ROM compliance J_k(rho) = f_hat^T K_hat(rho)^{-1} f_hat with
+    respect to the densities: dJ_k/drho_e = -y_hat^T (dK_hat/drho_e) y_hat
+    = -alpha'(rho_e) u_k,e^T K_e u_k,e with u_k = Phi y_hat.  For the compliance the
+    reduced adjoint equals the reduced state (Sec. 3.2), so this is the element
+    sensitivity of Sec. 2.4 evaluated at the ROM state.  Returns (dJ_k, J_k)."""
+    ev = rom_eval(mesh, rho, phi, mask, f, plane_stress)
+    uk = _masked(phi, mask) @ ev["yhat"]
+    return sensitivity(mesh, rho, uk, plane_stress), ev["Jk"]

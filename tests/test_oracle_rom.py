@@ -162,3 +162,45 @@ def test_masked_rows_are_ignored():
     a = O.rom_eval(p.mesh, rho, phi, p.mask, p.f)
     b = O.rom_eval(p.mesh, rho, noisy, p.mask, p.f)
     assert np.array_equal(a["Khat"], b["Khat"]) and a["Jk"] == b["Jk"]
+
+
+def test_rom_gradient_matches_finite_differences():
+    """dJ_k/drho_e by central differences of the ROM compliance itself (each J_k from
+    K_hat, f_hat and the reduced Cholesky solve, no sensitivity formula), 2D and 3D."""
+    for p, k in ((W.mbb2d(12, 5), 6), (W.cantilever3d(4, 3, 2), 7)):
+        m = p.mesh
+        rho = np.random.default_rng(4).uniform(0.2, 1.0, m.n_elems)
+        phi = W.cosine_basis(m, p.mask, k, 5, np.float64)
+        g, J = O.rom_gradient(m, rho, phi, p.mask, p.f)
+        for e in (0, m.n_elems // 3, m.n_elems - 1):
+            h = 1e-6 * rho[e]
+            rp, rm = rho.copy(), rho.copy()
+            rp[e] += h
+            rm[e] -= h
+            fd = (O.rom_eval(m, rp, phi, p.mask, p.f)["Jk"] - O.rom_eval(m, rm, phi, p.mask, p.f)["Jk"]) / (2 * h)
+            assert abs(g[e] - fd) <= 1e-6 * abs(fd) + 1e-12 * abs(J)
+        assert np.all(g <= 0)
+
+
+def test_rom_gradient_homogeneity():
+    """With Emin = 0 the reduced stiffness scales as t^p under rho -> t rho, so J_k is
+    homogeneous of degree -p and sum_e rho_e dJ_k/drho_e = -p J_k (Euler)."""
+    import dataclasses
+    p = W.mbb2d(16, 6)
+    m = dataclasses.replace(p.mesh, Emin=0.0)
+    rho = np.random.default_rng(8).uniform(0.1, 1.0, m.n_elems)
+    phi = W.cosine_basis(m, p.mask, 8, 3, np.float64)
+    g, J = O.rom_gradient(m, rho, phi, p.mask, p.f)
+    assert abs(np.dot(rho, g) / (-m.penal * J) - 1) < 1e-12
+
+
+def test_rom_gradient_exact_when_solution_in_span():
+    """u*(rho) in span(Phi): the ROM state is the HDM state, so the ROM sensitivity is
+    the HDM one (Sec. 3.3 sensitivity error with a zero residual)."""
+    p = W.mbb2d(20, 8)
+    rho = W.rho_jitter(p.mesh, 6)
+    u = O.solve_direct(p.mesh, rho, p.f, p.mask)
+    phi = np.column_stack([W.cosine_basis(p.mesh, p.mask, 4, 2, np.float64), u])
+    g, _ = O.rom_gradient(p.mesh, rho, phi, p.mask, p.f)
+    g0 = O.sensitivity(p.mesh, rho, u)
+    assert np.abs(g - g0).max() <= 1e-9 * np.abs(g0).max()
