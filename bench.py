@@ -5,7 +5,7 @@ One step = one pass of the whole hot path over one synthetic design:
   HDM state solve (Jacobi-PCG, float32 inner / float64 refinement, rtol 1e-10)
   -> compliance -> element sensitivity -> ROM build (K_hat by per-element MFMA
   contraction, f_hat) -> reduced float64 Cholesky solve -> residual error indicator
-  with reduced refinement.
+  with reduced refinement -> ROM sensitivity dJ_k/drho at the reduced state.
 Headline value: PCG DOF-iterations per second over the whole timed step
 (N_u x inner PCG iterations / wall time, ROM work included in the time).
 
@@ -353,6 +353,7 @@ def main():
     J = torch.empty(1, dtype=torch.float64, device=dev)
     Je = torch.empty(1, dtype=torch.float64, device=dev)
     rn = torch.empty(1, dtype=torch.float64, device=dev)
+    dJ = torch.empty((1, m.n_elems), dtype=torch.float64, device=dev)
     st = torch.empty(1, dtype=torch.int32, device=dev)
 
     ctx = binding.Context(0)
@@ -363,6 +364,7 @@ def main():
         ctx.rom_build(m, phi, k, mask, f, rho1, prec=prec, Khat=Kh, fhat=fh)
         ctx.rom_solve(Kh, fh, status=st, yhat=y, Jk=J)
         ctx.rom_estimate(m, phi, k, mask, f, rho1, Kh, y, max_refine=args.max_refine, Jk=Je, resnorm=rn)
+        ctx.rom_gradient(m, phi, k, mask, rho1, y, dJ=dJ)
         return info
 
     for _ in range(args.warmup):
@@ -420,9 +422,9 @@ def main():
     out = {
         "metric": "PCG DOF-iter/s (%HBM peak); ROM evals/s + p99 latency, mixed vs plain FP64",
         "value_definition": "PCG DOF-iterations per second of the whole hot-path step (HDM solve, "
-                            "sensitivity, ROM build, reduced solve and estimate inside the timed "
-                            "region); the %HBM peak is roofline.frac, the ROM evals/s and p99 "
-                            "latencies in each precision are under rom",
+                            "sensitivity, ROM build, reduced solve, estimate and ROM sensitivity "
+                            "inside the timed region); the %HBM peak is roofline.frac, the ROM "
+                            "evals/s and p99 latencies in each precision are under rom",
         "value": value,
         "unit": "DOF-iter/s",
         "n_gpus": 1,
@@ -466,6 +468,16 @@ def main():
                 torch.cuda.synchronize()
                 lat.append(time.perf_counter() - ta)
             lat.sort()
+            # the ROM sensitivity dJ_k/drho at the state just estimated (value + gradient
+            # of the trust-region model)
+            glat = []
+            for i in range(20):
+                ta = time.perf_counter()
+                ctx.rom_gradient(m, phi, k, mask, rho1, y, dJ=dJ)
+                torch.cuda.synchronize()
+                glat.append(time.perf_counter() - ta)
+            glat.sort()
+            extra[f"rom_{name}_gradient_ms"] = 1e3 * glat[len(glat) // 2]
             extra[f"rom_{name}"] = {"evals_per_s": len(lat) / sum(lat),
                                     "p50_ms": 1e3 * lat[len(lat) // 2],
                                     "p99_ms": 1e3 * lat[min(len(lat) - 1, int(0.99 * len(lat)))],

@@ -215,6 +215,19 @@ int topo_rom_estimate(topo_ctx* ctx, const topo_mesh* mesh, const void* phi,
                       double* yhat, double* Jk, double* resnorm, int32_t max_refine,
                       void* stream);
 
+/* Sensitivity of the ROM compliance J_k(rho) = f_hat^T K_hat(rho)^{-1} f_hat with
+ * respect to the densities (Sec. 3.2: for the compliance the reduced adjoint equals the
+ * reduced state; the element form is the sensitivity of Sec. 2.4 at u_k = Phi y_hat):
+ *   dJ[b][e] = -alpha'(rho[b][e]) u_k,e^T K_e u_k,e,   u_k = Phi yhat[b]  (float64).
+ * Phi, k, ldphi, mask as in topo_rom_build; rho [B][N_e] f64; yhat [B][k] f64 (the
+ * coefficients rom_solve / rom_estimate returned for those densities); dJ [B][N_e] f64
+ * out.  Only enqueues work.  Errors: TOPO_EINVAL (null pointer, B < 1, bad basis
+ * shape), TOPO_ENOMEM (workspace), TOPO_EDEVICE. */
+int topo_rom_gradient(topo_ctx* ctx, const topo_mesh* mesh, const void* phi,
+                      int32_t phi_fp32, int32_t k, int32_t ldphi, const uint8_t* mask,
+                      const double* rho, int32_t B, const double* yhat, double* dJ,
+                      void* stream);
+
 #ifdef __cplusplus
 }
 #endif

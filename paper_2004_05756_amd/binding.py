@@ -23,7 +23,7 @@ EXPORTED = (
     "topo_ctx_workspace_bytes", "topo_element_stiffness", "topo_element_factor", "topo_apply",
     "topo_hdm_solve",
     "topo_hdm_gradient", "topo_rom_build", "topo_rom_solve", "topo_rom_estimate",
-    "topo_ctx_set_timing", "topo_ctx_kernel_time",
+    "topo_rom_gradient", "topo_ctx_set_timing", "topo_ctx_kernel_time",
 )
 
 
@@ -69,6 +69,8 @@ _SIGS = {
     "topo_rom_solve": (C.c_int, [_P, C.c_int32, C.c_int32, _P, _P, _P, _P, _P, _P]),
     "topo_rom_estimate": (C.c_int, [_P, C.POINTER(TopoMesh), _P, C.c_int32, C.c_int32, C.c_int32,
                                     _P, _P, _P, C.c_int32, _P, _P, _P, _P, C.c_int32, _P]),
+    "topo_rom_gradient": (C.c_int, [_P, C.POINTER(TopoMesh), _P, C.c_int32, C.c_int32, C.c_int32,
+                                    _P, _P, C.c_int32, _P, _P, _P]),
 }
 
 _lib = None
@@ -297,6 +299,26 @@ class Context:
                                         _stream(stream))
         self._check(rc, "rom_estimate")
         return yhat, Jk, resnorm
+
+    def rom_gradient(self, mesh, phi, k, mask, rho, yhat, dJ=None, stream=None):
+        """dJ_k/drho [B][N_e] at the ROM state Phi yhat (topo_rom_gradient)."""
+        import torch
+        if rho.dim() == 1:
+            rho = rho.unsqueeze(0)
+        if yhat.dim() == 1:
+            yhat = yhat.unsqueeze(0)
+        B = rho.shape[0]
+        if dJ is None:
+            dJ = torch.empty_like(rho, dtype=torch.float64)
+        m = make_mesh(mesh)
+        fp32 = 1 if phi.dtype == torch.float32 else 0
+        rc = self.lib.topo_rom_gradient(self.h, C.byref(m), _ptr(phi, None, "phi"), fp32, int(k),
+                                        int(phi.shape[1]), _ptr(mask, torch.uint8, "mask"),
+                                        _ptr(rho, torch.float64, "rho"), B,
+                                        _ptr(yhat, torch.float64, "yhat"), _ptr(dJ, torch.float64, "dJ"),
+                                        _stream(stream))
+        self._check(rc, "rom_gradient")
+        return dJ
 
 
 _ctx = {}

@@ -599,7 +599,8 @@ __global__ void k_correct(long long n, double* __restrict__ u, const T* __restri
 }
 
 // ----------------------------------------------------------------------------------
-// Element sensitivity dc_e = -alpha'(rho_e) u_e^T K_e u_e   (float64)
+// Element sensitivity dc_e = -alpha'(rho_e) u_e^T K_e u_e   (float64), one field per
+// blockIdx.y (rho [B][N_e], u [B][N_u], dc [B][N_e])
 // ----------------------------------------------------------------------------------
 template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_gradient(Grid g, const double* __restrict__ rho,
@@ -611,6 +612,9 @@ __global__ __launch_bounds__(kBlock) void k_gradient(Grid g, const double* __res
     constexpr int NE = DIM * NEN;
     const int e = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (e >= g.n_elems) return;
+    rho += (size_t)blockIdx.y * g.n_elems;
+    u += (size_t)blockIdx.y * g.n_dofs;
+    dc += (size_t)blockIdx.y * g.n_elems;
     const int ex = e % g.nx;
     const int t = e / g.nx;
     const int ey = t % g.ny;
@@ -1280,19 +1284,28 @@ int topo_hdm_gradient(topo_ctx* ctx, const topo_mesh* mesh, const double* rho, c
     const Grid g = make_grid(*mesh);
     const ElemTables* tb = get_tables(ctx, *mesh);
     if (!tb) return set_error(ctx, TOPO_EDEVICE, "element table upload failed");
-    hipStream_t s = (hipStream_t)stream;
+    return gradient_launch(ctx, g, *mesh, tb, rho, u, 1, dc, (hipStream_t)stream);
+}
+
+}  // extern "C"
+
+namespace topo {
+
+int gradient_launch(Ctx* ctx, const Grid& g, const topo_mesh& m, const ElemTables* tb,
+                    const double* rho, const double* u, int B, double* dc, hipStream_t s) {
     TimedLaunch tl(ctx, KID_GRADIENT, s);
+    const dim3 grid(grid_blocks(g.n_elems), B);
     if (g.dim == 2)
-        hipLaunchKernelGGL((k_gradient<2>), dim3(grid_blocks(g.n_elems)), dim3(kBlock), 0, s, g, rho,
-                           tb->K64, u, mesh->E0, mesh->Emin, mesh->penal, dc);
+        hipLaunchKernelGGL((k_gradient<2>), grid, dim3(kBlock), 0, s, g, rho, tb->K64, u, m.E0,
+                           m.Emin, m.penal, dc);
     else
-        hipLaunchKernelGGL((k_gradient<3>), dim3(grid_blocks(g.n_elems)), dim3(kBlock), 0, s, g, rho,
-                           tb->K64, u, mesh->E0, mesh->Emin, mesh->penal, dc);
+        hipLaunchKernelGGL((k_gradient<3>), grid, dim3(kBlock), 0, s, g, rho, tb->K64, u, m.E0,
+                           m.Emin, m.penal, dc);
     TOPO_CHECK_LAUNCH();
     return TOPO_OK;
 }
 
-}  // extern "C"
+}  // namespace topo
 
 // Entry points shared with the ROM translation unit.
 namespace topo {

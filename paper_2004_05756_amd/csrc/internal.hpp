@@ -261,6 +261,11 @@ __host__ __device__ inline int march3_blocks(const Grid& g) {
     return march3_tiles_x(g) * march3_tiles_y(g) * ((g.nz1 + kz - 1) / kz);
 }
 
+// Element sensitivities dc_e = -alpha'(rho_e) u_e^T K_e u_e of B fields (rho [B][N_e],
+// u [B][N_u], dc [B][N_e], all float64 device arrays).
+int gradient_launch(Ctx* ctx, const Grid& g, const topo_mesh& m, const ElemTables* tb,
+                    const double* rho, const double* u, int B, double* dc, hipStream_t s);
+
 // Resident blocks of a 256-thread kernel on the whole device (its occupancy times the
 // CU count); 1024 when the runtime cannot tell.
 int march3_target(const Ctx* ctx, const void* kernel);

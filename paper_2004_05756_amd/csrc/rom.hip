@@ -889,6 +889,25 @@ static int phit_v(Ctx* ctx, const Grid& g, const void* phi, int fp32, int k, int
     return TOPO_OK;
 }
 
+// u[b] = Phi y[b] on free rows (0 on Dirichlet rows), B fields.
+static int phi_y_launch(Ctx* ctx, const void* phi, int fp32, int k, int ldphi, const uint8_t* mask,
+                        const double* y, long long N, int B, double* u, hipStream_t s) {
+    const size_t esz = fp32 ? 4 : 8;
+    const int rb = tile_rows(ldphi, esz);
+    const size_t lds = (size_t)((k + 1) & ~1) * sizeof(double) + tile_bytes(rb, ldphi, esz);
+    {
+        TimedLaunch tl(ctx, KID_PHI_Y, s);
+        if (fp32)
+            hipLaunchKernelGGL((k_phi_y<float>), dim3(grid_blocks(N, rb), B), dim3(256), lds, s, N,
+                               (const float*)phi, k, ldphi, mask, y, rb, u);
+        else
+            hipLaunchKernelGGL((k_phi_y<double>), dim3(grid_blocks(N, rb), B), dim3(256), lds, s, N,
+                               (const double*)phi, k, ldphi, mask, y, rb, u);
+    }
+    TOPO_CHECK_LAUNCH();
+    return TOPO_OK;
+}
+
 static int phit_chunks(const Grid& g) {
     long long c = g.n_dofs / 256;
     return (int)std::max(1LL, std::min(c, 2048LL));
@@ -1115,19 +1134,8 @@ int topo_rom_estimate(topo_ctx* ctx, const topo_mesh* mesh, const void* phi, int
     if (rc) return rc;
     // u = Phi y_hat, r = f - K u, ||r||^2 and f^T u per field
     auto pass = [&]() -> int {
-        const size_t esz = phi_fp32 ? 4 : 8;
-        const int rb = tile_rows(ldphi, esz);
-        const size_t lds = (size_t)((k + 1) & ~1) * sizeof(double) + tile_bytes(rb, ldphi, esz);
-        {
-            TimedLaunch tl(ctx, KID_PHI_Y, s);
-            if (phi_fp32)
-                hipLaunchKernelGGL((k_phi_y<float>), dim3(grid_blocks(N, rb), B), dim3(256), lds, s,
-                                   N, (const float*)phi, k, ldphi, mask, yhat, rb, u);
-            else
-                hipLaunchKernelGGL((k_phi_y<double>), dim3(grid_blocks(N, rb), B), dim3(256), lds, s,
-                                   N, (const double*)phi, k, ldphi, mask, yhat, rb, u);
-        }
-        TOPO_CHECK_LAUNCH();
+        int rc2 = phi_y_launch(ctx, phi, phi_fp32, k, ldphi, mask, yhat, N, B, u, s);
+        if (rc2) return rc2;
         return residual_fp64(ctx, g, tb, a64, mask, u, f, r, B, part, out, s);
     };
     // Galerkin residual r_hat = Phi^T r and its squared norm per field
@@ -1171,6 +1179,33 @@ int topo_rom_estimate(topo_ctx* ctx, const topo_mesh* mesh, const void* phi, int
                        (const double*)(max_refine > 0 ? keep : out), resnorm, Jk);
     TOPO_CHECK_LAUNCH();
     return TOPO_OK;
+}
+
+int topo_rom_gradient(topo_ctx* ctx, const topo_mesh* mesh, const void* phi, int32_t phi_fp32,
+                      int32_t k, int32_t ldphi, const uint8_t* mask, const double* rho, int32_t B,
+                      const double* yhat, double* dJ, void* stream) {
+    if (!ctx) return TOPO_EINVAL;
+    int rc = validate_mesh(ctx, mesh);
+    if (rc) return rc;
+    const Grid g = make_grid(*mesh);
+    rc = check_basis(ctx, g, phi, k, ldphi);
+    if (rc) return rc;
+    if (!mask || !rho || !yhat || !dJ || B < 1) return set_error(ctx, TOPO_EINVAL, "bad argument");
+    TOPO_HIP(hipSetDevice(ctx->device));
+    const ElemTables* tb = get_tables(ctx, *mesh);
+    if (!tb) return set_error(ctx, TOPO_EDEVICE, "element table upload failed");
+    hipStream_t s = (hipStream_t)stream;
+    const long long N = g.n_dofs;
+    Arena ar;
+    double* u;
+    ar.take(&u, (size_t)B * N);
+    rc = ar.commit(ctx, s);
+    if (rc) return rc;
+    // u_k = Phi y_hat, then the element sensitivities of the compliance at u_k: for the
+    // compliance the reduced adjoint is the reduced state itself
+    rc = phi_y_launch(ctx, phi, phi_fp32, k, ldphi, mask, yhat, N, B, u, s);
+    if (rc) return rc;
+    return gradient_launch(ctx, g, *mesh, tb, rho, u, B, dJ, s);
 }
 
 }  // extern "C"
