@@ -228,6 +228,54 @@ int topo_rom_gradient(topo_ctx* ctx, const topo_mesh* mesh, const void* phi,
                       const double* rho, int32_t B, const double* yhat, double* dJ,
                       void* stream);
 
+/* ---- Reduced basis at a trust-region centre (Sec. 4.2) --------------------------- */
+
+/* Largest snapshot window L the basis routines accept. */
+#define TOPO_POD_MAX_WINDOW 48
+
+/* Limited-memory snapshot window (Sec. 4.2, remark on keeping only the L most recent
+ * trust-region centres).  The caller owns the window state:
+ *   S [L][n] f64 device: slot i holds a snapshot at S + i*n;
+ *   G [L][L] f64 device: G[i][j] = S_i . S_j for the valid slots 0..*count-1;
+ *   *count (host, in/out): number of valid slots, 0 for an empty window;
+ *   *next  (host, in/out): the slot of the oldest snapshot once the window is full (0
+ *          while it fills).
+ * Pushes the snapshot u [n] f64 device: while *count < L it goes to slot *count and the
+ * window grows (rank-one update of G); once full it replaces slot *next, the oldest
+ * (rank-two update: one snapshot in, one out), and *next advances modulo L.  One
+ * streaming pass over the window computes the new row and column of G (deterministic
+ * float64 sums) and stores u.  Only enqueues work; *count and *next are updated on
+ * return.  Errors: TOPO_EINVAL (null pointer, n < 1, L outside [1,
+ * TOPO_POD_MAX_WINDOW], inconsistent count/next), TOPO_ENOMEM, TOPO_EDEVICE. */
+int topo_pod_push(topo_ctx* ctx, int64_t n, int32_t L, double* S, double* G, int32_t* count,
+                  int32_t* next, const double* u, void* stream);
+
+/* Reduced basis from the window and the snapshot at the new centre (Sec. 4.2, basis for
+ * compliance output, where the adjoint snapshots equal the primal ones):
+ *   Phi = GramSchmidt([POD_nk(U), u]),  n_k = min(count, nmax),
+ * POD_nk(U) being the n_k leading left singular vectors of the window's snapshot matrix
+ * U (count columns; their order in the window does not matter) and the Gram-Schmidt
+ * step the classical one (u minus its projections on the POD columns, normalised).
+ * Computed by the method of snapshots: eigen-decomposition of G (float64 Jacobi), POD
+ * column j = U V_j / sigma_j.  POD directions with sigma_j <= rtol * sigma_0 are not
+ * kept, and u adds no column when what is left of it has norm <= rtol * |u|.
+ *   u [n] f64 device, may be NULL (POD of the window only);
+ *   phi [n][ldphi] out, f32 (phi_fp32 != 0) or f64, row-major like every basis of this
+ *        library; columns 0..*ncols-1 are written, the others are left untouched;
+ *   *ncols (host out): columns written, the POD ones first then u's;
+ *   *npod (host out, may be NULL): POD columns kept;
+ *   sigma [count] f64 device out (may be NULL): singular values of U, descending.
+ * The accuracy of a POD direction degrades with the square of sigma_0 / sigma_j (the
+ * method of snapshots works with their squares), so rtol is meant to be >= about 1e-7.
+ * Synchronises the stream (the column count is returned to the host).  Errors:
+ * TOPO_EINVAL (null pointer, n < 1, L or count out of range, nmax < 0, rtol outside
+ * [0, 1), nothing to build, ldphi smaller than min(count, nmax) + (u != NULL)),
+ * TOPO_ENOMEM, TOPO_EDEVICE. */
+int topo_pod_basis(topo_ctx* ctx, int64_t n, int32_t L, const double* S, const double* G,
+                   int32_t count, const double* u, int32_t nmax, double rtol, void* phi,
+                   int32_t phi_fp32, int32_t ldphi, int32_t* ncols, int32_t* npod,
+                   double* sigma, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -23,8 +23,10 @@ EXPORTED = (
     "topo_ctx_workspace_bytes", "topo_element_stiffness", "topo_element_factor", "topo_apply",
     "topo_hdm_solve",
     "topo_hdm_gradient", "topo_rom_build", "topo_rom_solve", "topo_rom_estimate",
-    "topo_rom_gradient", "topo_ctx_set_timing", "topo_ctx_kernel_time",
+    "topo_rom_gradient", "topo_pod_push", "topo_pod_basis", "topo_ctx_set_timing",
+    "topo_ctx_kernel_time",
 )
+POD_MAX_WINDOW = 48
 
 
 class TopoError(RuntimeError):
@@ -71,6 +73,11 @@ _SIGS = {
                                     _P, _P, _P, C.c_int32, _P, _P, _P, _P, C.c_int32, _P]),
     "topo_rom_gradient": (C.c_int, [_P, C.POINTER(TopoMesh), _P, C.c_int32, C.c_int32, C.c_int32,
                                     _P, _P, C.c_int32, _P, _P, _P]),
+    "topo_pod_push": (C.c_int, [_P, C.c_int64, C.c_int32, _P, _P, C.POINTER(C.c_int32),
+                                C.POINTER(C.c_int32), _P, _P]),
+    "topo_pod_basis": (C.c_int, [_P, C.c_int64, C.c_int32, _P, _P, C.c_int32, _P, C.c_int32,
+                                 C.c_double, _P, C.c_int32, C.c_int32, C.POINTER(C.c_int32),
+                                 C.POINTER(C.c_int32), _P, _P]),
 }
 
 _lib = None
@@ -319,6 +326,58 @@ class Context:
                                         _stream(stream))
         self._check(rc, "rom_gradient")
         return dJ
+
+    def pod_push(self, S, G, state, u, stream=None):
+        """Push snapshot u into the window (S [L][n], G [L][L], state = [count, next]
+        host ints, updated in place) (topo_pod_push)."""
+        import torch
+        L, n = S.shape
+        cnt, nxt = C.c_int32(int(state[0])), C.c_int32(int(state[1]))
+        rc = self.lib.topo_pod_push(self.h, int(n), int(L), _ptr(S, torch.float64, "S"),
+                                    _ptr(G, torch.float64, "G"), C.byref(cnt), C.byref(nxt),
+                                    _ptr(u, torch.float64, "u"), _stream(stream))
+        self._check(rc, "pod_push")
+        state[0], state[1] = cnt.value, nxt.value
+
+    def pod_basis(self, S, G, count, u, nmax, phi, rtol=1e-7, sigma=None, stream=None):
+        """Basis GramSchmidt([POD(window), u]) written into phi [n][ldphi] (f32 or f64);
+        returns (columns written, POD columns kept) (topo_pod_basis)."""
+        import torch
+        L, n = S.shape
+        ncols, npod = C.c_int32(0), C.c_int32(0)
+        fp32 = 1 if phi.dtype == torch.float32 else 0
+        if phi.dtype not in (torch.float32, torch.float64):
+            raise TypeError("phi must be float32 or float64")
+        rc = self.lib.topo_pod_basis(self.h, int(n), int(L), _ptr(S, torch.float64, "S"),
+                                     _ptr(G, torch.float64, "G"), int(count),
+                                     _ptr(u, torch.float64, "u"), int(nmax), float(rtol),
+                                     _ptr(phi, None, "phi"), fp32, int(phi.shape[1]),
+                                     C.byref(ncols), C.byref(npod),
+                                     _ptr(sigma, torch.float64, "sigma"), _stream(stream))
+        self._check(rc, "pod_basis")
+        return ncols.value, npod.value
+
+
+class SnapshotWindow:
+    """Device-resident window of the L most recent snapshots of length n and their Gram
+    matrix, for Context.pod_push / pod_basis."""
+
+    def __init__(self, ctx, n, L, device="cuda"):
+        import torch
+        self.ctx = ctx
+        self.S = torch.zeros((L, n), dtype=torch.float64, device=device)
+        self.G = torch.zeros((L, L), dtype=torch.float64, device=device)
+        self.state = [0, 0]
+
+    @property
+    def count(self):
+        return self.state[0]
+
+    def push(self, u, stream=None):
+        self.ctx.pod_push(self.S, self.G, self.state, u, stream)
+
+    def basis(self, u, nmax, phi, rtol=1e-7, sigma=None, stream=None):
+        return self.ctx.pod_basis(self.S, self.G, self.count, u, nmax, phi, rtol, sigma, stream)
 
 
 _ctx = {}

@@ -295,6 +295,20 @@ def cosine_basis(mesh: Mesh, mask: np.ndarray, k: int, seed: int, dtype=np.float
     return phi.astype(dtype)
 
 
+def snapshot_fields(mesh: Mesh, mask: np.ndarray, count: int, seed: int, decay: float = 0.5,
+                    rank: int = 0) -> np.ndarray:
+    """count smooth displacement-like snapshots with a geometric spread of singular
+    values: u_i = c_0 + sum_{j=1..r-1} a_ij decay^j c_j with c_j the fields of
+    cosine_basis, a_ij ~ N(0, 1) seeded, r = rank or count + 1.  Zero on Dirichlet DOFs.
+    Returns [count][n_dofs] float64 (one contiguous snapshot per row)."""
+    r = rank if rank > 0 else count + 1
+    C = cosine_basis(mesh, mask, r, seed, np.float64)
+    rng = np.random.default_rng(seed + 1)
+    A = rng.standard_normal((count, r)) * decay ** np.arange(r)
+    A[:, 0] = 1.0
+    return np.ascontiguousarray(A @ C.T)
+
+
 def orthonormalize(cols: np.ndarray, mask: np.ndarray, dtype=np.float64):
     """Orthonormal basis (Householder QR in float64) of the given columns after zeroing
     Dirichlet rows; returned in ``dtype``."""
