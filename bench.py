@@ -256,6 +256,52 @@ def serving_leg(args, torch, W, binding, FP64, MIXED):
     }
 
 
+def basis_leg(torch, binding, ctx, n, L=20, nmax=19):
+    """Reduced-basis update at a trust-region centre on a full window of L snapshots of
+    length n: one push (rank-two update: the new snapshot replaces the oldest) and one
+    GramSchmidt([POD(window), u]) into a float32 basis.  Snapshots are synthetic
+    (a common random field plus perturbations of geometrically decreasing size).
+    Algorithmic bytes: push streams the L - 1 other snapshots, u, and writes u; the
+    basis call streams the window and u three times (dots, remainder norm, basis rows)
+    and writes n x (nmax + 1) floats."""
+    dev = torch.device("cuda", 0)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(11)
+    base = torch.randn(n, device=dev, dtype=torch.float64, generator=gen)
+    win = binding.SnapshotWindow(ctx, n, L)
+    snaps = [base + 0.6 ** i * torch.randn(n, device=dev, dtype=torch.float64, generator=gen)
+             for i in range(L + 1)]
+    for sn in snaps[:L]:
+        win.push(sn)
+    u = snaps[L]
+    phi = torch.empty((n, nmax + 1), device=dev, dtype=torch.float32)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    reps = 10
+    ev[0].record()
+    for i in range(reps):
+        win.push(snaps[i % (L + 1)])
+    ev[1].record()
+    torch.cuda.synchronize()
+    push_ms = ev[0].elapsed_time(ev[1]) / reps
+    lat = []
+    for _ in range(5):
+        t0 = time.perf_counter()
+        ncols, npod = win.basis(u, nmax, phi)
+        lat.append(time.perf_counter() - t0)
+    lat.sort()
+    basis_ms = 1e3 * lat[len(lat) // 2]
+    push_bytes = (L + 1) * n * 8
+    basis_bytes = 3 * (L + 1) * n * 8 + ncols * n * 4
+    out = {"n": n, "window": L, "nmax": nmax, "columns": ncols,
+           "push_ms": push_ms, "push_GB_s": push_bytes / (push_ms * 1e-3) / 1e9,
+           "basis_ms": basis_ms, "basis_GB_s": basis_bytes / (basis_ms * 1e-3) / 1e9}
+    out["push_hbm_frac"] = out["push_GB_s"] / HBM_PEAK_GBS
+    out["basis_hbm_frac"] = out["basis_GB_s"] / HBM_PEAK_GBS
+    del win, snaps, phi
+    return out
+
+
 def bridge_leg(torch, W, binding, FP64, MIXED):
     """The 192x96x96 bridge: the 16-field batched apply in both precisions (kernel time
     from the library's sampled events, algorithmic bytes, HBM fraction) and one HDM
@@ -301,6 +347,7 @@ def bridge_leg(torch, W, binding, FP64, MIXED):
         dt_s = time.perf_counter() - t0
         out[f"hdm_{name}"] = {"ms": 1e3 * dt_s, "iters": inf["iters"], "fp64_fallback": inf["fp64_fallback"],
                               "rel_resid": inf["rel_resid"], "dof_iter_per_s": m.n_dofs * inf["iters"] / dt_s}
+    out["basis"] = basis_leg(torch, binding, ctx, m.n_dofs)
     ctx.close()
     return out
 
@@ -482,6 +529,7 @@ def main():
                                     "p50_ms": 1e3 * lat[len(lat) // 2],
                                     "p99_ms": 1e3 * lat[min(len(lat) - 1, int(0.99 * len(lat)))],
                                     "Jk": float(Je[0]), "resnorm": float(rn[0])}
+        extra["basis"] = basis_leg(torch, binding, ctx, m.n_dofs)
         out["extra"] = extra
         out["rom"] = {nm: {q: extra[f"rom_{nm}"][q] for q in ("evals_per_s", "p50_ms", "p99_ms")}
                       for nm in ("mixed", "fp64")}

@@ -101,82 +101,123 @@ struct PodVecOut {
     __device__ void operator()(int, int e, double s) const { out[e] = s; }
 };
 
+// 1 / x and 1 / sqrt(x) in float64: the hardware approximation refined by two Newton
+// steps (each doubles the number of correct bits).
+__device__ __forceinline__ double pod_rcp(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return fma(r, fma(-x, r, 1.0), r);
+}
+__device__ __forceinline__ double pod_rsqrt(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const double h = 0.5 * x * y;
+        y = fma(y, fma(-h, y, 0.5), y);
+    }
+    return y;
+}
+
+constexpr int kEigThreads = 512;
+
 // POD of the window from its Gram matrix, and the coefficients of the new basis as a
 // combination of the window's snapshots and the new one.  One workgroup.
 //
 // Cyclic Jacobi: each step rotates m/2 disjoint index pairs (round-robin schedule, a
-// dummy index when m is odd, every pair once per sweep); the rotations of one step
-// commute, so A <- J^T A J is applied as all row rotations, then all column rotations
-// (and V <- V J).  Sweeps stop once the off-diagonal mass is below 1e-30 of the diagonal
+// dummy index when m is odd, every pair once per sweep).  For pairs a and b the 2 x 2
+// block of A on rows {p_a, q_a} and columns {p_b, q_b} becomes J_a^T A_ab J_b, a function
+// of that block alone, so one thread updates a whole block (and its mirror image) in
+// place, and one thread a pair of entries V[r][p_b], V[r][q_b] of V <- V J: one phase per
+// step, spread over all threads.  A pair is rotated only while a_pq^2 exceeds both
+// 1e-30 a_pp a_qq and (2e-16 |diag A|)^2 (the rounding level of G); sweeps stop after a
+// sweep without a rotation, or once the off-diagonal mass is below 1e-30 of the diagonal
 // mass.  Eigenvalues are sorted descending; sigma_i = sqrt(max(lambda_i, 0)).  POD
 // directions kept: the leading n <= min(m, nmax) with sigma_i > rtol * sigma_0.
 //
 // coef is (m + 1) x ldc, row i for snapshot i, row m for the new snapshot u:
-//   columns j < n       : W_ij = V_i,order(j) / sigma_j  (POD column j = S W_j)
-//   column ldc - 1 (u)  : the combination v = u - sum_j (Phi_j . u) Phi_j of the
-//                         Gram-Schmidt step, with Phi_j . u = W_j . gu, gu_i = S_i . u.
-__global__ __launch_bounds__(256) void k_pod_eig(int m, int L, const double* __restrict__ G,
-                                                 const double* __restrict__ gu, int nmax, double rtol,
-                                                 double* __restrict__ coef, int ldc,
-                                                 double* __restrict__ sigma, PodInfo* __restrict__ info) {
+//   columns j < n           : W_ij = V_i,order(j) / sigma_j  (POD column j = S W_j)
+//   columns n .. ldc - 2    : zero (and column ldc - 1 when there is no u)
+//   column ldc - 1 (u only) : the combination v = u - sum_j (Phi_j . u) Phi_j of the
+//                             Gram-Schmidt step, with Phi_j . u = W_j . gu, gu_i = S_i . u.
+__global__ __launch_bounds__(kEigThreads) void k_pod_eig(int m, int L, const double* __restrict__ G,
+                                                         const double* __restrict__ gu, int nmax, double rtol,
+                                                         double* __restrict__ coef, int ldc,
+                                                         double* __restrict__ sigma, PodInfo* __restrict__ info) {
+    constexpr int NW = kEigThreads / 64;
     __shared__ double A[kPodMaxL][kPodMaxL + 1];
     __shared__ double V[kPodMaxL][kPodMaxL + 1];
     __shared__ double cs[kPodMaxL / 2], sn[kPodMaxL / 2];
     __shared__ int pp[kPodMaxL / 2], pq[kPodMaxL / 2];
-    __shared__ double red[2][256];
+    __shared__ double red[2][NW];
     __shared__ int order[kPodMaxL];
-    __shared__ double sig[kPodMaxL], cvec[kPodMaxL];
-    __shared__ int s_n;
-    const int t = threadIdx.x, nt = blockDim.x;
-    for (int e = t; e < m * m; e += nt) {
-        const int i = e / m, j = e - i * m;
-        A[i][j] = G[(size_t)i * L + j];
-        V[i][j] = i == j ? 1.0 : 0.0;
-    }
+    __shared__ double sig[kPodMaxL], rsig[kPodMaxL], cvec[kPodMaxL];
+    __shared__ int s_n, s_rot, s_prev, s_step;
+    const int t = threadIdx.x;
+    const int lane = t & 63, wv = t >> 6;
+    for (int i = wv; i < m; i += NW)
+        if (lane < m) {
+            A[i][lane] = G[(size_t)i * L + lane];
+            V[i][lane] = i == lane ? 1.0 : 0.0;
+        }
     __syncthreads();
     const int M = m + (m & 1);
     const int P = M / 2;
+    // update items: A blocks e = ia + (ib << sa), V pairs e = r + (ib << sv)
+    const int sa = P <= 8 ? 3 : P <= 16 ? 4 : 5;
+    const int sv = m <= 16 ? 4 : m <= 32 ? 5 : 6;
+    const int na = P << sa, nitems = na + (P << sv);
     for (int sweep = 0; sweep < 60; ++sweep) {
         double off = 0.0, dia = 0.0;
-        for (int e = t; e < m * m; e += nt) {
-            const int i = e / m, j = e - i * m;
-            const double a = A[i][j];
-            if (i == j) dia += a * a;
-            else off += a * a;
-        }
-        red[0][t] = off;
-        red[1][t] = dia;
-        __syncthreads();
-        for (int h = nt >> 1; h > 0; h >>= 1) {
-            if (t < h) {
-                red[0][t] += red[0][t + h];
-                red[1][t] += red[1][t + h];
+        if (lane < m)
+            for (int i = wv; i < m; i += NW) {
+                const double a = A[i][lane];
+                if (i == lane) dia += a * a;
+                else off += a * a;
             }
-            __syncthreads();
+        off = wave_sum64(off);
+        dia = wave_sum64(dia);
+        if (lane == 0) {
+            red[0][wv] = off;
+            red[1][wv] = dia;
         }
-        const bool done = red[0][0] <= 1e-30 * red[1][0];
+        if (t == 0) s_rot = 0;
+        if (t == 1) s_step = 0;
         __syncthreads();
-        if (done) break;
+        double offs = 0.0, dias = 0.0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            offs += red[0][w];
+            dias += red[1][w];
+        }
+        __syncthreads();
+        if (offs <= 1e-30 * dias || (sweep > 0 && s_prev == 0)) break;
+        const double floor2 = 4e-32 * dias;  // (2e-16 |diag A|)^2
         for (int step = 0; step < M - 1; ++step) {
             if (t < P) {
                 int a, b;
                 if (t == 0) {
                     a = 0;
-                    b = 1 + step % (M - 1);
+                    b = 1 + step;
                 } else {
-                    a = 1 + (step + t) % (M - 1);
-                    b = 1 + (step - t + M - 1) % (M - 1);
+                    a = 1 + step + t;
+                    if (a > M - 1) a -= M - 1;
+                    b = 1 + step - t + M - 1;
+                    if (b > M - 1) b -= M - 1;
                 }
                 const int p = min(a, b), q = max(a, b);
                 double c = 1.0, s = 0.0;
                 if (q < m) {
-                    const double apq = A[p][q];
-                    if (apq != 0.0 && fabs(apq) > 1e-18 * sqrt(fabs(A[p][p] * A[q][q]))) {
-                        const double tau = (A[q][q] - A[p][p]) / (2.0 * apq);
-                        const double tt = tau >= 0.0 ? 1.0 / (tau + sqrt(1.0 + tau * tau))
-                                                     : -1.0 / (-tau + sqrt(1.0 + tau * tau));
-                        c = 1.0 / sqrt(1.0 + tt * tt);
+                    const double app = A[p][p], aqq = A[q][q], apq = A[p][q];
+                    const double a2 = apq * apq;
+                    if (a2 > floor2 && a2 > 1e-30 * fabs(app * aqq)) {
+                        const double tau = (aqq - app) * pod_rcp(2.0 * apq);
+                        const double at = fabs(tau);
+                        double tt = at > 1e150 ? 0.5 / at : pod_rcp(at + sqrt(1.0 + tau * tau));
+                        tt = tau < 0.0 ? -tt : tt;
+                        c = pod_rsqrt(1.0 + tt * tt);
                         s = tt * c;
+                        s_rot = 1;
+                        s_step = step + 1;
                     }
                 }
                 pp[t] = p;
@@ -185,69 +226,95 @@ __global__ __launch_bounds__(256) void k_pod_eig(int m, int L, const double* __r
                 sn[t] = s;
             }
             __syncthreads();
-            for (int e = t; e < P * m; e += nt) {
-                const int k = e / m, col = e - k * m;
-                const int p = pp[k], q = pq[k];
-                if (q >= m) continue;
-                const double c = cs[k], s = sn[k];
-                const double ap = A[p][col], aq = A[q][col];
-                A[p][col] = c * ap - s * aq;
-                A[q][col] = s * ap + c * aq;
-            }
-            __syncthreads();
-            for (int e = t; e < P * m; e += nt) {
-                const int k = e / m, row = e - k * m;
-                const int p = pp[k], q = pq[k];
-                if (q >= m) continue;
-                const double c = cs[k], s = sn[k];
-                const double ap = A[row][p], aq = A[row][q];
-                A[row][p] = c * ap - s * aq;
-                A[row][q] = s * ap + c * aq;
-                const double vp = V[row][p], vq = V[row][q];
-                V[row][p] = c * vp - s * vq;
-                V[row][q] = s * vp + c * vq;
+            if (s_step != step + 1) continue;  // no pair rotated in this step
+            for (int e = t; e < nitems; e += kEigThreads) {
+                if (e < na) {  // A: block (ia, ib), ia <= ib
+                    const int ia = e & ((1 << sa) - 1), ib = e >> sa;
+                    if (ia >= P || ia > ib) continue;
+                    const int p1 = pp[ia], q1 = pq[ia], p2 = pp[ib], q2 = pq[ib];
+                    const double c1 = cs[ia], s1 = sn[ia], c2 = cs[ib], s2 = sn[ib];
+                    const bool h1 = q1 < m, h2 = q2 < m;  // false: the dummy index
+                    const double x11 = A[p1][p2];
+                    const double x12 = h2 ? A[p1][q2] : 0.0;
+                    const double x21 = h1 ? A[q1][p2] : 0.0;
+                    const double x22 = h1 && h2 ? A[q1][q2] : 0.0;
+                    const double r1p = c1 * x11 - s1 * x21, r1q = c1 * x12 - s1 * x22;  // row p1 of J1^T X
+                    const double r2p = s1 * x11 + c1 * x21, r2q = s1 * x12 + c1 * x22;  // row q1
+                    const double y11 = r1p * c2 - r1q * s2, y12 = r1p * s2 + r1q * c2;
+                    const double y21 = r2p * c2 - r2q * s2, y22 = r2p * s2 + r2q * c2;
+                    A[p1][p2] = y11;
+                    A[p2][p1] = y11;
+                    if (h2) {
+                        A[p1][q2] = y12;
+                        A[q2][p1] = y12;
+                    }
+                    if (h1) {
+                        A[q1][p2] = y21;
+                        A[p2][q1] = y21;
+                    }
+                    if (h1 && h2) {
+                        A[q1][q2] = y22;
+                        A[q2][q1] = y22;
+                    }
+                } else {  // V <- V J: row r, pair ib
+                    const int ev = e - na;
+                    const int r = ev & ((1 << sv) - 1), ib = ev >> sv;
+                    const int p2 = pp[ib], q2 = pq[ib];
+                    if (r >= m || q2 >= m) continue;
+                    const double c2 = cs[ib], s2 = sn[ib];
+                    const double vp = V[r][p2], vq = V[r][q2];
+                    V[r][p2] = c2 * vp - s2 * vq;
+                    V[r][q2] = s2 * vp + c2 * vq;
+                }
             }
             __syncthreads();
         }
+        if (t == 0) s_prev = s_rot;
+        __syncthreads();
     }
-    if (t == 0) {
-        for (int i = 0; i < m; ++i) order[i] = i;
-        for (int i = 0; i < m; ++i) {
-            int best = i;
-            for (int k = i + 1; k < m; ++k)
-                if (A[order[k]][order[k]] > A[order[best]][order[best]]) best = k;
-            const int tmp = order[i];
-            order[i] = order[best];
-            order[best] = tmp;
+    // descending order by rank (ties by index)
+    if (t < m) {
+        const double li = A[t][t];
+        int rank = 0;
+        for (int k = 0; k < m; ++k) {
+            const double lk = A[k][k];
+            rank += (lk > li || (lk == li && k < t)) ? 1 : 0;
         }
-        for (int i = 0; i < m; ++i) sig[i] = sqrt(fmax(A[order[i]][order[i]], 0.0));
+        order[rank] = t;
+    }
+    __syncthreads();
+    if (t < m) {
+        const double sg = sqrt(fmax(A[order[t]][order[t]], 0.0));
+        if (sigma) sigma[t] = sg;
+        sig[t] = sg;
+        rsig[t] = sg > 0.0 ? 1.0 / sg : 0.0;
+    }
+    __syncthreads();
+    if (wv == 0) {
         const int lim = min(m, nmax);
-        int n = 0;
-        while (n < lim && sig[n] > 0.0 && sig[n] > rtol * sig[0]) ++n;
-        s_n = n;
+        const bool ok = lane < lim && sig[lane] > 0.0 && sig[lane] > rtol * sig[0];
+        const unsigned long long bad = __ballot(!ok);  // lanes >= lim are never ok
+        if (lane == 0) s_n = __ffsll((long long)bad) - 1;
     }
     __syncthreads();
     const int n = s_n;
-    if (sigma)
-        for (int i = t; i < m; i += nt) sigma[i] = sig[i];
-    for (int e = t; e < m * n; e += nt) {
-        const int i = e / n, j = e - i * n;
-        coef[(size_t)i * ldc + j] = V[i][order[j]] / sig[j];
-    }
+    const int vc = ldc - 1;
+    const int wc = gu ? vc : ldc;  // POD coefficient columns (the last one is v's when u is given)
+    for (int i = wv; i < m; i += NW)
+        for (int j = lane; j < wc; j += 64) coef[(size_t)i * ldc + j] = j < n ? V[i][order[j]] * rsig[j] : 0.0;
     if (gu) {
-        const int vc = ldc - 1;
         if (t < n) {
             double c = 0.0;
-            for (int i = 0; i < m; ++i) c += (V[i][order[t]] / sig[t]) * gu[i];
+            for (int i = 0; i < m; ++i) c += (V[i][order[t]] * rsig[t]) * gu[i];
             cvec[t] = c;
         }
         __syncthreads();
         if (t < m) {
             double w = 0.0;
-            for (int j = 0; j < n; ++j) w += (V[t][order[j]] / sig[j]) * cvec[j];
+            for (int j = 0; j < n; ++j) w += (V[t][order[j]] * rsig[j]) * cvec[j];
             coef[(size_t)t * ldc + vc] = -w;
         }
-        for (int j = t; j < vc; j += nt) coef[(size_t)m * ldc + j] = 0.0;
+        for (int j = t; j < vc; j += kEigThreads) coef[(size_t)m * ldc + j] = 0.0;
         if (t == 0) coef[(size_t)m * ldc + vc] = 1.0;
     }
     if (t == 0) {
@@ -297,12 +364,15 @@ __global__ __launch_bounds__(kPodBlock) void k_pod_vnorm(long long n, const doub
 // The basis rows: Phi[r][j] = sum_i coef[i][j] S_i[r] for the n POD columns, and, when the
 // new snapshot is kept, Phi[r][n] = v[r] / |v| (v as in k_pod_vnorm, same order of
 // operations).  The decision to keep it is taken here from |v| and |u|: |v| > rtol |u|.
-// A thread computes one row; the block's rows are staged in LDS and stored row-major
-// with consecutive threads on consecutive addresses.  Columns >= j are not touched.
+// coef rows have exactly JMAX entries (zero past the POD columns, v's combination last),
+// so every column is accumulated without a test and the compiler reads each coefficient
+// row with wide scalar loads.  A thread computes one row; the block's rows are staged in
+// LDS and stored row-major with consecutive threads on consecutive addresses.  Columns
+// >= j are not touched.
 template <typename TP, int JMAX>
 __global__ __launch_bounds__(kPodWrite) void k_pod_write(long long n, const double* __restrict__ S, int m,
                                                          const double* __restrict__ u,
-                                                         const double* __restrict__ coef, int ldc,
+                                                         const double* __restrict__ coef,
                                                          const double* __restrict__ vsq, double rtol,
                                                          PodInfo* __restrict__ info, TP* __restrict__ phi,
                                                          int ldphi) {
@@ -322,29 +392,25 @@ __global__ __launch_bounds__(kPodWrite) void k_pod_write(long long n, const doub
         info->keep = keep;
         info->vnorm = vn;
     }
-    const int vc = ldc - 1;
     const long long r0 = (long long)blockIdx.x * kPodWrite;
     const long long r = r0 + threadIdx.x;
     double acc[JMAX];
 #pragma unroll
     for (int c = 0; c < JMAX; ++c) acc[c] = 0.0;
-    double accv = 0.0;
     if (r < n) {
-        if (keep) accv = u[r];
+        if (u) acc[JMAX - 1] = u[r];
         for (int i = 0; i < m; ++i) {
             const double x = S[(size_t)i * n + r];
-            const double* ci = coef + (size_t)i * ldc;
+            const double* ci = coef + (size_t)i * JMAX;
 #pragma unroll
-            for (int c = 0; c < JMAX; ++c)
-                if (c < np) acc[c] += ci[c] * x;
-            if (keep) accv += ci[vc] * x;
+            for (int c = 0; c < JMAX; ++c) acc[c] += ci[c] * x;
         }
     }
     TP* row = tile + threadIdx.x * LT;
 #pragma unroll
     for (int c = 0; c < JMAX; ++c)
         if (c < np) row[c] = (TP)acc[c];
-    if (keep) row[np] = (TP)(accv * scale);
+    if (keep) row[np] = (TP)(acc[JMAX - 1] * scale);
     __syncthreads();
     const int nr = (int)min((long long)kPodWrite, n - r0);
     for (int e = threadIdx.x; e < nr * j; e += kPodWrite) {
@@ -357,18 +423,27 @@ static int pod_chunks(long long n) {
     return (int)((n + (long long)kPodBlock * kPodRows - 1) / ((long long)kPodBlock * kPodRows));
 }
 
+// Coefficient row length (and register tile) for a basis of at most jbound columns.
+static int pod_ldc(int jbound) {
+    for (int J : {8, 16, 24, 32, 40}) if (jbound <= J) return J;
+    return kPodMaxL + 1;
+}
+
 template <typename TP>
-static void launch_pod_write(int jbound, long long n, const double* S, int m, const double* u,
-                             const double* coef, int ldc, const double* vsq, double rtol, PodInfo* info,
-                             TP* phi, int ldphi, hipStream_t s) {
+static void launch_pod_write(int ldc, long long n, const double* S, int m, const double* u, const double* coef,
+                             const double* vsq, double rtol, PodInfo* info, TP* phi, int ldphi, hipStream_t s) {
     const dim3 grid((unsigned)((n + kPodWrite - 1) / kPodWrite));
-#define TOPO_POD_WRITE(J)                                                                          \
-    hipLaunchKernelGGL((k_pod_write<TP, J>), grid, dim3(kPodWrite), 0, s, n, S, m, u, coef, ldc, vsq, \
-                       rtol, info, phi, ldphi)
-    if (jbound <= 8) TOPO_POD_WRITE(8);
-    else if (jbound <= 16) TOPO_POD_WRITE(16);
-    else if (jbound <= 32) TOPO_POD_WRITE(32);
-    else TOPO_POD_WRITE(kPodMaxL + 1);
+#define TOPO_POD_WRITE(J)                                                                                  \
+    hipLaunchKernelGGL((k_pod_write<TP, J>), grid, dim3(kPodWrite), 0, s, n, S, m, u, coef, vsq, rtol, info, \
+                       phi, ldphi)
+    switch (ldc) {
+        case 8: TOPO_POD_WRITE(8); break;
+        case 16: TOPO_POD_WRITE(16); break;
+        case 24: TOPO_POD_WRITE(24); break;
+        case 32: TOPO_POD_WRITE(32); break;
+        case 40: TOPO_POD_WRITE(40); break;
+        default: TOPO_POD_WRITE(kPodMaxL + 1); break;
+    }
 #undef TOPO_POD_WRITE
 }
 
@@ -423,7 +498,7 @@ int topo_pod_basis(topo_ctx* ctx, int64_t n, int32_t L, const double* S, const d
     TOPO_HIP(hipSetDevice(ctx->device));
     hipStream_t s = (hipStream_t)stream;
     const int m = count;
-    const int ldc = u ? nb + 1 : std::max(nb, 1);
+    const int ldc = pod_ldc(jbound);
     const int nch = pod_chunks(n);
     Arena ar;
     double *part, *gu, *vsq, *coef, *infod;
@@ -442,7 +517,7 @@ int topo_pod_basis(topo_ctx* ctx, int64_t n, int32_t L, const double* S, const d
         launch_chunk_sum(m + 1, nch, 1, (const double*)part, PodVecOut{gu}, s);
         TOPO_CHECK_LAUNCH();
     }
-    hipLaunchKernelGGL(k_pod_eig, dim3(1), dim3(256), 0, s, m, (int)L, G, u ? (const double*)gu : nullptr,
+    hipLaunchKernelGGL(k_pod_eig, dim3(1), dim3(kEigThreads), 0, s, m, (int)L, G, u ? (const double*)gu : nullptr,
                        (int)nmax, rtol, coef, ldc, sigma, info);
     TOPO_CHECK_LAUNCH();
     if (u) {
@@ -453,9 +528,9 @@ int topo_pod_basis(topo_ctx* ctx, int64_t n, int32_t L, const double* S, const d
         TOPO_CHECK_LAUNCH();
     }
     if (phi_fp32)
-        launch_pod_write<float>(jbound, n, S, m, u, coef, ldc, vsq, rtol, info, (float*)phi, ldphi, s);
+        launch_pod_write<float>(ldc, n, S, m, u, coef, vsq, rtol, info, (float*)phi, ldphi, s);
     else
-        launch_pod_write<double>(jbound, n, S, m, u, coef, ldc, vsq, rtol, info, (double*)phi, ldphi, s);
+        launch_pod_write<double>(ldc, n, S, m, u, coef, vsq, rtol, info, (double*)phi, ldphi, s);
     TOPO_CHECK_LAUNCH();
     void* pin;
     rc = pinned_host(ctx, sizeof(PodInfo), &pin);
