@@ -23,8 +23,8 @@ EXPORTED = (
     "topo_ctx_workspace_bytes", "topo_element_stiffness", "topo_element_factor", "topo_apply",
     "topo_hdm_solve",
     "topo_hdm_gradient", "topo_rom_build", "topo_rom_solve", "topo_rom_estimate",
-    "topo_rom_gradient", "topo_pod_push", "topo_pod_basis", "topo_ctx_set_timing",
-    "topo_ctx_kernel_time",
+    "topo_rom_gradient", "topo_pod_push", "topo_pod_basis", "topo_filter_forward",
+    "topo_filter_adjoint", "topo_ctx_set_timing", "topo_ctx_kernel_time",
 )
 POD_MAX_WINDOW = 48
 
@@ -73,6 +73,10 @@ _SIGS = {
                                     _P, _P, _P, C.c_int32, _P, _P, _P, _P, C.c_int32, _P]),
     "topo_rom_gradient": (C.c_int, [_P, C.POINTER(TopoMesh), _P, C.c_int32, C.c_int32, C.c_int32,
                                     _P, _P, C.c_int32, _P, _P, _P]),
+    "topo_filter_forward": (C.c_int, [_P, C.POINTER(TopoMesh), C.c_double, _P, C.c_int32, _P, _P,
+                                      C.c_double, C.c_int32, C.POINTER(C.c_int32), _P]),
+    "topo_filter_adjoint": (C.c_int, [_P, C.POINTER(TopoMesh), C.c_double, _P, C.c_int32, _P, _P,
+                                      C.c_double, C.c_int32, C.POINTER(C.c_int32), _P]),
     "topo_pod_push": (C.c_int, [_P, C.c_int64, C.c_int32, _P, _P, C.POINTER(C.c_int32),
                                 C.POINTER(C.c_int32), _P, _P]),
     "topo_pod_basis": (C.c_int, [_P, C.c_int64, C.c_int32, _P, _P, C.c_int32, _P, C.c_int32,
@@ -326,6 +330,32 @@ class Context:
                                         _stream(stream))
         self._check(rc, "rom_gradient")
         return dJ
+
+    def _filter(self, fn, name, mesh, r, x, out, nodal, rtol, maxit, stream):
+        import torch
+        if x.dim() == 1:
+            x = x.unsqueeze(0)
+        B = x.shape[0]
+        if out is None:
+            out = torch.empty_like(x, dtype=torch.float64)
+        m = make_mesh(mesh)
+        its = C.c_int32(0)
+        rc = fn(self.h, C.byref(m), float(r), _ptr(x, torch.float64, "input"), B,
+                _ptr(out, torch.float64, "output"), _ptr(nodal, torch.float64, "nodal"), float(rtol),
+                int(maxit), C.byref(its), _stream(stream))
+        self._check(rc, name)
+        return out, its.value
+
+    def filter_forward(self, mesh, r, psi, rho=None, phi=None, rtol=1e-12, maxit=20000, stream=None):
+        """rho*(psi) through the Helmholtz filter [B][N_e]; returns (rho, iterations)
+        (topo_filter_forward)."""
+        return self._filter(self.lib.topo_filter_forward, "filter_forward", mesh, r, psi, rho, phi, rtol,
+                            maxit, stream)
+
+    def filter_adjoint(self, mesh, r, v, g=None, mu=None, rtol=1e-12, maxit=20000, stream=None):
+        """(d rho*/d psi)^T v [B][N_e]; returns (g, iterations) (topo_filter_adjoint)."""
+        return self._filter(self.lib.topo_filter_adjoint, "filter_adjoint", mesh, r, v, g, mu, rtol, maxit,
+                            stream)
 
     def pod_push(self, S, G, state, u, stream=None):
         """Push snapshot u into the window (S [L][n], G [L][L], state = [count, next]

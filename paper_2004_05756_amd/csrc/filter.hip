@@ -1,0 +1,414 @@
+// Helmholtz density filter (Sec. 2.2) and the gradient through it (Sec. 2.4), on the
+// nodal grid of the mesh, for B fields at once:
+//   forward:  H phi = b(psi), b_n = w sum_{e ∋ n} psi_e,   rho_e = (1/nen) sum_{n ∈ e} phi_n
+//   adjoint:  H mu = q(v),    q_n = (1/nen) sum_{e ∋ n} v_e,  g_e = w sum_{n ∈ e} mu_n
+// with H = sum_e (r^2 L_e + M_e) the bilinear / trilinear Helmholtz matrix (homogeneous
+// Neumann boundary: no constrained node), w = |Omega_e| / nen the entries of b_e.  H is
+// symmetric, so both directions use one solver: Jacobi-PCG in float64, matrix-free.
+//
+// PCG per iteration: k_helm_apply forms the new direction p = z + beta p_old on the fly
+// for its stencil (p double-buffered) and q = H p with per-block partials of p . q;
+// k_helm_update advances x, r and z = D^-1 r with partials of r . z and r . r.  All sums
+// are deterministic chunk sums.  A field stops (its step length becomes 0) at the first
+// check, every kHelmCheck iterations, where |r| <= rtol |b|; the checks fall at the same
+// iterations whatever the batch, so a field's result does not depend on its batch.
+#include <algorithm>
+#include <cmath>
+
+#include "internal.hpp"
+#include "reduce.hpp"
+
+namespace topo {
+
+constexpr int kHelmBlock = 256;
+constexpr int kHelmCheck = 8;
+constexpr int kHelmScal = 8;  // per-field scalars: rz_prev, rz, pq, rr, bb, active, -, -
+
+// Element Helmholtz matrix of the box element, local node order x fastest.
+struct HelmElem {
+    double H[64];
+    double w;     // |Omega_e| / nen
+    double diag;  // H[0][0]: every diagonal entry is equal on a box
+};
+
+// H_e = r^2 (sum over axes of K1 (x) M1 (x) M1 with K1 on that axis) + M1 (x) M1 (x) M1,
+// K1 = [1 -1; -1 1] / h, M1 = h [2 1; 1 2] / 6 per axis.
+static HelmElem helm_element(const topo_mesh& m, double r) {
+    HelmElem E{};
+    const int d = m.dim, nen = 1 << d;
+    double K1[3][2][2], M1[3][2][2];
+    for (int a = 0; a < d; ++a) {
+        const double h = m.h[a];
+        for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < 2; ++j) {
+                K1[a][i][j] = (i == j ? 1.0 : -1.0) / h;
+                M1[a][i][j] = h * (i == j ? 2.0 : 1.0) / 6.0;
+            }
+    }
+    double vol = 1.0;
+    for (int a = 0; a < d; ++a) vol *= m.h[a];
+    for (int li = 0; li < nen; ++li)
+        for (int lj = 0; lj < nen; ++lj) {
+            double mass = 1.0, lap = 0.0;
+            for (int a = 0; a < d; ++a) mass *= M1[a][(li >> a) & 1][(lj >> a) & 1];
+            for (int a = 0; a < d; ++a) {
+                double t = K1[a][(li >> a) & 1][(lj >> a) & 1];
+                for (int c = 0; c < d; ++c)
+                    if (c != a) t *= M1[c][(li >> c) & 1][(lj >> c) & 1];
+                lap += t;
+            }
+            E.H[li * nen + lj] = r * r * lap + mass;
+        }
+    E.w = vol / nen;
+    E.diag = E.H[0];
+    return E;
+}
+
+__device__ __forceinline__ void node_ijk(const Grid& g, int n, int& i, int& j, int& k) {
+    i = n % g.nx1;
+    const int t = n / g.nx1;
+    j = t % g.ny1;
+    k = t / g.ny1;
+}
+
+// out[b][n] = scale * sum over the elements around node n of in[b][e].
+template <int DIM>
+__global__ __launch_bounds__(kHelmBlock) void k_helm_e2n(Grid g, const double* __restrict__ in, double scale,
+                                                         double* __restrict__ out) {
+    const int n = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (n >= g.n_nodes) return;
+    const double* ib = in + (size_t)blockIdx.y * g.n_elems;
+    int i, j, k;
+    node_ijk(g, n, i, j, k);
+    double s = 0.0;
+    for (int c = (DIM == 3 ? -1 : 0); c <= 0; ++c)
+        for (int b = -1; b <= 0; ++b)
+            for (int a = -1; a <= 0; ++a) {
+                const int ei = i + a, ej = j + b, ek = k + c;
+                if (ei < 0 || ej < 0 || ek < 0 || ei >= g.nx || ej >= g.ny || ek >= g.nz) continue;
+                s += ib[ei + g.nx * (ej + g.ny * ek)];
+            }
+    out[(size_t)blockIdx.y * g.n_nodes + n] = scale * s;
+}
+
+// out[b][e] = scale * sum over the nodes of element e of in[b][n].
+template <int DIM>
+__global__ __launch_bounds__(kHelmBlock) void k_helm_n2e(Grid g, const double* __restrict__ in, double scale,
+                                                         double* __restrict__ out) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= g.n_elems) return;
+    const double* ib = in + (size_t)blockIdx.y * g.n_nodes;
+    const int i = e % g.nx, t = e / g.nx, j = t % g.ny, k = t / g.ny;
+    double s = 0.0;
+    for (int c = 0; c < (DIM == 3 ? 2 : 1); ++c)
+        for (int b = 0; b < 2; ++b)
+            for (int a = 0; a < 2; ++a) s += ib[(i + a) + g.nx1 * ((j + b) + g.ny1 * (k + c))];
+    out[(size_t)blockIdx.y * g.n_elems + e] = scale * s;
+}
+
+// (H x)_n for the node (i, j, k): sum over the elements around it of their row.
+template <int DIM, typename F>
+__device__ __forceinline__ double helm_row(const Grid& g, const HelmElem& E, int i, int j, int k, F x) {
+    constexpr int nen = 1 << DIM;
+    double s = 0.0;
+    for (int c = (DIM == 3 ? -1 : 0); c <= 0; ++c)
+        for (int b = -1; b <= 0; ++b)
+            for (int a = -1; a <= 0; ++a) {
+                const int ei = i + a, ej = j + b, ek = k + c;
+                if (ei < 0 || ej < 0 || ek < 0 || ei >= g.nx || ej >= g.ny || ek >= g.nz) continue;
+                const int li = (-a) + 2 * (-b) + 4 * (-c);
+                const double* row = E.H + li * nen;
+#pragma unroll
+                for (int lj = 0; lj < nen; ++lj) {
+                    const int ni = ei + (lj & 1), nj = ej + ((lj >> 1) & 1), nk = ek + ((lj >> 2) & 1);
+                    s += row[lj] * x(ni + g.nx1 * (nj + g.ny1 * nk));
+                }
+            }
+    return s;
+}
+
+// Jacobi diagonal of node (i, j, k): the number of elements around it times H_e[0][0].
+__device__ __forceinline__ double helm_dinv(const Grid& g, double diag, int i, int j, int k) {
+    const int cx = (i > 0) + (i < g.nx), cy = (j > 0) + (j < g.ny);
+    const int cz = g.dim == 3 ? (k > 0) + (k < g.nz) : 1;
+    return 1.0 / (diag * (cx * cy * cz));
+}
+
+// x = 0, r = bvec, z = D^-1 r, p_old = 0; partials of r . z and r . r.
+template <int DIM>
+__global__ __launch_bounds__(kHelmBlock) void k_helm_init(Grid g, double diag, const double* __restrict__ bvec,
+                                                          double* __restrict__ x, double* __restrict__ r,
+                                                          double* __restrict__ z, double* __restrict__ p,
+                                                          double* __restrict__ part) {
+    __shared__ double lds[32];
+    const int n = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const size_t o = (size_t)blockIdx.y * g.n_nodes + n;
+    double v[2] = {0.0, 0.0};
+    if (n < g.n_nodes) {
+        int i, j, k;
+        node_ijk(g, n, i, j, k);
+        const double rb = bvec[o];
+        const double zz = rb * helm_dinv(g, diag, i, j, k);
+        x[o] = 0.0;
+        r[o] = rb;
+        z[o] = zz;
+        p[o] = 0.0;
+        v[0] = rb * zz;
+        v[1] = rb * rb;
+    }
+    block_reduce<2>(v, lds);
+    if (threadIdx.x == 0) {
+        double* pb = part + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * 2;
+        pb[0] = v[0];
+        pb[1] = v[1];
+    }
+}
+
+// p_new = z + beta p_old (beta = rz / rz_prev, 0 on the first iteration), q = H p_new,
+// partials of p_new . q.
+template <int DIM>
+__global__ __launch_bounds__(kHelmBlock) void k_helm_apply(Grid g, HelmElem E, int first,
+                                                           const double* __restrict__ sc,
+                                                           const double* __restrict__ z,
+                                                           const double* __restrict__ pold,
+                                                           double* __restrict__ pnew, double* __restrict__ q,
+                                                           double* __restrict__ part) {
+    __shared__ double lds[32];
+    const int n = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const size_t base = (size_t)blockIdx.y * g.n_nodes;
+    const double* s = sc + blockIdx.y * kHelmScal;
+    const double beta = first || s[0] == 0.0 ? 0.0 : s[1] / s[0];  // r = 0 exactly: restart
+    const double* zb = z + base;
+    const double* pb = pold + base;
+    double v[1] = {0.0};
+    if (n < g.n_nodes) {
+        int i, j, k;
+        node_ijk(g, n, i, j, k);
+        const double pn = zb[n] + beta * pb[n];
+        const double qn = helm_row<DIM>(g, E, i, j, k, [&](int m) { return zb[m] + beta * pb[m]; });
+        pnew[base + n] = pn;
+        q[base + n] = qn;
+        v[0] = pn * qn;
+    }
+    block_reduce<1>(v, lds);
+    if (threadIdx.x == 0) part[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = v[0];
+}
+
+// For an active field alpha = rz / pq, x += alpha p, r -= alpha q, z = D^-1 r; partials
+// of r . z and r . r.
+template <int DIM>
+__global__ __launch_bounds__(kHelmBlock) void k_helm_update(Grid g, double diag, const double* __restrict__ sc,
+                                                            const double* __restrict__ p,
+                                                            const double* __restrict__ q,
+                                                            double* __restrict__ x, double* __restrict__ r,
+                                                            double* __restrict__ z, double* __restrict__ part) {
+    __shared__ double lds[32];
+    const int n = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const size_t o = (size_t)blockIdx.y * g.n_nodes + n;
+    const double* s = sc + blockIdx.y * kHelmScal;
+    // A stopped field is left as it is (its p may be meaningless, e.g. 0/0 for b = 0).
+    const bool active = s[5] != 0.0;
+    const double alpha = s[2] != 0.0 ? s[1] / s[2] : 0.0;
+    double v[2] = {0.0, 0.0};
+    if (n < g.n_nodes) {
+        double rn = r[o], zn = z[o];
+        if (active) {
+            int i, j, k;
+            node_ijk(g, n, i, j, k);
+            x[o] += alpha * p[o];
+            rn -= alpha * q[o];
+            zn = rn * helm_dinv(g, diag, i, j, k);
+            r[o] = rn;
+            z[o] = zn;
+        }
+        v[0] = rn * zn;
+        v[1] = rn * rn;
+    }
+    block_reduce<2>(v, lds);
+    if (threadIdx.x == 0) {
+        double* pb = part + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * 2;
+        pb[0] = v[0];
+        pb[1] = v[1];
+    }
+}
+
+// Chunk-sum epilogues into the per-field scalars.
+struct HelmInitOut {  // entries: r.z, r.r of the initial residual
+    double* sc;
+    __device__ void operator()(int b, int e, double s) const {
+        double* f = sc + b * kHelmScal;
+        if (e == 0) {
+            f[0] = s;
+            f[1] = s;
+        } else {
+            f[3] = s;
+            f[4] = s;
+            f[5] = s > 0.0 ? 1.0 : 0.0;
+        }
+    }
+};
+struct HelmPqOut {
+    double* sc;
+    __device__ void operator()(int b, int, double s) const { sc[b * kHelmScal + 2] = s; }
+};
+struct HelmRzOut {  // entries: new r.z, r.r
+    double* sc;
+    __device__ void operator()(int b, int e, double s) const {
+        double* f = sc + b * kHelmScal;
+        if (e == 0) {
+            f[0] = f[1];
+            f[1] = s;
+        } else {
+            f[3] = s;
+        }
+    }
+};
+
+// Stop the fields that have converged; count the active ones; record iterations.
+__global__ void k_helm_check(int B, double rtol2, int it, double* __restrict__ sc, int* __restrict__ nactive,
+                             int* __restrict__ iters) {
+    if (threadIdx.x != 0) return;
+    int cnt = 0;
+    for (int b = 0; b < B; ++b) {
+        double* f = sc + b * kHelmScal;
+        if (f[5] == 0.0) continue;
+        iters[b] = it;
+        if (f[3] <= rtol2 * f[4]) f[5] = 0.0;
+        else ++cnt;
+    }
+    *nactive = cnt;
+}
+
+// Workspace of one filter call (all pieces from one arena: every arena starts at the
+// beginning of the context's workspace).
+struct HelmWork {
+    double *bvec, *x, *r, *z, *p0, *p1, *q, *part, *sc;
+    int *cnt, *its;
+};
+
+template <int DIM>
+static int helm_solve(Ctx* ctx, const Grid& g, const HelmElem& E, int B, const HelmWork& w, double rtol,
+                      int maxit, int* iters_out, hipStream_t s) {
+    const int nb = grid_blocks(g.n_nodes, kHelmBlock);
+    double *x = w.x, *r = w.r, *z = w.z, *p0 = w.p0, *p1 = w.p1, *q = w.q, *part = w.part, *sc = w.sc;
+    int *cnt = w.cnt, *its = w.its;
+    const double* bvec = w.bvec;
+    void* pin;
+    int rc = pinned_host(ctx, sizeof(int) * std::max(B, 1), &pin);
+    if (rc) return rc;
+    const dim3 grid(nb, B);
+    hipLaunchKernelGGL(k_helm_init<DIM>, grid, dim3(kHelmBlock), 0, s, g, E.diag, bvec, x, r, z, p0, part);
+    TOPO_CHECK_LAUNCH();
+    launch_chunk_sum(2, nb, B, (const double*)part, HelmInitOut{sc}, s);
+    TOPO_CHECK_LAUNCH();
+    TOPO_HIP(hipMemsetAsync(its, 0, sizeof(int) * B, s));
+    double* pold = p0;
+    double* pnew = p1;
+    int it = 0, active = B;
+    while (it < maxit && active > 0) {
+        hipLaunchKernelGGL(k_helm_apply<DIM>, grid, dim3(kHelmBlock), 0, s, g, E, it == 0 ? 1 : 0,
+                           (const double*)sc, (const double*)z, (const double*)pold, pnew, q, part);
+        TOPO_CHECK_LAUNCH();
+        launch_chunk_sum(1, nb, B, (const double*)part, HelmPqOut{sc}, s);
+        TOPO_CHECK_LAUNCH();
+        hipLaunchKernelGGL(k_helm_update<DIM>, grid, dim3(kHelmBlock), 0, s, g, E.diag, (const double*)sc,
+                           (const double*)pnew, (const double*)q, x, r, z, part);
+        TOPO_CHECK_LAUNCH();
+        launch_chunk_sum(2, nb, B, (const double*)part, HelmRzOut{sc}, s);
+        TOPO_CHECK_LAUNCH();
+        std::swap(pold, pnew);
+        ++it;
+        if (it % kHelmCheck == 0 || it == maxit) {
+            hipLaunchKernelGGL(k_helm_check, dim3(1), dim3(1), 0, s, B, rtol * rtol, it, sc, cnt, its);
+            TOPO_CHECK_LAUNCH();
+            TOPO_HIP(hipMemcpyAsync(pin, cnt, sizeof(int), hipMemcpyDeviceToHost, s));
+            TOPO_HIP(hipStreamSynchronize(s));
+            active = *(const int*)pin;
+        }
+    }
+    TOPO_HIP(hipMemcpyAsync(pin, its, sizeof(int) * B, hipMemcpyDeviceToHost, s));
+    TOPO_HIP(hipStreamSynchronize(s));
+    int mx = 0;
+    for (int b = 0; b < B; ++b) mx = std::max(mx, ((const int*)pin)[b]);
+    if (iters_out) *iters_out = mx;
+    if (active > 0) return set_error(ctx, TOPO_ENOCONV, "filter solve: %d field(s) not converged in %d iterations",
+                                     active, maxit);
+    return TOPO_OK;
+}
+
+static int filter_checks(Ctx* ctx, const topo_mesh* mesh, double r, const void* in, int B, const void* out,
+                         double rtol, int maxit) {
+    int rc = validate_mesh(ctx, mesh);
+    if (rc) return rc;
+    if (!in || !out) return set_error(ctx, TOPO_EINVAL, "null pointer argument");
+    if (B < 1) return set_error(ctx, TOPO_EINVAL, "B must be >= 1");
+    if (!(r >= 0.0) || !std::isfinite(r)) return set_error(ctx, TOPO_EINVAL, "filter length r must be >= 0");
+    if (!(rtol > 0.0 && rtol < 1.0)) return set_error(ctx, TOPO_EINVAL, "rtol must lie in (0, 1)");
+    if (maxit < 1) return set_error(ctx, TOPO_EINVAL, "maxit must be >= 1");
+    return TOPO_OK;
+}
+
+template <int DIM>
+static int filter_run(Ctx* ctx, const topo_mesh& m, double r, const double* in, int B, double* out,
+                      double* nodal, double rtol, int maxit, int* iters, bool adjoint, hipStream_t s) {
+    const Grid g = make_grid(m);
+    const HelmElem E = helm_element(m, r);
+    constexpr int nen = 1 << DIM;
+    const int nb = grid_blocks(g.n_nodes, kHelmBlock);
+    const size_t NV = (size_t)B * g.n_nodes;
+    HelmWork w{};
+    Arena ar;
+    ar.take(&w.bvec, NV);
+    if (!nodal) ar.take(&w.x, NV);
+    ar.take(&w.r, NV);
+    ar.take(&w.z, NV);
+    ar.take(&w.p0, NV);
+    ar.take(&w.p1, NV);
+    ar.take(&w.q, NV);
+    ar.take(&w.part, (size_t)B * nb * 2);
+    ar.take(&w.sc, (size_t)B * kHelmScal);
+    ar.take(&w.cnt, 1);
+    ar.take(&w.its, (size_t)B);
+    int rc = ar.commit(ctx, s);
+    if (rc) return rc;
+    if (nodal) w.x = nodal;
+    const dim3 gn(nb, B), ge(grid_blocks(g.n_elems, kHelmBlock), B);
+    hipLaunchKernelGGL(k_helm_e2n<DIM>, gn, dim3(kHelmBlock), 0, s, g, in, adjoint ? 1.0 / nen : E.w, w.bvec);
+    TOPO_CHECK_LAUNCH();
+    rc = helm_solve<DIM>(ctx, g, E, B, w, rtol, maxit, iters, s);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_helm_n2e<DIM>, ge, dim3(kHelmBlock), 0, s, g, (const double*)w.x,
+                       adjoint ? E.w : 1.0 / nen, out);
+    TOPO_CHECK_LAUNCH();
+    return TOPO_OK;
+}
+
+}  // namespace topo
+
+using namespace topo;
+
+extern "C" {
+
+int topo_filter_forward(topo_ctx* ctx, const topo_mesh* mesh, double r, const double* psi, int32_t B,
+                        double* rho, double* phi, double rtol, int32_t maxit, int32_t* iters, void* stream) {
+    if (!ctx) return TOPO_EINVAL;
+    int rc = filter_checks(ctx, mesh, r, psi, B, rho, rtol, maxit);
+    if (rc) return rc;
+    TOPO_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    return mesh->dim == 2 ? filter_run<2>(ctx, *mesh, r, psi, B, rho, phi, rtol, maxit, iters, false, s)
+                          : filter_run<3>(ctx, *mesh, r, psi, B, rho, phi, rtol, maxit, iters, false, s);
+}
+
+int topo_filter_adjoint(topo_ctx* ctx, const topo_mesh* mesh, double r, const double* v, int32_t B, double* g,
+                        double* mu, double rtol, int32_t maxit, int32_t* iters, void* stream) {
+    if (!ctx) return TOPO_EINVAL;
+    int rc = filter_checks(ctx, mesh, r, v, B, g, rtol, maxit);
+    if (rc) return rc;
+    TOPO_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    return mesh->dim == 2 ? filter_run<2>(ctx, *mesh, r, v, B, g, mu, rtol, maxit, iters, true, s)
+                          : filter_run<3>(ctx, *mesh, r, v, B, g, mu, rtol, maxit, iters, true, s);
+}
+
+}  // extern "C"

@@ -102,7 +102,6 @@ def test_gradient_through_the_filter_matches_finite_differences(mk):
         pm[e] -= d
         fd = (J(pp) - J(pm)) / (2 * d)
         assert abs(fd - g[e]) <= 1e-6 * abs(g).max(), (e, fd, g[e])
-    assert np.all(g < 0)  # more material anywhere lowers the compliance
 
 
 def test_large_radius_gives_the_volume_mean():
