@@ -302,6 +302,32 @@ def basis_leg(torch, binding, ctx, n, L=20, nmax=19):
     return out
 
 
+def filter_leg(torch, ctx, mesh, R=3.0, rtol=1e-10):
+    """Helmholtz filter forward (psi -> rho) and adjoint (dJ/drho -> dJ/dpsi) on one field
+    of the mesh with filter radius R (in element sizes; r = 2 sqrt(3) R): wall time per
+    call (each synchronises) and PCG iterations."""
+    dev = torch.device("cuda", 0)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(13)
+    r = 2.0 * np.sqrt(3.0) * R
+    psi = torch.rand((1, mesh.n_elems), device=dev, dtype=torch.float64, generator=gen)
+    v = -torch.rand((1, mesh.n_elems), device=dev, dtype=torch.float64, generator=gen)
+    rho = torch.empty_like(psi)
+    g = torch.empty_like(psi)
+    out = {"R": R, "rtol": rtol, "n_nodes": mesh.n_nodes}
+    for name, fn, x, y in (("forward", ctx.filter_forward, psi, rho), ("adjoint", ctx.filter_adjoint, v, g)):
+        fn(mesh, r, x, y, rtol=rtol)
+        lat = []
+        for _ in range(5):
+            t0 = time.perf_counter()
+            _, its = fn(mesh, r, x, y, rtol=rtol)
+            lat.append(time.perf_counter() - t0)
+        lat.sort()
+        out[f"{name}_ms"] = 1e3 * lat[len(lat) // 2]
+        out[f"{name}_iters"] = its
+    return out
+
+
 def bridge_leg(torch, W, binding, FP64, MIXED):
     """The 192x96x96 bridge: the 16-field batched apply in both precisions (kernel time
     from the library's sampled events, algorithmic bytes, HBM fraction) and one HDM
@@ -348,6 +374,7 @@ def bridge_leg(torch, W, binding, FP64, MIXED):
         out[f"hdm_{name}"] = {"ms": 1e3 * dt_s, "iters": inf["iters"], "fp64_fallback": inf["fp64_fallback"],
                               "rel_resid": inf["rel_resid"], "dof_iter_per_s": m.n_dofs * inf["iters"] / dt_s}
     out["basis"] = basis_leg(torch, binding, ctx, m.n_dofs)
+    out["filter"] = filter_leg(torch, ctx, m)
     ctx.close()
     return out
 
@@ -530,6 +557,7 @@ def main():
                                     "p99_ms": 1e3 * lat[min(len(lat) - 1, int(0.99 * len(lat)))],
                                     "Jk": float(Je[0]), "resnorm": float(rn[0])}
         extra["basis"] = basis_leg(torch, binding, ctx, m.n_dofs)
+        extra["filter"] = filter_leg(torch, ctx, m)
         out["extra"] = extra
         out["rom"] = {nm: {q: extra[f"rom_{nm}"][q] for q in ("evals_per_s", "p50_ms", "p99_ms")}
                       for nm in ("mixed", "fp64")}
