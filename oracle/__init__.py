@@ -20,6 +20,7 @@ from .fem import (element_stiffness, constitutive, element_dofs, simp_alpha,
 from .rom import rom_operator, rom_load, rom_solve, rom_residual, rom_eval, rom_gradient
 from .basis import pod, gram_schmidt_step, basis_update, SnapshotWindow
 from .filter import filter_forward, filter_adjoint, filter_radius, helmholtz_assemble
+from . import tr
 
 __all__ = [
     "element_stiffness", "constitutive", "element_dofs", "simp_alpha", "simp_alpha_prime",
