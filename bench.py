@@ -328,6 +328,23 @@ def filter_leg(torch, ctx, mesh, R=3.0, rtol=1e-10):
     return out
 
 
+def tr_leg(torch, ctx, problem, R=3.0, vf=0.5, iters=3):
+    """Three outer iterations of the ROM trust-region method (residual trust region,
+    window 5, n_max 4) from the uniform design on the workload mesh: wall time, HDM
+    solves, model evaluations and the compliance at each centre."""
+    from paper_2004_05756_amd.trdriver import TrustRegion
+    r = 2.0 * np.sqrt(3.0) * R
+    drv = TrustRegion(ctx, problem.mesh, problem.mask, problem.f, r, vf, kind="res", window=5, nmax=4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, hist = drv.run(iters=iters, tau=0.1)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"R": R, "vf": vf, "outer_iters": iters, "seconds": dt, "hdm_solves": drv.hdm_solves,
+            "model_evals": drv.model_evals, "J_centres": [h["J"] for h in hist],
+            "accepted": [bool(h["accepted"]) for h in hist], "ratios": [float(h["ratio"]) for h in hist]}
+
+
 def bridge_leg(torch, W, binding, FP64, MIXED):
     """The 192x96x96 bridge: the 16-field batched apply in both precisions (kernel time
     from the library's sampled events, algorithmic bytes, HBM fraction) and one HDM
@@ -558,6 +575,7 @@ def main():
                                     "Jk": float(Je[0]), "resnorm": float(rn[0])}
         extra["basis"] = basis_leg(torch, binding, ctx, m.n_dofs)
         extra["filter"] = filter_leg(torch, ctx, m)
+        extra["trust_region"] = tr_leg(torch, ctx, cfg.problem)
         out["extra"] = extra
         out["rom"] = {nm: {q: extra[f"rom_{nm}"][q] for q in ("evals_per_s", "p50_ms", "p99_ms")}
                       for nm in ("mixed", "fp64")}
