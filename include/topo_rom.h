@@ -230,6 +230,10 @@ int topo_rom_gradient(topo_ctx* ctx, const topo_mesh* mesh, const void* phi,
 
 /* ---- Helmholtz density filter (Sec. 2.2) and the gradient through it (Sec. 2.4) ---- */
 
+/* Flag of topo_filter_forward / topo_filter_adjoint: the nodal array (phi or mu, then
+ * not NULL) holds an initial guess on entry. */
+#define TOPO_FILTER_WARM 1
+
 /* Filtered densities rho = rho*(psi) for B fields (Sec. 2.2): the nodal Helmholtz
  * problem H phi = b(psi) with H = sum_e (r^2 L_e + M_e) (bilinear / trilinear Laplacian
  * and mass matrices of the mesh's box element, homogeneous Neumann boundary, no node
@@ -239,12 +243,14 @@ int topo_rom_gradient(topo_ctx* ctx, const topo_mesh* mesh, const void* phi,
  *   psi [B][N_e] f64 device, rho [B][N_e] f64 device out, phi [B][N_n] f64 device out
  *   (may be NULL; nodal values, node = i + (nx+1)(j + (ny+1)k)).
  * Solved by Jacobi-PCG in float64 to |b - H phi| <= rtol |b| per field (maxit
- * iterations at most); *iters (host, may be NULL) gets the largest iteration count.
+ * iterations at most), from phi = 0, or from the phi passed in with flags ==
+ * TOPO_FILTER_WARM (a field whose guess already meets the tolerance takes no
+ * iteration); *iters (host, may be NULL) gets the largest iteration count.
  * Synchronises (convergence checks).  Errors: TOPO_EINVAL (mesh, null pointer, B < 1,
  * r < 0, rtol outside (0, 1), maxit < 1), TOPO_ENOCONV, TOPO_ENOMEM, TOPO_EDEVICE. */
 int topo_filter_forward(topo_ctx* ctx, const topo_mesh* mesh, double r, const double* psi,
                         int32_t B, double* rho, double* phi, double rtol, int32_t maxit,
-                        int32_t* iters, void* stream);
+                        int32_t flags, int32_t* iters, void* stream);
 
 /* Gradient through the filter (Sec. 2.4 and the adjoint derivation of the appendix):
  * g = (d rho* / d psi)^T v for B fields, i.e. H mu = q(v) with q_n = (1 / nen) sum of v_e
@@ -255,7 +261,7 @@ int topo_filter_forward(topo_ctx* ctx, const topo_mesh* mesh, double r, const do
  * as topo_filter_forward.  Synchronises.  Same errors. */
 int topo_filter_adjoint(topo_ctx* ctx, const topo_mesh* mesh, double r, const double* v,
                         int32_t B, double* g, double* mu, double rtol, int32_t maxit,
-                        int32_t* iters, void* stream);
+                        int32_t flags, int32_t* iters, void* stream);
 
 /* ---- Reduced basis at a trust-region centre (Sec. 4.2) --------------------------- */
 

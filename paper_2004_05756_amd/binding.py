@@ -74,9 +74,9 @@ _SIGS = {
     "topo_rom_gradient": (C.c_int, [_P, C.POINTER(TopoMesh), _P, C.c_int32, C.c_int32, C.c_int32,
                                     _P, _P, C.c_int32, _P, _P, _P]),
     "topo_filter_forward": (C.c_int, [_P, C.POINTER(TopoMesh), C.c_double, _P, C.c_int32, _P, _P,
-                                      C.c_double, C.c_int32, C.POINTER(C.c_int32), _P]),
+                                      C.c_double, C.c_int32, C.c_int32, C.POINTER(C.c_int32), _P]),
     "topo_filter_adjoint": (C.c_int, [_P, C.POINTER(TopoMesh), C.c_double, _P, C.c_int32, _P, _P,
-                                      C.c_double, C.c_int32, C.POINTER(C.c_int32), _P]),
+                                      C.c_double, C.c_int32, C.c_int32, C.POINTER(C.c_int32), _P]),
     "topo_pod_push": (C.c_int, [_P, C.c_int64, C.c_int32, _P, _P, C.POINTER(C.c_int32),
                                 C.POINTER(C.c_int32), _P, _P]),
     "topo_pod_basis": (C.c_int, [_P, C.c_int64, C.c_int32, _P, _P, C.c_int32, _P, C.c_int32,
@@ -331,7 +331,7 @@ class Context:
         self._check(rc, "rom_gradient")
         return dJ
 
-    def _filter(self, fn, name, mesh, r, x, out, nodal, rtol, maxit, stream):
+    def _filter(self, fn, name, mesh, r, x, out, nodal, rtol, maxit, warm, stream):
         import torch
         if x.dim() == 1:
             x = x.unsqueeze(0)
@@ -342,20 +342,22 @@ class Context:
         its = C.c_int32(0)
         rc = fn(self.h, C.byref(m), float(r), _ptr(x, torch.float64, "input"), B,
                 _ptr(out, torch.float64, "output"), _ptr(nodal, torch.float64, "nodal"), float(rtol),
-                int(maxit), C.byref(its), _stream(stream))
+                int(maxit), 1 if (warm and nodal is not None) else 0, C.byref(its), _stream(stream))
         self._check(rc, name)
         return out, its.value
 
-    def filter_forward(self, mesh, r, psi, rho=None, phi=None, rtol=1e-12, maxit=20000, stream=None):
-        """rho*(psi) through the Helmholtz filter [B][N_e]; returns (rho, iterations)
-        (topo_filter_forward)."""
+    def filter_forward(self, mesh, r, psi, rho=None, phi=None, rtol=1e-12, maxit=20000, warm=False,
+                       stream=None):
+        """rho*(psi) through the Helmholtz filter [B][N_e]; returns (rho, iterations).  With
+        warm=True, phi holds the initial guess (topo_filter_forward)."""
         return self._filter(self.lib.topo_filter_forward, "filter_forward", mesh, r, psi, rho, phi, rtol,
-                            maxit, stream)
+                            maxit, warm, stream)
 
-    def filter_adjoint(self, mesh, r, v, g=None, mu=None, rtol=1e-12, maxit=20000, stream=None):
-        """(d rho*/d psi)^T v [B][N_e]; returns (g, iterations) (topo_filter_adjoint)."""
+    def filter_adjoint(self, mesh, r, v, g=None, mu=None, rtol=1e-12, maxit=20000, warm=False, stream=None):
+        """(d rho*/d psi)^T v [B][N_e]; returns (g, iterations).  With warm=True, mu holds
+        the initial guess (topo_filter_adjoint)."""
         return self._filter(self.lib.topo_filter_adjoint, "filter_adjoint", mesh, r, v, g, mu, rtol, maxit,
-                            stream)
+                            warm, stream)
 
     def pod_push(self, S, G, state, u, stream=None):
         """Push snapshot u into the window (S [L][n], G [L][L], state = [count, next]

@@ -21,14 +21,16 @@
 namespace topo {
 
 constexpr int kHelmBlock = 256;
+constexpr int kHelmNPT = 4;   // nodes per thread in the PCG kernels (fewer block partials)
 constexpr int kHelmCheck = 8;
 constexpr int kHelmScal = 8;  // per-field scalars: rz_prev, rz, pq, rr, bb, active, -, -
 
 // Element Helmholtz matrix of the box element, local node order x fastest.
 struct HelmElem {
     double H[64];
-    double w;     // |Omega_e| / nen
-    double diag;  // H[0][0]: every diagonal entry is equal on a box
+    double S[27];  // assembled stencil of an interior node, offset (di, dj, dk) at 13 + di + 3 dj + 9 dk
+    double w;      // |Omega_e| / nen
+    double diag;   // H[0][0]: every diagonal entry is equal on a box
 };
 
 // H_e = r^2 (sum over axes of K1 (x) M1 (x) M1 with K1 on that axis) + M1 (x) M1 (x) M1,
@@ -61,6 +63,16 @@ static HelmElem helm_element(const topo_mesh& m, double r) {
         }
     E.w = vol / nen;
     E.diag = E.H[0];
+    // interior node: the rows of its 2^d elements, summed per neighbour offset
+    for (int c = (d == 3 ? -1 : 0); c <= 0; ++c)
+        for (int b = -1; b <= 0; ++b)
+            for (int a = -1; a <= 0; ++a) {
+                const int li = (-a) + 2 * (-b) + 4 * (-c);
+                for (int lj = 0; lj < nen; ++lj) {
+                    const int di = a + (lj & 1), dj = b + ((lj >> 1) & 1), dk = c + ((lj >> 2) & 1);
+                    E.S[13 + di + 3 * dj + 9 * dk] += E.H[li * nen + lj];
+                }
+            }
     return E;
 }
 
@@ -134,33 +146,45 @@ __device__ __forceinline__ double helm_dinv(const Grid& g, double diag, int i, i
     return 1.0 / (diag * (cx * cy * cz));
 }
 
-// x = 0, r = bvec, z = D^-1 r, p_old = 0; partials of r . z and r . r.
+// r = bvec - H x (warm: x holds the initial guess) or x = 0, r = bvec; z = D^-1 r,
+// p_old = 0; partials of r . z, r . r and b . b.
 template <int DIM>
-__global__ __launch_bounds__(kHelmBlock) void k_helm_init(Grid g, double diag, const double* __restrict__ bvec,
-                                                          double* __restrict__ x, double* __restrict__ r,
-                                                          double* __restrict__ z, double* __restrict__ p,
-                                                          double* __restrict__ part) {
-    __shared__ double lds[32];
-    const int n = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    const size_t o = (size_t)blockIdx.y * g.n_nodes + n;
-    double v[2] = {0.0, 0.0};
-    if (n < g.n_nodes) {
+__global__ __launch_bounds__(kHelmBlock) void k_helm_init(Grid g, HelmElem E, int warm,
+                                                          const double* __restrict__ bvec, double* __restrict__ x,
+                                                          double* __restrict__ r, double* __restrict__ z,
+                                                          double* __restrict__ p, double* __restrict__ part) {
+    __shared__ double lds[48];
+    const int n0 = xcd_block(blockIdx.x, gridDim.x) * (kHelmNPT * kHelmBlock) + threadIdx.x;
+    const size_t base = (size_t)blockIdx.y * g.n_nodes;
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int t = 0; t < kHelmNPT; ++t) {
+        const int n = n0 + t * kHelmBlock;
+        if (n >= g.n_nodes) break;
+        const size_t o = base + n;
         int i, j, k;
         node_ijk(g, n, i, j, k);
-        const double rb = bvec[o];
-        const double zz = rb * helm_dinv(g, diag, i, j, k);
-        x[o] = 0.0;
+        const double bb = bvec[o];
+        double rb = bb;
+        if (warm) {
+            const double* xb = x + base;
+            rb -= helm_row<DIM>(g, E, i, j, k, [&](int m) { return xb[m]; });
+        } else {
+            x[o] = 0.0;
+        }
+        const double zz = rb * helm_dinv(g, E.diag, i, j, k);
         r[o] = rb;
         z[o] = zz;
         p[o] = 0.0;
-        v[0] = rb * zz;
-        v[1] = rb * rb;
+        v[0] += rb * zz;
+        v[1] += rb * rb;
+        v[2] += bb * bb;
     }
-    block_reduce<2>(v, lds);
+    block_reduce<3>(v, lds);
     if (threadIdx.x == 0) {
-        double* pb = part + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * 2;
+        double* pb = part + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * 3;
         pb[0] = v[0];
         pb[1] = v[1];
+        pb[2] = v[2];
     }
 }
 
@@ -174,21 +198,39 @@ __global__ __launch_bounds__(kHelmBlock) void k_helm_apply(Grid g, HelmElem E, i
                                                            double* __restrict__ pnew, double* __restrict__ q,
                                                            double* __restrict__ part) {
     __shared__ double lds[32];
-    const int n = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const int n0 = xcd_block(blockIdx.x, gridDim.x) * (kHelmNPT * kHelmBlock) + threadIdx.x;
     const size_t base = (size_t)blockIdx.y * g.n_nodes;
     const double* s = sc + blockIdx.y * kHelmScal;
     const double beta = first || s[0] == 0.0 ? 0.0 : s[1] / s[0];  // r = 0 exactly: restart
     const double* zb = z + base;
     const double* pb = pold + base;
     double v[1] = {0.0};
-    if (n < g.n_nodes) {
+    for (int t = 0; t < kHelmNPT; ++t) {
+        const int n = n0 + t * kHelmBlock;
+        if (n >= g.n_nodes) break;
         int i, j, k;
         node_ijk(g, n, i, j, k);
         const double pn = zb[n] + beta * pb[n];
-        const double qn = helm_row<DIM>(g, E, i, j, k, [&](int m) { return zb[m] + beta * pb[m]; });
+        const bool interior = i > 0 && i < g.nx && j > 0 && j < g.ny && (DIM == 2 || (k > 0 && k < g.nz));
+        double qn;
+        if (interior) {  // assembled stencil, linear neighbour offsets
+            const int sy = g.nx1, sz = g.nx1 * g.ny1;
+            qn = 0.0;
+#pragma unroll
+            for (int dk = (DIM == 3 ? -1 : 0); dk <= (DIM == 3 ? 1 : 0); ++dk)
+#pragma unroll
+                for (int dj = -1; dj <= 1; ++dj)
+#pragma unroll
+                    for (int di = -1; di <= 1; ++di) {
+                        const int m = n + di + sy * dj + sz * dk;
+                        qn += E.S[13 + di + 3 * dj + 9 * dk] * (zb[m] + beta * pb[m]);
+                    }
+        } else {
+            qn = helm_row<DIM>(g, E, i, j, k, [&](int m) { return zb[m] + beta * pb[m]; });
+        }
         pnew[base + n] = pn;
         q[base + n] = qn;
-        v[0] = pn * qn;
+        v[0] += pn * qn;
     }
     block_reduce<1>(v, lds);
     if (threadIdx.x == 0) part[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = v[0];
@@ -203,14 +245,16 @@ __global__ __launch_bounds__(kHelmBlock) void k_helm_update(Grid g, double diag,
                                                             double* __restrict__ x, double* __restrict__ r,
                                                             double* __restrict__ z, double* __restrict__ part) {
     __shared__ double lds[32];
-    const int n = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    const size_t o = (size_t)blockIdx.y * g.n_nodes + n;
+    const int n0 = xcd_block(blockIdx.x, gridDim.x) * (kHelmNPT * kHelmBlock) + threadIdx.x;
     const double* s = sc + blockIdx.y * kHelmScal;
     // A stopped field is left as it is (its p may be meaningless, e.g. 0/0 for b = 0).
     const bool active = s[5] != 0.0;
     const double alpha = s[2] != 0.0 ? s[1] / s[2] : 0.0;
     double v[2] = {0.0, 0.0};
-    if (n < g.n_nodes) {
+    for (int t = 0; t < kHelmNPT; ++t) {
+        const int n = n0 + t * kHelmBlock;
+        if (n >= g.n_nodes) break;
+        const size_t o = (size_t)blockIdx.y * g.n_nodes + n;
         double rn = r[o], zn = z[o];
         if (active) {
             int i, j, k;
@@ -221,8 +265,8 @@ __global__ __launch_bounds__(kHelmBlock) void k_helm_update(Grid g, double diag,
             r[o] = rn;
             z[o] = zn;
         }
-        v[0] = rn * zn;
-        v[1] = rn * rn;
+        v[0] += rn * zn;
+        v[1] += rn * rn;
     }
     block_reduce<2>(v, lds);
     if (threadIdx.x == 0) {
@@ -233,20 +277,27 @@ __global__ __launch_bounds__(kHelmBlock) void k_helm_update(Grid g, double diag,
 }
 
 // Chunk-sum epilogues into the per-field scalars.
-struct HelmInitOut {  // entries: r.z, r.r of the initial residual
+struct HelmInitOut {  // entries: r.z, r.r of the initial residual, b.b
     double* sc;
     __device__ void operator()(int b, int e, double s) const {
         double* f = sc + b * kHelmScal;
         if (e == 0) {
             f[0] = s;
             f[1] = s;
-        } else {
+        } else if (e == 1) {
             f[3] = s;
+        } else {
             f[4] = s;
-            f[5] = s > 0.0 ? 1.0 : 0.0;
         }
     }
 };
+// A field starts active unless its initial residual already meets the tolerance.
+__global__ void k_helm_start(int B, double rtol2, double* __restrict__ sc) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    double* f = sc + b * kHelmScal;
+    f[5] = (f[4] > 0.0 && f[3] > rtol2 * f[4]) ? 1.0 : 0.0;
+}
 struct HelmPqOut {
     double* sc;
     __device__ void operator()(int b, int, double s) const { sc[b * kHelmScal + 2] = s; }
@@ -287,9 +338,9 @@ struct HelmWork {
 };
 
 template <int DIM>
-static int helm_solve(Ctx* ctx, const Grid& g, const HelmElem& E, int B, const HelmWork& w, double rtol,
-                      int maxit, int* iters_out, hipStream_t s) {
-    const int nb = grid_blocks(g.n_nodes, kHelmBlock);
+static int helm_solve(Ctx* ctx, const Grid& g, const HelmElem& E, int B, const HelmWork& w, bool warm,
+                      double rtol, int maxit, int* iters_out, hipStream_t s) {
+    const int nb = grid_blocks(g.n_nodes, kHelmNPT * kHelmBlock);
     double *x = w.x, *r = w.r, *z = w.z, *p0 = w.p0, *p1 = w.p1, *q = w.q, *part = w.part, *sc = w.sc;
     int *cnt = w.cnt, *its = w.its;
     const double* bvec = w.bvec;
@@ -297,14 +348,24 @@ static int helm_solve(Ctx* ctx, const Grid& g, const HelmElem& E, int B, const H
     int rc = pinned_host(ctx, sizeof(int) * std::max(B, 1), &pin);
     if (rc) return rc;
     const dim3 grid(nb, B);
-    hipLaunchKernelGGL(k_helm_init<DIM>, grid, dim3(kHelmBlock), 0, s, g, E.diag, bvec, x, r, z, p0, part);
+    hipLaunchKernelGGL(k_helm_init<DIM>, grid, dim3(kHelmBlock), 0, s, g, E, warm ? 1 : 0, bvec, x, r, z, p0,
+                       part);
     TOPO_CHECK_LAUNCH();
-    launch_chunk_sum(2, nb, B, (const double*)part, HelmInitOut{sc}, s);
+    launch_chunk_sum(3, nb, B, (const double*)part, HelmInitOut{sc}, s);
+    TOPO_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_helm_start, dim3((B + 63) / 64), dim3(64), 0, s, B, rtol * rtol, sc);
     TOPO_CHECK_LAUNCH();
     TOPO_HIP(hipMemsetAsync(its, 0, sizeof(int) * B, s));
     double* pold = p0;
     double* pnew = p1;
     int it = 0, active = B;
+    if (warm) {  // a guess that already meets the tolerance needs no iteration
+        hipLaunchKernelGGL(k_helm_check, dim3(1), dim3(1), 0, s, B, rtol * rtol, 0, sc, cnt, its);
+        TOPO_CHECK_LAUNCH();
+        TOPO_HIP(hipMemcpyAsync(pin, cnt, sizeof(int), hipMemcpyDeviceToHost, s));
+        TOPO_HIP(hipStreamSynchronize(s));
+        active = *(const int*)pin;
+    }
     while (it < maxit && active > 0) {
         hipLaunchKernelGGL(k_helm_apply<DIM>, grid, dim3(kHelmBlock), 0, s, g, E, it == 0 ? 1 : 0,
                            (const double*)sc, (const double*)z, (const double*)pold, pnew, q, part);
@@ -350,11 +411,11 @@ static int filter_checks(Ctx* ctx, const topo_mesh* mesh, double r, const void* 
 
 template <int DIM>
 static int filter_run(Ctx* ctx, const topo_mesh& m, double r, const double* in, int B, double* out,
-                      double* nodal, double rtol, int maxit, int* iters, bool adjoint, hipStream_t s) {
+                      double* nodal, bool warm, double rtol, int maxit, int* iters, bool adjoint, hipStream_t s) {
     const Grid g = make_grid(m);
     const HelmElem E = helm_element(m, r);
     constexpr int nen = 1 << DIM;
-    const int nb = grid_blocks(g.n_nodes, kHelmBlock);
+    const int nb = grid_blocks(g.n_nodes, kHelmNPT * kHelmBlock);
     const size_t NV = (size_t)B * g.n_nodes;
     HelmWork w{};
     Arena ar;
@@ -365,17 +426,17 @@ static int filter_run(Ctx* ctx, const topo_mesh& m, double r, const double* in, 
     ar.take(&w.p0, NV);
     ar.take(&w.p1, NV);
     ar.take(&w.q, NV);
-    ar.take(&w.part, (size_t)B * nb * 2);
+    ar.take(&w.part, (size_t)B * nb * 3);
     ar.take(&w.sc, (size_t)B * kHelmScal);
     ar.take(&w.cnt, 1);
     ar.take(&w.its, (size_t)B);
     int rc = ar.commit(ctx, s);
     if (rc) return rc;
     if (nodal) w.x = nodal;
-    const dim3 gn(nb, B), ge(grid_blocks(g.n_elems, kHelmBlock), B);
+    const dim3 gn(grid_blocks(g.n_nodes, kHelmBlock), B), ge(grid_blocks(g.n_elems, kHelmBlock), B);
     hipLaunchKernelGGL(k_helm_e2n<DIM>, gn, dim3(kHelmBlock), 0, s, g, in, adjoint ? 1.0 / nen : E.w, w.bvec);
     TOPO_CHECK_LAUNCH();
-    rc = helm_solve<DIM>(ctx, g, E, B, w, rtol, maxit, iters, s);
+    rc = helm_solve<DIM>(ctx, g, E, B, w, warm && nodal, rtol, maxit, iters, s);
     if (rc) return rc;
     hipLaunchKernelGGL(k_helm_n2e<DIM>, ge, dim3(kHelmBlock), 0, s, g, (const double*)w.x,
                        adjoint ? E.w : 1.0 / nen, out);
@@ -390,25 +451,28 @@ using namespace topo;
 extern "C" {
 
 int topo_filter_forward(topo_ctx* ctx, const topo_mesh* mesh, double r, const double* psi, int32_t B,
-                        double* rho, double* phi, double rtol, int32_t maxit, int32_t* iters, void* stream) {
+                        double* rho, double* phi, double rtol, int32_t maxit, int32_t flags, int32_t* iters,
+                        void* stream) {
     if (!ctx) return TOPO_EINVAL;
     int rc = filter_checks(ctx, mesh, r, psi, B, rho, rtol, maxit);
     if (rc) return rc;
     TOPO_HIP(hipSetDevice(ctx->device));
     hipStream_t s = (hipStream_t)stream;
-    return mesh->dim == 2 ? filter_run<2>(ctx, *mesh, r, psi, B, rho, phi, rtol, maxit, iters, false, s)
-                          : filter_run<3>(ctx, *mesh, r, psi, B, rho, phi, rtol, maxit, iters, false, s);
+    const bool warm = (flags & TOPO_FILTER_WARM) != 0;
+    return mesh->dim == 2 ? filter_run<2>(ctx, *mesh, r, psi, B, rho, phi, warm, rtol, maxit, iters, false, s)
+                          : filter_run<3>(ctx, *mesh, r, psi, B, rho, phi, warm, rtol, maxit, iters, false, s);
 }
 
 int topo_filter_adjoint(topo_ctx* ctx, const topo_mesh* mesh, double r, const double* v, int32_t B, double* g,
-                        double* mu, double rtol, int32_t maxit, int32_t* iters, void* stream) {
+                        double* mu, double rtol, int32_t maxit, int32_t flags, int32_t* iters, void* stream) {
     if (!ctx) return TOPO_EINVAL;
     int rc = filter_checks(ctx, mesh, r, v, B, g, rtol, maxit);
     if (rc) return rc;
     TOPO_HIP(hipSetDevice(ctx->device));
     hipStream_t s = (hipStream_t)stream;
-    return mesh->dim == 2 ? filter_run<2>(ctx, *mesh, r, v, B, g, mu, rtol, maxit, iters, true, s)
-                          : filter_run<3>(ctx, *mesh, r, v, B, g, mu, rtol, maxit, iters, true, s);
+    const bool warm = (flags & TOPO_FILTER_WARM) != 0;
+    return mesh->dim == 2 ? filter_run<2>(ctx, *mesh, r, v, B, g, mu, warm, rtol, maxit, iters, true, s)
+                          : filter_run<3>(ctx, *mesh, r, v, B, g, mu, warm, rtol, maxit, iters, true, s);
 }
 
 }  // extern "C"

@@ -19,6 +19,9 @@ design vector psi and takes the optimiser's decisions:
   when very successful, ratio >= 0.75);
 * the trust region is the ROM residual norm (kind "res") or the distance to the centre
   (kind "dist"); Delta_0 = tau |f| or tau |psi_0|.
+
+Consecutive filter solves start from the previous nodal solution (the designs the
+optimiser evaluates one after the other are close).
 """
 from __future__ import annotations
 
@@ -68,11 +71,17 @@ class TrustRegion:
         self.k = 0
         self.model_evals = 0
         self.hdm_solves = 0
+        # nodal filter solutions of the last forward / adjoint solve, warm starts for the next
+        self.phi_nodal = torch.zeros((1, mesh.n_nodes), dtype=torch.float64, device=self.dev)
+        self.mu_nodal = torch.zeros((1, mesh.n_nodes), dtype=torch.float64, device=self.dev)
+        self.warm_phi = self.warm_mu = False
 
     # -- evaluations on the device -------------------------------------------------
     def _rho(self, psi):
         x = self.torch.as_tensor(np.ascontiguousarray(psi, dtype=np.float64)[None]).to(self.dev)
-        rho, _ = self.ctx.filter_forward(self.mesh, self.r, x, rtol=self.filter_rtol)
+        rho, _ = self.ctx.filter_forward(self.mesh, self.r, x, phi=self.phi_nodal, rtol=self.filter_rtol,
+                                         warm=self.warm_phi)
+        self.warm_phi = True
         return rho
 
     def hdm(self, psi):
@@ -101,7 +110,9 @@ class TrustRegion:
         g = None
         if want_grad:
             dJ = self.ctx.rom_gradient(self.mesh, self.phi, self.k, self.mask, rho, y)
-            gd, _ = self.ctx.filter_adjoint(self.mesh, self.r, dJ, rtol=self.filter_rtol)
+            gd, _ = self.ctx.filter_adjoint(self.mesh, self.r, dJ, mu=self.mu_nodal, rtol=self.filter_rtol,
+                                            warm=self.warm_mu)
+            self.warm_mu = True
             g = gd[0].cpu().numpy()
         return float(Jk[0]), rn, g
 
