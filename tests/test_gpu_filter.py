@@ -29,10 +29,11 @@ def _kappa(m, r):
     return lmax / lmin
 
 
-CASES = [  # (mesh, filter radius R)
+CASES = [  # (mesh, filter radius R); the last two have non-square elements
     (W.mbb2d(13, 7).mesh, 1.2), (W.mbb2d(60, 20).mesh, 2.0), (W.mbb2d(60, 20).mesh, 0.0),
     (W.cantilever2d(37, 11).mesh, 3.5), (W.cantilever3d(7, 5, 3).mesh, 1.0),
     (W.bridge3d(6, 4, 5).mesh, 2.5), (W.mbb2d(1, 1).mesh, 1.0),
+    (W.Mesh(nel=(17, 9), h=(0.5, 2.0)), 1.5), (W.Mesh(nel=(6, 5, 7), h=(0.7, 1.3, 0.4)), 0.8),
 ]
 
 

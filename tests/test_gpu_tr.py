@@ -40,3 +40,22 @@ def test_trust_region_driver_matches_oracle(kind, tau, nmax, move, window):
         assert hd["basis"] == ho["basis"]
     assert np.abs(psi_d - psi_o).max() <= 1e-6
     assert psi_d.sum() <= prob.vmax + 1e-9 and psi_d.min() >= 0 and psi_d.max() <= 1
+
+
+def test_trust_region_driver_mixed_precision_takes_the_oracle_decisions():
+    """The same run with the mixed-precision HDM solve and FP32 reduced build on the
+    device: the compliance is still residual-corrected and the reduced model refined, so
+    the decisions and radii match the FP64 oracle and J agrees to 1e-6."""
+    torch_cuda()
+    from paper_2004_05756_amd import MIXED
+    from paper_2004_05756_amd.trdriver import TrustRegion
+    p = W.mbb2d(24, 8)
+    r = F.filter_radius(1.5)
+    prob = T.Problem(p.mesh, p.mask, p.f, r, 0.5)
+    _, hist_o = T.rom_tr(prob, kind="dist", tau=0.1, iters=3, window=4, nmax=3)
+    drv = TrustRegion(ctx(), p.mesh, p.mask, p.f, r, 0.5, kind="dist", window=4, nmax=3, prec=MIXED)
+    _, hist_d = drv.run(iters=3, tau=0.1)
+    assert [h["accepted"] for h in hist_d] == [h["accepted"] for h in hist_o]
+    for hd, ho in zip(hist_d, hist_o):
+        assert abs(hd["delta"] - ho["delta"]) <= 1e-12 * ho["delta"]
+        assert abs(hd["J"] - ho["J"]) <= 1e-6 * ho["J"]
