@@ -8,8 +8,9 @@
 //
 // PCG per iteration: k_helm_apply forms the new direction p = z + beta p_old on the fly
 // for its stencil (p double-buffered) and q = H p with per-block partials of p . q;
-// k_helm_update advances x, r and z = D^-1 r with partials of r . z and r . r.  All sums
-// are deterministic chunk sums.  A field stops (its step length becomes 0) at the first
+// k_helm_update advances x, r and z = D^-1 r with partials of r . z and r . r.  Each
+// kernel sums the partials it needs itself, every block in the same fixed order (the
+// r . z partials are kept for two iterations, by parity, for beta).  A field stops (its step length becomes 0) at the first
 // check, every kHelmCheck iterations, where |r| <= rtol |b|; the checks fall at the same
 // iterations whatever the batch, so a field's result does not depend on its batch.
 #include <algorithm>
@@ -23,7 +24,7 @@ namespace topo {
 constexpr int kHelmBlock = 256;
 constexpr int kHelmNPT = 4;   // nodes per thread in the PCG kernels (fewer block partials)
 constexpr int kHelmCheck = 8;
-constexpr int kHelmScal = 8;  // per-field scalars: rz_prev, rz, pq, rr, bb, active, -, -
+constexpr int kHelmScal = 8;  // per-field scalars: rz (two copies), -, rr, bb, active, -, - (initial values)
 
 // Element Helmholtz matrix of the box element, local node order x fastest.
 struct HelmElem {
@@ -152,7 +153,8 @@ template <int DIM>
 __global__ __launch_bounds__(kHelmBlock) void k_helm_init(Grid g, HelmElem E, int warm,
                                                           const double* __restrict__ bvec, double* __restrict__ x,
                                                           double* __restrict__ r, double* __restrict__ z,
-                                                          double* __restrict__ p, double* __restrict__ part) {
+                                                          double* __restrict__ p, double* __restrict__ part,
+                                                          double* __restrict__ prz, double* __restrict__ prr) {
     __shared__ double lds[48];
     const int n0 = xcd_block(blockIdx.x, gridDim.x) * (kHelmNPT * kHelmBlock) + threadIdx.x;
     const size_t base = (size_t)blockIdx.y * g.n_nodes;
@@ -181,10 +183,13 @@ __global__ __launch_bounds__(kHelmBlock) void k_helm_init(Grid g, HelmElem E, in
     }
     block_reduce<3>(v, lds);
     if (threadIdx.x == 0) {
-        double* pb = part + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * 3;
+        const size_t bi = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
+        double* pb = part + bi * 3;
         pb[0] = v[0];
         pb[1] = v[1];
         pb[2] = v[2];
+        prz[bi] = v[0];
+        prr[bi] = v[1];
     }
 }
 
@@ -192,16 +197,22 @@ __global__ __launch_bounds__(kHelmBlock) void k_helm_init(Grid g, HelmElem E, in
 // partials of p_new . q.
 template <int DIM>
 __global__ __launch_bounds__(kHelmBlock) void k_helm_apply(Grid g, HelmElem E, int first,
-                                                           const double* __restrict__ sc,
+                                                           const double* __restrict__ rz_cur,
+                                                           const double* __restrict__ rz_prev,
                                                            const double* __restrict__ z,
                                                            const double* __restrict__ pold,
                                                            double* __restrict__ pnew, double* __restrict__ q,
-                                                           double* __restrict__ part) {
+                                                           double* __restrict__ ppq) {
     __shared__ double lds[32];
-    const int n0 = xcd_block(blockIdx.x, gridDim.x) * (kHelmNPT * kHelmBlock) + threadIdx.x;
+    const int nb = gridDim.x;
+    const int n0 = xcd_block(blockIdx.x, nb) * (kHelmNPT * kHelmBlock) + threadIdx.x;
     const size_t base = (size_t)blockIdx.y * g.n_nodes;
-    const double* s = sc + blockIdx.y * kHelmScal;
-    const double beta = first || s[0] == 0.0 ? 0.0 : s[1] / s[0];  // r = 0 exactly: restart
+    double beta = 0.0;
+    if (!first) {  // every block sums the partials in the same order
+        const double rc = block_sum_array(rz_cur + (size_t)blockIdx.y * nb, nb, lds);
+        const double rp = block_sum_array(rz_prev + (size_t)blockIdx.y * nb, nb, lds);
+        beta = rp == 0.0 ? 0.0 : rc / rp;  // r = 0 exactly: restart
+    }
     const double* zb = z + base;
     const double* pb = pold + base;
     double v[1] = {0.0};
@@ -233,23 +244,28 @@ __global__ __launch_bounds__(kHelmBlock) void k_helm_apply(Grid g, HelmElem E, i
         v[0] += pn * qn;
     }
     block_reduce<1>(v, lds);
-    if (threadIdx.x == 0) part[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = v[0];
+    if (threadIdx.x == 0) ppq[(size_t)blockIdx.y * nb + blockIdx.x] = v[0];
 }
 
 // For an active field alpha = rz / pq, x += alpha p, r -= alpha q, z = D^-1 r; partials
 // of r . z and r . r.
 template <int DIM>
 __global__ __launch_bounds__(kHelmBlock) void k_helm_update(Grid g, double diag, const double* __restrict__ sc,
+                                                            const double* __restrict__ rz_cur,
+                                                            const double* __restrict__ ppq,
                                                             const double* __restrict__ p,
                                                             const double* __restrict__ q,
                                                             double* __restrict__ x, double* __restrict__ r,
-                                                            double* __restrict__ z, double* __restrict__ part) {
+                                                            double* __restrict__ z, double* __restrict__ rz_new,
+                                                            double* __restrict__ rr_new) {
     __shared__ double lds[32];
-    const int n0 = xcd_block(blockIdx.x, gridDim.x) * (kHelmNPT * kHelmBlock) + threadIdx.x;
-    const double* s = sc + blockIdx.y * kHelmScal;
+    const int nb = gridDim.x;
+    const int n0 = xcd_block(blockIdx.x, nb) * (kHelmNPT * kHelmBlock) + threadIdx.x;
     // A stopped field is left as it is (its p may be meaningless, e.g. 0/0 for b = 0).
-    const bool active = s[5] != 0.0;
-    const double alpha = s[2] != 0.0 ? s[1] / s[2] : 0.0;
+    const bool active = sc[blockIdx.y * kHelmScal + 5] != 0.0;
+    const double rz = block_sum_array(rz_cur + (size_t)blockIdx.y * nb, nb, lds);
+    const double pq = block_sum_array(ppq + (size_t)blockIdx.y * nb, nb, lds);
+    const double alpha = pq != 0.0 ? rz / pq : 0.0;
     double v[2] = {0.0, 0.0};
     for (int t = 0; t < kHelmNPT; ++t) {
         const int n = n0 + t * kHelmBlock;
@@ -270,13 +286,12 @@ __global__ __launch_bounds__(kHelmBlock) void k_helm_update(Grid g, double diag,
     }
     block_reduce<2>(v, lds);
     if (threadIdx.x == 0) {
-        double* pb = part + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * 2;
-        pb[0] = v[0];
-        pb[1] = v[1];
+        rz_new[(size_t)blockIdx.y * nb + blockIdx.x] = v[0];
+        rr_new[(size_t)blockIdx.y * nb + blockIdx.x] = v[1];
     }
 }
 
-// Chunk-sum epilogues into the per-field scalars.
+// Chunk-sum epilogue of the initial residual into the per-field scalars.
 struct HelmInitOut {  // entries: r.z, r.r of the initial residual, b.b
     double* sc;
     __device__ void operator()(int b, int e, double s) const {
@@ -298,42 +313,29 @@ __global__ void k_helm_start(int B, double rtol2, double* __restrict__ sc) {
     double* f = sc + b * kHelmScal;
     f[5] = (f[4] > 0.0 && f[3] > rtol2 * f[4]) ? 1.0 : 0.0;
 }
-struct HelmPqOut {
-    double* sc;
-    __device__ void operator()(int b, int, double s) const { sc[b * kHelmScal + 2] = s; }
-};
-struct HelmRzOut {  // entries: new r.z, r.r
-    double* sc;
-    __device__ void operator()(int b, int e, double s) const {
-        double* f = sc + b * kHelmScal;
-        if (e == 0) {
-            f[0] = f[1];
-            f[1] = s;
-        } else {
-            f[3] = s;
-        }
-    }
-};
 
-// Stop the fields that have converged; count the active ones; record iterations.
-__global__ void k_helm_check(int B, double rtol2, int it, double* __restrict__ sc, int* __restrict__ nactive,
-                             int* __restrict__ iters) {
+// Stop the fields that have converged (|r|^2 <= rtol^2 |b|^2, r.r summed from the block
+// partials); count the active ones; record iterations.  One block per field.
+__global__ __launch_bounds__(kHelmBlock) void k_helm_check(int nb, double rtol2, int it,
+                                                           const double* __restrict__ prr,
+                                                           double* __restrict__ sc, int* __restrict__ nactive,
+                                                           int* __restrict__ iters) {
+    __shared__ double lds[32];
+    const int b = blockIdx.x;
+    const double rr = block_sum_array(prr + (size_t)b * nb, nb, lds);
     if (threadIdx.x != 0) return;
-    int cnt = 0;
-    for (int b = 0; b < B; ++b) {
-        double* f = sc + b * kHelmScal;
-        if (f[5] == 0.0) continue;
-        iters[b] = it;
-        if (f[3] <= rtol2 * f[4]) f[5] = 0.0;
-        else ++cnt;
-    }
-    *nactive = cnt;
+    double* f = sc + b * kHelmScal;
+    if (f[5] == 0.0) return;
+    iters[b] = it;
+    if (rr <= rtol2 * f[4]) f[5] = 0.0;
+    else atomicAdd(nactive, 1);
 }
 
 // Workspace of one filter call (all pieces from one arena: every arena starts at the
 // beginning of the context's workspace).
 struct HelmWork {
     double *bvec, *x, *r, *z, *p0, *p1, *q, *part, *sc;
+    double *prz, *prr, *ppq;  // block partials of r.z and r.r ([2][B][nb], by iteration parity), p.q
     int *cnt, *its;
 };
 
@@ -348,8 +350,9 @@ static int helm_solve(Ctx* ctx, const Grid& g, const HelmElem& E, int B, const H
     int rc = pinned_host(ctx, sizeof(int) * std::max(B, 1), &pin);
     if (rc) return rc;
     const dim3 grid(nb, B);
+    const size_t BN = (size_t)B * nb;
     hipLaunchKernelGGL(k_helm_init<DIM>, grid, dim3(kHelmBlock), 0, s, g, E, warm ? 1 : 0, bvec, x, r, z, p0,
-                       part);
+                       part, w.prz, w.prr);
     TOPO_CHECK_LAUNCH();
     launch_chunk_sum(3, nb, B, (const double*)part, HelmInitOut{sc}, s);
     TOPO_CHECK_LAUNCH();
@@ -359,32 +362,36 @@ static int helm_solve(Ctx* ctx, const Grid& g, const HelmElem& E, int B, const H
     double* pold = p0;
     double* pnew = p1;
     int it = 0, active = B;
-    if (warm) {  // a guess that already meets the tolerance needs no iteration
-        hipLaunchKernelGGL(k_helm_check, dim3(1), dim3(1), 0, s, B, rtol * rtol, 0, sc, cnt, its);
+    auto check = [&](int at) -> int {
+        TOPO_HIP(hipMemsetAsync(cnt, 0, sizeof(int), s));
+        hipLaunchKernelGGL(k_helm_check, dim3(B), dim3(kHelmBlock), 0, s, nb, rtol * rtol, at,
+                           (const double*)(w.prr + (size_t)(at & 1) * BN), sc, cnt, its);
         TOPO_CHECK_LAUNCH();
         TOPO_HIP(hipMemcpyAsync(pin, cnt, sizeof(int), hipMemcpyDeviceToHost, s));
         TOPO_HIP(hipStreamSynchronize(s));
         active = *(const int*)pin;
+        return TOPO_OK;
+    };
+    if (warm) {  // a guess that already meets the tolerance needs no iteration
+        rc = check(0);
+        if (rc) return rc;
     }
     while (it < maxit && active > 0) {
-        hipLaunchKernelGGL(k_helm_apply<DIM>, grid, dim3(kHelmBlock), 0, s, g, E, it == 0 ? 1 : 0,
-                           (const double*)sc, (const double*)z, (const double*)pold, pnew, q, part);
+        const int cur = it & 1;
+        const double* rz_cur = w.prz + (size_t)cur * BN;
+        const double* rz_prev = w.prz + (size_t)(cur ^ 1) * BN;
+        hipLaunchKernelGGL(k_helm_apply<DIM>, grid, dim3(kHelmBlock), 0, s, g, E, it == 0 ? 1 : 0, rz_cur, rz_prev,
+                           (const double*)z, (const double*)pold, pnew, q, w.ppq);
         TOPO_CHECK_LAUNCH();
-        launch_chunk_sum(1, nb, B, (const double*)part, HelmPqOut{sc}, s);
-        TOPO_CHECK_LAUNCH();
-        hipLaunchKernelGGL(k_helm_update<DIM>, grid, dim3(kHelmBlock), 0, s, g, E.diag, (const double*)sc,
-                           (const double*)pnew, (const double*)q, x, r, z, part);
-        TOPO_CHECK_LAUNCH();
-        launch_chunk_sum(2, nb, B, (const double*)part, HelmRzOut{sc}, s);
+        hipLaunchKernelGGL(k_helm_update<DIM>, grid, dim3(kHelmBlock), 0, s, g, E.diag, (const double*)sc, rz_cur,
+                           (const double*)w.ppq, (const double*)pnew, (const double*)q, x, r, z,
+                           w.prz + (size_t)(cur ^ 1) * BN, w.prr + (size_t)(cur ^ 1) * BN);
         TOPO_CHECK_LAUNCH();
         std::swap(pold, pnew);
         ++it;
         if (it % kHelmCheck == 0 || it == maxit) {
-            hipLaunchKernelGGL(k_helm_check, dim3(1), dim3(1), 0, s, B, rtol * rtol, it, sc, cnt, its);
-            TOPO_CHECK_LAUNCH();
-            TOPO_HIP(hipMemcpyAsync(pin, cnt, sizeof(int), hipMemcpyDeviceToHost, s));
-            TOPO_HIP(hipStreamSynchronize(s));
-            active = *(const int*)pin;
+            rc = check(it);
+            if (rc) return rc;
         }
     }
     TOPO_HIP(hipMemcpyAsync(pin, its, sizeof(int) * B, hipMemcpyDeviceToHost, s));
@@ -427,6 +434,9 @@ static int filter_run(Ctx* ctx, const topo_mesh& m, double r, const double* in, 
     ar.take(&w.p1, NV);
     ar.take(&w.q, NV);
     ar.take(&w.part, (size_t)B * nb * 3);
+    ar.take(&w.prz, (size_t)2 * B * nb);
+    ar.take(&w.prr, (size_t)2 * B * nb);
+    ar.take(&w.ppq, (size_t)B * nb);
     ar.take(&w.sc, (size_t)B * kHelmScal);
     ar.take(&w.cnt, 1);
     ar.take(&w.its, (size_t)B);
