@@ -22,7 +22,10 @@
 namespace topo {
 
 constexpr int kHelmBlock = 256;
-constexpr int kHelmNPT = 4;   // nodes per thread in the PCG kernels (fewer block partials)
+// Nodes per thread in the PCG kernels: 4 in 3D (fewer block partials to sum), 1 in 2D
+// (the 2D meshes are small: one node per thread keeps every CU busy).
+template <int DIM>
+constexpr int helm_npt() { return DIM == 3 ? 4 : 1; }
 constexpr int kHelmCheck = 8;
 constexpr int kHelmScal = 8;  // per-field scalars: rz (two copies), -, rr, bb, active, -, - (initial values)
 
@@ -156,10 +159,10 @@ __global__ __launch_bounds__(kHelmBlock) void k_helm_init(Grid g, HelmElem E, in
                                                           double* __restrict__ p, double* __restrict__ part,
                                                           double* __restrict__ prz, double* __restrict__ prr) {
     __shared__ double lds[48];
-    const int n0 = xcd_block(blockIdx.x, gridDim.x) * (kHelmNPT * kHelmBlock) + threadIdx.x;
+    const int n0 = xcd_block(blockIdx.x, gridDim.x) * (helm_npt<DIM>() * kHelmBlock) + threadIdx.x;
     const size_t base = (size_t)blockIdx.y * g.n_nodes;
     double v[3] = {0.0, 0.0, 0.0};
-    for (int t = 0; t < kHelmNPT; ++t) {
+    for (int t = 0; t < helm_npt<DIM>(); ++t) {
         const int n = n0 + t * kHelmBlock;
         if (n >= g.n_nodes) break;
         const size_t o = base + n;
@@ -205,7 +208,7 @@ __global__ __launch_bounds__(kHelmBlock) void k_helm_apply(Grid g, HelmElem E, i
                                                            double* __restrict__ ppq) {
     __shared__ double lds[32];
     const int nb = gridDim.x;
-    const int n0 = xcd_block(blockIdx.x, nb) * (kHelmNPT * kHelmBlock) + threadIdx.x;
+    const int n0 = xcd_block(blockIdx.x, nb) * (helm_npt<DIM>() * kHelmBlock) + threadIdx.x;
     const size_t base = (size_t)blockIdx.y * g.n_nodes;
     double beta = 0.0;
     if (!first) {  // every block sums the partials in the same order
@@ -216,7 +219,7 @@ __global__ __launch_bounds__(kHelmBlock) void k_helm_apply(Grid g, HelmElem E, i
     const double* zb = z + base;
     const double* pb = pold + base;
     double v[1] = {0.0};
-    for (int t = 0; t < kHelmNPT; ++t) {
+    for (int t = 0; t < helm_npt<DIM>(); ++t) {
         const int n = n0 + t * kHelmBlock;
         if (n >= g.n_nodes) break;
         int i, j, k;
@@ -260,14 +263,14 @@ __global__ __launch_bounds__(kHelmBlock) void k_helm_update(Grid g, double diag,
                                                             double* __restrict__ rr_new) {
     __shared__ double lds[32];
     const int nb = gridDim.x;
-    const int n0 = xcd_block(blockIdx.x, nb) * (kHelmNPT * kHelmBlock) + threadIdx.x;
+    const int n0 = xcd_block(blockIdx.x, nb) * (helm_npt<DIM>() * kHelmBlock) + threadIdx.x;
     // A stopped field is left as it is (its p may be meaningless, e.g. 0/0 for b = 0).
     const bool active = sc[blockIdx.y * kHelmScal + 5] != 0.0;
     const double rz = block_sum_array(rz_cur + (size_t)blockIdx.y * nb, nb, lds);
     const double pq = block_sum_array(ppq + (size_t)blockIdx.y * nb, nb, lds);
     const double alpha = pq != 0.0 ? rz / pq : 0.0;
     double v[2] = {0.0, 0.0};
-    for (int t = 0; t < kHelmNPT; ++t) {
+    for (int t = 0; t < helm_npt<DIM>(); ++t) {
         const int n = n0 + t * kHelmBlock;
         if (n >= g.n_nodes) break;
         const size_t o = (size_t)blockIdx.y * g.n_nodes + n;
@@ -342,7 +345,7 @@ struct HelmWork {
 template <int DIM>
 static int helm_solve(Ctx* ctx, const Grid& g, const HelmElem& E, int B, const HelmWork& w, bool warm,
                       double rtol, int maxit, int* iters_out, hipStream_t s) {
-    const int nb = grid_blocks(g.n_nodes, kHelmNPT * kHelmBlock);
+    const int nb = grid_blocks(g.n_nodes, helm_npt<DIM>() * kHelmBlock);
     double *x = w.x, *r = w.r, *z = w.z, *p0 = w.p0, *p1 = w.p1, *q = w.q, *part = w.part, *sc = w.sc;
     int *cnt = w.cnt, *its = w.its;
     const double* bvec = w.bvec;
@@ -422,7 +425,7 @@ static int filter_run(Ctx* ctx, const topo_mesh& m, double r, const double* in, 
     const Grid g = make_grid(m);
     const HelmElem E = helm_element(m, r);
     constexpr int nen = 1 << DIM;
-    const int nb = grid_blocks(g.n_nodes, kHelmNPT * kHelmBlock);
+    const int nb = grid_blocks(g.n_nodes, helm_npt<DIM>() * kHelmBlock);
     const size_t NV = (size_t)B * g.n_nodes;
     HelmWork w{};
     Arena ar;
