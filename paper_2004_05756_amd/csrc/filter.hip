@@ -196,10 +196,20 @@ __global__ __launch_bounds__(kHelmBlock) void k_helm_init(Grid g, HelmElem E, in
     }
 }
 
+// beta = rz / rz_prev from the update's block partials of field blockIdx.y (every block
+// sums them in the same order); 0 on the first iteration or when r = 0 exactly.
+__device__ __forceinline__ double helm_beta(int first, int nrz, const double* rz_cur, const double* rz_prev,
+                                            double* lds) {
+    if (first) return 0.0;
+    const double rc = block_sum_array(rz_cur + (size_t)blockIdx.y * nrz, nrz, lds);
+    const double rp = block_sum_array(rz_prev + (size_t)blockIdx.y * nrz, nrz, lds);
+    return rp == 0.0 ? 0.0 : rc / rp;
+}
+
 // p_new = z + beta p_old (beta = rz / rz_prev, 0 on the first iteration), q = H p_new,
 // partials of p_new . q.
 template <int DIM>
-__global__ __launch_bounds__(kHelmBlock) void k_helm_apply(Grid g, HelmElem E, int first,
+__global__ __launch_bounds__(kHelmBlock) void k_helm_apply(Grid g, HelmElem E, int first, int nrz,
                                                            const double* __restrict__ rz_cur,
                                                            const double* __restrict__ rz_prev,
                                                            const double* __restrict__ z,
@@ -210,12 +220,7 @@ __global__ __launch_bounds__(kHelmBlock) void k_helm_apply(Grid g, HelmElem E, i
     const int nb = gridDim.x;
     const int n0 = xcd_block(blockIdx.x, nb) * (helm_npt<DIM>() * kHelmBlock) + threadIdx.x;
     const size_t base = (size_t)blockIdx.y * g.n_nodes;
-    double beta = 0.0;
-    if (!first) {  // every block sums the partials in the same order
-        const double rc = block_sum_array(rz_cur + (size_t)blockIdx.y * nb, nb, lds);
-        const double rp = block_sum_array(rz_prev + (size_t)blockIdx.y * nb, nb, lds);
-        beta = rp == 0.0 ? 0.0 : rc / rp;  // r = 0 exactly: restart
-    }
+    const double beta = helm_beta(first, nrz, rz_cur, rz_prev, lds);
     const double* zb = z + base;
     const double* pb = pold + base;
     double v[1] = {0.0};
@@ -250,11 +255,96 @@ __global__ __launch_bounds__(kHelmBlock) void k_helm_apply(Grid g, HelmElem E, i
     if (threadIdx.x == 0) ppq[(size_t)blockIdx.y * nb + blockIdx.x] = v[0];
 }
 
+// 3D apply as a march: a block owns a 32 x 8 tile of node columns over a run of z planes
+// and keeps three planes of v = z + beta p_old (tile plus a one-node halo) in LDS, so each
+// value is formed once per block instead of once per neighbour; interior nodes take the
+// 27-point stencil from LDS, boundary nodes the element rows from global memory.  Same
+// outputs as k_helm_apply: p_new and q of the owned nodes, partials of p_new . q.
+constexpr int kHX = 32, kHY = 8, kHLX = kHX + 2, kHLY = kHY + 2;
+struct HelmMarch {
+    int tx, ty, chunks, kz;  // tiles along x and y, z chunks, planes per chunk
+};
+static HelmMarch helm_march(const Grid& g) {
+    HelmMarch h;
+    h.tx = (g.nx1 + kHX - 1) / kHX;
+    h.ty = (g.ny1 + kHY - 1) / kHY;
+    const int target = 1024;  // about four blocks per CU
+    const int want = std::max(1, target / (h.tx * h.ty));
+    h.kz = std::max(2, (g.nz1 + want - 1) / want);
+    h.chunks = (g.nz1 + h.kz - 1) / h.kz;
+    return h;
+}
+
+__global__ __launch_bounds__(kHelmBlock) void k_helm_apply3m(Grid g, HelmElem E, HelmMarch hm, int first, int nrz,
+                                                             const double* __restrict__ rz_cur,
+                                                             const double* __restrict__ rz_prev,
+                                                             const double* __restrict__ z,
+                                                             const double* __restrict__ pold,
+                                                             double* __restrict__ pnew, double* __restrict__ q,
+                                                             double* __restrict__ ppq) {
+    __shared__ double lds[32];
+    __shared__ double pl[3][kHLY][kHLX];
+    const int nb = gridDim.x;
+    const int lb = xcd_block(blockIdx.x, nb);
+    const int txi = lb % hm.tx, t2 = lb / hm.tx, tyi = t2 % hm.ty, ch = t2 / hm.ty;
+    const int i0 = txi * kHX, j0 = tyi * kHY, k0 = ch * hm.kz, k1 = min(k0 + hm.kz, g.nz1);
+    const size_t base = (size_t)blockIdx.y * g.n_nodes;
+    const double beta = helm_beta(first, nrz, rz_cur, rz_prev, lds);
+    const double* zb = z + base;
+    const double* pb = pold + base;
+    const int lx = threadIdx.x % kHX, ly = threadIdx.x / kHX;
+    const int i = i0 + lx, j = j0 + ly;
+    const int sy = g.nx1, sz = g.nx1 * g.ny1;
+    auto load_plane = [&](int k, int slot) {
+        for (int e = threadIdx.x; e < kHLX * kHLY; e += kHelmBlock) {
+            const int ex = e % kHLX, ey = e / kHLX;
+            const int gi = i0 - 1 + ex, gj = j0 - 1 + ey;
+            double val = 0.0;
+            if (k >= 0 && k < g.nz1 && gi >= 0 && gi < g.nx1 && gj >= 0 && gj < g.ny1) {
+                const int m = gi + sy * gj + sz * k;
+                val = zb[m] + beta * pb[m];
+            }
+            pl[slot][ey][ex] = val;
+        }
+    };
+    load_plane(k0 - 1, (k0 + 2) % 3);
+    load_plane(k0, k0 % 3);
+    double v[1] = {0.0};
+    for (int k = k0; k < k1; ++k) {
+        load_plane(k + 1, (k + 1) % 3);
+        __syncthreads();
+        if (i < g.nx1 && j < g.ny1) {
+            const int n = i + sy * j + sz * k;
+            const double pn = pl[k % 3][ly + 1][lx + 1];
+            double qn = 0.0;
+            if (i > 0 && i < g.nx && j > 0 && j < g.ny && k > 0 && k < g.nz) {
+#pragma unroll
+                for (int dk = -1; dk <= 1; ++dk) {
+                    const int slot = (k + dk + 3) % 3;
+#pragma unroll
+                    for (int dj = -1; dj <= 1; ++dj)
+#pragma unroll
+                        for (int di = -1; di <= 1; ++di)
+                            qn += E.S[13 + di + 3 * dj + 9 * dk] * pl[slot][ly + 1 + dj][lx + 1 + di];
+                }
+            } else {
+                qn = helm_row<3>(g, E, i, j, k, [&](int m) { return zb[m] + beta * pb[m]; });
+            }
+            pnew[base + n] = pn;
+            q[base + n] = qn;
+            v[0] += pn * qn;
+        }
+        __syncthreads();  // the oldest plane is overwritten next
+    }
+    block_reduce<1>(v, lds);
+    if (threadIdx.x == 0) ppq[(size_t)blockIdx.y * nb + blockIdx.x] = v[0];
+}
+
 // For an active field alpha = rz / pq, x += alpha p, r -= alpha q, z = D^-1 r; partials
 // of r . z and r . r.
 template <int DIM>
 __global__ __launch_bounds__(kHelmBlock) void k_helm_update(Grid g, double diag, const double* __restrict__ sc,
-                                                            const double* __restrict__ rz_cur,
+                                                            int npq, const double* __restrict__ rz_cur,
                                                             const double* __restrict__ ppq,
                                                             const double* __restrict__ p,
                                                             const double* __restrict__ q,
@@ -267,7 +357,7 @@ __global__ __launch_bounds__(kHelmBlock) void k_helm_update(Grid g, double diag,
     // A stopped field is left as it is (its p may be meaningless, e.g. 0/0 for b = 0).
     const bool active = sc[blockIdx.y * kHelmScal + 5] != 0.0;
     const double rz = block_sum_array(rz_cur + (size_t)blockIdx.y * nb, nb, lds);
-    const double pq = block_sum_array(ppq + (size_t)blockIdx.y * nb, nb, lds);
+    const double pq = block_sum_array(ppq + (size_t)blockIdx.y * npq, npq, lds);
     const double alpha = pq != 0.0 ? rz / pq : 0.0;
     double v[2] = {0.0, 0.0};
     for (int t = 0; t < helm_npt<DIM>(); ++t) {
@@ -354,6 +444,9 @@ static int helm_solve(Ctx* ctx, const Grid& g, const HelmElem& E, int B, const H
     if (rc) return rc;
     const dim3 grid(nb, B);
     const size_t BN = (size_t)B * nb;
+    const HelmMarch hm = helm_march(g);
+    const int nbm = hm.tx * hm.ty * hm.chunks;  // blocks of the 3D march apply
+    const int npq = DIM == 3 ? nbm : nb;        // its partials of p . q per field
     hipLaunchKernelGGL(k_helm_init<DIM>, grid, dim3(kHelmBlock), 0, s, g, E, warm ? 1 : 0, bvec, x, r, z, p0,
                        part, w.prz, w.prr);
     TOPO_CHECK_LAUNCH();
@@ -383,11 +476,15 @@ static int helm_solve(Ctx* ctx, const Grid& g, const HelmElem& E, int B, const H
         const int cur = it & 1;
         const double* rz_cur = w.prz + (size_t)cur * BN;
         const double* rz_prev = w.prz + (size_t)(cur ^ 1) * BN;
-        hipLaunchKernelGGL(k_helm_apply<DIM>, grid, dim3(kHelmBlock), 0, s, g, E, it == 0 ? 1 : 0, rz_cur, rz_prev,
-                           (const double*)z, (const double*)pold, pnew, q, w.ppq);
+        if (DIM == 3)
+            hipLaunchKernelGGL(k_helm_apply3m, dim3(nbm, B), dim3(kHelmBlock), 0, s, g, E, hm, it == 0 ? 1 : 0, nb,
+                               rz_cur, rz_prev, (const double*)z, (const double*)pold, pnew, q, w.ppq);
+        else
+            hipLaunchKernelGGL(k_helm_apply<DIM>, grid, dim3(kHelmBlock), 0, s, g, E, it == 0 ? 1 : 0, nb, rz_cur,
+                               rz_prev, (const double*)z, (const double*)pold, pnew, q, w.ppq);
         TOPO_CHECK_LAUNCH();
-        hipLaunchKernelGGL(k_helm_update<DIM>, grid, dim3(kHelmBlock), 0, s, g, E.diag, (const double*)sc, rz_cur,
-                           (const double*)w.ppq, (const double*)pnew, (const double*)q, x, r, z,
+        hipLaunchKernelGGL(k_helm_update<DIM>, grid, dim3(kHelmBlock), 0, s, g, E.diag, (const double*)sc, npq,
+                           rz_cur, (const double*)w.ppq, (const double*)pnew, (const double*)q, x, r, z,
                            w.prz + (size_t)(cur ^ 1) * BN, w.prr + (size_t)(cur ^ 1) * BN);
         TOPO_CHECK_LAUNCH();
         std::swap(pold, pnew);
@@ -439,7 +536,7 @@ static int filter_run(Ctx* ctx, const topo_mesh& m, double r, const double* in, 
     ar.take(&w.part, (size_t)B * nb * 3);
     ar.take(&w.prz, (size_t)2 * B * nb);
     ar.take(&w.prr, (size_t)2 * B * nb);
-    ar.take(&w.ppq, (size_t)B * nb);
+    ar.take(&w.ppq, (size_t)B * std::max(nb, DIM == 3 ? helm_march(g).tx * helm_march(g).ty * helm_march(g).chunks : 0));
     ar.take(&w.sc, (size_t)B * kHelmScal);
     ar.take(&w.cnt, 1);
     ar.take(&w.its, (size_t)B);
