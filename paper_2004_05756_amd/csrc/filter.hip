@@ -220,36 +220,55 @@ __global__ __launch_bounds__(kHelmBlock) void k_helm_apply(Grid g, HelmElem E, i
     const int nb = gridDim.x;
     const int n0 = xcd_block(blockIdx.x, nb) * (helm_npt<DIM>() * kHelmBlock) + threadIdx.x;
     const size_t base = (size_t)blockIdx.y * g.n_nodes;
-    const double beta = helm_beta(first, nrz, rz_cur, rz_prev, lds);
     const double* zb = z + base;
     const double* pb = pold + base;
     double v[1] = {0.0};
-    for (int t = 0; t < helm_npt<DIM>(); ++t) {
-        const int n = n0 + t * kHelmBlock;
-        if (n >= g.n_nodes) break;
-        int i, j, k;
-        node_ijk(g, n, i, j, k);
-        const double pn = zb[n] + beta * pb[n];
-        const bool interior = i > 0 && i < g.nx && j > 0 && j < g.ny && (DIM == 2 || (k > 0 && k < g.nz));
-        double qn;
-        if (interior) {  // assembled stencil, linear neighbour offsets
-            const int sy = g.nx1, sz = g.nx1 * g.ny1;
-            qn = 0.0;
+    if (DIM == 2) {
+        // one node per thread: its 3 x 3 neighbourhood is loaded before beta is summed
+        const int n = n0;
+        const bool in = n < g.n_nodes;
+        int i = 0, j = 0, k = 0;
+        if (in) node_ijk(g, n, i, j, k);
+        const bool interior = in && i > 0 && i < g.nx && j > 0 && j < g.ny;
+        double zn[9], pn9[9];
+        if (interior) {
 #pragma unroll
-            for (int dk = (DIM == 3 ? -1 : 0); dk <= (DIM == 3 ? 1 : 0); ++dk)
+            for (int dj = -1; dj <= 1; ++dj)
 #pragma unroll
-                for (int dj = -1; dj <= 1; ++dj)
-#pragma unroll
-                    for (int di = -1; di <= 1; ++di) {
-                        const int m = n + di + sy * dj + sz * dk;
-                        qn += E.S[13 + di + 3 * dj + 9 * dk] * (zb[m] + beta * pb[m]);
-                    }
-        } else {
-            qn = helm_row<DIM>(g, E, i, j, k, [&](int m) { return zb[m] + beta * pb[m]; });
+                for (int di = -1; di <= 1; ++di) {
+                    const int m = n + di + g.nx1 * dj;
+                    zn[4 + di + 3 * dj] = zb[m];
+                    pn9[4 + di + 3 * dj] = pb[m];
+                }
         }
-        pnew[base + n] = pn;
-        q[base + n] = qn;
-        v[0] += pn * qn;
+        const double beta = helm_beta(first, nrz, rz_cur, rz_prev, lds);
+        if (in) {
+            double pn, qn = 0.0;
+            if (interior) {
+                pn = zn[4] + beta * pn9[4];
+#pragma unroll
+                for (int e = 0; e < 9; ++e) qn += E.S[13 + (e % 3 - 1) + 3 * (e / 3 - 1)] * (zn[e] + beta * pn9[e]);
+            } else {
+                pn = zb[n] + beta * pb[n];
+                qn = helm_row<DIM>(g, E, i, j, k, [&](int m) { return zb[m] + beta * pb[m]; });
+            }
+            pnew[base + n] = pn;
+            q[base + n] = qn;
+            v[0] += pn * qn;
+        }
+    } else {
+        const double beta = helm_beta(first, nrz, rz_cur, rz_prev, lds);
+        for (int t = 0; t < helm_npt<DIM>(); ++t) {
+            const int n = n0 + t * kHelmBlock;
+            if (n >= g.n_nodes) break;
+            int i, j, k;
+            node_ijk(g, n, i, j, k);
+            const double pn = zb[n] + beta * pb[n];
+            const double qn = helm_row<DIM>(g, E, i, j, k, [&](int m) { return zb[m] + beta * pb[m]; });
+            pnew[base + n] = pn;
+            q[base + n] = qn;
+            v[0] += pn * qn;
+        }
     }
     block_reduce<1>(v, lds);
     if (threadIdx.x == 0) ppq[(size_t)blockIdx.y * nb + blockIdx.x] = v[0];
@@ -354,22 +373,38 @@ __global__ __launch_bounds__(kHelmBlock) void k_helm_update(Grid g, double diag,
     __shared__ double lds[32];
     const int nb = gridDim.x;
     const int n0 = xcd_block(blockIdx.x, nb) * (helm_npt<DIM>() * kHelmBlock) + threadIdx.x;
+    constexpr int NPT = helm_npt<DIM>();
     // A stopped field is left as it is (its p may be meaningless, e.g. 0/0 for b = 0).
     const bool active = sc[blockIdx.y * kHelmScal + 5] != 0.0;
+    // the node values are loaded before the partial sums, so both latencies overlap
+    double xv[NPT], rv[NPT], zv[NPT], pv[NPT], qv[NPT];
+#pragma unroll
+    for (int t = 0; t < NPT; ++t) {
+        const int n = n0 + t * kHelmBlock;
+        if (n < g.n_nodes) {
+            const size_t o = (size_t)blockIdx.y * g.n_nodes + n;
+            xv[t] = x[o];
+            rv[t] = r[o];
+            zv[t] = z[o];
+            pv[t] = p[o];
+            qv[t] = q[o];
+        }
+    }
     const double rz = block_sum_array(rz_cur + (size_t)blockIdx.y * nb, nb, lds);
     const double pq = block_sum_array(ppq + (size_t)blockIdx.y * npq, npq, lds);
     const double alpha = pq != 0.0 ? rz / pq : 0.0;
     double v[2] = {0.0, 0.0};
-    for (int t = 0; t < helm_npt<DIM>(); ++t) {
+#pragma unroll
+    for (int t = 0; t < NPT; ++t) {
         const int n = n0 + t * kHelmBlock;
         if (n >= g.n_nodes) break;
         const size_t o = (size_t)blockIdx.y * g.n_nodes + n;
-        double rn = r[o], zn = z[o];
+        double rn = rv[t], zn = zv[t];
         if (active) {
             int i, j, k;
             node_ijk(g, n, i, j, k);
-            x[o] += alpha * p[o];
-            rn -= alpha * q[o];
+            x[o] = xv[t] + alpha * pv[t];
+            rn -= alpha * qv[t];
             zn = rn * helm_dinv(g, diag, i, j, k);
             r[o] = rn;
             z[o] = zn;
