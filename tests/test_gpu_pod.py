@@ -88,6 +88,7 @@ CASES = [  # (problem, L, snapshots pushed, nmax, decay)
     (W.cantilever3d(7, 5, 3), 6, 9, 2, 0.6),
     (W.bridge3d(6, 4, 5), 20, 20, 19, 0.8),
     (W.cantilever2d(600, 200), 20, 23, 19, 0.8),
+    (W.mbb2d(60, 20), 48, 50, 47, 0.9),  # the largest window and basis
 ]
 
 

@@ -59,3 +59,19 @@ def test_trust_region_driver_mixed_precision_takes_the_oracle_decisions():
     for hd, ho in zip(hist_d, hist_o):
         assert abs(hd["delta"] - ho["delta"]) <= 1e-12 * ho["delta"]
         assert abs(hd["J"] - ho["J"]) <= 1e-6 * ho["J"]
+
+
+def test_trust_region_driver_3d_matches_oracle():
+    torch_cuda()
+    from paper_2004_05756_amd.trdriver import TrustRegion
+    p = W.cantilever3d(8, 4, 4)
+    r = F.filter_radius(1.2)
+    prob = T.Problem(p.mesh, p.mask, p.f, r, 0.4)
+    psi_o, hist_o = T.rom_tr(prob, kind="res", tau=0.1, iters=3, window=3, nmax=2)
+    drv = TrustRegion(ctx(), p.mesh, p.mask, p.f, r, 0.4, kind="res", window=3, nmax=2)
+    psi_d, hist_d = drv.run(iters=3, tau=0.1)
+    assert [h["accepted"] for h in hist_d] == [h["accepted"] for h in hist_o]
+    for hd, ho in zip(hist_d, hist_o):
+        assert abs(hd["delta"] - ho["delta"]) <= 1e-12 * ho["delta"]
+        assert abs(hd["J"] - ho["J"]) <= 1e-8 * ho["J"]
+    assert np.abs(psi_d - psi_o).max() <= 1e-6
