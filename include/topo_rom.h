@@ -208,12 +208,15 @@ int topo_rom_solve(topo_ctx* ctx, int32_t k, int32_t B, const double* Khat,
  * Jk[b] = f^T Phi yhat[b] and resnorm are those of the refined yhat.  Every decision is
  * taken on the device: the call does not synchronise the stream.
  *   yhat [B][k] f64 in/out, Jk [B] f64 out (may be NULL), resnorm [B] f64 out,
- *   Khat [B][k][k] f64 (only read when max_refine > 0). */
+ *   Khat [B][k][k] f64 (only read when max_refine > 0),
+ *   dJ [B][N_e] f64 out (may be NULL): the ROM sensitivity at the returned yhat, as
+ *   topo_rom_gradient computes it, fused into the estimate (without refinement it is
+ *   evaluated on the same u = Phi yhat as the residual, so no extra pass over Phi). */
 int topo_rom_estimate(topo_ctx* ctx, const topo_mesh* mesh, const void* phi,
                       int32_t phi_fp32, int32_t k, int32_t ldphi, const uint8_t* mask,
                       const double* f, const double* rho, int32_t B, const double* Khat,
                       double* yhat, double* Jk, double* resnorm, int32_t max_refine,
-                      void* stream);
+                      double* dJ, void* stream);
 
 /* Sensitivity of the ROM compliance J_k(rho) = f_hat^T K_hat(rho)^{-1} f_hat with
  * respect to the densities (Sec. 3.2: for the compliance the reduced adjoint equals the

@@ -70,7 +70,7 @@ _SIGS = {
                                  _P, _P, C.c_int32, _P, _P, C.c_int32, _P]),
     "topo_rom_solve": (C.c_int, [_P, C.c_int32, C.c_int32, _P, _P, _P, _P, _P, _P]),
     "topo_rom_estimate": (C.c_int, [_P, C.POINTER(TopoMesh), _P, C.c_int32, C.c_int32, C.c_int32,
-                                    _P, _P, _P, C.c_int32, _P, _P, _P, _P, C.c_int32, _P]),
+                                    _P, _P, _P, C.c_int32, _P, _P, _P, _P, C.c_int32, _P, _P]),
     "topo_rom_gradient": (C.c_int, [_P, C.POINTER(TopoMesh), _P, C.c_int32, C.c_int32, C.c_int32,
                                     _P, _P, C.c_int32, _P, _P, _P]),
     "topo_filter_forward": (C.c_int, [_P, C.POINTER(TopoMesh), C.c_double, _P, C.c_int32, _P, _P,
@@ -289,7 +289,9 @@ class Context:
         return yhat, Jk
 
     def rom_estimate(self, mesh, phi, k, mask, f, rho, Khat, yhat, max_refine=1, stream=None,
-                     Jk=None, resnorm=None):
+                     Jk=None, resnorm=None, dJ=None):
+        """u = Phi yhat, ||f - K u|| with optional reduced refinement of yhat; with a dJ
+        tensor [B][N_e] also the ROM sensitivity at the returned yhat (topo_rom_estimate)."""
         import torch
         if rho.dim() == 1:
             rho = rho.unsqueeze(0)
@@ -307,7 +309,7 @@ class Context:
                                         B, _ptr(Khat, torch.float64, "Khat") if Khat is not None else None,
                                         _ptr(yhat, torch.float64, "yhat"), _ptr(Jk, torch.float64, "Jk"),
                                         _ptr(resnorm, torch.float64, "resnorm"), int(max_refine),
-                                        _stream(stream))
+                                        _ptr(dJ, torch.float64, "dJ"), _stream(stream))
         self._check(rc, "rom_estimate")
         return yhat, Jk, resnorm
 

@@ -1034,7 +1034,7 @@ int topo_rom_solve(topo_ctx* ctx, int32_t k, int32_t B, const double* Khat, cons
 int topo_rom_estimate(topo_ctx* ctx, const topo_mesh* mesh, const void* phi, int32_t phi_fp32,
                       int32_t k, int32_t ldphi, const uint8_t* mask, const double* f,
                       const double* rho, int32_t B, const double* Khat, double* yhat, double* Jk,
-                      double* resnorm, int32_t max_refine, void* stream) {
+                      double* resnorm, int32_t max_refine, double* dJ, void* stream) {
     if (!ctx) return TOPO_EINVAL;
     int rc = validate_mesh(ctx, mesh);
     if (rc) return rc;
@@ -1122,6 +1122,15 @@ int topo_rom_estimate(topo_ctx* ctx, const topo_mesh* mesh, const void* phi, int
     hipLaunchKernelGGL(k_estimate_out, dim3(1), dim3(64), 0, s, B,
                        (const double*)(max_refine > 0 ? keep : out), resnorm, Jk);
     TOPO_CHECK_LAUNCH();
+    if (dJ) {
+        // sensitivity at the returned y: u of the single pass, or re-formed after refinement
+        if (max_refine > 0) {
+            rc = phi_y_launch(ctx, phi, phi_fp32, k, ldphi, mask, yhat, N, B, u, s);
+            if (rc) return rc;
+        }
+        rc = gradient_launch(ctx, g, *mesh, tb, rho, u, B, dJ, s);
+        if (rc) return rc;
+    }
     return TOPO_OK;
 }
 

@@ -380,7 +380,7 @@ void run_job(topo_server* S, Worker& w, Job& job, std::vector<topo_result>& out)
         if (rc == TOPO_OK)
             rc = topo_rom_estimate(w.ctx, &mr.mesh, br.phi, br.fp32, k, br.kmax, mr.mask, mr.f,
                                    rho_d + (size_t)b * g.n_elems, 1, Kb, yhat, jk, rn,
-                                   job.max_refine, s);
+                                   job.max_refine, nullptr, s);
         double h[2] = {0.0, 0.0};
         if (rc == TOPO_OK) {
             hipError_t e = hipMemcpyAsync(&h[0], jk, 8, hipMemcpyDeviceToHost, s);

@@ -103,13 +103,15 @@ class TrustRegion:
         y, Jk = self.ctx.rom_solve(Kh, fh)
         self.model_evals += 1
         rn = 0.0
-        if self.kind == "res":
+        dJ = self.torch.empty_like(rho) if want_grad else None
+        if self.kind == "res":  # the sensitivity comes with the estimate (same u = Phi y)
             y, Je, resn = self.ctx.rom_estimate(self.mesh, self.phi, self.k, self.mask, self.f, rho, Kh, y,
-                                                max_refine=0)
+                                                max_refine=0, dJ=dJ)
             rn = float(resn[0])
+        elif want_grad:
+            dJ = self.ctx.rom_gradient(self.mesh, self.phi, self.k, self.mask, rho, y, dJ=dJ)
         g = None
         if want_grad:
-            dJ = self.ctx.rom_gradient(self.mesh, self.phi, self.k, self.mask, rho, y)
             gd, _ = self.ctx.filter_adjoint(self.mesh, self.r, dJ, mu=self.mu_nodal, rtol=self.filter_rtol,
                                             warm=self.warm_mu)
             self.warm_mu = True

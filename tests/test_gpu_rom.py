@@ -222,3 +222,28 @@ def test_rom_gradient_matches_oracle(p, k):
             assert np.abs(dJ[b] - ref[b]).max() <= tol * np.abs(ref[b]).max()
         one = host(ctx().rom_gradient(p.mesh, phid, k, m, r[1:2].contiguous(), y[1:2].contiguous()))
         assert np.array_equal(one[0], dJ[1])
+
+
+@pytest.mark.parametrize("max_refine", [0, 2])
+def test_estimate_fused_sensitivity_equals_separate_call(max_refine):
+    """The sensitivity returned with the estimate is the one topo_rom_gradient gives at the
+    returned coefficients (bitwise: the same kernels on the same u = Phi y), and in FP64
+    it matches the oracle's ROM sensitivity."""
+    torch = torch_cuda()
+    from paper_2004_05756_amd import FP64, MIXED
+    p = W.cantilever2d(37, 11)
+    k = 9
+    phi = dev(_basis(p, k, np.float32))
+    rho = dev(_rhos(p, 2, seed=5), torch.float64)
+    m, f = dev(p.mask, torch.uint8), dev(p.f, torch.float64)
+    prec = FP64 if max_refine == 0 else MIXED
+    Kh, fh = ctx().rom_build(p.mesh, phi, k, m, f, rho, prec=prec)
+    y, _ = ctx().rom_solve(Kh, fh)
+    dJ = torch.empty_like(rho)
+    y, J, rn = ctx().rom_estimate(p.mesh, phi, k, m, f, rho, Kh, y, max_refine=max_refine, dJ=dJ)
+    sep = ctx().rom_gradient(p.mesh, phi, k, m, rho, y)
+    assert torch.equal(dJ, sep)
+    if max_refine == 0:
+        for b in range(2):
+            go, _ = O.rom_gradient(p.mesh, host(rho)[b], _basis(p, k, np.float32), p.mask, p.f)
+            assert np.abs(host(dJ)[b] - go).max() <= 1e-9 * np.abs(go).max()
