@@ -55,12 +55,22 @@ def parse():
 
 def pcg_bytes(n_dofs, n_nodes, n_elems, word):
     """Algorithmic HBM bytes of one launch of each PCG kernel (each array once).
-    apply : read z, p_old (stencil), alpha, mask; write p_new, q
-    update: read/write x (float64), r; write z; read p, q, 1/sum(alpha) per node"""
+    step  (2D, one kernel per iteration): read r, w, s (stencil), p, mask, alpha,
+          1/sum(alpha) per node; read/write x (float64); write r, w, s, p
+    apply (3D): read z, p_old (stencil), alpha, mask; write p_new, q
+    update (3D): read/write x (float64), r; write z; read p, q, 1/sum(alpha) per node"""
     return {
+        "pcg_step": n_dofs * (8 * word + 17) + n_nodes * word + n_elems * word,
         "pcg_apply": n_dofs * (4 * word + 1) + n_elems * word,
         "pcg_update": n_dofs * (5 * word + 16) + n_nodes * word,
     }
+
+
+def pcg_kernel_name(kind, dim, word):
+    """Symbol (as rocprofv3 prints it) of a PCG kernel."""
+    t = "float" if word == 4 else "double"
+    return {"pcg_step": f"k_cg1_step2<{t},0>", "pcg_apply": f"k_pcg_apply{dim}<{t}>",
+            "pcg_update": f"k_pcg_update<{dim},{t}>"}[kind]
 
 
 # Device sources of the PCG kernels: measured HBM traffic recorded under profiles/ is
@@ -468,7 +478,7 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    names = ["pcg_apply", "pcg_update", "residual", "rom_contract", "rom_reduce", "phit_v",
+    names = ["pcg_step", "pcg_apply", "pcg_update", "residual", "rom_contract", "rom_reduce", "phit_v",
              "phi_y", "chol", "chol_solve", "gradient"]
     for nm in names:
         ctx.kernel_time(nm, reset=True)
@@ -494,7 +504,7 @@ def main():
         n, ms = ctx.kernel_time(nm)
         if n:
             ktimes[nm] = {"samples": n, "avg_us": 1e3 * ms / n}
-    launches = {"pcg_apply": iters, "pcg_update": iters, "rom_contract": args.steps}
+    launches = {"pcg_step": iters, "pcg_apply": iters, "pcg_update": iters, "rom_contract": args.steps}
     share = {nm: ktimes[nm]["avg_us"] * launches[nm] for nm in launches if nm in ktimes}
     dominant = max(share, key=share.get) if share else None
     pb = pcg_bytes(m.n_dofs, m.n_nodes, m.n_elems, word)
@@ -502,8 +512,7 @@ def main():
     if dominant in pb:
         avg_s = ktimes[dominant]["avg_us"] * 1e-6
         gbs = pb[dominant] / avg_s / 1e9
-        kname = f"k_pcg_{dominant.split('_')[1]}{m.dim if dominant == 'pcg_apply' else ''}" \
-                f"<{'' if dominant == 'pcg_apply' else str(m.dim) + ','}{'float' if word == 4 else 'double'}>"
+        kname = pcg_kernel_name(dominant, m.dim, word)
         roofline = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": gbs / HBM_PEAK_GBS, "traffic": measured_traffic(cfg.name, kname),
                     "kernel": kname, "bytes_per_launch": pb[dominant], "avg_us": ktimes[dominant]["avg_us"]}
@@ -554,6 +563,7 @@ def main():
             torch.cuda.synchronize()
             tb = time.perf_counter() - ta
             extra[f"hdm_{name}"] = {"ms": 1e3 * tb, "iters": inf["iters"],
+                                    "us_per_iter": 1e6 * tb / max(1, inf["iters"]),
                                     "dof_iter_per_s": m.n_dofs * inf["iters"] / tb,
                                     "compliance": inf["compliance_corr"]}
             lat = []

@@ -110,8 +110,10 @@ size_t topo_ctx_workspace_bytes(const topo_ctx* ctx);
 int topo_ctx_set_timing(topo_ctx* ctx, int32_t every);
 /* Sampled launches and their summed device time in ms for one hot kernel: "apply",
  * "pcg_apply", "pcg_update", "residual", "rom_contract", "rom_reduce", "phit_v",
- * "phi_y", "chol", "chol_solve", "gradient".  Waits for pending samples (host
- * outputs); reset != 0 clears the kernel's counters afterwards. */
+ * "phi_y", "chol", "chol_solve", "gradient", "pcg_step" (the one kernel per
+ * iteration of the 2D solve; "pcg_apply" / "pcg_update" are the two of the 3D solve).
+ * Waits for pending samples (host outputs); reset != 0 clears the kernel's counters
+ * afterwards. */
 int topo_ctx_kernel_time(topo_ctx* ctx, const char* kernel, int64_t* samples,
                          double* total_ms, int32_t reset);
 

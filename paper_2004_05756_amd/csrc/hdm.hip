@@ -424,8 +424,8 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_update(Grid g, const T* __res
 // done: its producer did not run then, and summing again would count a[0] twice.
 __global__ __launch_bounds__(1024) void k_partials_sum(double* __restrict__ a,
                                                        double* __restrict__ b, int n,
-                                                       const PcgState* st) {
-    if (st->done) return;
+                                                       const int* done) {
+    if (*done) return;
     __shared__ double lds[32];
     double v[2] = {0.0, 0.0};
     constexpr int U = 8;  // loads in flight per thread
@@ -482,6 +482,278 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_replace(Grid g, const double*
     if (threadIdx.x == 0) {
         part_rz(part, ps, cur)[blockIdx.x] = v[0];
         part_rr(part, ps, cur)[blockIdx.x] = v[1];
+    }
+}
+
+// ----------------------------------------------------------------------------------
+// 2D: Jacobi-PCG with one reduction phase per iteration (the Chronopoulos-Gear form of
+// CG), one kernel per iteration.  With u = D^{-1} r, w = K u and s = K p:
+//   beta_i = gamma_i / gamma_{i-1},  alpha_i = gamma_i / (delta_i - beta_i gamma_i / alpha_{i-1}),
+//   p_i = u_i + beta_i p_{i-1},  s_i = w_i + beta_i s_{i-1},  x += alpha_i p_i,
+//   r_{i+1} = r_i - alpha_i s_i,  u_{i+1} = D^{-1} r_{i+1},  w_{i+1} = K u_{i+1},
+//   gamma_{i+1} = r_{i+1}.u_{i+1},  delta_{i+1} = w_{i+1}.u_{i+1}.
+// The stencil needs u_{i+1} on the 3x3 neighbourhood of a node; a thread forms it
+// there from r_i, w_i and s_{i-1} (elementwise), so a launch needs nothing from another
+// block of the same launch, and its scalars come from the partials of the previous one.
+// r, w and s are double-buffered: step i reads set i & 1 (r_i, w_i, s_{i-1}) and writes
+// set (i + 1) & 1 (r_{i+1}, w_{i+1}, s_i); p and x are updated in place (own node only).
+// Partials: part = [gamma(0) | gamma(1) | delta(0) | delta(1) | rr(0) | rr(1) | u.s | p.s],
+// ps doubles apart, by the parity of the residual they belong to.  The state keeps
+// gamma, alpha and the iteration count by parity: step i reads the slots of step i - 1
+// and writes its own, so no block reads a value another block of its launch writes.
+// ----------------------------------------------------------------------------------
+struct Cg1State {
+    double bb;        // reference ||r||^2 of the stopping test
+    double rr;        // ||r||^2 at the last stopping test
+    double tol2;      // the segment stops when rr <= tol2 * bb
+    double gamma[2];  // gamma_i by parity of i
+    double alpha[2];  // alpha_i by parity of i
+    int done;         // 0 running, 1 converged, 2 iteration limit, 3 breakdown
+    int maxit;
+    int iters[2];     // step i writes iters[i & 1] = i + 1
+};
+
+enum { kCg1Step = 0, kCg1Fresh = 1, kCg1Continued = 2, kCg1Init = 3 };
+
+__device__ __forceinline__ double* cg1_part(double* p, int ps, int k) { return p + (size_t)k * ps; }
+
+// Node value of a per-node array on the 3x3 neighbourhood (zero outside the grid).
+template <typename T>
+__device__ __forceinline__ void load_node_nbhd2(const Grid& g, int i, int j, const T* __restrict__ a,
+                                                T (&v)[3][3]) {
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx) {
+            const int ii = i + dx - 1, jj = j + dy - 1;
+            const bool ok = (ii >= 0) & (ii < g.nx1) & (jj >= 0) & (jj < g.ny1);
+            v[dy][dx] = ok ? a[jj * g.nx1 + ii] : T(0);
+        }
+}
+
+// One step (KIND kCg1Step / kCg1Fresh / kCg1Continued) at parity `parity`, or the
+// initialisation (kCg1Init: r_0 = Rin = b, w_0 = K D^{-1} b, p = s = x = 0, written to
+// set 0 with parity = 1).  A fresh step takes beta = 0; a continued step (after a
+// residual replacement) takes the direction K-conjugate to the kept p, with the exact
+// p^T K p, from the u.s / p.s partials of k_cg1_replace2.
+template <typename T, int KIND>
+__global__ __launch_bounds__(kPcgBlock) void k_cg1_step2(
+    Grid g, const T* __restrict__ alpha, const T* __restrict__ K, const uint8_t* __restrict__ mask,
+    const T* __restrict__ winv, T ik0, T ik1, const T* __restrict__ Rin, const T* __restrict__ Win,
+    const T* __restrict__ Sin, T* __restrict__ Rout, T* __restrict__ Wout, T* __restrict__ Sout,
+    T* __restrict__ P, double* __restrict__ x, double* __restrict__ part, Cg1State* st, int ps,
+    int npart, int parity, int maxit, double tol2) {
+    if (KIND != kCg1Init && st->done) return;
+    __shared__ double lds[80];
+    const int n = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const bool own = n < g.n_nodes;
+    T rs[3][3][2], ws[3][3][2], ss[3][3][2], wv[3][3], al[2][2], pv[2];
+    double xv[2];
+    uint8_t mk[2];
+    int i = 0, j = 0, k = 0;
+    if (own) {  // every load is issued before the wait on the scalar reduction
+        node_ijk(g, n, i, j, k);
+        load_nbhd2(g, i, j, FetchPlain<T>{Rin, g.n_nodes}, rs);
+        if constexpr (KIND != kCg1Init) {
+            load_nbhd2(g, i, j, FetchPlain<T>{Win, g.n_nodes}, ws);
+            load_nbhd2(g, i, j, FetchPlain<T>{Sin, g.n_nodes}, ss);
+        }
+        load_node_nbhd2(g, i, j, winv, wv);
+        load_alpha2(g, i, j, alpha, al);
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const size_t idx = (size_t)c * g.n_nodes + n;
+            mk[c] = mask[idx];
+            if constexpr (KIND != kCg1Init) {
+                pv[c] = P[idx];
+                xv[c] = x[idx];
+            }
+        }
+    }
+    const int cur = parity, nxt = parity ^ 1;
+    double be = 0.0, ah = 0.0;
+    if constexpr (KIND == kCg1Init) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            st->done = 0;
+            st->maxit = maxit;
+            st->iters[0] = st->iters[1] = 0;
+            st->bb = st->rr = 0.0;
+            st->tol2 = tol2;
+        }
+    } else {
+        double red[5];
+        if constexpr (KIND == kCg1Continued) {
+            const double* arrs[5] = {cg1_part(part, ps, cur), cg1_part(part, ps, 2 + cur),
+                                     cg1_part(part, ps, 4 + cur), cg1_part(part, ps, 6),
+                                     cg1_part(part, ps, 7)};
+            block_sum_arrays<5>(arrs, npart, red, lds);
+        } else {
+            const double* arrs[3] = {cg1_part(part, ps, cur), cg1_part(part, ps, 2 + cur),
+                                     cg1_part(part, ps, 4 + cur)};
+            double r3[3];
+            block_sum_arrays<3>(arrs, npart, r3, lds);
+            red[0] = r3[0];
+            red[1] = r3[1];
+            red[2] = r3[2];
+        }
+        const double gam = red[0], dlt = red[1], rr = red[2];
+        const double bb = KIND == kCg1Fresh ? rr : st->bb;
+        int code = 0;
+        if (!isfinite(rr)) code = 3;
+        else if (rr <= st->tol2 * bb) code = 1;
+        else if (st->iters[nxt] >= st->maxit) code = 2;
+        if (!code) {
+            if constexpr (KIND == kCg1Fresh) {
+                ah = gam / dlt;
+            } else if constexpr (KIND == kCg1Continued) {
+                const double us = red[3], pss = red[4];
+                if (pss > 0.0 && isfinite(pss)) {
+                    be = -us / pss;
+                    ah = gam / (dlt + be * us);
+                } else {
+                    ah = gam / dlt;
+                }
+            } else {
+                be = gam / st->gamma[nxt];
+                ah = gam / (dlt - be * gam / st->alpha[nxt]);
+            }
+            if (!(ah > 0.0) || !isfinite(ah) || !isfinite(be)) code = 3;
+        }
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            if (KIND == kCg1Fresh) st->bb = rr;
+            st->rr = rr;
+            if (code) {
+                st->done = code;
+            } else {
+                st->gamma[cur] = gam;
+                st->alpha[cur] = ah;
+                st->iters[cur] = st->iters[nxt] + 1;
+            }
+        }
+        if (code) return;
+    }
+    double v[3] = {0.0, 0.0, 0.0};
+    if (own) {
+        const T tb = (T)be, ta = (T)ah;
+        const T ik[2] = {ik0, ik1};
+        T un[3][3][2], snew[2], rnew[2], unew[2];
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx)
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    T si = T(0), rn = rs[dy][dx][c];
+                    if constexpr (KIND != kCg1Init) {
+                        si = ws[dy][dx][c] + tb * ss[dy][dx][c];
+                        rn = rn - ta * si;
+                    }
+                    un[dy][dx][c] = rn * wv[dy][dx] * ik[c];
+                    if (dy == 1 && dx == 1) {
+                        snew[c] = si;
+                        rnew[c] = rn;
+                        unew[c] = un[1][1][c];
+                    }
+                }
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const size_t idx = (size_t)c * g.n_nodes + n;
+            if constexpr (KIND == kCg1Init) {
+                P[idx] = T(0);
+                x[idx] = 0.0;
+            } else {
+                const T pn = rs[1][1][c] * wv[1][1] * ik[c] + tb * pv[c];  // u_i + beta p_{i-1}
+                P[idx] = pn;
+                x[idx] = xv[c] + (double)ta * (double)pn;
+            }
+            Sout[idx] = snew[c];
+            Rout[idx] = rnew[c];
+        }
+        T out[2];
+        apply_nbhd2(K, un, al, out);
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const size_t idx = (size_t)c * g.n_nodes + n;
+            const T wn = mk[c] ? T(0) : out[c];
+            Wout[idx] = wn;
+            v[0] += (double)rnew[c] * (double)unew[c];
+            v[1] += (double)wn * (double)unew[c];
+            v[2] += (double)rnew[c] * (double)rnew[c];
+        }
+    }
+    block_reduce<3>(v, lds);
+    if (threadIdx.x == 0) {
+        cg1_part(part, ps, nxt)[blockIdx.x] = v[0];
+        cg1_part(part, ps, 2 + nxt)[blockIdx.x] = v[1];
+        cg1_part(part, ps, 4 + nxt)[blockIdx.x] = v[2];
+    }
+}
+
+// Residual replacement of the one-reduction recursion: r = scale * r64 (the float64 true
+// residual), u = D^{-1} r, w = K u, and s = K p computed exactly for the kept direction
+// p, written to set `cur` with x = 0; partials of gamma, delta, rr (parity cur) and of
+// u.s, p.s, from which the continued step takes its conjugate direction.
+template <typename T>
+__global__ __launch_bounds__(kPcgBlock) void k_cg1_replace2(
+    Grid g, const T* __restrict__ alpha, const T* __restrict__ K, const uint8_t* __restrict__ mask,
+    const T* __restrict__ winv, T ik0, T ik1, const double* __restrict__ r64, double scale,
+    const T* __restrict__ P, T* __restrict__ R, T* __restrict__ W, T* __restrict__ S,
+    double* __restrict__ x, double* __restrict__ part, int ps, int cur) {
+    __shared__ double lds[80];
+    const int n = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (n < g.n_nodes) {
+        int i, j, k;
+        node_ijk(g, n, i, j, k);
+        double rs[3][3][2];
+        T ps_[3][3][2], wv[3][3], al[2][2];
+        load_nbhd2(g, i, j, FetchPlain<double>{r64, g.n_nodes}, rs);
+        load_nbhd2(g, i, j, FetchPlain<T>{P, g.n_nodes}, ps_);
+        load_node_nbhd2(g, i, j, winv, wv);
+        load_alpha2(g, i, j, alpha, al);
+        const T ik[2] = {ik0, ik1};
+        T un[3][3][2], rown[2], uown[2], pown[2];
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx)
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    const T rn = (T)(scale * rs[dy][dx][c]);
+                    un[dy][dx][c] = rn * wv[dy][dx] * ik[c];
+                    if (dy == 1 && dx == 1) {
+                        rown[c] = rn;
+                        uown[c] = un[1][1][c];
+                        pown[c] = ps_[1][1][c];
+                    }
+                }
+        T wo[2], so[2];
+        apply_nbhd2(K, un, al, wo);
+        apply_nbhd2(K, ps_, al, so);
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const size_t idx = (size_t)c * g.n_nodes + n;
+            const bool fixed = mask[idx] != 0;
+            const T wn = fixed ? T(0) : wo[c];
+            const T sn = fixed ? T(0) : so[c];
+            R[idx] = rown[c];
+            W[idx] = wn;
+            S[idx] = sn;
+            x[idx] = 0.0;
+            v[0] += (double)rown[c] * (double)uown[c];
+            v[1] += (double)wn * (double)uown[c];
+            v[2] += (double)rown[c] * (double)rown[c];
+            v[3] += (double)uown[c] * (double)sn;
+            v[4] += (double)pown[c] * (double)sn;
+        }
+    }
+    block_reduce<5>(v, lds);
+    if (threadIdx.x == 0) {
+        cg1_part(part, ps, cur)[blockIdx.x] = v[0];
+        cg1_part(part, ps, 2 + cur)[blockIdx.x] = v[1];
+        cg1_part(part, ps, 4 + cur)[blockIdx.x] = v[2];
+        cg1_part(part, ps, 6)[blockIdx.x] = v[3];
+        cg1_part(part, ps, 7)[blockIdx.x] = v[4];
     }
 }
 
@@ -754,7 +1026,7 @@ struct LaunchSink {
 static void pcg_sum_rz(const PcgGeom& pg, double* part, int par, const PcgState* st, LaunchSink& L) {
     if (pg.nrz == 1 && pg.nupd > 1)
         L((const void*)k_partials_sum, dim3(1), dim3(1024), part + (1 + par) * (size_t)pg.ps,
-          part + (3 + par) * (size_t)pg.ps, (int)pg.nupd, st);
+          part + (3 + par) * (size_t)pg.ps, (int)pg.nupd, (const int*)&st->done);
 }
 
 // One PCG iteration (apply + update).
@@ -774,7 +1046,7 @@ static void pcg_iteration(Ctx* ctx, const Grid& g, const PcgRun<DIM, T>& w, cons
     }
     if (pg.npq == 1 && pg.napp > 1)
         L((const void*)k_partials_sum, dim3(1), dim3(1024), w.part, (double*)nullptr, (int)pg.napp,
-          (const PcgState*)w.st);
+          (const int*)&w.st->done);
     {
         TimedLaunch tl(ctx, KID_PCG_UPDATE, L.s, L.graph ? kTimeOff : timing, true);
         L.ev0 = tl.a;
@@ -786,23 +1058,9 @@ static void pcg_iteration(Ctx* ctx, const Grid& g, const PcgRun<DIM, T>& w, cons
     pcg_sum_rz(pg, w.part, parity, w.st, L);
 }
 
-// Graph of CH iterations starting at parity 1 (CH even, so every replay continues
-// the parity sequence).
-template <int DIM, typename T>
-static int pcg_graph(Ctx* ctx, const Grid& g, const PcgRun<DIM, T>& w, const PcgGeom& pg,
-                     int CH, hipGraphExec_t* out) {
-    std::vector<uintptr_t> key = {(uintptr_t)DIM, sizeof(T), (uintptr_t)pg.napp, (uintptr_t)CH,
-                                  (uintptr_t)g.nx, (uintptr_t)g.ny, (uintptr_t)g.nz,
-                                  (uintptr_t)w.alpha, (uintptr_t)w.K, (uintptr_t)w.mask,
-                                  (uintptr_t)w.winv, (uintptr_t)w.x, (uintptr_t)w.r, (uintptr_t)w.z,
-                                  (uintptr_t)w.p0, (uintptr_t)w.p1, (uintptr_t)w.q, (uintptr_t)w.part,
-                                  (uintptr_t)w.st};
-    for (int c = 0; c < 3; ++c) {
-        double ikd = (double)w.ik[c];
-        uint64_t ib;
-        std::memcpy(&ib, &ikd, sizeof ib);
-        key.push_back((uintptr_t)ib);
-    }
+// Instantiated graph for `key`, built by build(L) on first use and cached in ctx.
+template <typename Build>
+static int cached_graph(Ctx* ctx, const std::vector<uintptr_t>& key, Build build, hipGraphExec_t* out) {
     auto it = ctx->graphs.find(key);
     if (it != ctx->graphs.end()) {
         *out = it->second.exec;
@@ -819,7 +1077,7 @@ static int pcg_graph(Ctx* ctx, const Grid& g, const PcgRun<DIM, T>& w, const Pcg
     TOPO_HIP(hipGraphCreate(&ge.graph, 0));
     LaunchSink L;
     L.graph = ge.graph;
-    for (int c = 0; c < CH; ++c) pcg_iteration<DIM, T>(ctx, g, w, pg, (1 + c) & 1, 0, L, kTimeOff);
+    build(L);
     if (L.err != hipSuccess) {
         (void)hipGraphDestroy(ge.graph);
         return set_error(ctx, TOPO_EDEVICE, "graph construction failed: %s", hipGetErrorString(L.err));
@@ -834,6 +1092,85 @@ static int pcg_graph(Ctx* ctx, const Grid& g, const PcgRun<DIM, T>& w, const Pcg
     return TOPO_OK;
 }
 
+static void key_push_double(std::vector<uintptr_t>& key, double v) {
+    uint64_t ib;
+    std::memcpy(&ib, &v, sizeof ib);
+    key.push_back((uintptr_t)ib);
+}
+
+constexpr int kPcgChunk = 16;  // iterations per graph replay (even)
+
+// Graph of kPcgChunk iterations starting at parity 1 (so every replay continues the
+// parity sequence).
+template <int DIM, typename T>
+static int pcg_graph(Ctx* ctx, const Grid& g, const PcgRun<DIM, T>& w, const PcgGeom& pg,
+                     hipGraphExec_t* out) {
+    std::vector<uintptr_t> key = {(uintptr_t)DIM, sizeof(T), (uintptr_t)pg.napp, (uintptr_t)kPcgChunk,
+                                  (uintptr_t)g.nx, (uintptr_t)g.ny, (uintptr_t)g.nz,
+                                  (uintptr_t)w.alpha, (uintptr_t)w.K, (uintptr_t)w.mask,
+                                  (uintptr_t)w.winv, (uintptr_t)w.x, (uintptr_t)w.r, (uintptr_t)w.z,
+                                  (uintptr_t)w.p0, (uintptr_t)w.p1, (uintptr_t)w.q, (uintptr_t)w.part,
+                                  (uintptr_t)w.st};
+    for (int c = 0; c < 3; ++c) key_push_double(key, (double)w.ik[c]);
+    return cached_graph(ctx, key, [&](LaunchSink& L) {
+        for (int c = 0; c < kPcgChunk; ++c) pcg_iteration<DIM, T>(ctx, g, w, pg, (1 + c) & 1, 0, L, kTimeOff);
+    }, out);
+}
+
+// Runs iterations until the device state (type S, with a `done` field) reports done:
+// graph replays of kPcgChunk iterations (exec), or without graphs direct launches in
+// growing chunks; `direct(parity, mode)` launches one iteration.  issued: iterations
+// launched so far (odd when exec is used).  The host checks the state one chunk behind.
+template <typename S, typename Direct>
+static int pcg_poll(Ctx* ctx, hipStream_t s, const S* st, hipGraphExec_t exec, long long issued,
+                    long long cap, Direct direct, S* result) {
+    void* pin = nullptr;
+    int rc = pinned_host(ctx, 2 * sizeof(S), &pin);
+    if (rc) return rc;
+    S* hs = (S*)pin;
+    hipEvent_t ev[2];
+    TOPO_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+    TOPO_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+    bool pending[2] = {false, false};
+    long long replays = 0;
+    int chunk = 4;
+    int slot = 0;
+    while (true) {
+        const int every = ctx->timing.every;
+        if (exec && !(every > 0 && replays % every == 0)) {
+            TOPO_HIP(hipGraphLaunch(exec, s));
+            issued += kPcgChunk;
+        } else if (exec) {
+            // timing sample: two directly launched, timed iterations (keeps the parity)
+            for (int c = 0; c < 2; ++c, ++issued) direct((int)(issued & 1), kTimeForced);
+        } else {
+            for (int c = 0; c < chunk; ++c, ++issued) direct((int)(issued & 1), kTimeSampled);
+            if (chunk < 64) chunk *= 2;
+        }
+        ++replays;
+        TOPO_CHECK_LAUNCH();
+        TOPO_HIP(hipMemcpyAsync(&hs[slot], st, sizeof(S), hipMemcpyDeviceToHost, s));
+        TOPO_HIP(hipEventRecord(ev[slot], s));
+        pending[slot] = true;
+        const int other = slot ^ 1;
+        bool stop = false;
+        if (pending[other]) {
+            TOPO_HIP(hipEventSynchronize(ev[other]));
+            pending[other] = false;
+            stop = hs[other].done != 0;
+        }
+        if (stop || issued >= cap) break;
+        slot = other;
+    }
+    TOPO_HIP(hipStreamSynchronize(s));
+    TOPO_HIP(hipEventDestroy(ev[0]));
+    TOPO_HIP(hipEventDestroy(ev[1]));
+    TOPO_HIP(hipMemcpyAsync(&hs[0], st, sizeof(S), hipMemcpyDeviceToHost, s));
+    TOPO_HIP(hipStreamSynchronize(s));
+    *result = hs[0];
+    return TOPO_OK;
+}
+
 // Runs PCG iterations until the device state reports done.  fresh: initialise from
 // w.b (x = 0) with stopping tolerance tol and maxit, and run iteration 0 (which records
 // ||b||^2); otherwise continue a segment whose state (done = 0, bb, tol2) the host has
@@ -842,10 +1179,6 @@ template <int DIM, typename T>
 static int pcg_run(Ctx* ctx, const Grid& g, PcgRun<DIM, T>& w, bool fresh, double tol, int maxit,
                    int iters0, hipStream_t s, PcgState* result) {
     const PcgGeom pg = pcg_geom(g);
-    void* pin = nullptr;
-    int rc = pinned_host(ctx, 2 * sizeof(PcgState), &pin);
-    if (rc) return rc;
-    PcgState* hs = (PcgState*)pin;
     LaunchSink L;
     L.s = s;
     long long issued;
@@ -867,56 +1200,112 @@ static int pcg_run(Ctx* ctx, const Grid& g, PcgRun<DIM, T>& w, bool fresh, doubl
     }
     TOPO_CHECK_LAUNCH();
     TOPO_HIP(L.err);
-    constexpr int CH = 16;  // iterations per graph replay (even)
     hipGraphExec_t exec = nullptr;
     if (graphs_enabled()) {
-        rc = pcg_graph<DIM, T>(ctx, g, w, pg, CH, &exec);
+        const int rc = pcg_graph<DIM, T>(ctx, g, w, pg, &exec);
         if (rc) return rc;
     }
-    hipEvent_t ev[2];
-    TOPO_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
-    TOPO_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
-    bool pending[2] = {false, false};
-    long long replays = 0;
-    int chunk = 4;
-    int slot = 0;
-    const long long cap = (long long)maxit + 4096;
-    while (true) {
-        const int every = ctx->timing.every;
-        if (exec && !(every > 0 && replays % every == 0)) {
-            TOPO_HIP(hipGraphLaunch(exec, s));
-            issued += CH;
-        } else if (exec) {
-            // timing sample: two directly launched, timed iterations (keeps the parity)
-            for (int c = 0; c < 2; ++c, ++issued)
-                pcg_iteration<DIM, T>(ctx, g, w, pg, (int)(issued & 1), 0, L, kTimeForced);
-        } else {
-            for (int c = 0; c < chunk; ++c, ++issued)
-                pcg_iteration<DIM, T>(ctx, g, w, pg, (int)(issued & 1), 0, L, kTimeSampled);
-            if (chunk < 64) chunk *= 2;
-        }
-        ++replays;
-        TOPO_CHECK_LAUNCH();
-        TOPO_HIP(L.err);
-        TOPO_HIP(hipMemcpyAsync(&hs[slot], w.st, sizeof(PcgState), hipMemcpyDeviceToHost, s));
-        TOPO_HIP(hipEventRecord(ev[slot], s));
-        pending[slot] = true;
-        const int other = slot ^ 1;
-        bool stop = false;
-        if (pending[other]) {
-            TOPO_HIP(hipEventSynchronize(ev[other]));
-            pending[other] = false;
-            stop = hs[other].done != 0;
-        }
-        if (stop || issued >= cap) break;
-        slot = other;
+    auto direct = [&](int parity, int mode) { pcg_iteration<DIM, T>(ctx, g, w, pg, parity, 0, L, mode); };
+    const int rc = pcg_poll<PcgState>(ctx, s, w.st, exec, issued, (long long)maxit + 4096, direct, result);
+    if (rc) return rc;
+    TOPO_HIP(L.err);
+    return TOPO_OK;
+}
+
+// ----------------------------------------------------------------------------------
+// Host side of the 2D one-reduction recursion (k_cg1_step2).
+// ----------------------------------------------------------------------------------
+template <typename T>
+struct Cg1Run {
+    const T* alpha;
+    const T* K;
+    const uint8_t* mask;
+    const T* winv;
+    T ik[2];
+    T* b;
+    T *R[2], *W[2], *S[2];  // r, w = K D^{-1} r, s = K p by parity
+    T* P;
+    double* x;
+    double* part;
+    Cg1State* st;
+    int nb, npart, ps;  // blocks, partials each block sums, partial stride
+};
+
+// Collapse the partials of parity par (and the u.s / p.s ones of a replacement) when the
+// launch had more blocks than kPcgMaxBlocks.
+template <typename T>
+static void cg1_sum(const Cg1Run<T>& w, int par, bool extra, LaunchSink& L) {
+    if (w.npart != 1 || w.nb <= 1) return;
+    const int* done = &w.st->done;
+    const size_t ps = (size_t)w.ps;
+    L((const void*)k_partials_sum, dim3(1), dim3(1024), w.part + par * ps, w.part + (2 + par) * ps, w.nb, done);
+    L((const void*)k_partials_sum, dim3(1), dim3(1024), w.part + (4 + par) * ps,
+      extra ? w.part + 6 * ps : (double*)nullptr, w.nb, done);
+    if (extra)
+        L((const void*)k_partials_sum, dim3(1), dim3(1024), w.part + 7 * ps, (double*)nullptr, w.nb, done);
+}
+
+template <typename T>
+static void cg1_step(Ctx* ctx, const Grid& g, const Cg1Run<T>& w, int parity, int kind, LaunchSink& L,
+                     int timing) {
+    const int nxt = parity ^ 1;
+    {
+        TimedLaunch tl(ctx, KID_PCG_STEP, L.s, L.graph ? kTimeOff : timing, true);
+        L.ev0 = tl.a;
+        L.ev1 = tl.b;
+        const void* fn = kind == kCg1Fresh       ? (const void*)k_cg1_step2<T, kCg1Fresh>
+                         : kind == kCg1Continued ? (const void*)k_cg1_step2<T, kCg1Continued>
+                                                 : (const void*)k_cg1_step2<T, kCg1Step>;
+        L(fn, dim3(w.nb), dim3(kPcgBlock), g, w.alpha, w.K, w.mask, w.winv, w.ik[0], w.ik[1],
+          (const T*)w.R[parity], (const T*)w.W[parity], (const T*)w.S[parity], w.R[nxt], w.W[nxt],
+          w.S[nxt], w.P, w.x, w.part, w.st, w.ps, w.npart, parity, 0, 0.0);
     }
-    TOPO_HIP(hipStreamSynchronize(s));
-    TOPO_HIP(hipEventDestroy(ev[0]));
-    TOPO_HIP(hipEventDestroy(ev[1]));
-    TOPO_HIP(hipMemcpyAsync(&hs[0], w.st, sizeof(PcgState), hipMemcpyDeviceToHost, s));
-    TOPO_HIP(hipStreamSynchronize(s));
-    *result = hs[0];
+    cg1_sum(w, nxt, false, L);
+}
+
+// The one-reduction counterpart of pcg_run: fresh (init from w.b, then a first step with
+// beta = 0) or continued after k_cg1_replace2 has written set iters0 & 1.
+template <typename T>
+static int cg1_run(Ctx* ctx, const Grid& g, Cg1Run<T>& w, bool fresh, double tol, int maxit, int iters0,
+                   hipStream_t s, Cg1State* result) {
+    LaunchSink L;
+    L.s = s;
+    long long issued;
+    if (fresh) {
+        L((const void*)k_cg1_step2<T, kCg1Init>, dim3(w.nb), dim3(kPcgBlock), g, w.alpha, w.K, w.mask,
+          w.winv, w.ik[0], w.ik[1], (const T*)w.b, (const T*)nullptr, (const T*)nullptr, w.R[0], w.W[0],
+          w.S[0], w.P, w.x, w.part, w.st, w.ps, w.npart, 1, maxit, tol * tol);
+        cg1_sum(w, 0, false, L);
+        cg1_step(ctx, g, w, 0, kCg1Fresh, L, kTimeSampled);
+        issued = 1;
+    } else {
+        cg1_step(ctx, g, w, iters0 & 1, kCg1Continued, L, kTimeSampled);
+        issued = iters0 + 1;
+        if ((issued & 1) == 0) {  // graphs start at an odd iteration
+            cg1_step(ctx, g, w, 0, kCg1Step, L, kTimeSampled);
+            ++issued;
+        }
+    }
+    TOPO_CHECK_LAUNCH();
+    TOPO_HIP(L.err);
+    hipGraphExec_t exec = nullptr;
+    if (graphs_enabled()) {
+        std::vector<uintptr_t> key = {(uintptr_t)0xC61, sizeof(T), (uintptr_t)w.nb, (uintptr_t)w.npart,
+                                      (uintptr_t)w.ps, (uintptr_t)kPcgChunk, (uintptr_t)g.nx, (uintptr_t)g.ny,
+                                      (uintptr_t)w.alpha, (uintptr_t)w.K, (uintptr_t)w.mask, (uintptr_t)w.winv,
+                                      (uintptr_t)w.R[0], (uintptr_t)w.R[1], (uintptr_t)w.W[0], (uintptr_t)w.W[1],
+                                      (uintptr_t)w.S[0], (uintptr_t)w.S[1], (uintptr_t)w.P, (uintptr_t)w.x,
+                                      (uintptr_t)w.part, (uintptr_t)w.st};
+        for (int c = 0; c < 2; ++c) key_push_double(key, (double)w.ik[c]);
+        const int rc = cached_graph(ctx, key, [&](LaunchSink& G) {
+            for (int c = 0; c < kPcgChunk; ++c) cg1_step(ctx, g, w, (1 + c) & 1, kCg1Step, G, kTimeOff);
+        }, &exec);
+        if (rc) return rc;
+    }
+    auto direct = [&](int parity, int mode) { cg1_step(ctx, g, w, parity, kCg1Step, L, mode); };
+    const int rc = pcg_poll<Cg1State>(ctx, s, w.st, exec, issued, (long long)maxit + 4096, direct, result);
+    if (rc) return rc;
+    TOPO_HIP(L.err);
     return TOPO_OK;
 }
 
@@ -928,6 +1317,19 @@ static double replace_drift_max() {
         return e ? std::atof(e) : 4.0;
     }();
     return v;
+}
+
+// Whether a 2D solve runs the one-reduction recursion (one kernel per iteration):
+// float64 solves do; float32 solves keep the two-kernel recursion, whose recursively
+// updated residual stays closer to the true one in float32 (the one-reduction form also
+// updates s = K p recursively, and at 241k DOF needed 2.4x the iterations in float32).
+// TOPO_PCG_ONE_REDUCTION=1 / 0 selects it for both precisions / for neither.
+static bool one_reduction(bool fp64) {
+    static const int mode = [] {
+        const char* e = std::getenv("TOPO_PCG_ONE_REDUCTION");
+        return e && e[0] ? std::atoi(e) : -1;
+    }();
+    return mode < 0 ? fp64 : mode != 0;
 }
 
 // Reduction of the residual a float32 segment aims for before its residual is replaced
@@ -970,8 +1372,10 @@ template <typename T>
 struct HdmWs {
     double *a64, *w64, *r64, *part, *rpart, *rout, *x;
     T *b, *r, *z, *p0, *p1, *q;
+    T *e0 = nullptr, *e1 = nullptr;  // 2D: the one-reduction recursion's two further vectors
     float *a32 = nullptr, *w32 = nullptr;
     PcgState* st;
+    Cg1State* st1;
 };
 
 template <typename T>
@@ -985,10 +1389,11 @@ static void hdm_takes(Arena& ar, const Grid& g, bool mixed, HdmWs<T>& w) {
         ar.take(&w.w32, g.n_nodes);
     }
     ar.take(&w.r64, N);
-    ar.take(&w.part, 5 * (size_t)nb);
+    ar.take(&w.part, 8 * (size_t)nb);  // 5 arrays in 3D, 8 in 2D
     ar.take(&w.rpart, 3 * (size_t)nb);
     ar.take(&w.rout, 4);
     ar.take(&w.st, 1);
+    ar.take(&w.st1, 1);
     ar.take(&w.b, N);
     ar.take(&w.x, N);
     ar.take(&w.r, N);
@@ -996,6 +1401,10 @@ static void hdm_takes(Arena& ar, const Grid& g, bool mixed, HdmWs<T>& w) {
     ar.take(&w.p0, N);
     ar.take(&w.p1, N);
     ar.take(&w.q, N);
+    if (g.dim == 2) {
+        ar.take(&w.e0, N);
+        ar.take(&w.e1, N);
+    }
 }
 
 size_t ws_hdm_solve(const Grid& g, bool mixed) {
@@ -1061,11 +1470,12 @@ static int hdm_solve_impl(Ctx* ctx, const topo_mesh& m, const Grid& g0, const El
     w.st = st;
 
     TOPO_HIP(hipMemsetAsync(u, 0, N * sizeof(double), s));
-    // pinned host layout: [2 PcgState poll slots | 4 residual sums | PcgState upload]
-    const size_t pin_res = 2 * sizeof(PcgState);
+    // pinned host layout: [2 state poll slots | 4 residual sums | state upload]
+    constexpr size_t kStateBytes = sizeof(PcgState) > sizeof(Cg1State) ? sizeof(PcgState) : sizeof(Cg1State);
+    const size_t pin_res = 2 * kStateBytes;
     const size_t pin_up = pin_res + 4 * sizeof(double);
     void* pin = nullptr;
-    rc = pinned_host(ctx, pin_up + sizeof(PcgState), &pin);
+    rc = pinned_host(ctx, pin_up + kStateBytes, &pin);
     if (rc) return rc;
     auto residual = [&](double out[3]) -> int {
         int rc2 = residual_launch(ctx, g, g.dim == 2 ? tb->K64 : tb->M64, a64, mask, u, f, r64, 1, rpart, rout, s);
@@ -1095,7 +1505,59 @@ static int hdm_solve_impl(Ctx* ctx, const topo_mesh& m, const Grid& g0, const El
     int total = 0, base = 0, segments = 0, status = TOPO_OK;
     bool fresh = true;
     double rr = res[0], rr_prev = INFINITY;
-    PcgState fin{};
+    // 2D: the one-reduction recursion (one kernel per iteration)
+    const bool one_red = DIM == 2 && one_reduction(sizeof(T) == 8);
+    Cg1Run<T> w1{};
+    if (one_red) {
+        w1.alpha = w.alpha;
+        w1.K = w.K;
+        w1.mask = mask;
+        w1.winv = w.winv;
+        w1.ik[0] = w.ik[0];
+        w1.ik[1] = w.ik[1];
+        w1.b = b;
+        w1.R[0] = r;
+        w1.R[1] = z;
+        w1.W[0] = q;
+        w1.W[1] = ws.e0;
+        w1.S[0] = p0;
+        w1.S[1] = p1;
+        w1.P = ws.e1;
+        w1.x = x;
+        w1.part = part;
+        w1.st = ws.st1;
+        w1.nb = grid_blocks(g.n_nodes, kPcgBlock);
+        w1.npart = w1.nb > kPcgMaxBlocks ? 1 : w1.nb;
+        w1.ps = pg.ps;
+    }
+    struct {
+        int done, iters;
+        double rr, bb;
+    } fin{};
+    double last_rz[2] = {0.0, 0.0};  // 3D: r.z of the last two iterations of a segment
+    // one segment of the recursion; its end state goes to fin
+    auto run_segment = [&](bool fr, double tol, int mi, int it0) -> int {
+        if (one_red) {
+            Cg1State st1{};
+            const int rc2 = cg1_run<T>(ctx, g, w1, fr, tol, mi, it0, s, &st1);
+            if (rc2) return rc2;
+            fin.done = st1.done;
+            fin.iters = std::max(st1.iters[0], st1.iters[1]);
+            fin.rr = st1.rr;
+            fin.bb = st1.bb;
+        } else {
+            PcgState st0{};
+            const int rc2 = pcg_run<DIM, T>(ctx, g, w, fr, tol, mi, it0, s, &st0);
+            if (rc2) return rc2;
+            fin.done = st0.done;
+            fin.iters = st0.iters;
+            fin.rr = st0.rr;
+            fin.bb = st0.bb;
+            last_rz[0] = st0.rz[0];
+            last_rz[1] = st0.rz[1];
+        }
+        return TOPO_OK;
+    };
     while (true) {
         const double rel = nf > 0.0 ? std::sqrt(rr) / nf : 0.0;
         if (rel <= rtol) break;
@@ -1115,7 +1577,27 @@ static int hdm_solve_impl(Ctx* ctx, const topo_mesh& m, const Grid& g0, const El
             hipLaunchKernelGGL((k_scale_cast<T>), dim3(bl), dim3(kBlock), 0, s, N, r64, scale, b);
             TOPO_CHECK_LAUNCH();
             base = total;
-            rc = pcg_run<DIM, T>(ctx, g, w, true, tol_seg, maxit - base, 0, s, &fin);
+            rc = run_segment(true, tol_seg, maxit - base, 0);
+        } else if (one_red) {
+            Cg1State* up = (Cg1State*)((char*)pin + pin_up);
+            *up = Cg1State{};
+            up->bb = rr * scale * scale;
+            up->rr = up->bb;
+            up->tol2 = tol_seg * tol_seg;
+            up->done = 0;
+            up->maxit = maxit - base;
+            up->iters[0] = up->iters[1] = fin.iters;
+            TOPO_HIP(hipMemcpyAsync(w1.st, up, sizeof(Cg1State), hipMemcpyHostToDevice, s));
+            const int cur = fin.iters & 1;
+            hipLaunchKernelGGL((k_cg1_replace2<T>), dim3(w1.nb), dim3(kPcgBlock), 0, s, g, w1.alpha, w1.K,
+                               mask, w1.winv, w1.ik[0], w1.ik[1], (const double*)r64, scale,
+                               (const T*)w1.P, w1.R[cur], w1.W[cur], w1.S[cur], x, part, pg.ps, cur);
+            TOPO_CHECK_LAUNCH();
+            LaunchSink L;
+            L.s = s;
+            cg1_sum(w1, cur, true, L);
+            TOPO_HIP(L.err);
+            rc = run_segment(false, tol_seg, maxit - base, fin.iters);
         } else {
             // state first (done = 0), so that the partial sums below are not skipped
             PcgState* up = (PcgState*)((char*)pin + pin_up);
@@ -1127,8 +1609,8 @@ static int hdm_solve_impl(Ctx* ctx, const topo_mesh& m, const Grid& g0, const El
             up->iters = fin.iters;
             up->maxit = maxit - base;
             // the replaced residual's apply takes beta against the last recursive rz
-            up->rz[0] = fin.rz[0];
-            up->rz[1] = fin.rz[1];
+            up->rz[0] = last_rz[0];
+            up->rz[1] = last_rz[1];
             TOPO_HIP(hipMemcpyAsync(st, up, sizeof(PcgState), hipMemcpyHostToDevice, s));
             hipLaunchKernelGGL((k_pcg_replace<DIM, T>), dim3(pg.nupd), dim3(kPcgBlock), 0, s, g,
                                (const double*)r64, scale, w.winv, w.ik[0], w.ik[1], w.ik[2], x, r, z,
@@ -1138,7 +1620,7 @@ static int hdm_solve_impl(Ctx* ctx, const topo_mesh& m, const Grid& g0, const El
             L.s = s;
             pcg_sum_rz(pg, part, (fin.iters + 1) & 1, st, L);
             TOPO_HIP(L.err);
-            rc = pcg_run<DIM, T>(ctx, g, w, false, tol_seg, maxit - base, fin.iters, s, &fin);
+            rc = run_segment(false, tol_seg, maxit - base, fin.iters);
         }
         if (rc) return rc;
         const int seg_iters = base + fin.iters - total;

@@ -71,7 +71,7 @@ bool element_factor(const topo_mesh& m, const std::vector<double>& K, std::vecto
 // ----------------------------------------------------------------------------------
 enum KernelId {
     KID_APPLY, KID_PCG_APPLY, KID_PCG_UPDATE, KID_RESIDUAL, KID_ROM_CONTRACT, KID_ROM_REDUCE,
-    KID_PHIT_V, KID_PHI_Y, KID_CHOL, KID_CHOL_SOLVE, KID_GRADIENT, KID_COUNT
+    KID_PHIT_V, KID_PHI_Y, KID_CHOL, KID_CHOL_SOLVE, KID_GRADIENT, KID_PCG_STEP, KID_COUNT
 };
 extern const char* const kKernelNames[KID_COUNT];
 

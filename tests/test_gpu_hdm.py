@@ -144,3 +144,27 @@ def test_invalid_arguments():
         ctx().hdm_solve(p.mesh, r, m, f, rtol=0.0)
     with pytest.raises(TopoError):
         ctx().hdm_solve(p.mesh, r, m, f, maxit=0)
+
+
+def test_large_2d_solve_with_collapsed_partials():
+    """1200 x 1000 elements (1.2M nodes, 2.4M DOFs): the PCG launches have more than 2048
+    blocks, so one summing kernel collapses their per-block partials before the next
+    launch reads them.  The float64 solve (one kernel per iteration) and the mixed one
+    (two kernels per iteration) both meet the stopping rule on the true residual, which
+    the oracle recomputes from its assembled K, and agree on the compliance."""
+    torch = torch_cuda()
+    p = W.cantilever2d(1200, 1000)
+    assert (p.mesh.n_nodes + 511) // 512 > 2048
+    rho = W.rho_smoothed(p.mesh, 77)
+    rtol = 1e-8
+    K = O.assemble(p.mesh, rho)
+    free = p.mask == 0
+    comp = {}
+    for prec in ("fp64", "mixed"):
+        u, info, _ = _solve(p, rho, prec, rtol)
+        assert info["status"] == 0 and info["rel_resid"] <= rtol
+        ug = host(u)
+        res = np.linalg.norm((p.f - K @ ug)[free]) / np.linalg.norm(p.f)
+        assert res <= rtol * 1.01
+        comp[prec] = info["compliance_corr"]
+    assert abs(comp["mixed"] / comp["fp64"] - 1) <= 1e-8
