@@ -689,6 +689,33 @@ __global__ __launch_bounds__(kPcgBlock) void k_cg1_step2(
     }
 }
 
+// s = K p recomputed for the direction of the last step, into the set that step wrote.
+// The recursion s_i = w_i + beta_i s_{i-1} carries each rounding of K u through about
+// 1 / (1 - beta) iterations (beta ~ 0.98 here), which in float32 lets the recursive
+// residual drift from the true one; refreshing s every kPcgChunk iterations bounds
+// that sum.  Reads p (neighbourhood) only and writes s (own node).
+template <typename T>
+__global__ __launch_bounds__(kPcgBlock) void k_cg1_refresh2(Grid g, const T* __restrict__ alpha,
+                                                         const T* __restrict__ K,
+                                                         const uint8_t* __restrict__ mask,
+                                                         const T* __restrict__ P, T* __restrict__ S,
+                                                         const Cg1State* st) {
+    if (st->done) return;
+    const int n = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (n >= g.n_nodes) return;
+    int i, j, k;
+    node_ijk(g, n, i, j, k);
+    T ps_[3][3][2], al[2][2], out[2];
+    load_nbhd2(g, i, j, FetchPlain<T>{P, g.n_nodes}, ps_);
+    load_alpha2(g, i, j, alpha, al);
+    apply_nbhd2(K, ps_, al, out);
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const size_t idx = (size_t)c * g.n_nodes + n;
+        S[idx] = mask[idx] ? T(0) : out[c];
+    }
+}
+
 // Residual replacement of the one-reduction recursion: r = scale * r64 (the float64 true
 // residual), u = D^{-1} r, w = K u, and s = K p computed exactly for the kept direction
 // p, written to set `cur` with x = 0; partials of gamma, delta, rr (parity cur) and of
@@ -1119,7 +1146,7 @@ static int pcg_graph(Ctx* ctx, const Grid& g, const PcgRun<DIM, T>& w, const Pcg
 
 // Runs iterations until the device state (type S, with a `done` field) reports done:
 // graph replays of kPcgChunk iterations (exec), or without graphs direct launches in
-// growing chunks; `direct(parity, mode)` launches one iteration.  issued: iterations
+// growing chunks; `direct(it, mode)` launches iteration it (parity it & 1).  issued: iterations
 // launched so far (odd when exec is used).  The host checks the state one chunk behind.
 template <typename S, typename Direct>
 static int pcg_poll(Ctx* ctx, hipStream_t s, const S* st, hipGraphExec_t exec, long long issued,
@@ -1142,9 +1169,9 @@ static int pcg_poll(Ctx* ctx, hipStream_t s, const S* st, hipGraphExec_t exec, l
             issued += kPcgChunk;
         } else if (exec) {
             // timing sample: two directly launched, timed iterations (keeps the parity)
-            for (int c = 0; c < 2; ++c, ++issued) direct((int)(issued & 1), kTimeForced);
+            for (int c = 0; c < 2; ++c, ++issued) direct(issued, kTimeForced);
         } else {
-            for (int c = 0; c < chunk; ++c, ++issued) direct((int)(issued & 1), kTimeSampled);
+            for (int c = 0; c < chunk; ++c, ++issued) direct(issued, kTimeSampled);
             if (chunk < 64) chunk *= 2;
         }
         ++replays;
@@ -1205,7 +1232,7 @@ static int pcg_run(Ctx* ctx, const Grid& g, PcgRun<DIM, T>& w, bool fresh, doubl
         const int rc = pcg_graph<DIM, T>(ctx, g, w, pg, &exec);
         if (rc) return rc;
     }
-    auto direct = [&](int parity, int mode) { pcg_iteration<DIM, T>(ctx, g, w, pg, parity, 0, L, mode); };
+    auto direct = [&](long long it, int mode) { pcg_iteration<DIM, T>(ctx, g, w, pg, (int)(it & 1), 0, L, mode); };
     const int rc = pcg_poll<PcgState>(ctx, s, w.st, exec, issued, (long long)maxit + 4096, direct, result);
     if (rc) return rc;
     TOPO_HIP(L.err);
@@ -1247,7 +1274,7 @@ static void cg1_sum(const Cg1Run<T>& w, int par, bool extra, LaunchSink& L) {
 
 template <typename T>
 static void cg1_step(Ctx* ctx, const Grid& g, const Cg1Run<T>& w, int parity, int kind, LaunchSink& L,
-                     int timing) {
+                     int timing, bool refresh = false) {
     const int nxt = parity ^ 1;
     {
         TimedLaunch tl(ctx, KID_PCG_STEP, L.s, L.graph ? kTimeOff : timing, true);
@@ -1261,6 +1288,9 @@ static void cg1_step(Ctx* ctx, const Grid& g, const Cg1Run<T>& w, int parity, in
           w.S[nxt], w.P, w.x, w.part, w.st, w.ps, w.npart, parity, 0, 0.0);
     }
     cg1_sum(w, nxt, false, L);
+    if (refresh)
+        L((const void*)k_cg1_refresh2<T>, dim3(w.nb), dim3(kPcgBlock), g, w.alpha, w.K, w.mask, (const T*)w.P,
+          w.S[nxt], (const Cg1State*)w.st);
 }
 
 // The one-reduction counterpart of pcg_run: fresh (init from w.b, then a first step with
@@ -1298,11 +1328,15 @@ static int cg1_run(Ctx* ctx, const Grid& g, Cg1Run<T>& w, bool fresh, double tol
                                       (uintptr_t)w.part, (uintptr_t)w.st};
         for (int c = 0; c < 2; ++c) key_push_double(key, (double)w.ik[c]);
         const int rc = cached_graph(ctx, key, [&](LaunchSink& G) {
-            for (int c = 0; c < kPcgChunk; ++c) cg1_step(ctx, g, w, (1 + c) & 1, kCg1Step, G, kTimeOff);
+            for (int c = 0; c < kPcgChunk; ++c)
+                cg1_step(ctx, g, w, (1 + c) & 1, kCg1Step, G, kTimeOff, c == kPcgChunk - 1);
         }, &exec);
         if (rc) return rc;
     }
-    auto direct = [&](int parity, int mode) { cg1_step(ctx, g, w, parity, kCg1Step, L, mode); };
+    // iteration it refreshes s when it ends a chunk of kPcgChunk (as the graph's last step)
+    auto direct = [&](long long it, int mode) {
+        cg1_step(ctx, g, w, (int)(it & 1), kCg1Step, L, mode, (it % kPcgChunk) == 0);
+    };
     const int rc = pcg_poll<Cg1State>(ctx, s, w.st, exec, issued, (long long)maxit + 4096, direct, result);
     if (rc) return rc;
     TOPO_HIP(L.err);
