@@ -263,8 +263,8 @@ __device__ __forceinline__ int pcg_apply_scalars(double* part, PcgState* st, int
     return code;
 }
 
-// 2D: grid-stride over nodes.  The loads of a thread's first node are issued before it
-// waits on the scalar reduction.
+// 2D: one node per thread (the launch covers every node).  The node's loads are issued
+// before it waits on the scalar reduction.
 template <typename T>
 __global__ __launch_bounds__(kPcgBlock) void k_pcg_apply2(Grid g, const T* __restrict__ alpha,
                                                        const T* __restrict__ K,
@@ -276,24 +276,23 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_apply2(Grid g, const T* __res
                                                        int ps, int nupd, int parity, int first) {
     if (st->done) return;
     __shared__ double lds[48];
-    const int stride = gridDim.x * blockDim.x;
-    int n = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const int n = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const bool own = n < g.n_nodes;
     T zs[3][3][2], ps_[3][3][2], al[2][2];
     uint8_t mk[2];
-    auto load = [&](int node) {
+    if (own) {
         int i, j, k;
-        node_ijk(g, node, i, j, k);
+        node_ijk(g, n, i, j, k);
         load_nbhd2(g, i, j, FetchPlain<T>{z, g.n_nodes}, zs);
         load_nbhd2(g, i, j, FetchPlain<T>{p_old, g.n_nodes}, ps_);
         load_alpha2(g, i, j, alpha, al);
 #pragma unroll
-        for (int c = 0; c < 2; ++c) mk[c] = mask[(size_t)c * g.n_nodes + node];
-    };
-    if (n < g.n_nodes) load(n);
+        for (int c = 0; c < 2; ++c) mk[c] = mask[(size_t)c * g.n_nodes + n];
+    }
     T tb;
     if (pcg_apply_scalars(part, st, ps, nupd, parity, first, tb, lds)) return;
     double v[1] = {0.0};
-    while (n < g.n_nodes) {
+    if (own) {
         T out[2], pn[2];
         T xs[3][3][2];
 #pragma unroll
@@ -313,8 +312,6 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_apply2(Grid g, const T* __res
             q[idx] = qv;
             v[0] += (double)pn[c] * (double)qv;
         }
-        n += stride;
-        if (n < g.n_nodes) load(n);
     }
     block_reduce<1>(v, lds);
     if (threadIdx.x == 0) part[blockIdx.x] = v[0];
@@ -360,6 +357,8 @@ __global__ __launch_bounds__(kBlock) void k_pcg_apply3(Grid g, const T* __restri
     if (threadIdx.x == 0) part[blockIdx.x] = v[0];
 }
 
+// One node per thread (the launch covers every node); the node's loads are issued
+// before the wait on the scalar reduction.
 template <int DIM, typename T>
 __global__ __launch_bounds__(kPcgBlock) void k_pcg_update(Grid g, const T* __restrict__ winv,
                                                        T ik0, T ik1, T ik2, double* __restrict__ x,
@@ -370,23 +369,21 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_update(Grid g, const T* __res
                                                        int ps, int npq, int parity) {
     if (st->done) return;
     __shared__ double lds[32];
-    const int stride = gridDim.x * blockDim.x;
-    int n = blockIdx.x * blockDim.x + threadIdx.x;
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool own = n < g.n_nodes;
     double xv[DIM];
     T rv[DIM], pv[DIM], qv[DIM], w = T(0);
-    auto load = [&](int node) {
-        w = winv[node];
+    if (own) {
+        w = winv[n];
 #pragma unroll
         for (int c = 0; c < DIM; ++c) {
-            const size_t i = (size_t)c * g.n_nodes + node;
+            const size_t i = (size_t)c * g.n_nodes + n;
             xv[c] = x[i];
             rv[c] = r[i];
             pv[c] = p[i];
             qv[c] = q[i];
         }
-    };
-    // issue the first node's loads before waiting on the scalar reduction
-    if (n < g.n_nodes) load(n);
+    }
     const double pq = block_sum_array(part, npq, lds);
     if (!(pq > 0.0) || !isfinite(pq)) {
         if (blockIdx.x == 0 && threadIdx.x == 0) st->done = 3;
@@ -395,7 +392,7 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_update(Grid g, const T* __res
     const T a = (T)(st->rz[parity] / pq);
     const T ik[3] = {ik0, ik1, ik2};
     double v[2] = {0.0, 0.0};
-    while (n < g.n_nodes) {
+    if (own) {
 #pragma unroll
         for (int c = 0; c < DIM; ++c) {
             const size_t i = (size_t)c * g.n_nodes + n;
@@ -407,8 +404,6 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_update(Grid g, const T* __res
             v[0] += (double)ri * (double)zi;
             v[1] += (double)ri * (double)ri;
         }
-        n += stride;
-        if (n < g.n_nodes) load(n);
     }
     block_reduce<2>(v, lds);
     if (threadIdx.x == 0) {
