@@ -168,3 +168,28 @@ def test_large_2d_solve_with_collapsed_partials():
         assert res <= rtol * 1.01
         comp[prec] = info["compliance_corr"]
     assert abs(comp["mixed"] / comp["fp64"] - 1) <= 1e-8
+
+
+@pytest.mark.parametrize("nel", [(1, 1), (1, 7), (9, 1), (2, 3), (31, 2)], ids=str)
+@pytest.mark.parametrize("kind", ["cantilever2d", "mbb2d"])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_2d_solve_on_degenerate_shapes(nel, kind, prec):
+    """Meshes one element wide or tall, where every node's 3x3 neighbourhood is cut by the
+    grid boundary (the one-kernel float64 recursion rebuilds D^-1 r there), against the
+    oracle's direct solve.  With ||f - K u|| <= rtol ||f|| the error in u is at most
+    kappa(K_ff) rtol relative (kappa from the oracle's assembled matrix); the bound used is
+    10 kappa rtol, and the same for the residual-corrected compliance.  rtol = 1e-10: the
+    31 x 2 strip (kappa ~ 3e6) has its float64 true-residual floor near 1e-11."""
+    torch = torch_cuda()
+    p = getattr(W, kind)(*nel)
+    rho = W.rho_jitter(p.mesh, 5)
+    rtol = 1e-10
+    u, info, _ = _solve(p, rho, prec, rtol)
+    assert info["status"] == 0 and info["rel_resid"] <= rtol
+    uo = O.solve_direct(p.mesh, rho, p.f, p.mask)
+    co = O.compliance(p.f, uo)
+    free = p.mask == 0
+    ev = np.linalg.eigvalsh(O.assemble(p.mesh, rho).toarray()[np.ix_(free, free)])
+    tol = 10 * (ev[-1] / ev[0]) * rtol
+    assert rel(host(u), uo) <= tol
+    assert abs(info["compliance_corr"] / co - 1) <= max(tol, 1e-13)
