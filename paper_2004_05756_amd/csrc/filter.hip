@@ -16,6 +16,7 @@
 #include <algorithm>
 #include <cmath>
 
+#include "graphs.hpp"
 #include "internal.hpp"
 #include "reduce.hpp"
 
@@ -27,7 +28,8 @@ constexpr int kHelmBlock = 256;
 template <int DIM>
 constexpr int helm_npt() { return DIM == 3 ? 4 : 1; }
 constexpr int kHelmCheck = 8;
-constexpr int kHelmScal = 8;  // per-field scalars: rz (two copies), -, rr, bb, active, -, - (initial values)
+constexpr int kHelmScal = 12;  // per-field scalars: rz (two copies), -, rr, bb, active, -, - (initial values);
+                               // 2D one-reduction recursion: gamma by parity (8, 9), alpha by parity (10, 11)
 
 // Element Helmholtz matrix of the box element, local node order x fastest.
 struct HelmElem {
@@ -419,6 +421,115 @@ __global__ __launch_bounds__(kHelmBlock) void k_helm_update(Grid g, double diag,
     }
 }
 
+// 2D: one kernel per iteration (the one-reduction form of CG, as in the 2D elasticity
+// solve).  With u = D^-1 r, w = H u and s = H p carried by s_i = w_i + beta_i s_{i-1},
+// beta_i = gamma_i / gamma_{i-1} and alpha_i = gamma_i / (delta_i - beta_i gamma_i / alpha_{i-1})
+// (gamma = r.u, delta = w.u) come from the previous launch's partials.  A step rebuilds
+// u_{i+1} = D^-1 (r_i - alpha_i (w_i + beta_i s_{i-1})) on its node's neighbourhood, updates
+// s, r, p, x of its node (r, w, s double-buffered by parity) and forms w_{i+1} = H u_{i+1};
+// partials of gamma, delta and r.r of the new residual.  Stopped fields are left as they
+// are.  Block 0 of a field records gamma_i, alpha_i by parity (read back one step later).
+__global__ __launch_bounds__(kHelmBlock) void k_helm_step2(Grid g, HelmElem E, int first, int cur,
+                                                           const double* __restrict__ Rin,
+                                                           const double* __restrict__ Win,
+                                                           const double* __restrict__ Sin,
+                                                           double* __restrict__ Rout, double* __restrict__ Wout,
+                                                           double* __restrict__ Sout, double* __restrict__ P,
+                                                           double* __restrict__ x, double* __restrict__ sc,
+                                                           const double* __restrict__ gam_cur,
+                                                           const double* __restrict__ dlt_cur,
+                                                           double* __restrict__ gam_nxt, double* __restrict__ dlt_nxt,
+                                                           double* __restrict__ rr_nxt) {
+    __shared__ double lds[48];
+    double* f = sc + (size_t)blockIdx.y * kHelmScal;
+    if (f[5] == 0.0) return;
+    const int nb = gridDim.x;
+    const int n = xcd_block(blockIdx.x, nb) * kHelmBlock + threadIdx.x;
+    const size_t base = (size_t)blockIdx.y * g.n_nodes;
+    const double *rb = Rin + base, *wb = Win + base, *sb = Sin + base;
+    const bool in = n < g.n_nodes;
+    int i = 0, j = 0, k = 0;
+    if (in) node_ijk(g, n, i, j, k);
+    const bool interior = in && i > 0 && i < g.nx && j > 0 && j < g.ny;
+    // the node's loads (its 3 x 3 neighbourhood inside the grid) before the partial sums
+    double rn9[9], wn9[9], sn9[9];
+    double pv = 0.0, xv = 0.0;
+    if (interior) {
+#pragma unroll
+        for (int dj = -1; dj <= 1; ++dj)
+#pragma unroll
+            for (int di = -1; di <= 1; ++di) {
+                const int m = n + di + g.nx1 * dj;
+                rn9[4 + di + 3 * dj] = rb[m];
+                wn9[4 + di + 3 * dj] = wb[m];
+                sn9[4 + di + 3 * dj] = sb[m];
+            }
+    } else if (in) {
+        rn9[4] = rb[n];
+        wn9[4] = wb[n];
+        sn9[4] = sb[n];
+    }
+    if (in) {
+        pv = P[base + n];
+        xv = x[base + n];
+    }
+    const double* arrs[2] = {gam_cur + (size_t)blockIdx.y * nb, dlt_cur + (size_t)blockIdx.y * nb};
+    double red[2];
+    block_sum_arrays<2>(arrs, nb, red, lds);
+    const double gam = red[0], dlt = red[1];
+    const int prv = cur ^ 1;
+    double be = 0.0, den = dlt;
+    if (!first) {
+        const double gp = f[8 + prv], ap = f[10 + prv];
+        be = gp != 0.0 ? gam / gp : 0.0;
+        den = dlt - (ap != 0.0 ? be * gam / ap : 0.0);
+    }
+    // alpha = 0 (no step) once gamma is exactly 0 or the denominator is not positive
+    double ah = den > 0.0 ? gam / den : 0.0;
+    if (!isfinite(ah) || !isfinite(be)) ah = be = 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        f[8 + cur] = gam;
+        f[10 + cur] = ah;
+    }
+    double v[3] = {0.0, 0.0, 0.0};
+    if (in) {
+        auto unew = [&](double r, double w, double s_, int ii, int jj) {
+            return (r - ah * (w + be * s_)) * helm_dinv(g, E.diag, ii, jj, 0);
+        };
+        const double si = wn9[4] + be * sn9[4];
+        const double rnew = rn9[4] - ah * si;
+        const double dv = helm_dinv(g, E.diag, i, j, 0);
+        const double uown = rnew * dv;
+        const double pn = rn9[4] * dv + be * pv;  // u_i + beta p_{i-1}
+        double wn = 0.0;
+        if (interior) {
+#pragma unroll
+            for (int e = 0; e < 9; ++e)
+                wn += E.S[13 + (e % 3 - 1) + 3 * (e / 3 - 1)] *
+                      unew(rn9[e], wn9[e], sn9[e], i + e % 3 - 1, j + e / 3 - 1);
+        } else {
+            wn = helm_row<2>(g, E, i, j, k, [&](int m) {
+                return unew(rb[m], wb[m], sb[m], m % g.nx1, m / g.nx1);
+            });
+        }
+        P[base + n] = pn;
+        x[base + n] = xv + ah * pn;
+        Sout[base + n] = si;
+        Rout[base + n] = rnew;
+        Wout[base + n] = wn;
+        v[0] = rnew * uown;
+        v[1] = wn * uown;
+        v[2] = rnew * rnew;
+    }
+    block_reduce<3>(v, lds);
+    if (threadIdx.x == 0) {
+        const size_t o = (size_t)blockIdx.y * nb + blockIdx.x;
+        gam_nxt[o] = v[0];
+        dlt_nxt[o] = v[1];
+        rr_nxt[o] = v[2];
+    }
+}
+
 // Chunk-sum epilogue of the initial residual into the per-field scalars.
 struct HelmInitOut {  // entries: r.z, r.r of the initial residual, b.b
     double* sc;
@@ -464,6 +575,7 @@ __global__ __launch_bounds__(kHelmBlock) void k_helm_check(int nb, double rtol2,
 struct HelmWork {
     double *bvec, *x, *r, *z, *p0, *p1, *q, *part, *sc;
     double *prz, *prr, *ppq;  // block partials of r.z and r.r ([2][B][nb], by iteration parity), p.q
+    double *e0, *e1, *pdl;    // 2D: two more vectors and the partials of w.u ([2][B][nb])
     int *cnt, *its;
 };
 
@@ -475,7 +587,7 @@ static int helm_solve(Ctx* ctx, const Grid& g, const HelmElem& E, int B, const H
     int *cnt = w.cnt, *its = w.its;
     const double* bvec = w.bvec;
     void* pin;
-    int rc = pinned_host(ctx, sizeof(int) * std::max(B, 1), &pin);
+    int rc = pinned_host(ctx, sizeof(int) * std::max(B, 2), &pin);
     if (rc) return rc;
     const dim3 grid(nb, B);
     const size_t BN = (size_t)B * nb;
@@ -490,45 +602,116 @@ static int helm_solve(Ctx* ctx, const Grid& g, const HelmElem& E, int B, const H
     hipLaunchKernelGGL(k_helm_start, dim3((B + 63) / 64), dim3(64), 0, s, B, rtol * rtol, sc);
     TOPO_CHECK_LAUNCH();
     TOPO_HIP(hipMemsetAsync(its, 0, sizeof(int) * B, s));
-    double* pold = p0;
-    double* pnew = p1;
     int it = 0, active = B;
-    auto check = [&](int at) -> int {
-        TOPO_HIP(hipMemsetAsync(cnt, 0, sizeof(int), s));
+    // One iteration's launches: 2D the one-kernel step (r, w, s double-buffered by parity,
+    // p in place), 3D the march apply and the update (p_old / p_new by parity).
+    double* R2[2] = {r, z};
+    double* W2[2] = {q, w.e0};
+    double* S2[2] = {p0, w.e1};
+    auto iteration = [&](LaunchSink& L, int at) {
+        const int cur = at & 1, nxt = cur ^ 1;
+        const int first = at == 0 ? 1 : 0;
+        if constexpr (DIM == 2) {
+            L((const void*)k_helm_step2, grid, dim3(kHelmBlock), g, E, first, cur, (const double*)R2[cur],
+              (const double*)W2[cur], (const double*)S2[cur], R2[nxt], W2[nxt], S2[nxt], p1, x, sc,
+              (const double*)(w.prz + (size_t)cur * BN), (const double*)(w.pdl + (size_t)cur * BN),
+              w.prz + (size_t)nxt * BN, w.pdl + (size_t)nxt * BN, w.prr + (size_t)nxt * BN);
+        } else {
+            double* pold = cur ? p1 : p0;
+            double* pnew = cur ? p0 : p1;
+            const double* rz_cur = w.prz + (size_t)cur * BN;
+            const double* rz_prev = w.prz + (size_t)nxt * BN;
+            L((const void*)k_helm_apply3m, dim3(nbm, B), dim3(kHelmBlock), g, E, hm, first, nb, rz_cur, rz_prev,
+              (const double*)z, (const double*)pold, pnew, q, w.ppq);
+            L((const void*)k_helm_update<3>, grid, dim3(kHelmBlock), g, E.diag, (const double*)sc, npq, rz_cur,
+              (const double*)w.ppq, (const double*)pnew, (const double*)q, x, r, z, w.prz + (size_t)nxt * BN,
+              w.prr + (size_t)nxt * BN);
+        }
+    };
+    // Graph of kHelmCheck iterations (even, so that every replay keeps the parity); the
+    // first chunk differs by its first iteration's flag.
+    auto chunk_graph = [&](bool first_chunk, hipGraphExec_t* out) -> int {
+        std::vector<uintptr_t> key = {(uintptr_t)0xF17, (uintptr_t)DIM, (uintptr_t)first_chunk, (uintptr_t)B,
+                                      (uintptr_t)g.nx, (uintptr_t)g.ny, (uintptr_t)g.nz, (uintptr_t)nb,
+                                      (uintptr_t)nbm, (uintptr_t)x, (uintptr_t)r, (uintptr_t)z, (uintptr_t)p0,
+                                      (uintptr_t)p1, (uintptr_t)q, (uintptr_t)w.e0, (uintptr_t)w.e1,
+                                      (uintptr_t)w.prz, (uintptr_t)w.prr, (uintptr_t)w.pdl, (uintptr_t)w.ppq,
+                                      (uintptr_t)sc};
+        uint64_t words[(sizeof(HelmElem) + 7) / 8] = {};
+        std::memcpy(words, &E, sizeof(HelmElem));
+        for (uint64_t v : words) key.push_back((uintptr_t)v);
+        return cached_graph(ctx, key, [&](LaunchSink& G) {
+            for (int c = 0; c < kHelmCheck; ++c) iteration(G, first_chunk ? c : kHelmCheck + c);
+        }, out);
+    };
+    // The check after a chunk stops the converged fields on the device (their later
+    // launches return at once) and counts the active ones; the host reads the count one
+    // chunk behind, so it never waits for the chunk it has just launched.
+    int* hp = (int*)pin;
+    hipEvent_t ev[2];
+    TOPO_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+    TOPO_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+    auto launch_check = [&](int at, int sl) -> int {
+        TOPO_HIP(hipMemsetAsync(cnt + sl, 0, sizeof(int), s));
         hipLaunchKernelGGL(k_helm_check, dim3(B), dim3(kHelmBlock), 0, s, nb, rtol * rtol, at,
-                           (const double*)(w.prr + (size_t)(at & 1) * BN), sc, cnt, its);
+                           (const double*)(w.prr + (size_t)(at & 1) * BN), sc, cnt + sl, its);
         TOPO_CHECK_LAUNCH();
-        TOPO_HIP(hipMemcpyAsync(pin, cnt, sizeof(int), hipMemcpyDeviceToHost, s));
-        TOPO_HIP(hipStreamSynchronize(s));
-        active = *(const int*)pin;
+        TOPO_HIP(hipMemcpyAsync(hp + sl, cnt + sl, sizeof(int), hipMemcpyDeviceToHost, s));
+        TOPO_HIP(hipEventRecord(ev[sl], s));
         return TOPO_OK;
     };
     if (warm) {  // a guess that already meets the tolerance needs no iteration
-        rc = check(0);
+        rc = launch_check(0, 0);
         if (rc) return rc;
+        TOPO_HIP(hipEventSynchronize(ev[0]));
+        active = hp[0];
     }
-    while (it < maxit && active > 0) {
-        const int cur = it & 1;
-        const double* rz_cur = w.prz + (size_t)cur * BN;
-        const double* rz_prev = w.prz + (size_t)(cur ^ 1) * BN;
-        if (DIM == 3)
-            hipLaunchKernelGGL(k_helm_apply3m, dim3(nbm, B), dim3(kHelmBlock), 0, s, g, E, hm, it == 0 ? 1 : 0, nb,
-                               rz_cur, rz_prev, (const double*)z, (const double*)pold, pnew, q, w.ppq);
-        else
-            hipLaunchKernelGGL(k_helm_apply<DIM>, grid, dim3(kHelmBlock), 0, s, g, E, it == 0 ? 1 : 0, nb, rz_cur,
-                               rz_prev, (const double*)z, (const double*)pold, pnew, q, w.ppq);
+    if (DIM == 2 && active > 0) {
+        // w_0 = H D^-1 r_0 and the partials of delta_0 = w_0 . u_0: the apply with beta = 0
+        // (p_old = S[0] is zero from the initialisation; p_new = z_0 lands in p, where the
+        // first step's beta = 0 meets it)
+        hipLaunchKernelGGL(k_helm_apply<2>, grid, dim3(kHelmBlock), 0, s, g, E, 1, nb, (const double*)w.prz,
+                           (const double*)w.prz, (const double*)z, (const double*)p0, p1, q, w.pdl);
         TOPO_CHECK_LAUNCH();
-        hipLaunchKernelGGL(k_helm_update<DIM>, grid, dim3(kHelmBlock), 0, s, g, E.diag, (const double*)sc, npq,
-                           rz_cur, (const double*)w.ppq, (const double*)pnew, (const double*)q, x, r, z,
-                           w.prz + (size_t)(cur ^ 1) * BN, w.prr + (size_t)(cur ^ 1) * BN);
-        TOPO_CHECK_LAUNCH();
-        std::swap(pold, pnew);
-        ++it;
-        if (it % kHelmCheck == 0 || it == maxit) {
-            rc = check(it);
+    }
+    LaunchSink L;
+    L.s = s;
+    bool pending[2] = {false, false};
+    int slot = 0;
+    while (active > 0 && it < maxit) {
+        const int n_it = std::min(kHelmCheck, maxit - it);
+        if (graphs_enabled() && n_it == kHelmCheck) {
+            hipGraphExec_t exec = nullptr;
+            rc = chunk_graph(it == 0, &exec);
             if (rc) return rc;
+            TOPO_HIP(hipGraphLaunch(exec, s));
+        } else {
+            for (int c = 0; c < n_it; ++c) iteration(L, it + c);
+            TOPO_HIP(L.err);
         }
+        it += n_it;
+        rc = launch_check(it, slot);
+        if (rc) return rc;
+        pending[slot] = true;
+        if (it >= maxit) {  // the last check decides
+            TOPO_HIP(hipEventSynchronize(ev[slot]));
+            active = hp[slot];
+            break;
+        }
+        const int other = slot ^ 1;
+        if (pending[other]) {
+            TOPO_HIP(hipEventSynchronize(ev[other]));
+            pending[other] = false;
+            if (hp[other] == 0) {
+                active = 0;
+                break;
+            }
+        }
+        slot = other;
     }
+    TOPO_HIP(hipStreamSynchronize(s));
+    TOPO_HIP(hipEventDestroy(ev[0]));
+    TOPO_HIP(hipEventDestroy(ev[1]));
     TOPO_HIP(hipMemcpyAsync(pin, its, sizeof(int) * B, hipMemcpyDeviceToHost, s));
     TOPO_HIP(hipStreamSynchronize(s));
     int mx = 0;
@@ -573,7 +756,12 @@ static int filter_run(Ctx* ctx, const topo_mesh& m, double r, const double* in, 
     ar.take(&w.prr, (size_t)2 * B * nb);
     ar.take(&w.ppq, (size_t)B * std::max(nb, DIM == 3 ? helm_march(g).tx * helm_march(g).ty * helm_march(g).chunks : 0));
     ar.take(&w.sc, (size_t)B * kHelmScal);
-    ar.take(&w.cnt, 1);
+    if (DIM == 2) {
+        ar.take(&w.e0, NV);
+        ar.take(&w.e1, NV);
+        ar.take(&w.pdl, (size_t)2 * B * nb);
+    }
+    ar.take(&w.cnt, 2);  // active-field counters of two checks in flight
     ar.take(&w.its, (size_t)B);
     int rc = ar.commit(ctx, s);
     if (rc) return rc;
