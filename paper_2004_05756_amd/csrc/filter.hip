@@ -6,13 +6,15 @@
 // Neumann boundary: no constrained node), w = |Omega_e| / nen the entries of b_e.  H is
 // symmetric, so both directions use one solver: Jacobi-PCG in float64, matrix-free.
 //
-// PCG per iteration: k_helm_apply forms the new direction p = z + beta p_old on the fly
-// for its stencil (p double-buffered) and q = H p with per-block partials of p . q;
-// k_helm_update advances x, r and z = D^-1 r with partials of r . z and r . r.  Each
+// PCG per iteration in 3D: k_helm_apply3m forms the new direction p = z + beta p_old on
+// the fly for its stencil (p double-buffered) and q = H p with per-block partials of
+// p . q; k_helm_update advances x, r and z = D^-1 r with partials of r . z and r . r.  In
+// 2D one kernel per iteration, k_helm_step2 (the single-reduction form of CG).  Each
 // kernel sums the partials it needs itself, every block in the same fixed order (the
-// r . z partials are kept for two iterations, by parity, for beta).  A field stops (its step length becomes 0) at the first
-// check, every kHelmCheck iterations, where |r| <= rtol |b|; the checks fall at the same
-// iterations whatever the batch, so a field's result does not depend on its batch.
+// partials are kept for two iterations, by parity).  A stopped field is left as it is
+// from the first check, every kHelmCheck iterations, where |r| <= rtol |b|; the checks
+// fall at the same iterations whatever the batch, so a field's result does not depend
+// on its batch.  The iterations between checks are replayed as one graph.
 #include <algorithm>
 #include <cmath>
 
