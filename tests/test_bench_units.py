@@ -1,0 +1,37 @@
+"""Host-side units of bench.py: the algorithmic bytes of one launch of each PCG kernel,
+counted array by array, and the kernel names under which the measured HBM traffic of
+the committed counter summary is looked up."""
+import json
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_pcg_bytes_count_every_array_once():
+    nu, nn, ne = 2 * 35, 35, 24  # a 6 x 4 element Q4 mesh
+    for w in (4, 8):
+        b = bench.pcg_bytes(nu, nn, ne, w)
+        # step: r, w, s, p read (4 w), mask (1), x read + written (16); r, w, s, p written
+        # (4 w); alpha per element, 1 / sum(alpha) per node
+        assert b["pcg_step"] == nu * (4 * w + 1 + 16 + 4 * w) + nn * w + ne * w
+        # apply: z, p_old read, p_new, q written, mask; alpha per element
+        assert b["pcg_apply"] == nu * (2 * w + 2 * w + 1) + ne * w
+        # update: x read + written (16), r read + written, z written, p, q read; 1 / sum(alpha)
+        assert b["pcg_update"] == nu * (16 + 2 * w + w + 2 * w) + nn * w
+
+
+def test_kernel_names_match_the_traffic_summary():
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_cantilever2d_600x200.md")
+    rec = None
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("traffic-json: "):
+                rec = json.loads(line[len("traffic-json: "):])
+    assert rec is not None
+    assert bench.pcg_kernel_name("pcg_apply", 2, 4) in rec
+    assert bench.pcg_kernel_name("pcg_update", 2, 4) in rec
+    assert bench.pcg_kernel_name("pcg_step", 2, 8) in rec
