@@ -15,17 +15,18 @@ closed forms, invariants, brute force or textbook results (see the test modules
 ``test_oracle_*``); nothing is "parity unpinned".
 """
 from .fem import (element_stiffness, constitutive, element_dofs, simp_alpha,
-                  simp_alpha_prime, assemble, apply_masked, apply_rows, solve_direct,
+                  simp_alpha_prime, assemble, apply_masked, apply_ebe, apply_rows, solve_direct,
                   solve_cg, compliance, sensitivity, free_dofs)
 from .rom import rom_operator, rom_load, rom_solve, rom_residual, rom_eval, rom_gradient
 from .basis import pod, gram_schmidt_step, basis_update, SnapshotWindow
-from .filter import filter_forward, filter_adjoint, filter_radius, helmholtz_assemble
+from .filter import (filter_forward, filter_adjoint, filter_radius, filter_radius_cited,
+                     helmholtz_assemble)
 from . import tr
 
 __all__ = [
     "element_stiffness", "constitutive", "element_dofs", "simp_alpha", "simp_alpha_prime",
-    "assemble", "apply_masked", "apply_rows", "solve_direct", "solve_cg", "compliance",
+    "assemble", "apply_masked", "apply_ebe", "apply_rows", "solve_direct", "solve_cg", "compliance",
     "sensitivity", "free_dofs", "rom_operator", "rom_load", "rom_solve", "rom_residual",
     "rom_eval", "rom_gradient", "pod", "gram_schmidt_step", "basis_update", "SnapshotWindow",
-    "filter_forward", "filter_adjoint", "filter_radius", "helmholtz_assemble",
+    "filter_forward", "filter_adjoint", "filter_radius", "filter_radius_cited", "helmholtz_assemble",
 ]

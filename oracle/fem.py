@@ -160,6 +160,23 @@ def apply_masked(mesh, rho, mask, x, plane_stress=True):
     return np.where(free, K @ xf, 0.0)
 
 
+def apply_ebe(mesh, rho, mask, x, plane_stress=True, chunk=1 << 18):
+    """y = K(rho) x with Dirichlet DOFs eliminated (as apply_masked), summed element by
+    element without assembling K (for meshes whose assembled matrix does not fit in
+    host memory): y = sum_e alpha_e P_e K_e P_e^T x, in chunks of elements."""
+    K0 = _K0(mesh, plane_stress)
+    alpha = simp_alpha(rho, mesh.E0, mesh.Emin, mesh.penal)
+    free = np.asarray(mask) == 0
+    xf = np.where(free, np.asarray(x, dtype=np.float64), 0.0)
+    y = np.zeros(mesh.n_dofs)
+    edofs = element_dofs(mesh)
+    for e0 in range(0, mesh.n_elems, chunk):
+        ed = edofs[e0:e0 + chunk]
+        ye = (xf[ed] @ K0.T) * alpha[e0:e0 + chunk, None]
+        y += np.bincount(ed.ravel(), weights=ye.ravel(), minlength=mesh.n_dofs)
+    return np.where(free, y, 0.0)
+
+
 def apply_rows(mesh, rho, mask, x, nodes, plane_stress=True):
     """(K(rho) x) at the listed nodes only, summed element by element without any
     assembly (for meshes too large to assemble in a test).  Same Dirichlet convention
@@ -213,11 +230,12 @@ def solve_direct(mesh, rho, f, mask, plane_stress=True):
 
 
 def solve_cg(mesh, rho, f, mask, rtol=1e-13, maxiter=200000, plane_stress=True,
-             x0=None, restarts=20):
+             x0=None, restarts=20, info=None):
     """FP64 Jacobi-preconditioned CG on the assembled K_ff, for meshes too large for a
     direct factorisation in host memory.  CG is restarted from its iterate until the
     *true* residual ||f_f - K_ff u_f|| / ||f_f|| is at most rtol (or the restart budget
-    is spent).  Returns (u, relative true residual)."""
+    is spent).  Returns (u, relative true residual); a dict passed as info receives the
+    number of CG iterations ("iters")."""
     K = assemble(mesh, rho, plane_stress)
     free = free_dofs(mask)
     Kff = K[free][:, free].tocsr()
@@ -227,17 +245,24 @@ def solve_cg(mesh, rho, f, mask, rtol=1e-13, maxiter=200000, plane_stress=True,
     nb = np.linalg.norm(b)
     xf = np.zeros_like(b) if x0 is None else np.asarray(x0, dtype=np.float64)[free].copy()
     res = np.linalg.norm(b - Kff @ xf) / nb
+    its = [0]
+
+    def count(_xk):
+        its[0] += 1
+
     for _ in range(restarts):
         if res <= rtol:
             break
         r = b - Kff @ xf
         # solve the correction equation to a relative accuracy that lands below rtol
         dx, _info = spla.cg(Kff, r, rtol=max(rtol / res * 0.5, 1e-15), atol=0.0,
-                            maxiter=maxiter, M=M)
+                            maxiter=maxiter, M=M, callback=count)
         xf += dx
         res = np.linalg.norm(b - Kff @ xf) / nb
     u = np.zeros(mesh.n_dofs)
     u[free] = xf
+    if info is not None:
+        info["iters"] = its[0]
     return u, res
 
 

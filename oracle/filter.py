@@ -6,7 +6,9 @@ Forward map psi -> rho*(psi):
   rho_e = (1 / N_v^e) 1^T Q_e^T phi,
 with H_e = r^2 (element Laplacian) + (element mass) of the scalar bilinear / trilinear
 element, b_e = the integrals of the element's shape functions, homogeneous Neumann
-boundary (no constrained node) and r = 2 sqrt(3) R for a filter radius R.
+boundary (no constrained node).  The Helmholtz length r is an argument; Sec. 2.2
+prints r = 2 sqrt(3) R for a filter radius R, the cited filter reference has
+r = R / (2 sqrt(3)) (filter_radius / filter_radius_cited).
 
 Adjoint: for v in R^{N_e}, (d rho*/d psi)^T v has entries b_e^T Q_e^T mu, where
 H^T mu = q(v) = sum_e (v_e / N_v^e) Q_e 1.  The paper prints this with a leading minus
@@ -112,5 +114,12 @@ def filter_adjoint(mesh, r, v):
 
 
 def filter_radius(R):
-    """r = 2 sqrt(3) R for the filter's characteristic radius R (Sec. 2.2)."""
+    """r = 2 sqrt(3) R for the filter's characteristic radius R, as Sec. 2.2 prints it."""
     return 2.0 * np.sqrt(3.0) * R
+
+
+def filter_radius_cited(R):
+    """r = R / (2 sqrt(3)): the Helmholtz length whose filter kernel has the second moment
+    of the conic density filter of radius R, the relation of the filter reference that
+    Sec. 2.2 cites (the paper's text prints the inverse factor; see filter_radius)."""
+    return R / (2.0 * np.sqrt(3.0))

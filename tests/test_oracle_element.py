@@ -153,3 +153,28 @@ def test_two_point_gauss_is_exact(dim):
 def test_h8_scales_linearly_with_h_and_q4_is_scale_free():
     assert np.allclose(O.element_stiffness(3, (2, 2, 2)), 2 * O.element_stiffness(3, (1, 1, 1)), atol=1e-14)
     assert np.allclose(O.element_stiffness(2, (0.1, 0.1)), O.element_stiffness(2, (1, 1)), atol=1e-14)
+
+
+@pytest.mark.parametrize("nu", [0.0, 0.25, 0.3, 0.45])
+def test_plane_strain_is_3d_law_with_zero_out_of_plane_strain(nu):
+    """Plane strain pinned independently of its own branch: (a) it is the isotropic 3D
+    law (pinned through the H8 closed forms above) restricted to exx, eyy, gxy with
+    ezz = gyz = gxz = 0; (b) it equals plane stress with E' = E / (1 - nu^2) and
+    nu' = nu / (1 - nu), the textbook correspondence between the two states."""
+    E = 1.7
+    D3 = O.constitutive(3, E, nu)
+    keep = [0, 1, 5]  # exx, eyy, gxy in the 3D Voigt order [exx, eyy, ezz, gyz, gxz, gxy]
+    Dpe = O.constitutive(2, E, nu, plane_stress=False)
+    assert np.allclose(Dpe, D3[np.ix_(keep, keep)], rtol=1e-15, atol=0)
+    Dps = O.constitutive(2, E / (1 - nu ** 2), nu / (1 - nu), plane_stress=True)
+    assert np.allclose(Dpe, Dps, rtol=1e-14, atol=0)
+
+
+def test_plane_strain_element_from_plane_stress_correspondence():
+    """The plane-strain Q4 element equals the plane-stress element of the corresponding
+    material (E / (1 - nu^2), nu / (1 - nu)), whose quadrature and closed forms are
+    pinned above."""
+    nu, h = 0.3, (0.5, 2.0)
+    Kpe = O.element_stiffness(2, h, 1.0, nu, plane_stress=False)
+    Kps = O.element_stiffness(2, h, 1.0 / (1 - nu ** 2), nu / (1 - nu), plane_stress=True)
+    assert np.abs(Kpe - Kps).max() <= 1e-14 * np.abs(Kps).max()

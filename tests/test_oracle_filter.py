@@ -109,3 +109,25 @@ def test_large_radius_gives_the_volume_mean():
     psi = np.random.default_rng(1).uniform(0, 1, m.n_elems)
     rho, _ = F.filter_forward(m, 1e4, psi)
     assert np.abs(rho - psi.mean()).max() < 1e-6
+
+
+def test_cited_length_matches_the_conic_filter_second_moment():
+    """Which relation between r and R the two readings give, pinned on the oracle's own
+    filter: in 1D the Helmholtz kernel exp(-|x|/r)/(2r) has second moment 2 r^2 and the
+    conic filter of radius R (weights R - |x|) has R^2 / 6, so r = R / (2 sqrt(3))
+    gives a filter as wide as the conic one of radius R.  On a strip of unit elements,
+    a one-element impulse filtered with r = filter_radius_cited(R) spreads with that
+    variance (up to the O(h^2) of the element averages); with the printed r = 2 sqrt(3) R
+    it spreads 144 times wider."""
+    R = 24.0
+    m = W.Mesh((401, 1))
+    psi = np.zeros(m.n_elems)
+    psi[200] = 1.0
+    x = np.arange(m.n_elems) - 200.0
+    var = {}
+    for name, r in (("cited", F.filter_radius_cited(R)), ("printed", F.filter_radius(R))):
+        rho, _ = F.filter_forward(m, r, psi)
+        rho = rho[0] if rho.ndim == 2 else rho
+        var[name] = float(np.sum(x * x * rho) / np.sum(rho))
+    assert abs(var["cited"] / (R * R / 6.0) - 1.0) < 0.02, var
+    assert var["printed"] > 50 * R * R / 6.0 or var["printed"] > 0.5 * (400 ** 2 / 12), var
