@@ -89,7 +89,8 @@ typedef struct topo_info {
     int32_t fp64_fallback;  /* TOPO_MIXED only: 1 when a float32 correction failed to  */
                             /* reduce the true residual and the solve was redone in   */
                             /* float64 from u = 0 (iters counts both attempts)        */
-    int32_t reserved;
+    int32_t status;         /* outcome of this field: TOPO_OK, TOPO_ENOCONV or         */
+                            /* TOPO_ENOTSPD (for batched solves, per field)            */
 } topo_info;
 
 /* ---- context ------------------------------------------------------------------ */
@@ -111,11 +112,13 @@ int topo_ctx_set_timing(topo_ctx* ctx, int32_t every);
 /* Sampled launches and their summed device time in ms for one hot kernel: "apply",
  * "pcg_apply", "pcg_update", "residual", "rom_contract", "rom_reduce", "phit_v",
  * "phi_y", "chol", "chol_solve", "gradient", "pcg_step" (the one kernel per
- * iteration of the 2D solve; "pcg_apply" / "pcg_update" are the two of the 3D solve).
- * Waits for pending samples (host outputs); reset != 0 clears the kernel's counters
- * afterwards. */
+ * iteration of the 2D float64 solve; "pcg_apply" / "pcg_update" are the two of the
+ * other solves), and the number of launches of that kernel issued since the last
+ * reset while timing was on (graph replays included; may be NULL).  A launch of a
+ * batched kernel covers every field of its batch.  Waits for pending samples (host
+ * outputs); reset != 0 clears the kernel's counters afterwards. */
 int topo_ctx_kernel_time(topo_ctx* ctx, const char* kernel, int64_t* samples,
-                         double* total_ms, int32_t reset);
+                         double* total_ms, int64_t* launches, int32_t reset);
 
 /* ---- element operator --------------------------------------------------------- */
 
@@ -163,12 +166,33 @@ int topo_hdm_solve(topo_ctx* ctx, const topo_mesh* mesh, const double* rho,
                    int32_t maxit, int32_t prec, double* compliance, topo_info* info,
                    void* stream);
 
+/* Batched HDM state solve: B density fields sharing the mesh, the Dirichlet mask and
+ * the load (Sec. 2.1 state equation for each field; the method's trust-region
+ * iterates and the benchmark's field batches), solved together with B fields per
+ * kernel launch.  Same method, stopping rule and outputs per field as topo_hdm_solve;
+ * every stopping, restart and residual-replacement decision is taken per field and
+ * every reduction runs over the field's own data in a fixed order, so a field's u,
+ * compliance and info are bitwise the same whatever batch it is solved in.
+ *   rho [B][n_elems] f64, mask [N_u] u8, f [N_u] f64 (shared), u [B][N_u] f64 out.
+ *   compliance: HOST [B] (may be NULL), receives each compliance_corr.
+ *   info: HOST [B] (may be NULL); info[b].status is the field's outcome.  maxit bounds
+ *   each field's inner iterations.
+ * Returns TOPO_OK when every field converged, else the status of the first field that
+ * did not (u and info then hold every field's last iterate and diagnostics). */
+int topo_hdm_solve_batch(topo_ctx* ctx, const topo_mesh* mesh, const double* rho,
+                         const uint8_t* mask, const double* f, double* u, int32_t B,
+                         double rtol, int32_t maxit, int32_t prec, double* compliance,
+                         topo_info* info, void* stream);
+
 /* Element sensitivity of the compliance with respect to the filtered density,
  * dc[e] = -penal (E0 - Emin) rho_e^(penal-1) u_e^T K_e u_e (Sec. 2.4, compliance
  * remark: lambda* = u*, no adjoint solve), float64.
  *   rho [n_elems] f64, u [N_u] f64 (zero on Dirichlet DOFs), dc [n_elems] f64 out. */
 int topo_hdm_gradient(topo_ctx* ctx, const topo_mesh* mesh, const double* rho,
                       const double* u, double* dc, void* stream);
+/* The same for B fields: rho [B][n_elems], u [B][N_u], dc [B][n_elems] (float64). */
+int topo_hdm_gradient_batch(topo_ctx* ctx, const topo_mesh* mesh, const double* rho,
+                            const double* u, int32_t B, double* dc, void* stream);
 
 /* ---- reduced-order model --------------------------------------------------------- */
 

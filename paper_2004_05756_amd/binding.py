@@ -21,7 +21,7 @@ FP64, MIXED = 0, 1
 EXPORTED = (
     "topo_ctx_create", "topo_ctx_destroy", "topo_last_error", "topo_strerror",
     "topo_ctx_workspace_bytes", "topo_element_stiffness", "topo_element_factor", "topo_apply",
-    "topo_hdm_solve",
+    "topo_hdm_solve", "topo_hdm_solve_batch", "topo_hdm_gradient_batch",
     "topo_hdm_gradient", "topo_rom_build", "topo_rom_solve", "topo_rom_estimate",
     "topo_rom_gradient", "topo_pod_push", "topo_pod_basis", "topo_filter_forward",
     "topo_filter_adjoint", "topo_ctx_set_timing", "topo_ctx_kernel_time",
@@ -44,10 +44,10 @@ class TopoMesh(C.Structure):
 class TopoInfo(C.Structure):
     _fields_ = [("iters", C.c_int32), ("refinements", C.c_int32), ("rel_resid", C.c_double),
                 ("compliance_raw", C.c_double), ("compliance_corr", C.c_double),
-                ("fp64_fallback", C.c_int32), ("reserved", C.c_int32)]
+                ("fp64_fallback", C.c_int32), ("status", C.c_int32)]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 _P = C.c_void_p
@@ -59,13 +59,16 @@ _SIGS = {
     "topo_ctx_workspace_bytes": (C.c_size_t, [_P]),
     "topo_ctx_set_timing": (C.c_int, [_P, C.c_int32]),
     "topo_ctx_kernel_time": (C.c_int, [_P, C.c_char_p, C.POINTER(C.c_int64), C.POINTER(C.c_double),
-                                       C.c_int32]),
+                                       C.POINTER(C.c_int64), C.c_int32]),
     "topo_element_stiffness": (C.c_int, [C.POINTER(TopoMesh), C.POINTER(C.c_double)]),
     "topo_element_factor": (C.c_int, [C.POINTER(TopoMesh), C.POINTER(C.c_double)]),
     "topo_apply": (C.c_int, [_P, C.POINTER(TopoMesh), _P, _P, _P, _P, C.c_int32, C.c_int32, _P]),
     "topo_hdm_solve": (C.c_int, [_P, C.POINTER(TopoMesh), _P, _P, _P, _P, C.c_double, C.c_int32,
                                  C.c_int32, C.POINTER(C.c_double), C.POINTER(TopoInfo), _P]),
+    "topo_hdm_solve_batch": (C.c_int, [_P, C.POINTER(TopoMesh), _P, _P, _P, _P, C.c_int32, C.c_double,
+                                       C.c_int32, C.c_int32, C.POINTER(C.c_double), C.POINTER(TopoInfo), _P]),
     "topo_hdm_gradient": (C.c_int, [_P, C.POINTER(TopoMesh), _P, _P, _P, _P]),
+    "topo_hdm_gradient_batch": (C.c_int, [_P, C.POINTER(TopoMesh), _P, _P, C.c_int32, _P, _P]),
     "topo_rom_build": (C.c_int, [_P, C.POINTER(TopoMesh), _P, C.c_int32, C.c_int32, C.c_int32, _P,
                                  _P, _P, C.c_int32, _P, _P, C.c_int32, _P]),
     "topo_rom_solve": (C.c_int, [_P, C.c_int32, C.c_int32, _P, _P, _P, _P, _P, _P]),
@@ -165,6 +168,38 @@ def _stream(stream):
     return s.cuda_stream
 
 
+def mesh_sizes(m: TopoMesh):
+    """(elements, nodes, DOFs) of a TopoMesh."""
+    ne, nn = 1, 1
+    for i in range(m.dim):
+        ne *= int(m.nel[i])
+        nn *= int(m.nel[i]) + 1
+    return ne, nn, m.dim * nn
+
+
+def _numel(t, n, name):
+    """Raise ValueError unless tensor t (if given) holds exactly n entries: a mis-shaped
+    array would make the kernels read or write outside it."""
+    if t is not None and int(t.numel()) != int(n):
+        raise ValueError(f"{name} has {int(t.numel())} entries, expected {int(n)}")
+
+
+def _rows(phi, n_dofs, k):
+    if phi.dim() != 2 or int(phi.shape[0]) != n_dofs:
+        raise ValueError(f"phi must be [N_u={n_dofs}][ldphi], got {tuple(phi.shape)}")
+    if not 1 <= int(k) <= int(phi.shape[1]):
+        raise ValueError(f"k={k} must lie in [1, ldphi={int(phi.shape[1])}]")
+
+
+def _solve_shapes(B, k, k2, fhat, yhat, Jk, status):
+    if k != k2:
+        raise ValueError(f"Khat must be [B][k][k], got [{B}][{k}][{k2}]")
+    _numel(fhat, k, "fhat")
+    _numel(yhat, B * k, "yhat")
+    _numel(Jk, B, "Jk")
+    _numel(status, B, "status")
+
+
 class Context:
     """One library context (device workspace + element tables) on one GPU."""
 
@@ -199,12 +234,17 @@ class Context:
         """Sample one launch in `every` of each hot kernel with HIP events (0 = off)."""
         self._check(self.lib.topo_ctx_set_timing(self.h, int(every)), "set_timing")
 
-    def kernel_time(self, name: str, reset: bool = False):
-        """(sampled launches, summed device ms) of one hot kernel."""
+    def kernel_time(self, name: str, reset: bool = False, launches: bool = False):
+        """(sampled launches, summed device ms) of one hot kernel, and with launches=True
+        also the launches issued while timing was on."""
         n = C.c_int64()
         ms = C.c_double()
-        rc = self.lib.topo_ctx_kernel_time(self.h, name.encode(), C.byref(n), C.byref(ms), int(reset))
+        nl = C.c_int64()
+        rc = self.lib.topo_ctx_kernel_time(self.h, name.encode(), C.byref(n), C.byref(ms), C.byref(nl),
+                                           int(reset))
         self._check(rc, "kernel_time")
+        if launches:
+            return int(n.value), float(ms.value), int(nl.value)
         return int(n.value), float(ms.value)
 
     # -- full-order model -------------------------------------------------------------
@@ -215,6 +255,11 @@ class Context:
         if y is None:
             y = torch.empty_like(x)
         m = make_mesh(mesh)
+        ne, _, nu = mesh_sizes(m)
+        _numel(rho, B * ne, "rho")
+        _numel(mask, nu, "mask")
+        _numel(x, B * nu, "x")
+        _numel(y, B * nu, "y")
         rc = self.lib.topo_apply(self.h, C.byref(m), _ptr(rho, torch.float64, "rho"),
                                  _ptr(mask, torch.uint8, "mask"), _ptr(x, dt, "x"),
                                  _ptr(y, dt, "y"), B, prec, _stream(stream))
@@ -227,6 +272,11 @@ class Context:
         if u is None:
             u = torch.empty_like(f)
         m = make_mesh(mesh)
+        ne, _, nu = mesh_sizes(m)
+        _numel(rho, ne, "rho")
+        _numel(mask, nu, "mask")
+        _numel(f, nu, "f")
+        _numel(u, nu, "u")
         info = TopoInfo()
         comp = C.c_double()
         rc = self.lib.topo_hdm_solve(self.h, C.byref(m), _ptr(rho, torch.float64, "rho"),
@@ -239,11 +289,60 @@ class Context:
         d["status"] = rc
         return u, d
 
+    def hdm_solve_batch(self, mesh, rho, mask, f, u=None, rtol=1e-10, maxit=200000, prec=FP64,
+                        stream=None, check=True):
+        """B fields rho [B][N_e] sharing mask and load f: u [B][N_u] and one info dict per
+        field (topo_hdm_solve_batch; each field's result does not depend on the batch)."""
+        import torch
+        if rho.dim() == 1:
+            rho = rho.unsqueeze(0)
+        B = int(rho.shape[0])
+        if u is None:
+            u = torch.empty((B, f.numel()), dtype=torch.float64, device=f.device)
+        m = make_mesh(mesh)
+        ne, _, nu = mesh_sizes(m)
+        _numel(rho, B * ne, "rho")
+        _numel(mask, nu, "mask")
+        _numel(f, nu, "f")
+        _numel(u, B * nu, "u")
+        infos = (TopoInfo * B)()
+        comp = (C.c_double * B)()
+        rc = self.lib.topo_hdm_solve_batch(self.h, C.byref(m), _ptr(rho, torch.float64, "rho"),
+                                           _ptr(mask, torch.uint8, "mask"), _ptr(f, torch.float64, "f"),
+                                           _ptr(u, torch.float64, "u"), B, float(rtol), int(maxit), prec,
+                                           comp, infos, _stream(stream))
+        if check:
+            self._check(rc, "hdm_solve_batch")
+        return u, [infos[b].as_dict() for b in range(B)]
+
+    def hdm_gradient_batch(self, mesh, rho, u, dc=None, stream=None):
+        """dc/drho [B][N_e] of B fields at their states u [B][N_u] (topo_hdm_gradient_batch)."""
+        import torch
+        if rho.dim() == 1:
+            rho = rho.unsqueeze(0)
+        B = int(rho.shape[0])
+        if dc is None:
+            dc = torch.empty_like(rho)
+        m = make_mesh(mesh)
+        ne, _, nu = mesh_sizes(m)
+        _numel(rho, B * ne, "rho")
+        _numel(u, B * nu, "u")
+        _numel(dc, B * ne, "dc")
+        rc = self.lib.topo_hdm_gradient_batch(self.h, C.byref(m), _ptr(rho, torch.float64, "rho"),
+                                              _ptr(u, torch.float64, "u"), B, _ptr(dc, torch.float64, "dc"),
+                                              _stream(stream))
+        self._check(rc, "hdm_gradient_batch")
+        return dc
+
     def hdm_gradient(self, mesh, rho, u, dc=None, stream=None):
         import torch
         if dc is None:
             dc = torch.empty_like(rho)
         m = make_mesh(mesh)
+        ne, _, nu = mesh_sizes(m)
+        _numel(rho, ne, "rho")
+        _numel(u, nu, "u")
+        _numel(dc, ne, "dc")
         rc = self.lib.topo_hdm_gradient(self.h, C.byref(m), _ptr(rho, torch.float64, "rho"),
                                         _ptr(u, torch.float64, "u"), _ptr(dc, torch.float64, "dc"),
                                         _stream(stream))
@@ -263,6 +362,13 @@ class Context:
         if with_fhat and fhat is None:
             fhat = torch.empty(k, dtype=torch.float64, device=dev)
         m = make_mesh(mesh)
+        ne, _, nu = mesh_sizes(m)
+        _rows(phi, nu, k)
+        _numel(rho, B * ne, "rho")
+        _numel(mask, nu, "mask")
+        _numel(f, nu, "f")
+        _numel(Khat, B * k * k, "Khat")
+        _numel(fhat if with_fhat else None, k, "fhat")
         fp32 = 1 if phi.dtype == torch.float32 else 0
         rc = self.lib.topo_rom_build(self.h, C.byref(m), _ptr(phi, None, "phi"), fp32, int(k),
                                      int(phi.shape[1]), _ptr(mask, torch.uint8, "mask"),
@@ -275,11 +381,12 @@ class Context:
 
     def rom_solve(self, Khat, fhat, status=None, yhat=None, Jk=None, stream=None):
         import torch
-        B, k, _ = Khat.shape
+        B, k, k2 = Khat.shape
         if yhat is None:
             yhat = torch.empty((B, k), dtype=torch.float64, device=Khat.device)
         if Jk is None:
             Jk = torch.empty(B, dtype=torch.float64, device=Khat.device)
+        _solve_shapes(B, k, k2, fhat, yhat, Jk, status)
         rc = self.lib.topo_rom_solve(self.h, k, B, _ptr(Khat, torch.float64, "Khat"),
                                      _ptr(fhat, torch.float64, "fhat"), _ptr(yhat, torch.float64, "yhat"),
                                      _ptr(Jk, torch.float64, "Jk"),
@@ -302,6 +409,16 @@ class Context:
         if resnorm is None:
             resnorm = torch.empty(B, dtype=torch.float64, device=dev)
         m = make_mesh(mesh)
+        ne, _, nu = mesh_sizes(m)
+        _rows(phi, nu, k)
+        _numel(rho, B * ne, "rho")
+        _numel(mask, nu, "mask")
+        _numel(f, nu, "f")
+        _numel(Khat, B * k * k, "Khat")
+        _numel(yhat, B * k, "yhat")
+        _numel(Jk, B, "Jk")
+        _numel(resnorm, B, "resnorm")
+        _numel(dJ, B * ne, "dJ")
         fp32 = 1 if phi.dtype == torch.float32 else 0
         rc = self.lib.topo_rom_estimate(self.h, C.byref(m), _ptr(phi, None, "phi"), fp32, int(k),
                                         int(phi.shape[1]), _ptr(mask, torch.uint8, "mask"),
@@ -324,6 +441,12 @@ class Context:
         if dJ is None:
             dJ = torch.empty_like(rho, dtype=torch.float64)
         m = make_mesh(mesh)
+        ne, _, nu = mesh_sizes(m)
+        _rows(phi, nu, k)
+        _numel(rho, B * ne, "rho")
+        _numel(mask, nu, "mask")
+        _numel(yhat, B * k, "yhat")
+        _numel(dJ, B * ne, "dJ")
         fp32 = 1 if phi.dtype == torch.float32 else 0
         rc = self.lib.topo_rom_gradient(self.h, C.byref(m), _ptr(phi, None, "phi"), fp32, int(k),
                                         int(phi.shape[1]), _ptr(mask, torch.uint8, "mask"),
@@ -341,6 +464,10 @@ class Context:
         if out is None:
             out = torch.empty_like(x, dtype=torch.float64)
         m = make_mesh(mesh)
+        ne, nn, _ = mesh_sizes(m)
+        _numel(x, B * ne, "input")
+        _numel(out, B * ne, "output")
+        _numel(nodal, B * nn, "nodal")
         its = C.c_int32(0)
         rc = fn(self.h, C.byref(m), float(r), _ptr(x, torch.float64, "input"), B,
                 _ptr(out, torch.float64, "output"), _ptr(nodal, torch.float64, "nodal"), float(rtol),
@@ -366,6 +493,8 @@ class Context:
         host ints, updated in place) (topo_pod_push)."""
         import torch
         L, n = S.shape
+        _numel(G, L * L, "G")
+        _numel(u, n, "u")
         cnt, nxt = C.c_int32(int(state[0])), C.c_int32(int(state[1]))
         rc = self.lib.topo_pod_push(self.h, int(n), int(L), _ptr(S, torch.float64, "S"),
                                     _ptr(G, torch.float64, "G"), C.byref(cnt), C.byref(nxt),
@@ -378,6 +507,11 @@ class Context:
         returns (columns written, POD columns kept) (topo_pod_basis)."""
         import torch
         L, n = S.shape
+        _numel(G, L * L, "G")
+        _numel(u, n, "u")
+        if phi.dim() != 2 or int(phi.shape[0]) != n:
+            raise ValueError(f"phi must be [n={n}][ldphi], got {tuple(phi.shape)}")
+        _numel(sigma, int(count), "sigma")
         ncols, npod = C.c_int32(0), C.c_int32(0)
         fp32 = 1 if phi.dtype == torch.float32 else 0
         if phi.dtype not in (torch.float32, torch.float64):
@@ -502,6 +636,7 @@ class Server:
             raise TopoError(rc, "server creation")
         self.h = h
         self._meshes = {}
+        self._held = {}  # device densities of pending requests, by ticket
 
     def _check(self, rc, what):
         if rc != TOPO_OK:
@@ -515,6 +650,7 @@ class Server:
         if getattr(self, "h", None):
             self.lib.topo_server_destroy(self.h)
             self.h = None
+        getattr(self, "_held", {}).clear()
 
     def __del__(self):  # pragma: no cover
         try:
@@ -549,17 +685,30 @@ class Server:
     def _submit(self, req, rho):
         import numpy as np
         t = C.c_uint64()
-        if hasattr(rho, "is_cuda") and rho.is_cuda:
-            req.rho = _ptr(rho, None, "rho")
+        mesh = self._meshes.get(int(req.mesh_id))
+        on_dev = hasattr(rho, "is_cuda") and rho.is_cuda
+        if mesh is not None:
+            ne, _, _ = mesh_sizes(make_mesh(mesh))
+            n = int(rho.numel()) if on_dev else int(np.asarray(rho).size)
+            if n != ne:
+                raise ValueError(f"rho has {n} entries, the mesh has {ne} elements")
+        if on_dev:
+            import torch
+            req.rho = _ptr(rho, torch.float64, "rho")
             req.rho_on_device = 1
+            # the worker reads rho later on its own stream: everything queued on the
+            # caller's stream (the producer of rho) must have finished, and the tensor
+            # must stay alive until the request completes (released by wait / poll)
+            torch.cuda.current_stream(rho.device).synchronize()
             keep = rho
         else:
             keep = np.ascontiguousarray(rho, dtype=np.float64)
             req.rho = keep.ctypes.data
             req.rho_on_device = 0
         rc = self.lib.topo_server_submit(self.h, C.byref(req), C.byref(t))
-        del keep  # host densities are copied during submit
         self._check(rc, "submit")
+        if on_dev:
+            self._held[t.value] = keep
         return t.value
 
     def submit_hdm(self, mesh_id, rho, rtol=1e-10, prec=MIXED, maxit=0):
@@ -575,6 +724,7 @@ class Server:
     def wait(self, ticket):
         res = TopoResult()
         self.lib.topo_server_wait(self.h, C.c_uint64(ticket), C.byref(res))
+        self._held.pop(ticket, None)
         return res.as_dict()
 
     def poll(self, ticket):
@@ -582,6 +732,7 @@ class Server:
         rc = self.lib.topo_server_poll(self.h, C.c_uint64(ticket), C.byref(res))
         if rc == TOPO_EAGAIN:
             return None
+        self._held.pop(ticket, None)
         return res.as_dict()
 
     def stats(self):

@@ -222,8 +222,10 @@ int Arena::commit(Ctx* ctx, hipStream_t s) {
     const size_t total = this->total();
     if (total > ctx->ws_bytes) {
         if (ctx->ws) {
+            // the old arena is last used by this context's work on s (calls of one
+            // context on other streams are ordered by the caller), so draining s is
+            // enough; other contexts on the device keep running
             TOPO_HIP(hipStreamSynchronize(s));
-            TOPO_HIP(hipDeviceSynchronize());
             TOPO_HIP(hipFree(ctx->ws));
             ctx->ws = nullptr;
             ctx->ws_bytes = 0;
@@ -310,6 +312,7 @@ TimedLaunch::TimedLaunch(Ctx* ctx, int k, hipStream_t st, int mode, bool ik)
     if (!c || mode == kTimeOff) return;
     Timing& t = c->timing;
     if (t.every <= 0) return;
+    if (!in_kernel) ++t.launched[kid];  // the PCG kernels are counted by their phase driver
     if (t.seen[kid]++ % t.every != 0 && mode != kTimeForced) return;
     a = timing_event(c);
     if (!a) return;
@@ -448,7 +451,7 @@ int topo_ctx_set_timing(topo_ctx* c, int32_t every) {
 }
 
 int topo_ctx_kernel_time(topo_ctx* c, const char* kernel, int64_t* samples, double* total_ms,
-                         int32_t reset) {
+                         int64_t* launches, int32_t reset) {
     if (!c || !kernel) return TOPO_EINVAL;
     int kid = -1;
     for (int i = 0; i < KID_COUNT; ++i)
@@ -458,7 +461,9 @@ int topo_ctx_kernel_time(topo_ctx* c, const char* kernel, int64_t* samples, doub
     timing_drain(c);
     if (samples) *samples = c->timing.samples[kid];
     if (total_ms) *total_ms = c->timing.total_ms[kid];
+    if (launches) *launches = c->timing.launched[kid];
     if (reset) {
+        c->timing.launched[kid] = 0;
         c->timing.samples[kid] = 0;
         c->timing.total_ms[kid] = 0.0;
         c->timing.seen[kid] = 0;

@@ -644,7 +644,7 @@ static int helm_solve(Ctx* ctx, const Grid& g, const HelmElem& E, int B, const H
         for (uint64_t v : words) key.push_back((uintptr_t)v);
         return cached_graph(ctx, key, [&](LaunchSink& G) {
             for (int c = 0; c < kHelmCheck; ++c) iteration(G, first_chunk ? c : kHelmCheck + c);
-        }, out);
+        }, out, s);
     };
     // The check after a chunk stops the converged fields on the device (their later
     // launches return at once) and counts the active ones; the host reads the count one

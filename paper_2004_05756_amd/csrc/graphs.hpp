@@ -23,6 +23,9 @@ inline bool graphs_enabled() {
     return on;
 }
 
+// Instantiated graphs a context keeps before it releases them all.
+constexpr size_t kGraphCacheMax = 16;
+
 // Where kernel launches go: directly onto a stream, or appended as kernel nodes (each
 // depending on the previous one) to a graph under construction.  Graphs are built
 // node by node rather than by stream capture, so that building one never interferes
@@ -60,15 +63,22 @@ struct LaunchSink {
     }
 };
 
-// Instantiated graph for `key`, built by build(L) on first use and cached in ctx.
+// Instantiated graph for `key`, built by build(L) on first use and cached in ctx.  When
+// the cache is full every entry is released, after the stream `s` the graphs of this
+// context run on has drained: a graph launched earlier in the same call (or an earlier
+// call on s) may still be executing, and its kernel arguments live in the executable
+// graph.  Calls of one context on other streams are ordered by the caller (a context's
+// calls share its workspace), so they have finished too.
 template <typename Build>
-static int cached_graph(Ctx* ctx, const std::vector<uintptr_t>& key, Build build, hipGraphExec_t* out) {
+static int cached_graph(Ctx* ctx, const std::vector<uintptr_t>& key, Build build, hipGraphExec_t* out,
+                        hipStream_t s) {
     auto it = ctx->graphs.find(key);
     if (it != ctx->graphs.end()) {
         *out = it->second.exec;
         return TOPO_OK;
     }
-    if (ctx->graphs.size() >= 16) {
+    if (ctx->graphs.size() >= kGraphCacheMax) {
+        TOPO_HIP(hipStreamSynchronize(s));
         for (auto& kv : ctx->graphs) {
             (void)hipGraphExecDestroy(kv.second.exec);
             (void)hipGraphDestroy(kv.second.graph);

@@ -1,15 +1,24 @@
 // Full-order model on the device: matrix-free K(rho) apply, Jacobi-preconditioned CG
 // with float64 iterative refinement, compliance and element sensitivity
-// (Sec. 2.1 state equation, Sec. 2.3 compliance, Sec. 2.4 sensitivity).
+// (Sec. 2.1 state equation, Sec. 2.3 compliance, Sec. 2.4 sensitivity), for B density
+// fields per launch.
 //
 // Global reductions never cross blocks inside a kernel: each kernel writes one
 // partial per block, and the consumer kernel (the next one in the stream) sums the
 // partials of its producer in a fixed order, redundantly in every block.  Kernel
 // boundaries provide the coherence between the XCDs' L2 caches, so no fences or
 // atomics are needed and every result is bitwise reproducible.
+//
+// Batches: every launch of a solve covers B fields (one per blockIdx.y, or mapped with
+// field_block); each field has its own vectors, partial arrays and recursion state,
+// and every stopping, restart and replacement decision is taken per field, so a
+// field's result is bitwise the same alone and in any batch.
 #include <algorithm>
 #include <cmath>
+#include <cstddef>
 #include <cstdlib>
+#include <initializer_list>
+#include <vector>
 
 #include <hip/hip_ext.h>
 
@@ -20,7 +29,8 @@
 namespace topo {
 
 // ----------------------------------------------------------------------------------
-// Per-solve tables: alpha_e in both precisions, 1 / sum_{e ∋ n} alpha_e per node.
+// Per-solve tables: alpha_e in both precisions, 1 / sum_{e ∋ n} alpha_e per node, for
+// B fields (blockIdx.y).
 // ----------------------------------------------------------------------------------
 __global__ void k_alpha(int ne, const double* __restrict__ rho, double E0, double Emin,
                         double p, double* __restrict__ a64, float* __restrict__ a32) {
@@ -36,12 +46,13 @@ __global__ void k_winv(Grid g, const double* __restrict__ a64, double* __restric
                        float* __restrict__ w32) {
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= g.n_nodes) return;
+    const size_t b = blockIdx.y;
     int i, j, k;
     node_ijk(g, n, i, j, k);
-    const double s = node_alpha_sum(g, i, j, k, a64);
+    const double s = node_alpha_sum(g, i, j, k, a64 + b * g.n_elems);
     const double w = s > 0.0 ? 1.0 / s : 0.0;
-    if (w64) w64[n] = w;
-    if (w32) w32[n] = (float)w;
+    if (w64) w64[b * g.n_nodes + n] = w;
+    if (w32) w32[b * g.n_nodes + n] = (float)w;
 }
 
 // ----------------------------------------------------------------------------------
@@ -52,9 +63,10 @@ __global__ __launch_bounds__(kBlock) void k_apply2(Grid g, const T* __restrict__
                                                    const T* __restrict__ K,
                                                    const uint8_t* __restrict__ mask,
                                                    const T* __restrict__ x, T* __restrict__ y) {
-    const int n = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const FieldBlock fb = field_block();
+    const int n = fb.blk * blockDim.x + threadIdx.x;
     if (n >= g.n_nodes) return;
-    const size_t b = blockIdx.y;
+    const size_t b = fb.field;
     const T* xb = x + b * g.n_dofs;
     T* yb = y + b * g.n_dofs;
     const T* ab = alpha + b * g.n_elems;
@@ -137,16 +149,17 @@ __device__ __forceinline__ void march3_prologue(const Grid& g, const MarchBlock&
     }
 }
 
-// 3D: one block per march column (blockIdx.x), one field per blockIdx.y.  M is the
-// table of reduced element blocks (apply3_from_n).
+// 3D: one block per march column and field.  M is the table of reduced element blocks
+// (apply3_from_n).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_apply3(Grid g, const T* __restrict__ alpha,
                                                    const T* __restrict__ M,
                                                    const uint8_t* __restrict__ mask,
                                                    const T* __restrict__ x, T* __restrict__ y) {
     __shared__ MarchLds<T> L;
-    const size_t b = blockIdx.y;
-    const MarchBlock m = march3_block(g, xcd_block(blockIdx.x, gridDim.x));
+    const FieldBlock fb = field_block();
+    const size_t b = fb.field;
+    const MarchBlock m = march3_block(g, fb.blk);
     for (int i = threadIdx.x; i < kFacSize; i += blockDim.x) L.M[i] = M[i];
     const MarchSlots sl = march3_slots(g, m);
     SrcMasked<T> src{x + b * g.n_dofs, mask, g.n_nodes};
@@ -163,32 +176,42 @@ __global__ __launch_bounds__(kBlock) void k_apply3(Grid g, const T* __restrict__
 }
 
 // ----------------------------------------------------------------------------------
-// Jacobi-PCG, two kernels per iteration:
+// Jacobi-PCG, two kernels per iteration (3D solves, and 2D solves in float32):
 //   k_pcg_apply (iteration it): beta = rz_it / rz_{it-1}; p_new = z + beta p_old fused
 //                 into the stencil; q = K p_new; pq partials.  Also the stopping test
 //                 on rr = ||r_it||^2.
 //   k_pcg_update(iteration it): alpha = rz_it / pq; x += alpha p, r -= alpha q,
 //                 z = D^{-1} r; rz / rr partials of the next iteration.
-// Partials: part = [pq | rz(parity 0) | rz(parity 1) | rr(parity 0) | rr(parity 1)],
-// ps doubles apart; the apply writes one pq partial per stencil block (napp), the
-// initialisation and the update one rz / rr partial per node-linear block (nupd).
-// Iteration it writes rz/rr into parity it & 1 and reads the current ones from parity
-// (it + 1) & 1.  The PCG initialisation writes parity 1.  The apply of iteration it
-// records its summed rz_it in the state by parity (rz[it & 1]): the update of the same
-// iteration and the next apply read it there instead of summing its partials again.
-// Block 0 alone writes the state record (done flag, iteration count, norms, rz).
+// Partials of a field: [pq | rz(parity 0) | rz(parity 1) | rr(parity 0) | rr(parity 1)],
+// ps doubles apart; the apply writes one pq partial per stencil block (napp), the start
+// and the update one rz / rr partial per node-linear block (nupd).  Iteration it of a
+// field writes rz/rr into parity it & 1 and reads the current ones from parity
+// (it + 1) & 1.  The apply of iteration it records its summed rz_it in the state by
+// parity (rz[it & 1]): the update of the same iteration and the next apply read it
+// there instead of summing its partials again.  The logical block 0 of a field alone
+// writes its state record (done flag, iteration count, norms, rz).
+//
+// Parity: launches carry a launch parity lp (alternating); a field's iteration parity
+// is lp ^ poff, poff being fixed by the host when the field's segment starts, so that
+// fields at different iteration counts run in the same launches.
 // ----------------------------------------------------------------------------------
 struct PcgState {
-    double bb;    // reference ||r||^2 of the stopping test (set by the first apply, or by
-                  // the host when a segment continues after a residual replacement)
+    double bb;    // reference ||r||^2 of the stopping test (set by the first apply of a
+                  // fresh segment, or by the host when a segment continues after a
+                  // residual replacement)
     double rr;    // ||r||^2 at the last stopping test
     double tol2;  // the segment stops when rr <= tol2 * bb
     double rz[2]; // summed r.z of the last two applies, by iteration parity
-    int done;     // 0 running, 1 converged, 2 iteration limit, 3 breakdown
-    int iters;    // completed iterations (over all segments)
+    int done;     // 0 running, 1 converged, 2 iteration limit, 3 breakdown, 4 idle
+    int iters;    // completed iterations of the recursion (since its last fresh start)
     int maxit;
+    int poff;     // iteration parity = launch parity ^ poff
+    int fresh;    // the recursion starts here: the first apply records bb, beta = 0
     int pad;
 };
+
+constexpr int kPcgParts = 8;  // partial arrays per field (5 used by the two-kernel
+                              // recursion, 8 by the one-reduction recursion)
 
 __device__ __forceinline__ double* part_rz(double* p, int ps, int parity) { return p + (1 + parity) * ps; }
 __device__ __forceinline__ double* part_rr(double* p, int ps, int parity) { return p + (3 + parity) * ps; }
@@ -198,54 +221,69 @@ __device__ __forceinline__ double* part_rr(double* p, int ps, int parity) { retu
 // shorter kernels than with 256 threads; 1024 threads were slower again).
 constexpr int kPcgBlock = 512;
 
+// Start of a segment of a field's recursion (one node per thread, grid (nupd, B)):
+// r = scale * r64 (the float64 true residual, scaled), z = D^{-1} r, x = 0, and the
+// rz / rr partials into the parity the segment's first apply reads.  A fresh start
+// also clears p (its first apply takes beta = 0); a continued one keeps the search
+// direction, so the Krylov progress of the earlier segments is not lost.  Idle fields
+// (done != 0 in the uploaded state) are skipped.
 template <int DIM, typename T>
-__global__ __launch_bounds__(kPcgBlock) void k_pcg_init(Grid g, const T* __restrict__ b,
-                                                     const T* __restrict__ winv, T ik0, T ik1,
-                                                     T ik2, double* __restrict__ x, T* __restrict__ r,
-                                                     T* __restrict__ z, T* __restrict__ p,
-                                                     double* __restrict__ part, PcgState* st,
-                                                     int ps, int maxit, double tol2) {
+__global__ __launch_bounds__(kPcgBlock) void k_pcg_start(Grid g, const double* __restrict__ r64,
+                                                      const double* __restrict__ fsc,
+                                                      const T* __restrict__ winv, T ik0, T ik1,
+                                                      T ik2, double* __restrict__ x, T* __restrict__ r,
+                                                      T* __restrict__ z, T* __restrict__ p0,
+                                                      double* __restrict__ part, const PcgState* st,
+                                                      int ps) {
+    const int f = blockIdx.y;
+    const PcgState* sb = st + f;
+    if (sb->done) return;
     __shared__ double lds[32];
+    const size_t fo = (size_t)f * g.n_dofs;
+    r64 += fo;
+    x += fo;
+    r += fo;
+    z += fo;
+    p0 += fo;
+    winv += (size_t)f * g.n_nodes;
+    const double scale = fsc[f];
+    const bool fresh = sb->fresh != 0;
+    const int cur = (sb->iters + 1) & 1;
     double v[2] = {0.0, 0.0};
     const T ik[3] = {ik0, ik1, ik2};
-    for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < g.n_nodes; n += gridDim.x * blockDim.x) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n < g.n_nodes) {
         const T w = winv[n];
 #pragma unroll
         for (int c = 0; c < DIM; ++c) {
             const size_t i = (size_t)c * g.n_nodes + n;
-            const T bi = b[i];
-            const T zi = bi * w * ik[c];
+            const T ri = (T)(scale * r64[i]);
+            const T zi = ri * w * ik[c];
             x[i] = 0.0;
-            r[i] = bi;
+            r[i] = ri;
             z[i] = zi;
-            p[i] = T(0);
-            v[0] += (double)bi * (double)zi;
-            v[1] += (double)bi * (double)bi;
+            if (fresh) p0[i] = T(0);
+            v[0] += (double)ri * (double)zi;
+            v[1] += (double)ri * (double)ri;
         }
     }
     block_reduce<2>(v, lds);
     if (threadIdx.x == 0) {
-        part_rz(part, ps, 1)[blockIdx.x] = v[0];
-        part_rr(part, ps, 1)[blockIdx.x] = v[1];
-        if (blockIdx.x == 0) {
-            st->done = 0;
-            st->iters = 0;
-            st->maxit = maxit;
-            st->bb = 0.0;
-            st->rr = 0.0;
-            st->tol2 = tol2;
-        }
+        double* pb = part + (size_t)f * kPcgParts * ps;
+        part_rz(pb, ps, cur)[blockIdx.x] = v[0];
+        part_rr(pb, ps, cur)[blockIdx.x] = v[1];
     }
 }
 
 // Stopping test and CG coefficient of an apply, from the update partials (every block
-// computes the same values).  Returns the done code; tb is beta.
+// of the field computes the same values).  Returns the done code; tb is beta.
 template <typename T>
-__device__ __forceinline__ int pcg_apply_scalars(double* part, PcgState* st, int ps, int nupd,
-                                                 int parity, int first, T& tb, double* lds) {
+__device__ __forceinline__ int pcg_apply_scalars(const double* part, PcgState* st, int ps, int nupd,
+                                                 int parity, bool lead, T& tb, double* lds) {
     const int cur = (parity + 1) & 1;
+    const int first = st->fresh != 0 && st->iters == 0;
     // rr and rz of the current residual (one pass); rz of the previous apply from the state
-    const double* arrs[2] = {part_rr(part, ps, cur), part_rz(part, ps, cur)};
+    const double* arrs[2] = {part + (3 + cur) * ps, part + (1 + cur) * ps};
     double red[2];
     block_sum_arrays<2>(arrs, nupd, red, lds);
     const double rr = red[0];
@@ -254,7 +292,7 @@ __device__ __forceinline__ int pcg_apply_scalars(double* part, PcgState* st, int
     if (!isfinite(rr)) code = 3;
     else if (rr <= st->tol2 * bb) code = 1;
     else if (st->iters >= st->maxit) code = 2;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (lead && threadIdx.x == 0) {
         if (first) st->bb = rr;
         st->rr = rr;
         if (code) st->done = code;
@@ -264,20 +302,29 @@ __device__ __forceinline__ int pcg_apply_scalars(double* part, PcgState* st, int
     return code;
 }
 
-// 2D: one node per thread (the launch covers every node).  The node's loads are issued
-// before it waits on the scalar reduction.
+// 2D: one node per thread (the launch covers every node of every field).  The node's
+// loads are issued before it waits on the scalar reduction.
 template <typename T>
 __global__ __launch_bounds__(kPcgBlock) void k_pcg_apply2(Grid g, const T* __restrict__ alpha,
                                                        const T* __restrict__ K,
                                                        const uint8_t* __restrict__ mask,
-                                                       const T* __restrict__ z,
-                                                       const T* __restrict__ p_old,
-                                                       T* __restrict__ p_new, T* __restrict__ q,
+                                                       const T* __restrict__ z, T* __restrict__ p0,
+                                                       T* __restrict__ p1, T* __restrict__ q,
                                                        double* __restrict__ part, PcgState* st,
-                                                       int ps, int nupd, int parity, int first) {
-    if (st->done) return;
+                                                       int ps, int nupd, int lp) {
+    const FieldBlock fb = field_block();
+    PcgState* sb = st + fb.field;
+    if (sb->done) return;
     __shared__ double lds[48];
-    const int n = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const int parity = lp ^ sb->poff;
+    const size_t fo = (size_t)fb.field * g.n_dofs;
+    alpha += (size_t)fb.field * g.n_elems;
+    z += fo;
+    const T* p_old = (parity ? p1 : p0) + fo;
+    T* p_new = (parity ? p0 : p1) + fo;
+    q += fo;
+    double* pb = part + (size_t)fb.field * kPcgParts * ps;
+    const int n = fb.blk * blockDim.x + threadIdx.x;
     const bool own = n < g.n_nodes;
     T zs[3][3][2], ps_[3][3][2], al[2][2];
     uint8_t mk[2];
@@ -291,7 +338,7 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_apply2(Grid g, const T* __res
         for (int c = 0; c < 2; ++c) mk[c] = mask[(size_t)c * g.n_nodes + n];
     }
     T tb;
-    if (pcg_apply_scalars(part, st, ps, nupd, parity, first, tb, lds)) return;
+    if (pcg_apply_scalars(pb, sb, ps, nupd, parity, fb.blk == 0, tb, lds)) return;
     double v[1] = {0.0};
     if (own) {
         T out[2], pn[2];
@@ -315,32 +362,41 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_apply2(Grid g, const T* __res
         }
     }
     block_reduce<1>(v, lds);
-    if (threadIdx.x == 0) part[blockIdx.x] = v[0];
+    if (threadIdx.x == 0) pb[fb.blk] = v[0];
 }
 
-// 3D: one block per march column.  The first two node planes of z and p_old are
-// fetched before the scalar reduction; p_new = z + beta p_old is formed per node as
+// 3D: one block per march column and field.  The first two node planes of z and p_old
+// are fetched before the scalar reduction; p_new = z + beta p_old is formed per node as
 // the planes are staged, and the element march runs from LDS.  M is the table of
 // reduced element blocks.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_pcg_apply3(Grid g, const T* __restrict__ alpha,
                                                        const T* __restrict__ M,
                                                        const uint8_t* __restrict__ mask,
-                                                       const T* __restrict__ z,
-                                                       const T* __restrict__ p_old,
-                                                       T* __restrict__ p_new, T* __restrict__ q,
+                                                       const T* __restrict__ z, T* __restrict__ p0,
+                                                       T* __restrict__ p1, T* __restrict__ q,
                                                        double* __restrict__ part, PcgState* st,
-                                                       int ps, int nrz, int parity, int first) {
-    if (st->done) return;
+                                                       int ps, int nrz, int lp) {
+    const FieldBlock fb = field_block();
+    PcgState* sb = st + fb.field;
+    if (sb->done) return;
     __shared__ MarchLds<T> L;
     __shared__ double lds[48];
-    const MarchBlock m = march3_block(g, xcd_block(blockIdx.x, gridDim.x));
+    const int parity = lp ^ sb->poff;
+    const size_t fo = (size_t)fb.field * g.n_dofs;
+    alpha += (size_t)fb.field * g.n_elems;
+    z += fo;
+    const T* p_old = (parity ? p1 : p0) + fo;
+    T* p_new = (parity ? p0 : p1) + fo;
+    q += fo;
+    double* pb = part + (size_t)fb.field * kPcgParts * ps;
+    const MarchBlock m = march3_block(g, fb.blk);
     for (int i = threadIdx.x; i < kFacSize; i += blockDim.x) L.M[i] = M[i];
     const MarchSlots sl = march3_slots(g, m);
     SrcDirection<T> src{z, p_old, T(0), g.n_nodes};
     march3_prologue(g, m, sl, src);
     T tb;
-    if (pcg_apply_scalars(part, st, ps, nrz, parity, first, tb, lds)) return;
+    if (pcg_apply_scalars(pb, sb, ps, nrz, parity, fb.blk == 0, tb, lds)) return;
     src.beta = tb;
     double v[1] = {0.0};
     auto emit = [&](int n, const T (&out)[3], const T (&pn)[3]) {
@@ -355,21 +411,33 @@ __global__ __launch_bounds__(kBlock) void k_pcg_apply3(Grid g, const T* __restri
     };
     march3_run(g, m, sl, alpha, L, src, emit);
     block_reduce<1>(v, lds);
-    if (threadIdx.x == 0) part[blockIdx.x] = v[0];
+    if (threadIdx.x == 0) pb[fb.blk] = v[0];
 }
 
-// One node per thread (the launch covers every node); the node's loads are issued
-// before the wait on the scalar reduction.
+// One node per thread (grid (nupd, B)); the node's loads are issued before the wait on
+// the scalar reduction.
 template <int DIM, typename T>
 __global__ __launch_bounds__(kPcgBlock) void k_pcg_update(Grid g, const T* __restrict__ winv,
                                                        T ik0, T ik1, T ik2, double* __restrict__ x,
                                                        T* __restrict__ r, T* __restrict__ z,
-                                                       const T* __restrict__ p,
+                                                       const T* __restrict__ p0,
+                                                       const T* __restrict__ p1,
                                                        const T* __restrict__ q,
                                                        double* __restrict__ part, PcgState* st,
-                                                       int ps, int npq, int parity) {
-    if (st->done) return;
+                                                       int ps, int npq, int lp) {
+    const int f = blockIdx.y;
+    PcgState* sb = st + f;
+    if (sb->done) return;
     __shared__ double lds[32];
+    const int parity = lp ^ sb->poff;
+    const size_t fo = (size_t)f * g.n_dofs;
+    winv += (size_t)f * g.n_nodes;
+    x += fo;
+    r += fo;
+    z += fo;
+    const T* p = (parity ? p0 : p1) + fo;  // the apply's p_new
+    q += fo;
+    double* pb = part + (size_t)f * kPcgParts * ps;
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     const bool own = n < g.n_nodes;
     double xv[DIM];
@@ -385,12 +453,12 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_update(Grid g, const T* __res
             qv[c] = q[i];
         }
     }
-    const double pq = block_sum_array(part, npq, lds);
+    const double pq = block_sum_array(pb, npq, lds);
     if (!(pq > 0.0) || !isfinite(pq)) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) st->done = 3;
+        if (blockIdx.x == 0 && threadIdx.x == 0) sb->done = 3;
         return;
     }
-    const T a = (T)(st->rz[parity] / pq);
+    const T a = (T)(sb->rz[parity] / pq);
     const T ik[3] = {ik0, ik1, ik2};
     double v[2] = {0.0, 0.0};
     if (own) {
@@ -408,21 +476,29 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_update(Grid g, const T* __res
     }
     block_reduce<2>(v, lds);
     if (threadIdx.x == 0) {
-        part_rz(part, ps, parity)[blockIdx.x] = v[0];
-        part_rr(part, ps, parity)[blockIdx.x] = v[1];
-        if (blockIdx.x == 0) st->iters = st->iters + 1;
+        part_rz(pb, ps, parity)[blockIdx.x] = v[0];
+        part_rr(pb, ps, parity)[blockIdx.x] = v[1];
+        if (blockIdx.x == 0) sb->iters = sb->iters + 1;
     }
 }
 
-// In-place fixed-order sum of the per-block partials of large launches: a[0] = sum of
-// a[0..n), and likewise b when given (one block).  The consumer then reads 1 value
-// instead of every block summing all partials again.  Skipped once the recursion is
-// done: its producer did not run then, and summing again would count a[0] twice.
-__global__ __launch_bounds__(1024) void k_partials_sum(double* __restrict__ a,
-                                                       double* __restrict__ b, int n,
-                                                       const int* done) {
-    if (*done) return;
+// In-place fixed-order sum of the per-block partials of large launches, one block per
+// field: A[0] = sum of A[0..n), and likewise B when sb >= 0.  Array X sits at slot
+// sx (+ the field's iteration parity when px, that parity being lp ^ poff ^ flip) of
+// the field's partials.  The consumer then reads 1 value instead of every block summing
+// all partials again.  Skipped once the field's recursion is done: its producer did
+// not run then, and summing again would count A[0] twice.
+template <typename S>
+__global__ __launch_bounds__(1024) void k_partials_sum(double* __restrict__ part, int ps, int n, int sa,
+                                                       int pa, int sb, int pb, const S* st, int lp,
+                                                       int flip) {
+    const int f = blockIdx.x;
+    if (st[f].done) return;
     __shared__ double lds[32];
+    const int par = lp ^ st[f].poff ^ flip;
+    double* base = part + (size_t)f * kPcgParts * ps;
+    double* a = base + (size_t)(sa + (pa ? par : 0)) * ps;
+    double* b = sb >= 0 ? base + (size_t)(sb + (pb ? par : 0)) * ps : nullptr;
     double v[2] = {0.0, 0.0};
     constexpr int U = 8;  // loads in flight per thread
     for (int i0 = threadIdx.x; i0 < n; i0 += U * blockDim.x) {
@@ -446,41 +522,6 @@ __global__ __launch_bounds__(1024) void k_partials_sum(double* __restrict__ a,
     }
 }
 
-// Residual replacement: the segment's correction has been added to u in float64 and
-// the true residual r64 = f - K u recomputed; the recursion continues from
-// r = scale * r64 (x restarts at 0, the search direction p is kept), so the Krylov
-// progress of the earlier segments is not lost.  Writes the rz / rr partials of the
-// replaced residual into parity `cur`, where the next apply reads them.
-template <int DIM, typename T>
-__global__ __launch_bounds__(kPcgBlock) void k_pcg_replace(Grid g, const double* __restrict__ r64,
-                                                        double scale, const T* __restrict__ winv,
-                                                        T ik0, T ik1, T ik2, double* __restrict__ x,
-                                                        T* __restrict__ r, T* __restrict__ z,
-                                                        double* __restrict__ part, int ps, int cur) {
-    __shared__ double lds[32];
-    double v[2] = {0.0, 0.0};
-    const T ik[3] = {ik0, ik1, ik2};
-    for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < g.n_nodes; n += gridDim.x * blockDim.x) {
-        const T w = winv[n];
-#pragma unroll
-        for (int c = 0; c < DIM; ++c) {
-            const size_t i = (size_t)c * g.n_nodes + n;
-            const T ri = (T)(scale * r64[i]);
-            const T zi = ri * w * ik[c];
-            x[i] = 0.0;
-            r[i] = ri;
-            z[i] = zi;
-            v[0] += (double)ri * (double)zi;
-            v[1] += (double)ri * (double)ri;
-        }
-    }
-    block_reduce<2>(v, lds);
-    if (threadIdx.x == 0) {
-        part_rz(part, ps, cur)[blockIdx.x] = v[0];
-        part_rr(part, ps, cur)[blockIdx.x] = v[1];
-    }
-}
-
 // ----------------------------------------------------------------------------------
 // 2D: Jacobi-PCG with one reduction phase per iteration (the Chronopoulos-Gear form of
 // CG), one kernel per iteration.  With u = D^{-1} r, w = K u and s = K p:
@@ -493,8 +534,8 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_replace(Grid g, const double*
 // block of the same launch, and its scalars come from the partials of the previous one.
 // r, w and s are double-buffered: step i reads set i & 1 (r_i, w_i, s_{i-1}) and writes
 // set (i + 1) & 1 (r_{i+1}, w_{i+1}, s_i); p and x are updated in place (own node only).
-// Partials: part = [gamma(0) | gamma(1) | delta(0) | delta(1) | rr(0) | rr(1) | u.s | p.s],
-// ps doubles apart, by the parity of the residual they belong to.  The state keeps
+// Partials of a field: [gamma(0) | gamma(1) | delta(0) | delta(1) | rr(0) | rr(1) | u.s |
+// p.s], ps doubles apart, by the parity of the residual they belong to.  The state keeps
 // gamma, alpha and the iteration count by parity: step i reads the slots of step i - 1
 // and writes its own, so no block reads a value another block of its launch writes.
 // ----------------------------------------------------------------------------------
@@ -504,12 +545,16 @@ struct Cg1State {
     double tol2;      // the segment stops when rr <= tol2 * bb
     double gamma[2];  // gamma_i by parity of i
     double alpha[2];  // alpha_i by parity of i
-    int done;         // 0 running, 1 converged, 2 iteration limit, 3 breakdown
+    int done;         // 0 running, 1 converged, 2 iteration limit, 3 breakdown, 4 idle
     int maxit;
     int iters[2];     // step i writes iters[i & 1] = i + 1
+    int poff;         // iteration parity = launch parity ^ poff
+    int kind0;        // kind of the segment's first step (kCg1Fresh / kCg1Continued)
+    int it0;          // iteration count at the segment's start
+    int pad;
 };
 
-enum { kCg1Step = 0, kCg1Fresh = 1, kCg1Continued = 2, kCg1Init = 3 };
+enum { kCg1Step = 0, kCg1Fresh = 1, kCg1Continued = 2 };
 
 __device__ __forceinline__ double* cg1_part(double* p, int ps, int k) { return p + (size_t)k * ps; }
 
@@ -527,21 +572,35 @@ __device__ __forceinline__ void load_node_nbhd2(const Grid& g, int i, int j, con
         }
 }
 
-// One step (KIND kCg1Step / kCg1Fresh / kCg1Continued) at parity `parity`, or the
-// initialisation (kCg1Init: r_0 = Rin = b, w_0 = K D^{-1} b, p = s = x = 0, written to
-// set 0 with parity = 1).  A fresh step takes beta = 0; a continued step (after a
-// residual replacement) takes the direction K-conjugate to the kept p, with the exact
-// p^T K p, from the u.s / p.s partials of k_cg1_replace2.
-template <typename T, int KIND>
+// One step of every running field.  The first step of a segment is fresh (beta = 0) or
+// continued (after a residual replacement: the direction K-conjugate to the kept p,
+// with the exact p^T K p, from the u.s / p.s partials of k_cg1_start2); the kind is
+// read from the field's state.
+template <typename T>
 __global__ __launch_bounds__(kPcgBlock) void k_cg1_step2(
     Grid g, const T* __restrict__ alpha, const T* __restrict__ K, const uint8_t* __restrict__ mask,
-    const T* __restrict__ winv, T ik0, T ik1, const T* __restrict__ Rin, const T* __restrict__ Win,
-    const T* __restrict__ Sin, T* __restrict__ Rout, T* __restrict__ Wout, T* __restrict__ Sout,
-    T* __restrict__ P, double* __restrict__ x, double* __restrict__ part, Cg1State* st, int ps,
-    int npart, int parity, int maxit, double tol2) {
-    if (KIND != kCg1Init && st->done) return;
+    const T* __restrict__ winv, T ik0, T ik1, T* __restrict__ R0, T* __restrict__ R1, T* __restrict__ W0,
+    T* __restrict__ W1, T* __restrict__ S0, T* __restrict__ S1, T* __restrict__ P, double* __restrict__ x,
+    double* __restrict__ part, Cg1State* st, int ps, int npart, int lp) {
+    const FieldBlock fb = field_block();
+    Cg1State* sb = st + fb.field;
+    if (sb->done) return;
     __shared__ double lds[80];
-    const int n = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const int cur = lp ^ sb->poff, nxt = cur ^ 1;
+    const int kind = sb->iters[nxt] == sb->it0 ? sb->kind0 : kCg1Step;
+    const size_t fo = (size_t)fb.field * g.n_dofs;
+    alpha += (size_t)fb.field * g.n_elems;
+    winv += (size_t)fb.field * g.n_nodes;
+    const T* Rin = (cur ? R1 : R0) + fo;
+    const T* Win = (cur ? W1 : W0) + fo;
+    const T* Sin = (cur ? S1 : S0) + fo;
+    T* Rout = (nxt ? R1 : R0) + fo;
+    T* Wout = (nxt ? W1 : W0) + fo;
+    T* Sout = (nxt ? S1 : S0) + fo;
+    P += fo;
+    x += fo;
+    double* pb = part + (size_t)fb.field * kPcgParts * ps;
+    const int n = fb.blk * blockDim.x + threadIdx.x;
     const bool own = n < g.n_nodes;
     T rs[3][3][2], ws[3][3][2], ss[3][3][2], wv[3][3], al[2][2], pv[2];
     double xv[2];
@@ -550,42 +609,28 @@ __global__ __launch_bounds__(kPcgBlock) void k_cg1_step2(
     if (own) {  // every load is issued before the wait on the scalar reduction
         node_ijk(g, n, i, j, k);
         load_nbhd2(g, i, j, FetchPlain<T>{Rin, g.n_nodes}, rs);
-        if constexpr (KIND != kCg1Init) {
-            load_nbhd2(g, i, j, FetchPlain<T>{Win, g.n_nodes}, ws);
-            load_nbhd2(g, i, j, FetchPlain<T>{Sin, g.n_nodes}, ss);
-        }
+        load_nbhd2(g, i, j, FetchPlain<T>{Win, g.n_nodes}, ws);
+        load_nbhd2(g, i, j, FetchPlain<T>{Sin, g.n_nodes}, ss);
         load_node_nbhd2(g, i, j, winv, wv);
         load_alpha2(g, i, j, alpha, al);
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
             const size_t idx = (size_t)c * g.n_nodes + n;
             mk[c] = mask[idx];
-            if constexpr (KIND != kCg1Init) {
-                pv[c] = P[idx];
-                xv[c] = x[idx];
-            }
+            pv[c] = P[idx];
+            xv[c] = x[idx];
         }
     }
-    const int cur = parity, nxt = parity ^ 1;
     double be = 0.0, ah = 0.0;
-    if constexpr (KIND == kCg1Init) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-            st->done = 0;
-            st->maxit = maxit;
-            st->iters[0] = st->iters[1] = 0;
-            st->bb = st->rr = 0.0;
-            st->tol2 = tol2;
-        }
-    } else {
-        double red[5];
-        if constexpr (KIND == kCg1Continued) {
-            const double* arrs[5] = {cg1_part(part, ps, cur), cg1_part(part, ps, 2 + cur),
-                                     cg1_part(part, ps, 4 + cur), cg1_part(part, ps, 6),
-                                     cg1_part(part, ps, 7)};
+    {
+        double red[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        if (kind == kCg1Continued) {
+            const double* arrs[5] = {cg1_part(pb, ps, cur), cg1_part(pb, ps, 2 + cur),
+                                     cg1_part(pb, ps, 4 + cur), cg1_part(pb, ps, 6), cg1_part(pb, ps, 7)};
             block_sum_arrays<5>(arrs, npart, red, lds);
         } else {
-            const double* arrs[3] = {cg1_part(part, ps, cur), cg1_part(part, ps, 2 + cur),
-                                     cg1_part(part, ps, 4 + cur)};
+            const double* arrs[3] = {cg1_part(pb, ps, cur), cg1_part(pb, ps, 2 + cur),
+                                     cg1_part(pb, ps, 4 + cur)};
             double r3[3];
             block_sum_arrays<3>(arrs, npart, r3, lds);
             red[0] = r3[0];
@@ -593,15 +638,15 @@ __global__ __launch_bounds__(kPcgBlock) void k_cg1_step2(
             red[2] = r3[2];
         }
         const double gam = red[0], dlt = red[1], rr = red[2];
-        const double bb = KIND == kCg1Fresh ? rr : st->bb;
+        const double bb = kind == kCg1Fresh ? rr : sb->bb;
         int code = 0;
         if (!isfinite(rr)) code = 3;
-        else if (rr <= st->tol2 * bb) code = 1;
-        else if (st->iters[nxt] >= st->maxit) code = 2;
+        else if (rr <= sb->tol2 * bb) code = 1;
+        else if (sb->iters[nxt] >= sb->maxit) code = 2;
         if (!code) {
-            if constexpr (KIND == kCg1Fresh) {
+            if (kind == kCg1Fresh) {
                 ah = gam / dlt;
-            } else if constexpr (KIND == kCg1Continued) {
+            } else if (kind == kCg1Continued) {
                 const double us = red[3], pss = red[4];
                 if (pss > 0.0 && isfinite(pss)) {
                     be = -us / pss;
@@ -610,20 +655,20 @@ __global__ __launch_bounds__(kPcgBlock) void k_cg1_step2(
                     ah = gam / dlt;
                 }
             } else {
-                be = gam / st->gamma[nxt];
-                ah = gam / (dlt - be * gam / st->alpha[nxt]);
+                be = gam / sb->gamma[nxt];
+                ah = gam / (dlt - be * gam / sb->alpha[nxt]);
             }
             if (!(ah > 0.0) || !isfinite(ah) || !isfinite(be)) code = 3;
         }
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-            if (KIND == kCg1Fresh) st->bb = rr;
-            st->rr = rr;
+        if (fb.blk == 0 && threadIdx.x == 0) {
+            if (kind == kCg1Fresh) sb->bb = rr;
+            sb->rr = rr;
             if (code) {
-                st->done = code;
+                sb->done = code;
             } else {
-                st->gamma[cur] = gam;
-                st->alpha[cur] = ah;
-                st->iters[cur] = st->iters[nxt] + 1;
+                sb->gamma[cur] = gam;
+                sb->alpha[cur] = ah;
+                sb->iters[cur] = sb->iters[nxt] + 1;
             }
         }
         if (code) return;
@@ -639,11 +684,8 @@ __global__ __launch_bounds__(kPcgBlock) void k_cg1_step2(
             for (int dx = 0; dx < 3; ++dx)
 #pragma unroll
                 for (int c = 0; c < 2; ++c) {
-                    T si = T(0), rn = rs[dy][dx][c];
-                    if constexpr (KIND != kCg1Init) {
-                        si = ws[dy][dx][c] + tb * ss[dy][dx][c];
-                        rn = rn - ta * si;
-                    }
+                    const T si = ws[dy][dx][c] + tb * ss[dy][dx][c];
+                    const T rn = rs[dy][dx][c] - ta * si;
                     un[dy][dx][c] = rn * wv[dy][dx] * ik[c];
                     if (dy == 1 && dx == 1) {
                         snew[c] = si;
@@ -654,14 +696,9 @@ __global__ __launch_bounds__(kPcgBlock) void k_cg1_step2(
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
             const size_t idx = (size_t)c * g.n_nodes + n;
-            if constexpr (KIND == kCg1Init) {
-                P[idx] = T(0);
-                x[idx] = 0.0;
-            } else {
-                const T pn = rs[1][1][c] * wv[1][1] * ik[c] + tb * pv[c];  // u_i + beta p_{i-1}
-                P[idx] = pn;
-                x[idx] = xv[c] + (double)ta * (double)pn;
-            }
+            const T pn = rs[1][1][c] * wv[1][1] * ik[c] + tb * pv[c];  // u_i + beta p_{i-1}
+            P[idx] = pn;
+            x[idx] = xv[c] + (double)ta * (double)pn;
             Sout[idx] = snew[c];
             Rout[idx] = rnew[c];
         }
@@ -679,26 +716,33 @@ __global__ __launch_bounds__(kPcgBlock) void k_cg1_step2(
     }
     block_reduce<3>(v, lds);
     if (threadIdx.x == 0) {
-        cg1_part(part, ps, nxt)[blockIdx.x] = v[0];
-        cg1_part(part, ps, 2 + nxt)[blockIdx.x] = v[1];
-        cg1_part(part, ps, 4 + nxt)[blockIdx.x] = v[2];
+        cg1_part(pb, ps, nxt)[fb.blk] = v[0];
+        cg1_part(pb, ps, 2 + nxt)[fb.blk] = v[1];
+        cg1_part(pb, ps, 4 + nxt)[fb.blk] = v[2];
     }
 }
 
-// s = K p recomputed for the direction of the last step, into the set that step wrote.
-// The recursion s_i = w_i + beta_i s_{i-1} carries each rounding of K u through about
-// 1 / (1 - beta) iterations (beta ~ 0.98 here), which in float32 lets the recursive
-// residual drift from the true one; refreshing s every kPcgChunk iterations bounds
-// that sum.  Reads p (neighbourhood) only and writes s (own node).
+// s = K p recomputed for the direction of the step launched at parity lp, into the set
+// that step wrote.  The recursion s_i = w_i + beta_i s_{i-1} carries each rounding of
+// K u through about 1 / (1 - beta) iterations (beta ~ 0.98 here), which would let the
+// recursive residual drift from the true one; refreshing s every kPcgChunk iterations
+// bounds that sum.  Reads p (neighbourhood) only and writes s (own node).
 template <typename T>
 __global__ __launch_bounds__(kPcgBlock) void k_cg1_refresh2(Grid g, const T* __restrict__ alpha,
                                                          const T* __restrict__ K,
                                                          const uint8_t* __restrict__ mask,
-                                                         const T* __restrict__ P, T* __restrict__ S,
-                                                         const Cg1State* st) {
-    if (st->done) return;
-    const int n = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+                                                         const T* __restrict__ P, T* __restrict__ S0,
+                                                         T* __restrict__ S1, const Cg1State* st, int lp) {
+    const FieldBlock fb = field_block();
+    const Cg1State* sb = st + fb.field;
+    if (sb->done) return;
+    const int n = fb.blk * blockDim.x + threadIdx.x;
     if (n >= g.n_nodes) return;
+    const int nxt = lp ^ sb->poff ^ 1;
+    const size_t fo = (size_t)fb.field * g.n_dofs;
+    P += fo;
+    T* S = (nxt ? S1 : S0) + fo;
+    alpha += (size_t)fb.field * g.n_elems;
     int i, j, k;
     node_ijk(g, n, i, j, k);
     T ps_[3][3][2], al[2][2], out[2];
@@ -712,18 +756,37 @@ __global__ __launch_bounds__(kPcgBlock) void k_cg1_refresh2(Grid g, const T* __r
     }
 }
 
-// Residual replacement of the one-reduction recursion: r = scale * r64 (the float64 true
-// residual), u = D^{-1} r, w = K u, and s = K p computed exactly for the kept direction
-// p, written to set `cur` with x = 0; partials of gamma, delta, rr (parity cur) and of
-// u.s, p.s, from which the continued step takes its conjugate direction.
+// Start of a segment of the one-reduction recursion, written to set it0 & 1 with x = 0:
+// r = scale * r64 (the float64 true residual, scaled), u = D^{-1} r, w = K u, and the
+// partials of gamma, delta, rr.  A fresh start clears p and s (its first step takes
+// beta = 0); a continued one computes s = K p exactly for the kept direction p and the
+// partials of u.s, p.s, from which its first step takes the conjugate direction.
+// Idle fields are skipped.
 template <typename T>
-__global__ __launch_bounds__(kPcgBlock) void k_cg1_replace2(
+__global__ __launch_bounds__(kPcgBlock) void k_cg1_start2(
     Grid g, const T* __restrict__ alpha, const T* __restrict__ K, const uint8_t* __restrict__ mask,
-    const T* __restrict__ winv, T ik0, T ik1, const double* __restrict__ r64, double scale,
-    const T* __restrict__ P, T* __restrict__ R, T* __restrict__ W, T* __restrict__ S,
-    double* __restrict__ x, double* __restrict__ part, int ps, int cur) {
+    const T* __restrict__ winv, T ik0, T ik1, const double* __restrict__ r64, const double* __restrict__ fsc,
+    T* __restrict__ P, T* __restrict__ R0, T* __restrict__ R1, T* __restrict__ W0, T* __restrict__ W1,
+    T* __restrict__ S0, T* __restrict__ S1, double* __restrict__ x, double* __restrict__ part,
+    const Cg1State* st, int ps) {
+    const FieldBlock fb = field_block();
+    const Cg1State* sb = st + fb.field;
+    if (sb->done) return;
     __shared__ double lds[80];
-    const int n = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const int cur = sb->it0 & 1;
+    const bool fresh = sb->kind0 == kCg1Fresh;
+    const double scale = fsc[fb.field];
+    const size_t fo = (size_t)fb.field * g.n_dofs;
+    alpha += (size_t)fb.field * g.n_elems;
+    winv += (size_t)fb.field * g.n_nodes;
+    r64 += fo;
+    P += fo;
+    x += fo;
+    T* R = (cur ? R1 : R0) + fo;
+    T* W = (cur ? W1 : W0) + fo;
+    T* S = (cur ? S1 : S0) + fo;
+    double* pb = part + (size_t)fb.field * kPcgParts * ps;
+    const int n = fb.blk * blockDim.x + threadIdx.x;
     double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     if (n < g.n_nodes) {
         int i, j, k;
@@ -731,11 +794,11 @@ __global__ __launch_bounds__(kPcgBlock) void k_cg1_replace2(
         double rs[3][3][2];
         T ps_[3][3][2], wv[3][3], al[2][2];
         load_nbhd2(g, i, j, FetchPlain<double>{r64, g.n_nodes}, rs);
-        load_nbhd2(g, i, j, FetchPlain<T>{P, g.n_nodes}, ps_);
+        if (!fresh) load_nbhd2(g, i, j, FetchPlain<T>{P, g.n_nodes}, ps_);
         load_node_nbhd2(g, i, j, winv, wv);
         load_alpha2(g, i, j, alpha, al);
         const T ik[2] = {ik0, ik1};
-        T un[3][3][2], rown[2], uown[2], pown[2];
+        T un[3][3][2], rown[2], uown[2], pown[2] = {T(0), T(0)};
 #pragma unroll
         for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
@@ -747,12 +810,12 @@ __global__ __launch_bounds__(kPcgBlock) void k_cg1_replace2(
                     if (dy == 1 && dx == 1) {
                         rown[c] = rn;
                         uown[c] = un[1][1][c];
-                        pown[c] = ps_[1][1][c];
+                        if (!fresh) pown[c] = ps_[1][1][c];
                     }
                 }
-        T wo[2], so[2];
+        T wo[2], so[2] = {T(0), T(0)};
         apply_nbhd2(K, un, al, wo);
-        apply_nbhd2(K, ps_, al, so);
+        if (!fresh) apply_nbhd2(K, ps_, al, so);
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
             const size_t idx = (size_t)c * g.n_nodes + n;
@@ -762,6 +825,7 @@ __global__ __launch_bounds__(kPcgBlock) void k_cg1_replace2(
             R[idx] = rown[c];
             W[idx] = wn;
             S[idx] = sn;
+            if (fresh) P[idx] = T(0);
             x[idx] = 0.0;
             v[0] += (double)rown[c] * (double)uown[c];
             v[1] += (double)wn * (double)uown[c];
@@ -772,125 +836,23 @@ __global__ __launch_bounds__(kPcgBlock) void k_cg1_replace2(
     }
     block_reduce<5>(v, lds);
     if (threadIdx.x == 0) {
-        cg1_part(part, ps, cur)[blockIdx.x] = v[0];
-        cg1_part(part, ps, 2 + cur)[blockIdx.x] = v[1];
-        cg1_part(part, ps, 4 + cur)[blockIdx.x] = v[2];
-        cg1_part(part, ps, 6)[blockIdx.x] = v[3];
-        cg1_part(part, ps, 7)[blockIdx.x] = v[4];
+        cg1_part(pb, ps, cur)[fb.blk] = v[0];
+        cg1_part(pb, ps, 2 + cur)[fb.blk] = v[1];
+        cg1_part(pb, ps, 4 + cur)[fb.blk] = v[2];
+        cg1_part(pb, ps, 6)[fb.blk] = v[3];
+        cg1_part(pb, ps, 7)[fb.blk] = v[4];
     }
 }
 
-// ----------------------------------------------------------------------------------
-// float64 residual r = f - K u over free DOFs (u zero on Dirichlet DOFs), with
-// per-block partials of ||r||^2, f^T u and u^T r for every field (blockIdx.y);
-// k_residual_sum reduces them (one block per field) into out[4*b .. 4*b+2].
-// ----------------------------------------------------------------------------------
-// Residual, compliance and u^T r terms of one free DOF, accumulated into v.
-__device__ __forceinline__ double residual_dof(const uint8_t* __restrict__ mask,
-                                               const double* __restrict__ f,
-                                               const double* __restrict__ ub, double* rb,
-                                               size_t idx, double o, double (&v)[3]) {
-    const bool fixed = mask[idx] != 0;
-    const double fi = fixed ? 0.0 : f[idx];
-    const double ui = ub[idx];
-    const double ri = fixed ? 0.0 : fi - o;
-    if (rb) rb[idx] = ri;
-    v[0] += ri * ri;
-    v[1] += fi * ui;
-    v[2] += ui * ri;
-    return ri;
-}
-
-__device__ __forceinline__ void residual_partials(double (&v)[3], double* __restrict__ part,
-                                                  size_t b, double* lds) {
-    block_reduce<3>(v, lds);
-    const int nb = gridDim.x;
-    double* pb = part + b * 3 * nb;
-    if (threadIdx.x == 0) {
-        pb[blockIdx.x] = v[0];
-        pb[nb + blockIdx.x] = v[1];
-        pb[2 * nb + blockIdx.x] = v[2];
-    }
-}
-
-__global__ __launch_bounds__(kBlock) void k_residual2(Grid g, const double* __restrict__ alpha,
-                                                      const double* __restrict__ K,
-                                                      const uint8_t* __restrict__ mask,
-                                                      const double* __restrict__ u,
-                                                      const double* __restrict__ f,
-                                                      double* __restrict__ r,
-                                                      double* __restrict__ part) {
-    __shared__ double lds[48];
-    const size_t b = blockIdx.y;
-    const int n = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    const double* ub = u + b * g.n_dofs;
-    double v[3] = {0.0, 0.0, 0.0};
-    if (n < g.n_nodes) {
-        int i, j, k;
-        node_ijk(g, n, i, j, k);
-        double o[2];
-        node_apply2<double>(g, i, j, alpha + b * g.n_elems, K, FetchPlain<double>{ub, g.n_nodes}, o);
-#pragma unroll
-        for (int c = 0; c < 2; ++c)
-            residual_dof(mask, f, ub, r ? r + b * g.n_dofs : nullptr, (size_t)c * g.n_nodes + n, o[c], v);
-    }
-    residual_partials(v, part, b, lds);
-}
-
-// 3D: one block per march column; M is the table of reduced element blocks.
-__global__ __launch_bounds__(kBlock) void k_residual3(Grid g, const double* __restrict__ alpha,
-                                                      const double* __restrict__ M,
-                                                      const uint8_t* __restrict__ mask,
-                                                      const double* __restrict__ u,
-                                                      const double* __restrict__ f,
-                                                      double* __restrict__ r,
-                                                      double* __restrict__ part) {
-    __shared__ MarchLds<double> L;
-    __shared__ double lds[48];
-    const size_t b = blockIdx.y;
-    const double* ub = u + b * g.n_dofs;
-    const MarchBlock m = march3_block(g, xcd_block(blockIdx.x, gridDim.x));
-    for (int i = threadIdx.x; i < kFacSize; i += blockDim.x) L.M[i] = M[i];
-    const MarchSlots sl = march3_slots(g, m);
-    SrcPlain<double> src{ub, g.n_nodes};
-    march3_prologue(g, m, sl, src);
-    double v[3] = {0.0, 0.0, 0.0};
-    double* rb = r ? r + b * g.n_dofs : nullptr;
-    auto emit = [&](int n, const double (&o)[3], const double (&)[3]) {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) residual_dof(mask, f, ub, rb, (size_t)c * g.n_nodes + n, o[c], v);
-    };
-    march3_run(g, m, sl, alpha + b * g.n_elems, L, src, emit);
-    residual_partials(v, part, b, lds);
-}
-
-__global__ __launch_bounds__(kBlock) void k_residual_sum(int nb, const double* __restrict__ part,
-                                                         double* __restrict__ out) {
-    __shared__ double lds[16];
-    const int b = blockIdx.x;
-    const double* pb = part + (size_t)b * 3 * nb;
-    const double s0 = block_sum_array(pb, nb, lds);
-    const double s1 = block_sum_array(pb + nb, nb, lds);
-    const double s2 = block_sum_array(pb + 2 * nb, nb, lds);
-    if (threadIdx.x == 0) {
-        out[4 * b + 0] = s0;
-        out[4 * b + 1] = s1;
-        out[4 * b + 2] = s2;
-    }
-}
-
-// rhs of a correction solve: b = s * r (cast to the inner precision)
+// u_b += s_b * d_b for the fields with s_b != 0 (grid (blocks, B))
 template <typename T>
-__global__ void k_scale_cast(long long n, const double* __restrict__ r, double s, T* __restrict__ b) {
+__global__ void k_correct(long long n, double* __restrict__ u, const T* __restrict__ d,
+                          const double* __restrict__ s) {
+    const int f = blockIdx.y;
+    const double sf = s[f];
+    if (sf == 0.0) return;
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) b[i] = (T)(s * r[i]);
-}
-
-// u += s * d
-template <typename T>
-__global__ void k_correct(long long n, double* __restrict__ u, const T* __restrict__ d, double s) {
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) u[i] += s * (double)d[i];
+    if (i < n) u[(size_t)f * n + i] += sf * (double)d[(size_t)f * n + i];
 }
 
 // ----------------------------------------------------------------------------------
@@ -950,6 +912,111 @@ __global__ __launch_bounds__(kBlock) void k_gradient(Grid g, const double* __res
 }
 
 // ----------------------------------------------------------------------------------
+// float64 residual r = f - K u over free DOFs (u zero on Dirichlet DOFs), with
+// per-block partials of ||r||^2, f^T u and u^T r for every field (f shared by the
+// fields); k_residual_sum reduces them (one block per field) into out[4*b .. 4*b+2].
+// Fields with skip[b] != 0 (skip may be NULL) are left out.
+// ----------------------------------------------------------------------------------
+// Residual, compliance and u^T r terms of one free DOF, accumulated into v.
+__device__ __forceinline__ double residual_dof(const uint8_t* __restrict__ mask,
+                                               const double* __restrict__ f,
+                                               const double* __restrict__ ub, double* rb,
+                                               size_t idx, double o, double (&v)[3]) {
+    const bool fixed = mask[idx] != 0;
+    const double fi = fixed ? 0.0 : f[idx];
+    const double ui = ub[idx];
+    const double ri = fixed ? 0.0 : fi - o;
+    if (rb) rb[idx] = ri;
+    v[0] += ri * ri;
+    v[1] += fi * ui;
+    v[2] += ui * ri;
+    return ri;
+}
+
+__device__ __forceinline__ void residual_partials(double (&v)[3], double* __restrict__ part,
+                                                  const FieldBlock& fb, double* lds) {
+    block_reduce<3>(v, lds);
+    const int nb = gridDim.x;
+    double* pb = part + (size_t)fb.field * 3 * nb;
+    if (threadIdx.x == 0) {
+        pb[fb.blk] = v[0];
+        pb[nb + fb.blk] = v[1];
+        pb[2 * nb + fb.blk] = v[2];
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_residual2(Grid g, const double* __restrict__ alpha,
+                                                      const double* __restrict__ K,
+                                                      const uint8_t* __restrict__ mask,
+                                                      const double* __restrict__ u,
+                                                      const double* __restrict__ f,
+                                                      double* __restrict__ r,
+                                                      double* __restrict__ part, const int* skip) {
+    const FieldBlock fb = field_block();
+    if (skip && skip[fb.field]) return;
+    __shared__ double lds[48];
+    const size_t b = fb.field;
+    const int n = fb.blk * blockDim.x + threadIdx.x;
+    const double* ub = u + b * g.n_dofs;
+    double v[3] = {0.0, 0.0, 0.0};
+    if (n < g.n_nodes) {
+        int i, j, k;
+        node_ijk(g, n, i, j, k);
+        double o[2];
+        node_apply2<double>(g, i, j, alpha + b * g.n_elems, K, FetchPlain<double>{ub, g.n_nodes}, o);
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+            residual_dof(mask, f, ub, r ? r + b * g.n_dofs : nullptr, (size_t)c * g.n_nodes + n, o[c], v);
+    }
+    residual_partials(v, part, fb, lds);
+}
+
+// 3D: one block per march column and field; M is the table of reduced element blocks.
+__global__ __launch_bounds__(kBlock) void k_residual3(Grid g, const double* __restrict__ alpha,
+                                                      const double* __restrict__ M,
+                                                      const uint8_t* __restrict__ mask,
+                                                      const double* __restrict__ u,
+                                                      const double* __restrict__ f,
+                                                      double* __restrict__ r,
+                                                      double* __restrict__ part, const int* skip) {
+    const FieldBlock fb = field_block();
+    if (skip && skip[fb.field]) return;
+    __shared__ MarchLds<double> L;
+    __shared__ double lds[48];
+    const size_t b = fb.field;
+    const double* ub = u + b * g.n_dofs;
+    const MarchBlock m = march3_block(g, fb.blk);
+    for (int i = threadIdx.x; i < kFacSize; i += blockDim.x) L.M[i] = M[i];
+    const MarchSlots sl = march3_slots(g, m);
+    SrcPlain<double> src{ub, g.n_nodes};
+    march3_prologue(g, m, sl, src);
+    double v[3] = {0.0, 0.0, 0.0};
+    double* rb = r ? r + b * g.n_dofs : nullptr;
+    auto emit = [&](int n, const double (&o)[3], const double (&)[3]) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) residual_dof(mask, f, ub, rb, (size_t)c * g.n_nodes + n, o[c], v);
+    };
+    march3_run(g, m, sl, alpha + b * g.n_elems, L, src, emit);
+    residual_partials(v, part, fb, lds);
+}
+
+__global__ __launch_bounds__(kBlock) void k_residual_sum(int nb, const double* __restrict__ part,
+                                                         double* __restrict__ out, const int* skip) {
+    __shared__ double lds[16];
+    const int b = blockIdx.x;
+    if (skip && skip[b]) return;
+    const double* pb = part + (size_t)b * 3 * nb;
+    const double s0 = block_sum_array(pb, nb, lds);
+    const double s1 = block_sum_array(pb + nb, nb, lds);
+    const double s2 = block_sum_array(pb + 2 * nb, nb, lds);
+    if (threadIdx.x == 0) {
+        out[4 * b + 0] = s0;
+        out[4 * b + 1] = s1;
+        out[4 * b + 2] = s2;
+    }
+}
+
+// ----------------------------------------------------------------------------------
 // Host drivers
 // ----------------------------------------------------------------------------------
 static int launch_tables(Ctx* ctx, const Grid& g, const topo_mesh& m, const double* rho,
@@ -960,31 +1027,16 @@ static int launch_tables(Ctx* ctx, const Grid& g, const topo_mesh& m, const doub
                        a64, a32);
     TOPO_CHECK_LAUNCH();
     if (w64 || w32) {
-        hipLaunchKernelGGL(k_winv, dim3(grid_blocks(g.n_nodes)), dim3(kBlock), 0, s, g, a64, w64, w32);
+        hipLaunchKernelGGL(k_winv, dim3(grid_blocks(g.n_nodes), B), dim3(kBlock), 0, s, g, a64, w64, w32);
         TOPO_CHECK_LAUNCH();
     }
     return TOPO_OK;
 }
 
-// Inner PCG solve K x = b in precision T to ||r||/||b|| <= tol (recursive residual).
-template <int DIM, typename T>
-struct PcgRun {
-    const T* alpha;
-    const T* K;
-    const uint8_t* mask;
-    const T* winv;
-    T ik[3];
-    T *b, *r, *z, *p0, *p1, *q;
-    double* x;  // the segment's correction, accumulated in float64
-    double* part;
-    PcgState* st;
-};
-
-
-// Launch geometry of the PCG kernels: node-linear blocks for the init / update, stencil
+// Launch geometry of the PCG kernels: node-linear blocks for the start / update, stencil
 // blocks for the apply, the stride of the partial arrays, and how many partials each
 // consumer sums (1 when a launch has more blocks than kPcgMaxBlocks: its partials are
-// then summed once by k_partials_sum).
+// then summed once by k_partials_sum).  The one-reduction step uses nupd / nrz.
 struct PcgGeom {
     int nupd, napp, ps;
     int npq, nrz;  // partials read of the apply's pq and of the update's rz / rr
@@ -1000,300 +1052,203 @@ static PcgGeom pcg_geom(const Grid& g) {
     return pg;
 }
 
+// Device buffers of a batched solve.  The one-reduction recursion (2D float64) uses
+// r, z as its residual sets, q, e0 as its w sets, p0, p1 as its s sets and e1 as p.
+template <typename T>
+struct PcgBufs {
+    int B;
+    const T* alpha;    // [B][N_e]
+    const T* K;        // 2D: dense element matrix; 3D: reduced element blocks
+    const uint8_t* mask;
+    const T* winv;     // [B][N_n]
+    T ik[3];           // 1 / K_e[c][c]
+    T *r, *z, *p0, *p1, *q, *e0, *e1;  // [B][N_u]
+    double* x;         // [B][N_u] the segment's correction, accumulated in float64
+    double* part;      // [B][kPcgParts][ps]
+    PcgState* st;      // [B]
+    Cg1State* st1;     // [B]
+    const double* r64; // [B][N_u] float64 true residual
+    const double* fsc; // [B] scale of each field's inner system
+};
 
-// Collapse the rz / rr partials of parity `par` written by a node-linear launch.
-static void pcg_sum_rz(const PcgGeom& pg, double* part, int par, const PcgState* st, LaunchSink& L) {
-    if (pg.nrz == 1 && pg.nupd > 1)
-        L((const void*)k_partials_sum, dim3(1), dim3(1024), part + (1 + par) * (size_t)pg.ps,
-          part + (3 + par) * (size_t)pg.ps, (int)pg.nupd, (const int*)&st->done);
-}
-
-// One PCG iteration (apply + update).
+// One iteration of the two-kernel recursion (apply + update) at launch parity lp.
 template <int DIM, typename T>
-static void pcg_iteration(Ctx* ctx, const Grid& g, const PcgRun<DIM, T>& w, const PcgGeom& pg,
-                          int parity, int first, LaunchSink& L, int timing) {
-    const T* pold = parity ? w.p1 : w.p0;
-    T* pnew = parity ? w.p0 : w.p1;
-    const T* zc = w.z;
+static void pcg_iteration(Ctx* ctx, const Grid& g, const PcgBufs<T>& w, const PcgGeom& pg, int lp,
+                          LaunchSink& L, int timing) {
     {
         TimedLaunch tl(ctx, KID_PCG_APPLY, L.s, L.graph ? kTimeOff : timing, true);
         L.ev0 = tl.a;
         L.ev1 = tl.b;
         const void* fn = DIM == 2 ? (const void*)k_pcg_apply2<T> : (const void*)k_pcg_apply3<T>;
-        L(fn, dim3(pg.napp), dim3(DIM == 2 ? kPcgBlock : kBlock), g, w.alpha, w.K, w.mask, zc, pold, pnew, w.q, w.part, w.st,
-          (int)pg.ps, (int)pg.nrz, parity, first);
+        L(fn, dim3(pg.napp, w.B), dim3(DIM == 2 ? kPcgBlock : kBlock), g, w.alpha, w.K, w.mask,
+          (const T*)w.z, w.p0, w.p1, w.q, w.part, w.st, pg.ps, pg.nrz, lp);
     }
     if (pg.npq == 1 && pg.napp > 1)
-        L((const void*)k_partials_sum, dim3(1), dim3(1024), w.part, (double*)nullptr, (int)pg.napp,
-          (const int*)&w.st->done);
+        L((const void*)k_partials_sum<PcgState>, dim3(w.B), dim3(1024), w.part, pg.ps, pg.napp, 0, 0, -1, 0,
+          (const PcgState*)w.st, lp, 0);
     {
         TimedLaunch tl(ctx, KID_PCG_UPDATE, L.s, L.graph ? kTimeOff : timing, true);
         L.ev0 = tl.a;
         L.ev1 = tl.b;
-        L((const void*)k_pcg_update<DIM, T>, dim3(pg.nupd), dim3(kPcgBlock), g, w.winv, w.ik[0], w.ik[1],
-          w.ik[2], w.x, w.r, w.z, (const T*)pnew, (const T*)w.q, w.part, w.st, (int)pg.ps, (int)pg.npq,
-          parity);
+        L((const void*)k_pcg_update<DIM, T>, dim3(pg.nupd, w.B), dim3(kPcgBlock), g, w.winv, w.ik[0], w.ik[1],
+          w.ik[2], w.x, w.r, w.z, (const T*)w.p0, (const T*)w.p1, (const T*)w.q, w.part, w.st, pg.ps, pg.npq,
+          lp);
     }
-    pcg_sum_rz(pg, w.part, parity, w.st, L);
+    if (pg.nrz == 1 && pg.nupd > 1)  // rz / rr of the update's own parity
+        L((const void*)k_partials_sum<PcgState>, dim3(w.B), dim3(1024), w.part, pg.ps, pg.nupd, 1, 1, 3, 1,
+          (const PcgState*)w.st, lp, 0);
+}
+
+// One step of the one-reduction recursion at launch parity lp (then s = K p when refresh).
+template <typename T>
+static void cg1_step(Ctx* ctx, const Grid& g, const PcgBufs<T>& w, const PcgGeom& pg, int lp, LaunchSink& L,
+                     int timing, bool refresh) {
+    {
+        TimedLaunch tl(ctx, KID_PCG_STEP, L.s, L.graph ? kTimeOff : timing, true);
+        L.ev0 = tl.a;
+        L.ev1 = tl.b;
+        L((const void*)k_cg1_step2<T>, dim3(pg.nupd, w.B), dim3(kPcgBlock), g, w.alpha, w.K, w.mask, w.winv,
+          w.ik[0], w.ik[1], w.r, w.z, w.q, w.e0, w.p0, w.p1, w.e1, w.x, w.part, w.st1, pg.ps, pg.nrz, lp);
+    }
+    if (pg.nrz == 1 && pg.nupd > 1) {  // the set the step wrote: its parity ^ 1
+        L((const void*)k_partials_sum<Cg1State>, dim3(w.B), dim3(1024), w.part, pg.ps, pg.nupd, 0, 1, 2, 1,
+          (const Cg1State*)w.st1, lp, 1);
+        L((const void*)k_partials_sum<Cg1State>, dim3(w.B), dim3(1024), w.part, pg.ps, pg.nupd, 4, 1, -1, 0,
+          (const Cg1State*)w.st1, lp, 1);
+    }
+    if (refresh)
+        L((const void*)k_cg1_refresh2<T>, dim3(pg.nupd, w.B), dim3(kPcgBlock), g, w.alpha, w.K, w.mask,
+          (const T*)w.e1, w.p0, w.p1, (const Cg1State*)w.st1, lp);
 }
 
 constexpr int kPcgChunk = 16;  // iterations per graph replay (even)
 
-// Graph of kPcgChunk iterations starting at parity 1 (so every replay continues the
-// parity sequence).
+// Start of a phase: every running field's segment starts (state uploaded by the host),
+// its partials are written for the first launch of the phase (launch parity 1).
 template <int DIM, typename T>
-static int pcg_graph(Ctx* ctx, const Grid& g, const PcgRun<DIM, T>& w, const PcgGeom& pg,
-                     hipGraphExec_t* out) {
-    std::vector<uintptr_t> key = {(uintptr_t)DIM, sizeof(T), (uintptr_t)pg.napp, (uintptr_t)kPcgChunk,
-                                  (uintptr_t)g.nx, (uintptr_t)g.ny, (uintptr_t)g.nz,
-                                  (uintptr_t)w.alpha, (uintptr_t)w.K, (uintptr_t)w.mask,
-                                  (uintptr_t)w.winv, (uintptr_t)w.x, (uintptr_t)w.r, (uintptr_t)w.z,
-                                  (uintptr_t)w.p0, (uintptr_t)w.p1, (uintptr_t)w.q, (uintptr_t)w.part,
-                                  (uintptr_t)w.st};
-    for (int c = 0; c < 3; ++c) key_push_double(key, (double)w.ik[c]);
-    return cached_graph(ctx, key, [&](LaunchSink& L) {
-        for (int c = 0; c < kPcgChunk; ++c) pcg_iteration<DIM, T>(ctx, g, w, pg, (1 + c) & 1, 0, L, kTimeOff);
-    }, out);
+static void phase_start(const Grid& g, const PcgBufs<T>& w, const PcgGeom& pg, bool one_red, LaunchSink& L) {
+    if (one_red) {
+        L((const void*)k_cg1_start2<T>, dim3(pg.nupd, w.B), dim3(kPcgBlock), g, w.alpha, w.K, w.mask, w.winv,
+          w.ik[0], w.ik[1], w.r64, w.fsc, w.e1, w.r, w.z, w.q, w.e0, w.p0, w.p1, w.x, w.part,
+          (const Cg1State*)w.st1, pg.ps);
+        if (pg.nrz == 1 && pg.nupd > 1) {  // set it0 & 1, the first step's parity
+            L((const void*)k_partials_sum<Cg1State>, dim3(w.B), dim3(1024), w.part, pg.ps, pg.nupd, 0, 1, 2, 1,
+              (const Cg1State*)w.st1, 1, 0);
+            L((const void*)k_partials_sum<Cg1State>, dim3(w.B), dim3(1024), w.part, pg.ps, pg.nupd, 4, 1, 6, 0,
+              (const Cg1State*)w.st1, 1, 0);
+            L((const void*)k_partials_sum<Cg1State>, dim3(w.B), dim3(1024), w.part, pg.ps, pg.nupd, 7, 0, -1, 0,
+              (const Cg1State*)w.st1, 1, 0);
+        }
+    } else {
+        L((const void*)k_pcg_start<DIM, T>, dim3(pg.nupd, w.B), dim3(kPcgBlock), g, w.r64, w.fsc, w.winv,
+          w.ik[0], w.ik[1], w.ik[2], w.x, w.r, w.z, w.p0, w.part, (const PcgState*)w.st, pg.ps);
+        if (pg.nrz == 1 && pg.nupd > 1)  // the parity the first apply reads: its own ^ 1
+            L((const void*)k_partials_sum<PcgState>, dim3(w.B), dim3(1024), w.part, pg.ps, pg.nupd, 1, 1, 3, 1,
+              (const PcgState*)w.st, 1, 1);
+    }
 }
 
-// Runs iterations until the device state (type S, with a `done` field) reports done:
-// graph replays of kPcgChunk iterations (exec), or without graphs direct launches in
-// growing chunks; `direct(it, mode)` launches iteration it (parity it & 1).  issued: iterations
-// launched so far (odd when exec is used).  The host checks the state one chunk behind.
+// Iteration `it` of a phase (its launch parity is it & 1; a phase starts at it = 1).
+// The one-reduction recursion refreshes s after every iteration it with it % kPcgChunk
+// == 0, which is where every graph replay ends, so that graph and direct launches take
+// the same steps.
+template <int DIM, typename T>
+static void phase_iteration(Ctx* ctx, const Grid& g, const PcgBufs<T>& w, const PcgGeom& pg, bool one_red,
+                            long long it, LaunchSink& L, int timing) {
+    if (one_red) cg1_step<T>(ctx, g, w, pg, (int)(it & 1), L, timing, it % kPcgChunk == 0);
+    else pcg_iteration<DIM, T>(ctx, g, w, pg, (int)(it & 1), L, timing);
+}
+
+// Graph of kPcgChunk iterations starting at launch parity 1.
+template <int DIM, typename T>
+static int phase_graph(Ctx* ctx, const Grid& g, const PcgBufs<T>& w, const PcgGeom& pg, bool one_red,
+                       hipGraphExec_t* out, hipStream_t s) {
+    std::vector<uintptr_t> key = {(uintptr_t)0xB7C6, (uintptr_t)DIM, sizeof(T), (uintptr_t)one_red,
+                                  (uintptr_t)w.B, (uintptr_t)pg.napp, (uintptr_t)pg.nupd, (uintptr_t)kPcgChunk,
+                                  (uintptr_t)g.nx, (uintptr_t)g.ny, (uintptr_t)g.nz, (uintptr_t)g.mtarget,
+                                  (uintptr_t)w.alpha, (uintptr_t)w.K, (uintptr_t)w.mask, (uintptr_t)w.winv,
+                                  (uintptr_t)w.x, (uintptr_t)w.r, (uintptr_t)w.z, (uintptr_t)w.p0,
+                                  (uintptr_t)w.p1, (uintptr_t)w.q, (uintptr_t)w.e0, (uintptr_t)w.e1,
+                                  (uintptr_t)w.part, (uintptr_t)w.st, (uintptr_t)w.st1};
+    for (int c = 0; c < 3; ++c) key_push_double(key, (double)w.ik[c]);
+    return cached_graph(ctx, key, [&](LaunchSink& G) {
+        for (int c = 0; c < kPcgChunk; ++c)
+            phase_iteration<DIM, T>(ctx, g, w, pg, one_red, 1 + c, G, kTimeOff);
+    }, out, s);
+}
+
+// Runs a phase until every field's device state (type S, with a `done` field) reports
+// done: graph replays of kPcgChunk iterations (exec), or without graphs direct launches
+// in growing chunks; `direct(it, mode)` launches iteration it.  The host checks the
+// states one chunk behind.  A timing sample replaces one replay by kPcgChunk direct
+// iterations, the first two of them timed.  hs: pinned host slots [2][B]; result: [B].
 template <typename S, typename Direct>
-static int pcg_poll(Ctx* ctx, hipStream_t s, const S* st, hipGraphExec_t exec, long long issued,
-                    long long cap, Direct direct, S* result) {
-    void* pin = nullptr;
-    int rc = pinned_host(ctx, 2 * sizeof(S), &pin);
-    if (rc) return rc;
-    S* hs = (S*)pin;
+static int run_phase(Ctx* ctx, hipStream_t s, const S* st, int B, hipGraphExec_t exec, long long cap,
+                     Direct direct, S* hs, S* result, std::initializer_list<int> kids) {
     hipEvent_t ev[2];
     TOPO_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
     TOPO_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
     bool pending[2] = {false, false};
-    long long replays = 0;
+    long long replays = 0, issued = 1;
     int chunk = 4;
     int slot = 0;
+    int rc = TOPO_OK;
     while (true) {
         const int every = ctx->timing.every;
+        const long long issued_before = issued;
         if (exec && !(every > 0 && replays % every == 0)) {
-            TOPO_HIP(hipGraphLaunch(exec, s));
+            const hipError_t e = hipGraphLaunch(exec, s);
+            if (e != hipSuccess) {
+                rc = set_error(ctx, TOPO_EDEVICE, "hipGraphLaunch: %s", hipGetErrorString(e));
+                break;
+            }
             issued += kPcgChunk;
         } else if (exec) {
-            // timing sample: two directly launched, timed iterations (keeps the parity)
-            for (int c = 0; c < 2; ++c, ++issued) direct(issued, kTimeForced);
+            for (int c = 0; c < kPcgChunk; ++c, ++issued) direct(issued, c < 2 ? kTimeForced : kTimeOff);
         } else {
             for (int c = 0; c < chunk; ++c, ++issued) direct(issued, kTimeSampled);
             if (chunk < 64) chunk *= 2;
         }
         ++replays;
-        TOPO_CHECK_LAUNCH();
-        TOPO_HIP(hipMemcpyAsync(&hs[slot], st, sizeof(S), hipMemcpyDeviceToHost, s));
-        TOPO_HIP(hipEventRecord(ev[slot], s));
+        if (every > 0)
+            for (int kid : kids) ctx->timing.launched[kid] += issued - issued_before;
+        hipError_t e = hipGetLastError();
+        if (e == hipSuccess) e = hipMemcpyAsync(hs + (size_t)slot * B, st, B * sizeof(S), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipEventRecord(ev[slot], s);
+        if (e != hipSuccess) {
+            rc = set_error(ctx, TOPO_EDEVICE, "PCG phase launch: %s", hipGetErrorString(e));
+            break;
+        }
         pending[slot] = true;
         const int other = slot ^ 1;
         bool stop = false;
         if (pending[other]) {
-            TOPO_HIP(hipEventSynchronize(ev[other]));
+            e = hipEventSynchronize(ev[other]);
+            if (e != hipSuccess) {
+                rc = set_error(ctx, TOPO_EDEVICE, "PCG phase: %s", hipGetErrorString(e));
+                break;
+            }
             pending[other] = false;
-            stop = hs[other].done != 0;
+            stop = true;
+            for (int b = 0; b < B; ++b) stop &= hs[(size_t)other * B + b].done != 0;
         }
         if (stop || issued >= cap) break;
         slot = other;
     }
-    TOPO_HIP(hipStreamSynchronize(s));
-    TOPO_HIP(hipEventDestroy(ev[0]));
-    TOPO_HIP(hipEventDestroy(ev[1]));
-    TOPO_HIP(hipMemcpyAsync(&hs[0], st, sizeof(S), hipMemcpyDeviceToHost, s));
-    TOPO_HIP(hipStreamSynchronize(s));
-    *result = hs[0];
-    return TOPO_OK;
-}
-
-// Runs PCG iterations until the device state reports done.  fresh: initialise from
-// w.b (x = 0) with stopping tolerance tol and maxit, and run iteration 0 (which records
-// ||b||^2); otherwise continue a segment whose state (done = 0, bb, tol2) the host has
-// uploaded after a residual replacement, at iteration iters0.
-template <int DIM, typename T>
-static int pcg_run(Ctx* ctx, const Grid& g, PcgRun<DIM, T>& w, bool fresh, double tol, int maxit,
-                   int iters0, hipStream_t s, PcgState* result) {
-    const PcgGeom pg = pcg_geom(g);
-    LaunchSink L;
-    L.s = s;
-    long long issued;
-    if (fresh) {
-        hipLaunchKernelGGL((k_pcg_init<DIM, T>), dim3(pg.nupd), dim3(kPcgBlock), 0, s, g, w.b, w.winv,
-                           w.ik[0], w.ik[1], w.ik[2], w.x, w.r, w.z, w.p0, w.part, w.st, pg.ps,
-                           maxit, tol * tol);
-        TOPO_CHECK_LAUNCH();
-        pcg_sum_rz(pg, w.part, 1, w.st, L);
-        // iteration 0 (parity 0) records ||b||; the rest continue at parity 1
-        pcg_iteration<DIM, T>(ctx, g, w, pg, 0, 1, L, kTimeSampled);
-        issued = 1;
-    } else {
-        issued = iters0;
-        if ((issued & 1) == 0) {  // graphs start at an odd iteration
-            pcg_iteration<DIM, T>(ctx, g, w, pg, 0, 0, L, kTimeSampled);
-            ++issued;
-        }
-    }
-    TOPO_CHECK_LAUNCH();
-    TOPO_HIP(L.err);
-    hipGraphExec_t exec = nullptr;
-    if (graphs_enabled()) {
-        const int rc = pcg_graph<DIM, T>(ctx, g, w, pg, &exec);
-        if (rc) return rc;
-    }
-    auto direct = [&](long long it, int mode) { pcg_iteration<DIM, T>(ctx, g, w, pg, (int)(it & 1), 0, L, mode); };
-    const int rc = pcg_poll<PcgState>(ctx, s, w.st, exec, issued, (long long)maxit + 4096, direct, result);
+    (void)hipStreamSynchronize(s);
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
     if (rc) return rc;
-    TOPO_HIP(L.err);
+    TOPO_HIP(hipMemcpyAsync(hs, st, B * sizeof(S), hipMemcpyDeviceToHost, s));
+    TOPO_HIP(hipStreamSynchronize(s));
+    std::copy(hs, hs + B, result);
     return TOPO_OK;
-}
-
-// ----------------------------------------------------------------------------------
-// Host side of the 2D one-reduction recursion (k_cg1_step2).
-// ----------------------------------------------------------------------------------
-template <typename T>
-struct Cg1Run {
-    const T* alpha;
-    const T* K;
-    const uint8_t* mask;
-    const T* winv;
-    T ik[2];
-    T* b;
-    T *R[2], *W[2], *S[2];  // r, w = K D^{-1} r, s = K p by parity
-    T* P;
-    double* x;
-    double* part;
-    Cg1State* st;
-    int nb, npart, ps;  // blocks, partials each block sums, partial stride
-};
-
-// Collapse the partials of parity par (and the u.s / p.s ones of a replacement) when the
-// launch had more blocks than kPcgMaxBlocks.
-template <typename T>
-static void cg1_sum(const Cg1Run<T>& w, int par, bool extra, LaunchSink& L) {
-    if (w.npart != 1 || w.nb <= 1) return;
-    const int* done = &w.st->done;
-    const size_t ps = (size_t)w.ps;
-    L((const void*)k_partials_sum, dim3(1), dim3(1024), w.part + par * ps, w.part + (2 + par) * ps, w.nb, done);
-    L((const void*)k_partials_sum, dim3(1), dim3(1024), w.part + (4 + par) * ps,
-      extra ? w.part + 6 * ps : (double*)nullptr, w.nb, done);
-    if (extra)
-        L((const void*)k_partials_sum, dim3(1), dim3(1024), w.part + 7 * ps, (double*)nullptr, w.nb, done);
-}
-
-template <typename T>
-static void cg1_step(Ctx* ctx, const Grid& g, const Cg1Run<T>& w, int parity, int kind, LaunchSink& L,
-                     int timing, bool refresh = false) {
-    const int nxt = parity ^ 1;
-    {
-        TimedLaunch tl(ctx, KID_PCG_STEP, L.s, L.graph ? kTimeOff : timing, true);
-        L.ev0 = tl.a;
-        L.ev1 = tl.b;
-        const void* fn = kind == kCg1Fresh       ? (const void*)k_cg1_step2<T, kCg1Fresh>
-                         : kind == kCg1Continued ? (const void*)k_cg1_step2<T, kCg1Continued>
-                                                 : (const void*)k_cg1_step2<T, kCg1Step>;
-        L(fn, dim3(w.nb), dim3(kPcgBlock), g, w.alpha, w.K, w.mask, w.winv, w.ik[0], w.ik[1],
-          (const T*)w.R[parity], (const T*)w.W[parity], (const T*)w.S[parity], w.R[nxt], w.W[nxt],
-          w.S[nxt], w.P, w.x, w.part, w.st, w.ps, w.npart, parity, 0, 0.0);
-    }
-    cg1_sum(w, nxt, false, L);
-    if (refresh)
-        L((const void*)k_cg1_refresh2<T>, dim3(w.nb), dim3(kPcgBlock), g, w.alpha, w.K, w.mask, (const T*)w.P,
-          w.S[nxt], (const Cg1State*)w.st);
-}
-
-// The one-reduction counterpart of pcg_run: fresh (init from w.b, then a first step with
-// beta = 0) or continued after k_cg1_replace2 has written set iters0 & 1.
-template <typename T>
-static int cg1_run(Ctx* ctx, const Grid& g, Cg1Run<T>& w, bool fresh, double tol, int maxit, int iters0,
-                   hipStream_t s, Cg1State* result) {
-    LaunchSink L;
-    L.s = s;
-    long long issued;
-    if (fresh) {
-        L((const void*)k_cg1_step2<T, kCg1Init>, dim3(w.nb), dim3(kPcgBlock), g, w.alpha, w.K, w.mask,
-          w.winv, w.ik[0], w.ik[1], (const T*)w.b, (const T*)nullptr, (const T*)nullptr, w.R[0], w.W[0],
-          w.S[0], w.P, w.x, w.part, w.st, w.ps, w.npart, 1, maxit, tol * tol);
-        cg1_sum(w, 0, false, L);
-        cg1_step(ctx, g, w, 0, kCg1Fresh, L, kTimeSampled);
-        issued = 1;
-    } else {
-        cg1_step(ctx, g, w, iters0 & 1, kCg1Continued, L, kTimeSampled);
-        issued = iters0 + 1;
-        if ((issued & 1) == 0) {  // graphs start at an odd iteration
-            cg1_step(ctx, g, w, 0, kCg1Step, L, kTimeSampled);
-            ++issued;
-        }
-    }
-    TOPO_CHECK_LAUNCH();
-    TOPO_HIP(L.err);
-    hipGraphExec_t exec = nullptr;
-    if (graphs_enabled()) {
-        std::vector<uintptr_t> key = {(uintptr_t)0xC61, sizeof(T), (uintptr_t)w.nb, (uintptr_t)w.npart,
-                                      (uintptr_t)w.ps, (uintptr_t)kPcgChunk, (uintptr_t)g.nx, (uintptr_t)g.ny,
-                                      (uintptr_t)w.alpha, (uintptr_t)w.K, (uintptr_t)w.mask, (uintptr_t)w.winv,
-                                      (uintptr_t)w.R[0], (uintptr_t)w.R[1], (uintptr_t)w.W[0], (uintptr_t)w.W[1],
-                                      (uintptr_t)w.S[0], (uintptr_t)w.S[1], (uintptr_t)w.P, (uintptr_t)w.x,
-                                      (uintptr_t)w.part, (uintptr_t)w.st};
-        for (int c = 0; c < 2; ++c) key_push_double(key, (double)w.ik[c]);
-        const int rc = cached_graph(ctx, key, [&](LaunchSink& G) {
-            for (int c = 0; c < kPcgChunk; ++c)
-                cg1_step(ctx, g, w, (1 + c) & 1, kCg1Step, G, kTimeOff, c == kPcgChunk - 1);
-        }, &exec);
-        if (rc) return rc;
-    }
-    // iteration it refreshes s when it ends a chunk of kPcgChunk (as the graph's last step)
-    auto direct = [&](long long it, int mode) {
-        cg1_step(ctx, g, w, (int)(it & 1), kCg1Step, L, mode, (it % kPcgChunk) == 0);
-    };
-    const int rc = pcg_poll<Cg1State>(ctx, s, w.st, exec, issued, (long long)maxit + 4096, direct, result);
-    if (rc) return rc;
-    TOPO_HIP(L.err);
-    return TOPO_OK;
-}
-
-// Largest ratio of true to recursive residual at the end of a segment for which the
-// recursion is continued after the residual replacement (else it restarts).
-static double replace_drift_max() {
-    static double v = [] {
-        const char* e = std::getenv("TOPO_REPLACE_DRIFT");
-        return e ? std::atof(e) : 4.0;
-    }();
-    return v;
-}
-
-// Whether a 2D solve runs the one-reduction recursion (one kernel per iteration):
-// float64 solves do; float32 solves keep the two-kernel recursion, whose recursively
-// updated residual stays closer to the true one in float32 (the one-reduction form also
-// updates s = K p recursively, and at 241k DOF needed 2.4x the iterations in float32).
-// TOPO_PCG_ONE_REDUCTION=1 / 0 selects it for both precisions / for neither.
-static bool one_reduction(bool fp64) {
-    static const int mode = [] {
-        const char* e = std::getenv("TOPO_PCG_ONE_REDUCTION");
-        return e && e[0] ? std::atoi(e) : -1;
-    }();
-    return mode < 0 ? fp64 : mode != 0;
-}
-
-// Reduction of the residual a float32 segment aims for before its residual is replaced
-// by the float64 one (small enough to keep the replacements rare, large enough that the
-// float32 recursion has not drifted from the true residual).
-static double mixed_segment_tol() {
-    static double v = [] {
-        const char* e = std::getenv("TOPO_MIXED_SEGMENT_TOL");
-        double t = e ? std::atof(e) : 0.0;
-        return t > 0.0 ? t : 1e-2;
-    }();
-    return v;
 }
 
 // K64: the dense element matrix in 2D, the reduced element blocks in 3D.
 static int residual_launch(Ctx* ctx, const Grid& g0, const double* K64, const double* alpha64,
                            const uint8_t* mask, const double* u, const double* f, double* r, int B,
-                           double* part, double* out, hipStream_t s) {
+                           double* part, double* out, const int* skip, hipStream_t s) {
     // the residual march fits its own resident wave (never more blocks than a grid with
     // the default target, which sized the caller's partial arrays)
     Grid g = g0;
@@ -1303,308 +1258,386 @@ static int residual_launch(Ctx* ctx, const Grid& g0, const double* K64, const do
         TimedLaunch tl(ctx, KID_RESIDUAL, s);
         if (g.dim == 2)
             hipLaunchKernelGGL(k_residual2, dim3(nb, B), dim3(kBlock), 0, s, g, alpha64, K64, mask,
-                               u, f, r, part);
+                               u, f, r, part, skip);
         else
             hipLaunchKernelGGL(k_residual3, dim3(nb, B), dim3(kBlock), 0, s, g, alpha64, K64, mask,
-                               u, f, r, part);
+                               u, f, r, part, skip);
     }
     TOPO_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_residual_sum, dim3(B), dim3(kBlock), 0, s, nb, (const double*)part, out);
+    hipLaunchKernelGGL(k_residual_sum, dim3(B), dim3(kBlock), 0, s, nb, (const double*)part, out, skip);
     TOPO_CHECK_LAUNCH();
     return TOPO_OK;
 }
 
 template <typename T>
 struct HdmWs {
-    double *a64, *w64, *r64, *part, *rpart, *rout, *x;
-    T *b, *r, *z, *p0, *p1, *q;
-    T *e0 = nullptr, *e1 = nullptr;  // 2D: the one-reduction recursion's two further vectors
+    double *a64 = nullptr, *w64 = nullptr, *r64 = nullptr, *part = nullptr, *rpart = nullptr,
+           *rout = nullptr, *x = nullptr, *fsc = nullptr, *corr = nullptr;
+    T *r = nullptr, *z = nullptr, *p0 = nullptr, *p1 = nullptr, *q = nullptr;
+    T *e0 = nullptr, *e1 = nullptr;  // 2D float64: the one-reduction recursion's two further vectors
     float *a32 = nullptr, *w32 = nullptr;
-    PcgState* st;
-    Cg1State* st1;
+    int* skip = nullptr;
+    PcgState* st = nullptr;
+    Cg1State* st1 = nullptr;
 };
 
 template <typename T>
-static void hdm_takes(Arena& ar, const Grid& g, bool mixed, HdmWs<T>& w) {
-    const long long N = g.n_dofs;
-    const int nb = partial_stride(g);
-    ar.take(&w.a64, g.n_elems);
-    ar.take(&w.w64, g.n_nodes);
+static void hdm_takes(Arena& ar, const Grid& g, bool mixed, int B, HdmWs<T>& w) {
+    const size_t N = (size_t)B * g.n_dofs;
+    const size_t ps = partial_stride(g);
+    ar.take(&w.a64, (size_t)B * g.n_elems);
+    ar.take(&w.w64, (size_t)B * g.n_nodes);
     if (mixed) {
-        ar.take(&w.a32, g.n_elems);
-        ar.take(&w.w32, g.n_nodes);
+        ar.take(&w.a32, (size_t)B * g.n_elems);
+        ar.take(&w.w32, (size_t)B * g.n_nodes);
     }
     ar.take(&w.r64, N);
-    ar.take(&w.part, 8 * (size_t)nb);  // 5 arrays in 3D, 8 in 2D
-    ar.take(&w.rpart, 3 * (size_t)nb);
-    ar.take(&w.rout, 4);
-    ar.take(&w.st, 1);
-    ar.take(&w.st1, 1);
-    ar.take(&w.b, N);
+    ar.take(&w.part, (size_t)B * kPcgParts * ps);
+    ar.take(&w.rpart, (size_t)B * 3 * ps);
+    ar.take(&w.rout, (size_t)4 * B);
+    ar.take(&w.fsc, (size_t)B);
+    ar.take(&w.corr, (size_t)B);
+    ar.take(&w.skip, (size_t)B);
+    ar.take(&w.st, (size_t)B);
+    ar.take(&w.st1, (size_t)B);
     ar.take(&w.x, N);
     ar.take(&w.r, N);
     ar.take(&w.z, N);
     ar.take(&w.p0, N);
     ar.take(&w.p1, N);
     ar.take(&w.q, N);
-    if (g.dim == 2) {
+    if (g.dim == 2 && !mixed) {
         ar.take(&w.e0, N);
         ar.take(&w.e1, N);
     }
 }
 
-size_t ws_hdm_solve(const Grid& g, bool mixed) {
+size_t ws_hdm_solve(const Grid& g, bool mixed, int B) {
     Arena ar;
     if (mixed) {
         HdmWs<float> w;
-        hdm_takes(ar, g, true, w);
+        hdm_takes(ar, g, true, B, w);
     } else {
         HdmWs<double> w;
-        hdm_takes(ar, g, false, w);
+        hdm_takes(ar, g, false, B, w);
     }
     return ar.total();
 }
 
+// Largest ratio of true to recursive residual at the end of a segment for which the
+// recursion is continued after the residual replacement (else it restarts).
+constexpr double kReplaceDriftMax = 4.0;
+// Reduction of the residual a float32 segment aims for before its residual is replaced
+// by the float64 one (small enough to keep the replacements rare, large enough that the
+// float32 recursion has not drifted from the true residual; 3e-3 .. 1e-1 measured
+// within 2 % of each other in iterations).
+constexpr double kMixedSegmentTol = 1e-2;
+
+// Batched HDM solve of the fields with solve[b] != 0 (the others are left untouched):
+// one Krylov recursion per field in precision T, cut into segments: each segment runs
+// until its recursive residual has dropped by its tolerance, then its correction is
+// added to u in float64, the true residual f - K u is recomputed in float64 and
+// replaces the recursive one, and the recursion continues with the same search
+// direction (or restarts when it had drifted).  The inner system of each field is
+// scaled by 1 / ||f|| so that float32 values stay O(1).  2D float64 solves run the
+// one-reduction recursion (one kernel per iteration).  Per-field outcomes go to
+// status[b] (TOPO_OK, TOPO_ENOCONV, TOPO_ENOTSPD) and stagnated[b]; the return value
+// is a device or allocation error only.
 template <int DIM, typename T>
-static int hdm_solve_impl(Ctx* ctx, const topo_mesh& m, const Grid& g0, const ElemTables* tb,
-                          const double* rho, const uint8_t* mask, const double* f, double* u,
-                          double rtol, int maxit, bool mixed, double* compliance,
-                          topo_info* info, hipStream_t s, bool* stagnated) {
+static int hdm_batch_impl(Ctx* ctx, const topo_mesh& m, const Grid& g0, const ElemTables* tb,
+                          const double* rho, const uint8_t* mask, const double* f, double* u, int B,
+                          double rtol, const int* maxit, const uint8_t* solve, bool mixed, topo_info* info,
+                          int* status, uint8_t* stagnated, hipStream_t s) {
     Grid g = g0;
     if constexpr (DIM == 3) g.mtarget = march3_target(ctx, (const void*)k_pcg_apply3<T>);
     const long long N = g.n_dofs;
-    if (stagnated) *stagnated = false;
+    const bool one_red = DIM == 2 && sizeof(T) == 8;
+    const PcgGeom pg = pcg_geom(g);
     Arena ar;
     HdmWs<T> ws;
-    hdm_takes(ar, g, mixed, ws);
+    hdm_takes(ar, g, mixed, B, ws);
     int rc = ar.commit(ctx, s);
     if (rc) return rc;
-    double *a64 = ws.a64, *w64 = ws.w64, *r64 = ws.r64, *part = ws.part, *rpart = ws.rpart,
-           *rout = ws.rout;
-    T *b = ws.b, *r = ws.r, *z = ws.z, *p0 = ws.p0, *p1 = ws.p1, *q = ws.q;
-    double* x = ws.x;
-    float *a32 = ws.a32, *w32 = ws.w32;
-    PcgState* st = ws.st;
+    rc = launch_tables(ctx, g, m, rho, B, ws.a64, ws.a32, ws.w64, ws.w32, s);
     if (rc) return rc;
-    rc = launch_tables(ctx, g, m, rho, 1, a64, a32, w64, w32, s);
-    if (rc) return rc;
-    const T* ta;
-    const T* tw;
+    PcgBufs<T> w{};
+    w.B = B;
     if constexpr (sizeof(T) == 4) {
-        ta = (const T*)a32;
-        tw = (const T*)w32;
+        w.alpha = (const T*)ws.a32;
+        w.winv = (const T*)ws.w32;
     } else {
-        ta = (const T*)a64;
-        tw = (const T*)w64;
+        w.alpha = (const T*)ws.a64;
+        w.winv = (const T*)ws.w64;
     }
-    PcgRun<DIM, T> w;
-    w.alpha = ta;
     // 2D: the dense element matrix; 3D: the reduced blocks of the symmetry-blocked form
     if constexpr (DIM == 2) w.K = sizeof(T) == 4 ? (const T*)tb->K32 : (const T*)tb->K64;
     else w.K = sizeof(T) == 4 ? (const T*)tb->M32 : (const T*)tb->M64;
     w.mask = mask;
-    w.winv = tw;
     for (int c = 0; c < 3; ++c) w.ik[c] = c < DIM ? (T)(1.0 / tb->diag[c]) : T(0);
-    w.b = b;
-    w.x = x;
-    w.r = r;
-    w.z = z;
-    w.p0 = p0;
-    w.p1 = p1;
-    w.q = q;
-    w.part = part;
-    w.st = st;
+    w.r = ws.r;
+    w.z = ws.z;
+    w.p0 = ws.p0;
+    w.p1 = ws.p1;
+    w.q = ws.q;
+    w.e0 = ws.e0;
+    w.e1 = ws.e1;
+    w.x = ws.x;
+    w.part = ws.part;
+    w.st = ws.st;
+    w.st1 = ws.st1;
+    w.r64 = ws.r64;
+    w.fsc = ws.fsc;
 
-    TOPO_HIP(hipMemsetAsync(u, 0, N * sizeof(double), s));
-    // pinned host layout: [2 state poll slots | 4 residual sums | state upload]
-    constexpr size_t kStateBytes = sizeof(PcgState) > sizeof(Cg1State) ? sizeof(PcgState) : sizeof(Cg1State);
-    const size_t pin_res = 2 * kStateBytes;
-    const size_t pin_up = pin_res + 4 * sizeof(double);
+    for (int b = 0; b < B; ++b)
+        if (solve[b]) TOPO_HIP(hipMemsetAsync(u + (size_t)b * N, 0, N * sizeof(double), s));
+
+    // pinned host layout: [2 poll slots | spare | state upload] x B states, then 4B
+    // residual sums, B scales, B corrections, B skip flags
+    constexpr size_t kSt = sizeof(PcgState) > sizeof(Cg1State) ? sizeof(PcgState) : sizeof(Cg1State);
+    const size_t off_res = 4 * B * kSt, off_fsc = off_res + 4 * B * sizeof(double),
+                 off_corr = off_fsc + B * sizeof(double), off_skip = off_corr + B * sizeof(double);
     void* pin = nullptr;
-    rc = pinned_host(ctx, pin_up + kStateBytes, &pin);
+    rc = pinned_host(ctx, off_skip + B * sizeof(int), &pin);
     if (rc) return rc;
-    auto residual = [&](double out[3]) -> int {
-        int rc2 = residual_launch(ctx, g, g.dim == 2 ? tb->K64 : tb->M64, a64, mask, u, f, r64, 1, rpart, rout, s);
+    char* pc = (char*)pin;
+    double* h_res = (double*)(pc + off_res);
+    double* h_fsc = (double*)(pc + off_fsc);
+    double* h_corr = (double*)(pc + off_corr);
+    int* h_skip = (int*)(pc + off_skip);
+    PcgState* up0 = (PcgState*)(pc + 3 * B * kSt);  // state upload area (one array of the
+    Cg1State* up1 = (Cg1State*)(pc + 3 * B * kSt);  // recursion's state type)
+
+    struct Field {
+        bool live = false, fresh = true, stagnated = false;
+        int total = 0, base = 0, segments = 0, status = TOPO_OK;
+        double nf = 0.0, scale = 1.0, rr = 0.0, rr_prev = INFINITY, res[3] = {0.0, 0.0, 0.0};
+        int fin_done = 0, fin_iters = 0;
+        double fin_rr = 0.0, last_rz[2] = {0.0, 0.0};
+    };
+    std::vector<Field> F(B);
+    // float64 residual of the fields with want[b]: r64, ||r||^2, f^T u, u^T r
+    auto residual = [&](const std::vector<char>& want) -> int {
+        for (int b = 0; b < B; ++b) h_skip[b] = want[b] ? 0 : 1;
+        TOPO_HIP(hipMemcpyAsync(ws.skip, h_skip, B * sizeof(int), hipMemcpyHostToDevice, s));
+        int rc2 = residual_launch(ctx, g, g.dim == 2 ? tb->K64 : tb->M64, ws.a64, mask, u, f, ws.r64, B,
+                                  ws.rpart, ws.rout, ws.skip, s);
         if (rc2) return rc2;
-        double* h = (double*)((char*)pin + pin_res);
-        TOPO_HIP(hipMemcpyAsync(h, rout, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+        TOPO_HIP(hipMemcpyAsync(h_res, ws.rout, 4 * B * sizeof(double), hipMemcpyDeviceToHost, s));
         TOPO_HIP(hipStreamSynchronize(s));
-        out[0] = h[0];
-        out[1] = h[1];
-        out[2] = h[2];
+        for (int b = 0; b < B; ++b)
+            if (want[b])
+                for (int q = 0; q < 3; ++q) F[b].res[q] = h_res[4 * b + q];
         return TOPO_OK;
     };
-    double res[3];
-    rc = residual(res);
+    std::vector<char> want(B, 0);
+    for (int b = 0; b < B; ++b) want[b] = solve[b] != 0;
+    rc = residual(want);
     if (rc) return rc;
-    // One Krylov recursion in precision T, cut into segments: each segment runs until
-    // its recursive residual has dropped by tol_seg, then its correction is added to u
-    // in float64, the true residual f - K u is recomputed in float64 and replaces the
-    // recursive one, and the recursion continues with the same search direction.  The
-    // inner system is scaled by 1 / ||f|| so that float32 values stay O(1).
-    const double nf = std::sqrt(res[0]);
-    const double scale = nf > 0.0 ? 1.0 / nf : 1.0;
-    const double seg_min = mixed ? mixed_segment_tol() : 0.0;
-    const PcgGeom pg = pcg_geom(g);
-    const int bl = grid_blocks(N);
-    const double drift_max = replace_drift_max();
-    int total = 0, base = 0, segments = 0, status = TOPO_OK;
-    bool fresh = true;
-    double rr = res[0], rr_prev = INFINITY;
-    // 2D: the one-reduction recursion (one kernel per iteration)
-    const bool one_red = DIM == 2 && one_reduction(sizeof(T) == 8);
-    Cg1Run<T> w1{};
-    if (one_red) {
-        w1.alpha = w.alpha;
-        w1.K = w.K;
-        w1.mask = mask;
-        w1.winv = w.winv;
-        w1.ik[0] = w.ik[0];
-        w1.ik[1] = w.ik[1];
-        w1.b = b;
-        w1.R[0] = r;
-        w1.R[1] = z;
-        w1.W[0] = q;
-        w1.W[1] = ws.e0;
-        w1.S[0] = p0;
-        w1.S[1] = p1;
-        w1.P = ws.e1;
-        w1.x = x;
-        w1.part = part;
-        w1.st = ws.st1;
-        w1.nb = grid_blocks(g.n_nodes, kPcgBlock);
-        w1.npart = w1.nb > kPcgMaxBlocks ? 1 : w1.nb;
-        w1.ps = pg.ps;
+    long long cap = 0;
+    for (int b = 0; b < B; ++b) {
+        Field& fd = F[b];
+        fd.live = solve[b] != 0;
+        fd.nf = std::sqrt(fd.res[0]);
+        fd.scale = fd.nf > 0.0 ? 1.0 / fd.nf : 1.0;
+        fd.rr = fd.res[0];
+        if (fd.live) cap = std::max(cap, (long long)maxit[b]);
     }
-    struct {
-        int done, iters;
-        double rr, bb;
-    } fin{};
-    double last_rz[2] = {0.0, 0.0};  // 3D: r.z of the last two iterations of a segment
-    // one segment of the recursion; its end state goes to fin
-    auto run_segment = [&](bool fr, double tol, int mi, int it0) -> int {
-        if (one_red) {
-            Cg1State st1{};
-            const int rc2 = cg1_run<T>(ctx, g, w1, fr, tol, mi, it0, s, &st1);
-            if (rc2) return rc2;
-            fin.done = st1.done;
-            fin.iters = std::max(st1.iters[0], st1.iters[1]);
-            fin.rr = st1.rr;
-            fin.bb = st1.bb;
-        } else {
-            PcgState st0{};
-            const int rc2 = pcg_run<DIM, T>(ctx, g, w, fr, tol, mi, it0, s, &st0);
-            if (rc2) return rc2;
-            fin.done = st0.done;
-            fin.iters = st0.iters;
-            fin.rr = st0.rr;
-            fin.bb = st0.bb;
-            last_rz[0] = st0.rz[0];
-            last_rz[1] = st0.rz[1];
-        }
-        return TOPO_OK;
-    };
+    cap += 4096;
+    const double seg_min = mixed ? kMixedSegmentTol : 0.0;
+    hipGraphExec_t exec = nullptr;
+    if (graphs_enabled()) {
+        rc = phase_graph<DIM, T>(ctx, g, w, pg, one_red, &exec, s);
+        if (rc) return rc;
+    }
+    std::vector<PcgState> res0(B);
+    std::vector<Cg1State> res1(B);
     while (true) {
-        const double rel = nf > 0.0 ? std::sqrt(rr) / nf : 0.0;
-        if (rel <= rtol) break;
-        if (total >= maxit || segments >= 400) {
-            status = set_error(ctx, TOPO_ENOCONV, "no convergence: rel. residual %.3e after %d iterations",
-                               rel, total);
-            break;
+        bool any = false;
+        for (int b = 0; b < B; ++b) {
+            Field& fd = F[b];
+            if (!fd.live) continue;
+            const double rel = fd.nf > 0.0 ? std::sqrt(fd.rr) / fd.nf : 0.0;
+            if (rel <= rtol) {
+                fd.live = false;
+            } else if (fd.total >= maxit[b] || fd.segments >= 400) {
+                fd.status = TOPO_ENOCONV;
+                fd.live = false;
+            } else if (fd.segments > 0 && !(fd.rr < 0.5 * fd.rr_prev)) {
+                fd.status = TOPO_ENOCONV;
+                fd.stagnated = true;
+                if (stagnated) stagnated[b] = 1;
+                fd.live = false;
+            } else {
+                any = true;
+            }
         }
-        if (segments > 0 && !(rr < 0.5 * rr_prev)) {
-            status = set_error(ctx, TOPO_ENOCONV, "residual replacement stagnated at rel. residual %.3e", rel);
-            if (stagnated) *stagnated = true;
-            break;
+        if (!any) break;
+        // per-field segment setup, uploaded as the fields' states
+        for (int b = 0; b < B; ++b) {
+            Field& fd = F[b];
+            h_fsc[b] = fd.live ? fd.scale : 0.0;
+            double tol_seg = 0.0;
+            if (fd.live) {
+                tol_seg = std::max(0.5 * rtol * fd.nf / std::sqrt(fd.rr), seg_min);
+                tol_seg = std::min(std::max(tol_seg, 1e-15), 0.5);
+                if (fd.fresh) fd.base = fd.total;
+            }
+            const int it0 = fd.live && !fd.fresh ? fd.fin_iters : 0;
+            const double bb = fd.live && !fd.fresh ? fd.rr * fd.scale * fd.scale : 0.0;
+            if (one_red) {
+                Cg1State c{};
+                c.done = fd.live ? 0 : 4;
+                c.tol2 = tol_seg * tol_seg;
+                c.bb = c.rr = bb;
+                c.maxit = maxit[b] - fd.base;
+                c.iters[0] = c.iters[1] = it0;
+                c.poff = (it0 & 1) ^ 1;
+                c.kind0 = fd.fresh ? kCg1Fresh : kCg1Continued;
+                c.it0 = it0;
+                up1[b] = c;
+            } else {
+                PcgState p{};
+                p.done = fd.live ? 0 : 4;
+                p.tol2 = tol_seg * tol_seg;
+                p.bb = p.rr = bb;
+                p.maxit = maxit[b] - fd.base;
+                p.iters = it0;
+                p.poff = (it0 & 1) ^ 1;
+                p.fresh = fd.fresh ? 1 : 0;
+                // the replaced residual's apply takes beta against the last recursive rz
+                p.rz[0] = fd.fresh ? 0.0 : fd.last_rz[0];
+                p.rz[1] = fd.fresh ? 0.0 : fd.last_rz[1];
+                up0[b] = p;
+            }
         }
-        double tol_seg = std::max(0.5 * rtol * nf / std::sqrt(rr), seg_min);
-        tol_seg = std::min(std::max(tol_seg, 1e-15), 0.5);
-        if (fresh) {
-            hipLaunchKernelGGL((k_scale_cast<T>), dim3(bl), dim3(kBlock), 0, s, N, r64, scale, b);
-            TOPO_CHECK_LAUNCH();
-            base = total;
-            rc = run_segment(true, tol_seg, maxit - base, 0);
-        } else if (one_red) {
-            Cg1State* up = (Cg1State*)((char*)pin + pin_up);
-            *up = Cg1State{};
-            up->bb = rr * scale * scale;
-            up->rr = up->bb;
-            up->tol2 = tol_seg * tol_seg;
-            up->done = 0;
-            up->maxit = maxit - base;
-            up->iters[0] = up->iters[1] = fin.iters;
-            TOPO_HIP(hipMemcpyAsync(w1.st, up, sizeof(Cg1State), hipMemcpyHostToDevice, s));
-            const int cur = fin.iters & 1;
-            hipLaunchKernelGGL((k_cg1_replace2<T>), dim3(w1.nb), dim3(kPcgBlock), 0, s, g, w1.alpha, w1.K,
-                               mask, w1.winv, w1.ik[0], w1.ik[1], (const double*)r64, scale,
-                               (const T*)w1.P, w1.R[cur], w1.W[cur], w1.S[cur], x, part, pg.ps, cur);
-            TOPO_CHECK_LAUNCH();
-            LaunchSink L;
-            L.s = s;
-            cg1_sum(w1, cur, true, L);
-            TOPO_HIP(L.err);
-            rc = run_segment(false, tol_seg, maxit - base, fin.iters);
-        } else {
-            // state first (done = 0), so that the partial sums below are not skipped
-            PcgState* up = (PcgState*)((char*)pin + pin_up);
-            *up = PcgState{};
-            up->bb = rr * scale * scale;
-            up->rr = up->bb;
-            up->tol2 = tol_seg * tol_seg;
-            up->done = 0;
-            up->iters = fin.iters;
-            up->maxit = maxit - base;
-            // the replaced residual's apply takes beta against the last recursive rz
-            up->rz[0] = last_rz[0];
-            up->rz[1] = last_rz[1];
-            TOPO_HIP(hipMemcpyAsync(st, up, sizeof(PcgState), hipMemcpyHostToDevice, s));
-            hipLaunchKernelGGL((k_pcg_replace<DIM, T>), dim3(pg.nupd), dim3(kPcgBlock), 0, s, g,
-                               (const double*)r64, scale, w.winv, w.ik[0], w.ik[1], w.ik[2], x, r, z,
-                               part, pg.ps, (fin.iters + 1) & 1);
-            TOPO_CHECK_LAUNCH();
-            LaunchSink L;
-            L.s = s;
-            pcg_sum_rz(pg, part, (fin.iters + 1) & 1, st, L);
-            TOPO_HIP(L.err);
-            rc = run_segment(false, tol_seg, maxit - base, fin.iters);
-        }
+        if (one_red)
+            TOPO_HIP(hipMemcpyAsync(ws.st1, up1, B * sizeof(Cg1State), hipMemcpyHostToDevice, s));
+        else
+            TOPO_HIP(hipMemcpyAsync(ws.st, up0, B * sizeof(PcgState), hipMemcpyHostToDevice, s));
+        TOPO_HIP(hipMemcpyAsync(ws.fsc, h_fsc, B * sizeof(double), hipMemcpyHostToDevice, s));
+        LaunchSink L;
+        L.s = s;
+        phase_start<DIM, T>(g, w, pg, one_red, L);
+        TOPO_HIP(L.err);
+        auto direct = [&](long long it, int mode) {
+            phase_iteration<DIM, T>(ctx, g, w, pg, one_red, it, L, mode);
+        };
+        if (one_red)
+            rc = run_phase<Cg1State>(ctx, s, ws.st1, B, exec, cap, direct, (Cg1State*)pin, res1.data(),
+                                     {KID_PCG_STEP});
+        else
+            rc = run_phase<PcgState>(ctx, s, ws.st, B, exec, cap, direct, (PcgState*)pin, res0.data(),
+                                     {KID_PCG_APPLY, KID_PCG_UPDATE});
         if (rc) return rc;
-        const int seg_iters = base + fin.iters - total;
-        total = base + fin.iters;
-        if (std::getenv("TOPO_DEBUG_PCG"))
-            fprintf(stderr, "[pcg] segment %d (%s): %d its, done %d, recursive rel %.3e (tol %.1e), true rel before %.3e\n",
-                    segments, fresh ? "fresh" : "continued", seg_iters, fin.done,
-                    std::sqrt(fin.rr / std::max(fin.bb, 1e-300)), tol_seg, std::sqrt(rr) / nf);
-        if (fin.done == 3 && seg_iters == 0) {
-            status = set_error(ctx, TOPO_ENOTSPD, "CG breakdown: p^T K p <= 0");
-            break;
+        TOPO_HIP(L.err);
+        // fold each running field's segment into u
+        bool corr_any = false;
+        for (int b = 0; b < B; ++b) {
+            Field& fd = F[b];
+            h_corr[b] = 0.0;
+            want[b] = 0;
+            if (!fd.live) continue;
+            if (one_red) {
+                fd.fin_done = res1[b].done;
+                fd.fin_iters = std::max(res1[b].iters[0], res1[b].iters[1]);
+                fd.fin_rr = res1[b].rr;
+            } else {
+                fd.fin_done = res0[b].done;
+                fd.fin_iters = res0[b].iters;
+                fd.fin_rr = res0[b].rr;
+                fd.last_rz[0] = res0[b].rz[0];
+                fd.last_rz[1] = res0[b].rz[1];
+            }
+            const int seg_iters = fd.base + fd.fin_iters - fd.total;
+            fd.total = fd.base + fd.fin_iters;
+            if (fd.fin_done == 3 && seg_iters == 0) {
+                fd.status = set_error(ctx, TOPO_ENOTSPD, "CG breakdown: p^T K p <= 0 (field %d)", b);
+                fd.live = false;
+                continue;
+            }
+            h_corr[b] = fd.nf > 0.0 ? fd.nf : 1.0;
+            want[b] = 1;
+            corr_any = true;
+            ++fd.segments;
+            fd.rr_prev = fd.rr;
         }
-        hipLaunchKernelGGL((k_correct<double>), dim3(bl), dim3(kBlock), 0, s, N, u, (const double*)x,
-                           nf > 0.0 ? nf : 1.0);
+        if (!corr_any) continue;
+        TOPO_HIP(hipMemcpyAsync(ws.corr, h_corr, B * sizeof(double), hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL((k_correct<double>), dim3(grid_blocks(N), B), dim3(kBlock), 0, s, N, u,
+                           (const double*)ws.x, (const double*)ws.corr);
         TOPO_CHECK_LAUNCH();
-        ++segments;
-        rr_prev = rr;
-        rc = residual(res);
+        rc = residual(want);
         if (rc) return rc;
-        rr = res[0];
-        if (fin.done == 3 && !(rr < rr_prev)) {
-            status = set_error(ctx, TOPO_ENOTSPD, "CG breakdown: p^T K p <= 0");
-            break;
+        for (int b = 0; b < B; ++b) {
+            Field& fd = F[b];
+            if (!want[b]) continue;
+            fd.rr = fd.res[0];
+            if (fd.fin_done == 3 && !(fd.rr < fd.rr_prev)) {
+                fd.status = set_error(ctx, TOPO_ENOTSPD, "CG breakdown: p^T K p <= 0 (field %d)", b);
+                fd.live = false;
+                continue;
+            }
+            // continue the recursion only while it still tracks the true residual; a
+            // segment whose true residual drifted far from the recursive one restarts
+            const double drift = fd.fin_rr > 0.0 ? std::sqrt(fd.rr) * fd.scale / std::sqrt(fd.fin_rr) : INFINITY;
+            fd.fresh = !(drift <= kReplaceDriftMax) || fd.fin_done != 1;
         }
-        // continue the recursion only while it still tracks the true residual; a
-        // segment whose true residual drifted far from the recursive one restarts
-        const double drift = fin.rr > 0.0 ? std::sqrt(rr) * scale / std::sqrt(fin.rr) : INFINITY;
-        fresh = !(drift <= drift_max) || fin.done != 1;
     }
-    if (info) {
-        info->iters = total;
-        info->refinements = segments;
-        info->rel_resid = nf > 0.0 ? std::sqrt(rr) / nf : 0.0;
-        info->compliance_raw = res[1];
-        info->compliance_corr = res[1] + res[2];
+    for (int b = 0; b < B; ++b) {
+        if (!solve[b]) continue;
+        const Field& fd = F[b];
+        topo_info& in = info[b];
+        in.iters = fd.total;
+        in.refinements = fd.segments;
+        in.rel_resid = fd.nf > 0.0 ? std::sqrt(fd.rr) / fd.nf : 0.0;
+        in.compliance_raw = fd.res[1];
+        in.compliance_corr = fd.res[1] + fd.res[2];
+        in.status = fd.status;
+        if (fd.status == TOPO_ENOCONV && !fd.stagnated)
+            set_error(ctx, TOPO_ENOCONV, "no convergence: rel. residual %.3e after %d iterations (field %d)",
+                      in.rel_resid, fd.total, b);
+        else if (fd.status == TOPO_ENOCONV)
+            set_error(ctx, TOPO_ENOCONV, "residual replacement stagnated at rel. residual %.3e (field %d)",
+                      in.rel_resid, b);
+        status[b] = fd.status;
     }
-    if (compliance) *compliance = res[1] + res[2];
-    return status;
+    return TOPO_OK;
+}
+
+// Batched solve with the mixed-precision fallback: a field whose float32 corrections
+// stop reducing the true residual (float32 rounding too coarse for its operator) is
+// redone in float64 from zero with the iterations it has left.
+template <int DIM>
+static int hdm_solve_batch(Ctx* ctx, const topo_mesh& m, const Grid& g, const ElemTables* tb, const double* rho,
+                           const uint8_t* mask, const double* f, double* u, int B, double rtol, int maxit,
+                           bool mixed, topo_info* info, hipStream_t s) {
+    std::vector<int> mi(B, maxit), status(B, TOPO_OK);
+    std::vector<uint8_t> solve(B, 1), stag(B, 0);
+    for (int b = 0; b < B; ++b) info[b] = topo_info{};
+    if (!mixed)
+        return hdm_batch_impl<DIM, double>(ctx, m, g, tb, rho, mask, f, u, B, rtol, mi.data(), solve.data(),
+                                           false, info, status.data(), nullptr, s);
+    int rc = hdm_batch_impl<DIM, float>(ctx, m, g, tb, rho, mask, f, u, B, rtol, mi.data(), solve.data(), true,
+                                        info, status.data(), stag.data(), s);
+    if (rc) return rc;
+    bool any = false;
+    std::vector<topo_info> first(info, info + B);
+    for (int b = 0; b < B; ++b) {
+        solve[b] = stag[b] && maxit - first[b].iters >= 1;
+        mi[b] = maxit - first[b].iters;
+        any |= solve[b] != 0;
+    }
+    if (!any) return TOPO_OK;
+    rc = hdm_batch_impl<DIM, double>(ctx, m, g, tb, rho, mask, f, u, B, rtol, mi.data(), solve.data(), false,
+                                     info, status.data(), nullptr, s);
+    if (rc) return rc;
+    for (int b = 0; b < B; ++b)
+        if (solve[b]) {
+            info[b].iters += first[b].iters;
+            info[b].refinements += first[b].refinements;
+            info[b].fp64_fallback = 1;
+        }
+    return TOPO_OK;
 }
 
 }  // namespace topo
@@ -1658,13 +1691,14 @@ int topo_apply(topo_ctx* ctx, const topo_mesh* mesh, const double* rho, const ui
     return TOPO_OK;
 }
 
-int topo_hdm_solve(topo_ctx* ctx, const topo_mesh* mesh, const double* rho, const uint8_t* mask,
-                   const double* f, double* u, double rtol, int32_t maxit, int32_t prec,
-                   double* compliance, topo_info* info, void* stream) {
+int topo_hdm_solve_batch(topo_ctx* ctx, const topo_mesh* mesh, const double* rho, const uint8_t* mask,
+                         const double* f, double* u, int32_t B, double rtol, int32_t maxit, int32_t prec,
+                         double* compliance, topo_info* info, void* stream) {
     if (!ctx) return TOPO_EINVAL;
     int rc = validate_mesh(ctx, mesh);
     if (rc) return rc;
     if (!rho || !mask || !f || !u) return set_error(ctx, TOPO_EINVAL, "null pointer argument");
+    if (B < 1) return set_error(ctx, TOPO_EINVAL, "B must be >= 1");
     if (!(rtol > 0.0) || !(rtol < 1.0)) return set_error(ctx, TOPO_EINVAL, "rtol must lie in (0, 1)");
     if (maxit < 1) return set_error(ctx, TOPO_EINVAL, "maxit must be >= 1");
     if (prec != TOPO_FP64 && prec != TOPO_MIXED) return set_error(ctx, TOPO_EINVAL, "bad precision");
@@ -1673,46 +1707,53 @@ int topo_hdm_solve(topo_ctx* ctx, const topo_mesh* mesh, const double* rho, cons
     const ElemTables* tb = get_tables(ctx, *mesh);
     if (!tb) return set_error(ctx, TOPO_EDEVICE, "element table upload failed");
     hipStream_t s = (hipStream_t)stream;
-    topo_info local{};
-    topo_info* inf = info ? info : &local;
-    *inf = topo_info{};
-    if (prec == TOPO_FP64)
-        return g.dim == 2 ? hdm_solve_impl<2, double>(ctx, *mesh, g, tb, rho, mask, f, u, rtol, maxit,
-                                                      false, compliance, inf, s, nullptr)
-                          : hdm_solve_impl<3, double>(ctx, *mesh, g, tb, rho, mask, f, u, rtol, maxit,
-                                                      false, compliance, inf, s, nullptr);
-    // mixed: float32 inner solves; if a float32 correction fails to reduce the true
-    // residual (float32 rounding too coarse for this operator), redo the solve in float64
-    bool stagnated = false;
-    rc = g.dim == 2 ? hdm_solve_impl<2, float>(ctx, *mesh, g, tb, rho, mask, f, u, rtol, maxit, true,
-                                               compliance, inf, s, &stagnated)
-                    : hdm_solve_impl<3, float>(ctx, *mesh, g, tb, rho, mask, f, u, rtol, maxit, true,
-                                               compliance, inf, s, &stagnated);
-    if (rc != TOPO_ENOCONV || !stagnated) return rc;
-    const topo_info first = *inf;
-    const int left = maxit - first.iters;
-    if (left < 1) return rc;
-    rc = g.dim == 2 ? hdm_solve_impl<2, double>(ctx, *mesh, g, tb, rho, mask, f, u, rtol, left, false,
-                                                compliance, inf, s, nullptr)
-                    : hdm_solve_impl<3, double>(ctx, *mesh, g, tb, rho, mask, f, u, rtol, left, false,
-                                                compliance, inf, s, nullptr);
-    inf->iters += first.iters;
-    inf->refinements += first.refinements;
-    inf->fp64_fallback = 1;
-    return rc;
+    std::vector<topo_info> local;
+    topo_info* inf = info;
+    if (!inf) {
+        local.resize(B);
+        inf = local.data();
+    }
+    const bool mixed = prec == TOPO_MIXED;
+    rc = g.dim == 2 ? hdm_solve_batch<2>(ctx, *mesh, g, tb, rho, mask, f, u, B, rtol, maxit, mixed, inf, s)
+                    : hdm_solve_batch<3>(ctx, *mesh, g, tb, rho, mask, f, u, B, rtol, maxit, mixed, inf, s);
+    if (rc) return rc;
+    int first_bad = -1;
+    for (int b = 0; b < B; ++b) {
+        if (compliance) compliance[b] = inf[b].compliance_corr;
+        if (inf[b].status != TOPO_OK && first_bad < 0) first_bad = b;
+    }
+    if (first_bad < 0) return TOPO_OK;
+    const int code = inf[first_bad].status;
+    if (B > 1) {
+        const std::string msg = ctx->err;
+        set_error(ctx, code, "field %d: %s", first_bad, msg.c_str());
+    }
+    return code;
 }
 
-int topo_hdm_gradient(topo_ctx* ctx, const topo_mesh* mesh, const double* rho, const double* u,
-                      double* dc, void* stream) {
+int topo_hdm_solve(topo_ctx* ctx, const topo_mesh* mesh, const double* rho, const uint8_t* mask,
+                   const double* f, double* u, double rtol, int32_t maxit, int32_t prec,
+                   double* compliance, topo_info* info, void* stream) {
+    return topo_hdm_solve_batch(ctx, mesh, rho, mask, f, u, 1, rtol, maxit, prec, compliance, info, stream);
+}
+
+int topo_hdm_gradient_batch(topo_ctx* ctx, const topo_mesh* mesh, const double* rho, const double* u,
+                            int32_t B, double* dc, void* stream) {
     if (!ctx) return TOPO_EINVAL;
     int rc = validate_mesh(ctx, mesh);
     if (rc) return rc;
     if (!rho || !u || !dc) return set_error(ctx, TOPO_EINVAL, "null pointer argument");
+    if (B < 1) return set_error(ctx, TOPO_EINVAL, "B must be >= 1");
     TOPO_HIP(hipSetDevice(ctx->device));
     const Grid g = make_grid(*mesh);
     const ElemTables* tb = get_tables(ctx, *mesh);
     if (!tb) return set_error(ctx, TOPO_EDEVICE, "element table upload failed");
-    return gradient_launch(ctx, g, *mesh, tb, rho, u, 1, dc, (hipStream_t)stream);
+    return gradient_launch(ctx, g, *mesh, tb, rho, u, B, dc, (hipStream_t)stream);
+}
+
+int topo_hdm_gradient(topo_ctx* ctx, const topo_mesh* mesh, const double* rho, const double* u,
+                      double* dc, void* stream) {
+    return topo_hdm_gradient_batch(ctx, mesh, rho, u, 1, dc, stream);
 }
 
 }  // extern "C"
@@ -1733,15 +1774,12 @@ int gradient_launch(Ctx* ctx, const Grid& g, const topo_mesh& m, const ElemTable
     return TOPO_OK;
 }
 
-}  // namespace topo
-
 // Entry points shared with the ROM translation unit.
-namespace topo {
-
 int residual_fp64(Ctx* ctx, const Grid& g, const ElemTables* tb, const double* alpha64,
                   const uint8_t* mask, const double* u, const double* f, double* r, int B,
                   double* part, double* out, hipStream_t s) {
-    return residual_launch(ctx, g, g.dim == 2 ? tb->K64 : tb->M64, alpha64, mask, u, f, r, B, part, out, s);
+    return residual_launch(ctx, g, g.dim == 2 ? tb->K64 : tb->M64, alpha64, mask, u, f, r, B, part, out,
+                           nullptr, s);
 }
 
 int alpha_tables(Ctx* ctx, const Grid& g, const topo_mesh& m, const double* rho, int B,

@@ -78,6 +78,7 @@ extern const char* const kKernelNames[KID_COUNT];
 struct Timing {
     int every = 0;
     long long seen[KID_COUNT] = {};
+    long long launched[KID_COUNT] = {};  // launches issued (graph replays included)
     long long samples[KID_COUNT] = {};
     double total_ms[KID_COUNT] = {};
     struct Rec { hipEvent_t a, b; int kid; };
@@ -148,7 +149,7 @@ struct Arena {
 };
 
 // Device workspace (bytes, before the arena's growth margin) of each entry point.
-size_t ws_hdm_solve(const Grid& g, bool mixed);
+size_t ws_hdm_solve(const Grid& g, bool mixed, int B);
 size_t ws_rom_build(const Grid& g, int k, int B, bool f64, int cu);
 size_t ws_rom_solve(int k, int B);
 size_t ws_rom_estimate(const Grid& g, int k, int B, int max_refine);
@@ -239,6 +240,20 @@ constexpr int kXcds = 8;
 __device__ __forceinline__ int xcd_block(int b, int nb) {
     const int x = b % kXcds, q = nb / kXcds, r = nb % kXcds;
     return x * q + (x < r ? x : r) + b / kXcds;
+}
+
+// Field and block of a batched stencil launch (grid nb x B, one field per blockIdx.y):
+// the linear workgroup id is mapped XCD-aware over the whole batch, so that every XCD
+// takes one contiguous range of (field, block) pairs and the halo a block re-reads
+// stays in its own L2.  With B = 1 this is xcd_block(blockIdx.x, nb).
+struct FieldBlock {
+    int field, blk;
+};
+__device__ __forceinline__ FieldBlock field_block() {
+    const int gx = gridDim.x;
+    const int l = xcd_block(blockIdx.x + gx * blockIdx.y, gx * gridDim.y);
+    const int f = l / gx;
+    return {f, l - f * gx};
 }
 
 // 3D element-centric march: a block owns 31 x 7 node columns (a 32 x 8 tile of element

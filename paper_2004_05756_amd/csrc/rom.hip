@@ -333,76 +333,102 @@ __device__ __forceinline__ void stage_rows(const TP* __restrict__ phi, int ldphi
     }
 }
 
-template <typename TP>
+// Fields of one projection launch share every staged basis tile: a block reads its rows
+// of Phi once for a group of up to G fields (grid.y covers further groups); G = 16
+// unless the per-thread accumulators or the coefficients in LDS would not fit.
+
+// out[b][j] partials = sum_i Phi[i][j] v[b][i] over the chunk's free rows (float64).
+// Thread t accumulates columns t + 256 q (q < CQ) for the group's nf fields.
+template <typename TP, int CQ, int G>
 __global__ __launch_bounds__(256) void k_phit_v(long long nrows, const TP* __restrict__ phi, int k,
                                                 int ldphi, const uint8_t* __restrict__ mask,
-                                                const double* __restrict__ v, long long vstride,
+                                                const double* __restrict__ v, long long vstride, int B,
                                                 int rows_per_chunk, int rb,
                                                 double* __restrict__ partials) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int lds_ld = ldphi | 1;
     TP* tile = (TP*)smem;                                  // [rb][lds_ld]
-    double* sv = (double*)(smem + (((size_t)rb * lds_ld * sizeof(TP) + 15) & ~(size_t)15));  // [rb]
-    const int b = blockIdx.y;
+    double* sv = (double*)(smem + (((size_t)rb * lds_ld * sizeof(TP) + 15) & ~(size_t)15));  // [nf][rb]
+    const int b0 = blockIdx.y * G;
+    const int nf = min(G, B - b0);
     const long long r0 = (long long)blockIdx.x * rows_per_chunk;
     const long long r1 = min(r0 + rows_per_chunk, nrows);
-    const double* vb = v + (size_t)b * vstride;
-    double* dst = partials + ((size_t)b * gridDim.x + blockIdx.x) * k;
-    constexpr int CMAX = 4;  // columns per thread (k <= 1024)
-    double acc[CMAX] = {0.0, 0.0, 0.0, 0.0};
+    double acc[CQ][G];
+#pragma unroll
+    for (int q = 0; q < CQ; ++q)
+#pragma unroll
+        for (int f = 0; f < G; ++f) acc[q][f] = 0.0;
     for (long long t0 = r0; t0 < r1; t0 += rb) {
         const int nr = (int)min((long long)rb, r1 - t0);
         __syncthreads();
         stage_rows(phi, ldphi, t0, nr, lds_ld, tile);
-        for (int r = threadIdx.x; r < nr; r += blockDim.x) sv[r] = mask[t0 + r] ? 0.0 : vb[t0 + r];
+        for (int idx = threadIdx.x; idx < nf * rb; idx += blockDim.x) {
+            const int f = idx / rb, r = idx - f * rb;
+            sv[idx] = (r < nr && !mask[t0 + r]) ? v[(size_t)(b0 + f) * vstride + t0 + r] : 0.0;
+        }
         __syncthreads();
 #pragma unroll
-        for (int q = 0; q < CMAX; ++q) {
+        for (int q = 0; q < CQ; ++q) {
             const int j = threadIdx.x + q * blockDim.x;
             if (j < k) {
-                double s0 = 0.0, s1 = 0.0;
-                int r = 0;
-                for (; r + 1 < nr; r += 2) {
-                    s0 += (double)tile[r * lds_ld + j] * sv[r];
-                    s1 += (double)tile[(r + 1) * lds_ld + j] * sv[r + 1];
+                for (int r = 0; r < nr; ++r) {
+                    const double t = (double)tile[r * lds_ld + j];
+#pragma unroll
+                    for (int f = 0; f < G; ++f)
+                        if (f < nf) acc[q][f] += t * sv[f * rb + r];
                 }
-                if (r < nr) s0 += (double)tile[r * lds_ld + j] * sv[r];
-                acc[q] += s0 + s1;
             }
         }
     }
 #pragma unroll
-    for (int q = 0; q < CMAX; ++q) {
+    for (int q = 0; q < CQ; ++q) {
         const int j = threadIdx.x + q * blockDim.x;
-        if (j < k) dst[j] = acc[q];
+        if (j < k)
+#pragma unroll
+            for (int f = 0; f < G; ++f)
+                if (f < nf) partials[((size_t)(b0 + f) * gridDim.x + blockIdx.x) * k + j] = acc[q][f];
     }
 }
 
-// u[b][i] = Phi[i][:] . y[b][:] on free rows, 0 on Dirichlet rows (float64 accumulation).
-// A block handles a contiguous tile of rb rows (staged in LDS with coalesced loads);
-// 256 / rb threads share a row and combine their column sums with lane shuffles.
-template <typename TP>
+// u[b][i] = Phi[i][:] . y[b][:] on free rows, 0 on Dirichlet rows (float64 accumulation),
+// for the group's nf fields.  A block handles a contiguous tile of rb rows (staged in
+// LDS with coalesced loads, read once for all the group's fields); 256 / rb threads
+// share a row and combine their column sums with lane shuffles.
+template <typename TP, int G>
 __global__ __launch_bounds__(256) void k_phi_y(long long nrows, const TP* __restrict__ phi, int k,
                                                int ldphi, const uint8_t* __restrict__ mask,
-                                               const double* __restrict__ y, int rb,
+                                               const double* __restrict__ y, int B, int rb,
                                                double* __restrict__ u) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int lds_ld = ldphi | 1;
-    double* sy = (double*)smem;                 // [k]
-    TP* tile = (TP*)(sy + ((k + 1) & ~1));      // [rb][lds_ld]
-    const int b = blockIdx.y;
-    for (int j = threadIdx.x; j < k; j += blockDim.x) sy[j] = y[(size_t)b * k + j];
+    const int b0 = blockIdx.y * G;
+    const int nf = min(G, B - b0);
+    double* sy = (double*)smem;                           // [nf][k]
+    TP* tile = (TP*)(sy + (((size_t)G * k + 1) & ~(size_t)1));  // [rb][lds_ld]
+    for (int idx = threadIdx.x; idx < nf * k; idx += blockDim.x) sy[idx] = y[(size_t)b0 * k + idx];
     const long long r0 = (long long)blockIdx.x * rb;
     const int nr = (int)min((long long)rb, nrows - r0);
     stage_rows(phi, ldphi, r0, nr, lds_ld, tile);
     __syncthreads();
     const int tpr = blockDim.x / rb;            // threads per row (power of two <= 64)
     const int r = threadIdx.x / tpr, q = threadIdx.x - r * tpr;
-    double s = 0.0;
+    double s[G];
+#pragma unroll
+    for (int f = 0; f < G; ++f) s[f] = 0.0;
     if (r < nr)
-        for (int j = q; j < k; j += tpr) s += (double)tile[r * lds_ld + j] * sy[j];
-    for (int off = tpr >> 1; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-    if (q == 0 && r < nr) u[(size_t)b * nrows + r0 + r] = mask[r0 + r] ? 0.0 : s;
+        for (int j = q; j < k; j += tpr) {
+            const double t = (double)tile[r * lds_ld + j];
+#pragma unroll
+            for (int f = 0; f < G; ++f)
+                if (f < nf) s[f] += t * sy[f * k + j];
+        }
+#pragma unroll
+    for (int f = 0; f < G; ++f) {
+        if (f >= nf) break;
+        double x = s[f];
+        for (int off = tpr >> 1; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+        if (q == 0 && r < nr) u[(size_t)(b0 + f) * nrows + r0 + r] = mask[r0 + r] ? 0.0 : x;
+    }
 }
 
 // ----------------------------------------------------------------------------------
@@ -816,16 +842,33 @@ static int phit_v(Ctx* ctx, const Grid& g, const void* phi, int fp32, int k, int
     const int rpc = (int)((nrows + nchunks - 1) / nchunks + 3) & ~3;
     const size_t esz = fp32 ? 4 : 8;
     const int rb = tile_rows(ldphi, esz);
-    const size_t lds = tile_bytes(rb, ldphi, esz) + (size_t)rb * sizeof(double);
     if (k > 1024) return set_error(ctx, TOPO_EINVAL, "k > 1024 not supported by the projection kernel");
+    // columns per thread and fields per group: at most 32 float64 accumulators a thread
+    const int cq = (k + 255) / 256;
+    const int G = cq == 1 ? 16 : cq == 2 ? 8 : 4;
+    const size_t lds = tile_bytes(rb, ldphi, esz) + (size_t)G * rb * sizeof(double);
+    const dim3 grid(nchunks, (B + G - 1) / G);
     {
         TimedLaunch tl(ctx, KID_PHIT_V, s);
-        if (fp32)
-            hipLaunchKernelGGL((k_phit_v<float>), dim3(nchunks, B), dim3(256), lds, s, nrows,
-                               (const float*)phi, k, ldphi, mask, v, vstride, rpc, rb, partials);
-        else
-            hipLaunchKernelGGL((k_phit_v<double>), dim3(nchunks, B), dim3(256), lds, s, nrows,
-                               (const double*)phi, k, ldphi, mask, v, vstride, rpc, rb, partials);
+#define TOPO_PHIT_CASE(CQ, GG)                                                                          \
+    case CQ:                                                                                           \
+        if (fp32) {                                                                                    \
+            TOPO_HIP(hipFuncSetAttribute((const void*)k_phit_v<float, CQ, GG>,                         \
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));       \
+            hipLaunchKernelGGL((k_phit_v<float, CQ, GG>), grid, dim3(256), lds, s, nrows,              \
+                               (const float*)phi, k, ldphi, mask, v, vstride, B, rpc, rb, partials);  \
+        } else {                                                                                       \
+            TOPO_HIP(hipFuncSetAttribute((const void*)k_phit_v<double, CQ, GG>,                        \
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));       \
+            hipLaunchKernelGGL((k_phit_v<double, CQ, GG>), grid, dim3(256), lds, s, nrows,             \
+                               (const double*)phi, k, ldphi, mask, v, vstride, B, rpc, rb, partials); \
+        }                                                                                              \
+        break;
+        switch (cq) {
+            TOPO_PHIT_CASE(1, 16) TOPO_PHIT_CASE(2, 8) TOPO_PHIT_CASE(3, 4) TOPO_PHIT_CASE(4, 4)
+            default: return set_error(ctx, TOPO_EINVAL, "k > 1024 not supported by the projection kernel");
+        }
+#undef TOPO_PHIT_CASE
     }
     TOPO_CHECK_LAUNCH();
     launch_chunk_sum(k, nchunks, B, partials, ColsumOut{k, out}, s);
@@ -833,20 +876,34 @@ static int phit_v(Ctx* ctx, const Grid& g, const void* phi, int fp32, int k, int
     return TOPO_OK;
 }
 
-// u[b] = Phi y[b] on free rows (0 on Dirichlet rows), B fields.
 static int phi_y_launch(Ctx* ctx, const void* phi, int fp32, int k, int ldphi, const uint8_t* mask,
                         const double* y, long long N, int B, double* u, hipStream_t s) {
     const size_t esz = fp32 ? 4 : 8;
     const int rb = tile_rows(ldphi, esz);
-    const size_t lds = (size_t)((k + 1) & ~1) * sizeof(double) + tile_bytes(rb, ldphi, esz);
+    // the group's coefficients in LDS: at most 64 KB beside the 48 KB basis tile
+    const int G = k <= 512 ? 16 : 8;
+    const size_t lds = (((size_t)G * k + 1) & ~(size_t)1) * sizeof(double) + tile_bytes(rb, ldphi, esz);
+    const dim3 grid(grid_blocks(N, rb), (B + G - 1) / G);
     {
+        const void* kern = G == 16 ? (fp32 ? (const void*)k_phi_y<float, 16> : (const void*)k_phi_y<double, 16>)
+                                   : (fp32 ? (const void*)k_phi_y<float, 8> : (const void*)k_phi_y<double, 8>);
+        TOPO_HIP(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         TimedLaunch tl(ctx, KID_PHI_Y, s);
-        if (fp32)
-            hipLaunchKernelGGL((k_phi_y<float>), dim3(grid_blocks(N, rb), B), dim3(256), lds, s, N,
-                               (const float*)phi, k, ldphi, mask, y, rb, u);
-        else
-            hipLaunchKernelGGL((k_phi_y<double>), dim3(grid_blocks(N, rb), B), dim3(256), lds, s, N,
-                               (const double*)phi, k, ldphi, mask, y, rb, u);
+        if (G == 16) {
+            if (fp32)
+                hipLaunchKernelGGL((k_phi_y<float, 16>), grid, dim3(256), lds, s, N, (const float*)phi, k, ldphi,
+                                   mask, y, B, rb, u);
+            else
+                hipLaunchKernelGGL((k_phi_y<double, 16>), grid, dim3(256), lds, s, N, (const double*)phi, k,
+                                   ldphi, mask, y, B, rb, u);
+        } else {
+            if (fp32)
+                hipLaunchKernelGGL((k_phi_y<float, 8>), grid, dim3(256), lds, s, N, (const float*)phi, k, ldphi,
+                                   mask, y, B, rb, u);
+            else
+                hipLaunchKernelGGL((k_phi_y<double, 8>), grid, dim3(256), lds, s, N, (const double*)phi, k,
+                                   ldphi, mask, y, B, rb, u);
+        }
     }
     TOPO_CHECK_LAUNCH();
     return TOPO_OK;

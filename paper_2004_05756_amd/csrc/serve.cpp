@@ -116,7 +116,7 @@ void size_job(topo_server* S, Job& j, int B) {
     const Grid& g = mr.g;
     const bool mixed = j.prec == TOPO_MIXED;
     if (j.kind == TOPO_REQ_HDM) {
-        j.ws_need = ws_hdm_solve(g, mixed);
+        j.ws_need = ws_hdm_solve(g, mixed, 1);
         j.staging_need = align_up((size_t)g.n_elems * 8) + align_up((size_t)g.n_dofs * 8);
     } else {
         const int kb = j.kb;

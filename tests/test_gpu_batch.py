@@ -1,0 +1,147 @@
+"""Batched HDM solves (topo_hdm_solve_batch): B density fields per kernel launch with
+per-field stopping.  Every field's result must be bitwise the same as its solve alone
+(B = 1) and as in any other batch, since every decision and every reduction is per
+field; and each field must meet the oracle at the parity bars (FP64 1e-10, mixed
+1e-8 compliance / 1e-6 gradient)."""
+import os
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from gpu_util import ctx, dev, host, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _fields(p, B, seed):
+    """B seeded densities of mixed character: smoothed fields, a jittered one and a
+    uniform one (different iteration counts and segment patterns per field)."""
+    m = p.mesh
+    out = []
+    for b in range(B):
+        if b % 3 == 1:
+            out.append(W.rho_jitter(m, seed + b))
+        elif b % 3 == 2:
+            out.append(np.full(m.n_elems, 0.3 + 0.1 * b))
+        else:
+            out.append(W.rho_smoothed(m, seed + b))
+    return np.stack(out)
+
+
+def _batch(p, rhos, prec, rtol):
+    torch = torch_cuda()
+    from paper_2004_05756_amd import FP64, MIXED
+    pr = FP64 if prec == "fp64" else MIXED
+    u, infos = ctx().hdm_solve_batch(p.mesh, dev(rhos, torch.float64), dev(p.mask, torch.uint8),
+                                     dev(p.f, torch.float64), rtol=rtol, prec=pr)
+    torch.cuda.synchronize()
+    return host(u), infos
+
+
+CASES = [W.mbb2d(60, 20), W.cantilever2d(45, 15), W.cantilever3d(12, 6, 6), W.bridge3d(10, 5, 8)]
+
+
+@pytest.mark.parametrize("p", CASES, ids=lambda p: p.name)
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_batch_is_bitwise_the_single_field_solve(p, prec):
+    B = 5
+    rhos = _fields(p, B, 4100)
+    print(f"batch {p.name} {prec} B={B}", flush=True)
+    ub, ib = _batch(p, rhos, prec, 1e-10)
+    # each field alone, and the batch in reverse order
+    for b in range(B):
+        ua, ia = _batch(p, rhos[b:b + 1], prec, 1e-10)
+        assert np.array_equal(ua[0], ub[b]), (b, np.abs(ua[0] - ub[b]).max())
+        for key in ("iters", "refinements", "rel_resid", "compliance_raw", "compliance_corr", "status"):
+            assert ia[0][key] == ib[b][key], (b, key, ia[0][key], ib[b][key])
+    ur, ir = _batch(p, rhos[::-1].copy(), prec, 1e-10)
+    assert np.array_equal(ur[::-1], ub)
+    assert [i["iters"] for i in ir[::-1]] == [i["iters"] for i in ib]
+    # the fields really differ in their iteration counts (per-field stopping exercised)
+    assert len({i["iters"] for i in ib}) > 1
+
+
+@pytest.mark.parametrize("p", CASES, ids=lambda p: p.name)
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_batch_fields_match_oracle(p, prec):
+    torch = torch_cuda()
+    B = 4
+    rhos = _fields(p, B, 4100)
+    rtol = 1e-10
+    # inputs for which a float64 solve can reach rtol: its attainable true residual is
+    # about eps ||K|| ||u|| / ||f|| (near-mechanism densities push it above 1e-10)
+    for b in range(B):
+        K = O.assemble(p.mesh, rhos[b])
+        free = p.mask == 0
+        uo = O.solve_direct(p.mesh, rhos[b], p.f, p.mask)
+        bound = np.abs(K[free][:, free]).sum(axis=0).max() * np.linalg.norm(uo) / np.linalg.norm(p.f)
+        assert np.finfo(float).eps * bound < rtol, (b, bound)
+    ub, ib = _batch(p, rhos, prec, rtol)
+    tol_c = 1e-10 if prec == "fp64" else 1e-8
+    tol_g = 1e-8 if prec == "fp64" else 1e-6
+    dc = host(ctx().hdm_gradient_batch(p.mesh, dev(rhos, torch.float64), dev(ub, torch.float64)))
+    for b in range(B):
+        assert ib[b]["status"] == 0 and ib[b]["rel_resid"] <= rtol
+        uo = O.solve_direct(p.mesh, rhos[b], p.f, p.mask)
+        co = O.compliance(p.f, uo)
+        K = O.assemble(p.mesh, rhos[b])
+        res = np.linalg.norm((p.f - K @ ub[b])[p.mask == 0]) / np.linalg.norm(p.f)
+        assert res <= rtol * 1.01
+        assert abs(ib[b]["compliance_corr"] / co - 1) <= tol_c
+        go = O.sensitivity(p.mesh, rhos[b], uo)
+        assert np.abs(dc[b] - go).max() <= tol_g * np.abs(go).max()
+        # the batched gradient equals the single-field one
+        d1 = host(ctx().hdm_gradient(p.mesh, dev(rhos[b], torch.float64), dev(ub[b], torch.float64)))
+        assert np.array_equal(d1, dc[b])
+
+
+def test_batch_collapsed_partials_path():
+    """A 2D mesh whose node-linear launches exceed 2048 blocks (partials summed by the
+    collapse kernel, per field): batch of 2 against each alone, both recursions."""
+    p = W.cantilever2d(1100, 960)
+    rhos = np.stack([W.rho_jitter(p.mesh, 4301), np.full(p.mesh.n_elems, 0.7)])
+    for prec, rtol in (("mixed", 1e-6), ("fp64", 1e-6)):
+        print(f"collapsed {prec}", flush=True)
+        ub, ib = _batch(p, rhos, prec, rtol)
+        for b in range(2):
+            ua, ia = _batch(p, rhos[b:b + 1], prec, rtol)
+            assert np.array_equal(ua[0], ub[b])
+            assert ia[0]["iters"] == ib[b]["iters"]
+            assert ib[b]["rel_resid"] <= rtol
+
+
+def test_batch_without_graphs_is_bitwise_the_graph_path():
+    """Direct launches (graphs off) take exactly the steps of the graph replays,
+    including the one-reduction recursion's refresh of s every 16 iterations."""
+    torch_cuda()
+    code = r"""
+import sys, numpy as np, torch
+sys.path.insert(0, {root!r})
+import workloads as W
+from paper_2004_05756_amd import binding, FP64, MIXED
+p = W.mbb2d(60, 20)
+rhos = np.stack([W.rho_smoothed(p.mesh, 4400 + b) for b in range(3)])
+c = binding.Context(0)
+d = torch.device("cuda", 0)
+out = []
+for pr in (FP64, MIXED):
+    u, inf = c.hdm_solve_batch(p.mesh, torch.as_tensor(rhos).to(d), torch.as_tensor(p.mask).to(d),
+                               torch.as_tensor(p.f).to(d), rtol=1e-10, prec=pr, check=False)
+    out.append(u.cpu().numpy())
+np.save(sys.argv[1], np.stack(out))
+""".format(root=ROOT)
+    outs = []
+    for flag in ("0", "1"):
+        path = os.path.join(ROOT, "gpurun_out", f"graph_{flag}.npy") if os.path.isdir(
+            os.path.join(ROOT, "gpurun_out")) else f"/tmp/graph_{flag}_{os.getpid()}.npy"
+        env = dict(os.environ, TOPO_NO_GRAPH=flag)
+        r = subprocess.run([sys.executable, "-c", code, path], env=env, timeout=300, capture_output=True, text=True)
+        assert r.returncode == 0, r.stderr[-2000:]
+        outs.append(np.load(path))
+    assert np.array_equal(outs[0], outs[1])
