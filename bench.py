@@ -1,15 +1,21 @@
 #!/usr/bin/env python3
 """Benchmark of the ROM-accelerated SIMP compliance hot path on one MI355X.
 
-One step = one pass of the whole hot path over one synthetic design:
-  HDM state solve (Jacobi-PCG, float32 inner / float64 refinement, rtol 1e-10)
-  -> compliance -> element sensitivity -> ROM build (K_hat by per-element MFMA
-  contraction, f_hat) -> reduced float64 Cholesky solve -> residual error indicator
-  with reduced refinement -> ROM sensitivity dJ_k/drho at the reduced state.
+One step = one pass of the whole hot path over one batch of B density fields on one
+mesh (default: the 192x96x96 H8 bridge, B = 16, k = 200, mixed precision):
+  batched HDM state solve (Jacobi-PCG, float32 inner / float64 refinement, rtol 1e-8)
+  -> compliances -> element sensitivities -> ROM build (K_hat of the B fields by the
+  per-element MFMA contraction, f_hat) -> reduced float64 Cholesky solves -> residual
+  error indicator with one reduced refinement step and the ROM sensitivity fused in.
 Headline value: PCG DOF-iterations per second over the whole timed step
-(N_u x inner PCG iterations / wall time, ROM work included in the time).
+(sum over fields of N_u x inner PCG iterations / wall time, ROM work included).
 
-    python bench.py [--steps K] [--warmup W] [--workload cantilever2d_600x200]
+The B fields are trust-region candidates around a centre design (seeded smoothed
+perturbations of a seeded smoothed field); the basis is the one the method builds at
+that centre: GramSchmidt([POD of 8 earlier HDM snapshots, u*(centre)]) on the device,
+completed to k columns with smooth cosine fields.
+
+    python bench.py [--steps K] [--warmup W] [--workload bridge3d_192x96x96]
 """
 from __future__ import annotations
 
@@ -26,39 +32,48 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 HBM_PEAK_GBS = 8000.0
 FP32_MFMA_PEAK_TFS = 157.3
 FP64_MFMA_PEAK_TFS = 78.6
+SNAPSHOTS = 8  # earlier trust-region centres in the basis window
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="cantilever2d_600x200")
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="bridge3d_192x96x96")
+    ap.add_argument("--fields", type=int, default=None, help="density fields per step (default: the workload's)")
     ap.add_argument("--prec", choices=["mixed", "fp64"], default="mixed")
     ap.add_argument("--rtol", type=float, default=None)
     ap.add_argument("--k", type=int, default=None)
     ap.add_argument("--max-refine", type=int, default=1)
-    ap.add_argument("--rom-evals", type=int, default=200, help="ROM evaluations per precision for evals/s and latency")
+    ap.add_argument("--rom-evals", type=int, default=5, help="batched ROM evaluations per precision")
     ap.add_argument("--timing-every", type=int, default=4, help="sample one launch in N of each hot kernel")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extra", action="store_true", help="skip the ROM evals/s and FP64 comparison legs")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the precision, 2D batch, per-config, basis, filter and trust-region legs")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-stream leg")
     ap.add_argument("--serving-requests", type=int, default=512)
     ap.add_argument("--serving-workers", type=int, default=4)
-    ap.add_argument("--no-bridge", action="store_true",
-                    help="skip the 192x96x96 leg (16-field batched apply, one HDM solve per precision)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes (5 times), the "
                          "reference kernel that scales the HBM byte counters")
+    ap.add_argument("--profile-step", action="store_true",
+                    help="only set up and run warmup + steps of the headline step (for profilers)")
     return ap.parse_args()
 
 
+# ----------------------------------------------------------------------------------
+# Algorithmic costs
+# ----------------------------------------------------------------------------------
+
 def pcg_bytes(n_dofs, n_nodes, n_elems, word):
-    """Algorithmic HBM bytes of one launch of each PCG kernel (each array once).
-    step  (2D, one kernel per iteration): read r, w, s (stencil), p, mask, alpha,
-          1/sum(alpha) per node; read/write x (float64); write r, w, s, p
-    apply (3D): read z, p_old (stencil), alpha, mask; write p_new, q
-    update (3D): read/write x (float64), r; write z; read p, q, 1/sum(alpha) per node"""
+    """Algorithmic HBM bytes of one field's share of one launch of each PCG kernel
+    (each array once).
+    step  (2D float64, one kernel per iteration): read r, w, s (stencil), p, mask,
+          alpha, 1/sum(alpha) per node; read/write x (float64); write r, w, s, p
+    apply (two-kernel form): read z, p_old (stencil), alpha, mask; write p_new, q
+    update (two-kernel form): read/write x (float64), r; write z; read p, q,
+          1/sum(alpha) per node"""
     return {
         "pcg_step": n_dofs * (8 * word + 17) + n_nodes * word + n_elems * word,
         "pcg_apply": n_dofs * (4 * word + 1) + n_elems * word,
@@ -69,13 +84,20 @@ def pcg_bytes(n_dofs, n_nodes, n_elems, word):
 def pcg_kernel_name(kind, dim, word):
     """Symbol (as rocprofv3 prints it) of a PCG kernel."""
     t = "float" if word == 4 else "double"
-    return {"pcg_step": f"k_cg1_step2<{t},0>", "pcg_apply": f"k_pcg_apply{dim}<{t}>",
+    return {"pcg_step": f"k_cg1_step2<{t}>", "pcg_apply": f"k_pcg_apply{dim}<{t}>",
             "pcg_update": f"k_pcg_update<{dim},{t}>"}[kind]
+
+
+def rom_contract_flops(n_elems, k, ne):
+    """Algorithmic flops of the per-element K_hat contraction for one density field
+    (operation count of the paper's cost analysis, Sec. 3.4)."""
+    return n_elems * (2 * k * ne * ne + 2 * k * k * ne)
 
 
 # Device sources of the PCG kernels: measured HBM traffic recorded under profiles/ is
 # used only while these files are unchanged since the counters were taken.
 KERNEL_SOURCES = ("paper_2004_05756_amd/csrc/hdm.hip", "paper_2004_05756_amd/csrc/stencil.hpp",
+                  "paper_2004_05756_amd/csrc/march3.hpp", "paper_2004_05756_amd/csrc/elemfac.hpp",
                   "paper_2004_05756_amd/csrc/internal.hpp")
 
 
@@ -104,56 +126,161 @@ def measured_traffic(workload, kernel):
     return None
 
 
-def rom_contract_flops(n_elems, k, ne):
-    """Algorithmic flops of the per-element K_hat contraction for one density field
-    (operation count of the paper's cost analysis, Sec. 3.4)."""
-    return n_elems * (2 * k * ne * ne + 2 * k * k * ne)
-
-
-def cpu_baseline(cfg, phi_np, gpu_iters_per_step, n_dofs, min_seconds=10.0, max_steps=8):
-    """The oracle as it stands, full steps on the same workload (one density field of the
-    workload's seeded series per step), 1 thread, until at least min_seconds of CPU work
-    (at most max_steps steps)."""
-    import oracle as O
-    from threadpoolctl import threadpool_limits
-    p = cfg.problem
-    steps, dt = 0, 0.0
-    with threadpool_limits(1):
-        while steps < max_steps and (steps == 0 or dt < min_seconds):
-            rho = cfg.rho(steps)
-            t0 = time.perf_counter()
-            u = O.solve_direct(p.mesh, rho, p.f, p.mask)
-            O.compliance(p.f, u)
-            O.sensitivity(p.mesh, rho, u)
-            O.rom_eval(p.mesh, rho, phi_np, p.mask, p.f)
-            dt += time.perf_counter() - t0
-            steps += 1
-    return {
-        "value": n_dofs * gpu_iters_per_step * steps / dt,
-        "unit": "DOF-iter/s",
-        "cores": 1,
-        "kind": "oracle",
-        "sample": (f"{steps} full oracle step{'s' if steps > 1 else ''} on {cfg.name} (sparse direct solve, compliance, "
-                   f"sensitivity, assembled-matrix ROM eval k={phi_np.shape[1]}; density fields 0..{steps - 1} "
-                   f"of the workload's series), single thread; expressed as N_u x GPU PCG iterations per "
-                   f"step / oracle time per step"),
-        "seconds": dt,
-        "steps": steps,
-    }
-
-
 def _pct(xs, q):
     xs = sorted(xs)
     return xs[min(len(xs) - 1, int(q * len(xs)))] if xs else None
 
 
+def _ms(x):
+    return None if x is None else 1e3 * x
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+# ----------------------------------------------------------------------------------
+# Inputs of the headline workload
+# ----------------------------------------------------------------------------------
+
+def headline_inputs(W, cfg, B):
+    """The centre design, the B trust-region candidates around it (the step's fields)
+    and SNAPSHOTS earlier centres (the basis window)."""
+    m = cfg.problem.mesh
+    centre = cfg.rho(0)
+    fields = W.trust_region_fields(m, centre, B, cfg.rho_seed0 + 100, step=0.1)
+    snaps = W.trust_region_fields(m, centre, SNAPSHOTS, cfg.rho_seed0 + 200, step=0.3)
+    return centre, fields, snaps
+
+
+def build_basis(torch, W, binding, ctx, cfg, centre, snaps, k, rtol, dev):
+    """GramSchmidt([POD(HDM snapshots at the earlier centres), u*(centre)]) on the device
+    (the basis of the method at a trust-region centre), then smooth cosine fields up to
+    k columns; float32 [N_u][k]."""
+    from paper_2004_05756_amd.binding import MIXED
+    p = cfg.problem
+    m = p.mesh
+    mask = torch.as_tensor(p.mask).to(dev)
+    f = torch.as_tensor(p.f).to(dev)
+    rhos = torch.as_tensor(np.vstack([centre[None], snaps])).to(dev)
+    u, infos = ctx.hdm_solve_batch(m, rhos, mask, f, rtol=rtol, prec=MIXED, check=False)
+    win = binding.SnapshotWindow(ctx, m.n_dofs, SNAPSHOTS)
+    for j in range(SNAPSHOTS):
+        win.push(u[1 + j])
+    phi = torch.empty((m.n_dofs, k), dtype=torch.float32, device=dev)
+    ncols, npod = win.basis(u[0], min(SNAPSHOTS, k - 1), phi)
+    rest = k - ncols
+    if rest > 0:
+        phi[:, ncols:] = torch.as_tensor(W.cosine_basis(m, p.mask, rest, cfg.basis_seed, np.float32)).to(dev)
+    torch.cuda.synchronize()
+    del u, win
+    return phi, {"snapshots": SNAPSHOTS, "pod_columns": npod, "snapshot_columns": ncols,
+                 "cosine_columns": max(rest, 0), "snapshot_iters": [i["iters"] for i in infos]}
+
+
+# ----------------------------------------------------------------------------------
+# Side legs
+# ----------------------------------------------------------------------------------
+
+def batch_scaling_leg(torch, W, binding, FP64, MIXED, counts=(1, 4, 16)):
+    """The 600x200 cantilever solved for B = 1 / 4 / 16 fields per launch in both
+    precisions: wall time, PCG iterations, DOF-iter/s and the HBM fraction of the PCG
+    kernels (algorithmic bytes of the active fields over the sampled launch times)."""
+    cfg = W.config("cantilever2d_600x200")
+    p, m = cfg.problem, cfg.problem.mesh
+    dev = torch.device("cuda", 0)
+    mask = torch.as_tensor(p.mask).to(dev)
+    f = torch.as_tensor(p.f).to(dev)
+    allr = torch.as_tensor(np.stack([cfg.rho(i) for i in range(max(counts))])).to(dev)
+    ctx = binding.Context(0)
+    out = {"workload": cfg.name, "n_dofs": m.n_dofs, "rtol": cfg.rtol}
+    for name, pr in (("mixed", MIXED), ("fp64", FP64)):
+        w = 4 if pr == MIXED else 8
+        kinds = ["pcg_apply", "pcg_update"] if pr == MIXED else ["pcg_step"]
+        pb = pcg_bytes(m.n_dofs, m.n_nodes, m.n_elems, w)
+        res = {}
+        for B in counts:
+            R = allr[:B].contiguous()
+            ctx.hdm_solve_batch(m, R, mask, f, rtol=cfg.rtol, prec=pr, check=False)  # warm
+            for kd in kinds:
+                ctx.kernel_time(kd, reset=True)
+            ctx.set_timing(4)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, infos = ctx.hdm_solve_batch(m, R, mask, f, rtol=cfg.rtol, prec=pr, check=False)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            ctx.set_timing(0)
+            its = [i["iters"] for i in infos]
+            rec = {"ms": 1e3 * dt, "iters": its, "dof_iter_per_s": m.n_dofs * sum(its) / dt,
+                   "solves_per_s": B / dt}
+            for kd in kinds:
+                n, ms, nl = ctx.kernel_time(kd, reset=True, launches=True)
+                if n and nl:
+                    avg = 1e-3 * ms / n
+                    nbytes = pb[kd] * sum(its) / nl  # the active fields of an average launch
+                    rec[kd] = {"avg_us": 1e6 * avg, "launches": nl, "GB_s": nbytes / avg / 1e9,
+                               "hbm_frac": nbytes / avg / 1e9 / HBM_PEAK_GBS}
+            res[f"B{B}"] = rec
+        out[name] = res
+    ctx.close()
+    return out
+
+
+def config_leg(torch, W, binding, FP64, MIXED, name, rom_evals=20):
+    """One field of a named workload: HDM time to solution in both precisions, and ROM
+    evaluations (build + reduced solve + estimate) per second with p50 / p99 in both
+    precisions (mixed with one reduced refinement step)."""
+    cfg = W.config(name)
+    p, m = cfg.problem, cfg.problem.mesh
+    dev = torch.device("cuda", 0)
+    rho = torch.as_tensor(cfg.rho(0)).to(dev)
+    mask = torch.as_tensor(p.mask).to(dev)
+    f = torch.as_tensor(p.f).to(dev)
+    phi = torch.as_tensor(W.cosine_basis(m, p.mask, cfg.k, cfg.basis_seed, np.float32)).to(dev)
+    ctx = binding.Context(0)
+    out = {"n_dofs": m.n_dofs, "k": cfg.k, "rtol": cfg.rtol}
+    for pname, pr in (("mixed", MIXED), ("fp64", FP64)):
+        ctx.hdm_solve(m, rho, mask, f, rtol=cfg.rtol, prec=pr, check=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, inf = ctx.hdm_solve(m, rho, mask, f, rtol=cfg.rtol, prec=pr, check=False)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        rec = {"hdm_ms": 1e3 * dt, "iters": inf["iters"], "dof_iter_per_s": m.n_dofs * inf["iters"] / dt,
+               "rel_resid": inf["rel_resid"], "fp64_fallback": inf["fp64_fallback"]}
+        R1 = rho.view(1, -1)
+        lat = []
+        for i in range(rom_evals + 2):
+            t0 = time.perf_counter()
+            Kh, fh = ctx.rom_build(m, phi, cfg.k, mask, f, R1, prec=pr)
+            y, _ = ctx.rom_solve(Kh, fh)
+            ctx.rom_estimate(m, phi, cfg.k, mask, f, R1, Kh, y, max_refine=1 if pr == MIXED else 0)
+            torch.cuda.synchronize()
+            if i >= 2:
+                lat.append(time.perf_counter() - t0)
+        rec.update({"rom_evals_per_s": len(lat) / sum(lat), "rom_p50_ms": _ms(_pct(lat, 0.5)),
+                    "rom_p99_ms": _ms(_pct(lat, 0.99))})
+        out[pname] = rec
+    out["faster_hdm"] = min(("mixed", "fp64"), key=lambda q: out[q]["hdm_ms"])
+    ctx.close()
+    return out
+
+
 def serving_leg(args, torch, W, binding, FP64, MIXED):
     """The serving workload: the seeded stream of ROM / HDM requests over four meshes,
     (a) plain FP64 one request at a time through the context, (b) the continuous-
-    batching server in mixed precision with every request submitted at once
-    (saturation throughput), (c) the same server with Poisson arrivals at 0.7x the
-    FP64 sequential rate (latency under load).  Densities and bases are resident on
-    the device for (a); the server receives host densities (copied at submit)."""
+    batching server in FP64 with every request submitted at once, (c) the same server
+    in mixed precision, and (d) the mixed server with Poisson arrivals at 0.7x the FP64
+    sequential rate (latency under load).  Densities and bases are resident on the
+    device for (a); the server receives host densities (copied at submit)."""
     dev = torch.device("cuda", 0)
     cfgs = [W.config(nm) for nm in W.SERVING_MESHES]
     kmax = 128
@@ -197,80 +324,92 @@ def serving_leg(args, torch, W, binding, FP64, MIXED):
     fp64_rate = len(reqs) / sum(lat_a)
     ctx.close()
 
-    # (b), (c) the server in mixed precision
-    srv = binding.Server(0, budget_bytes=32 << 30, max_batch=16, workers=args.serving_workers)
-    ids = []
-    for c, phi in zip(cfgs, phis):
-        p = c.problem
-        mid = srv.register_mesh(p.mesh, p.mask, p.f)
-        ids.append((mid, srv.register_basis(mid, phi)))
+    def make_server():
+        srv = binding.Server(0, budget_bytes=32 << 30, max_batch=16, workers=args.serving_workers)
+        ids = []
+        for c, phi in zip(cfgs, phis):
+            p = c.problem
+            mid = srv.register_mesh(p.mesh, p.mask, p.f)
+            ids.append((mid, srv.register_basis(mid, phi)))
+        return srv, ids
 
-    def submit(q):
+    def submit(srv, ids, q, prec):
         c = cfgs[q.mesh]
         mid, bid = ids[q.mesh]
         rho = pool[q.mesh][q.rho_id]
         if q.kind == "hdm":
-            return srv.submit_hdm(mid, rho, rtol=c.rtol, prec=MIXED)
-        return srv.submit_rom(mid, bid, q.k, rho, prec=MIXED, max_refine=1)
+            return srv.submit_hdm(mid, rho, rtol=c.rtol, prec=prec)
+        return srv.submit_rom(mid, bid, q.k, rho, prec=prec, max_refine=1 if prec == MIXED else 0)
 
-    warm = []
-    seen = set()
-    for q in reqs:
-        if (q.mesh, q.kind) not in seen:
-            seen.add((q.mesh, q.kind))
-            warm.append(submit(q))
-    for t in warm:
-        srv.wait(t)
-    t0 = time.perf_counter()
-    res_b = [srv.wait(t) for t in [submit(q) for q in reqs]]
-    sat_s = time.perf_counter() - t0
-    arr = W.poisson_arrivals(len(reqs), 0.7 * fp64_rate)
-    tickets = []
-    t0 = time.perf_counter()
-    for q, ta in zip(reqs, arr):
-        dt = t0 + ta - time.perf_counter()
-        if dt > 0:
-            time.sleep(dt)
-        tickets.append(submit(q))
-    res_c = [srv.wait(t) for t in tickets]
-    st = srv.stats()
-    srv.close()
+    def saturated(prec):
+        srv, ids = make_server()
+        warm, seen2 = [], set()
+        for q in reqs:
+            if (q.mesh, q.kind) not in seen2:
+                seen2.add((q.mesh, q.kind))
+                warm.append(submit(srv, ids, q, prec))
+        for t in warm:
+            srv.wait(t)
+        t0 = time.perf_counter()
+        res = [srv.wait(t) for t in [submit(srv, ids, q, prec) for q in reqs]]
+        dt = time.perf_counter() - t0
+        return srv, ids, res, dt
+
+    def job_busy(res):
+        """Device-side service time of the jobs (a fused ROM batch is one job: its
+        requests share worker and start time), summed per kind."""
+        jobs = {}
+        for r, q in zip(res, reqs):
+            key = (r["worker"], r["t_start"], q.kind)
+            jobs[key] = max(jobs.get(key, 0.0), r["t_done"] - r["t_start"])
+        return {kd: sum(v for (_, _, k2), v in jobs.items() if k2 == kd) for kd in ("hdm", "rom")}, len(jobs)
+
+    def rel_diff(res, kind):
+        d = [abs(r["J"] / ja - 1.0) for r, ja, q in zip(res, J_a, reqs) if q.kind == kind and ja != 0]
+        return max(d) if d else None
 
     def lat(res, kind=None):
         return [r["t_done"] - r["t_submit"] for r, q in zip(res, reqs) if kind in (None, q.kind)]
 
-    def rel_diff(kind):
-        d = [abs(r["J"] / ja - 1.0) for r, ja, q in zip(res_b, J_a, reqs) if q.kind == kind and ja != 0]
-        return max(d) if d else None
-
-    failed = sum(1 for r in res_b + res_c if r["status"] != 0)
-    # device-side overlap of the saturated run: summed job service time over makespan
-    busy = {kd: sum(r["t_done"] - r["t_start"] for r, q in zip(res_b, reqs) if q.kind == kd)
-            for kd in ("hdm", "rom")}
-    fp64_busy = {kd: sum(x for x, q in zip(lat_a, reqs) if q.kind == kd) for kd in ("hdm", "rom")}
-    ms = lambda x: None if x is None else 1e3 * x  # noqa: E731
-    return {
-        "requests": len(reqs),
-        "mix": {"meshes": list(W.SERVING_MESHES), "rom_frac": 0.8, "k": [8, kmax],
-                "hdm": sum(q.kind == "hdm" for q in reqs)},
-        "fp64_sequential": {"evals_per_s": fp64_rate, "p50_ms": ms(_pct(lat_a, 0.5)),
-                            "p99_ms": ms(_pct(lat_a, 0.99)), "service_s": fp64_busy},
-        "served_mixed_saturated": {"evals_per_s": len(reqs) / sat_s, "makespan_s": sat_s,
-                                   "p50_ms": ms(_pct(lat(res_b), 0.5)), "p99_ms": ms(_pct(lat(res_b), 0.99)),
-                                   "speedup_vs_fp64_sequential": (len(reqs) / sat_s) / fp64_rate,
-                                   "service_s": busy, "overlap": (busy["hdm"] + busy["rom"]) / sat_s},
-        "served_mixed_poisson": {"arrival_rate_per_s": 0.7 * fp64_rate,
-                                 "p50_ms": ms(_pct(lat(res_c), 0.5)), "p99_ms": ms(_pct(lat(res_c), 0.99)),
-                                 "p50_ms_rom": ms(_pct(lat(res_c, "rom"), 0.5)),
-                                 "p99_ms_rom": ms(_pct(lat(res_c, "rom"), 0.99)),
-                                 "p50_ms_hdm": ms(_pct(lat(res_c, "hdm"), 0.5)),
-                                 "p99_ms_hdm": ms(_pct(lat(res_c, "hdm"), 0.99))},
-        "max_rel_diff_vs_fp64": {"hdm_J": rel_diff("hdm"), "rom_Jk": rel_diff("rom")},
-        "mean_rom_batch": st["mean_rom_batch"],
-        "max_held_gb": st["max_held_bytes"] / 2**30,
-        "failed": failed,
-        "workers": args.serving_workers,
-    }
+    out = {"requests": len(reqs),
+           "mix": {"meshes": list(W.SERVING_MESHES), "rom_frac": 0.8, "k": [8, kmax],
+                   "hdm": sum(q.kind == "hdm" for q in reqs)},
+           "fp64_sequential": {"evals_per_s": fp64_rate, "p50_ms": _ms(_pct(lat_a, 0.5)),
+                               "p99_ms": _ms(_pct(lat_a, 0.99))}}
+    failed = 0
+    for name, prec in (("served_fp64_saturated", FP64), ("served_mixed_saturated", MIXED)):
+        srv, ids, res, dt = saturated(prec)
+        busy, njobs = job_busy(res)
+        st = srv.stats()
+        failed += sum(1 for r in res if r["status"] != 0)
+        out[name] = {"evals_per_s": len(reqs) / dt, "makespan_s": dt,
+                     "p50_ms": _ms(_pct(lat(res), 0.5)), "p99_ms": _ms(_pct(lat(res), 0.99)),
+                     "speedup_vs_fp64_sequential": (len(reqs) / dt) / fp64_rate,
+                     "jobs": njobs, "mean_rom_batch": st["mean_rom_batch"],
+                     "mean_hdm_batch": st.get("mean_hdm_batch"),
+                     "job_service_s": busy, "overlap": (busy["hdm"] + busy["rom"]) / dt,
+                     "max_rel_diff_vs_fp64_sequential": {"hdm_J": rel_diff(res, "hdm"), "rom_Jk": rel_diff(res, "rom")},
+                     "max_held_gb": st["max_held_bytes"] / 2**30}
+        if prec == MIXED:
+            arr = W.poisson_arrivals(len(reqs), 0.7 * fp64_rate)
+            tickets = []
+            t0 = time.perf_counter()
+            for q, ta in zip(reqs, arr):
+                dtw = t0 + ta - time.perf_counter()
+                if dtw > 0:
+                    time.sleep(dtw)
+                tickets.append(submit(srv, ids, q, MIXED))
+            res_c = [srv.wait(t) for t in tickets]
+            failed += sum(1 for r in res_c if r["status"] != 0)
+            out["served_mixed_poisson"] = {
+                "arrival_rate_per_s": 0.7 * fp64_rate,
+                "p50_ms": _ms(_pct(lat(res_c), 0.5)), "p99_ms": _ms(_pct(lat(res_c), 0.99)),
+                "p50_ms_rom": _ms(_pct(lat(res_c, "rom"), 0.5)), "p99_ms_rom": _ms(_pct(lat(res_c, "rom"), 0.99)),
+                "p50_ms_hdm": _ms(_pct(lat(res_c, "hdm"), 0.5)), "p99_ms_hdm": _ms(_pct(lat(res_c, "hdm"), 0.99))}
+        srv.close()
+    out["failed"] = failed
+    out["workers"] = args.serving_workers
+    return out
 
 
 def basis_leg(torch, binding, ctx, n, L=20, nmax=19):
@@ -319,19 +458,27 @@ def basis_leg(torch, binding, ctx, n, L=20, nmax=19):
     return out
 
 
+def helmholtz_length(R):
+    """Helmholtz length r of a filter radius R: the conic filter's second moment
+    matched, r = R / (2 sqrt(3)) (the relation of the filter reference the paper cites
+    for Sec. 2.2; its text prints the inverse factor, which gives a filter about 12
+    times wider)."""
+    return R / (2.0 * np.sqrt(3.0))
+
+
 def filter_leg(torch, ctx, mesh, R=3.0, rtol=1e-10):
     """Helmholtz filter forward (psi -> rho) and adjoint (dJ/drho -> dJ/dpsi) on one field
-    of the mesh with filter radius R (in element sizes; r = 2 sqrt(3) R): wall time per
-    call (each synchronises) and PCG iterations."""
+    of the mesh with filter radius R (in element sizes): wall time per call (each
+    synchronises) and PCG iterations."""
     dev = torch.device("cuda", 0)
     gen = torch.Generator(device=dev)
     gen.manual_seed(13)
-    r = 2.0 * np.sqrt(3.0) * R
+    r = helmholtz_length(R)
     psi = torch.rand((1, mesh.n_elems), device=dev, dtype=torch.float64, generator=gen)
     v = -torch.rand((1, mesh.n_elems), device=dev, dtype=torch.float64, generator=gen)
     rho = torch.empty_like(psi)
     g = torch.empty_like(psi)
-    out = {"R": R, "rtol": rtol, "n_nodes": mesh.n_nodes}
+    out = {"R": R, "r": r, "rtol": rtol, "n_nodes": mesh.n_nodes}
     for name, fn, x, y in (("forward", ctx.filter_forward, psi, rho), ("adjoint", ctx.filter_adjoint, v, g)):
         fn(mesh, r, x, y, rtol=rtol)
         lat = []
@@ -347,78 +494,175 @@ def filter_leg(torch, ctx, mesh, R=3.0, rtol=1e-10):
 
 def tr_leg(torch, ctx, problem, R=3.0, vf=0.5, iters=3):
     """Three outer iterations of the ROM trust-region method (residual trust region,
-    window 5, n_max 4) from the uniform design on the workload mesh: wall time, HDM
-    solves, model evaluations and the compliance at each centre."""
+    window 5, n_max 4) from the uniform design on the mesh: wall time, HDM solves, model
+    evaluations and the compliance at each centre."""
     from paper_2004_05756_amd.trdriver import TrustRegion
-    r = 2.0 * np.sqrt(3.0) * R
+    r = helmholtz_length(R)
     drv = TrustRegion(ctx, problem.mesh, problem.mask, problem.f, r, vf, kind="res", window=5, nmax=4)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     _, hist = drv.run(iters=iters, tau=0.1)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    return {"R": R, "vf": vf, "outer_iters": iters, "seconds": dt, "hdm_solves": drv.hdm_solves,
+    return {"R": R, "r": r, "vf": vf, "outer_iters": iters, "seconds": dt, "hdm_solves": drv.hdm_solves,
             "model_evals": drv.model_evals, "J_centres": [h["J"] for h in hist],
             "accepted": [bool(h["accepted"]) for h in hist], "ratios": [float(h["ratio"]) for h in hist]}
 
 
-def bridge_leg(torch, W, binding, FP64, MIXED):
-    """The 192x96x96 bridge: the 16-field batched apply in both precisions (kernel time
-    from the library's sampled events, algorithmic bytes, HBM fraction) and one HDM
-    solve per precision to the workload's tolerance.  The 16 density fields are four
-    seeded smoothed fields, each used four times (the smoothing of 16 fields on the host
-    would dominate the leg; the apply's cost does not depend on the values)."""
-    cfg = W.config("bridge3d_192x96x96")
-    p, m = cfg.problem, cfg.problem.mesh
-    dev = torch.device("cuda", 0)
-    base = [cfg.rho(i) for i in range(4)]
-    rhos = torch.as_tensor(np.stack([base[i % 4] for i in range(cfg.batch)])).to(dev)
-    mask = torch.as_tensor(p.mask).to(dev)
-    f = torch.as_tensor(p.f).to(dev)
-    ctx = binding.Context(0)
-    out = {"workload": cfg.name, "n_dofs": m.n_dofs, "fields": cfg.batch}
-    gen = torch.Generator(device=dev)
-    gen.manual_seed(7)
-    for name, pr, dt in (("mixed", MIXED, torch.float32), ("fp64", FP64, torch.float64)):
-        w = 4 if pr == MIXED else 8
-        x = torch.randn(cfg.batch, m.n_dofs, device=dev, dtype=dt, generator=gen)
-        y = torch.empty_like(x)
-        for _ in range(2):
-            ctx.apply(m, rhos, mask, x, y=y, prec=pr)
-        torch.cuda.synchronize()
-        ctx.kernel_time("apply", reset=True)
-        ctx.set_timing(1)
-        reps = 10
-        for _ in range(reps):
-            ctx.apply(m, rhos, mask, x, y=y, prec=pr)
-        torch.cuda.synchronize()
-        ctx.set_timing(0)
-        n, ms = ctx.kernel_time("apply", reset=True)
-        us = 1e3 * ms / max(n, 1)
-        nbytes = cfg.batch * (m.n_dofs * (2 * w + 1) + m.n_elems * w)
-        gbs = nbytes / (us * 1e-6) / 1e9
-        out[f"apply_{name}"] = {"kernel_us": us, "bytes_per_launch": nbytes, "GB_s": gbs,
-                                "hbm_frac": gbs / HBM_PEAK_GBS}
-        del x, y
-        torch.cuda.synchronize()
+# ----------------------------------------------------------------------------------
+# CPU baseline and accuracy (the only part of the benchmark that runs the oracle)
+# ----------------------------------------------------------------------------------
+
+def _oracle_cg_worker(args):
+    """One field of the CPU sample, in a fresh process: the oracle's FP64 Jacobi-CG
+    solve (assembly included) of the bridge problem at the sample's size."""
+    nel, seed0, b, rtol = args
+    sys.path.insert(0, ROOT)
+    from threadpoolctl import threadpool_limits
+    import oracle as O
+    import workloads as W
+    with threadpool_limits(1):
+        p = W.bridge3d(*nel)
+        centre = W.rho_smoothed(p.mesh, seed0)
+        rho = W.trust_region_fields(p.mesh, centre, 1, seed0 + 100 + b, step=0.1)[0]
+        info = {}
         t0 = time.perf_counter()
-        _, inf = ctx.hdm_solve(m, rhos[0], mask, f, rtol=cfg.rtol, prec=pr)
-        torch.cuda.synchronize()
-        dt_s = time.perf_counter() - t0
-        out[f"hdm_{name}"] = {"ms": 1e3 * dt_s, "iters": inf["iters"], "fp64_fallback": inf["fp64_fallback"],
-                              "rel_resid": inf["rel_resid"], "dof_iter_per_s": m.n_dofs * inf["iters"] / dt_s}
-    out["basis"] = basis_leg(torch, binding, ctx, m.n_dofs)
-    out["filter"] = filter_leg(torch, ctx, m)
+        _, res = O.solve_cg(p.mesh, rho, p.f, p.mask, rtol=rtol, info=info)
+        dt = time.perf_counter() - t0
+    return {"seconds": dt, "iters": info["iters"], "n_dofs": p.mesh.n_dofs, "rel_resid": res}
+
+
+def cpu_baseline_leg(cfg, rtol, fields_np, gpu, phi_cols, cores=None):
+    """(cpu_baseline, accuracy).
+
+    cpu_baseline: the oracle as it stands on the host cores: its FP64 Jacobi-CG solves
+    (sparse assembly + scipy CG on the assembled matrix, restarted on the true
+    residual) of the workload's problem at a quarter of its linear size (48x24x24 for
+    the bridge, 91,875 DOF: the oracle's CG takes 0.1 s per iteration at 698,691 DOF
+    already), one candidate field per
+    process on every available core, to the workload's tolerance; value = sum of
+    N_u x CG iterations / wall time of the parallel run.
+
+    accuracy: each timed result of the GPU step (field 0) against the oracle at the
+    GPU's own state (the oracle cannot solve 5.4M DOF within the sample): the true
+    residual of u recomputed element by element in FP64, the corrected compliance from
+    that residual, the element sensitivities at u, and for the ROM the residual norm and
+    compliance at the GPU's coefficients and three columns of K_hat from the oracle's
+    own products K Phi_j."""
+    import multiprocessing as mp
+    import oracle as O
+    ncores = cores or max(1, min(16, len(os.sched_getaffinity(0))))
+    sample_nel = tuple(max(1, n // 4) for n in cfg.problem.mesh.nel)
+    ctxm = mp.get_context("spawn")
+    t0 = time.perf_counter()
+    with ctxm.Pool(ncores) as pool:
+        recs = pool.map(_oracle_cg_worker, [(sample_nel, cfg.rho_seed0, b, rtol) for b in range(ncores)])
+    wall = time.perf_counter() - t0
+    dof_iters = sum(r["n_dofs"] * r["iters"] for r in recs)
+    base = {"value": dof_iters / wall, "unit": "DOF-iter/s", "cores": ncores, "kind": "oracle",
+            "cpu_model": cpu_model(),
+            "sample": (f"oracle FP64 Jacobi-CG (sparse assembly + scipy CG, restarted on the true residual) of "
+                       f"the bridge problem at {sample_nel[0]}x{sample_nel[1]}x{sample_nel[2]} "
+                       f"({recs[0]['n_dofs']} DOF), {ncores} trust-region candidate fields in parallel "
+                       f"processes (one per core, one thread each) to rel. residual {rtol:g}; value = sum of "
+                       f"N_u x CG iterations / wall time of the parallel run, assembly included"),
+            "seconds": wall, "iters": [r["iters"] for r in recs],
+            "oracle_solve_s": [r["seconds"] for r in recs]}
+
+    p, m = cfg.problem, cfg.problem.mesh
+    rho0 = fields_np[0]
+    u = gpu["u0"]
+    acc = {"field": 0, "definition": "relative errors of the GPU step's results for field 0 against the "
+                                     "oracle evaluated at the GPU's state (FP64)"}
+    ta = time.perf_counter()
+    Ku = O.apply_ebe(m, rho0, p.mask, u)
+    free = p.mask == 0
+    r = np.where(free, p.f - Ku, 0.0)
+    nf = np.linalg.norm(np.where(free, p.f, 0.0))
+    acc["hdm_rel_resid_oracle"] = float(np.linalg.norm(r) / nf)
+    acc["hdm_rel_resid_gpu"] = gpu["rel_resid0"]
+    c_or = float(np.dot(np.where(free, p.f, 0.0), u) + np.dot(u, r))
+    acc["compliance_rel_err"] = abs(gpu["compliance0"] / c_or - 1.0)
+    g_or = O.sensitivity(m, rho0, u)
+    acc["gradient_rel_err"] = float(np.abs(gpu["dc0"] - g_or).max() / np.abs(g_or).max())
+    # ROM at the GPU's coefficients: u_k = Phi y, r = f - K u_k, J_k = f^T u_k (the float32
+    # basis promoted exactly, in row chunks)
+    P = phi_cols
+    ch = 1 << 20
+
+    def p_y(y):
+        return np.concatenate([P[i:i + ch].astype(np.float64) @ y for i in range(0, P.shape[0], ch)])
+
+    def pt_v(v):
+        return sum(P[i:i + ch].astype(np.float64).T @ v[i:i + ch] for i in range(0, P.shape[0], ch))
+
+    uk = np.where(free, p_y(gpu["y0"]), 0.0)
+    rk = np.where(free, p.f - O.apply_ebe(m, rho0, p.mask, uk), 0.0)
+    acc["rom_resnorm_rel_err"] = abs(gpu["resnorm0"] / np.linalg.norm(rk) - 1.0)
+    acc["rom_resnorm_over_f"] = float(np.linalg.norm(rk) / nf)
+    Jk_or = float(np.dot(np.where(free, p.f, 0.0), uk))
+    acc["rom_Jk_rel_err"] = abs(gpu["Jk0"] / Jk_or - 1.0)
+    acc["rom_Jk_over_compliance"] = Jk_or / c_or
+    cols = [0, P.shape[1] // 2, P.shape[1] - 1]
+    errs = []
+    for j in cols:
+        kcol = pt_v(O.apply_ebe(m, rho0, p.mask, np.where(free, P[:, j].astype(np.float64), 0.0)))
+        errs.append(float(np.abs(gpu["Khat0"][:, j] - kcol).max() / np.abs(kcol).max()))
+    acc["rom_Khat_columns"] = cols
+    acc["rom_Khat_rel_err"] = max(errs)
+    acc["seconds"] = time.perf_counter() - ta
+    return base, acc
+
+
+def small_config_accuracy(torch, W, binding, FP64, MIXED):
+    """Configs 1 and 2 (the oracle factorises them): compliance, sensitivity, J_k and
+    ||r|| of the GPU path in both precisions against the oracle's direct solve and its
+    assembled Phi^T (K Phi).  Runs the oracle, so it belongs to the CPU-baseline leg."""
+    import oracle as O
+    dev = torch.device("cuda", 0)
+    ctx = binding.Context(0)
+    out = {}
+    for name in ("mbb2d_60x20", "cantilever2d_600x200"):
+        cfg = W.config(name)
+        p, m = cfg.problem, cfg.problem.mesh
+        rho_np = cfg.rho(0)
+        phi_np = W.cosine_basis(m, p.mask, cfg.k, cfg.basis_seed, np.float32)
+        uo = O.solve_direct(m, rho_np, p.f, p.mask)
+        co = O.compliance(p.f, uo)
+        go = O.sensitivity(m, rho_np, uo)
+        ev = O.rom_eval(m, rho_np, phi_np, p.mask, p.f)
+        rho = torch.as_tensor(rho_np).to(dev)
+        mask = torch.as_tensor(p.mask).to(dev)
+        f = torch.as_tensor(p.f).to(dev)
+        phi = torch.as_tensor(phi_np).to(dev)
+        rec = {}
+        for pname, pr in (("fp64", FP64), ("mixed", MIXED)):
+            u, inf = ctx.hdm_solve(m, rho, mask, f, rtol=cfg.rtol, prec=pr)
+            g = ctx.hdm_gradient(m, rho, u).cpu().numpy()
+            Kh, fh = ctx.rom_build(m, phi, cfg.k, mask, f, rho.view(1, -1), prec=pr)
+            y, _ = ctx.rom_solve(Kh, fh)
+            _, Je, rn = ctx.rom_estimate(m, phi, cfg.k, mask, f, rho.view(1, -1), Kh, y,
+                                         max_refine=1 if pr == MIXED else 0)
+            rec[pname] = {"compliance_rel_err": abs(inf["compliance_corr"] / co - 1),
+                          "gradient_rel_err": float(np.abs(g - go).max() / np.abs(go).max()),
+                          "Jk_rel_err": abs(float(Je[0]) / ev["Jk"] - 1),
+                          "resnorm_rel_err": abs(float(rn[0]) / ev["resnorm"] - 1)}
+        out[name] = rec
     ctx.close()
     return out
 
+
+# ----------------------------------------------------------------------------------
+# Main
+# ----------------------------------------------------------------------------------
 
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "the benchmark runs on one GPU only: sharding across GPUs "
-                                   "is designed but not implemented", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this build runs on one GPU only: multi-GPU sharding is designed "
+                                   "but not implemented, so no figure at several GPUs is produced",
+                          "n_gpus": args.gpus}))
         sys.exit(2)
 
     import torch
@@ -437,47 +681,70 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"calibrate_copy_bytes": 4 * n, "launches": 5}))
         return
+
+    def progress(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
     cfg = W.config(args.workload)
     p = cfg.problem
     m = p.mesh
+    B = args.fields or cfg.batch
     k = args.k or cfg.k
     rtol = args.rtol or cfg.rtol
     prec = MIXED if args.prec == "mixed" else FP64
     word = 4 if prec == MIXED else 8
     dev = torch.device("cuda", 0)
+    one_red = m.dim == 2 and prec == FP64
 
-    rho_np = cfg.rho(0)
-    phi_np = W.cosine_basis(m, p.mask, k, cfg.basis_seed, np.float32)
-    rho = torch.as_tensor(rho_np).to(dev)
-    rho1 = rho.view(1, -1)
+    progress(f"inputs: {cfg.name}, {B} fields, k = {k}")
+    centre, fields_np, snaps_np = headline_inputs(W, cfg, B)
     mask = torch.as_tensor(p.mask).to(dev)
     f = torch.as_tensor(p.f).to(dev)
-    phi = torch.as_tensor(phi_np).to(dev)
-    u = torch.empty_like(f)
-    dc = torch.empty_like(rho)
-    Kh = torch.empty((1, k, k), dtype=torch.float64, device=dev)
-    fh = torch.empty(k, dtype=torch.float64, device=dev)
-    y = torch.empty((1, k), dtype=torch.float64, device=dev)
-    J = torch.empty(1, dtype=torch.float64, device=dev)
-    Je = torch.empty(1, dtype=torch.float64, device=dev)
-    rn = torch.empty(1, dtype=torch.float64, device=dev)
-    dJ = torch.empty((1, m.n_elems), dtype=torch.float64, device=dev)
-    st = torch.empty(1, dtype=torch.int32, device=dev)
-
+    R = torch.as_tensor(fields_np).to(dev)
     ctx = binding.Context(0)
+    progress("basis from the snapshot window")
+    phi, basis_info = build_basis(torch, W, binding, ctx, cfg, centre, snaps_np, k, rtol, dev)
 
-    def step():
-        _, info = ctx.hdm_solve(m, rho, mask, f, u=u, rtol=rtol, prec=prec)
-        ctx.hdm_gradient(m, rho, u, dc=dc)
-        ctx.rom_build(m, phi, k, mask, f, rho1, prec=prec, Khat=Kh, fhat=fh)
-        ctx.rom_solve(Kh, fh, status=st, yhat=y, Jk=J)
-        ctx.rom_estimate(m, phi, k, mask, f, rho1, Kh, y, max_refine=args.max_refine, Jk=Je, resnorm=rn)
-        ctx.rom_gradient(m, phi, k, mask, rho1, y, dJ=dJ)
-        return info
+    U = torch.empty((B, m.n_dofs), dtype=torch.float64, device=dev)
+    DC = torch.empty((B, m.n_elems), dtype=torch.float64, device=dev)
+    KH = torch.empty((B, k, k), dtype=torch.float64, device=dev)
+    FH = torch.empty(k, dtype=torch.float64, device=dev)
+    Y = torch.empty((B, k), dtype=torch.float64, device=dev)
+    J = torch.empty(B, dtype=torch.float64, device=dev)
+    JE = torch.empty(B, dtype=torch.float64, device=dev)
+    RN = torch.empty(B, dtype=torch.float64, device=dev)
+    DJ = torch.empty((B, m.n_elems), dtype=torch.float64, device=dev)
+    ST = torch.empty(B, dtype=torch.int32, device=dev)
+    phases = {"hdm": 0.0, "rom": 0.0}
 
-    for _ in range(args.warmup):
+    def step(pr=prec, refine=args.max_refine, record=None):
+        t0 = time.perf_counter()
+        _, infos = ctx.hdm_solve_batch(m, R, mask, f, u=U, rtol=rtol, prec=pr, check=False)
+        ctx.hdm_gradient_batch(m, R, U, dc=DC)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ctx.rom_build(m, phi, k, mask, f, R, prec=pr, Khat=KH, fhat=FH)
+        ctx.rom_solve(KH, FH, status=ST, yhat=Y, Jk=J)
+        ctx.rom_estimate(m, phi, k, mask, f, R, KH, Y, max_refine=refine if pr == MIXED else 0, Jk=JE,
+                         resnorm=RN, dJ=DJ)
+        if record is not None:
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            record["hdm"] += t1 - t0
+            record["rom"] += t2 - t1
+        return infos
+
+    if args.profile_step:
+        for i in range(args.warmup + args.steps):
+            infos = step()
+            torch.cuda.synchronize()
+            progress(f"profile step {i}: iters {[x['iters'] for x in infos]}")
+        return
+
+    for i in range(args.warmup):
         step()
-    torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        progress(f"warmup {i} done")
     names = ["pcg_step", "pcg_apply", "pcg_update", "residual", "rom_contract", "rom_reduce", "phit_v",
              "phi_y", "chol", "chol_solve", "gradient"]
     for nm in names:
@@ -486,51 +753,69 @@ def main():
 
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    iters = 0
-    infos = []
-    for _ in range(args.steps):
-        info = step()
-        iters += info["iters"]
-        infos.append(info)
+    field_iters = 0
+    infos_all = []
+    for i in range(args.steps):
+        infos = step(record=phases)
+        field_iters += sum(x["iters"] for x in infos)
+        infos_all.append(infos)
+        progress(f"step {i}: iters {[x['iters'] for x in infos]}")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ctx.set_timing(0)
     elapsed = t1 - t0
-    value = m.n_dofs * iters / elapsed
+    value = m.n_dofs * field_iters / elapsed
 
     # live per-kernel durations from the sampled HIP events of the timed region
     ktimes = {}
     for nm in names:
-        n, ms = ctx.kernel_time(nm)
+        n, ms, nl = ctx.kernel_time(nm, launches=True)
         if n:
-            ktimes[nm] = {"samples": n, "avg_us": 1e3 * ms / n}
-    launches = {"pcg_step": iters, "pcg_apply": iters, "pcg_update": iters, "rom_contract": args.steps}
-    share = {nm: ktimes[nm]["avg_us"] * launches[nm] for nm in launches if nm in ktimes}
+            ktimes[nm] = {"samples": n, "avg_us": 1e3 * ms / n, "launches": nl,
+                          "est_total_ms": ms / n * nl}
+    pcg_kinds = ["pcg_step"] if one_red else ["pcg_apply", "pcg_update"]
+    share = {nm: ktimes[nm]["est_total_ms"] for nm in pcg_kinds + ["rom_contract"] if nm in ktimes}
     dominant = max(share, key=share.get) if share else None
     pb = pcg_bytes(m.n_dofs, m.n_nodes, m.n_elems, word)
-    roofline = None
-    if dominant in pb:
-        avg_s = ktimes[dominant]["avg_us"] * 1e-6
-        gbs = pb[dominant] / avg_s / 1e9
-        kname = pcg_kernel_name(dominant, m.dim, word)
-        roofline = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": gbs / HBM_PEAK_GBS, "traffic": measured_traffic(cfg.name, kname),
-                    "kernel": kname, "bytes_per_launch": pb[dominant], "avg_us": ktimes[dominant]["avg_us"]}
-    elif dominant == "rom_contract":
+
+    def pcg_roofline(kd):
+        kt = ktimes[kd]
+        avg_s = kt["avg_us"] * 1e-6
+        per_launch = pb[kd] * field_iters / kt["launches"]  # bytes of the active fields per launch
+        gbs = per_launch / avg_s / 1e9
+        kname = pcg_kernel_name(kd, m.dim, word)
+        return {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": gbs / HBM_PEAK_GBS, "traffic": measured_traffic(cfg.name, kname),
+                "kernel": kname, "bytes_per_launch": per_launch, "bytes_per_field_launch": pb[kd],
+                "mean_active_fields": field_iters / kt["launches"], "avg_us": kt["avg_us"]}
+
+    def contract_roofline():
+        kt = ktimes["rom_contract"]
         ne = m.dim * 2 ** m.dim
-        fl = rom_contract_flops(m.n_elems, k, ne)
-        avg_s = ktimes[dominant]["avg_us"] * 1e-6
+        fl = B * rom_contract_flops(m.n_elems, k, ne)
+        avg_s = kt["avg_us"] * 1e-6
         peak = FP32_MFMA_PEAK_TFS if word == 4 else FP64_MFMA_PEAK_TFS
         tfs = fl / avg_s / 1e12
-        roofline = {"bound": "mfma", "achieved": tfs, "peak": peak, "unit": "TFLOP/s", "frac": tfs / peak,
-                    "traffic": None, "kernel": "k_rom_contract", "flops_per_launch": fl,
-                    "avg_us": ktimes[dominant]["avg_us"]}
+        return {"bound": "mfma", "achieved": tfs, "peak": peak, "unit": "TFLOP/s", "frac": tfs / peak,
+                "traffic": None, "kernel": "k_rom_contract", "flops_per_launch": fl, "fields": B,
+                "avg_us": kt["avg_us"]}
 
+    roofline = None
+    if dominant in pb:
+        roofline = pcg_roofline(dominant)
+    elif dominant == "rom_contract":
+        roofline = contract_roofline()
+    rooflines = {kd: pcg_roofline(kd) for kd in pcg_kinds if kd in ktimes}
+    if "rom_contract" in ktimes:
+        rooflines["rom_contract"] = contract_roofline()
+
+    last = infos_all[-1]
     out = {
         "metric": "PCG DOF-iter/s (%HBM peak); ROM evals/s + p99 latency, mixed vs plain FP64",
-        "value_definition": "PCG DOF-iterations per second of the whole hot-path step (HDM solve, "
-                            "sensitivity, ROM build, reduced solve, estimate and ROM sensitivity "
-                            "inside the timed region); the %HBM peak is roofline.frac, the ROM "
+        "value_definition": "PCG DOF-iterations per second of the whole hot-path step (batched HDM solve of "
+                            "the fields, sensitivities, ROM build, reduced solves, estimate with the ROM "
+                            "sensitivity fused in, all inside the timed region): sum over fields of N_u x "
+                            "inner PCG iterations / wall time; the %HBM peak is roofline.frac, the ROM "
                             "evals/s and p99 latencies in each precision are under rom",
         "value": value,
         "unit": "DOF-iter/s",
@@ -543,68 +828,96 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+f64" if prec == MIXED else "f64",
         "data": "synthetic",
-        "config": {"workload": cfg.name, "n_dofs": m.n_dofs, "n_elems": m.n_elems, "k": k, "rtol": rtol,
-                   "precision": args.prec, "max_refine": args.max_refine},
+        "config": {"workload": cfg.name, "fields": B, "k": k, "n_dofs": m.n_dofs, "n_elems": m.n_elems,
+                   "rtol": rtol, "precision": args.prec, "max_refine": args.max_refine,
+                   "fields_recipe": "trust-region candidates around a seeded smoothed centre (step 0.1)",
+                   "basis": basis_info},
         "roofline": roofline,
-        "pcg_iters_per_step": iters / args.steps,
-        "refinements_per_step": statistics.mean(i["refinements"] for i in infos),
-        "rel_resid": infos[-1]["rel_resid"],
+        "rooflines": rooflines,
+        "time_to_solution": {args.prec: {"hdm_s_per_step": phases["hdm"] / args.steps,
+                                         "rom_s_per_step": phases["rom"] / args.steps,
+                                         "hdm_solves_per_s": B * args.steps / phases["hdm"],
+                                         "rom_evals_per_s": B * args.steps / phases["rom"]}},
+        "pcg_iters_per_step": field_iters / args.steps,
+        "iters_per_field": [x["iters"] for x in last],
+        "refinements": [x["refinements"] for x in last],
+        "fp64_fallback": [x["fp64_fallback"] for x in last],
+        "rel_resid_max": max(x["rel_resid"] for x in last),
+        "status": [x["status"] for x in last],
+        "rom_Jk_over_compliance": float((JE / torch.tensor([x["compliance_corr"] for x in last],
+                                                             dtype=torch.float64, device=dev)).mean()),
+        "rom_resnorm_over_f": float(RN.max() / torch.linalg.vector_norm(f)),
         "kernels": ktimes,
     }
+    torch.cuda.synchronize()
+    gpu0 = {"u0": U[0].cpu().numpy(), "dc0": DC[0].cpu().numpy(), "y0": Y[0].cpu().numpy(),
+            "Khat0": KH[0].cpu().numpy(), "Jk0": float(JE[0]), "resnorm0": float(RN[0]),
+            "compliance0": last[0]["compliance_corr"], "rel_resid0": last[0]["rel_resid"]}
+
+    # ROM evaluations per second and latency of the batch, mixed vs plain FP64
+    rom = {}
+    for pname, pr in (("mixed", MIXED), ("fp64", FP64)):
+        lat = []
+        for i in range(args.rom_evals + 1):
+            ta = time.perf_counter()
+            ctx.rom_build(m, phi, k, mask, f, R, prec=pr, Khat=KH, fhat=FH)
+            ctx.rom_solve(KH, FH, status=ST, yhat=Y, Jk=J)
+            ctx.rom_estimate(m, phi, k, mask, f, R, KH, Y, max_refine=args.max_refine if pr == MIXED else 0,
+                             Jk=JE, resnorm=RN, dJ=DJ)
+            torch.cuda.synchronize()
+            if i > 0:
+                lat.append(time.perf_counter() - ta)
+        rom[pname] = {"evals_per_s": B * len(lat) / sum(lat), "batch": B,
+                      "p50_ms": _ms(_pct(lat, 0.5)), "p99_ms": _ms(_pct(lat, 0.99)),
+                      "latency": "per batched evaluation of all fields"}
+    out["rom"] = rom
+    progress("rom legs done")
 
     if not args.no_extra:
-        # HDM-only throughput in each precision, and ROM evals/s with latency percentiles
-        # (one eval = build + reduced solve + estimate), mixed vs plain FP64.
+        # the same step in the other precision: time to solution of each half
+        other = "fp64" if args.prec == "mixed" else "mixed"
+        rec = {"hdm": 0.0, "rom": 0.0}
+        infos = step(pr=FP64 if other == "fp64" else MIXED, record=rec)
+        out["time_to_solution"][other] = {"hdm_s_per_step": rec["hdm"], "rom_s_per_step": rec["rom"],
+                                          "hdm_solves_per_s": B / rec["hdm"], "rom_evals_per_s": B / rec["rom"],
+                                          "iters_per_field": [x["iters"] for x in infos]}
+        tts = out["time_to_solution"]
+        out["faster_precision"] = {"hdm": min(tts, key=lambda q: tts[q]["hdm_s_per_step"]),
+                                   "rom": min(tts, key=lambda q: tts[q]["rom_s_per_step"])}
+        progress("precision leg done")
+    del KH, DJ
+    ctx.close()
+    torch.cuda.empty_cache()
+
+    if not args.no_extra:
         extra = {}
-        for name, pr in (("mixed", MIXED), ("fp64", FP64)):
-            torch.cuda.synchronize()
-            ta = time.perf_counter()
-            _, inf = ctx.hdm_solve(m, rho, mask, f, u=u, rtol=rtol, prec=pr)
-            torch.cuda.synchronize()
-            tb = time.perf_counter() - ta
-            extra[f"hdm_{name}"] = {"ms": 1e3 * tb, "iters": inf["iters"],
-                                    "us_per_iter": 1e6 * tb / max(1, inf["iters"]),
-                                    "dof_iter_per_s": m.n_dofs * inf["iters"] / tb,
-                                    "compliance": inf["compliance_corr"]}
-            lat = []
-            for i in range(args.rom_evals):
-                ta = time.perf_counter()
-                ctx.rom_build(m, phi, k, mask, f, rho1, prec=pr, Khat=Kh, fhat=fh)
-                ctx.rom_solve(Kh, fh, status=st, yhat=y, Jk=J)
-                ctx.rom_estimate(m, phi, k, mask, f, rho1, Kh, y,
-                                 max_refine=args.max_refine if pr == MIXED else 0, Jk=Je, resnorm=rn)
-                torch.cuda.synchronize()
-                lat.append(time.perf_counter() - ta)
-            lat.sort()
-            # the ROM sensitivity dJ_k/drho at the state just estimated (value + gradient
-            # of the trust-region model)
-            glat = []
-            for i in range(20):
-                ta = time.perf_counter()
-                ctx.rom_gradient(m, phi, k, mask, rho1, y, dJ=dJ)
-                torch.cuda.synchronize()
-                glat.append(time.perf_counter() - ta)
-            glat.sort()
-            extra[f"rom_{name}_gradient_ms"] = 1e3 * glat[len(glat) // 2]
-            extra[f"rom_{name}"] = {"evals_per_s": len(lat) / sum(lat),
-                                    "p50_ms": 1e3 * lat[len(lat) // 2],
-                                    "p99_ms": 1e3 * lat[min(len(lat) - 1, int(0.99 * len(lat)))],
-                                    "Jk": float(Je[0]), "resnorm": float(rn[0])}
-        extra["basis"] = basis_leg(torch, binding, ctx, m.n_dofs)
-        extra["filter"] = filter_leg(torch, ctx, m)
-        extra["trust_region"] = tr_leg(torch, ctx, cfg.problem)
+        extra["batch_2d"] = batch_scaling_leg(torch, W, binding, FP64, MIXED)
+        progress("2D batch leg done")
+        extra["configs"] = {nm: config_leg(torch, W, binding, FP64, MIXED, nm)
+                            for nm in ("mbb2d_60x20", "cantilever2d_600x200", "cantilever3d_96x48x48")}
+        progress("per-config legs done")
+        c2 = W.config("cantilever2d_600x200")
+        ctx2 = binding.Context(0)
+        extra["basis"] = basis_leg(torch, binding, ctx2, c2.problem.mesh.n_dofs)
+        extra["basis_bridge"] = basis_leg(torch, binding, ctx2, m.n_dofs)
+        extra["filter"] = filter_leg(torch, ctx2, c2.problem.mesh)
+        extra["filter_bridge"] = filter_leg(torch, ctx2, m)
+        extra["trust_region"] = tr_leg(torch, ctx2, c2.problem)
+        ctx2.close()
+        progress("basis / filter / trust-region legs done")
         out["extra"] = extra
-        out["rom"] = {nm: {q: extra[f"rom_{nm}"][q] for q in ("evals_per_s", "p50_ms", "p99_ms")}
-                      for nm in ("mixed", "fp64")}
 
     if not args.no_serving:
         out["serving"] = serving_leg(args, torch, W, binding, FP64, MIXED)
-
-    if not args.no_bridge:
-        out["bridge"] = bridge_leg(torch, W, binding, FP64, MIXED)
+        progress("serving leg done")
 
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cfg, phi_np, iters / args.steps, m.n_dofs)
+        phi_np = phi.cpu().numpy()
+        base, acc = cpu_baseline_leg(cfg, rtol, fields_np, gpu0, phi_np)
+        out["cpu_baseline"] = base
+        out["accuracy"] = {cfg.name: acc}
+        out["accuracy"].update(small_config_accuracy(torch, W, binding, FP64, MIXED))
+        progress("cpu baseline and accuracy done")
     print(json.dumps(out))
 
 

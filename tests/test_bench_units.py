@@ -24,14 +24,16 @@ def test_pcg_bytes_count_every_array_once():
         assert b["pcg_update"] == nu * (16 + 2 * w + w + 2 * w) + nn * w
 
 
-def test_kernel_names_match_the_traffic_summary():
-    path = os.path.join(ROOT, "profiles", "hbm_traffic_cantilever2d_600x200.md")
-    rec = None
-    with open(path) as fh:
-        for line in fh:
-            if line.startswith("traffic-json: "):
-                rec = json.loads(line[len("traffic-json: "):])
-    assert rec is not None
-    assert bench.pcg_kernel_name("pcg_apply", 2, 4) in rec
-    assert bench.pcg_kernel_name("pcg_update", 2, 4) in rec
-    assert bench.pcg_kernel_name("pcg_step", 2, 8) in rec
+def test_kernel_names_match_the_traffic_summaries():
+    """Every PCG kernel recorded in a committed traffic summary is named as bench.py
+    looks it up (the symbol rocprofv3 prints)."""
+    import glob
+    names = {bench.pcg_kernel_name(kd, d, w) for kd in ("pcg_step", "pcg_apply", "pcg_update")
+             for d in (2, 3) for w in (4, 8)}
+    for path in glob.glob(os.path.join(ROOT, "profiles", "hbm_traffic_*.md")):
+        with open(path) as fh:
+            for line in fh:
+                if line.startswith("traffic-json: "):
+                    for key in json.loads(line[len("traffic-json: "):]):
+                        if key.startswith(("k_pcg", "k_cg1")):
+                            assert key in names, (path, key)

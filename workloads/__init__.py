@@ -26,7 +26,7 @@ import numpy as np
 __all__ = [
     "Mesh", "Problem", "mbb2d", "cantilever2d", "cantilever3d", "bridge3d",
     "paper_mbb", "paper_cantilever", "paper_ssbeam",
-    "rho_jitter", "rho_smoothed", "rho_batch", "cosine_basis", "orthonormalize",
+    "rho_jitter", "rho_smoothed", "rho_batch", "trust_region_fields", "cosine_basis", "orthonormalize",
     "config", "CONFIG_NAMES", "SERVING_MESHES", "ServingRequest", "serving_stream", "poisson_arrivals",
 ]
 
@@ -261,6 +261,18 @@ def rho_smoothed(mesh: Mesh, seed: int, sigma=3.0, lo=0.05, hi=1.0):
     return (lo + (hi - lo) * s).ravel()
 
 
+def trust_region_fields(mesh: Mesh, centre: np.ndarray, count: int, seed: int, step: float = 0.1,
+                        lo: float = 0.05, hi: float = 1.0) -> np.ndarray:
+    """count densities around a centre design, as the trust-region iterates that a ROM is
+    evaluated on: rho_b = clip(centre + step (2 s_b - 1), lo, hi) with s_b a seeded
+    smoothed field in [0, 1] (rho_smoothed's recipe).  Returns [count][n_elems]."""
+    out = np.empty((count, mesh.n_elems))
+    for b in range(count):
+        s = rho_smoothed(mesh, seed + b, lo=0.0, hi=1.0)
+        out[b] = np.clip(centre + step * (2.0 * s - 1.0), lo, hi)
+    return out
+
+
 def rho_batch(mesh: Mesh, base_seed: int, count: int, kind="smoothed"):
     fn = rho_smoothed if kind == "smoothed" else rho_jitter
     return np.stack([fn(mesh, base_seed + i) for i in range(count)])
@@ -272,9 +284,12 @@ def cosine_basis(mesh: Mesh, mask: np.ndarray, k: int, seed: int, dtype=np.float
     Dirichlet DOFs.  Row-major [n_dofs][k]."""
     rng = np.random.default_rng(seed)
     d = mesh.dim
-    coords = mesh.node_coords().astype(np.float64)
+    nn = mesh.nn
     L = np.array(mesh.nel, dtype=np.float64)
-    phi = np.zeros((mesh.n_dofs, k), dtype=np.float64)
+    # columns are built one contiguous row of phi^T at a time (in float64, then stored
+    # in dtype), the node value being the product of per-axis cosine factors
+    phit = np.zeros((k, mesh.n_dofs), dtype=dtype)
+    fixed = mask.astype(bool)
     used = set()
     maxw = 1
     col = 0
@@ -286,13 +301,15 @@ def cosine_basis(mesh: Mesh, mask: np.ndarray, k: int, seed: int, dtype=np.float
             continue
         used.add((c,) + wav)
         ph = rng.uniform(0, np.pi, d)
-        vals = np.ones(mesh.n_nodes)
-        for a in range(d):
-            vals *= np.cos(np.pi * wav[a] * coords[a] / L[a] + ph[a])
-        phi[c * mesh.n_nodes:(c + 1) * mesh.n_nodes, col] = vals
+        vals = None
+        for a in range(d):  # x fastest: ((f_x f_y) f_z), the product taken axis by axis
+            fa = np.cos(np.pi * wav[a] * np.arange(nn[a], dtype=np.float64) / L[a] + ph[a])
+            vals = fa if vals is None else np.multiply.outer(fa, vals).ravel()
+        rowv = phit[col]
+        rowv[c * mesh.n_nodes:(c + 1) * mesh.n_nodes] = vals
+        rowv[fixed] = 0
         col += 1
-    phi[mask.astype(bool), :] = 0.0
-    return phi.astype(dtype)
+    return np.ascontiguousarray(phit.T)
 
 
 def snapshot_fields(mesh: Mesh, mask: np.ndarray, count: int, seed: int, decay: float = 0.5,
