@@ -223,6 +223,25 @@ int topo_rom_solve(topo_ctx* ctx, int32_t k, int32_t B, const double* Khat,
                    const double* fhat, double* yhat, double* Jk, int32_t* status,
                    void* stream);
 
+/* Allocation-free variant of topo_rom_solve, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, kernels and results as topo_rom_solve, except that
+ * status [B] int32 DEVICE out is required (the call never synchronises).  The
+ * Cholesky factors go to a fixed device array of the library instead of the context's
+ * workspace: B * k * k * 8 bytes must not exceed topo_rom_solve_noalloc_max_bytes()
+ * (8 MiB; e.g. k = 200 with B <= 26), else TOPO_EINVAL before any device work.  No
+ * device or host memory is allocated and the context's workspace is not touched.  Each
+ * GPU holds one copy of that array until the process ends, shared by every call on
+ * that GPU: calls that overlap on one GPU (other streams, other contexts, other host
+ * threads) race on it, so the caller orders them.  It keeps the last call's factors;
+ * nothing in it needs clearing (the factorisation writes every entry the solve reads).
+ * Errors: TOPO_EINVAL (k, B < 1, null pointer, over the size limit), TOPO_EDEVICE. */
+int topo_rom_solve_noalloc(topo_ctx* ctx, int32_t k, int32_t B, const double* Khat,
+                           const double* fhat, double* yhat, double* Jk, int32_t* status,
+                           void* stream);
+/* Size in bytes of the fixed device array topo_rom_solve_noalloc uses (host scalar). */
+size_t topo_rom_solve_noalloc_max_bytes(void);
+
 /* Residual-based error indicator (Sec. 3.3 primal residual; Sec. 3.4 cost
  * analysis; Sec. 4.3 residual trust-region constraint):
  *   u_b = Phi yhat[b] (float64 accumulation), r_b = f - K(rho_b) u_b on free DOFs in

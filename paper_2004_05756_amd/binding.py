@@ -22,7 +22,8 @@ EXPORTED = (
     "topo_ctx_create", "topo_ctx_destroy", "topo_last_error", "topo_strerror",
     "topo_ctx_workspace_bytes", "topo_element_stiffness", "topo_element_factor", "topo_apply",
     "topo_hdm_solve", "topo_hdm_solve_batch", "topo_hdm_gradient_batch",
-    "topo_hdm_gradient", "topo_rom_build", "topo_rom_solve", "topo_rom_estimate",
+    "topo_hdm_gradient", "topo_rom_build", "topo_rom_solve", "topo_rom_solve_noalloc",
+    "topo_rom_solve_noalloc_max_bytes", "topo_rom_estimate",
     "topo_rom_gradient", "topo_pod_push", "topo_pod_basis", "topo_filter_forward",
     "topo_filter_adjoint", "topo_ctx_set_timing", "topo_ctx_kernel_time",
 )
@@ -72,6 +73,8 @@ _SIGS = {
     "topo_rom_build": (C.c_int, [_P, C.POINTER(TopoMesh), _P, C.c_int32, C.c_int32, C.c_int32, _P,
                                  _P, _P, C.c_int32, _P, _P, C.c_int32, _P]),
     "topo_rom_solve": (C.c_int, [_P, C.c_int32, C.c_int32, _P, _P, _P, _P, _P, _P]),
+    "topo_rom_solve_noalloc": (C.c_int, [_P, C.c_int32, C.c_int32, _P, _P, _P, _P, _P, _P]),
+    "topo_rom_solve_noalloc_max_bytes": (C.c_size_t, []),
     "topo_rom_estimate": (C.c_int, [_P, C.POINTER(TopoMesh), _P, C.c_int32, C.c_int32, C.c_int32,
                                     _P, _P, _P, C.c_int32, _P, _P, _P, _P, C.c_int32, _P, _P]),
     "topo_rom_gradient": (C.c_int, [_P, C.POINTER(TopoMesh), _P, C.c_int32, C.c_int32, C.c_int32,
@@ -393,6 +396,19 @@ class Context:
                                      _ptr(status, torch.int32, "status") if status is not None else None,
                                      _stream(stream))
         self._check(rc, "rom_solve")
+        return yhat, Jk
+
+    def rom_solve_noalloc(self, Khat, fhat, status, yhat, Jk, stream=None):
+        """topo_rom_solve_noalloc: the reduced solve with its factors in the library's
+        fixed device array (no device allocation); every output tensor is the caller's."""
+        import torch
+        B, k, k2 = Khat.shape
+        _solve_shapes(B, k, k2, fhat, yhat, Jk, status)
+        rc = self.lib.topo_rom_solve_noalloc(self.h, k, B, _ptr(Khat, torch.float64, "Khat"),
+                                             _ptr(fhat, torch.float64, "fhat"),
+                                             _ptr(yhat, torch.float64, "yhat"), _ptr(Jk, torch.float64, "Jk"),
+                                             _ptr(status, torch.int32, "status"), _stream(stream))
+        self._check(rc, "rom_solve_noalloc")
         return yhat, Jk
 
     def rom_estimate(self, mesh, phi, k, mask, f, rho, Khat, yhat, max_refine=1, stream=None,

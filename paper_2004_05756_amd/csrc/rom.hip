@@ -6,6 +6,7 @@
 //   ||f - K(rho) Phi y_hat||  with optional float64 reduced refinement.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 
 #include "elemfac.hpp"
 #include "reduce.hpp"
@@ -1085,6 +1086,73 @@ int topo_rom_solve(topo_ctx* ctx, int32_t k, int32_t B, const double* Khat, cons
         for (int b = 0; b < B; ++b)
             if (h[b] != 0) return set_error(ctx, TOPO_ENOTSPD, "reduced operator %d is not SPD", b);
     }
+    return TOPO_OK;
+}
+
+}  // extern "C"
+
+// ----------------------------------------------------------------------------------
+// Allocation-free reduced solve.  The Cholesky factors of topo_rom_solve live in this
+// fixed device array instead of the context's workspace, for callers that cannot
+// allocate device memory.  Each GPU holds its own copy until the process ends; host
+// code reaches it only through the address hipGetSymbolAddress returns on that device
+// (the array's name is not a device address in host code).
+// ----------------------------------------------------------------------------------
+namespace topo {
+
+constexpr size_t kNoAllocScratchBytes = size_t(8) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kNoAllocMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kNoAllocMaxDevices] = {};
+
+// Device address of `scratch` on the context's device (looked up once per device, with
+// that device current).
+static int noalloc_scratch(Ctx* ctx, void** out) {
+    if (ctx->device < 0 || ctx->device >= kNoAllocMaxDevices)
+        return set_error(ctx, TOPO_EINVAL, "device %d beyond the allocation-free path's range", ctx->device);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[ctx->device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return set_error(ctx, TOPO_EDEVICE, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+        }
+        g_scratch_ptr[ctx->device] = p;
+    }
+    *out = g_scratch_ptr[ctx->device];
+    return TOPO_OK;
+}
+
+}  // namespace topo
+
+extern "C" {
+
+size_t topo_rom_solve_noalloc_max_bytes(void) { return kNoAllocScratchBytes; }
+
+int topo_rom_solve_noalloc(topo_ctx* ctx, int32_t k, int32_t B, const double* Khat, const double* fhat,
+                           double* yhat, double* Jk, int32_t* status, void* stream) {
+    if (!ctx) return TOPO_EINVAL;
+    if (k < 1 || B < 1) return set_error(ctx, TOPO_EINVAL, "k and B must be >= 1");
+    if (!Khat || !fhat || !yhat || !Jk || !status)
+        return set_error(ctx, TOPO_EINVAL, "null pointer argument (status is required)");
+    const size_t need = (size_t)B * (size_t)k * (size_t)k * sizeof(double);
+    if (need > kNoAllocScratchBytes)
+        return set_error(ctx, TOPO_EINVAL, "B k^2 doubles = %zu bytes exceed the fixed scratch of %zu bytes",
+                         need, kNoAllocScratchBytes);
+    TOPO_HIP(hipSetDevice(ctx->device));
+    void* sp = nullptr;
+    const int rc = noalloc_scratch(ctx, &sp);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    double* L = (double*)sp;  // every entry the solve reads is written by the factorisation
+    launch_chol(k, B, Khat, L, (int*)status, s);
+    TOPO_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_chol_solve, dim3(B), dim3(256), 0, s, k, (const double*)L, fhat, 0LL, yhat, 0,
+                       (const double*)nullptr, fhat, Jk);
+    TOPO_CHECK_LAUNCH();
     return TOPO_OK;
 }
 

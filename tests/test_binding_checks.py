@@ -83,6 +83,8 @@ def test_rom_shapes(ctx):
     with pytest.raises(ValueError, match="status"):
         ctx.rom_solve(f64(3, 4, 4), f64(4), status=torch.zeros(2, dtype=torch.int32))
     with pytest.raises(ValueError, match="yhat"):
+        ctx.rom_solve_noalloc(f64(3, 4, 4), f64(4), torch.zeros(3, dtype=torch.int32), f64(3, 3), f64(3))
+    with pytest.raises(ValueError, match="yhat"):
         ctx.rom_estimate(m, phi, 4, u8(70), f64(70), f64(3, 24), f64(3, 4, 4), f64(2, 4))
     with pytest.raises(ValueError, match="dJ"):
         ctx.rom_estimate(m, phi, 4, u8(70), f64(70), f64(3, 24), f64(3, 4, 4), f64(3, 4), dJ=f64(3, 23))
