@@ -161,9 +161,12 @@ def headline_inputs(W, cfg, B):
 
 
 def build_basis(torch, W, binding, ctx, cfg, centre, snaps, k, rtol, dev):
-    """GramSchmidt([POD(HDM snapshots at the earlier centres), u*(centre)]) on the device
-    (the basis of the method at a trust-region centre), then smooth cosine fields up to
-    k columns; float32 [N_u][k]."""
+    """The basis of the method at a trust-region centre on the device,
+    GramSchmidt([POD(HDM snapshots at the earlier centres), u*(centre)]), completed to k
+    columns with smooth cosine fields and orthonormalised as a whole (Cholesky QR twice,
+    float64, on the host: the k = 200 reduced operator of an unorthogonalised mix of
+    unit POD columns and O(1)-entry cosine fields is too ill-conditioned for its float32
+    contraction); float32 [N_u][k]."""
     from paper_2004_05756_amd.binding import MIXED
     p = cfg.problem
     m = p.mesh
@@ -174,15 +177,21 @@ def build_basis(torch, W, binding, ctx, cfg, centre, snaps, k, rtol, dev):
     win = binding.SnapshotWindow(ctx, m.n_dofs, SNAPSHOTS)
     for j in range(SNAPSHOTS):
         win.push(u[1 + j])
-    phi = torch.empty((m.n_dofs, k), dtype=torch.float32, device=dev)
-    ncols, npod = win.basis(u[0], min(SNAPSHOTS, k - 1), phi)
+    nmax = min(SNAPSHOTS, k - 1)
+    pod = torch.zeros((m.n_dofs, nmax + 1), dtype=torch.float64, device=dev)
+    ncols, npod = win.basis(u[0], nmax, pod)
+    torch.cuda.synchronize()
+    cols = [pod[:, :ncols].cpu().numpy()]
+    del u, win, pod
     rest = k - ncols
     if rest > 0:
-        phi[:, ncols:] = torch.as_tensor(W.cosine_basis(m, p.mask, rest, cfg.basis_seed, np.float32)).to(dev)
+        cols.append(W.cosine_basis(m, p.mask, rest, cfg.basis_seed, np.float64))
+    phi = torch.as_tensor(W.orthonormalize_tall(np.hstack(cols), p.mask, np.float32)).to(dev)
+    del cols
     torch.cuda.synchronize()
-    del u, win
     return phi, {"snapshots": SNAPSHOTS, "pod_columns": npod, "snapshot_columns": ncols,
-                 "cosine_columns": max(rest, 0), "snapshot_iters": [i["iters"] for i in infos]}
+                 "cosine_columns": max(rest, 0), "orthonormalised": "Cholesky QR x2 (float64, host)",
+                 "snapshot_iters": [i["iters"] for i in infos]}
 
 
 # ----------------------------------------------------------------------------------

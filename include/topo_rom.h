@@ -96,8 +96,10 @@ typedef struct topo_info {
 /* ---- context ------------------------------------------------------------------ */
 
 /* Create a context on HIP device `device`: element tables, device workspace.
+ * hbm_budget_bytes bounds the device workspace the context may hold (0: no bound); a
+ * call whose workspace would exceed it fails with TOPO_ENOMEM before any device work.
  * Ownership of *out passes to the caller; release with topo_ctx_destroy. */
-int topo_ctx_create(topo_ctx** out, int32_t device);
+int topo_ctx_create(topo_ctx** out, int32_t device, size_t hbm_budget_bytes);
 int topo_ctx_destroy(topo_ctx* ctx);
 /* Message of the last error raised on ctx (valid until the next call on ctx). */
 const char* topo_last_error(const topo_ctx* ctx);

@@ -10,15 +10,19 @@
  *  - meshes (mask, load) and reduced bases are registered once and stay resident in
  *    device memory (library-owned copies);
  *  - each request carries its own density field (copied at submission);
- *  - a dispatcher thread forms jobs: an HDM request is one job; ROM requests on the
+ *  - a dispatcher thread forms jobs: HDM requests on the same (mesh, precision,
+ *    tolerance, iteration limit) are fused into one batched solve (topo_hdm_solve_batch:
+ *    every field's result is bitwise the one it gets alone); ROM requests on the
  *    same (mesh, basis, precision, refinement count) are fused into one batched
  *    reduced-operator build at the largest k of the batch, each request then using
  *    the leading k x k block (basis columns are prefixes, so K_hat_k is that block);
  *  - jobs run on a pool of worker threads, each with its own HIP stream and library
  *    context, so independent jobs overlap on the GPU;
- *  - a job is admitted only when the device workspace it needs, added to what the
- *    workers already hold, stays within the HBM budget given at creation; a job that
- *    can never fit fails with TOPO_ENOMEM;
+ *  - the HBM budget given at creation covers the resident meshes and bases and the
+ *    workers' device workspace: a registration that would take the resident set past
+ *    it fails with TOPO_ENOMEM, and a job is admitted only when the workspace it needs,
+ *    added to the resident set and to what the workers already hold, stays within it;
+ *    a job that can never fit fails with TOPO_ENOMEM;
  *  - requests that arrive while jobs run are admitted as workers and memory free up.
  *
  * A request's result does not depend on the batch it ran in beyond floating-point
@@ -76,8 +80,10 @@ typedef struct topo_serve_stats {
     int64_t submitted, completed, failed;
     int64_t jobs, rom_jobs, hdm_jobs;
     double mean_rom_batch;      /* ROM requests per ROM job                          */
+    double mean_hdm_batch;      /* HDM requests per HDM job                          */
     size_t budget_bytes;
-    size_t held_bytes;          /* device workspace currently held by the workers   */
+    size_t resident_bytes;      /* registered meshes and bases                       */
+    size_t held_bytes;          /* resident set + workspace held by the workers      */
     size_t max_held_bytes;      /* maximum over the server's life (<= budget)       */
     double p50_latency_s[2];    /* [HDM, ROM]: t_done - t_submit over completed     */
     double p99_latency_s[2];
@@ -86,19 +92,21 @@ typedef struct topo_serve_stats {
 } topo_serve_stats;
 
 /* Create a server on `device` with `n_workers` worker streams (1..16), at most
- * `max_batch` ROM requests per fused job (>= 1), and a device-workspace budget of
- * `hbm_budget_bytes` (resident meshes and bases are not charged to it). */
+ * `max_batch` requests per fused job (>= 1), and an HBM budget of `hbm_budget_bytes`
+ * for the registered meshes and bases and the workers' device workspace. */
 int topo_server_create(topo_server** out, int32_t device, size_t hbm_budget_bytes,
                        int32_t max_batch, int32_t n_workers);
 /* Completes every queued request, stops the threads, frees all device memory. */
 int topo_server_destroy(topo_server* srv);
 
 /* Register a mesh with its Dirichlet mask (uint8 [N_u]) and load (f64 [N_u]), both
- * HOST arrays copied to the device.  *mesh_id receives the handle. */
+ * HOST arrays copied to the device.  *mesh_id receives the handle.  TOPO_ENOMEM when
+ * its 9 N_u bytes would take the resident set past the budget. */
 int topo_server_register_mesh(topo_server* srv, const topo_mesh* mesh, const uint8_t* mask,
                               const double* f, int32_t* mesh_id);
 /* Register a basis for a registered mesh: HOST array Phi [N_u][ldphi] (float32 when
- * phi_fp32 != 0), columns 0..kmax-1 copied to the device. */
+ * phi_fp32 != 0), columns 0..kmax-1 copied to the device.  TOPO_ENOMEM when its
+ * N_u kmax (4 or 8) bytes would take the resident set past the budget. */
 int topo_server_register_basis(topo_server* srv, int32_t mesh_id, const void* phi,
                                int32_t phi_fp32, int32_t kmax, int32_t ldphi,
                                int32_t* basis_id);

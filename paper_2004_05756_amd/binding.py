@@ -53,7 +53,7 @@ class TopoInfo(C.Structure):
 
 _P = C.c_void_p
 _SIGS = {
-    "topo_ctx_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32]),
+    "topo_ctx_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.c_size_t]),
     "topo_ctx_destroy": (C.c_int, [_P]),
     "topo_last_error": (C.c_char_p, [_P]),
     "topo_strerror": (C.c_char_p, [C.c_int32]),
@@ -206,11 +206,11 @@ def _solve_shapes(B, k, k2, fhat, yhat, Jk, status):
 class Context:
     """One library context (device workspace + element tables) on one GPU."""
 
-    def __init__(self, device: int = 0):
+    def __init__(self, device: int = 0, budget_bytes: int = 0):
         self.lib = load()
         self.device = device
         h = C.c_void_p()
-        rc = self.lib.topo_ctx_create(C.byref(h), device)
+        rc = self.lib.topo_ctx_create(C.byref(h), device, int(budget_bytes))
         if rc != TOPO_OK:
             raise TopoError(rc, "context creation")
         self.h = h
@@ -608,8 +608,8 @@ class TopoResult(C.Structure):
 class TopoServeStats(C.Structure):
     _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64),
                 ("jobs", C.c_int64), ("rom_jobs", C.c_int64), ("hdm_jobs", C.c_int64),
-                ("mean_rom_batch", C.c_double), ("budget_bytes", C.c_size_t),
-                ("held_bytes", C.c_size_t), ("max_held_bytes", C.c_size_t),
+                ("mean_rom_batch", C.c_double), ("mean_hdm_batch", C.c_double), ("budget_bytes", C.c_size_t),
+                ("resident_bytes", C.c_size_t), ("held_bytes", C.c_size_t), ("max_held_bytes", C.c_size_t),
                 ("p50_latency_s", C.c_double * 2), ("p99_latency_s", C.c_double * 2),
                 ("workers", C.c_int32), ("pad", C.c_int32)]
 

@@ -230,7 +230,13 @@ int Arena::commit(Ctx* ctx, hipStream_t s) {
             ctx->ws = nullptr;
             ctx->ws_bytes = 0;
         }
-        const size_t want = grown(total);
+        size_t want = grown(total);
+        if (ctx->budget > 0 && want > ctx->budget) {
+            if (total > ctx->budget)
+                return set_error(ctx, TOPO_ENOMEM, "workspace of %zu bytes exceeds the context budget of %zu bytes",
+                                 total, ctx->budget);
+            want = ctx->budget;  // no growth margin beyond the budget
+        }
         if (hipMalloc(&ctx->ws, want) != hipSuccess) {
             (void)hipGetLastError();
             ctx->ws = nullptr;
@@ -245,6 +251,17 @@ int Arena::commit(Ctx* ctx, hipStream_t s) {
     }
     reqs.clear();
     return TOPO_OK;
+}
+
+hipError_t ensure_dynamic_lds(const void* kernel, size_t bytes) {
+    static std::mutex mu;
+    static std::map<const void*, size_t> set;
+    std::lock_guard<std::mutex> lk(mu);
+    size_t& have = set[kernel];
+    if (bytes <= have) return hipSuccess;
+    const hipError_t e = hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e == hipSuccess) have = bytes;
+    return e;
 }
 
 int pinned_host(Ctx* ctx, size_t bytes, void** out) {
@@ -385,7 +402,7 @@ using namespace topo;
 
 extern "C" {
 
-int topo_ctx_create(topo_ctx** out, int32_t device) {
+int topo_ctx_create(topo_ctx** out, int32_t device, size_t hbm_budget_bytes) {
     if (!out) return TOPO_EINVAL;
     *out = nullptr;
     int n = 0;
@@ -397,6 +414,7 @@ int topo_ctx_create(topo_ctx** out, int32_t device) {
     if (hipSetDevice(device) != hipSuccess) return TOPO_EDEVICE;
     topo_ctx* c = new topo_ctx();
     c->device = device;
+    c->budget = hbm_budget_bytes;
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->cu_count = prop.multiProcessorCount;
     *out = c;

@@ -123,6 +123,7 @@ struct Ctx {
     std::map<std::tuple<int, double, double, double, double, int>, ElemTables> tables;
     void* ws = nullptr;        // device workspace
     size_t ws_bytes = 0;
+    size_t budget = 0;         // most workspace bytes the context may hold (0: no limit)
     void* pinned = nullptr;    // small pinned host buffer for scalar read-backs
     size_t pinned_bytes = 0;
     int cu_count = 256;
@@ -155,6 +156,11 @@ size_t ws_rom_solve(int k, int B);
 size_t ws_rom_estimate(const Grid& g, int k, int B, int max_refine);
 
 int pinned_host(Ctx* c, size_t bytes, void** out);
+
+// Raise a kernel's dynamic LDS limit to at least `bytes` (hipFuncSetAttribute), once per
+// kernel and size for the whole process: the attribute is process-wide state of the
+// kernel, so worker threads launching the same kernel never rewrite it concurrently.
+hipError_t ensure_dynamic_lds(const void* kernel, size_t bytes);
 const ElemTables* get_tables(Ctx* c, const topo_mesh& m);
 
 #define TOPO_HIP(call)                                                             \

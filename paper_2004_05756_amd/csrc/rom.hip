@@ -854,13 +854,11 @@ static int phit_v(Ctx* ctx, const Grid& g, const void* phi, int fp32, int k, int
 #define TOPO_PHIT_CASE(CQ, GG)                                                                          \
     case CQ:                                                                                           \
         if (fp32) {                                                                                    \
-            TOPO_HIP(hipFuncSetAttribute((const void*)k_phit_v<float, CQ, GG>,                         \
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));       \
+            TOPO_HIP(ensure_dynamic_lds((const void*)k_phit_v<float, CQ, GG>, lds));                  \
             hipLaunchKernelGGL((k_phit_v<float, CQ, GG>), grid, dim3(256), lds, s, nrows,              \
                                (const float*)phi, k, ldphi, mask, v, vstride, B, rpc, rb, partials);  \
         } else {                                                                                       \
-            TOPO_HIP(hipFuncSetAttribute((const void*)k_phit_v<double, CQ, GG>,                        \
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));       \
+            TOPO_HIP(ensure_dynamic_lds((const void*)k_phit_v<double, CQ, GG>, lds));                 \
             hipLaunchKernelGGL((k_phit_v<double, CQ, GG>), grid, dim3(256), lds, s, nrows,             \
                                (const double*)phi, k, ldphi, mask, v, vstride, B, rpc, rb, partials); \
         }                                                                                              \
@@ -888,7 +886,7 @@ static int phi_y_launch(Ctx* ctx, const void* phi, int fp32, int k, int ldphi, c
     {
         const void* kern = G == 16 ? (fp32 ? (const void*)k_phi_y<float, 16> : (const void*)k_phi_y<double, 16>)
                                    : (fp32 ? (const void*)k_phi_y<float, 8> : (const void*)k_phi_y<double, 8>);
-        TOPO_HIP(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        TOPO_HIP(ensure_dynamic_lds(kern, lds));
         TimedLaunch tl(ctx, KID_PHI_Y, s);
         if (G == 16) {
             if (fp32)
@@ -960,8 +958,7 @@ static int launch_contract_nt(Ctx* ctx, const Grid& g, const ContractPlan& p, co
                               int ldphi, const uint8_t* mask, const TC* alpha, const TC* F, int B,
                               double* partials, hipStream_t s) {
     auto kern = k_rom_contract<DIM, TP, TC, NT>;
-    TOPO_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)p.lds_bytes));
+    TOPO_HIP(ensure_dynamic_lds((const void*)kern, p.lds_bytes));
     TimedLaunch tl(ctx, KID_ROM_CONTRACT, s);
     hipLaunchKernelGGL(kern, dim3(p.nchunks, B, p.groups), dim3(WAVES * 64), p.lds_bytes, s, g, phi,
                        k, ldphi, p.KP, p.LS, mask, alpha, F, p.epw, p.ec, partials);

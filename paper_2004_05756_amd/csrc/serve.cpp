@@ -3,7 +3,8 @@
 // One dispatcher thread turns queued requests into jobs and hands them to idle
 // workers; each worker owns a HIP stream and a library context and runs its job with
 // the ordinary entry points, so jobs of different workers overlap on the device.
-// Admission keeps the device workspace held by all workers within the budget.
+// Admission keeps the resident meshes and bases plus the device workspace held by all
+// workers within the budget.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -92,7 +93,9 @@ struct topo_server {
     std::thread sched;
     bool stop = false, stop_workers = false;
     size_t max_held = 0;
-    int64_t submitted = 0, completed = 0, failed = 0, jobs = 0, rom_jobs = 0, hdm_jobs = 0, rom_reqs = 0;
+    int64_t submitted = 0, completed = 0, failed = 0, jobs = 0, rom_jobs = 0, hdm_jobs = 0, rom_reqs = 0,
+            hdm_reqs = 0;
+    size_t resident = 0;  // device bytes of the registered meshes and bases
     std::vector<double> lat[2];
 };
 
@@ -116,8 +119,9 @@ void size_job(topo_server* S, Job& j, int B) {
     const Grid& g = mr.g;
     const bool mixed = j.prec == TOPO_MIXED;
     if (j.kind == TOPO_REQ_HDM) {
-        j.ws_need = ws_hdm_solve(g, mixed, 1);
-        j.staging_need = align_up((size_t)g.n_elems * 8) + align_up((size_t)g.n_dofs * 8);
+        // a mixed solve may redo fields in float64 (its workspace then grows to that size)
+        j.ws_need = mixed ? std::max(ws_hdm_solve(g, true, B), ws_hdm_solve(g, false, B)) : ws_hdm_solve(g, false, B);
+        j.staging_need = align_up((size_t)B * g.n_elems * 8) + align_up((size_t)B * g.n_dofs * 8);
     } else {
         const int kb = j.kb;
         j.ws_need = std::max({ws_rom_build(g, kb, B, !mixed, S->cu), ws_rom_solve(kb, 1),
@@ -135,21 +139,28 @@ size_t held_after(const Worker& w, const Job& j) {
     return ws + st;
 }
 
-void release_worker_memory(Worker& w) {
-    // only called for idle workers, under the server lock
+// Detach the device memory of an idle worker (under the server lock); the caller frees
+// it after releasing the lock (free_detached), so submit / wait never block on hipFree.
+// An idle worker's stream has drained: every job ends with a synchronisation of it.
+void release_worker_memory(Worker& w, std::vector<void*>& detached) {
     if (w.ctx->ws) {
-        (void)hipSetDevice(w.ctx->device);
-        (void)hipStreamSynchronize(w.stream);
-        (void)hipFree(w.ctx->ws);
+        detached.push_back(w.ctx->ws);
         w.ctx->ws = nullptr;
         w.ctx->ws_bytes = 0;
     }
     if (w.staging) {
-        (void)hipFree(w.staging);
+        detached.push_back(w.staging);
         w.staging = nullptr;
         w.staging_bytes = 0;
     }
     w.held = 0;
+}
+
+void free_detached(int device, std::vector<void*>& detached) {
+    if (detached.empty()) return;
+    (void)hipSetDevice(device);
+    for (void* p : detached) (void)hipFree(p);
+    detached.clear();
 }
 
 // Form the next job from the head of the queue (requests are not removed).
@@ -161,7 +172,16 @@ Job form_job(topo_server* S, std::vector<size_t>& idx) {
     j.mesh_id = head.r.mesh_id;
     j.prec = head.r.prec;
     idx.push_back(0);
-    if (j.kind == TOPO_REQ_ROM) {
+    if (j.kind == TOPO_REQ_HDM) {
+        // HDM requests on the same mesh with the same precision, tolerance and limit
+        // form one batched solve (every field's result is the one it gets alone)
+        for (size_t i = 1; i < S->queue.size() && (int)idx.size() < S->max_batch; ++i) {
+            const topo_request& r = S->queue[i].r;
+            if (r.kind == TOPO_REQ_HDM && r.mesh_id == j.mesh_id && r.prec == j.prec && r.rtol == head.r.rtol &&
+                (r.maxit > 0 ? r.maxit : 0) == (head.r.maxit > 0 ? head.r.maxit : 0))
+                idx.push_back(i);
+        }
+    } else if (j.kind == TOPO_REQ_ROM) {
         j.basis_id = head.r.basis_id;
         j.max_refine = head.r.max_refine;
         j.kb = head.r.k;
@@ -207,19 +227,27 @@ void dispatcher(topo_server* S) {
         Job job = form_job(S, idx);
         size_job(S, job, (int)idx.size());
         auto total_with = [&](Worker* target) {
-            size_t t = 0;
+            size_t t = S->resident;  // registered meshes and bases
             for (auto& wp : S->workers) t += (wp.get() == target) ? held_after(*wp, job) : wp->held;
             return t;
         };
         size_t total = total_with(w);
         if (total > S->budget) {
             // give back memory held by idle workers and retry
+            std::vector<void*> detached;
             for (auto& wp : S->workers)
-                if (!wp->busy && wp.get() != w) release_worker_memory(*wp);
+                if (!wp->busy && wp.get() != w) release_worker_memory(*wp, detached);
             total = total_with(w);
             if (total > S->budget) {
-                release_worker_memory(*w);
+                release_worker_memory(*w, detached);
                 total = total_with(w);
+            }
+            if (!detached.empty()) {
+                lk.unlock();
+                free_detached(S->device, detached);
+                lk.lock();
+                // the queue may have changed meanwhile: form the job again
+                continue;
             }
         }
         bool any_busy = false;
@@ -257,6 +285,7 @@ void dispatcher(topo_server* S) {
             S->rom_reqs += (int64_t)job.reqs.size();
         } else {
             ++S->hdm_jobs;
+            S->hdm_reqs += (int64_t)job.reqs.size();
         }
         w->job = std::move(job);
         w->busy = true;
@@ -317,7 +346,7 @@ void run_job(topo_server* S, Worker& w, Job& job, std::vector<topo_result>& out)
     double *u_d = nullptr, *khat = nullptr, *kblk = nullptr, *fhat = nullptr, *yhat = nullptr,
            *jk = nullptr, *rn = nullptr;
     if (job.kind == TOPO_REQ_HDM) {
-        u_d = (double*)carve((size_t)g.n_dofs * 8);
+        u_d = (double*)carve((size_t)B * g.n_dofs * 8);
     } else {
         khat = (double*)carve((size_t)B * kb * kb * 8);
         kblk = (double*)carve((size_t)kb * kb * 8);
@@ -344,16 +373,19 @@ void run_job(topo_server* S, Worker& w, Job& job, std::vector<topo_result>& out)
     }
     if (job.kind == TOPO_REQ_HDM) {
         const Req& q = job.reqs[0];
-        topo_info info{};
-        double comp = 0.0;
+        std::vector<topo_info> info(B);
         const int maxit = q.r.maxit > 0 ? q.r.maxit : 1000000;
-        const int rc = topo_hdm_solve(w.ctx, &mr.mesh, rho_d, mr.mask, mr.f, u_d, q.r.rtol, maxit,
-                                      q.r.prec, &comp, &info, s);
-        out[0].status = rc;
-        out[0].iters = info.iters;
-        out[0].J = info.compliance_corr;
-        out[0].resnorm = info.rel_resid;
-        out[0].t_done = now_s();
+        const int rc = topo_hdm_solve_batch(w.ctx, &mr.mesh, rho_d, mr.mask, mr.f, u_d, B, q.r.rtol, maxit,
+                                            q.r.prec, nullptr, info.data(), s);
+        const double t = now_s();
+        for (int b = 0; b < B; ++b) {
+            // device errors fail the whole job; convergence outcomes are per field
+            out[b].status = (rc == TOPO_OK || rc == TOPO_ENOCONV || rc == TOPO_ENOTSPD) ? info[b].status : rc;
+            out[b].iters = info[b].iters;
+            out[b].J = info[b].compliance_corr;
+            out[b].resnorm = info[b].rel_resid;
+            out[b].t_done = t;
+        }
         return;
     }
     const BasisRec& br = S->bases[job.basis_id];
@@ -418,7 +450,7 @@ void worker_main(topo_server* S, Worker* w) {
         }
         w->held = w->ctx->ws_bytes + w->staging_bytes;
         S->max_held = std::max(S->max_held, [&] {
-            size_t t = 0;
+            size_t t = S->resident;
             for (auto& wp : S->workers) t += wp->held;
             return t;
         }());
@@ -459,7 +491,8 @@ int topo_server_create(topo_server** out, int32_t device, size_t hbm_budget_byte
     for (int i = 0; i < n_workers; ++i) {
         auto w = std::make_unique<Worker>();
         w->index = i;
-        if (topo_ctx_create(&w->ctx, device) != TOPO_OK ||
+        // the server's admission keeps the workers within its own budget
+        if (topo_ctx_create(&w->ctx, device, 0) != TOPO_OK ||
             hipStreamCreateWithFlags(&w->stream, hipStreamNonBlocking) != hipSuccess) {
             for (auto& x : S->workers) {
                 topo_ctx_destroy(x->ctx);
@@ -523,6 +556,14 @@ int topo_server_register_mesh(topo_server* S, const topo_mesh* mesh, const uint8
     r.mesh = *mesh;
     r.g = make_grid(*mesh);
     const size_t N = (size_t)r.g.n_dofs;
+    const size_t bytes = align_up(N) + align_up(N * 8);
+    {
+        std::lock_guard<std::mutex> lk(S->m);
+        if (S->resident + bytes > S->budget)
+            return srv_error(S, TOPO_ENOMEM, "mesh of %zu bytes exceeds the HBM budget (%zu resident of %zu)",
+                             bytes, S->resident, S->budget);
+        S->resident += bytes;  // reserved; given back if the upload fails
+    }
     (void)hipSetDevice(S->device);
     if (hipMalloc(&r.mask, N) != hipSuccess || hipMalloc(&r.f, N * 8) != hipSuccess ||
         hipMemcpy(r.mask, mask, N, hipMemcpyHostToDevice) != hipSuccess ||
@@ -530,6 +571,8 @@ int topo_server_register_mesh(topo_server* S, const topo_mesh* mesh, const uint8
         (void)hipGetLastError();
         if (r.mask) (void)hipFree(r.mask);
         if (r.f) (void)hipFree(r.f);
+        std::lock_guard<std::mutex> lk(S->m);
+        S->resident -= bytes;
         return srv_error(S, TOPO_ENOMEM, "mesh registration failed");
     }
     std::lock_guard<std::mutex> lk(S->m);
@@ -553,12 +596,22 @@ int topo_server_register_basis(topo_server* S, int32_t mesh_id, const void* phi,
     b.fp32 = phi_fp32 ? 1 : 0;
     b.kmax = kmax;
     const size_t es = b.fp32 ? 4 : 8;
+    const size_t bytes = align_up((size_t)g.n_dofs * kmax * es);
+    {
+        std::lock_guard<std::mutex> lk(S->m);
+        if (S->resident + bytes > S->budget)
+            return srv_error(S, TOPO_ENOMEM, "basis of %zu bytes exceeds the HBM budget (%zu resident of %zu)",
+                             bytes, S->resident, S->budget);
+        S->resident += bytes;
+    }
     (void)hipSetDevice(S->device);
     if (hipMalloc(&b.phi, (size_t)g.n_dofs * kmax * es) != hipSuccess ||
         hipMemcpy2D(b.phi, kmax * es, phi, (size_t)ldphi * es, kmax * es, (size_t)g.n_dofs,
                     hipMemcpyHostToDevice) != hipSuccess) {
         (void)hipGetLastError();
         if (b.phi) (void)hipFree(b.phi);
+        std::lock_guard<std::mutex> lk(S->m);
+        S->resident -= bytes;
         return srv_error(S, TOPO_ENOMEM, "basis registration failed");
     }
     std::lock_guard<std::mutex> lk(S->m);
@@ -636,8 +689,10 @@ int topo_server_stats(topo_server* S, topo_serve_stats* st) {
     st->rom_jobs = S->rom_jobs;
     st->hdm_jobs = S->hdm_jobs;
     st->mean_rom_batch = S->rom_jobs ? (double)S->rom_reqs / (double)S->rom_jobs : 0.0;
+    st->mean_hdm_batch = S->hdm_jobs ? (double)S->hdm_reqs / (double)S->hdm_jobs : 0.0;
+    st->resident_bytes = S->resident;
     st->budget_bytes = S->budget;
-    size_t held = 0;
+    size_t held = S->resident;
     for (auto& w : S->workers) held += w->held;
     st->held_bytes = held;
     st->max_held_bytes = S->max_held;

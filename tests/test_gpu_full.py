@@ -34,6 +34,11 @@ def test_config_mbb_60x20_recipe():
     u, info = ctx().hdm_solve(m, r, mk, f, rtol=1e-10, prec=FP64)
     assert abs(info["compliance_corr"] / co - 1) <= 1e-10
     assert rel(host(ctx().hdm_gradient(m, r, u)), go) <= 1e-8
+    # the FP64 sensitivity bar (1e-10) at the tolerance it needs (float64 defines it to
+    # 6e-11 on this workload, see the oracle's definition-limit test)
+    u, info = ctx().hdm_solve(m, r, mk, f, rtol=1e-12, prec=FP64)
+    eg = rel(host(ctx().hdm_gradient(m, r, u)), go)
+    assert info["status"] == 0 and eg <= 1e-10, eg
     ev = O.rom_eval(m, rho, phi, p.mask, p.f)
     for prec in (FP64, MIXED):
         Kh, fh = ctx().rom_build(m, dev(phi), 8, mk, f, r.view(1, -1), prec=prec)
@@ -54,15 +59,17 @@ def test_config_cantilever_600x200_full():
     uo = O.solve_direct(m, rho, p.f, p.mask)
     co = O.compliance(p.f, uo)
     go = O.sensitivity(m, rho, uo)
-    # FP64 gate 1e-9, not 1e-10: on this mesh (density contrast 8000, displacements
-    # ~1e3) the compliance moves by 6.4e-10 when the oracle's own K_e is projected onto
-    # exact translation invariance (a 1e-16 change of its entries), so neither side can
-    # define it more tightly in float64.
-    for prec, tc, tg in ((MIXED, 1e-8, 1e-6), (FP64, 1e-9, 1e-8)):
-        u, info = ctx().hdm_solve(m, r, mk, f, rtol=1e-10, prec=prec)
-        assert info["status"] == 0 and info["rel_resid"] <= 1e-10
-        assert abs(info["compliance_corr"] / co - 1) <= tc
-        assert rel(host(ctx().hdm_gradient(m, r, u)), go) <= tg
+    # FP64 gates 2e-9 (compliance) and 3e-10 (sensitivity), not 1e-10: on this mesh
+    # (density contrast 8000) one rounding of the element matrix moves the compliance by
+    # 1.06e-9 and the sensitivity by 1.35e-10, so no float64 evaluation defines them more
+    # tightly (pinned on the CPU by the oracle's definition-limit test); the gates are
+    # twice those moves, at a solve tolerance (1e-11) below them.
+    for prec, rtol, tc, tg in ((MIXED, 1e-10, 1e-8, 1e-6), (FP64, 1e-11, 2e-9, 3e-10)):
+        u, info = ctx().hdm_solve(m, r, mk, f, rtol=rtol, prec=prec)
+        assert info["status"] == 0 and info["rel_resid"] <= rtol
+        ec = abs(info["compliance_corr"] / co - 1)
+        eg = rel(host(ctx().hdm_gradient(m, r, u)), go)
+        assert ec <= tc and eg <= tg, (prec, ec, eg)
     phi = W.cosine_basis(m, p.mask, cfg.k, cfg.basis_seed, np.float32)
     ev = O.rom_eval(m, rho, phi, p.mask, p.f)
     Kh, fh = ctx().rom_build(m, dev(phi), cfg.k, mk, f, r.view(1, -1), prec=MIXED)
@@ -101,6 +108,92 @@ def test_config_cantilever3d_96x48x48_full():
     ref = P.T @ (K @ P)  # the oracle's assembled-matrix projection, K assembled once
     assert rel(host(Kh)[0], ref) <= 1e-6
     assert rel(host(fh), O.rom_load(phi, p.mask, p.f)) <= 1e-13
+
+
+def test_config_cantilever3d_96x48x48_golden():
+    """698,691 DOF against stored oracle values (tests/golden/make_golden.py: the
+    compliance certified by the oracle's CG on the assembled matrix, with its bracket,
+    and the k = 100 Galerkin J_k and ||r|| from the assembled Phi^T (K Phi)): FP64
+    compliance 1e-10 and mixed 1e-8; J_k and ||r|| of both ROM paths."""
+    import json
+    import os
+    from paper_2004_05756_amd import FP64, MIXED
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                           "cantilever3d_96x48x48.json")) as fh:
+        gold = json.load(fh)
+    cfg = W.config("cantilever3d_96x48x48")
+    p, m = cfg.problem, cfg.problem.mesh
+    assert gold["rho_seed"] == cfg.rho_seed0 and gold["k"] == cfg.k and gold["basis_seed"] == cfg.basis_seed
+    rho = cfg.rho(0)
+    r, mk, f = _tensors(p, rho)
+    c = gold["compliance_corr"]
+    slack = gold["bracket"] / c  # c* lies in [c~, c~ + bracket]
+    for prec, tol in ((FP64, 1e-10), (MIXED, 1e-8)):
+        u, info = ctx().hdm_solve(m, r, mk, f, rtol=1e-10, prec=prec)
+        e = abs(info["compliance_corr"] / c - 1)
+        assert info["status"] == 0 and e <= tol + slack, (prec, e, slack)
+    phi = W.cosine_basis(m, p.mask, cfg.k, cfg.basis_seed, np.float32)
+    for prec, refine in ((FP64, 0), (MIXED, 2)):
+        Kh, fh = ctx().rom_build(m, dev(phi), cfg.k, mk, f, r.view(1, -1), prec=prec)
+        y, _ = ctx().rom_solve(Kh, fh)
+        y, J, rn = ctx().rom_estimate(m, dev(phi), cfg.k, mk, f, r.view(1, -1), Kh, y, max_refine=refine)
+        eJ = abs(host(J)[0] / gold["Jk"] - 1)
+        er = abs(host(rn)[0] / gold["resnorm"] - 1)
+        assert eJ <= 1e-8 and er <= 1e-8, (prec, eJ, er)
+
+
+def test_config_bridge3d_192x96x96_batched_full():
+    """The benchmark's step at full size: 16 trust-region candidate fields on the
+    192x96x96 bridge solved in one batched mixed-precision call to rel. residual 1e-8.
+    Every field's true residual recomputed by the oracle element by element in FP64;
+    field 0's sensitivity against the oracle's at the same state; the k = 200, B = 16
+    contraction on three columns of K_hat against the oracle's products K Phi_j; and
+    ROM exactness at full size: with field 0's state in the basis, J_k = c~ (the
+    Galerkin solution in a span containing u is at least as good: c~ <= J_k <= c*)."""
+    torch = torch_cuda()
+    from paper_2004_05756_amd import FP64, MIXED
+    cfg = W.config("bridge3d_192x96x96")
+    p, m = cfg.problem, cfg.problem.mesh
+    B, k = cfg.batch, cfg.k
+    centre = cfg.rho(0)
+    rhos = W.trust_region_fields(m, centre, B, cfg.rho_seed0 + 100, step=0.1)
+    R = dev(rhos, torch.float64)
+    mk, f = dev(p.mask, torch.uint8), dev(p.f, torch.float64)
+    print("bridge batched solve", flush=True)
+    u, infos = ctx().hdm_solve_batch(m, R, mk, f, rtol=cfg.rtol, prec=MIXED)
+    free = p.mask == 0
+    nf = np.linalg.norm(np.where(free, p.f, 0.0))
+    for b in range(B):
+        assert infos[b]["status"] == 0
+        ub = host(u[b])
+        res = np.linalg.norm(np.where(free, p.f - O.apply_ebe(m, rhos[b], p.mask, ub), 0.0)) / nf
+        assert res <= cfg.rtol * 1.01, (b, res)
+    u0 = host(u[0])
+    g = host(ctx().hdm_gradient_batch(m, R, u))[0]
+    assert rel(g, O.sensitivity(m, rhos[0], u0)) <= 1e-12
+    print("bridge contraction", flush=True)
+    phi = W.cosine_basis(m, p.mask, k, cfg.basis_seed, np.float32)
+    Kh, _ = ctx().rom_build(m, dev(phi), k, mk, f, R, prec=MIXED)
+    Kh0 = host(Kh[0])
+    for j in (0, k // 2, k - 1):
+        pj = np.where(free, phi[:, j].astype(np.float64), 0.0)
+        kp = O.apply_ebe(m, rhos[0], p.mask, pj)
+        ch = 1 << 20
+        kcol = sum(phi[i:i + ch].astype(np.float64).T @ kp[i:i + ch] for i in range(0, m.n_dofs, ch))
+        assert np.abs(Kh0[:, j] - kcol).max() <= 2e-6 * np.abs(kcol).max(), j
+    del Kh
+    # exactness: field 0's state as the first basis column
+    print("bridge exactness", flush=True)
+    phi_x = phi.copy()
+    phi_x[:, 0] = (u0 / np.abs(u0).max()).astype(np.float32)
+    c0 = infos[0]["compliance_corr"]
+    for prec, refine, tol in ((FP64, 0, 1e-10), (MIXED, 2, 1e-8)):
+        Kh, fh = ctx().rom_build(m, dev(phi_x), k, mk, f, R[:1], prec=prec)
+        y, _ = ctx().rom_solve(Kh, fh)
+        y, J, rn = ctx().rom_estimate(m, dev(phi_x), k, mk, f, R[:1], Kh, y, max_refine=refine)
+        # the basis holds the float32 rounding of u, which changes the best energy in
+        # the span only to second order (~(6e-8)^2)
+        assert abs(host(J)[0] / c0 - 1) <= tol, (prec, host(J)[0], c0)
 
 
 def test_config_bridge3d_192x96x96_sampled():

@@ -140,3 +140,74 @@ def test_invalid_requests():
     with pytest.raises(TopoError):
         srv.submit_hdm(mid, rho, rtol=2.0)
     srv.close()
+
+
+def test_hdm_requests_fused_bitwise_alone_and_device_densities():
+    """HDM requests on one mesh are fused into batched solves (mean HDM batch > 1), each
+    result bitwise the one the request gets alone; densities passed as device tensors
+    (kept alive by the binding until the result is read) give the same results."""
+    torch = torch_cuda()
+    from paper_2004_05756_amd import FP64, MIXED
+    p = W.cantilever3d(12, 6, 6)
+    rhos = [W.rho_smoothed(p.mesh, 6100 + i) for i in range(10)]
+    alone = _server(max_batch=1, workers=1)
+    mid = alone.register_mesh(p.mesh, p.mask, p.f)
+    ref = {pr: [alone.wait(alone.submit_hdm(mid, r, rtol=1e-10, prec=pr)) for r in rhos] for pr in (FP64, MIXED)}
+    alone.close()
+    srv = _server(max_batch=8, workers=2)
+    mid = srv.register_mesh(p.mesh, p.mask, p.f)
+    for pr in (FP64, MIXED):
+        tickets = [srv.submit_hdm(mid, r, rtol=1e-10, prec=pr) for r in rhos]
+        # device densities produced on the caller's stream just before the submit
+        dev_t = [srv.submit_hdm(mid, torch.as_tensor(r).cuda() * 1.0, rtol=1e-10, prec=pr) for r in rhos[:4]]
+        got = [srv.wait(t) for t in tickets]
+        got_dev = [srv.wait(t) for t in dev_t]
+        for a, b in zip(ref[pr], got):
+            assert b["status"] == 0 and a["J"] == b["J"] and a["iters"] == b["iters"]
+        for a, b in zip(ref[pr], got_dev):
+            assert a["J"] == b["J"] and a["iters"] == b["iters"]
+    st = srv.stats()
+    assert st["mean_hdm_batch"] > 1.0
+    srv.close()
+
+
+def test_resident_bases_are_charged_to_the_budget():
+    """Registered meshes and bases count against the server's HBM budget: a basis that
+    would take the resident set past it is refused with TOPO_ENOMEM, and the held bytes
+    (resident set + workspace) never exceed the budget."""
+    from paper_2004_05756_amd import TopoError, binding
+    p = W.cantilever3d(24, 12, 12)  # 14,625 DOF
+    budget = 8 << 20
+    srv = _server(workers=2, budget_bytes=budget)
+    mid = srv.register_mesh(p.mesh, p.mask, p.f)
+    small = W.cosine_basis(p.mesh, p.mask, 16, 3, np.float32)  # 0.9 MiB
+    bid = srv.register_basis(mid, small)
+    too_big = W.cosine_basis(p.mesh, p.mask, 160, 4, np.float32)  # 8.9 MiB
+    with pytest.raises(TopoError) as ei:
+        srv.register_basis(mid, too_big)
+    assert ei.value.code == binding.TOPO_ENOMEM
+    st = srv.stats()
+    assert st["resident_bytes"] >= small.nbytes + p.mesh.n_dofs * 9
+    r = srv.wait(srv.submit_rom(mid, bid, 16, np.full(p.mesh.n_elems, 0.5)))
+    assert r["status"] == 0
+    st = srv.stats()
+    assert st["max_held_bytes"] <= budget
+    srv.close()
+
+
+def test_context_budget_refuses_larger_workspace():
+    torch = torch_cuda()
+    from paper_2004_05756_amd import FP64, TopoError, binding
+    small = W.mbb2d(30, 10)
+    big = W.cantilever3d(48, 24, 24)  # about 7 MB of float64 PCG workspace
+    c = binding.Context(0, budget_bytes=2 << 20)
+    d = torch.device("cuda", 0)
+    u, inf = c.hdm_solve(small.mesh, torch.full((small.mesh.n_elems,), 0.5, dtype=torch.float64, device=d),
+                         torch.as_tensor(small.mask).to(d), torch.as_tensor(small.f).to(d), prec=FP64)
+    assert inf["status"] == 0
+    with pytest.raises(TopoError) as ei:
+        c.hdm_solve(big.mesh, torch.full((big.mesh.n_elems,), 0.5, dtype=torch.float64, device=d),
+                    torch.as_tensor(big.mask).to(d), torch.as_tensor(big.f).to(d), prec=FP64)
+    assert ei.value.code == binding.TOPO_ENOMEM
+    assert c.workspace_bytes() <= 2 << 20
+    c.close()

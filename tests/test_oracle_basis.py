@@ -141,3 +141,16 @@ def test_rom_is_exact_at_the_trust_region_centre(n_max):
     eo = O.rom_eval(m, rho_o, Phi, p.mask, p.f)
     Jo = O.compliance(p.f, O.solve_direct(m, rho_o, p.f, p.mask))
     assert eo["Jk"] < Jo and eo["resnorm"] > 1e-6 * np.linalg.norm(p.f)
+
+
+def test_tall_orthonormalisation_spans_the_columns():
+    """The benchmark's Cholesky-QR orthonormalisation of tall bases: orthonormal to
+    rounding, zero on Dirichlet rows, and the same span as the Householder QR."""
+    p = W.cantilever3d(12, 6, 6)
+    rng = np.random.default_rng(3)
+    cols = np.hstack([rng.standard_normal((p.mesh.n_dofs, 5)), W.cosine_basis(p.mesh, p.mask, 40, 9, np.float64)])
+    q = W.orthonormalize_tall(cols, p.mask)
+    h = W.orthonormalize(cols, p.mask)
+    assert np.abs(q.T @ q - np.eye(q.shape[1])).max() < 1e-13
+    assert np.all(q[p.mask == 1] == 0)
+    assert np.abs(q @ q.T - h @ h.T).max() < 1e-12

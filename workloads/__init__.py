@@ -27,6 +27,7 @@ __all__ = [
     "Mesh", "Problem", "mbb2d", "cantilever2d", "cantilever3d", "bridge3d",
     "paper_mbb", "paper_cantilever", "paper_ssbeam",
     "rho_jitter", "rho_smoothed", "rho_batch", "trust_region_fields", "cosine_basis", "orthonormalize",
+    "orthonormalize_tall",
     "config", "CONFIG_NAMES", "SERVING_MESHES", "ServingRequest", "serving_stream", "poisson_arrivals",
 ]
 
@@ -333,6 +334,20 @@ def orthonormalize(cols: np.ndarray, mask: np.ndarray, dtype=np.float64):
     a[mask.astype(bool), :] = 0.0
     q, _ = np.linalg.qr(a)
     return q.astype(dtype)
+
+
+def orthonormalize_tall(cols: np.ndarray, mask: np.ndarray, dtype=np.float64, passes: int = 2):
+    """Orthonormal basis of tall columns (rows >> columns) by Cholesky QR repeated
+    `passes` times in float64 (Gram matrix, its Cholesky factor, a triangular solve):
+    the same span as orthonormalize, an order of magnitude faster for millions of rows
+    (the Gram matrix of well-conditioned columns loses nothing in the second pass)."""
+    import scipy.linalg as sla
+    a = np.array(cols, dtype=np.float64, copy=True)
+    a[mask.astype(bool), :] = 0.0
+    for _ in range(passes):
+        L = np.linalg.cholesky(a.T @ a)
+        a = np.ascontiguousarray(sla.solve_triangular(L, a.T, lower=True).T)
+    return a.astype(dtype)
 
 
 # ---------------------------------------------------------------------------------
