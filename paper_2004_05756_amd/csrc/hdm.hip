@@ -17,7 +17,6 @@
 #include <cmath>
 #include <cstddef>
 #include <cstdlib>
-#include <initializer_list>
 #include <vector>
 
 #include <hip/hip_ext.h>
@@ -225,8 +224,8 @@ constexpr int kPcgBlock = 512;
 // r = scale * r64 (the float64 true residual, scaled), z = D^{-1} r, x = 0, and the
 // rz / rr partials into the parity the segment's first apply reads.  A fresh start
 // also clears p (its first apply takes beta = 0); a continued one keeps the search
-// direction, so the Krylov progress of the earlier segments is not lost.  Idle fields
-// (done != 0 in the uploaded state) are skipped.
+// direction, so the Krylov progress of the earlier segments is not lost.  Only fields
+// with a nonzero scale fsc[b] start a segment; the others are left as they are.
 template <int DIM, typename T>
 __global__ __launch_bounds__(kPcgBlock) void k_pcg_start(Grid g, const double* __restrict__ r64,
                                                       const double* __restrict__ fsc,
@@ -237,7 +236,7 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_start(Grid g, const double* _
                                                       int ps) {
     const int f = blockIdx.y;
     const PcgState* sb = st + f;
-    if (sb->done) return;
+    if (fsc[f] == 0.0) return;  // field not starting a segment now
     __shared__ double lds[32];
     const size_t fo = (size_t)f * g.n_dofs;
     r64 += fo;
@@ -486,14 +485,15 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_update(Grid g, const T* __res
 // field: A[0] = sum of A[0..n), and likewise B when sb >= 0.  Array X sits at slot
 // sx (+ the field's iteration parity when px, that parity being lp ^ poff ^ flip) of
 // the field's partials.  The consumer then reads 1 value instead of every block summing
-// all partials again.  Skipped once the field's recursion is done: its producer did
-// not run then, and summing again would count A[0] twice.
+// all partials again.  Skipped once the field's recursion is done (its producer did
+// not run then, and summing again would count A[0] twice), or, with a gate (the
+// segment starts), for the fields whose gate entry is zero.
 template <typename S>
 __global__ __launch_bounds__(1024) void k_partials_sum(double* __restrict__ part, int ps, int n, int sa,
                                                        int pa, int sb, int pb, const S* st, int lp,
-                                                       int flip) {
+                                                       int flip, const double* gate) {
     const int f = blockIdx.x;
-    if (st[f].done) return;
+    if (gate ? gate[f] == 0.0 : st[f].done != 0) return;
     __shared__ double lds[32];
     const int par = lp ^ st[f].poff ^ flip;
     double* base = part + (size_t)f * kPcgParts * ps;
@@ -761,7 +761,7 @@ __global__ __launch_bounds__(kPcgBlock) void k_cg1_refresh2(Grid g, const T* __r
 // partials of gamma, delta, rr.  A fresh start clears p and s (its first step takes
 // beta = 0); a continued one computes s = K p exactly for the kept direction p and the
 // partials of u.s, p.s, from which its first step takes the conjugate direction.
-// Idle fields are skipped.
+// Only fields with a nonzero scale fsc[b] start a segment.
 template <typename T>
 __global__ __launch_bounds__(kPcgBlock) void k_cg1_start2(
     Grid g, const T* __restrict__ alpha, const T* __restrict__ K, const uint8_t* __restrict__ mask,
@@ -771,7 +771,7 @@ __global__ __launch_bounds__(kPcgBlock) void k_cg1_start2(
     const Cg1State* st, int ps) {
     const FieldBlock fb = field_block();
     const Cg1State* sb = st + fb.field;
-    if (sb->done) return;
+    if (fsc[fb.field] == 0.0) return;  // field not starting a segment now
     __shared__ double lds[80];
     const int cur = sb->it0 & 1;
     const bool fresh = sb->kind0 == kCg1Fresh;
@@ -844,15 +844,15 @@ __global__ __launch_bounds__(kPcgBlock) void k_cg1_start2(
     }
 }
 
-// u_b += s_b * d_b for the fields with s_b != 0 (grid (blocks, B))
+// u_b += s_b * d_b for the fields with s_b != 0 (grid (blocks, B), grid-stride)
 template <typename T>
 __global__ void k_correct(long long n, double* __restrict__ u, const T* __restrict__ d,
                           const double* __restrict__ s) {
     const int f = blockIdx.y;
     const double sf = s[f];
     if (sf == 0.0) return;
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) u[(size_t)f * n + i] += sf * (double)d[(size_t)f * n + i];
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        u[(size_t)f * n + i] += sf * (double)d[(size_t)f * n + i];
 }
 
 // ----------------------------------------------------------------------------------
@@ -1085,7 +1085,7 @@ static void pcg_iteration(Ctx* ctx, const Grid& g, const PcgBufs<T>& w, const Pc
     }
     if (pg.npq == 1 && pg.napp > 1)
         L((const void*)k_partials_sum<PcgState>, dim3(w.B), dim3(1024), w.part, pg.ps, pg.napp, 0, 0, -1, 0,
-          (const PcgState*)w.st, lp, 0);
+          (const PcgState*)w.st, lp, 0, (const double*)nullptr);
     {
         TimedLaunch tl(ctx, KID_PCG_UPDATE, L.s, L.graph ? kTimeOff : timing, true);
         L.ev0 = tl.a;
@@ -1096,7 +1096,7 @@ static void pcg_iteration(Ctx* ctx, const Grid& g, const PcgBufs<T>& w, const Pc
     }
     if (pg.nrz == 1 && pg.nupd > 1)  // rz / rr of the update's own parity
         L((const void*)k_partials_sum<PcgState>, dim3(w.B), dim3(1024), w.part, pg.ps, pg.nupd, 1, 1, 3, 1,
-          (const PcgState*)w.st, lp, 0);
+          (const PcgState*)w.st, lp, 0, (const double*)nullptr);
 }
 
 // One step of the one-reduction recursion at launch parity lp (then s = K p when refresh).
@@ -1112,19 +1112,214 @@ static void cg1_step(Ctx* ctx, const Grid& g, const PcgBufs<T>& w, const PcgGeom
     }
     if (pg.nrz == 1 && pg.nupd > 1) {  // the set the step wrote: its parity ^ 1
         L((const void*)k_partials_sum<Cg1State>, dim3(w.B), dim3(1024), w.part, pg.ps, pg.nupd, 0, 1, 2, 1,
-          (const Cg1State*)w.st1, lp, 1);
+          (const Cg1State*)w.st1, lp, 1, (const double*)nullptr);
         L((const void*)k_partials_sum<Cg1State>, dim3(w.B), dim3(1024), w.part, pg.ps, pg.nupd, 4, 1, -1, 0,
-          (const Cg1State*)w.st1, lp, 1);
+          (const Cg1State*)w.st1, lp, 1, (const double*)nullptr);
     }
     if (refresh)
         L((const void*)k_cg1_refresh2<T>, dim3(pg.nupd, w.B), dim3(kPcgBlock), g, w.alpha, w.K, w.mask,
           (const T*)w.e1, w.p0, w.p1, (const Cg1State*)w.st1, lp);
 }
 
+// ----------------------------------------------------------------------------------
+// Segment control on the device.  A field's recursion runs in segments; when one ends
+// (its state reports done), the end of the 16-iteration chunk in which it ended adds
+// the segment's correction to u in float64, recomputes the true residual f - K u in
+// float64, and either retires the field (converged, iteration limit, stagnation,
+// breakdown) or starts its next segment: continued with the same search direction
+// from the replaced residual, or restarted when the recursion had drifted from the true
+// residual.  Every decision uses the field's own numbers only, and happens at a chunk
+// boundary fixed by the field's own iteration count, so fields in one batch never wait
+// for each other and a field's result does not depend on the batch.
+// ----------------------------------------------------------------------------------
+// Largest ratio of true to recursive residual at the end of a segment for which the
+// recursion is continued after the residual replacement (else it restarts).
+constexpr double kReplaceDriftMax = 4.0;
+// Reduction of the residual a float32 segment aims for before its residual is replaced
+// by the float64 one (small enough to keep the replacements rare, large enough that the
+// float32 recursion has not drifted from the true residual; 3e-3 .. 1e-1 measured
+// within 2 % of each other in iterations).
+constexpr double kMixedSegmentTol = 1e-2;
+constexpr int kMaxSegments = 400;
+
+struct SegCtl {
+    double nf;          // ||f_f|| (the inner system is scaled by 1 / nf)
+    double scale;       // 1 / nf (1 when f = 0)
+    double rr;          // ||f - K u||^2 of the current u
+    double rr_prev;     // the same before the last segment
+    double fin_rr;      // recursive (scaled) ||r||^2 at the end of the last segment
+    double res[3];      // residual sums of the current u: ||r||^2, f^T u, u^T r
+    double last_rz[2];  // r.z of the last two iterations of the last segment
+    int live;           // 1 while the field is being solved
+    int fresh;          // the next segment restarts the recursion
+    int ending;         // the field's segment ended in the chunk just run
+    int stagnated;      // retired because replacements stopped reducing the residual
+    int total, base, segments, status, maxit, seg_iters, fin_done, fin_iters;
+};
+
+__device__ __forceinline__ int st_iters(const PcgState& s) { return s.iters; }
+__device__ __forceinline__ int st_iters(const Cg1State& s) { return s.iters[0] > s.iters[1] ? s.iters[0] : s.iters[1]; }
+__device__ __forceinline__ void st_rz(const PcgState& s, SegCtl& c) {
+    c.last_rz[0] = s.rz[0];
+    c.last_rz[1] = s.rz[1];
+}
+__device__ __forceinline__ void st_rz(const Cg1State&, SegCtl&) {}
+
+// The state of the field's next segment (fresh: x = 0, beta = 0 at its first step;
+// continued: same direction, the stopping test against the replaced residual).
+__device__ __forceinline__ void seg_state(const SegCtl& c, double tol2, PcgState& p) {
+    const int it0 = c.fresh ? 0 : c.fin_iters;
+    p = PcgState{};
+    p.bb = p.rr = c.fresh ? 0.0 : c.rr * c.scale * c.scale;
+    p.tol2 = tol2;
+    p.rz[0] = c.fresh ? 0.0 : c.last_rz[0];
+    p.rz[1] = c.fresh ? 0.0 : c.last_rz[1];
+    p.maxit = c.maxit - c.base;
+    p.iters = it0;
+    p.poff = (it0 & 1) ^ 1;  // the segment's first launch has launch parity 1
+    p.fresh = c.fresh;
+}
+__device__ __forceinline__ void seg_state(const SegCtl& c, double tol2, Cg1State& q) {
+    const int it0 = c.fresh ? 0 : c.fin_iters;
+    q = Cg1State{};
+    q.bb = q.rr = c.fresh ? 0.0 : c.rr * c.scale * c.scale;
+    q.tol2 = tol2;
+    q.maxit = c.maxit - c.base;
+    q.iters[0] = q.iters[1] = it0;
+    q.poff = (it0 & 1) ^ 1;
+    q.kind0 = c.fresh ? kCg1Fresh : kCg1Continued;
+    q.it0 = it0;
+}
+
+// Stopping tests at the current u, then the next segment (fsc[b] = scale) or retirement.
+template <typename S>
+__device__ __forceinline__ void seg_next(SegCtl& c, S& st, double* fsc, int* live, int b, double rtol,
+                                         double seg_min) {
+    const double rel = c.nf > 0.0 ? sqrt(c.rr) / c.nf : 0.0;
+    if (rel <= rtol) {
+        c.live = 0;
+    } else if (c.total >= c.maxit || c.segments >= kMaxSegments) {
+        c.status = TOPO_ENOCONV;
+        c.live = 0;
+    } else if (c.segments > 0 && !(c.rr < 0.5 * c.rr_prev)) {
+        c.status = TOPO_ENOCONV;
+        c.stagnated = 1;
+        c.live = 0;
+    }
+    if (!c.live) {
+        st.done = 4;
+        live[b] = 0;
+        return;
+    }
+    double tol_seg = fmax(0.5 * rtol * c.nf / sqrt(c.rr), seg_min);
+    tol_seg = fmin(fmax(tol_seg, 1e-15), 0.5);
+    if (c.fresh) c.base = c.total;
+    seg_state(c, tol_seg * tol_seg, st);
+    fsc[b] = c.scale;
+}
+
+// After the initial residual (out[4b..4b+2]): every field to solve starts its first,
+// fresh segment (or is done at once when u = 0 already meets the tolerance).
+template <typename S>
+__global__ void k_seg_init(int B, S* __restrict__ st, SegCtl* __restrict__ ctl, const double* __restrict__ out,
+                           double* __restrict__ fsc, int* __restrict__ live, const int* __restrict__ solve,
+                           const int* __restrict__ maxit, double rtol, double seg_min) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    SegCtl c{};
+    fsc[b] = 0.0;
+    live[b] = 0;
+    if (!solve[b]) {
+        st[b].done = 4;
+        ctl[b] = c;
+        return;
+    }
+    for (int q = 0; q < 3; ++q) c.res[q] = out[4 * b + q];
+    c.nf = sqrt(c.res[0]);
+    c.scale = c.nf > 0.0 ? 1.0 / c.nf : 1.0;
+    c.rr = c.res[0];
+    c.rr_prev = INFINITY;
+    c.live = 1;
+    c.fresh = 1;
+    c.maxit = maxit[b];
+    c.status = TOPO_OK;
+    live[b] = 1;
+    seg_next(c, st[b], fsc, live, b, rtol, seg_min);
+    ctl[b] = c;
+}
+
+// End of a chunk, before the correction: the fields whose segment ended in it.  Their
+// correction weight goes to corr[b] (0: none), the residual is recomputed for them only
+// (skip[b] = 0); a breakdown without progress retires the field at once.
+template <typename S>
+__global__ void k_seg_mark(int B, S* __restrict__ st, SegCtl* __restrict__ ctl, int* __restrict__ skip,
+                           double* __restrict__ corr, double* __restrict__ fsc, int* __restrict__ live) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    SegCtl& c = ctl[b];
+    fsc[b] = 0.0;
+    corr[b] = 0.0;
+    skip[b] = 1;
+    c.ending = 0;
+    const int done = st[b].done;
+    if (!c.live || done == 0) return;
+    c.fin_done = done;
+    c.fin_iters = st_iters(st[b]);
+    c.fin_rr = st[b].rr;
+    st_rz(st[b], c);
+    c.seg_iters = c.base + c.fin_iters - c.total;
+    c.total = c.base + c.fin_iters;
+    if (done == 3 && c.seg_iters == 0) {
+        c.status = TOPO_ENOTSPD;
+        c.live = 0;
+        live[b] = 0;
+        st[b].done = 4;
+        return;
+    }
+    c.ending = 1;
+    skip[b] = 0;
+    corr[b] = c.nf > 0.0 ? c.nf : 1.0;
+    ++c.segments;
+    c.rr_prev = c.rr;
+}
+
+// End of a chunk, after the corrected u's residual (out[4b..4b+2]): retire the field or
+// start its next segment.
+template <typename S>
+__global__ void k_seg_control(int B, S* __restrict__ st, SegCtl* __restrict__ ctl, const double* __restrict__ out,
+                              double* __restrict__ fsc, int* __restrict__ live, double rtol, double seg_min) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    SegCtl& c = ctl[b];
+    if (!c.ending) return;
+    c.ending = 0;
+    for (int q = 0; q < 3; ++q) c.res[q] = out[4 * b + q];
+    c.rr = c.res[0];
+    if (c.fin_done == 3 && !(c.rr < c.rr_prev)) {
+        c.status = TOPO_ENOTSPD;
+        c.live = 0;
+        live[b] = 0;
+        st[b].done = 4;
+        return;
+    }
+    // continue the recursion only while it still tracks the true residual; a segment
+    // whose true residual drifted far from the recursive one restarts
+    const double drift = c.fin_rr > 0.0 ? sqrt(c.rr) * c.scale / sqrt(c.fin_rr) : INFINITY;
+    c.fresh = !(drift <= kReplaceDriftMax) || c.fin_done != 1;
+    seg_next(c, st[b], fsc, live, b, rtol, seg_min);
+}
+
+// skip[b] = !solve[b]
+__global__ void k_skip_from_solve(int B, const int* __restrict__ solve, int* __restrict__ skip) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < B) skip[b] = solve[b] ? 0 : 1;
+}
+
 constexpr int kPcgChunk = 16;  // iterations per graph replay (even)
 
-// Start of a phase: every running field's segment starts (state uploaded by the host),
-// its partials are written for the first launch of the phase (launch parity 1).
+// Start of a segment for the fields with a nonzero scale fsc[b] (their states written
+// by the segment controller): its partials for the first launch of the next chunk
+// (launch parity 1).
 template <int DIM, typename T>
 static void phase_start(const Grid& g, const PcgBufs<T>& w, const PcgGeom& pg, bool one_red, LaunchSink& L) {
     if (one_red) {
@@ -1133,116 +1328,29 @@ static void phase_start(const Grid& g, const PcgBufs<T>& w, const PcgGeom& pg, b
           (const Cg1State*)w.st1, pg.ps);
         if (pg.nrz == 1 && pg.nupd > 1) {  // set it0 & 1, the first step's parity
             L((const void*)k_partials_sum<Cg1State>, dim3(w.B), dim3(1024), w.part, pg.ps, pg.nupd, 0, 1, 2, 1,
-              (const Cg1State*)w.st1, 1, 0);
+              (const Cg1State*)w.st1, 1, 0, w.fsc);
             L((const void*)k_partials_sum<Cg1State>, dim3(w.B), dim3(1024), w.part, pg.ps, pg.nupd, 4, 1, 6, 0,
-              (const Cg1State*)w.st1, 1, 0);
+              (const Cg1State*)w.st1, 1, 0, w.fsc);
             L((const void*)k_partials_sum<Cg1State>, dim3(w.B), dim3(1024), w.part, pg.ps, pg.nupd, 7, 0, -1, 0,
-              (const Cg1State*)w.st1, 1, 0);
+              (const Cg1State*)w.st1, 1, 0, w.fsc);
         }
     } else {
         L((const void*)k_pcg_start<DIM, T>, dim3(pg.nupd, w.B), dim3(kPcgBlock), g, w.r64, w.fsc, w.winv,
           w.ik[0], w.ik[1], w.ik[2], w.x, w.r, w.z, w.p0, w.part, (const PcgState*)w.st, pg.ps);
         if (pg.nrz == 1 && pg.nupd > 1)  // the parity the first apply reads: its own ^ 1
             L((const void*)k_partials_sum<PcgState>, dim3(w.B), dim3(1024), w.part, pg.ps, pg.nupd, 1, 1, 3, 1,
-              (const PcgState*)w.st, 1, 1);
+              (const PcgState*)w.st, 1, 1, w.fsc);
     }
 }
 
-// Iteration `it` of a phase (its launch parity is it & 1; a phase starts at it = 1).
-// The one-reduction recursion refreshes s after every iteration it with it % kPcgChunk
-// == 0, which is where every graph replay ends, so that graph and direct launches take
-// the same steps.
+// Iteration `it` of a chunk sequence (its launch parity is it & 1; chunks of kPcgChunk
+// iterations start at it = 1 mod kPcgChunk).  The one-reduction recursion refreshes s
+// after every iteration it with it % kPcgChunk == 0, the last of each chunk.
 template <int DIM, typename T>
 static void phase_iteration(Ctx* ctx, const Grid& g, const PcgBufs<T>& w, const PcgGeom& pg, bool one_red,
                             long long it, LaunchSink& L, int timing) {
     if (one_red) cg1_step<T>(ctx, g, w, pg, (int)(it & 1), L, timing, it % kPcgChunk == 0);
     else pcg_iteration<DIM, T>(ctx, g, w, pg, (int)(it & 1), L, timing);
-}
-
-// Graph of kPcgChunk iterations starting at launch parity 1.
-template <int DIM, typename T>
-static int phase_graph(Ctx* ctx, const Grid& g, const PcgBufs<T>& w, const PcgGeom& pg, bool one_red,
-                       hipGraphExec_t* out, hipStream_t s) {
-    std::vector<uintptr_t> key = {(uintptr_t)0xB7C6, (uintptr_t)DIM, sizeof(T), (uintptr_t)one_red,
-                                  (uintptr_t)w.B, (uintptr_t)pg.napp, (uintptr_t)pg.nupd, (uintptr_t)kPcgChunk,
-                                  (uintptr_t)g.nx, (uintptr_t)g.ny, (uintptr_t)g.nz, (uintptr_t)g.mtarget,
-                                  (uintptr_t)w.alpha, (uintptr_t)w.K, (uintptr_t)w.mask, (uintptr_t)w.winv,
-                                  (uintptr_t)w.x, (uintptr_t)w.r, (uintptr_t)w.z, (uintptr_t)w.p0,
-                                  (uintptr_t)w.p1, (uintptr_t)w.q, (uintptr_t)w.e0, (uintptr_t)w.e1,
-                                  (uintptr_t)w.part, (uintptr_t)w.st, (uintptr_t)w.st1};
-    for (int c = 0; c < 3; ++c) key_push_double(key, (double)w.ik[c]);
-    return cached_graph(ctx, key, [&](LaunchSink& G) {
-        for (int c = 0; c < kPcgChunk; ++c)
-            phase_iteration<DIM, T>(ctx, g, w, pg, one_red, 1 + c, G, kTimeOff);
-    }, out, s);
-}
-
-// Runs a phase until every field's device state (type S, with a `done` field) reports
-// done: graph replays of kPcgChunk iterations (exec), or without graphs direct launches
-// in growing chunks; `direct(it, mode)` launches iteration it.  The host checks the
-// states one chunk behind.  A timing sample replaces one replay by kPcgChunk direct
-// iterations, the first two of them timed.  hs: pinned host slots [2][B]; result: [B].
-template <typename S, typename Direct>
-static int run_phase(Ctx* ctx, hipStream_t s, const S* st, int B, hipGraphExec_t exec, long long cap,
-                     Direct direct, S* hs, S* result, std::initializer_list<int> kids) {
-    hipEvent_t ev[2];
-    TOPO_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
-    TOPO_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
-    bool pending[2] = {false, false};
-    long long replays = 0, issued = 1;
-    int chunk = 4;
-    int slot = 0;
-    int rc = TOPO_OK;
-    while (true) {
-        const int every = ctx->timing.every;
-        const long long issued_before = issued;
-        if (exec && !(every > 0 && replays % every == 0)) {
-            const hipError_t e = hipGraphLaunch(exec, s);
-            if (e != hipSuccess) {
-                rc = set_error(ctx, TOPO_EDEVICE, "hipGraphLaunch: %s", hipGetErrorString(e));
-                break;
-            }
-            issued += kPcgChunk;
-        } else if (exec) {
-            for (int c = 0; c < kPcgChunk; ++c, ++issued) direct(issued, c < 2 ? kTimeForced : kTimeOff);
-        } else {
-            for (int c = 0; c < chunk; ++c, ++issued) direct(issued, kTimeSampled);
-            if (chunk < 64) chunk *= 2;
-        }
-        ++replays;
-        if (every > 0)
-            for (int kid : kids) ctx->timing.launched[kid] += issued - issued_before;
-        hipError_t e = hipGetLastError();
-        if (e == hipSuccess) e = hipMemcpyAsync(hs + (size_t)slot * B, st, B * sizeof(S), hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess) e = hipEventRecord(ev[slot], s);
-        if (e != hipSuccess) {
-            rc = set_error(ctx, TOPO_EDEVICE, "PCG phase launch: %s", hipGetErrorString(e));
-            break;
-        }
-        pending[slot] = true;
-        const int other = slot ^ 1;
-        bool stop = false;
-        if (pending[other]) {
-            e = hipEventSynchronize(ev[other]);
-            if (e != hipSuccess) {
-                rc = set_error(ctx, TOPO_EDEVICE, "PCG phase: %s", hipGetErrorString(e));
-                break;
-            }
-            pending[other] = false;
-            stop = true;
-            for (int b = 0; b < B; ++b) stop &= hs[(size_t)other * B + b].done != 0;
-        }
-        if (stop || issued >= cap) break;
-        slot = other;
-    }
-    (void)hipStreamSynchronize(s);
-    (void)hipEventDestroy(ev[0]);
-    (void)hipEventDestroy(ev[1]);
-    if (rc) return rc;
-    TOPO_HIP(hipMemcpyAsync(hs, st, B * sizeof(S), hipMemcpyDeviceToHost, s));
-    TOPO_HIP(hipStreamSynchronize(s));
-    std::copy(hs, hs + B, result);
-    return TOPO_OK;
 }
 
 // K64: the dense element matrix in 2D, the reduced element blocks in 3D.
@@ -1276,7 +1384,8 @@ struct HdmWs {
     T *r = nullptr, *z = nullptr, *p0 = nullptr, *p1 = nullptr, *q = nullptr;
     T *e0 = nullptr, *e1 = nullptr;  // 2D float64: the one-reduction recursion's two further vectors
     float *a32 = nullptr, *w32 = nullptr;
-    int* skip = nullptr;
+    int *skip = nullptr, *live = nullptr, *solve = nullptr, *maxit = nullptr;
+    SegCtl* ctl = nullptr;
     PcgState* st = nullptr;
     Cg1State* st1 = nullptr;
 };
@@ -1298,6 +1407,10 @@ static void hdm_takes(Arena& ar, const Grid& g, bool mixed, int B, HdmWs<T>& w) 
     ar.take(&w.fsc, (size_t)B);
     ar.take(&w.corr, (size_t)B);
     ar.take(&w.skip, (size_t)B);
+    ar.take(&w.live, (size_t)B);
+    ar.take(&w.solve, (size_t)B);
+    ar.take(&w.maxit, (size_t)B);
+    ar.take(&w.ctl, (size_t)B);
     ar.take(&w.st, (size_t)B);
     ar.take(&w.st1, (size_t)B);
     ar.take(&w.x, N);
@@ -1324,25 +1437,61 @@ size_t ws_hdm_solve(const Grid& g, bool mixed, int B) {
     return ar.total();
 }
 
-// Largest ratio of true to recursive residual at the end of a segment for which the
-// recursion is continued after the residual replacement (else it restarts).
-constexpr double kReplaceDriftMax = 4.0;
-// Reduction of the residual a float32 segment aims for before its residual is replaced
-// by the float64 one (small enough to keep the replacements rare, large enough that the
-// float32 recursion has not drifted from the true residual; 3e-3 .. 1e-1 measured
-// within 2 % of each other in iterations).
-constexpr double kMixedSegmentTol = 1e-2;
+
+// Buffers of the segment controller.
+struct SegBufs {
+    SegCtl* ctl;    // [B]
+    int* skip;      // [B] residual skipped for the field
+    int* live;      // [B] the field is still being solved
+    double* corr;   // [B] weight of the segment's correction in u (0: none)
+    double* fsc;    // [B] scale of a segment starting now (0: none)
+    int* solve;     // [B] fields to solve
+    int* maxit;     // [B]
+};
+
+// The residual kernels of residual_launch, as launches of L (for chunk graphs).
+static void residual_sink(LaunchSink& L, const Grid& g, const double* K64, const double* a64, const uint8_t* mask,
+                          const double* u, const double* f, double* r, int B, double* part, double* out,
+                          const int* skip) {
+    const int nb = stencil_blocks(g);
+    L(g.dim == 2 ? (const void*)k_residual2 : (const void*)k_residual3, dim3(nb, B), dim3(kBlock), g, a64, K64,
+      mask, u, f, r, part, skip);
+    L((const void*)k_residual_sum, dim3(B), dim3(kBlock), nb, (const double*)part, out, skip);
+}
+
+// End of a chunk: the fields whose segment ended get their correction, their residual
+// and the controller's decision; the next segments start.
+template <int DIM, typename T>
+static void chunk_end(const Grid& g, const Grid& gres, const double* K64, const double* a64, const double* f,
+                      double* u, double* rpart, double* rout, const PcgBufs<T>& w, const PcgGeom& pg, bool one_red,
+                      const SegBufs& c, double rtol, double seg_min, LaunchSink& L) {
+    const dim3 gb(grid_blocks(w.B, 64)), bb(64);
+    const long long N = g.n_dofs;
+    if (one_red)
+        L((const void*)k_seg_mark<Cg1State>, gb, bb, w.B, w.st1, c.ctl, c.skip, c.corr, c.fsc, c.live);
+    else
+        L((const void*)k_seg_mark<PcgState>, gb, bb, w.B, w.st, c.ctl, c.skip, c.corr, c.fsc, c.live);
+    L((const void*)k_correct<double>, dim3(std::min(grid_blocks(N), 1024), w.B), dim3(kBlock), N, u,
+      (const double*)w.x, (const double*)c.corr);
+    residual_sink(L, gres, K64, a64, w.mask, u, f, (double*)w.r64, w.B, rpart, rout, (const int*)c.skip);
+    if (one_red)
+        L((const void*)k_seg_control<Cg1State>, gb, bb, w.B, w.st1, c.ctl, (const double*)rout, c.fsc, c.live, rtol,
+          seg_min);
+    else
+        L((const void*)k_seg_control<PcgState>, gb, bb, w.B, w.st, c.ctl, (const double*)rout, c.fsc, c.live, rtol,
+          seg_min);
+    phase_start<DIM, T>(g, w, pg, one_red, L);
+}
 
 // Batched HDM solve of the fields with solve[b] != 0 (the others are left untouched):
-// one Krylov recursion per field in precision T, cut into segments: each segment runs
-// until its recursive residual has dropped by its tolerance, then its correction is
-// added to u in float64, the true residual f - K u is recomputed in float64 and
-// replaces the recursive one, and the recursion continues with the same search
-// direction (or restarts when it had drifted).  The inner system of each field is
-// scaled by 1 / ||f|| so that float32 values stay O(1).  2D float64 solves run the
-// one-reduction recursion (one kernel per iteration).  Per-field outcomes go to
-// status[b] (TOPO_OK, TOPO_ENOCONV, TOPO_ENOTSPD) and stagnated[b]; the return value
-// is a device or allocation error only.
+// one Krylov recursion per field in precision T, cut into segments (see the segment
+// controller above), iterations replayed as graphs of one chunk each (kPcgChunk
+// iterations and the chunk end); the host launches chunks and checks the fields' live
+// flags one chunk behind.  The inner system of each field is scaled by 1 / ||f|| so
+// that float32 values stay O(1).  2D float64 solves run the one-reduction recursion
+// (one kernel per iteration).  Per-field outcomes go to status[b] (TOPO_OK,
+// TOPO_ENOCONV, TOPO_ENOTSPD) and stagnated[b]; the return value is a device or
+// allocation error only.
 template <int DIM, typename T>
 static int hdm_batch_impl(Ctx* ctx, const topo_mesh& m, const Grid& g0, const ElemTables* tb,
                           const double* rho, const uint8_t* mask, const double* f, double* u, int B,
@@ -1350,6 +1499,8 @@ static int hdm_batch_impl(Ctx* ctx, const topo_mesh& m, const Grid& g0, const El
                           int* status, uint8_t* stagnated, hipStream_t s) {
     Grid g = g0;
     if constexpr (DIM == 3) g.mtarget = march3_target(ctx, (const void*)k_pcg_apply3<T>);
+    Grid gres = g;  // the residual march fits its own resident wave (and the partial arrays)
+    if constexpr (DIM == 3) gres.mtarget = std::min(march3_target(ctx, (const void*)k_residual3), g.mtarget);
     const long long N = g.n_dofs;
     const bool one_red = DIM == 2 && sizeof(T) == 8;
     const PcgGeom pg = pcg_geom(g);
@@ -1358,6 +1509,7 @@ static int hdm_batch_impl(Ctx* ctx, const topo_mesh& m, const Grid& g0, const El
     hdm_takes(ar, g, mixed, B, ws);
     int rc = ar.commit(ctx, s);
     if (rc) return rc;
+    SegBufs c{ws.ctl, ws.skip, ws.live, ws.corr, ws.fsc, ws.solve, ws.maxit};
     rc = launch_tables(ctx, g, m, rho, B, ws.a64, ws.a32, ws.w64, ws.w32, s);
     if (rc) return rc;
     PcgBufs<T> w{};
@@ -1373,7 +1525,7 @@ static int hdm_batch_impl(Ctx* ctx, const topo_mesh& m, const Grid& g0, const El
     if constexpr (DIM == 2) w.K = sizeof(T) == 4 ? (const T*)tb->K32 : (const T*)tb->K64;
     else w.K = sizeof(T) == 4 ? (const T*)tb->M32 : (const T*)tb->M64;
     w.mask = mask;
-    for (int c = 0; c < 3; ++c) w.ik[c] = c < DIM ? (T)(1.0 / tb->diag[c]) : T(0);
+    for (int q = 0; q < 3; ++q) w.ik[q] = q < DIM ? (T)(1.0 / tb->diag[q]) : T(0);
     w.r = ws.r;
     w.z = ws.z;
     w.p0 = ws.p0;
@@ -1387,205 +1539,143 @@ static int hdm_batch_impl(Ctx* ctx, const topo_mesh& m, const Grid& g0, const El
     w.st1 = ws.st1;
     w.r64 = ws.r64;
     w.fsc = ws.fsc;
+    const double* K64 = DIM == 2 ? tb->K64 : tb->M64;
+    const double seg_min = mixed ? kMixedSegmentTol : 0.0;
 
-    for (int b = 0; b < B; ++b)
-        if (solve[b]) TOPO_HIP(hipMemsetAsync(u + (size_t)b * N, 0, N * sizeof(double), s));
-
-    // pinned host layout: [2 poll slots | spare | state upload] x B states, then 4B
-    // residual sums, B scales, B corrections, B skip flags
-    constexpr size_t kSt = sizeof(PcgState) > sizeof(Cg1State) ? sizeof(PcgState) : sizeof(Cg1State);
-    const size_t off_res = 4 * B * kSt, off_fsc = off_res + 4 * B * sizeof(double),
-                 off_corr = off_fsc + B * sizeof(double), off_skip = off_corr + B * sizeof(double);
+    // pinned host layout: [2 live slots of B ints | B solve flags | B limits | B controls]
+    const size_t off_solve = 2 * B * sizeof(int), off_maxit = off_solve + B * sizeof(int),
+                 off_ctl = (off_maxit + B * sizeof(int) + 15) & ~size_t(15);
     void* pin = nullptr;
-    rc = pinned_host(ctx, off_skip + B * sizeof(int), &pin);
+    rc = pinned_host(ctx, off_ctl + B * sizeof(SegCtl), &pin);
     if (rc) return rc;
     char* pc = (char*)pin;
-    double* h_res = (double*)(pc + off_res);
-    double* h_fsc = (double*)(pc + off_fsc);
-    double* h_corr = (double*)(pc + off_corr);
-    int* h_skip = (int*)(pc + off_skip);
-    PcgState* up0 = (PcgState*)(pc + 3 * B * kSt);  // state upload area (one array of the
-    Cg1State* up1 = (Cg1State*)(pc + 3 * B * kSt);  // recursion's state type)
-
-    struct Field {
-        bool live = false, fresh = true, stagnated = false;
-        int total = 0, base = 0, segments = 0, status = TOPO_OK;
-        double nf = 0.0, scale = 1.0, rr = 0.0, rr_prev = INFINITY, res[3] = {0.0, 0.0, 0.0};
-        int fin_done = 0, fin_iters = 0;
-        double fin_rr = 0.0, last_rz[2] = {0.0, 0.0};
-    };
-    std::vector<Field> F(B);
-    // float64 residual of the fields with want[b]: r64, ||r||^2, f^T u, u^T r
-    auto residual = [&](const std::vector<char>& want) -> int {
-        for (int b = 0; b < B; ++b) h_skip[b] = want[b] ? 0 : 1;
-        TOPO_HIP(hipMemcpyAsync(ws.skip, h_skip, B * sizeof(int), hipMemcpyHostToDevice, s));
-        int rc2 = residual_launch(ctx, g, g.dim == 2 ? tb->K64 : tb->M64, ws.a64, mask, u, f, ws.r64, B,
-                                  ws.rpart, ws.rout, ws.skip, s);
-        if (rc2) return rc2;
-        TOPO_HIP(hipMemcpyAsync(h_res, ws.rout, 4 * B * sizeof(double), hipMemcpyDeviceToHost, s));
-        TOPO_HIP(hipStreamSynchronize(s));
-        for (int b = 0; b < B; ++b)
-            if (want[b])
-                for (int q = 0; q < 3; ++q) F[b].res[q] = h_res[4 * b + q];
-        return TOPO_OK;
-    };
-    std::vector<char> want(B, 0);
-    for (int b = 0; b < B; ++b) want[b] = solve[b] != 0;
-    rc = residual(want);
-    if (rc) return rc;
+    int* h_live = (int*)pc;
+    int* h_solve = (int*)(pc + off_solve);
+    int* h_maxit = (int*)(pc + off_maxit);
+    SegCtl* h_ctl = (SegCtl*)(pc + off_ctl);
     long long cap = 0;
     for (int b = 0; b < B; ++b) {
-        Field& fd = F[b];
-        fd.live = solve[b] != 0;
-        fd.nf = std::sqrt(fd.res[0]);
-        fd.scale = fd.nf > 0.0 ? 1.0 / fd.nf : 1.0;
-        fd.rr = fd.res[0];
-        if (fd.live) cap = std::max(cap, (long long)maxit[b]);
+        h_solve[b] = solve[b] ? 1 : 0;
+        h_maxit[b] = maxit[b];
+        if (solve[b]) {
+            TOPO_HIP(hipMemsetAsync(u + (size_t)b * N, 0, N * sizeof(double), s));
+            cap = std::max(cap, (long long)maxit[b]);
+        }
     }
     cap += 4096;
-    const double seg_min = mixed ? kMixedSegmentTol : 0.0;
-    hipGraphExec_t exec = nullptr;
-    if (graphs_enabled()) {
-        rc = phase_graph<DIM, T>(ctx, g, w, pg, one_red, &exec, s);
-        if (rc) return rc;
-    }
-    std::vector<PcgState> res0(B);
-    std::vector<Cg1State> res1(B);
-    while (true) {
-        bool any = false;
-        for (int b = 0; b < B; ++b) {
-            Field& fd = F[b];
-            if (!fd.live) continue;
-            const double rel = fd.nf > 0.0 ? std::sqrt(fd.rr) / fd.nf : 0.0;
-            if (rel <= rtol) {
-                fd.live = false;
-            } else if (fd.total >= maxit[b] || fd.segments >= 400) {
-                fd.status = TOPO_ENOCONV;
-                fd.live = false;
-            } else if (fd.segments > 0 && !(fd.rr < 0.5 * fd.rr_prev)) {
-                fd.status = TOPO_ENOCONV;
-                fd.stagnated = true;
-                if (stagnated) stagnated[b] = 1;
-                fd.live = false;
-            } else {
-                any = true;
-            }
-        }
-        if (!any) break;
-        // per-field segment setup, uploaded as the fields' states
-        for (int b = 0; b < B; ++b) {
-            Field& fd = F[b];
-            h_fsc[b] = fd.live ? fd.scale : 0.0;
-            double tol_seg = 0.0;
-            if (fd.live) {
-                tol_seg = std::max(0.5 * rtol * fd.nf / std::sqrt(fd.rr), seg_min);
-                tol_seg = std::min(std::max(tol_seg, 1e-15), 0.5);
-                if (fd.fresh) fd.base = fd.total;
-            }
-            const int it0 = fd.live && !fd.fresh ? fd.fin_iters : 0;
-            const double bb = fd.live && !fd.fresh ? fd.rr * fd.scale * fd.scale : 0.0;
-            if (one_red) {
-                Cg1State c{};
-                c.done = fd.live ? 0 : 4;
-                c.tol2 = tol_seg * tol_seg;
-                c.bb = c.rr = bb;
-                c.maxit = maxit[b] - fd.base;
-                c.iters[0] = c.iters[1] = it0;
-                c.poff = (it0 & 1) ^ 1;
-                c.kind0 = fd.fresh ? kCg1Fresh : kCg1Continued;
-                c.it0 = it0;
-                up1[b] = c;
-            } else {
-                PcgState p{};
-                p.done = fd.live ? 0 : 4;
-                p.tol2 = tol_seg * tol_seg;
-                p.bb = p.rr = bb;
-                p.maxit = maxit[b] - fd.base;
-                p.iters = it0;
-                p.poff = (it0 & 1) ^ 1;
-                p.fresh = fd.fresh ? 1 : 0;
-                // the replaced residual's apply takes beta against the last recursive rz
-                p.rz[0] = fd.fresh ? 0.0 : fd.last_rz[0];
-                p.rz[1] = fd.fresh ? 0.0 : fd.last_rz[1];
-                up0[b] = p;
-            }
-        }
-        if (one_red)
-            TOPO_HIP(hipMemcpyAsync(ws.st1, up1, B * sizeof(Cg1State), hipMemcpyHostToDevice, s));
-        else
-            TOPO_HIP(hipMemcpyAsync(ws.st, up0, B * sizeof(PcgState), hipMemcpyHostToDevice, s));
-        TOPO_HIP(hipMemcpyAsync(ws.fsc, h_fsc, B * sizeof(double), hipMemcpyHostToDevice, s));
+    TOPO_HIP(hipMemcpyAsync(c.solve, h_solve, B * sizeof(int), hipMemcpyHostToDevice, s));
+    TOPO_HIP(hipMemcpyAsync(c.maxit, h_maxit, B * sizeof(int), hipMemcpyHostToDevice, s));
+    // the initial residual of the fields to solve, their first segments
+    {
         LaunchSink L;
         L.s = s;
+        hipLaunchKernelGGL(k_skip_from_solve, dim3(grid_blocks(B, 64)), dim3(64), 0, s, B, (const int*)c.solve,
+                           c.skip);
+        residual_sink(L, gres, K64, ws.a64, mask, u, f, ws.r64, B, ws.rpart, ws.rout, (const int*)c.skip);
+        if (one_red)
+            L((const void*)k_seg_init<Cg1State>, dim3(grid_blocks(B, 64)), dim3(64), B, ws.st1, c.ctl,
+              (const double*)ws.rout, c.fsc, c.live, (const int*)c.solve, (const int*)c.maxit, rtol, seg_min);
+        else
+            L((const void*)k_seg_init<PcgState>, dim3(grid_blocks(B, 64)), dim3(64), B, ws.st, c.ctl,
+              (const double*)ws.rout, c.fsc, c.live, (const int*)c.solve, (const int*)c.maxit, rtol, seg_min);
         phase_start<DIM, T>(g, w, pg, one_red, L);
         TOPO_HIP(L.err);
-        auto direct = [&](long long it, int mode) {
-            phase_iteration<DIM, T>(ctx, g, w, pg, one_red, it, L, mode);
-        };
-        if (one_red)
-            rc = run_phase<Cg1State>(ctx, s, ws.st1, B, exec, cap, direct, (Cg1State*)pin, res1.data(),
-                                     {KID_PCG_STEP});
-        else
-            rc = run_phase<PcgState>(ctx, s, ws.st, B, exec, cap, direct, (PcgState*)pin, res0.data(),
-                                     {KID_PCG_APPLY, KID_PCG_UPDATE});
-        if (rc) return rc;
-        TOPO_HIP(L.err);
-        // fold each running field's segment into u
-        bool corr_any = false;
-        for (int b = 0; b < B; ++b) {
-            Field& fd = F[b];
-            h_corr[b] = 0.0;
-            want[b] = 0;
-            if (!fd.live) continue;
-            if (one_red) {
-                fd.fin_done = res1[b].done;
-                fd.fin_iters = std::max(res1[b].iters[0], res1[b].iters[1]);
-                fd.fin_rr = res1[b].rr;
-            } else {
-                fd.fin_done = res0[b].done;
-                fd.fin_iters = res0[b].iters;
-                fd.fin_rr = res0[b].rr;
-                fd.last_rz[0] = res0[b].rz[0];
-                fd.last_rz[1] = res0[b].rz[1];
-            }
-            const int seg_iters = fd.base + fd.fin_iters - fd.total;
-            fd.total = fd.base + fd.fin_iters;
-            if (fd.fin_done == 3 && seg_iters == 0) {
-                fd.status = set_error(ctx, TOPO_ENOTSPD, "CG breakdown: p^T K p <= 0 (field %d)", b);
-                fd.live = false;
-                continue;
-            }
-            h_corr[b] = fd.nf > 0.0 ? fd.nf : 1.0;
-            want[b] = 1;
-            corr_any = true;
-            ++fd.segments;
-            fd.rr_prev = fd.rr;
-        }
-        if (!corr_any) continue;
-        TOPO_HIP(hipMemcpyAsync(ws.corr, h_corr, B * sizeof(double), hipMemcpyHostToDevice, s));
-        hipLaunchKernelGGL((k_correct<double>), dim3(grid_blocks(N), B), dim3(kBlock), 0, s, N, u,
-                           (const double*)ws.x, (const double*)ws.corr);
         TOPO_CHECK_LAUNCH();
-        rc = residual(want);
-        if (rc) return rc;
-        for (int b = 0; b < B; ++b) {
-            Field& fd = F[b];
-            if (!want[b]) continue;
-            fd.rr = fd.res[0];
-            if (fd.fin_done == 3 && !(fd.rr < fd.rr_prev)) {
-                fd.status = set_error(ctx, TOPO_ENOTSPD, "CG breakdown: p^T K p <= 0 (field %d)", b);
-                fd.live = false;
-                continue;
-            }
-            // continue the recursion only while it still tracks the true residual; a
-            // segment whose true residual drifted far from the recursive one restarts
-            const double drift = fd.fin_rr > 0.0 ? std::sqrt(fd.rr) * fd.scale / std::sqrt(fd.fin_rr) : INFINITY;
-            fd.fresh = !(drift <= kReplaceDriftMax) || fd.fin_done != 1;
-        }
     }
+    // mode: kTimeOff (graph construction), kTimeForced (a timing sample replacing a
+    // replay: its first two iterations timed), kTimeSampled (no graphs)
+    auto chunk = [&](LaunchSink& L, int mode) {
+        for (int q = 0; q < kPcgChunk; ++q) {
+            const int tm = mode == kTimeForced ? (q < 2 ? kTimeForced : kTimeOff) : mode;
+            phase_iteration<DIM, T>(ctx, g, w, pg, one_red, 1 + q, L, tm);
+        }
+        chunk_end<DIM, T>(g, gres, K64, ws.a64, f, u, ws.rpart, ws.rout, w, pg, one_red, c, rtol, seg_min, L);
+    };
+    hipGraphExec_t exec = nullptr;
+    if (graphs_enabled()) {
+        std::vector<uintptr_t> key = {(uintptr_t)0xB7C7, (uintptr_t)DIM, sizeof(T), (uintptr_t)one_red,
+                                      (uintptr_t)B, (uintptr_t)pg.napp, (uintptr_t)pg.nupd, (uintptr_t)kPcgChunk,
+                                      (uintptr_t)g.nx, (uintptr_t)g.ny, (uintptr_t)g.nz, (uintptr_t)g.mtarget,
+                                      (uintptr_t)gres.mtarget, (uintptr_t)w.alpha, (uintptr_t)w.K,
+                                      (uintptr_t)w.mask, (uintptr_t)w.winv, (uintptr_t)w.x, (uintptr_t)w.r,
+                                      (uintptr_t)w.z, (uintptr_t)w.p0, (uintptr_t)w.p1, (uintptr_t)w.q,
+                                      (uintptr_t)w.e0, (uintptr_t)w.e1, (uintptr_t)w.part, (uintptr_t)w.st,
+                                      (uintptr_t)w.st1, (uintptr_t)ws.a64, (uintptr_t)ws.r64, (uintptr_t)ws.rpart,
+                                      (uintptr_t)ws.rout, (uintptr_t)u, (uintptr_t)f, (uintptr_t)c.ctl,
+                                      (uintptr_t)c.skip, (uintptr_t)c.live, (uintptr_t)c.corr, (uintptr_t)c.fsc};
+        for (int q = 0; q < 3; ++q) key_push_double(key, (double)w.ik[q]);
+        key_push_double(key, rtol);
+        key_push_double(key, seg_min);
+        rc = cached_graph(ctx, key, [&](LaunchSink& G) { chunk(G, kTimeOff); }, &exec, s);
+        if (rc) return rc;
+    }
+    // chunks until every field has retired; the host reads the live flags one chunk
+    // behind.  A timing sample replaces one replay by direct launches (two timed).
+    hipEvent_t ev[2];
+    TOPO_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+    TOPO_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+    bool pending[2] = {false, false};
+    long long issued = 0, replays = 0;
+    int slot = 0;
+    LaunchSink L;
+    L.s = s;
+    const int kids[2] = {one_red ? KID_PCG_STEP : KID_PCG_APPLY, one_red ? -1 : KID_PCG_UPDATE};
+    while (true) {
+        const int every = ctx->timing.every;
+        if (exec && !(every > 0 && replays % every == 0)) {
+            const hipError_t e = hipGraphLaunch(exec, s);
+            if (e != hipSuccess) {
+                rc = set_error(ctx, TOPO_EDEVICE, "hipGraphLaunch: %s", hipGetErrorString(e));
+                break;
+            }
+        } else {
+            chunk(L, exec ? kTimeForced : kTimeSampled);
+            if (L.err != hipSuccess) {
+                rc = set_error(ctx, TOPO_EDEVICE, "PCG chunk launch: %s", hipGetErrorString(L.err));
+                break;
+            }
+        }
+        issued += kPcgChunk;
+        ++replays;
+        if (every > 0)
+            for (int kid : kids)
+                if (kid >= 0) ctx->timing.launched[kid] += kPcgChunk;
+        hipError_t e = hipGetLastError();
+        if (e == hipSuccess) e = hipMemcpyAsync(h_live + (size_t)slot * B, c.live, B * sizeof(int), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipEventRecord(ev[slot], s);
+        if (e != hipSuccess) {
+            rc = set_error(ctx, TOPO_EDEVICE, "PCG chunk: %s", hipGetErrorString(e));
+            break;
+        }
+        pending[slot] = true;
+        const int other = slot ^ 1;
+        bool stop = false;
+        if (pending[other]) {
+            e = hipEventSynchronize(ev[other]);
+            if (e != hipSuccess) {
+                rc = set_error(ctx, TOPO_EDEVICE, "PCG chunk: %s", hipGetErrorString(e));
+                break;
+            }
+            pending[other] = false;
+            stop = true;
+            for (int b = 0; b < B; ++b) stop &= h_live[(size_t)other * B + b] == 0;
+        }
+        if (stop || issued >= cap) break;
+        slot = other;
+    }
+    (void)hipStreamSynchronize(s);
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+    if (rc) return rc;
+    TOPO_HIP(hipMemcpyAsync(h_ctl, c.ctl, B * sizeof(SegCtl), hipMemcpyDeviceToHost, s));
+    TOPO_HIP(hipStreamSynchronize(s));
     for (int b = 0; b < B; ++b) {
         if (!solve[b]) continue;
-        const Field& fd = F[b];
+        SegCtl& fd = h_ctl[b];
+        if (fd.live) {  // the iteration cap of the chunk loop (every field has a limit below it)
+            fd.status = TOPO_ENOCONV;
+            fd.live = 0;
+        }
         topo_info& in = info[b];
         in.iters = fd.total;
         in.refinements = fd.segments;
@@ -1593,12 +1683,15 @@ static int hdm_batch_impl(Ctx* ctx, const topo_mesh& m, const Grid& g0, const El
         in.compliance_raw = fd.res[1];
         in.compliance_corr = fd.res[1] + fd.res[2];
         in.status = fd.status;
+        if (stagnated) stagnated[b] = fd.stagnated ? 1 : 0;
         if (fd.status == TOPO_ENOCONV && !fd.stagnated)
             set_error(ctx, TOPO_ENOCONV, "no convergence: rel. residual %.3e after %d iterations (field %d)",
                       in.rel_resid, fd.total, b);
         else if (fd.status == TOPO_ENOCONV)
             set_error(ctx, TOPO_ENOCONV, "residual replacement stagnated at rel. residual %.3e (field %d)",
                       in.rel_resid, b);
+        else if (fd.status == TOPO_ENOTSPD)
+            set_error(ctx, TOPO_ENOTSPD, "CG breakdown: p^T K p <= 0 (field %d)", b);
         status[b] = fd.status;
     }
     return TOPO_OK;
