@@ -364,51 +364,127 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_apply2(Grid g, const T* __res
     if (threadIdx.x == 0) pb[fb.blk] = v[0];
 }
 
-// 3D: one block per march column and field.  The first two node planes of z and p_old
-// are fetched before the scalar reduction; p_new = z + beta p_old is formed per node as
-// the planes are staged, and the element march runs from LDS.  M is the table of
-// reduced element blocks.
+// Emitter of the 3D PCG apply (once3_run): at each node slot of a plane the block
+// writes p_new and its part of q when it is the node's primary block, else its part
+// into the side section the node belongs to for this block; masked DOFs get a zero part.
+// The node's mask bytes are loaded one element layer ahead.  pq sums p_new . part over
+// every part written.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_pcg_apply3(Grid g, const T* __restrict__ alpha,
+struct PcgEmit3 {
+    const Grid& g;
+    const OnceBlock& m;
+    const MarchSlots& sl;
+    const SideGeom& sg;
+    const OnceLds<T>& L;
+    const uint8_t* __restrict__ mask;
+    T* __restrict__ p_new;
+    T* __restrict__ q;
+    T* __restrict__ side;
+    int sec[2];      // side section of the slot on the planes below the chunk's top (0: primary)
+    int sidx[2];     // its side index at plane 0 ...
+    int sstr[2];     // ... and per plane
+    unsigned mk[2], mk_next[2];  // mask bytes of the slot's node (component c at bits 8c)
+    double pq = 0.0;
+
+    __device__ __forceinline__ PcgEmit3(const Grid& g_, const OnceBlock& m_, const MarchSlots& sl_,
+                                        const SideGeom& sg_, const OnceLds<T>& L_, const uint8_t* mask_,
+                                        T* p_new_, T* q_, T* side_)
+        : g(g_), m(m_), sl(sl_), sg(sg_), L(L_), mask(mask_), p_new(p_new_), q(q_), side(side_) {
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const int qs = threadIdx.x + r * kBlock;
+            const int s = once3_section(g, m, qs, 0);  // no z bit below the top plane
+            sec[r] = sl.base[r] >= 0 ? s : 0;
+            const int i = m.ex0 + qs % MPX, j = m.ey0 + qs / MPX;
+            const long long i0 = s ? side_index(sg, s, i, j, 0) : 0;
+            const long long i1 = s ? side_index(sg, s, i, j, 1) : 0;
+            sidx[r] = (int)i0;
+            sstr[r] = (int)(i1 - i0);
+            mk[r] = mk_next[r] = 0;
+        }
+    }
+    __device__ __forceinline__ void load(int k) {
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const int n = march3_node(g, sl, r, k);
+            const int nn = n >= 0 ? n : 0;
+            const unsigned b0 = mask[nn], b1 = mask[g.n_nodes + nn], b2 = mask[2 * (size_t)g.n_nodes + nn];
+            mk_next[r] = n >= 0 ? (b0 | (b1 << 8) | (b2 << 16)) : 0u;
+        }
+    }
+    __device__ __forceinline__ void rotate() {
+        mk[0] = mk_next[0];
+        mk[1] = mk_next[1];
+    }
+    template <bool TOP>
+    __device__ __forceinline__ void emit(int r, int k, int buf, const T (&y)[3]) {
+        const int qs = threadIdx.x + r * kBlock;
+        const int n = sl.base[r] + k * sl.pstride;
+        int s = sec[r], si = sidx[r] + k * sstr[r];
+        if (TOP && k < g.nz) {  // the chunk's top plane: the block above is primary
+            s = once3_section(g, m, qs, k);
+            si = (int)side_index(sg, s, m.ex0 + qs % MPX, m.ey0 + qs / MPX, k);
+        }
+        T* dst = s ? side + si : q + n;
+        const size_t cs = s ? (size_t)sg.total : (size_t)g.n_nodes;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const T pn = L.plane[buf][c][qs];
+            const T qv = (mk[r] >> (8 * c)) & 0xffu ? T(0) : y[c];
+            dst[c * cs] = qv;
+            if (!s) p_new[c * (size_t)g.n_nodes + n] = pn;
+            pq += (double)pn * (double)qv;
+        }
+    }
+};
+
+// 3D: one block per element tile and field, each element evaluated once (once3_run).
+// The first two node planes of z and p_old are fetched before the scalar reduction;
+// p_new = z + beta p_old is formed per node as the planes are staged.  The block writes
+// p_new and its part of q = K p_new at the nodes it is primary for, and its part at the
+// other nodes of its tile into the side sections (side [B][3][total]); the update adds
+// them.  The pq partial sums p_new . part over every part the block writes, which adds
+// up to p_new . q over the blocks.  M is the table of reduced element blocks.
+template <typename T>
+__global__ __launch_bounds__(kBlock, sizeof(T) == 4 ? 3 : 2) void k_pcg_apply3(Grid g, const T* __restrict__ alpha,
                                                        const T* __restrict__ M,
                                                        const uint8_t* __restrict__ mask,
                                                        const T* __restrict__ z, T* __restrict__ p0,
                                                        T* __restrict__ p1, T* __restrict__ q,
-                                                       double* __restrict__ part, PcgState* st,
-                                                       int ps, int nrz, int lp) {
+                                                       T* __restrict__ side, double* __restrict__ part,
+                                                       PcgState* st, int ps, int nrz, int lp) {
     const FieldBlock fb = field_block();
     PcgState* sb = st + fb.field;
     if (sb->done) return;
-    __shared__ MarchLds<T> L;
+    __shared__ OnceLds<T> L;
     __shared__ double lds[48];
     const int parity = lp ^ sb->poff;
     const size_t fo = (size_t)fb.field * g.n_dofs;
+    const SideGeom sg = side_geom(g);
     alpha += (size_t)fb.field * g.n_elems;
     z += fo;
     const T* p_old = (parity ? p1 : p0) + fo;
     T* p_new = (parity ? p0 : p1) + fo;
     q += fo;
+    side += (size_t)fb.field * 3 * sg.total;
     double* pb = part + (size_t)fb.field * kPcgParts * ps;
-    const MarchBlock m = march3_block(g, fb.blk);
+    const OnceBlock m = once3_block(g, fb.blk);
     for (int i = threadIdx.x; i < kFacSize; i += blockDim.x) L.M[i] = M[i];
-    const MarchSlots sl = march3_slots(g, m);
+    const MarchSlots sl = once3_slots(g, m);
     SrcDirection<T> src{z, p_old, T(0), g.n_nodes};
-    march3_prologue(g, m, sl, src);
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        src.fetch(r, march3_node(g, sl, r, m.ez0));
+        src.fetch(2 + r, march3_node(g, sl, r, m.ez0 + 1));
+    }
+    PcgEmit3<T> E(g, m, sl, sg, L, mask, p_new, q, side);
+    E.load(m.ez0);
+    E.rotate();
     T tb;
     if (pcg_apply_scalars(pb, sb, ps, nrz, parity, fb.blk == 0, tb, lds)) return;
     src.beta = tb;
-    double v[1] = {0.0};
-    auto emit = [&](int n, const T (&out)[3], const T (&pn)[3]) {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const size_t idx = (size_t)c * g.n_nodes + n;
-            const T qv = mask[idx] ? T(0) : out[c];
-            p_new[idx] = pn[c];
-            q[idx] = qv;
-            v[0] += (double)pn[c] * (double)qv;
-        }
-    };
-    march3_run(g, m, sl, alpha, L, src, emit);
+    once3_run(g, m, sl, alpha, L, src, E);
+    double v[1] = {E.pq};
     block_reduce<1>(v, lds);
     if (threadIdx.x == 0) pb[fb.blk] = v[0];
 }
@@ -422,6 +498,7 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_update(Grid g, const T* __res
                                                        const T* __restrict__ p0,
                                                        const T* __restrict__ p1,
                                                        const T* __restrict__ q,
+                                                       const T* __restrict__ side,
                                                        double* __restrict__ part, PcgState* st,
                                                        int ps, int npq, int lp) {
     const int f = blockIdx.y;
@@ -450,6 +527,22 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_update(Grid g, const T* __res
             rv[c] = r[i];
             pv[c] = p[i];
             qv[c] = q[i];
+        }
+        if constexpr (DIM == 3) {
+            // q = the primary block's part + the parts of the blocks below the node, in
+            // the order of their side sections
+            const SideGeom sg = side_geom(g);
+            const int i = n % g.nx1, jk = n / g.nx1, j = jk % g.ny1, k = jk / g.ny1;
+            const int ax = side_axes(g, sg, i, j, k);
+            if (ax) {
+                side += (size_t)f * 3 * sg.total;
+                for (int sec = 1; sec < 8; ++sec)
+                    if ((sec & ax) == sec) {
+                        const long long si = side_index(sg, sec, i, j, k);
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) qv[c] += side[(size_t)c * sg.total + si];
+                    }
+            }
         }
     }
     const double pq = block_sum_array(pb, npq, lds);
@@ -1045,7 +1138,7 @@ struct PcgGeom {
 static PcgGeom pcg_geom(const Grid& g) {
     PcgGeom pg;
     pg.nupd = grid_blocks(g.n_nodes, kPcgBlock);
-    pg.napp = g.dim == 2 ? grid_blocks(g.n_nodes, kPcgBlock) : stencil_blocks(g);
+    pg.napp = g.dim == 2 ? grid_blocks(g.n_nodes, kPcgBlock) : once3_blocks(g);
     pg.ps = std::max(pg.nupd, pg.napp);
     pg.npq = pg.napp > kPcgMaxBlocks ? 1 : pg.napp;
     pg.nrz = pg.nupd > kPcgMaxBlocks ? 1 : pg.nupd;
@@ -1063,6 +1156,7 @@ struct PcgBufs {
     const T* winv;     // [B][N_n]
     T ik[3];           // 1 / K_e[c][c]
     T *r, *z, *p0, *p1, *q, *e0, *e1;  // [B][N_u]
+    T* side;           // 3D: [B][3][side total] the apply's parts of shared nodes
     double* x;         // [B][N_u] the segment's correction, accumulated in float64
     double* part;      // [B][kPcgParts][ps]
     PcgState* st;      // [B]
@@ -1080,8 +1174,12 @@ static void pcg_iteration(Ctx* ctx, const Grid& g, const PcgBufs<T>& w, const Pc
         L.ev0 = tl.a;
         L.ev1 = tl.b;
         const void* fn = DIM == 2 ? (const void*)k_pcg_apply2<T> : (const void*)k_pcg_apply3<T>;
-        L(fn, dim3(pg.napp, w.B), dim3(DIM == 2 ? kPcgBlock : kBlock), g, w.alpha, w.K, w.mask,
-          (const T*)w.z, w.p0, w.p1, w.q, w.part, w.st, pg.ps, pg.nrz, lp);
+        if constexpr (DIM == 2)
+            L(fn, dim3(pg.napp, w.B), dim3(kPcgBlock), g, w.alpha, w.K, w.mask, (const T*)w.z, w.p0, w.p1,
+              w.q, w.part, w.st, pg.ps, pg.nrz, lp);
+        else
+            L(fn, dim3(pg.napp, w.B), dim3(kBlock), g, w.alpha, w.K, w.mask, (const T*)w.z, w.p0, w.p1, w.q,
+              w.side, w.part, w.st, pg.ps, pg.nrz, lp);
     }
     if (pg.npq == 1 && pg.napp > 1)
         L((const void*)k_partials_sum<PcgState>, dim3(w.B), dim3(1024), w.part, pg.ps, pg.napp, 0, 0, -1, 0,
@@ -1091,8 +1189,8 @@ static void pcg_iteration(Ctx* ctx, const Grid& g, const PcgBufs<T>& w, const Pc
         L.ev0 = tl.a;
         L.ev1 = tl.b;
         L((const void*)k_pcg_update<DIM, T>, dim3(pg.nupd, w.B), dim3(kPcgBlock), g, w.winv, w.ik[0], w.ik[1],
-          w.ik[2], w.x, w.r, w.z, (const T*)w.p0, (const T*)w.p1, (const T*)w.q, w.part, w.st, pg.ps, pg.npq,
-          lp);
+          w.ik[2], w.x, w.r, w.z, (const T*)w.p0, (const T*)w.p1, (const T*)w.q, (const T*)w.side, w.part,
+          w.st, pg.ps, pg.npq, lp);
     }
     if (pg.nrz == 1 && pg.nupd > 1)  // rz / rr of the update's own parity
         L((const void*)k_partials_sum<PcgState>, dim3(w.B), dim3(1024), w.part, pg.ps, pg.nupd, 1, 1, 3, 1,
@@ -1383,6 +1481,7 @@ struct HdmWs {
            *rout = nullptr, *x = nullptr, *fsc = nullptr, *corr = nullptr;
     T *r = nullptr, *z = nullptr, *p0 = nullptr, *p1 = nullptr, *q = nullptr;
     T *e0 = nullptr, *e1 = nullptr;  // 2D float64: the one-reduction recursion's two further vectors
+    T* side = nullptr;               // 3D: the apply's parts of shared nodes
     float *a32 = nullptr, *w32 = nullptr;
     int *skip = nullptr, *live = nullptr, *solve = nullptr, *maxit = nullptr;
     SegCtl* ctl = nullptr;
@@ -1423,6 +1522,7 @@ static void hdm_takes(Arena& ar, const Grid& g, bool mixed, int B, HdmWs<T>& w) 
         ar.take(&w.e0, N);
         ar.take(&w.e1, N);
     }
+    if (g.dim == 3) ar.take(&w.side, (size_t)B * 3 * side_geom(g).total);
 }
 
 size_t ws_hdm_solve(const Grid& g, bool mixed, int B) {
@@ -1533,6 +1633,7 @@ static int hdm_batch_impl(Ctx* ctx, const topo_mesh& m, const Grid& g0, const El
     w.q = ws.q;
     w.e0 = ws.e0;
     w.e1 = ws.e1;
+    w.side = ws.side;
     w.x = ws.x;
     w.part = ws.part;
     w.st = ws.st;
@@ -1599,7 +1700,8 @@ static int hdm_batch_impl(Ctx* ctx, const topo_mesh& m, const Grid& g0, const El
                                       (uintptr_t)gres.mtarget, (uintptr_t)w.alpha, (uintptr_t)w.K,
                                       (uintptr_t)w.mask, (uintptr_t)w.winv, (uintptr_t)w.x, (uintptr_t)w.r,
                                       (uintptr_t)w.z, (uintptr_t)w.p0, (uintptr_t)w.p1, (uintptr_t)w.q,
-                                      (uintptr_t)w.e0, (uintptr_t)w.e1, (uintptr_t)w.part, (uintptr_t)w.st,
+                                      (uintptr_t)w.e0, (uintptr_t)w.e1, (uintptr_t)w.side, (uintptr_t)w.part,
+                                      (uintptr_t)w.st,
                                       (uintptr_t)w.st1, (uintptr_t)ws.a64, (uintptr_t)ws.r64, (uintptr_t)ws.rpart,
                                       (uintptr_t)ws.rout, (uintptr_t)u, (uintptr_t)f, (uintptr_t)c.ctl,
                                       (uintptr_t)c.skip, (uintptr_t)c.live, (uintptr_t)c.corr, (uintptr_t)c.fsc};

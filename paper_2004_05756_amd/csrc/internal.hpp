@@ -282,6 +282,77 @@ __host__ __device__ inline int march3_blocks(const Grid& g) {
     return march3_tiles_x(g) * march3_tiles_y(g) * ((g.nz1 + kz - 1) / kz);
 }
 
+// Element-once 3D march (the PCG apply): a block owns a 32 x 8 tile of element columns
+// (no overlap with its neighbours) over KZ element layers, so every element is
+// evaluated exactly once.  A node shared by several blocks (on the high x / y / z face
+// of one block and inside or on the low face of another) is completed later: the
+// block whose tile holds the element at the node's own (i, j, k) corner, its primary
+// block, writes its part to the main array, every other block writes its part to one
+// of seven side sections (by which of its high faces the node lies on), and the
+// consumer adds the sections in a fixed order.  KZ is sized like march3_kz.
+__host__ __device__ inline int once3_tiles_x(const Grid& g) { return (g.nx + MEX - 1) / MEX; }
+__host__ __device__ inline int once3_tiles_y(const Grid& g) { return (g.ny + MEY - 1) / MEY; }
+__host__ __device__ inline int once3_kz(const Grid& g) {
+    const int xy = once3_tiles_x(g) * once3_tiles_y(g);
+    const int target = g.mtarget > 0 ? g.mtarget : 1024;
+    const int chunks = target > xy ? target / xy : 1;
+    return (g.nz + chunks - 1) / chunks;
+}
+__host__ __device__ inline int once3_chunks(const Grid& g) {
+    const int kz = once3_kz(g);
+    return (g.nz + kz - 1) / kz;
+}
+__host__ __device__ inline int once3_blocks(const Grid& g) {
+    return once3_tiles_x(g) * once3_tiles_y(g) * once3_chunks(g);
+}
+
+// Side sections s = 1..7 (bit 1: the contributing block is below the node in x, bit 2:
+// in y, bit 4: in z).  Along an axis in s the section holds only the interior block
+// boundaries (index = boundary number - 1), along the others every node; the sections
+// follow each other in the order of s, one component after the other ([c][total]).
+struct SideGeom {
+    int nb[3];        // interior block boundaries along x, y, z
+    int nn[3];        // nodes along x, y, z
+    int kz;           // element layers per chunk
+    long long total;  // nodes over all sections
+};
+
+__host__ __device__ inline long long side_count(const SideGeom& sg, int s) {
+    return (long long)(s & 1 ? sg.nb[0] : sg.nn[0]) * (s & 2 ? sg.nb[1] : sg.nn[1]) *
+           (s & 4 ? sg.nb[2] : sg.nn[2]);
+}
+
+__host__ __device__ inline SideGeom side_geom(const Grid& g) {
+    SideGeom sg;
+    sg.kz = once3_kz(g);
+    sg.nb[0] = once3_tiles_x(g) - 1;
+    sg.nb[1] = once3_tiles_y(g) - 1;
+    sg.nb[2] = once3_chunks(g) - 1;
+    sg.nn[0] = g.nx1;
+    sg.nn[1] = g.ny1;
+    sg.nn[2] = g.nz1;
+    sg.total = 0;
+    for (int t = 1; t < 8; ++t) sg.total += side_count(sg, t);
+    return sg;
+}
+
+// Index in section s of node (i, j, k) (s's axes on a block boundary of the node).
+__host__ __device__ inline long long side_index(const SideGeom& sg, int s, int i, int j, int k) {
+    long long off = 0;
+#pragma unroll
+    for (int t = 1; t < 7; ++t) off += t < s ? side_count(sg, t) : 0;
+    const int a = s & 1 ? i / MEX - 1 : i;
+    const int b = s & 2 ? j / MEY - 1 : j;
+    const int c = s & 4 ? k / sg.kz - 1 : k;
+    return off + ((long long)c * (s & 2 ? sg.nb[1] : sg.nn[1]) + b) * (s & 1 ? sg.nb[0] : sg.nn[0]) + a;
+}
+
+// Axes along which node (i, j, k) lies on an interior block boundary (bit per axis).
+__host__ __device__ inline int side_axes(const Grid& g, const SideGeom& sg, int i, int j, int k) {
+    return (i % MEX == 0 && i > 0 && i < g.nx ? 1 : 0) | (j % MEY == 0 && j > 0 && j < g.ny ? 2 : 0) |
+           (k % sg.kz == 0 && k > 0 && k < g.nz ? 4 : 0);
+}
+
 // Element sensitivities dc_e = -alpha'(rho_e) u_e^T K_e u_e of B fields (rho [B][N_e],
 // u [B][N_u], dc [B][N_e], all float64 device arrays).
 int gradient_launch(Ctx* ctx, const Grid& g, const topo_mesh& m, const ElemTables* tb,
@@ -306,7 +377,9 @@ constexpr int kPcgMaxBlocks = 2048;
 // PCG kernels.
 inline int partial_stride(const Grid& g) {
     const int a = stencil_blocks(g), b = grid_blocks(g.n_nodes);
-    return a > b ? a : b;
+    const int c = g.dim == 3 ? once3_blocks(g) : 0;
+    const int ab = a > b ? a : b;
+    return ab > c ? ab : c;
 }
 
 // Sum each of NV arrays (array q has n[q] doubles) in one pass, fixed order.

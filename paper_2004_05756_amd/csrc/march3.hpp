@@ -10,6 +10,8 @@
 // (deterministic, no atomics).
 #pragma once
 
+#include <type_traits>
+
 #include "elemfac.hpp"
 
 namespace topo {
@@ -212,6 +214,193 @@ __device__ __forceinline__ void march3_run(const Grid& g, const MarchBlock& m,
             }
         fb = ft;
     }
+}
+
+}  // namespace topo
+
+namespace topo {
+
+// ----------------------------------------------------------------------------------
+// Element-once march.  The block's tile is elements [ex0, ex0+32) x [ey0, ey0+8) over
+// element layers [ez0, ez1); its node planes are the 33 x 9 nodes [ex0, ex0+32] x
+// [ey0, ey0+8].  Each element layer is evaluated once, every node of the plane below it
+// is emitted with the corner sums of the (up to) four tile elements of the layer below
+// and the four of the layer above, and the top plane of the chunk is emitted with the
+// last layer's corners alone.  The corner exchange has a zero border (34 x 10 slots per
+// corner and component) so that a node of the tile's edge reads the missing elements as
+// zeros without a test.
+// ----------------------------------------------------------------------------------
+constexpr int OXX = MEX + 2;              // padded exchange row
+constexpr int OXN = OXX * (MEY + 2);      // 340 slots
+
+template <typename T>
+struct OnceLds {
+    T plane[3][3][MPN];   // node planes, triple-buffered (plane k in buffer (k - ez0) % 3)
+    T xch[3][4][OXN];     // corner sums [c][corner][padded element slot]
+    T M[kFacSize];
+};
+
+struct OnceBlock {
+    int ex0, ey0, ez0, ez1;
+};
+
+__device__ __forceinline__ OnceBlock once3_block(const Grid& g, int b) {
+    const int tx = once3_tiles_x(g), ty = once3_tiles_y(g), kz = once3_kz(g);
+    OnceBlock m;
+    m.ex0 = (b % tx) * MEX;
+    m.ey0 = ((b / tx) % ty) * MEY;
+    m.ez0 = (b / (tx * ty)) * kz;
+    m.ez1 = min(m.ez0 + kz, g.nz);
+    return m;
+}
+
+// Plane slots q = tid, tid + kBlock of the tile's node plane (px = q % 33, py = q / 33).
+__device__ __forceinline__ MarchSlots once3_slots(const Grid& g, const OnceBlock& m) {
+    MarchSlots sl;
+    sl.pstride = g.nx1 * g.ny1;
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const int q = threadIdx.x + r * kBlock;
+        const int i = m.ex0 + q % MPX, j = m.ey0 + q / MPX;
+        const bool ok = (q < MPN) & (i < g.nx1) & (j < g.ny1);
+        sl.base[r] = ok ? j * g.nx1 + i : -1;
+    }
+    return sl;
+}
+
+// Side section of node slot q at node plane k for this block: 0 when the block is the
+// node's primary, else the bits of the high faces the node lies on.
+__device__ __forceinline__ int once3_section(const Grid& g, const OnceBlock& m, int q, int k) {
+    const int px = q % MPX, py = q / MPX;
+    return (px == MEX && m.ex0 + MEX < g.nx ? 1 : 0) | (py == MEY && m.ey0 + MEY < g.ny ? 2 : 0) |
+           (k == m.ez1 && k < g.nz ? 4 : 0);
+}
+
+// The march.  Src as for march3_run, except that the caller has fetched planes ez0
+// (slots 0, 1) and ez0 + 1 (slots 2, 3).  Emit is an object with
+//   load(int k)    issue the loads of what the emit of node plane k needs (called one
+//                  element layer ahead, after the first barrier of the layer)
+//   emit<TOP>(int r, int k, int buf, const T (&y)[3])  y = this block's part of (K x)
+//                  at the node of slot r at plane k, whose values x are in L.plane[buf]
+//                  (a plane buffer is written again only two layers later, after a
+//                  barrier every emitter has passed); TOP: k is the chunk's top plane
+//   rotate()       the loads of the last load() become those of the next emit
+// Emit has loaded plane ez0 before the call.  Barriers per element layer: after the
+// plane is staged and after the corner exchange.
+template <typename T, typename Src, typename Emit>
+__device__ __forceinline__ void once3_run(const Grid& g, const OnceBlock& m, const MarchSlots& sl,
+                                          const T* __restrict__ alpha, OnceLds<T>& L, Src& src,
+                                          Emit& E) {
+    const int tid = threadIdx.x;
+    const int tx = tid % MEX, ty = tid / MEX;
+    const int ex = m.ex0 + tx, ey = m.ey0 + ty;
+    const bool exy = (ex < g.nx) & (ey < g.ny);
+    const int abase = exy ? ey * g.nx + ex : 0;
+    const int astride = g.nx * g.ny;
+    const int xs = (ty + 1) * OXX + tx + 1;  // this element's exchange slot
+    for (int i = tid; i < 3 * 4 * OXN; i += kBlock) (&L.xch[0][0][0])[i] = T(0);
+#pragma unroll
+    for (int set = 0; set < 2; ++set)
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const int q = tid + r * kBlock;
+            if (q < MPN)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) L.plane[set][c][q] = src.value(2 * set + r, c);
+        }
+    const int K = m.ez1 - m.ez0;
+    T top[4][3];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) top[v][0] = top[v][1] = top[v][2] = T(0);
+    T al_next = exy ? alpha[(size_t)m.ez0 * astride + abase] : T(0);
+    T ab[4][3];
+    FaceSums<T> fb;
+    // every valid node slot of plane k: the sum of the four tile elements around it
+    // (zero border outside the tile)
+    auto emit_plane = [&](int k, int buf, auto top_plane) {
+        constexpr bool TOP = decltype(top_plane)::value;
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const int q = tid + r * kBlock;
+            if (sl.base[r] >= 0) {
+                const int o = (q / MPX) * OXX + q % MPX;
+                T y[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    y[c] = (L.xch[c][3][o] + L.xch[c][2][o + 1]) +
+                           (L.xch[c][1][o + OXX] + L.xch[c][0][o + OXX + 1]);
+                E.template emit<TOP>(r, k, buf, y);
+            }
+        }
+        E.rotate();
+    };
+    int bot = 0, topb = 1;  // buffers of node planes ez and ez + 1
+    for (int s = 0; s < K; ++s) {
+        const int ez = m.ez0 + s;  // element layer between node planes ez and ez + 1
+        if (s >= 1) {
+#pragma unroll
+            for (int r = 0; r < 2; ++r) {
+                const int q = tid + r * kBlock;
+                if (q < MPN)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) L.plane[topb][c][q] = src.value(r, c);
+            }
+        }
+        __syncthreads();
+        const T al = al_next;
+        if (s + 1 < K) {
+#pragma unroll
+            for (int r = 0; r < 2; ++r) src.fetch(r, march3_node(g, sl, r, ez + 2));
+            al_next = exy ? alpha[(size_t)(ez + 1) * astride + abase] : T(0);
+        }
+        E.load(ez + 1);
+        if (s == 0) {
+#pragma unroll
+            for (int f = 0; f < 4; ++f) {
+                const int q = (ty + (f >> 1)) * MPX + tx + (f & 1);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) ab[f][c] = L.plane[bot][c][q];
+            }
+            face_sums(ab, fb);
+        }
+        T at[4][3];
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+            const int q = (ty + (f >> 1)) * MPX + tx + (f & 1);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) at[f][c] = L.plane[topb][c][q];
+        }
+        FaceSums<T> ft;
+        face_sums(at, ft);
+        T N[8][3], Y[8][3];
+        neg_wht3_faces(ab, at, fb, ft, N);
+        apply3_from_n(N, L.M, al, Y);
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) L.xch[c][v][xs] = top[v][c] + Y[v][c];
+        __syncthreads();
+        emit_plane(ez, bot, std::false_type{});
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                top[v][c] = Y[v + 4][c];
+                ab[v][c] = at[v][c];
+            }
+        fb = ft;
+        bot = topb;
+        topb = topb == 2 ? 0 : topb + 1;
+    }
+    // the chunk's top node plane (buffer bot now): the last layer's upper corners only,
+    // written once every thread has emitted the plane below
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) L.xch[c][v][xs] = top[v][c];
+    __syncthreads();
+    emit_plane(m.ez1, bot, std::true_type{});
 }
 
 }  // namespace topo

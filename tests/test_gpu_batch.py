@@ -44,7 +44,10 @@ def _batch(p, rhos, prec, rtol):
     return host(u), infos
 
 
-CASES = [W.mbb2d(60, 20), W.cantilever2d(45, 15), W.cantilever3d(12, 6, 6), W.bridge3d(10, 5, 8)]
+# the 36 x 18 x 14 cantilever spans 2 x 3 element tiles of the 3D PCG apply with ragged last
+# tiles in x and y (nodes shared by up to eight blocks)
+CASES = [W.mbb2d(60, 20), W.cantilever2d(45, 15), W.cantilever3d(12, 6, 6), W.bridge3d(10, 5, 8),
+         W.cantilever3d(36, 18, 14)]
 
 
 @pytest.mark.parametrize("p", CASES, ids=lambda p: p.name)
