@@ -10,10 +10,11 @@ mesh (default: the 192x96x96 H8 bridge, B = 16, k = 200, mixed precision):
 Headline value: PCG DOF-iterations per second over the whole timed step
 (sum over fields of N_u x inner PCG iterations / wall time, ROM work included).
 
-The B fields are trust-region candidates around a centre design (seeded smoothed
-perturbations of a seeded smoothed field); the basis is the one the method builds at
-that centre: GramSchmidt([POD of 8 earlier HDM snapshots, u*(centre)]) on the device,
-completed to k columns with smooth cosine fields.
+The B fields are candidate designs of a trust-region subproblem: points on a seeded
+smooth design path through a centre design (a seeded smoothed field); the basis is the
+one the method builds at that centre: GramSchmidt([POD of the HDM snapshots at 8
+earlier centres on the same path, u*(centre)]) on the device, completed to k columns
+with smooth cosine fields and orthonormalised.
 
     python bench.py [--steps K] [--warmup W] [--workload bridge3d_192x96x96]
 """
@@ -150,13 +151,20 @@ def cpu_model():
 # Inputs of the headline workload
 # ----------------------------------------------------------------------------------
 
+def candidate_ts(B):
+    """Path parameters of the B candidate designs of the step: t = 1/32 .. B/32."""
+    return [(b + 1) / 32.0 for b in range(B)]
+
+
 def headline_inputs(W, cfg, B):
-    """The centre design, the B trust-region candidates around it (the step's fields)
-    and SNAPSHOTS earlier centres (the basis window)."""
+    """The centre design, B candidate designs of its trust-region subproblem (the step's
+    fields) and SNAPSHOTS earlier centres (the basis window), all on one seeded smooth
+    design path through the centre (W.path_fields: earlier centres at t = -1/8 .. -1,
+    candidates at t = 1/32 .. B/32)."""
     m = cfg.problem.mesh
     centre = cfg.rho(0)
-    fields = W.trust_region_fields(m, centre, B, cfg.rho_seed0 + 100, step=0.1)
-    snaps = W.trust_region_fields(m, centre, SNAPSHOTS, cfg.rho_seed0 + 200, step=0.3)
+    fields = W.path_fields(m, centre, candidate_ts(B), cfg.rho_seed0 + 100)
+    snaps = W.path_fields(m, centre, [-(j + 1) / 8.0 for j in range(SNAPSHOTS)], cfg.rho_seed0 + 100)
     return centre, fields, snaps
 
 
@@ -533,7 +541,7 @@ def _oracle_cg_worker(args):
     with threadpool_limits(1):
         p = W.bridge3d(*nel)
         centre = W.rho_smoothed(p.mesh, seed0)
-        rho = W.trust_region_fields(p.mesh, centre, 1, seed0 + 100 + b, step=0.1)[0]
+        rho = W.path_fields(p.mesh, centre, [(b + 1) / 32.0], seed0 + 100)[0]
         info = {}
         t0 = time.perf_counter()
         _, res = O.solve_cg(p.mesh, rho, p.f, p.mask, rtol=rtol, info=info)
@@ -572,7 +580,7 @@ def cpu_baseline_leg(cfg, rtol, fields_np, gpu, phi_cols, cores=None):
             "cpu_model": cpu_model(),
             "sample": (f"oracle FP64 Jacobi-CG (sparse assembly + scipy CG, restarted on the true residual) of "
                        f"the bridge problem at {sample_nel[0]}x{sample_nel[1]}x{sample_nel[2]} "
-                       f"({recs[0]['n_dofs']} DOF), {ncores} trust-region candidate fields in parallel "
+                       f"({recs[0]['n_dofs']} DOF), {ncores} candidate designs in parallel "
                        f"processes (one per core, one thread each) to rel. residual {rtol:g}; value = sum of "
                        f"N_u x CG iterations / wall time of the parallel run, assembly included"),
             "seconds": wall, "iters": [r["iters"] for r in recs],
@@ -839,7 +847,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": cfg.name, "fields": B, "k": k, "n_dofs": m.n_dofs, "n_elems": m.n_elems,
                    "rtol": rtol, "precision": args.prec, "max_refine": args.max_refine,
-                   "fields_recipe": "trust-region candidates around a seeded smoothed centre (step 0.1)",
+                   "fields_recipe": "candidate designs on a seeded smooth design path through a smoothed centre (t = 1/32 .. 16/32, amplitude 0.1); basis window from the earlier centres on the same path (t = -1/8 .. -1)",
                    "basis": basis_info},
         "roofline": roofline,
         "rooflines": rooflines,

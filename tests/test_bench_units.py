@@ -37,3 +37,20 @@ def test_kernel_names_match_the_traffic_summaries():
                     for key in json.loads(line[len("traffic-json: "):]):
                         if key.startswith(("k_pcg", "k_cg1")):
                             assert key in names, (path, key)
+
+
+def test_design_path_fields():
+    """The benchmark's candidate designs and earlier centres lie on one smooth path
+    through the centre: t = 0 is the centre itself, and a point moves from it by at most
+    amp (|t| + t^2 / 2), clipped to the density bounds."""
+    import numpy as np
+    import workloads as W
+    m = W.bridge3d(8, 4, 4).mesh
+    centre = W.rho_smoothed(m, 11)
+    ts = [-1.0, -0.125, 0.0, 1 / 32, 0.5]
+    rh = W.path_fields(m, centre, ts, 900, amp=0.1)
+    assert np.array_equal(rh[2], np.clip(centre, 0.05, 1.0))
+    for t, r in zip(ts, rh):
+        assert np.abs(r - centre).max() <= 0.1 * (abs(t) + 0.5 * t * t) + 1e-15
+        assert r.min() >= 0.05 and r.max() <= 1.0
+    assert bench.candidate_ts(16) == [(b + 1) / 32 for b in range(16)]

@@ -143,8 +143,8 @@ def test_config_cantilever3d_96x48x48_golden():
 
 
 def test_config_bridge3d_192x96x96_batched_full():
-    """The benchmark's step at full size: 16 trust-region candidate fields on the
-    192x96x96 bridge solved in one batched mixed-precision call to rel. residual 1e-8.
+    """The benchmark's step at full size: 16 candidate designs (on a smooth design path
+    through the centre, as the benchmark draws them) on the 192x96x96 bridge solved in one batched mixed-precision call to rel. residual 1e-8.
     Every field's true residual recomputed by the oracle element by element in FP64;
     field 0's sensitivity against the oracle's at the same state; the k = 200, B = 16
     contraction on three columns of K_hat against the oracle's products K Phi_j; and
@@ -156,7 +156,7 @@ def test_config_bridge3d_192x96x96_batched_full():
     p, m = cfg.problem, cfg.problem.mesh
     B, k = cfg.batch, cfg.k
     centre = cfg.rho(0)
-    rhos = W.trust_region_fields(m, centre, B, cfg.rho_seed0 + 100, step=0.1)
+    rhos = W.path_fields(m, centre, [(b + 1) / 32.0 for b in range(B)], cfg.rho_seed0 + 100)
     R = dev(rhos, torch.float64)
     mk, f = dev(p.mask, torch.uint8), dev(p.f, torch.float64)
     print("bridge batched solve", flush=True)

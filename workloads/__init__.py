@@ -274,6 +274,21 @@ def trust_region_fields(mesh: Mesh, centre: np.ndarray, count: int, seed: int, s
     return out
 
 
+def path_fields(mesh: Mesh, centre: np.ndarray, ts, seed: int, amp: float = 0.1, lo: float = 0.05,
+                hi: float = 1.0) -> np.ndarray:
+    """Densities on a smooth design path through a trust-region centre, as an optimiser
+    visits them: rho(t) = clip(centre + amp (t d1 + t^2 d2 / 2), lo, hi) with d1, d2
+    seeded smoothed fields in [-1, 1] (rho_smoothed's recipe).  Negative t are the
+    earlier centres (the snapshot window of the basis), small positive t the candidate
+    designs of the current trust-region subproblem.  Returns [len(ts)][n_elems]."""
+    d1 = 2.0 * rho_smoothed(mesh, seed, lo=0.0, hi=1.0) - 1.0
+    d2 = 2.0 * rho_smoothed(mesh, seed + 1, lo=0.0, hi=1.0) - 1.0
+    out = np.empty((len(ts), mesh.n_elems))
+    for b, t in enumerate(ts):
+        out[b] = np.clip(centre + amp * (t * d1 + 0.5 * t * t * d2), lo, hi)
+    return out
+
+
 def rho_batch(mesh: Mesh, base_seed: int, count: int, kind="smoothed"):
     fn = rho_smoothed if kind == "smoothed" else rho_jitter
     return np.stack([fn(mesh, base_seed + i) for i in range(count)])
