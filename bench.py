@@ -112,9 +112,10 @@ def kernel_source_hash():
 
 
 def measured_traffic(workload, kernel):
-    """HBM bytes per launch of `kernel` from the rocprofv3 FETCH_SIZE / WRITE_SIZE
-    summary under profiles/ (each counter scaled by what it reads for a plain copy of
-    known size), or None when there is none or the kernel sources changed since."""
+    """HBM bytes of one field's share of a launch of `kernel` (a batched launch moves
+    this per active field) from the rocprofv3 FETCH_SIZE / WRITE_SIZE summary under
+    profiles/ (each counter scaled by what it reads for a plain copy of known size), or
+    None when there is none or the kernel sources changed since."""
     path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.md")
     if not os.path.exists(path):
         return None
@@ -123,7 +124,7 @@ def measured_traffic(workload, kernel):
             if line.startswith("traffic-json: "):
                 rec = json.loads(line[len("traffic-json: "):]).get(kernel)
                 if rec and rec.get("source_hash") == kernel_source_hash():
-                    return rec["bytes_per_launch"]
+                    return rec["bytes_per_field_launch"]
     return None
 
 
@@ -801,8 +802,10 @@ def main():
         per_launch = pb[kd] * field_iters / kt["launches"]  # bytes of the active fields per launch
         gbs = per_launch / avg_s / 1e9
         kname = pcg_kernel_name(kd, m.dim, word)
+        tf = measured_traffic(cfg.name, kname)
         return {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": gbs / HBM_PEAK_GBS, "traffic": measured_traffic(cfg.name, kname),
+                "frac": gbs / HBM_PEAK_GBS,
+                "traffic": None if tf is None else tf * field_iters / kt["launches"],
                 "kernel": kname, "bytes_per_launch": per_launch, "bytes_per_field_launch": pb[kd],
                 "mean_active_fields": field_iters / kt["launches"], "avg_us": kt["avg_us"]}
 

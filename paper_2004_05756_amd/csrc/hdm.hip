@@ -118,6 +118,24 @@ struct SrcPlain {
     __device__ __forceinline__ T value(int slot, int c) const { return v[slot][c]; }
 };
 
+// Source of the element-once march: p_new = z + beta p_old at nodes of the grid.
+template <typename T>
+struct SrcDirection3 {
+    const T* __restrict__ z;
+    const T* __restrict__ p;
+    T beta;
+    unsigned nn;
+    T zv[4][3], pv[4][3];
+    __device__ __forceinline__ void fetch(int slot, unsigned node) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            zv[slot][c] = z[c * nn + node];
+            pv[slot][c] = p[c * nn + node];
+        }
+    }
+    __device__ __forceinline__ T value(int slot, int c) const { return zv[slot][c] + beta * pv[slot][c]; }
+};
+
 template <typename T>
 struct SrcDirection {  // p_new = z + beta p_old
     const T* __restrict__ z;
@@ -406,10 +424,8 @@ struct PcgEmit3 {
     __device__ __forceinline__ void load(int k) {
 #pragma unroll
         for (int r = 0; r < 2; ++r) {
-            const int n = march3_node(g, sl, r, k);
-            const int nn = n >= 0 ? n : 0;
-            const unsigned b0 = mask[nn], b1 = mask[g.n_nodes + nn], b2 = mask[2 * (size_t)g.n_nodes + nn];
-            mk_next[r] = n >= 0 ? (b0 | (b1 << 8) | (b2 << 16)) : 0u;
+            const unsigned n = once3_node(sl, r, k), nn = (unsigned)g.n_nodes;
+            mk_next[r] = (unsigned)mask[n] | ((unsigned)mask[nn + n] << 8) | ((unsigned)mask[2 * nn + n] << 16);
         }
     }
     __device__ __forceinline__ void rotate() {
@@ -426,15 +442,17 @@ struct PcgEmit3 {
             si = (int)side_index(sg, s, m.ex0 + qs % MPX, m.ey0 + qs / MPX, k);
         }
         T* dst = s ? side + si : q + n;
-        const size_t cs = s ? (size_t)sg.total : (size_t)g.n_nodes;
+        const unsigned cs = s ? (unsigned)sg.total : (unsigned)g.n_nodes;
+        T d = T(0);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const T pn = L.plane[buf][c][qs];
             const T qv = (mk[r] >> (8 * c)) & 0xffu ? T(0) : y[c];
             dst[c * cs] = qv;
-            if (!s) p_new[c * (size_t)g.n_nodes + n] = pn;
-            pq += (double)pn * (double)qv;
+            if (!s) p_new[c * (unsigned)g.n_nodes + n] = pn;
+            d += pn * qv;
         }
+        pq += (double)d;
     }
 };
 
@@ -471,11 +489,11 @@ __global__ __launch_bounds__(kBlock, sizeof(T) == 4 ? 3 : 2) void k_pcg_apply3(G
     const OnceBlock m = once3_block(g, fb.blk);
     for (int i = threadIdx.x; i < kFacSize; i += blockDim.x) L.M[i] = M[i];
     const MarchSlots sl = once3_slots(g, m);
-    SrcDirection<T> src{z, p_old, T(0), g.n_nodes};
+    SrcDirection3<T> src{z, p_old, T(0), (unsigned)g.n_nodes};
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
-        src.fetch(r, march3_node(g, sl, r, m.ez0));
-        src.fetch(2 + r, march3_node(g, sl, r, m.ez0 + 1));
+        src.fetch(r, once3_node(sl, r, m.ez0));
+        src.fetch(2 + r, once3_node(sl, r, m.ez0 + 1));
     }
     PcgEmit3<T> E(g, m, sl, sg, L, mask, p_new, q, side);
     E.load(m.ez0);

@@ -276,8 +276,18 @@ __device__ __forceinline__ int once3_section(const Grid& g, const OnceBlock& m, 
            (k == m.ez1 && k < g.nz ? 4 : 0);
 }
 
-// The march.  Src as for march3_run, except that the caller has fetched planes ez0
-// (slots 0, 1) and ez0 + 1 (slots 2, 3).  Emit is an object with
+// Node of slot r at node plane k for the element-once march, clamped to a node of the
+// grid: a slot outside the grid (ragged tile) reads some node's finite values, which
+// reach only the elements outside the mesh, whose alpha is zero.
+__device__ __forceinline__ unsigned once3_node(const MarchSlots& sl, int r, int k) {
+    return (unsigned)((sl.base[r] >= 0 ? sl.base[r] : 0) + k * sl.pstride);
+}
+
+// The march.  Src:
+//   fetch(int slot, unsigned node)  issue the loads of node
+//   value(int slot, int c)          the fetched value
+// the caller has fetched planes ez0 (slots 0, 1) and ez0 + 1 (slots 2, 3).  Emit is an
+// object with
 //   load(int k)    issue the loads of what the emit of node plane k needs (called one
 //                  element layer ahead, after the first barrier of the layer)
 //   emit<TOP>(int r, int k, int buf, const T (&y)[3])  y = this block's part of (K x)
@@ -295,8 +305,8 @@ __device__ __forceinline__ void once3_run(const Grid& g, const OnceBlock& m, con
     const int tx = tid % MEX, ty = tid / MEX;
     const int ex = m.ex0 + tx, ey = m.ey0 + ty;
     const bool exy = (ex < g.nx) & (ey < g.ny);
-    const int abase = exy ? ey * g.nx + ex : 0;
-    const int astride = g.nx * g.ny;
+    const unsigned abase = exy ? ey * g.nx + ex : 0;
+    const unsigned astride = g.nx * g.ny;
     const int xs = (ty + 1) * OXX + tx + 1;  // this element's exchange slot
     for (int i = tid; i < 3 * 4 * OXN; i += kBlock) (&L.xch[0][0][0])[i] = T(0);
 #pragma unroll
@@ -309,15 +319,10 @@ __device__ __forceinline__ void once3_run(const Grid& g, const OnceBlock& m, con
                 for (int c = 0; c < 3; ++c) L.plane[set][c][q] = src.value(2 * set + r, c);
         }
     const int K = m.ez1 - m.ez0;
-    T top[4][3];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) top[v][0] = top[v][1] = top[v][2] = T(0);
-    T al_next = exy ? alpha[(size_t)m.ez0 * astride + abase] : T(0);
-    T ab[4][3];
-    FaceSums<T> fb;
+    T al_next = exy ? alpha[m.ez0 * astride + abase] : T(0);
     // every valid node slot of plane k: the sum of the four tile elements around it
     // (zero border outside the tile)
-    auto emit_plane = [&](int k, int buf, auto top_plane) {
+    auto emit_plane = [&](int k, int buf, auto top_plane) __attribute__((always_inline)) {
         constexpr bool TOP = decltype(top_plane)::value;
 #pragma unroll
         for (int r = 0; r < 2; ++r) {
@@ -335,7 +340,10 @@ __device__ __forceinline__ void once3_run(const Grid& g, const OnceBlock& m, con
         E.rotate();
     };
     int bot = 0, topb = 1;  // buffers of node planes ez and ez + 1
-    for (int s = 0; s < K; ++s) {
+    // one element layer: bottom face (ab, fb) in, top face (at, ft) out; the upper
+    // corners of the layer below in tin, this layer's in tout
+    auto layer = [&](int s, const T (&ab)[4][3], const FaceSums<T>& fb, T (&at)[4][3], FaceSums<T>& ft,
+                     const T (&tin)[4][3], T (&tout)[4][3]) __attribute__((always_inline)) {
         const int ez = m.ez0 + s;  // element layer between node planes ez and ez + 1
         if (s >= 1) {
 #pragma unroll
@@ -350,27 +358,16 @@ __device__ __forceinline__ void once3_run(const Grid& g, const OnceBlock& m, con
         const T al = al_next;
         if (s + 1 < K) {
 #pragma unroll
-            for (int r = 0; r < 2; ++r) src.fetch(r, march3_node(g, sl, r, ez + 2));
-            al_next = exy ? alpha[(size_t)(ez + 1) * astride + abase] : T(0);
+            for (int r = 0; r < 2; ++r) src.fetch(r, once3_node(sl, r, ez + 2));
+            al_next = exy ? alpha[(ez + 1) * astride + abase] : T(0);
         }
         E.load(ez + 1);
-        if (s == 0) {
-#pragma unroll
-            for (int f = 0; f < 4; ++f) {
-                const int q = (ty + (f >> 1)) * MPX + tx + (f & 1);
-#pragma unroll
-                for (int c = 0; c < 3; ++c) ab[f][c] = L.plane[bot][c][q];
-            }
-            face_sums(ab, fb);
-        }
-        T at[4][3];
 #pragma unroll
         for (int f = 0; f < 4; ++f) {
             const int q = (ty + (f >> 1)) * MPX + tx + (f & 1);
 #pragma unroll
             for (int c = 0; c < 3; ++c) at[f][c] = L.plane[topb][c][q];
         }
-        FaceSums<T> ft;
         face_sums(at, ft);
         T N[8][3], Y[8][3];
         neg_wht3_faces(ab, at, fb, ft, N);
@@ -378,19 +375,37 @@ __device__ __forceinline__ void once3_run(const Grid& g, const OnceBlock& m, con
 #pragma unroll
         for (int v = 0; v < 4; ++v)
 #pragma unroll
-            for (int c = 0; c < 3; ++c) L.xch[c][v][xs] = top[v][c] + Y[v][c];
+            for (int c = 0; c < 3; ++c) {
+                L.xch[c][v][xs] = tin[v][c] + Y[v][c];
+                tout[v][c] = Y[v + 4][c];
+            }
         __syncthreads();
         emit_plane(ez, bot, std::false_type{});
+        bot = topb;
+        topb = topb == 2 ? 0 : topb + 1;
+    };
+    T fa[4][3], fbv[4][3], t0[4][3], t1[4][3];
+    FaceSums<T> sa, sb;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) t0[v][0] = t0[v][1] = t0[v][2] = T(0);
+    __syncthreads();  // the prologue planes are staged
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+        const int q = (ty + (f >> 1)) * MPX + tx + (f & 1);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) fa[f][c] = L.plane[0][c][q];
+    }
+    face_sums(fa, sa);
+    for (int s = 0; s < K; ++s) {
+        layer(s, fa, sa, fbv, sb, t0, t1);
 #pragma unroll
         for (int v = 0; v < 4; ++v)
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                top[v][c] = Y[v + 4][c];
-                ab[v][c] = at[v][c];
+                fa[v][c] = fbv[v][c];
+                t0[v][c] = t1[v][c];
             }
-        fb = ft;
-        bot = topb;
-        topb = topb == 2 ? 0 : topb + 1;
+        sa = sb;
     }
     // the chunk's top node plane (buffer bot now): the last layer's upper corners only,
     // written once every thread has emitted the plane below
@@ -398,7 +413,7 @@ __device__ __forceinline__ void once3_run(const Grid& g, const OnceBlock& m, con
 #pragma unroll
     for (int v = 0; v < 4; ++v)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) L.xch[c][v][xs] = top[v][c];
+        for (int c = 0; c < 3; ++c) L.xch[c][v][xs] = t0[v][c];
     __syncthreads();
     emit_plane(m.ez1, bot, std::true_type{});
 }
