@@ -17,6 +17,7 @@
 #include <cmath>
 #include <cstddef>
 #include <cstdlib>
+#include <type_traits>
 #include <vector>
 
 #include <hip/hip_ext.h>
@@ -118,6 +119,12 @@ struct SrcPlain {
     __device__ __forceinline__ T value(int slot, int c) const { return v[slot][c]; }
 };
 
+// Offsets of the 3D PCG apply's loads and stores: 32-bit for float (the compiler then
+// forms no 64-bit addresses), 64-bit for double (whose register budget the 32-bit form
+// overruns).
+template <typename T>
+using ApplyOff = typename std::conditional<sizeof(T) == 4, unsigned, size_t>::type;
+
 // Source of the element-once march: p_new = z + beta p_old at nodes of the grid.
 template <typename T>
 struct SrcDirection3 {
@@ -129,8 +136,8 @@ struct SrcDirection3 {
     __device__ __forceinline__ void fetch(int slot, unsigned node) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            zv[slot][c] = z[c * nn + node];
-            pv[slot][c] = p[c * nn + node];
+            zv[slot][c] = z[(ApplyOff<T>)c * nn + node];
+            pv[slot][c] = p[(ApplyOff<T>)c * nn + node];
         }
     }
     __device__ __forceinline__ T value(int slot, int c) const { return zv[slot][c] + beta * pv[slot][c]; }
@@ -385,7 +392,7 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_apply2(Grid g, const T* __res
 // Emitter of the 3D PCG apply (once3_run): at each node slot of a plane the block
 // writes p_new and its part of q when it is the node's primary block, else its part
 // into the side section the node belongs to for this block; masked DOFs get a zero part.
-// The node's mask bytes are loaded one element layer ahead.  pq sums p_new . part over
+// The node's mask bytes are loaded ahead of the emit (by plane parity).  pq sums p_new . part over
 // every part written.
 template <typename T>
 struct PcgEmit3 {
@@ -398,10 +405,9 @@ struct PcgEmit3 {
     T* __restrict__ p_new;
     T* __restrict__ q;
     T* __restrict__ side;
-    int sec[2];      // side section of the slot on the planes below the chunk's top (0: primary)
-    int sidx[2];     // its side index at plane 0 ...
-    int sstr[2];     // ... and per plane
-    unsigned mk[2], mk_next[2];  // mask bytes of the slot's node (component c at bits 8c)
+    int sinfo[2];    // side section of the slot on the planes below the chunk's top (bits
+                     // 0-1, 0: primary) and its side index at plane 0 (bits 2-)
+    unsigned mk0[2], mk1[2];  // mask bytes of the slot's node at even / odd planes (component c at bits 8c)
     double pq = 0.0;
 
     __device__ __forceinline__ PcgEmit3(const Grid& g_, const OnceBlock& m_, const MarchSlots& sl_,
@@ -411,45 +417,43 @@ struct PcgEmit3 {
 #pragma unroll
         for (int r = 0; r < 2; ++r) {
             const int qs = threadIdx.x + r * kBlock;
-            const int s = once3_section(g, m, qs, 0);  // no z bit below the top plane
-            sec[r] = sl.base[r] >= 0 ? s : 0;
+            const int s = sl.base[r] >= 0 ? once3_section(g, m, qs, 0) : 0;  // no z bit below the top
             const int i = m.ex0 + qs % MPX, j = m.ey0 + qs / MPX;
-            const long long i0 = s ? side_index(sg, s, i, j, 0) : 0;
-            const long long i1 = s ? side_index(sg, s, i, j, 1) : 0;
-            sidx[r] = (int)i0;
-            sstr[r] = (int)(i1 - i0);
-            mk[r] = mk_next[r] = 0;
+            sinfo[r] = s | (s ? (int)side_index(sg, s, i, j, 0) << 2 : 0);
+            mk0[r] = mk1[r] = 0;
         }
     }
     __device__ __forceinline__ void load(int k) {
 #pragma unroll
         for (int r = 0; r < 2; ++r) {
             const unsigned n = once3_node(sl, r, k), nn = (unsigned)g.n_nodes;
-            mk_next[r] = (unsigned)mask[n] | ((unsigned)mask[nn + n] << 8) | ((unsigned)mask[2 * nn + n] << 16);
+            const unsigned v = (unsigned)mask[n] | ((unsigned)mask[nn + n] << 8) | ((unsigned)mask[2 * nn + n] << 16);
+            if (k & 1) mk1[r] = v;
+            else mk0[r] = v;
         }
-    }
-    __device__ __forceinline__ void rotate() {
-        mk[0] = mk_next[0];
-        mk[1] = mk_next[1];
     }
     template <bool TOP>
     __device__ __forceinline__ void emit(int r, int k, int buf, const T (&y)[3]) {
         const int qs = threadIdx.x + r * kBlock;
         const int n = sl.base[r] + k * sl.pstride;
-        int s = sec[r], si = sidx[r] + k * sstr[r];
+        // sections 1-3 advance by one x-y layer of the section per plane
+        int s = sinfo[r] & 3;
+        const int sstr = s == 1 ? sg.nbx * sg.nny : s == 2 ? sg.nnx * sg.nby : sg.nbx * sg.nby;
+        int si = (sinfo[r] >> 2) + k * sstr;
         if (TOP && k < g.nz) {  // the chunk's top plane: the block above is primary
             s = once3_section(g, m, qs, k);
             si = (int)side_index(sg, s, m.ex0 + qs % MPX, m.ey0 + qs / MPX, k);
         }
+        const unsigned mk = (k & 1) ? mk1[r] : mk0[r];
         T* dst = s ? side + si : q + n;
-        const unsigned cs = s ? (unsigned)sg.total : (unsigned)g.n_nodes;
+        const ApplyOff<T> cs = s ? (ApplyOff<T>)sg.total : (ApplyOff<T>)g.n_nodes;
         T d = T(0);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const T pn = L.plane[buf][c][qs];
-            const T qv = (mk[r] >> (8 * c)) & 0xffu ? T(0) : y[c];
+            const T qv = (mk >> (8 * c)) & 0xffu ? T(0) : y[c];
             dst[c * cs] = qv;
-            if (!s) p_new[c * (unsigned)g.n_nodes + n] = pn;
+            if (!s) p_new[c * (ApplyOff<T>)g.n_nodes + n] = pn;
             d += pn * qv;
         }
         pq += (double)d;
@@ -496,8 +500,6 @@ __global__ __launch_bounds__(kBlock, sizeof(T) == 4 ? 3 : 2) void k_pcg_apply3(G
         src.fetch(2 + r, once3_node(sl, r, m.ez0 + 1));
     }
     PcgEmit3<T> E(g, m, sl, sg, L, mask, p_new, q, side);
-    E.load(m.ez0);
-    E.rotate();
     T tb;
     if (pcg_apply_scalars(pb, sb, ps, nrz, parity, fb.blk == 0, tb, lds)) return;
     src.beta = tb;
@@ -836,7 +838,7 @@ __global__ __launch_bounds__(kPcgBlock) void k_cg1_step2(
 // s = K p recomputed for the direction of the step launched at parity lp, into the set
 // that step wrote.  The recursion s_i = w_i + beta_i s_{i-1} carries each rounding of
 // K u through about 1 / (1 - beta) iterations (beta ~ 0.98 here), which would let the
-// recursive residual drift from the true one; refreshing s every kPcgChunk iterations
+// recursive residual drift from the true one; refreshing s every kCg1Refresh iterations
 // bounds that sum.  Reads p (neighbourhood) only and writes s (own node).
 template <typename T>
 __global__ __launch_bounds__(kPcgBlock) void k_cg1_refresh2(Grid g, const T* __restrict__ alpha,
@@ -1239,7 +1241,7 @@ static void cg1_step(Ctx* ctx, const Grid& g, const PcgBufs<T>& w, const PcgGeom
 
 // ----------------------------------------------------------------------------------
 // Segment control on the device.  A field's recursion runs in segments; when one ends
-// (its state reports done), the end of the 16-iteration chunk in which it ended adds
+// (its state reports done), the end of the chunk (graph replay) in which it ended adds
 // the segment's correction to u in float64, recomputes the true residual f - K u in
 // float64, and either retires the field (converged, iteration limit, stagnation,
 // breakdown) or starts its next segment: continued with the same search direction
@@ -1431,7 +1433,15 @@ __global__ void k_skip_from_solve(int B, const int* __restrict__ solve, int* __r
     if (b < B) skip[b] = solve[b] ? 0 : 1;
 }
 
-constexpr int kPcgChunk = 16;  // iterations per graph replay (even)
+// Iterations per graph replay: 16, or 64 when the batch is small (N_u B <= 4M DOF), where
+// the chunk end (segment control, ~8 small kernels) would cost a third of a 16-iteration
+// chunk.  Segments start at chunk ends, which are multiples of 16 launches either way,
+// and the one-reduction recursion refreshes s every 16 launches, so a field's arithmetic
+// does not depend on the chunk length (nor on the batch that chose it).
+constexpr int kCg1Refresh = 16;
+static int pcg_chunk_len(const Grid& g, int B) {
+    return (long long)g.n_dofs * B <= (4LL << 20) ? 64 : 16;
+}
 
 // Start of a segment for the fields with a nonzero scale fsc[b] (their states written
 // by the segment controller): its partials for the first launch of the next chunk
@@ -1459,13 +1469,12 @@ static void phase_start(const Grid& g, const PcgBufs<T>& w, const PcgGeom& pg, b
     }
 }
 
-// Iteration `it` of a chunk sequence (its launch parity is it & 1; chunks of kPcgChunk
-// iterations start at it = 1 mod kPcgChunk).  The one-reduction recursion refreshes s
-// after every iteration it with it % kPcgChunk == 0, the last of each chunk.
+// Iteration `it` of a chunk (its launch parity is it & 1; chunks start at it = 1).  The
+// one-reduction recursion refreshes s after every iteration it with it % kCg1Refresh == 0.
 template <int DIM, typename T>
 static void phase_iteration(Ctx* ctx, const Grid& g, const PcgBufs<T>& w, const PcgGeom& pg, bool one_red,
                             long long it, LaunchSink& L, int timing) {
-    if (one_red) cg1_step<T>(ctx, g, w, pg, (int)(it & 1), L, timing, it % kPcgChunk == 0);
+    if (one_red) cg1_step<T>(ctx, g, w, pg, (int)(it & 1), L, timing, it % kCg1Refresh == 0);
     else pcg_iteration<DIM, T>(ctx, g, w, pg, (int)(it & 1), L, timing);
 }
 
@@ -1603,7 +1612,7 @@ static void chunk_end(const Grid& g, const Grid& gres, const double* K64, const 
 
 // Batched HDM solve of the fields with solve[b] != 0 (the others are left untouched):
 // one Krylov recursion per field in precision T, cut into segments (see the segment
-// controller above), iterations replayed as graphs of one chunk each (kPcgChunk
+// controller above), iterations replayed as graphs of one chunk each (pcg_chunk_len
 // iterations and the chunk end); the host launches chunks and checks the fields' live
 // flags one chunk behind.  The inner system of each field is scaled by 1 / ||f|| so
 // that float32 values stay O(1).  2D float64 solves run the one-reduction recursion
@@ -1703,8 +1712,9 @@ static int hdm_batch_impl(Ctx* ctx, const topo_mesh& m, const Grid& g0, const El
     }
     // mode: kTimeOff (graph construction), kTimeForced (a timing sample replacing a
     // replay: its first two iterations timed), kTimeSampled (no graphs)
+    const int chunk_len = pcg_chunk_len(g, B);
     auto chunk = [&](LaunchSink& L, int mode) {
-        for (int q = 0; q < kPcgChunk; ++q) {
+        for (int q = 0; q < chunk_len; ++q) {
             const int tm = mode == kTimeForced ? (q < 2 ? kTimeForced : kTimeOff) : mode;
             phase_iteration<DIM, T>(ctx, g, w, pg, one_red, 1 + q, L, tm);
         }
@@ -1713,7 +1723,7 @@ static int hdm_batch_impl(Ctx* ctx, const topo_mesh& m, const Grid& g0, const El
     hipGraphExec_t exec = nullptr;
     if (graphs_enabled()) {
         std::vector<uintptr_t> key = {(uintptr_t)0xB7C7, (uintptr_t)DIM, sizeof(T), (uintptr_t)one_red,
-                                      (uintptr_t)B, (uintptr_t)pg.napp, (uintptr_t)pg.nupd, (uintptr_t)kPcgChunk,
+                                      (uintptr_t)B, (uintptr_t)pg.napp, (uintptr_t)pg.nupd, (uintptr_t)chunk_len,
                                       (uintptr_t)g.nx, (uintptr_t)g.ny, (uintptr_t)g.nz, (uintptr_t)g.mtarget,
                                       (uintptr_t)gres.mtarget, (uintptr_t)w.alpha, (uintptr_t)w.K,
                                       (uintptr_t)w.mask, (uintptr_t)w.winv, (uintptr_t)w.x, (uintptr_t)w.r,
@@ -1755,11 +1765,11 @@ static int hdm_batch_impl(Ctx* ctx, const topo_mesh& m, const Grid& g0, const El
                 break;
             }
         }
-        issued += kPcgChunk;
+        issued += chunk_len;
         ++replays;
         if (every > 0)
             for (int kid : kids)
-                if (kid >= 0) ctx->timing.launched[kid] += kPcgChunk;
+                if (kid >= 0) ctx->timing.launched[kid] += chunk_len;
         hipError_t e = hipGetLastError();
         if (e == hipSuccess) e = hipMemcpyAsync(h_live + (size_t)slot * B, c.live, B * sizeof(int), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipEventRecord(ev[slot], s);

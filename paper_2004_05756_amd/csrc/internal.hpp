@@ -311,26 +311,29 @@ __host__ __device__ inline int once3_blocks(const Grid& g) {
 // boundaries (index = boundary number - 1), along the others every node; the sections
 // follow each other in the order of s, one component after the other ([c][total]).
 struct SideGeom {
-    int nb[3];        // interior block boundaries along x, y, z
-    int nn[3];        // nodes along x, y, z
-    int kz;           // element layers per chunk
-    long long total;  // nodes over all sections
+    int nbx, nby, nbz;  // interior block boundaries along x, y, z
+    int nnx, nny, nnz;  // nodes along x, y, z
+    int kz;             // element layers per chunk
+    long long total;    // nodes over all sections
+    // extent of section s along x / y / z
+    __host__ __device__ int ex(int s) const { return s & 1 ? nbx : nnx; }
+    __host__ __device__ int ey(int s) const { return s & 2 ? nby : nny; }
+    __host__ __device__ int ez(int s) const { return s & 4 ? nbz : nnz; }
 };
 
 __host__ __device__ inline long long side_count(const SideGeom& sg, int s) {
-    return (long long)(s & 1 ? sg.nb[0] : sg.nn[0]) * (s & 2 ? sg.nb[1] : sg.nn[1]) *
-           (s & 4 ? sg.nb[2] : sg.nn[2]);
+    return (long long)sg.ex(s) * sg.ey(s) * sg.ez(s);
 }
 
 __host__ __device__ inline SideGeom side_geom(const Grid& g) {
     SideGeom sg;
     sg.kz = once3_kz(g);
-    sg.nb[0] = once3_tiles_x(g) - 1;
-    sg.nb[1] = once3_tiles_y(g) - 1;
-    sg.nb[2] = once3_chunks(g) - 1;
-    sg.nn[0] = g.nx1;
-    sg.nn[1] = g.ny1;
-    sg.nn[2] = g.nz1;
+    sg.nbx = once3_tiles_x(g) - 1;
+    sg.nby = once3_tiles_y(g) - 1;
+    sg.nbz = once3_chunks(g) - 1;
+    sg.nnx = g.nx1;
+    sg.nny = g.ny1;
+    sg.nnz = g.nz1;
     sg.total = 0;
     for (int t = 1; t < 8; ++t) sg.total += side_count(sg, t);
     return sg;
@@ -344,7 +347,7 @@ __host__ __device__ inline long long side_index(const SideGeom& sg, int s, int i
     const int a = s & 1 ? i / MEX - 1 : i;
     const int b = s & 2 ? j / MEY - 1 : j;
     const int c = s & 4 ? k / sg.kz - 1 : k;
-    return off + ((long long)c * (s & 2 ? sg.nb[1] : sg.nn[1]) + b) * (s & 1 ? sg.nb[0] : sg.nn[0]) + a;
+    return off + ((long long)c * sg.ey(s) + b) * sg.ex(s) + a;
 }
 
 // Axes along which node (i, j, k) lies on an interior block boundary (bit per axis).

@@ -288,15 +288,14 @@ __device__ __forceinline__ unsigned once3_node(const MarchSlots& sl, int r, int 
 //   value(int slot, int c)          the fetched value
 // the caller has fetched planes ez0 (slots 0, 1) and ez0 + 1 (slots 2, 3).  Emit is an
 // object with
-//   load(int k)    issue the loads of what the emit of node plane k needs (called one
-//                  element layer ahead, after the first barrier of the layer)
+//   load(int k)    issue the loads of what the emit of node plane k needs (one element
+//                  layer ahead of that emit; at most two planes are pending)
 //   emit<TOP>(int r, int k, int buf, const T (&y)[3])  y = this block's part of (K x)
 //                  at the node of slot r at plane k, whose values x are in L.plane[buf]
 //                  (a plane buffer is written again only two layers later, after a
-//                  barrier every emitter has passed); TOP: k is the chunk's top plane
-//   rotate()       the loads of the last load() become those of the next emit
-// Emit has loaded plane ez0 before the call.  Barriers per element layer: after the
-// plane is staged and after the corner exchange.
+//                  barrier every emitter of that plane has passed); TOP: k is the
+//                  chunk's top plane
+// Barriers per element layer: after the plane is staged and after the corner exchange.
 template <typename T, typename Src, typename Emit>
 __device__ __forceinline__ void once3_run(const Grid& g, const OnceBlock& m, const MarchSlots& sl,
                                           const T* __restrict__ alpha, OnceLds<T>& L, Src& src,
@@ -320,8 +319,8 @@ __device__ __forceinline__ void once3_run(const Grid& g, const OnceBlock& m, con
         }
     const int K = m.ez1 - m.ez0;
     T al_next = exy ? alpha[m.ez0 * astride + abase] : T(0);
-    // every valid node slot of plane k: the sum of the four tile elements around it
-    // (zero border outside the tile)
+    // every valid node slot of plane k (plane buffer buf): the sum of the four tile
+    // elements around it (zero border outside the tile)
     auto emit_plane = [&](int k, int buf, auto top_plane) __attribute__((always_inline)) {
         constexpr bool TOP = decltype(top_plane)::value;
 #pragma unroll
@@ -332,18 +331,17 @@ __device__ __forceinline__ void once3_run(const Grid& g, const OnceBlock& m, con
                 T y[3];
 #pragma unroll
                 for (int c = 0; c < 3; ++c)
-                    y[c] = (L.xch[c][3][o] + L.xch[c][2][o + 1]) +
-                           (L.xch[c][1][o + OXX] + L.xch[c][0][o + OXX + 1]);
+                    y[c] = (L.xch[c][3][o] + L.xch[c][2][o + 1]) + (L.xch[c][1][o + OXX] + L.xch[c][0][o + OXX + 1]);
                 E.template emit<TOP>(r, k, buf, y);
             }
         }
-        E.rotate();
     };
     int bot = 0, topb = 1;  // buffers of node planes ez and ez + 1
-    // one element layer: bottom face (ab, fb) in, top face (at, ft) out; the upper
-    // corners of the layer below in tin, this layer's in tout
+    // one element layer s: bottom face (ab, fb) in, top face (at, ft) out; the upper
+    // corners of the layer below in top, replaced by this layer's (each entry read
+    // before it is replaced)
     auto layer = [&](int s, const T (&ab)[4][3], const FaceSums<T>& fb, T (&at)[4][3], FaceSums<T>& ft,
-                     const T (&tin)[4][3], T (&tout)[4][3]) __attribute__((always_inline)) {
+                     T (&top)[4][3]) __attribute__((always_inline)) {
         const int ez = m.ez0 + s;  // element layer between node planes ez and ez + 1
         if (s >= 1) {
 #pragma unroll
@@ -376,18 +374,19 @@ __device__ __forceinline__ void once3_run(const Grid& g, const OnceBlock& m, con
         for (int v = 0; v < 4; ++v)
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                L.xch[c][v][xs] = tin[v][c] + Y[v][c];
-                tout[v][c] = Y[v + 4][c];
+                L.xch[c][v][xs] = top[v][c] + Y[v][c];
+                top[v][c] = Y[v + 4][c];
             }
         __syncthreads();
         emit_plane(ez, bot, std::false_type{});
         bot = topb;
         topb = topb == 2 ? 0 : topb + 1;
     };
-    T fa[4][3], fbv[4][3], t0[4][3], t1[4][3];
+    T fa[4][3], fbv[4][3], top[4][3];
     FaceSums<T> sa, sb;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) t0[v][0] = t0[v][1] = t0[v][2] = T(0);
+    for (int v = 0; v < 4; ++v) top[v][0] = top[v][1] = top[v][2] = T(0);
+    E.load(m.ez0);
     __syncthreads();  // the prologue planes are staged
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
@@ -397,14 +396,11 @@ __device__ __forceinline__ void once3_run(const Grid& g, const OnceBlock& m, con
     }
     face_sums(fa, sa);
     for (int s = 0; s < K; ++s) {
-        layer(s, fa, sa, fbv, sb, t0, t1);
+        layer(s, fa, sa, fbv, sb, top);
 #pragma unroll
         for (int v = 0; v < 4; ++v)
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                fa[v][c] = fbv[v][c];
-                t0[v][c] = t1[v][c];
-            }
+            for (int c = 0; c < 3; ++c) fa[v][c] = fbv[v][c];
         sa = sb;
     }
     // the chunk's top node plane (buffer bot now): the last layer's upper corners only,
@@ -413,7 +409,7 @@ __device__ __forceinline__ void once3_run(const Grid& g, const OnceBlock& m, con
 #pragma unroll
     for (int v = 0; v < 4; ++v)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) L.xch[c][v][xs] = t0[v][c];
+        for (int c = 0; c < 3; ++c) L.xch[c][v][xs] = top[v][c];
     __syncthreads();
     emit_plane(m.ez1, bot, std::true_type{});
 }
