@@ -473,8 +473,9 @@ __global__ __launch_bounds__(kBlock, sizeof(T) == 4 ? 3 : 2) void k_pcg_apply3(G
                                                        const uint8_t* __restrict__ mask,
                                                        const T* __restrict__ z, T* __restrict__ p0,
                                                        T* __restrict__ p1, T* __restrict__ q,
-                                                       T* __restrict__ side, double* __restrict__ part,
-                                                       PcgState* st, int ps, int nrz, int lp) {
+                                                       T* __restrict__ side, const SideGeom sg,
+                                                       double* __restrict__ part, PcgState* st, int ps,
+                                                       int nrz, int lp) {
     const FieldBlock fb = field_block();
     PcgState* sb = st + fb.field;
     if (sb->done) return;
@@ -482,7 +483,6 @@ __global__ __launch_bounds__(kBlock, sizeof(T) == 4 ? 3 : 2) void k_pcg_apply3(G
     __shared__ double lds[48];
     const int parity = lp ^ sb->poff;
     const size_t fo = (size_t)fb.field * g.n_dofs;
-    const SideGeom sg = side_geom(g);
     alpha += (size_t)fb.field * g.n_elems;
     z += fo;
     const T* p_old = (parity ? p1 : p0) + fo;
@@ -518,7 +518,7 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_update(Grid g, const T* __res
                                                        const T* __restrict__ p0,
                                                        const T* __restrict__ p1,
                                                        const T* __restrict__ q,
-                                                       const T* __restrict__ side,
+                                                       const T* __restrict__ side, const SideGeom sg,
                                                        double* __restrict__ part, PcgState* st,
                                                        int ps, int npq, int lp) {
     const int f = blockIdx.y;
@@ -551,7 +551,6 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_update(Grid g, const T* __res
         if constexpr (DIM == 3) {
             // q = the primary block's part + the parts of the blocks below the node, in
             // the order of their side sections
-            const SideGeom sg = side_geom(g);
             const int i = n % g.nx1, jk = n / g.nx1, j = jk % g.ny1, k = jk / g.ny1;
             const int ax = side_axes(g, sg, i, j, k);
             if (ax) {
@@ -1177,6 +1176,7 @@ struct PcgBufs {
     T ik[3];           // 1 / K_e[c][c]
     T *r, *z, *p0, *p1, *q, *e0, *e1;  // [B][N_u]
     T* side;           // 3D: [B][3][side total] the apply's parts of shared nodes
+    SideGeom sg;       // 3D: their sections (from the apply's launch geometry)
     double* x;         // [B][N_u] the segment's correction, accumulated in float64
     double* part;      // [B][kPcgParts][ps]
     PcgState* st;      // [B]
@@ -1199,7 +1199,7 @@ static void pcg_iteration(Ctx* ctx, const Grid& g, const PcgBufs<T>& w, const Pc
               w.q, w.part, w.st, pg.ps, pg.nrz, lp);
         else
             L(fn, dim3(pg.napp, w.B), dim3(kBlock), g, w.alpha, w.K, w.mask, (const T*)w.z, w.p0, w.p1, w.q,
-              w.side, w.part, w.st, pg.ps, pg.nrz, lp);
+              w.side, w.sg, w.part, w.st, pg.ps, pg.nrz, lp);
     }
     if (pg.npq == 1 && pg.napp > 1)
         L((const void*)k_partials_sum<PcgState>, dim3(w.B), dim3(1024), w.part, pg.ps, pg.napp, 0, 0, -1, 0,
@@ -1209,8 +1209,8 @@ static void pcg_iteration(Ctx* ctx, const Grid& g, const PcgBufs<T>& w, const Pc
         L.ev0 = tl.a;
         L.ev1 = tl.b;
         L((const void*)k_pcg_update<DIM, T>, dim3(pg.nupd, w.B), dim3(kPcgBlock), g, w.winv, w.ik[0], w.ik[1],
-          w.ik[2], w.x, w.r, w.z, (const T*)w.p0, (const T*)w.p1, (const T*)w.q, (const T*)w.side, w.part,
-          w.st, pg.ps, pg.npq, lp);
+          w.ik[2], w.x, w.r, w.z, (const T*)w.p0, (const T*)w.p1, (const T*)w.q, (const T*)w.side, w.sg,
+          w.part, w.st, pg.ps, pg.npq, lp);
     }
     if (pg.nrz == 1 && pg.nupd > 1)  // rz / rr of the update's own parity
         L((const void*)k_partials_sum<PcgState>, dim3(w.B), dim3(1024), w.part, pg.ps, pg.nupd, 1, 1, 3, 1,
@@ -1661,6 +1661,7 @@ static int hdm_batch_impl(Ctx* ctx, const topo_mesh& m, const Grid& g0, const El
     w.e0 = ws.e0;
     w.e1 = ws.e1;
     w.side = ws.side;
+    if constexpr (DIM == 3) w.sg = side_geom(g);
     w.x = ws.x;
     w.part = ws.part;
     w.st = ws.st;
