@@ -67,18 +67,22 @@ def parse():
 # Algorithmic costs
 # ----------------------------------------------------------------------------------
 
-def pcg_bytes(n_dofs, n_nodes, n_elems, word):
+def pcg_bytes(n_dofs, n_nodes, n_elems, word, dim=2):
     """Algorithmic HBM bytes of one field's share of one launch of each PCG kernel
     (each array once).
     step  (2D float64, one kernel per iteration): read r, w, s (stencil), p, mask,
           alpha, 1/sum(alpha) per node; read/write x (float64); write r, w, s, p
     apply (two-kernel form): read z, p_old (stencil), alpha, mask; write p_new, q
-    update (two-kernel form): read/write x (float64), r; write z; read p, q,
-          1/sum(alpha) per node"""
+    update (two-kernel form): read r; write r, z; read p, q, 1/sum(alpha) per node; and
+          at every second update of a segment (x takes two steps at a time) read and
+          write x (float64) and read the previous p: on average 8 + w/2 bytes per DOF
+    The 3D float32 apply reads r and 1/sum(alpha) per node and forms z itself, so its
+    update writes no z."""
+    forms_z = dim == 3 and word == 4
     return {
         "pcg_step": n_dofs * (8 * word + 17) + n_nodes * word + n_elems * word,
-        "pcg_apply": n_dofs * (4 * word + 1) + n_elems * word,
-        "pcg_update": n_dofs * (5 * word + 16) + n_nodes * word,
+        "pcg_apply": n_dofs * (4 * word + 1) + n_elems * word + (n_nodes * word if forms_z else 0),
+        "pcg_update": n_dofs * ((4 if forms_z else 5) * word + 8 + word // 2) + n_nodes * word,
     }
 
 
@@ -222,7 +226,7 @@ def batch_scaling_leg(torch, W, binding, FP64, MIXED, counts=(1, 4, 16)):
     for name, pr in (("mixed", MIXED), ("fp64", FP64)):
         w = 4 if pr == MIXED else 8
         kinds = ["pcg_apply", "pcg_update"] if pr == MIXED else ["pcg_step"]
-        pb = pcg_bytes(m.n_dofs, m.n_nodes, m.n_elems, w)
+        pb = pcg_bytes(m.n_dofs, m.n_nodes, m.n_elems, w, m.dim)
         res = {}
         for B in counts:
             R = allr[:B].contiguous()
@@ -794,7 +798,7 @@ def main():
     pcg_kinds = ["pcg_step"] if one_red else ["pcg_apply", "pcg_update"]
     share = {nm: ktimes[nm]["est_total_ms"] for nm in pcg_kinds + ["rom_contract"] if nm in ktimes}
     dominant = max(share, key=share.get) if share else None
-    pb = pcg_bytes(m.n_dofs, m.n_nodes, m.n_elems, word)
+    pb = pcg_bytes(m.n_dofs, m.n_nodes, m.n_elems, word, m.dim)
 
     def pcg_roofline(kd):
         kt = ktimes[kd]

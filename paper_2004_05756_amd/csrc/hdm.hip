@@ -125,22 +125,45 @@ struct SrcPlain {
 template <typename T>
 using ApplyOff = typename std::conditional<sizeof(T) == 4, unsigned, size_t>::type;
 
-// Source of the element-once march: p_new = z + beta p_old at nodes of the grid.
+// The Jacobi-preconditioned residual z = r / K_ii = (r (1 / sum alpha)) (1 / K_e,cc), rounded
+// after each product, so that the update (for r.z) and the 3D apply (for p) form the
+// same value.
+__device__ __forceinline__ float jacobi_z(float r, float w, float ik) { return __fmul_rn(__fmul_rn(r, w), ik); }
+__device__ __forceinline__ double jacobi_z(double r, double w, double ik) {
+    return __dmul_rn(__dmul_rn(r, w), ik);
+}
+
+// The float32 3D apply forms z from r and 1 / sum alpha (the update then stores no z);
+// the float64 one reads z, whose registers it could not hold beside r and 1 / sum alpha.
+template <typename T>
+struct ApplyFormsZ {
+    static constexpr bool value = sizeof(T) == 4;
+};
+
+// Source of the element-once march: p_new = z + beta p_old at nodes of the grid, z read
+// (float64) or formed from r and 1 / sum alpha of the node (float32).
 template <typename T>
 struct SrcDirection3 {
-    const T* __restrict__ z;
+    const T* __restrict__ r;
+    const T* __restrict__ winv;
     const T* __restrict__ p;
+    T ik[3];
     T beta;
     unsigned nn;
-    T zv[4][3], pv[4][3];
+    static constexpr bool FORM = ApplyFormsZ<T>::value;
+    T rv[4][3], pv[4][3], wv[FORM ? 4 : 1];
     __device__ __forceinline__ void fetch(int slot, unsigned node) {
+        if constexpr (FORM) wv[slot] = winv[node];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            zv[slot][c] = z[(ApplyOff<T>)c * nn + node];
+            rv[slot][c] = r[(ApplyOff<T>)c * nn + node];  // r, or z when not FORM
             pv[slot][c] = p[(ApplyOff<T>)c * nn + node];
         }
     }
-    __device__ __forceinline__ T value(int slot, int c) const { return zv[slot][c] + beta * pv[slot][c]; }
+    __device__ __forceinline__ T value(int slot, int c) const {
+        if constexpr (FORM) return jacobi_z(rv[slot][c], wv[slot], ik[c]) + beta * pv[slot][c];
+        else return rv[slot][c] + beta * pv[slot][c];
+    }
 };
 
 template <typename T>
@@ -231,7 +254,8 @@ struct PcgState {
     int maxit;
     int poff;     // iteration parity = launch parity ^ poff
     int fresh;    // the recursion starts here: the first apply records bb, beta = 0
-    int pad;
+    int it0;      // iterations at the segment's start
+    double alpha[2];  // alpha of the last two updates, by iteration parity
 };
 
 constexpr int kPcgParts = 8;  // partial arrays per field (5 used by the two-kernel
@@ -282,10 +306,10 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_start(Grid g, const double* _
         for (int c = 0; c < DIM; ++c) {
             const size_t i = (size_t)c * g.n_nodes + n;
             const T ri = (T)(scale * r64[i]);
-            const T zi = ri * w * ik[c];
+            const T zi = jacobi_z(ri, w, ik[c]);
             x[i] = 0.0;
             r[i] = ri;
-            z[i] = zi;
+            if (DIM == 2 || !ApplyFormsZ<T>::value) z[i] = zi;  // else the 3D apply forms z
             if (fresh) p0[i] = T(0);
             v[0] += (double)ri * (double)zi;
             v[1] += (double)ri * (double)ri;
@@ -471,7 +495,9 @@ template <typename T>
 __global__ __launch_bounds__(kBlock, sizeof(T) == 4 ? 3 : 2) void k_pcg_apply3(Grid g, const T* __restrict__ alpha,
                                                        const T* __restrict__ M,
                                                        const uint8_t* __restrict__ mask,
-                                                       const T* __restrict__ z, T* __restrict__ p0,
+                                                       const T* __restrict__ r /* z when float64 */,
+                                                       const T* __restrict__ winv,
+                                                       T ik0, T ik1, T ik2, T* __restrict__ p0,
                                                        T* __restrict__ p1, T* __restrict__ q,
                                                        T* __restrict__ side, const SideGeom sg,
                                                        double* __restrict__ part, PcgState* st, int ps,
@@ -484,7 +510,8 @@ __global__ __launch_bounds__(kBlock, sizeof(T) == 4 ? 3 : 2) void k_pcg_apply3(G
     const int parity = lp ^ sb->poff;
     const size_t fo = (size_t)fb.field * g.n_dofs;
     alpha += (size_t)fb.field * g.n_elems;
-    z += fo;
+    r += fo;
+    winv += (size_t)fb.field * g.n_nodes;
     const T* p_old = (parity ? p1 : p0) + fo;
     T* p_new = (parity ? p0 : p1) + fo;
     q += fo;
@@ -493,7 +520,7 @@ __global__ __launch_bounds__(kBlock, sizeof(T) == 4 ? 3 : 2) void k_pcg_apply3(G
     const OnceBlock m = once3_block(g, fb.blk);
     for (int i = threadIdx.x; i < kFacSize; i += blockDim.x) L.M[i] = M[i];
     const MarchSlots sl = once3_slots(g, m);
-    SrcDirection3<T> src{z, p_old, T(0), (unsigned)g.n_nodes};
+    SrcDirection3<T> src{r, winv, p_old, {ik0, ik1, ik2}, T(0), (unsigned)g.n_nodes};
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
         src.fetch(r, once3_node(sl, r, m.ez0));
@@ -530,20 +557,27 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_update(Grid g, const T* __res
     winv += (size_t)f * g.n_nodes;
     x += fo;
     r += fo;
-    z += fo;
-    const T* p = (parity ? p0 : p1) + fo;  // the apply's p_new
+    if (z) z += fo;
+    const T* p = (parity ? p0 : p1) + fo;       // the apply's p_new (p_i)
+    const T* pprev = (parity ? p1 : p0) + fo;   // its p_old (p_{i-1})
     q += fo;
     double* pb = part + (size_t)f * kPcgParts * ps;
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     const bool own = n < g.n_nodes;
+    // the correction x takes two steps at once: alpha_{i-1} p_{i-1} + alpha_i p_i at every
+    // second update of the segment (the first one of a pair only records its alpha)
+    const bool pair = parity != (sb->it0 & 1);
     double xv[DIM];
-    T rv[DIM], pv[DIM], qv[DIM], w = T(0);
+    T rv[DIM], pv[DIM], ppv[DIM], qv[DIM], w = T(0);
     if (own) {
         w = winv[n];
 #pragma unroll
         for (int c = 0; c < DIM; ++c) {
             const size_t i = (size_t)c * g.n_nodes + n;
-            xv[c] = x[i];
+            if (pair) {
+                xv[c] = x[i];
+                ppv[c] = pprev[i];
+            }
             rv[c] = r[i];
             pv[c] = p[i];
             qv[c] = q[i];
@@ -570,17 +604,18 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_update(Grid g, const T* __res
         return;
     }
     const T a = (T)(sb->rz[parity] / pq);
+    const double a0 = pair ? sb->alpha[parity ^ 1] : 0.0;
     const T ik[3] = {ik0, ik1, ik2};
     double v[2] = {0.0, 0.0};
     if (own) {
 #pragma unroll
         for (int c = 0; c < DIM; ++c) {
             const size_t i = (size_t)c * g.n_nodes + n;
-            x[i] = xv[c] + (double)a * (double)pv[c];
+            if (pair) x[i] = xv[c] + (a0 * (double)ppv[c] + (double)a * (double)pv[c]);
             const T ri = rv[c] - a * qv[c];
-            const T zi = ri * w * ik[c];
+            const T zi = jacobi_z(ri, w, ik[c]);
             r[i] = ri;
-            z[i] = zi;
+            if (DIM == 2 || !ApplyFormsZ<T>::value) z[i] = zi;  // else the 3D apply forms z
             v[0] += (double)ri * (double)zi;
             v[1] += (double)ri * (double)ri;
         }
@@ -589,7 +624,10 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_update(Grid g, const T* __res
     if (threadIdx.x == 0) {
         part_rz(pb, ps, parity)[blockIdx.x] = v[0];
         part_rr(pb, ps, parity)[blockIdx.x] = v[1];
-        if (blockIdx.x == 0) sb->iters = sb->iters + 1;
+        if (blockIdx.x == 0) {
+            sb->alpha[parity] = (double)a;
+            sb->iters = sb->iters + 1;
+        }
     }
 }
 
@@ -967,6 +1005,28 @@ __global__ void k_correct(long long n, double* __restrict__ u, const T* __restri
         u[(size_t)f * n + i] += sf * (double)d[(size_t)f * n + i];
 }
 
+// u += s * x for the two-kernel recursion, whose x lacks the last step alpha_n p_n when
+// the segment's updates ended on the first of a pair (x takes two steps at a time):
+// that step is added here from the state (alpha by parity) and p_n (the buffer the
+// apply of iteration n wrote).
+template <typename T>
+__global__ void k_correct_pcg(long long n, double* __restrict__ u, const double* __restrict__ x,
+                              const T* __restrict__ p0, const T* __restrict__ p1, const PcgState* __restrict__ st,
+                              const double* __restrict__ s) {
+    const int f = blockIdx.y;
+    const double sf = s[f];
+    if (sf == 0.0) return;
+    const PcgState& S = st[f];
+    const int last = (S.iters - 1) & 1;  // parity of the segment's last update
+    const bool pend = ((S.iters - S.it0) & 1) != 0;
+    const double a = pend ? S.alpha[last] : 0.0;
+    const T* pl = (last ? p0 : p1) + (size_t)f * n;
+    x += (size_t)f * n;
+    u += (size_t)f * n;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        u[i] += sf * (pend ? x[i] + a * (double)pl[i] : x[i]);
+}
+
 // ----------------------------------------------------------------------------------
 // Element sensitivity dc_e = -alpha'(rho_e) u_e^T K_e u_e   (float64), one field per
 // blockIdx.y (rho [B][N_e], u [B][N_u], dc [B][N_e])
@@ -1198,8 +1258,9 @@ static void pcg_iteration(Ctx* ctx, const Grid& g, const PcgBufs<T>& w, const Pc
             L(fn, dim3(pg.napp, w.B), dim3(kPcgBlock), g, w.alpha, w.K, w.mask, (const T*)w.z, w.p0, w.p1,
               w.q, w.part, w.st, pg.ps, pg.nrz, lp);
         else
-            L(fn, dim3(pg.napp, w.B), dim3(kBlock), g, w.alpha, w.K, w.mask, (const T*)w.z, w.p0, w.p1, w.q,
-              w.side, w.sg, w.part, w.st, pg.ps, pg.nrz, lp);
+            L(fn, dim3(pg.napp, w.B), dim3(kBlock), g, w.alpha, w.K, w.mask,
+              (const T*)(ApplyFormsZ<T>::value ? w.r : w.z), w.winv, w.ik[0],
+              w.ik[1], w.ik[2], w.p0, w.p1, w.q, w.side, w.sg, w.part, w.st, pg.ps, pg.nrz, lp);
     }
     if (pg.npq == 1 && pg.napp > 1)
         L((const void*)k_partials_sum<PcgState>, dim3(w.B), dim3(1024), w.part, pg.ps, pg.napp, 0, 0, -1, 0,
@@ -1296,6 +1357,7 @@ __device__ __forceinline__ void seg_state(const SegCtl& c, double tol2, PcgState
     p.iters = it0;
     p.poff = (it0 & 1) ^ 1;  // the segment's first launch has launch parity 1
     p.fresh = c.fresh;
+    p.it0 = it0;
 }
 __device__ __forceinline__ void seg_state(const SegCtl& c, double tol2, Cg1State& q) {
     const int it0 = c.fresh ? 0 : c.fin_iters;
@@ -1541,7 +1603,7 @@ static void hdm_takes(Arena& ar, const Grid& g, bool mixed, int B, HdmWs<T>& w) 
     ar.take(&w.st1, (size_t)B);
     ar.take(&w.x, N);
     ar.take(&w.r, N);
-    ar.take(&w.z, N);
+    if (!(g.dim == 3 && ApplyFormsZ<T>::value)) ar.take(&w.z, N);  // the float 3D apply forms z
     ar.take(&w.p0, N);
     ar.take(&w.p1, N);
     ar.take(&w.q, N);
@@ -1598,8 +1660,12 @@ static void chunk_end(const Grid& g, const Grid& gres, const double* K64, const 
         L((const void*)k_seg_mark<Cg1State>, gb, bb, w.B, w.st1, c.ctl, c.skip, c.corr, c.fsc, c.live);
     else
         L((const void*)k_seg_mark<PcgState>, gb, bb, w.B, w.st, c.ctl, c.skip, c.corr, c.fsc, c.live);
-    L((const void*)k_correct<double>, dim3(std::min(grid_blocks(N), 1024), w.B), dim3(kBlock), N, u,
-      (const double*)w.x, (const double*)c.corr);
+    if (one_red)
+        L((const void*)k_correct<double>, dim3(std::min(grid_blocks(N), 1024), w.B), dim3(kBlock), N, u,
+          (const double*)w.x, (const double*)c.corr);
+    else
+        L((const void*)k_correct_pcg<T>, dim3(std::min(grid_blocks(N), 1024), w.B), dim3(kBlock), N, u,
+          (const double*)w.x, (const T*)w.p0, (const T*)w.p1, (const PcgState*)w.st, (const double*)c.corr);
     residual_sink(L, gres, K64, a64, w.mask, u, f, (double*)w.r64, w.B, rpart, rout, (const int*)c.skip);
     if (one_red)
         L((const void*)k_seg_control<Cg1State>, gb, bb, w.B, w.st1, c.ctl, (const double*)rout, c.fsc, c.live, rtol,

@@ -20,8 +20,15 @@ def test_pcg_bytes_count_every_array_once():
         assert b["pcg_step"] == nu * (4 * w + 1 + 16 + 4 * w) + nn * w + ne * w
         # apply: z, p_old read, p_new, q written, mask; alpha per element
         assert b["pcg_apply"] == nu * (2 * w + 2 * w + 1) + ne * w
-        # update: x read + written (16), r read + written, z written, p, q read; 1 / sum(alpha)
-        assert b["pcg_update"] == nu * (16 + 2 * w + w + 2 * w) + nn * w
+        # update: r read + written, z written, p, q read, 1 / sum(alpha); x read + written
+        # (16) and the previous p read at every second update only: 8 + w / 2 on average
+        assert b["pcg_update"] == nu * (8 + w // 2 + 2 * w + w + 2 * w) + nn * w
+    # the 3D float32 apply forms z from r and 1 / sum(alpha): one more read per node in the
+    # apply, no z written by the update
+    b3 = bench.pcg_bytes(nu, nn, ne, 4, 3)
+    assert b3["pcg_apply"] == nu * (2 * 4 + 2 * 4 + 1) + ne * 4 + nn * 4
+    assert b3["pcg_update"] == nu * (8 + 2 + 2 * 4 + 2 * 4) + nn * 4
+    assert bench.pcg_bytes(nu, nn, ne, 8, 3) == bench.pcg_bytes(nu, nn, ne, 8, 2)
 
 
 def test_kernel_names_match_the_traffic_summaries():
