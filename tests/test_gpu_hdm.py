@@ -193,3 +193,36 @@ def test_2d_solve_on_degenerate_shapes(nel, kind, prec):
     tol = 10 * (ev[-1] / ev[0]) * rtol
     assert rel(host(u), uo) <= tol
     assert abs(info["compliance_corr"] / co - 1) <= max(tol, 1e-13)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("maxit", [6, 7])
+def test_iteration_limit_returns_the_last_iterate(prec, maxit):
+    """A solve stopped by its iteration limit after an even or an odd number of steps.
+    The two-kernel recursion adds its steps to the correction two at a time, so an odd
+    count leaves one step pending when the segment ends; the returned u must still be
+    the k-th Jacobi-PCG iterate from u = 0 (Sec. 3.1's inner solver), here scipy's CG
+    with the same preconditioner on the oracle's assembled K_ff, and the reported
+    residual must be that of the returned u."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    from paper_2004_05756_amd import FP64, MIXED, binding
+    pr = FP64 if prec == "fp64" else MIXED
+    for p in (W.cantilever3d(12, 6, 6), W.cantilever2d(37, 11)):
+        if p.mesh.dim == 2 and pr == FP64:
+            continue  # the 2D FP64 solve runs the one-reduction recursion (x at every step)
+        rho = W.rho_smoothed(p.mesh, 61)
+        r, m, f = problem_tensors(p, rho)
+        u, info = ctx().hdm_solve(p.mesh, r, m, f, rtol=1e-12, maxit=maxit, prec=pr, check=False)
+        assert info["status"] == binding.TOPO_ENOCONV and info["iters"] == maxit
+        uh = host(u)
+        free = p.mask == 0
+        K = O.assemble(p.mesh, rho)
+        Kff = K[free][:, free].tocsr()
+        xk, _ = spla.cg(Kff, p.f[free], x0=np.zeros(int(free.sum())), rtol=1e-30, atol=0.0,
+                        maxiter=maxit, M=sp.diags(1.0 / Kff.diagonal()))
+        tol = 1e-10 if pr == FP64 else 1e-4
+        assert rel(uh[free], xk) <= tol, (p.name, rel(uh[free], xk))
+        assert np.all(uh[~free] == 0)
+        res = np.linalg.norm((p.f - K @ uh)[free]) / np.linalg.norm(p.f)
+        assert abs(res / info["rel_resid"] - 1) <= 1e-9, (p.name, res, info["rel_resid"])
