@@ -76,20 +76,25 @@ def pcg_bytes(n_dofs, n_nodes, n_elems, word, dim=2):
     update (two-kernel form): read r; write r, z; read p, q, 1/sum(alpha) per node; and
           at every second update of a segment (x takes two steps at a time) read and
           write x (float64) and read the previous p: on average 8 + w/2 bytes per DOF
-    The 3D float32 apply reads r and 1/sum(alpha) per node and forms z itself, so its
-    update writes no z."""
+    In 3D the update applies the mask (one byte per DOF moves from the apply to the
+    update), and the float32 apply reads r and 1/sum(alpha) per node and forms z itself,
+    so its update writes no z."""
     forms_z = dim == 3 and word == 4
+    mask_apply = 1 if dim == 2 else 0
     return {
         "pcg_step": n_dofs * (8 * word + 17) + n_nodes * word + n_elems * word,
-        "pcg_apply": n_dofs * (4 * word + 1) + n_elems * word + (n_nodes * word if forms_z else 0),
-        "pcg_update": n_dofs * ((4 if forms_z else 5) * word + 8 + word // 2) + n_nodes * word,
+        "pcg_apply": n_dofs * (4 * word + mask_apply) + n_elems * word + (n_nodes * word if forms_z else 0),
+        "pcg_update": n_dofs * ((4 if forms_z else 5) * word + 8 + word // 2 + 1 - mask_apply) + n_nodes * word,
     }
 
 
 def pcg_kernel_name(kind, dim, word):
-    """Symbol (as rocprofv3 prints it) of a PCG kernel."""
+    """Symbol (as rocprofv3 prints it) of a PCG kernel.  The 3D apply is named with its
+    index type: 32-bit for float32 on the meshes measured here (per-field arrays under
+    4 GiB), 64-bit for float64."""
     t = "float" if word == 4 else "double"
-    return {"pcg_step": f"k_cg1_step2<{t}>", "pcg_apply": f"k_pcg_apply{dim}<{t}>",
+    apply3 = "k_pcg_apply3<float, unsigned int>" if word == 4 else "k_pcg_apply3<double, unsigned long>"
+    return {"pcg_step": f"k_cg1_step2<{t}>", "pcg_apply": apply3 if dim == 3 else f"k_pcg_apply2<{t}>",
             "pcg_update": f"k_pcg_update<{dim},{t}>"}[kind]
 
 

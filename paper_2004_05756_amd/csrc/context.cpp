@@ -306,6 +306,10 @@ const ElemTables* get_tables(Ctx* ctx, const topo_mesh& m) {
         hipMemcpy(t.M64, mblk.data(), kFacSize * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(t.M32, mblk32.data(), kFacSize * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
         return nullptr;
+    for (int i = 0; i < kFacSize; ++i) {
+        t.Mv64.m[i] = mblk[i];
+        t.Mv32.m[i] = mblk32[i];
+    }
     return &(ctx->tables[key] = t);
 }
 

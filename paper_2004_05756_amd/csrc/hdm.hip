@@ -119,11 +119,6 @@ struct SrcPlain {
     __device__ __forceinline__ T value(int slot, int c) const { return v[slot][c]; }
 };
 
-// Offsets of the 3D PCG apply's loads and stores: 32-bit for float (the compiler then
-// forms no 64-bit addresses), 64-bit for double (whose register budget the 32-bit form
-// overruns).
-template <typename T>
-using ApplyOff = typename std::conditional<sizeof(T) == 4, unsigned, size_t>::type;
 
 // The Jacobi-preconditioned residual z = r / K_ii = (r (1 / sum alpha)) (1 / K_e,cc), rounded
 // after each product, so that the update (for r.z) and the 3D apply (for p) form the
@@ -141,9 +136,10 @@ struct ApplyFormsZ {
 };
 
 // Source of the element-once march: p_new = z + beta p_old at nodes of the grid, z read
-// (float64) or formed from r and 1 / sum alpha of the node (float32).
-template <typename T>
+// (float64) or formed from r and 1 / sum alpha of the node (float32).  I: index type.
+template <typename T, typename I>
 struct SrcDirection3 {
+    using Index = I;
     const T* __restrict__ r;
     const T* __restrict__ winv;
     const T* __restrict__ p;
@@ -153,11 +149,11 @@ struct SrcDirection3 {
     static constexpr bool FORM = ApplyFormsZ<T>::value;
     T rv[4][3], pv[4][3], wv[FORM ? 4 : 1];
     __device__ __forceinline__ void fetch(int slot, unsigned node) {
-        if constexpr (FORM) wv[slot] = winv[node];
+        if constexpr (FORM) wv[slot] = ld_at(winv, (I)node);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            rv[slot][c] = r[(ApplyOff<T>)c * nn + node];  // r, or z when not FORM
-            pv[slot][c] = p[(ApplyOff<T>)c * nn + node];
+            rv[slot][c] = ld_at(r, (I)c * nn + node);  // r, or z when not FORM
+            pv[slot][c] = ld_at(p, (I)c * nn + node);
         }
     }
     __device__ __forceinline__ T value(int slot, int c) const {
@@ -415,45 +411,33 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_apply2(Grid g, const T* __res
 
 // Emitter of the 3D PCG apply (once3_run): at each node slot of a plane the block
 // writes p_new and its part of q when it is the node's primary block, else its part
-// into the side section the node belongs to for this block; masked DOFs get a zero part.
-// The node's mask bytes are loaded ahead of the emit (by plane parity).  pq sums p_new . part over
-// every part written.
-template <typename T>
+// into the side section the node belongs to for this block.  The parts are not masked:
+// p_new is zero at masked DOFs (so is r, hence z), so their products with p_new add
+// nothing, and the update zeroes q there.  pq sums p_new . part over every part written.
+template <typename T, typename I>
 struct PcgEmit3 {
     const Grid& g;
     const OnceBlock& m;
     const MarchSlots& sl;
     const SideGeom& sg;
     const OnceLds<T>& L;
-    const uint8_t* __restrict__ mask;
     T* __restrict__ p_new;
     T* __restrict__ q;
     T* __restrict__ side;
-    int sinfo[2];    // side section of the slot on the planes below the chunk's top (bits
+    using SInfo = typename std::conditional<sizeof(I) == 4, int, long long>::type;
+    SInfo sinfo[2];  // side section of the slot on the planes below the chunk's top (bits
                      // 0-1, 0: primary) and its side index at plane 0 (bits 2-)
-    unsigned mk0[2], mk1[2];  // mask bytes of the slot's node at even / odd planes (component c at bits 8c)
     double pq = 0.0;
 
     __device__ __forceinline__ PcgEmit3(const Grid& g_, const OnceBlock& m_, const MarchSlots& sl_,
-                                        const SideGeom& sg_, const OnceLds<T>& L_, const uint8_t* mask_,
-                                        T* p_new_, T* q_, T* side_)
-        : g(g_), m(m_), sl(sl_), sg(sg_), L(L_), mask(mask_), p_new(p_new_), q(q_), side(side_) {
+                                        const SideGeom& sg_, const OnceLds<T>& L_, T* p_new_, T* q_, T* side_)
+        : g(g_), m(m_), sl(sl_), sg(sg_), L(L_), p_new(p_new_), q(q_), side(side_) {
 #pragma unroll
         for (int r = 0; r < 2; ++r) {
             const int qs = threadIdx.x + r * kBlock;
             const int s = sl.base[r] >= 0 ? once3_section(g, m, qs, 0) : 0;  // no z bit below the top
             const int i = m.ex0 + qs % MPX, j = m.ey0 + qs / MPX;
-            sinfo[r] = s | (s ? (int)side_index(sg, s, i, j, 0) << 2 : 0);
-            mk0[r] = mk1[r] = 0;
-        }
-    }
-    __device__ __forceinline__ void load(int k) {
-#pragma unroll
-        for (int r = 0; r < 2; ++r) {
-            const unsigned n = once3_node(sl, r, k), nn = (unsigned)g.n_nodes;
-            const unsigned v = (unsigned)mask[n] | ((unsigned)mask[nn + n] << 8) | ((unsigned)mask[2 * nn + n] << 16);
-            if (k & 1) mk1[r] = v;
-            else mk0[r] = v;
+            sinfo[r] = s | (s ? (SInfo)side_index(sg, s, i, j, 0) << 2 : 0);
         }
     }
     template <bool TOP>
@@ -461,24 +445,25 @@ struct PcgEmit3 {
         const int qs = threadIdx.x + r * kBlock;
         const int n = sl.base[r] + k * sl.pstride;
         // sections 1-3 advance by one x-y layer of the section per plane
-        int s = sinfo[r] & 3;
-        const int sstr = s == 1 ? sg.nbx * sg.nny : s == 2 ? sg.nnx * sg.nby : sg.nbx * sg.nby;
-        int si = (sinfo[r] >> 2) + k * sstr;
+        int s = (int)(sinfo[r] & 3);
+        const SInfo sstr = s == 1 ? sg.nbx * sg.nny : s == 2 ? sg.nnx * sg.nby : sg.nbx * sg.nby;
+        SInfo si = (sinfo[r] >> 2) + k * sstr;
         if (TOP && k < g.nz) {  // the chunk's top plane: the block above is primary
             s = once3_section(g, m, qs, k);
-            si = (int)side_index(sg, s, m.ex0 + qs % MPX, m.ey0 + qs / MPX, k);
+            si = (SInfo)side_index(sg, s, m.ex0 + qs % MPX, m.ey0 + qs / MPX, k);
         }
-        const unsigned mk = (k & 1) ? mk1[r] : mk0[r];
-        T* dst = s ? side + si : q + n;
-        const ApplyOff<T> cs = s ? (ApplyOff<T>)sg.total : (ApplyOff<T>)g.n_nodes;
         T d = T(0);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const T pn = L.plane[buf][c][qs];
-            const T qv = (mk >> (8 * c)) & 0xffu ? T(0) : y[c];
-            dst[c * cs] = qv;
-            if (!s) p_new[c * (ApplyOff<T>)g.n_nodes + n] = pn;
-            d += pn * qv;
+            // separate stores (not one through a selected pointer) keep each base uniform
+            if (s) {
+                st_at(side, (I)si + (I)c * (I)sg.total, y[c]);
+            } else {
+                st_at(q, (I)n + (I)c * (I)g.n_nodes, y[c]);
+                st_at(p_new, (I)n + (I)c * (I)g.n_nodes, pn);
+            }
+            d += pn * y[c];
         }
         pq += (double)d;
     }
@@ -490,11 +475,11 @@ struct PcgEmit3 {
 // p_new and its part of q = K p_new at the nodes it is primary for, and its part at the
 // other nodes of its tile into the side sections (side [B][3][total]); the update adds
 // them.  The pq partial sums p_new . part over every part the block writes, which adds
-// up to p_new . q over the blocks.  M is the table of reduced element blocks.
-template <typename T>
-__global__ __launch_bounds__(kBlock, sizeof(T) == 4 ? 3 : 2) void k_pcg_apply3(Grid g, const T* __restrict__ alpha,
-                                                       const T* __restrict__ M,
-                                                       const uint8_t* __restrict__ mask,
+// up to p_new . q over the blocks.  Mv: the reduced element blocks (apply3_from_n);
+// I: index type of the per-field arrays (32-bit when their bytes fit).
+template <typename T, typename I>
+__global__ __launch_bounds__(kBlock, sizeof(T) == 4 ? 4 : 2) void k_pcg_apply3(Grid g, const T* __restrict__ alpha,
+                                                       const FacTab<T> Mv,
                                                        const T* __restrict__ r /* z when float64 */,
                                                        const T* __restrict__ winv,
                                                        T ik0, T ik1, T ik2, T* __restrict__ p0,
@@ -518,28 +503,29 @@ __global__ __launch_bounds__(kBlock, sizeof(T) == 4 ? 3 : 2) void k_pcg_apply3(G
     side += (size_t)fb.field * 3 * sg.total;
     double* pb = part + (size_t)fb.field * kPcgParts * ps;
     const OnceBlock m = once3_block(g, fb.blk);
-    for (int i = threadIdx.x; i < kFacSize; i += blockDim.x) L.M[i] = M[i];
     const MarchSlots sl = once3_slots(g, m);
-    SrcDirection3<T> src{r, winv, p_old, {ik0, ik1, ik2}, T(0), (unsigned)g.n_nodes};
+    SrcDirection3<T, I> src{r, winv, p_old, {ik0, ik1, ik2}, T(0), (unsigned)g.n_nodes};
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
         src.fetch(r, once3_node(sl, r, m.ez0));
         src.fetch(2 + r, once3_node(sl, r, m.ez0 + 1));
     }
-    PcgEmit3<T> E(g, m, sl, sg, L, mask, p_new, q, side);
+    PcgEmit3<T, I> E(g, m, sl, sg, L, p_new, q, side);
     T tb;
     if (pcg_apply_scalars(pb, sb, ps, nrz, parity, fb.blk == 0, tb, lds)) return;
     src.beta = tb;
-    once3_run(g, m, sl, alpha, L, src, E);
+    once3_run(g, m, sl, alpha, L, src, E, Mv.m);
     double v[1] = {E.pq};
     block_reduce<1>(v, lds);
     if (threadIdx.x == 0) pb[fb.blk] = v[0];
 }
 
 // One node per thread (grid (nupd, B)); the node's loads are issued before the wait on
-// the scalar reduction.
+// the scalar reduction.  3D: q is zeroed at masked DOFs here (the 3D apply writes
+// unmasked parts), so that r stays zero there; the 2D apply masks q itself.
 template <int DIM, typename T>
 __global__ __launch_bounds__(kPcgBlock) void k_pcg_update(Grid g, const T* __restrict__ winv,
+                                                       const uint8_t* __restrict__ mask,
                                                        T ik0, T ik1, T ik2, double* __restrict__ x,
                                                        T* __restrict__ r, T* __restrict__ z,
                                                        const T* __restrict__ p0,
@@ -583,6 +569,9 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_update(Grid g, const T* __res
             qv[c] = q[i];
         }
         if constexpr (DIM == 3) {
+            uint8_t mk[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) mk[c] = mask[(size_t)c * g.n_nodes + n];
             // q = the primary block's part + the parts of the blocks below the node, in
             // the order of their side sections
             const int i = n % g.nx1, jk = n / g.nx1, j = jk % g.ny1, k = jk / g.ny1;
@@ -596,6 +585,9 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_update(Grid g, const T* __res
                         for (int c = 0; c < 3; ++c) qv[c] += side[(size_t)c * sg.total + si];
                     }
             }
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                if (mk[c]) qv[c] = T(0);
         }
     }
     const double pq = block_sum_array(pb, npq, lds);
@@ -1237,6 +1229,8 @@ struct PcgBufs {
     T *r, *z, *p0, *p1, *q, *e0, *e1;  // [B][N_u]
     T* side;           // 3D: [B][3][side total] the apply's parts of shared nodes
     SideGeom sg;       // 3D: their sections (from the apply's launch geometry)
+    FacTab<T> Mv;      // 3D: the reduced element blocks, passed by value
+    bool narrow;       // 3D: the apply indexes its arrays with 32-bit offsets
     double* x;         // [B][N_u] the segment's correction, accumulated in float64
     double* part;      // [B][kPcgParts][ps]
     PcgState* st;      // [B]
@@ -1244,6 +1238,24 @@ struct PcgBufs {
     const double* r64; // [B][N_u] float64 true residual
     const double* fsc; // [B] scale of each field's inner system
 };
+
+// The float32 3D apply takes 32-bit indices when the bytes of every per-field array it
+// reads or writes fit in 32 bits (below 4 GiB each); the float64 one 64-bit indices.
+// The side sections hold under 4 N_n / 3 nodes for any chunk height (the z sections at
+// most N_n, the x and y ones N_n / 32 and N_n / 8), so 2 N_n bounds them before the
+// launch geometry is known.
+template <typename T>
+static bool apply3_narrow(const Grid& g) {
+    const unsigned long long lim = 1ull << 32, nn = (unsigned long long)g.n_nodes;
+    return sizeof(T) == 4 && 3ull * 2ull * nn * sizeof(T) < lim && (unsigned long long)g.n_elems * sizeof(T) < lim;
+}
+
+template <typename T>
+static const void* pcg_apply3_fn(bool narrow) {
+    if constexpr (sizeof(T) == 4)
+        if (narrow) return (const void*)k_pcg_apply3<T, unsigned>;
+    return (const void*)k_pcg_apply3<T, size_t>;
+}
 
 // One iteration of the two-kernel recursion (apply + update) at launch parity lp.
 template <int DIM, typename T>
@@ -1253,12 +1265,11 @@ static void pcg_iteration(Ctx* ctx, const Grid& g, const PcgBufs<T>& w, const Pc
         TimedLaunch tl(ctx, KID_PCG_APPLY, L.s, L.graph ? kTimeOff : timing, true);
         L.ev0 = tl.a;
         L.ev1 = tl.b;
-        const void* fn = DIM == 2 ? (const void*)k_pcg_apply2<T> : (const void*)k_pcg_apply3<T>;
         if constexpr (DIM == 2)
-            L(fn, dim3(pg.napp, w.B), dim3(kPcgBlock), g, w.alpha, w.K, w.mask, (const T*)w.z, w.p0, w.p1,
-              w.q, w.part, w.st, pg.ps, pg.nrz, lp);
+            L((const void*)k_pcg_apply2<T>, dim3(pg.napp, w.B), dim3(kPcgBlock), g, w.alpha, w.K, w.mask,
+              (const T*)w.z, w.p0, w.p1, w.q, w.part, w.st, pg.ps, pg.nrz, lp);
         else
-            L(fn, dim3(pg.napp, w.B), dim3(kBlock), g, w.alpha, w.K, w.mask,
+            L(pcg_apply3_fn<T>(w.narrow), dim3(pg.napp, w.B), dim3(kBlock), g, w.alpha, w.Mv,
               (const T*)(ApplyFormsZ<T>::value ? w.r : w.z), w.winv, w.ik[0],
               w.ik[1], w.ik[2], w.p0, w.p1, w.q, w.side, w.sg, w.part, w.st, pg.ps, pg.nrz, lp);
     }
@@ -1269,9 +1280,9 @@ static void pcg_iteration(Ctx* ctx, const Grid& g, const PcgBufs<T>& w, const Pc
         TimedLaunch tl(ctx, KID_PCG_UPDATE, L.s, L.graph ? kTimeOff : timing, true);
         L.ev0 = tl.a;
         L.ev1 = tl.b;
-        L((const void*)k_pcg_update<DIM, T>, dim3(pg.nupd, w.B), dim3(kPcgBlock), g, w.winv, w.ik[0], w.ik[1],
-          w.ik[2], w.x, w.r, w.z, (const T*)w.p0, (const T*)w.p1, (const T*)w.q, (const T*)w.side, w.sg,
-          w.part, w.st, pg.ps, pg.npq, lp);
+        L((const void*)k_pcg_update<DIM, T>, dim3(pg.nupd, w.B), dim3(kPcgBlock), g, w.winv, w.mask, w.ik[0],
+          w.ik[1], w.ik[2], w.x, w.r, w.z, (const T*)w.p0, (const T*)w.p1, (const T*)w.q, (const T*)w.side,
+          w.sg, w.part, w.st, pg.ps, pg.npq, lp);
     }
     if (pg.nrz == 1 && pg.nupd > 1)  // rz / rr of the update's own parity
         L((const void*)k_partials_sum<PcgState>, dim3(w.B), dim3(1024), w.part, pg.ps, pg.nupd, 1, 1, 3, 1,
@@ -1691,7 +1702,7 @@ static int hdm_batch_impl(Ctx* ctx, const topo_mesh& m, const Grid& g0, const El
                           double rtol, const int* maxit, const uint8_t* solve, bool mixed, topo_info* info,
                           int* status, uint8_t* stagnated, hipStream_t s) {
     Grid g = g0;
-    if constexpr (DIM == 3) g.mtarget = march3_target(ctx, (const void*)k_pcg_apply3<T>);
+    if constexpr (DIM == 3) g.mtarget = march3_target(ctx, pcg_apply3_fn<T>(apply3_narrow<T>(g0)));
     Grid gres = g;  // the residual march fits its own resident wave (and the partial arrays)
     if constexpr (DIM == 3) gres.mtarget = std::min(march3_target(ctx, (const void*)k_residual3), g.mtarget);
     const long long N = g.n_dofs;
@@ -1727,7 +1738,11 @@ static int hdm_batch_impl(Ctx* ctx, const topo_mesh& m, const Grid& g0, const El
     w.e0 = ws.e0;
     w.e1 = ws.e1;
     w.side = ws.side;
-    if constexpr (DIM == 3) w.sg = side_geom(g);
+    if constexpr (DIM == 3) {
+        w.sg = side_geom(g);
+        w.Mv = sizeof(T) == 4 ? *(const FacTab<T>*)&tb->Mv32 : *(const FacTab<T>*)&tb->Mv64;
+        w.narrow = apply3_narrow<T>(g);
+    }
     w.x = ws.x;
     w.part = ws.part;
     w.st = ws.st;

@@ -42,6 +42,14 @@ Grid make_grid(const topo_mesh& m);
 constexpr int kFacSize = 51;
 constexpr int kFacH = 48;
 
+// The reduced blocks as a by-value kernel argument: uniform values that the kernel reads
+// from its argument segment into scalar registers instead of holding them in vector
+// registers or LDS.
+template <typename T>
+struct FacTab {
+    T m[kFacSize];
+};
+
 // Element tables of one (dim, h, nu, plane) combination, resident on the device.
 struct ElemTables {
     int ne;            // element DOFs: 8 (Q4) or 24 (H8)
@@ -51,6 +59,8 @@ struct ElemTables {
     float* F32 = nullptr;   // device [kFacSize]
     double* M64 = nullptr;  // device [kFacSize] the reduced blocks M = L L^T themselves
     float* M32 = nullptr;   // device [kFacSize]
+    FacTab<double> Mv64{};  // host copies of M64 / M32 (kernel arguments)
+    FacTab<float> Mv32{};
     double diag[3];    // K_e diagonal per displacement component (host copy)
     std::vector<double> host;  // host copy of K64
 };

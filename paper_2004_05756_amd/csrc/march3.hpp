@@ -16,6 +16,27 @@
 
 namespace topo {
 
+// Element access at index i of an array whose base is uniform: with a 32-bit index the
+// byte offset is formed in 32 bits, so that a load or store takes the base in scalar
+// registers and one 32-bit offset (no 64-bit address per access); with a 64-bit index
+// (arrays of 4 GiB or more, and the float64 apply) it is a plain subscript.
+template <typename T>
+__device__ __forceinline__ T ld_at(const T* __restrict__ b, unsigned i) {
+    return *(const T*)((const char*)b + i * (unsigned)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ T ld_at(const T* __restrict__ b, size_t i) {
+    return b[i];
+}
+template <typename T>
+__device__ __forceinline__ void st_at(T* __restrict__ b, unsigned i, T v) {
+    *(T*)((char*)b + i * (unsigned)sizeof(T)) = v;
+}
+template <typename T>
+__device__ __forceinline__ void st_at(T* __restrict__ b, size_t i, T v) {
+    b[i] = v;
+}
+
 constexpr int MPX = MEX + 1, MPY = MEY + 1;         // staged node plane
 constexpr int MPN = MPX * MPY;                      // 297 nodes
 static_assert(MEX * MEY == kBlock, "one thread per element column");
@@ -237,7 +258,6 @@ template <typename T>
 struct OnceLds {
     T plane[3][3][MPN];   // node planes, triple-buffered (plane k in buffer (k - ez0) % 3)
     T xch[3][4][OXN];     // corner sums [c][corner][padded element slot]
-    T M[kFacSize];
 };
 
 struct OnceBlock {
@@ -284,22 +304,22 @@ __device__ __forceinline__ unsigned once3_node(const MarchSlots& sl, int r, int 
 }
 
 // The march.  Src:
+//   Index                           index type of its arrays and of alpha
 //   fetch(int slot, unsigned node)  issue the loads of node
 //   value(int slot, int c)          the fetched value
-// the caller has fetched planes ez0 (slots 0, 1) and ez0 + 1 (slots 2, 3).  Emit is an
-// object with
-//   load(int k)    issue the loads of what the emit of node plane k needs (one element
-//                  layer ahead of that emit; at most two planes are pending)
+// the caller has fetched planes ez0 (slots 0, 1) and ez0 + 1 (slots 2, 3).  Emit:
 //   emit<TOP>(int r, int k, int buf, const T (&y)[3])  y = this block's part of (K x)
 //                  at the node of slot r at plane k, whose values x are in L.plane[buf]
 //                  (a plane buffer is written again only two layers later, after a
 //                  barrier every emitter of that plane has passed); TOP: k is the
 //                  chunk's top plane
-// Barriers per element layer: after the plane is staged and after the corner exchange.
+// Mt: the reduced element blocks (apply3_from_n).  Barriers per element layer: after the
+// plane is staged and after the corner exchange.
 template <typename T, typename Src, typename Emit>
 __device__ __forceinline__ void once3_run(const Grid& g, const OnceBlock& m, const MarchSlots& sl,
                                           const T* __restrict__ alpha, OnceLds<T>& L, Src& src,
-                                          Emit& E) {
+                                          Emit& E, const T* Mt) {
+    using I = typename Src::Index;
     const int tid = threadIdx.x;
     const int tx = tid % MEX, ty = tid / MEX;
     const int ex = m.ex0 + tx, ey = m.ey0 + ty;
@@ -318,7 +338,7 @@ __device__ __forceinline__ void once3_run(const Grid& g, const OnceBlock& m, con
                 for (int c = 0; c < 3; ++c) L.plane[set][c][q] = src.value(2 * set + r, c);
         }
     const int K = m.ez1 - m.ez0;
-    T al_next = exy ? alpha[m.ez0 * astride + abase] : T(0);
+    T al_next = exy ? ld_at(alpha, (I)(m.ez0 * astride + abase)) : T(0);
     // every valid node slot of plane k (plane buffer buf): the sum of the four tile
     // elements around it (zero border outside the tile)
     auto emit_plane = [&](int k, int buf, auto top_plane) __attribute__((always_inline)) {
@@ -337,11 +357,11 @@ __device__ __forceinline__ void once3_run(const Grid& g, const OnceBlock& m, con
         }
     };
     int bot = 0, topb = 1;  // buffers of node planes ez and ez + 1
-    // one element layer s: bottom face (ab, fb) in, top face (at, ft) out; the upper
-    // corners of the layer below in top, replaced by this layer's (each entry read
+    // one element layer s: the bottom face's edge sums fb in, the top face's ft out; the
+    // upper corners of the layer below in top, replaced by this layer's (each entry read
     // before it is replaced)
-    auto layer = [&](int s, const T (&ab)[4][3], const FaceSums<T>& fb, T (&at)[4][3], FaceSums<T>& ft,
-                     T (&top)[4][3]) __attribute__((always_inline)) {
+    auto layer = [&](int s, const FaceSums<T>& fb, FaceSums<T>& ft, T (&top)[4][3])
+                     __attribute__((always_inline)) {
         const int ez = m.ez0 + s;  // element layer between node planes ez and ez + 1
         if (s >= 1) {
 #pragma unroll
@@ -357,19 +377,24 @@ __device__ __forceinline__ void once3_run(const Grid& g, const OnceBlock& m, con
         if (s + 1 < K) {
 #pragma unroll
             for (int r = 0; r < 2; ++r) src.fetch(r, once3_node(sl, r, ez + 2));
-            al_next = exy ? alpha[(ez + 1) * astride + abase] : T(0);
+            al_next = exy ? ld_at(alpha, (I)((ez + 1) * astride + abase)) : T(0);
         }
-        E.load(ez + 1);
+        // the top face from the plane just staged; the bottom face again from its plane
+        // (still in buffer bot), for the z-edge differences
+        T at[4][3], ab[4][3];
 #pragma unroll
         for (int f = 0; f < 4; ++f) {
             const int q = (ty + (f >> 1)) * MPX + tx + (f & 1);
 #pragma unroll
-            for (int c = 0; c < 3; ++c) at[f][c] = L.plane[topb][c][q];
+            for (int c = 0; c < 3; ++c) {
+                at[f][c] = L.plane[topb][c][q];
+                ab[f][c] = L.plane[bot][c][q];
+            }
         }
         face_sums(at, ft);
         T N[8][3], Y[8][3];
         neg_wht3_faces(ab, at, fb, ft, N);
-        apply3_from_n(N, L.M, al, Y);
+        apply3_from_n(N, Mt, al, Y);
 #pragma unroll
         for (int v = 0; v < 4; ++v)
 #pragma unroll
@@ -382,25 +407,23 @@ __device__ __forceinline__ void once3_run(const Grid& g, const OnceBlock& m, con
         bot = topb;
         topb = topb == 2 ? 0 : topb + 1;
     };
-    T fa[4][3], fbv[4][3], top[4][3];
+    T top[4][3];
     FaceSums<T> sa, sb;
 #pragma unroll
     for (int v = 0; v < 4; ++v) top[v][0] = top[v][1] = top[v][2] = T(0);
-    E.load(m.ez0);
     __syncthreads();  // the prologue planes are staged
+    {
+        T fa[4][3];
 #pragma unroll
-    for (int f = 0; f < 4; ++f) {
-        const int q = (ty + (f >> 1)) * MPX + tx + (f & 1);
+        for (int f = 0; f < 4; ++f) {
+            const int q = (ty + (f >> 1)) * MPX + tx + (f & 1);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) fa[f][c] = L.plane[0][c][q];
+            for (int c = 0; c < 3; ++c) fa[f][c] = L.plane[0][c][q];
+        }
+        face_sums(fa, sa);
     }
-    face_sums(fa, sa);
     for (int s = 0; s < K; ++s) {
-        layer(s, fa, sa, fbv, sb, top);
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) fa[v][c] = fbv[v][c];
+        layer(s, sa, sb, top);
         sa = sb;
     }
     // the chunk's top node plane (buffer bot now): the last layer's upper corners only,
