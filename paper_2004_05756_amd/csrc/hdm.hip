@@ -1702,7 +1702,12 @@ static int hdm_batch_impl(Ctx* ctx, const topo_mesh& m, const Grid& g0, const El
                           double rtol, const int* maxit, const uint8_t* solve, bool mixed, topo_info* info,
                           int* status, uint8_t* stagnated, hipStream_t s) {
     Grid g = g0;
-    if constexpr (DIM == 3) g.mtarget = march3_target(ctx, pcg_apply3_fn<T>(apply3_narrow<T>(g0)));
+    // 3D: chunk heights sized for one resident wave of the apply per field, shared out
+    // when more than 8 fields run in one launch: taller chunks then leave fewer side
+    // entries and block prologues while the launch still spans several waves (16 fields
+    // on 192x96x96: 14 layers, 504 blocks per field, 7.9 waves)
+    if constexpr (DIM == 3)
+        g.mtarget = std::max(1, march3_target(ctx, pcg_apply3_fn<T>(apply3_narrow<T>(g0))) / ((B + 7) / 8));
     Grid gres = g;  // the residual march fits its own resident wave (and the partial arrays)
     if constexpr (DIM == 3) gres.mtarget = std::min(march3_target(ctx, (const void*)k_residual3), g.mtarget);
     const long long N = g.n_dofs;
