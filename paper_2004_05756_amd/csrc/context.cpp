@@ -334,7 +334,7 @@ TimedLaunch::TimedLaunch(Ctx* ctx, int k, hipStream_t st, int mode, bool ik)
     Timing& t = c->timing;
     if (t.every <= 0) return;
     if (!in_kernel) ++t.launched[kid];  // the PCG kernels are counted by their phase driver
-    if (t.seen[kid]++ % t.every != 0 && mode != kTimeForced) return;
+    if ((t.seen[kid]++ / kTimeRun) % t.every != 0 && mode != kTimeForced) return;
     a = timing_event(c);
     if (!a) return;
     if (in_kernel) {

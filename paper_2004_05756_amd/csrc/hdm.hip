@@ -249,9 +249,25 @@ struct PcgState {
     int iters;    // completed iterations of the recursion (since its last fresh start)
     int maxit;
     int poff;     // iteration parity = launch parity ^ poff
+    int qoff;     // 3D: iteration phase (mod 4) = (launch index + qoff) mod 4
     int fresh;    // the recursion starts here: the first apply records bb, beta = 0
     int it0;      // iterations at the segment's start
-    double alpha[2];  // alpha of the last two updates, by iteration parity
+    double alpha[4];  // alpha of the last updates of a correction group, by iteration
+                      // phase (mod the group size)
+};
+
+// Steps the float64 correction x takes at once (a group), and with it the ring of search
+// directions p_i (in slot i mod G) that the apply writes and the update reads: 2 in 2D
+// (p0, p1), 4 in 3D (p0..p3).  x += sum of alpha_j p_{j+1} over the group's updates j, at
+// the group's last update; the earlier ones only record alpha_j.
+template <int DIM>
+struct XGroup {
+    static constexpr int value = DIM == 3 ? 4 : 2;
+};
+
+template <typename T>
+struct PRing {
+    T* s[4];
 };
 
 constexpr int kPcgParts = 8;  // partial arrays per field (5 used by the two-kernel
@@ -482,23 +498,24 @@ __global__ __launch_bounds__(kBlock, sizeof(T) == 4 ? 4 : 2) void k_pcg_apply3(G
                                                        const FacTab<T> Mv,
                                                        const T* __restrict__ r /* z when float64 */,
                                                        const T* __restrict__ winv,
-                                                       T ik0, T ik1, T ik2, T* __restrict__ p0,
-                                                       T* __restrict__ p1, T* __restrict__ q,
+                                                       T ik0, T ik1, T ik2, const PRing<T> pr,
+                                                       T* __restrict__ q,
                                                        T* __restrict__ side, const SideGeom sg,
                                                        double* __restrict__ part, PcgState* st, int ps,
-                                                       int nrz, int lp) {
+                                                       int nrz, int lq) {
     const FieldBlock fb = field_block();
     PcgState* sb = st + fb.field;
     if (sb->done) return;
     __shared__ OnceLds<T> L;
     __shared__ double lds[48];
-    const int parity = lp ^ sb->poff;
+    const int phase = (lq + sb->qoff) & 3;  // iteration mod 4: p_i in slot phase
+    const int parity = phase & 1;
     const size_t fo = (size_t)fb.field * g.n_dofs;
     alpha += (size_t)fb.field * g.n_elems;
     r += fo;
     winv += (size_t)fb.field * g.n_nodes;
-    const T* p_old = (parity ? p1 : p0) + fo;
-    T* p_new = (parity ? p0 : p1) + fo;
+    const T* p_old = pr.s[phase] + fo;
+    T* p_new = pr.s[(phase + 1) & 3] + fo;
     q += fo;
     side += (size_t)fb.field * 3 * sg.total;
     double* pb = part + (size_t)fb.field * kPcgParts * ps;
@@ -528,41 +545,44 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_update(Grid g, const T* __res
                                                        const uint8_t* __restrict__ mask,
                                                        T ik0, T ik1, T ik2, double* __restrict__ x,
                                                        T* __restrict__ r, T* __restrict__ z,
-                                                       const T* __restrict__ p0,
-                                                       const T* __restrict__ p1,
+                                                       const PRing<T> pr,
                                                        const T* __restrict__ q,
                                                        const T* __restrict__ side, const SideGeom sg,
                                                        double* __restrict__ part, PcgState* st,
-                                                       int ps, int npq, int lp) {
+                                                       int ps, int npq, int lq) {
+    constexpr int G = XGroup<DIM>::value;
     const int f = blockIdx.y;
     PcgState* sb = st + f;
     if (sb->done) return;
     __shared__ double lds[32];
-    const int parity = lp ^ sb->poff;
+    // iteration i mod G (G = 4: from the launch index mod 4; G = 2: the parity)
+    const int phase = G == 4 ? ((lq + sb->qoff) & 3) : ((lq ^ sb->poff) & 1);
+    const int parity = phase & 1;
     const size_t fo = (size_t)f * g.n_dofs;
     winv += (size_t)f * g.n_nodes;
     x += fo;
     r += fo;
     if (z) z += fo;
-    const T* p = (parity ? p0 : p1) + fo;       // the apply's p_new (p_i)
-    const T* pprev = (parity ? p1 : p0) + fo;   // its p_old (p_{i-1})
+    const T* p = pr.s[(phase + 1) & (G - 1)] + fo;  // the apply's p_new
     q += fo;
     double* pb = part + (size_t)f * kPcgParts * ps;
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     const bool own = n < g.n_nodes;
-    // the correction x takes two steps at once: alpha_{i-1} p_{i-1} + alpha_i p_i at every
-    // second update of the segment (the first one of a pair only records its alpha)
-    const bool pair = parity != (sb->it0 & 1);
+    // the correction x takes G steps at once, at the group's last update of the segment
+    // (the earlier ones only record their alpha): the directions of the group's earlier
+    // updates are older slots of the ring
+    const bool flush = ((phase - sb->it0) & (G - 1)) == G - 1;
     double xv[DIM];
-    T rv[DIM], pv[DIM], ppv[DIM], qv[DIM], w = T(0);
+    T rv[DIM], pv[DIM], ppv[G - 1][DIM], qv[DIM], w = T(0);
     if (own) {
         w = winv[n];
 #pragma unroll
         for (int c = 0; c < DIM; ++c) {
             const size_t i = (size_t)c * g.n_nodes + n;
-            if (pair) {
+            if (flush) {
                 xv[c] = x[i];
-                ppv[c] = pprev[i];
+#pragma unroll
+                for (int j = 1; j < G; ++j) ppv[j - 1][c] = pr.s[(phase + 1 - j) & (G - 1)][fo + i];
             }
             rv[c] = r[i];
             pv[c] = p[i];
@@ -596,14 +616,21 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_update(Grid g, const T* __res
         return;
     }
     const T a = (T)(sb->rz[parity] / pq);
-    const double a0 = pair ? sb->alpha[parity ^ 1] : 0.0;
+    double ao[G - 1];  // alpha of the group's earlier updates (j steps back)
+#pragma unroll
+    for (int j = 1; j < G; ++j) ao[j - 1] = flush ? sb->alpha[(phase - j) & (G - 1)] : 0.0;
     const T ik[3] = {ik0, ik1, ik2};
     double v[2] = {0.0, 0.0};
     if (own) {
 #pragma unroll
         for (int c = 0; c < DIM; ++c) {
             const size_t i = (size_t)c * g.n_nodes + n;
-            if (pair) x[i] = xv[c] + (a0 * (double)ppv[c] + (double)a * (double)pv[c]);
+            if (flush) {
+                // pairs of steps, oldest pair first
+                double s = ao[0] * (double)ppv[0][c] + (double)a * (double)pv[c];
+                if constexpr (G == 4) s = (ao[2] * (double)ppv[2][c] + ao[1] * (double)ppv[1][c]) + s;
+                x[i] = xv[c] + s;
+            }
             const T ri = rv[c] - a * qv[c];
             const T zi = jacobi_z(ri, w, ik[c]);
             r[i] = ri;
@@ -617,7 +644,7 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_update(Grid g, const T* __res
         part_rz(pb, ps, parity)[blockIdx.x] = v[0];
         part_rr(pb, ps, parity)[blockIdx.x] = v[1];
         if (blockIdx.x == 0) {
-            sb->alpha[parity] = (double)a;
+            sb->alpha[phase] = (double)a;
             sb->iters = sb->iters + 1;
         }
     }
@@ -997,26 +1024,32 @@ __global__ void k_correct(long long n, double* __restrict__ u, const T* __restri
         u[(size_t)f * n + i] += sf * (double)d[(size_t)f * n + i];
 }
 
-// u += s * x for the two-kernel recursion, whose x lacks the last step alpha_n p_n when
-// the segment's updates ended on the first of a pair (x takes two steps at a time):
-// that step is added here from the state (alpha by parity) and p_n (the buffer the
-// apply of iteration n wrote).
-template <typename T>
+// u += s * x for the two-kernel recursion, whose x lacks the last m = (iters - it0) mod G
+// steps when the segment's updates ended inside a correction group (x takes G steps at a
+// time): those steps are added here from the state (alpha by iteration phase) and the
+// ring of directions (p_{j+1} of update j in slot (j + 1) mod G).
+template <typename T, int G>
 __global__ void k_correct_pcg(long long n, double* __restrict__ u, const double* __restrict__ x,
-                              const T* __restrict__ p0, const T* __restrict__ p1, const PcgState* __restrict__ st,
-                              const double* __restrict__ s) {
+                              const PRing<T> pr, const PcgState* __restrict__ st, const double* __restrict__ s) {
     const int f = blockIdx.y;
     const double sf = s[f];
     if (sf == 0.0) return;
     const PcgState& S = st[f];
-    const int last = (S.iters - 1) & 1;  // parity of the segment's last update
-    const bool pend = ((S.iters - S.it0) & 1) != 0;
-    const double a = pend ? S.alpha[last] : 0.0;
-    const T* pl = (last ? p0 : p1) + (size_t)f * n;
+    const int m = (S.iters - S.it0) & (G - 1);
+    double a[G - 1];
+    const T* pl[G - 1];
+#pragma unroll
+    for (int j = 0; j < G - 1; ++j) {  // update iters - 1 - j and its direction
+        a[j] = j < m ? S.alpha[(S.iters - 1 - j) & (G - 1)] : 0.0;
+        pl[j] = pr.s[(S.iters - j) & (G - 1)] + (size_t)f * n;
+    }
     x += (size_t)f * n;
     u += (size_t)f * n;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
-        u[i] += sf * (pend ? x[i] + a * (double)pl[i] : x[i]);
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        double add = 0.0;
+        for (int j = m - 1; j >= 0; --j) add += a[j] * (double)pl[j][i];
+        u[i] += sf * (m ? x[i] + add : x[i]);
+    }
 }
 
 // ----------------------------------------------------------------------------------
@@ -1227,6 +1260,8 @@ struct PcgBufs {
     const T* winv;     // [B][N_n]
     T ik[3];           // 1 / K_e[c][c]
     T *r, *z, *p0, *p1, *q, *e0, *e1;  // [B][N_u]
+    T *p2, *p3;        // 3D: the further slots of the ring of directions
+    PRing<T> ring() const { return PRing<T>{{p0, p1, p2, p3}}; }
     T* side;           // 3D: [B][3][side total] the apply's parts of shared nodes
     SideGeom sg;       // 3D: their sections (from the apply's launch geometry)
     FacTab<T> Mv;      // 3D: the reduced element blocks, passed by value
@@ -1257,10 +1292,12 @@ static const void* pcg_apply3_fn(bool narrow) {
     return (const void*)k_pcg_apply3<T, size_t>;
 }
 
-// One iteration of the two-kernel recursion (apply + update) at launch parity lp.
+// One iteration of the two-kernel recursion (apply + update) at launch index lq mod 4
+// (launch parity lp = lq & 1).
 template <int DIM, typename T>
-static void pcg_iteration(Ctx* ctx, const Grid& g, const PcgBufs<T>& w, const PcgGeom& pg, int lp,
+static void pcg_iteration(Ctx* ctx, const Grid& g, const PcgBufs<T>& w, const PcgGeom& pg, int lq,
                           LaunchSink& L, int timing) {
+    const int lp = lq & 1;
     {
         TimedLaunch tl(ctx, KID_PCG_APPLY, L.s, L.graph ? kTimeOff : timing, true);
         L.ev0 = tl.a;
@@ -1271,7 +1308,7 @@ static void pcg_iteration(Ctx* ctx, const Grid& g, const PcgBufs<T>& w, const Pc
         else
             L(pcg_apply3_fn<T>(w.narrow), dim3(pg.napp, w.B), dim3(kBlock), g, w.alpha, w.Mv,
               (const T*)(ApplyFormsZ<T>::value ? w.r : w.z), w.winv, w.ik[0],
-              w.ik[1], w.ik[2], w.p0, w.p1, w.q, w.side, w.sg, w.part, w.st, pg.ps, pg.nrz, lp);
+              w.ik[1], w.ik[2], w.ring(), w.q, w.side, w.sg, w.part, w.st, pg.ps, pg.nrz, lq);
     }
     if (pg.npq == 1 && pg.napp > 1)
         L((const void*)k_partials_sum<PcgState>, dim3(w.B), dim3(1024), w.part, pg.ps, pg.napp, 0, 0, -1, 0,
@@ -1281,8 +1318,8 @@ static void pcg_iteration(Ctx* ctx, const Grid& g, const PcgBufs<T>& w, const Pc
         L.ev0 = tl.a;
         L.ev1 = tl.b;
         L((const void*)k_pcg_update<DIM, T>, dim3(pg.nupd, w.B), dim3(kPcgBlock), g, w.winv, w.mask, w.ik[0],
-          w.ik[1], w.ik[2], w.x, w.r, w.z, (const T*)w.p0, (const T*)w.p1, (const T*)w.q, (const T*)w.side,
-          w.sg, w.part, w.st, pg.ps, pg.npq, lp);
+          w.ik[1], w.ik[2], w.x, w.r, w.z, w.ring(), (const T*)w.q, (const T*)w.side,
+          w.sg, w.part, w.st, pg.ps, pg.npq, lq);
     }
     if (pg.nrz == 1 && pg.nupd > 1)  // rz / rr of the update's own parity
         L((const void*)k_partials_sum<PcgState>, dim3(w.B), dim3(1024), w.part, pg.ps, pg.nupd, 1, 1, 3, 1,
@@ -1367,6 +1404,7 @@ __device__ __forceinline__ void seg_state(const SegCtl& c, double tol2, PcgState
     p.maxit = c.maxit - c.base;
     p.iters = it0;
     p.poff = (it0 & 1) ^ 1;  // the segment's first launch has launch parity 1
+    p.qoff = (it0 - 1) & 3;  // and launch index 1 mod 4
     p.fresh = c.fresh;
     p.it0 = it0;
 }
@@ -1548,7 +1586,7 @@ template <int DIM, typename T>
 static void phase_iteration(Ctx* ctx, const Grid& g, const PcgBufs<T>& w, const PcgGeom& pg, bool one_red,
                             long long it, LaunchSink& L, int timing) {
     if (one_red) cg1_step<T>(ctx, g, w, pg, (int)(it & 1), L, timing, it % kCg1Refresh == 0);
-    else pcg_iteration<DIM, T>(ctx, g, w, pg, (int)(it & 1), L, timing);
+    else pcg_iteration<DIM, T>(ctx, g, w, pg, (int)(it & 3), L, timing);
 }
 
 // K64: the dense element matrix in 2D, the reduced element blocks in 3D.
@@ -1579,7 +1617,7 @@ template <typename T>
 struct HdmWs {
     double *a64 = nullptr, *w64 = nullptr, *r64 = nullptr, *part = nullptr, *rpart = nullptr,
            *rout = nullptr, *x = nullptr, *fsc = nullptr, *corr = nullptr;
-    T *r = nullptr, *z = nullptr, *p0 = nullptr, *p1 = nullptr, *q = nullptr;
+    T *r = nullptr, *z = nullptr, *p0 = nullptr, *p1 = nullptr, *p2 = nullptr, *p3 = nullptr, *q = nullptr;
     T *e0 = nullptr, *e1 = nullptr;  // 2D float64: the one-reduction recursion's two further vectors
     T* side = nullptr;               // 3D: the apply's parts of shared nodes
     float *a32 = nullptr, *w32 = nullptr;
@@ -1617,6 +1655,10 @@ static void hdm_takes(Arena& ar, const Grid& g, bool mixed, int B, HdmWs<T>& w) 
     if (!(g.dim == 3 && ApplyFormsZ<T>::value)) ar.take(&w.z, N);  // the float 3D apply forms z
     ar.take(&w.p0, N);
     ar.take(&w.p1, N);
+    if (g.dim == 3) {  // the ring of four directions
+        ar.take(&w.p2, N);
+        ar.take(&w.p3, N);
+    }
     ar.take(&w.q, N);
     if (g.dim == 2 && !mixed) {
         ar.take(&w.e0, N);
@@ -1675,8 +1717,8 @@ static void chunk_end(const Grid& g, const Grid& gres, const double* K64, const 
         L((const void*)k_correct<double>, dim3(std::min(grid_blocks(N), 1024), w.B), dim3(kBlock), N, u,
           (const double*)w.x, (const double*)c.corr);
     else
-        L((const void*)k_correct_pcg<T>, dim3(std::min(grid_blocks(N), 1024), w.B), dim3(kBlock), N, u,
-          (const double*)w.x, (const T*)w.p0, (const T*)w.p1, (const PcgState*)w.st, (const double*)c.corr);
+        L((const void*)k_correct_pcg<T, XGroup<DIM>::value>, dim3(std::min(grid_blocks(N), 1024), w.B),
+          dim3(kBlock), N, u, (const double*)w.x, w.ring(), (const PcgState*)w.st, (const double*)c.corr);
     residual_sink(L, gres, K64, a64, w.mask, u, f, (double*)w.r64, w.B, rpart, rout, (const int*)c.skip);
     if (one_red)
         L((const void*)k_seg_control<Cg1State>, gb, bb, w.B, w.st1, c.ctl, (const double*)rout, c.fsc, c.live, rtol,
@@ -1739,6 +1781,8 @@ static int hdm_batch_impl(Ctx* ctx, const topo_mesh& m, const Grid& g0, const El
     w.z = ws.z;
     w.p0 = ws.p0;
     w.p1 = ws.p1;
+    w.p2 = ws.p2;
+    w.p3 = ws.p3;
     w.q = ws.q;
     w.e0 = ws.e0;
     w.e1 = ws.e1;
@@ -1798,11 +1842,12 @@ static int hdm_batch_impl(Ctx* ctx, const topo_mesh& m, const Grid& g0, const El
         TOPO_CHECK_LAUNCH();
     }
     // mode: kTimeOff (graph construction), kTimeForced (a timing sample replacing a
-    // replay: its first two iterations timed), kTimeSampled (no graphs)
+    // replay: its first kTimeRun iterations timed, a whole correction group), kTimeSampled
+    // (no graphs)
     const int chunk_len = pcg_chunk_len(g, B);
     auto chunk = [&](LaunchSink& L, int mode) {
         for (int q = 0; q < chunk_len; ++q) {
-            const int tm = mode == kTimeForced ? (q < 2 ? kTimeForced : kTimeOff) : mode;
+            const int tm = mode == kTimeForced ? (q < kTimeRun ? kTimeForced : kTimeOff) : mode;
             phase_iteration<DIM, T>(ctx, g, w, pg, one_red, 1 + q, L, tm);
         }
         chunk_end<DIM, T>(g, gres, K64, ws.a64, f, u, ws.rpart, ws.rout, w, pg, one_red, c, rtol, seg_min, L);
@@ -1814,7 +1859,7 @@ static int hdm_batch_impl(Ctx* ctx, const topo_mesh& m, const Grid& g0, const El
                                       (uintptr_t)g.nx, (uintptr_t)g.ny, (uintptr_t)g.nz, (uintptr_t)g.mtarget,
                                       (uintptr_t)gres.mtarget, (uintptr_t)w.alpha, (uintptr_t)w.K,
                                       (uintptr_t)w.mask, (uintptr_t)w.winv, (uintptr_t)w.x, (uintptr_t)w.r,
-                                      (uintptr_t)w.z, (uintptr_t)w.p0, (uintptr_t)w.p1, (uintptr_t)w.q,
+                                      (uintptr_t)w.z, (uintptr_t)w.p0, (uintptr_t)w.p1, (uintptr_t)w.p2, (uintptr_t)w.p3, (uintptr_t)w.q,
                                       (uintptr_t)w.e0, (uintptr_t)w.e1, (uintptr_t)w.side, (uintptr_t)w.part,
                                       (uintptr_t)w.st,
                                       (uintptr_t)w.st1, (uintptr_t)ws.a64, (uintptr_t)ws.r64, (uintptr_t)ws.rpart,
