@@ -49,8 +49,8 @@ def parse():
     ap.add_argument("--max-refine", type=int, default=1)
     ap.add_argument("--rom-evals", type=int, default=5, help="batched ROM evaluations per precision")
     ap.add_argument("--timing-every", type=int, default=4,
-                    help="sample one run of 4 consecutive launches in N of each hot kernel (with graphs: "
-                         "the first 4 iterations of one chunk replay in N)")
+                    help="sample one run of 8 consecutive launches in N of each hot kernel (with graphs: "
+                         "the first 8 iterations of one chunk replay in N)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the precision, 2D batch, per-config, basis, filter and trust-region legs")
@@ -77,14 +77,14 @@ def pcg_bytes(n_dofs, n_nodes, n_elems, word, dim=2):
     apply (two-kernel form): read z, p_old (stencil), alpha, mask; write p_new, q
     update (two-kernel form): read r; write r, z; read p, q, 1/sum(alpha) per node; and
           at the last update of each group of G (x takes G steps at a time: G = 2 in 2D,
-          4 in 3D) read and write x (float64) and read the group's G - 1 earlier
+          8 in 3D) read and write x (float64) and read the group's G - 1 earlier
           directions: on average (16 + (G - 1) w) / G bytes per DOF
     In 3D the update applies the mask (one byte per DOF moves from the apply to the
     update), and the float32 apply reads r and 1/sum(alpha) per node and forms z itself,
     so its update writes no z."""
     forms_z = dim == 3 and word == 4
     mask_apply = 1 if dim == 2 else 0
-    group = 4 if dim == 3 else 2
+    group = 8 if dim == 3 else 2
     x_bytes = (16 + (group - 1) * word) / group
     return {
         "pcg_step": n_dofs * (8 * word + 17) + n_nodes * word + n_elems * word,

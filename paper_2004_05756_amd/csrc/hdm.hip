@@ -249,25 +249,26 @@ struct PcgState {
     int iters;    // completed iterations of the recursion (since its last fresh start)
     int maxit;
     int poff;     // iteration parity = launch parity ^ poff
-    int qoff;     // 3D: iteration phase (mod 4) = (launch index + qoff) mod 4
+    int qoff;     // 3D: iteration phase (mod 8) = (launch index + qoff) mod 8
     int fresh;    // the recursion starts here: the first apply records bb, beta = 0
     int it0;      // iterations at the segment's start
-    double alpha[4];  // alpha of the last updates of a correction group, by iteration
+    double alpha[8];  // alpha of the last updates of a correction group, by iteration
                       // phase (mod the group size)
 };
 
 // Steps the float64 correction x takes at once (a group), and with it the ring of search
 // directions p_i (in slot i mod G) that the apply writes and the update reads: 2 in 2D
-// (p0, p1), 4 in 3D (p0..p3).  x += sum of alpha_j p_{j+1} over the group's updates j, at
+// (p0, p1), 8 in 3D (p0..p7).  x += sum of alpha_j p_{j+1} over the group's updates j, at
 // the group's last update; the earlier ones only record alpha_j.
+constexpr int kRing3 = 8;
 template <int DIM>
 struct XGroup {
-    static constexpr int value = DIM == 3 ? 4 : 2;
+    static constexpr int value = DIM == 3 ? kRing3 : 2;
 };
 
 template <typename T>
 struct PRing {
-    T* s[4];
+    T* s[kRing3];
 };
 
 constexpr int kPcgParts = 8;  // partial arrays per field (5 used by the two-kernel
@@ -508,14 +509,14 @@ __global__ __launch_bounds__(kBlock, sizeof(T) == 4 ? 4 : 2) void k_pcg_apply3(G
     if (sb->done) return;
     __shared__ OnceLds<T> L;
     __shared__ double lds[48];
-    const int phase = (lq + sb->qoff) & 3;  // iteration mod 4: p_i in slot phase
+    const int phase = (lq + sb->qoff) & (kRing3 - 1);  // iteration mod 8: p_i in slot phase
     const int parity = phase & 1;
     const size_t fo = (size_t)fb.field * g.n_dofs;
     alpha += (size_t)fb.field * g.n_elems;
     r += fo;
     winv += (size_t)fb.field * g.n_nodes;
     const T* p_old = pr.s[phase] + fo;
-    T* p_new = pr.s[(phase + 1) & 3] + fo;
+    T* p_new = pr.s[(phase + 1) & (kRing3 - 1)] + fo;
     q += fo;
     side += (size_t)fb.field * 3 * sg.total;
     double* pb = part + (size_t)fb.field * kPcgParts * ps;
@@ -540,7 +541,7 @@ __global__ __launch_bounds__(kBlock, sizeof(T) == 4 ? 4 : 2) void k_pcg_apply3(G
 // One node per thread (grid (nupd, B)); the node's loads are issued before the wait on
 // the scalar reduction.  3D: q is zeroed at masked DOFs here (the 3D apply writes
 // unmasked parts), so that r stays zero there; the 2D apply masks q itself.
-template <int DIM, typename T>
+template <int DIM, typename T, bool FLUSH>
 __global__ __launch_bounds__(kPcgBlock) void k_pcg_update(Grid g, const T* __restrict__ winv,
                                                        const uint8_t* __restrict__ mask,
                                                        T ik0, T ik1, T ik2, double* __restrict__ x,
@@ -555,8 +556,8 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_update(Grid g, const T* __res
     PcgState* sb = st + f;
     if (sb->done) return;
     __shared__ double lds[32];
-    // iteration i mod G (G = 4: from the launch index mod 4; G = 2: the parity)
-    const int phase = G == 4 ? ((lq + sb->qoff) & 3) : ((lq ^ sb->poff) & 1);
+    // iteration i mod G (3D: from the launch index mod 8; 2D: the parity)
+    const int phase = G == kRing3 ? ((lq + sb->qoff) & (kRing3 - 1)) : ((lq ^ sb->poff) & 1);
     const int parity = phase & 1;
     const size_t fo = (size_t)f * g.n_dofs;
     winv += (size_t)f * g.n_nodes;
@@ -568,10 +569,12 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_update(Grid g, const T* __res
     double* pb = part + (size_t)f * kPcgParts * ps;
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     const bool own = n < g.n_nodes;
-    // the correction x takes G steps at once, at the group's last update of the segment
-    // (the earlier ones only record their alpha): the directions of the group's earlier
-    // updates are older slots of the ring
-    const bool flush = ((phase - sb->it0) & (G - 1)) == G - 1;
+    // the correction x takes G steps at once, at the group's last update (the earlier ones
+    // only record their alpha): the directions of the group's earlier updates are older
+    // slots of the ring.  Segments start at launch 1 of a chunk and chunks hold a multiple
+    // of G launches, so every field's groups end together, at the launches whose index
+    // is a multiple of G: those run this kernel with FLUSH.
+    constexpr bool flush = FLUSH;
     double xv[DIM];
     T rv[DIM], pv[DIM], ppv[G - 1][DIM], qv[DIM], w = T(0);
     if (own) {
@@ -619,6 +622,7 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_update(Grid g, const T* __res
     double ao[G - 1];  // alpha of the group's earlier updates (j steps back)
 #pragma unroll
     for (int j = 1; j < G; ++j) ao[j - 1] = flush ? sb->alpha[(phase - j) & (G - 1)] : 0.0;
+    (void)ao;
     const T ik[3] = {ik0, ik1, ik2};
     double v[2] = {0.0, 0.0};
     if (own) {
@@ -626,9 +630,13 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_update(Grid g, const T* __res
         for (int c = 0; c < DIM; ++c) {
             const size_t i = (size_t)c * g.n_nodes + n;
             if (flush) {
-                // pairs of steps, oldest pair first
-                double s = ao[0] * (double)ppv[0][c] + (double)a * (double)pv[c];
-                if constexpr (G == 4) s = (ao[2] * (double)ppv[2][c] + ao[1] * (double)ppv[1][c]) + s;
+                // pairs of steps summed from the oldest pair to the newest
+                double s = G > 2 ? ao[G - 2] * (double)ppv[G - 2][c] + ao[G - 3] * (double)ppv[G - 3][c]
+                                 : ao[0] * (double)ppv[0][c] + (double)a * (double)pv[c];
+#pragma unroll
+                for (int k = G / 2 - 2; k >= 1; --k)
+                    s += ao[2 * k] * (double)ppv[2 * k][c] + ao[2 * k - 1] * (double)ppv[2 * k - 1][c];
+                if constexpr (G > 2) s += ao[0] * (double)ppv[0][c] + (double)a * (double)pv[c];
                 x[i] = xv[c] + s;
             }
             const T ri = rv[c] - a * qv[c];
@@ -1260,8 +1268,14 @@ struct PcgBufs {
     const T* winv;     // [B][N_n]
     T ik[3];           // 1 / K_e[c][c]
     T *r, *z, *p0, *p1, *q, *e0, *e1;  // [B][N_u]
-    T *p2, *p3;        // 3D: the further slots of the ring of directions
-    PRing<T> ring() const { return PRing<T>{{p0, p1, p2, p3}}; }
+    T* pk[kRing3 - 2];  // 3D: the further slots of the ring of directions
+    PRing<T> ring() const {
+        PRing<T> r{};
+        r.s[0] = p0;
+        r.s[1] = p1;
+        for (int k = 2; k < kRing3; ++k) r.s[k] = pk[k - 2];
+        return r;
+    }
     T* side;           // 3D: [B][3][side total] the apply's parts of shared nodes
     SideGeom sg;       // 3D: their sections (from the apply's launch geometry)
     FacTab<T> Mv;      // 3D: the reduced element blocks, passed by value
@@ -1292,7 +1306,7 @@ static const void* pcg_apply3_fn(bool narrow) {
     return (const void*)k_pcg_apply3<T, size_t>;
 }
 
-// One iteration of the two-kernel recursion (apply + update) at launch index lq mod 4
+// One iteration of the two-kernel recursion (apply + update) at launch index lq mod 8
 // (launch parity lp = lq & 1).
 template <int DIM, typename T>
 static void pcg_iteration(Ctx* ctx, const Grid& g, const PcgBufs<T>& w, const PcgGeom& pg, int lq,
@@ -1317,9 +1331,10 @@ static void pcg_iteration(Ctx* ctx, const Grid& g, const PcgBufs<T>& w, const Pc
         TimedLaunch tl(ctx, KID_PCG_UPDATE, L.s, L.graph ? kTimeOff : timing, true);
         L.ev0 = tl.a;
         L.ev1 = tl.b;
-        L((const void*)k_pcg_update<DIM, T>, dim3(pg.nupd, w.B), dim3(kPcgBlock), g, w.winv, w.mask, w.ik[0],
-          w.ik[1], w.ik[2], w.x, w.r, w.z, w.ring(), (const T*)w.q, (const T*)w.side,
-          w.sg, w.part, w.st, pg.ps, pg.npq, lq);
+        const bool flush = (lq & (XGroup<DIM>::value - 1)) == 0;  // a group's last update
+        L(flush ? (const void*)k_pcg_update<DIM, T, true> : (const void*)k_pcg_update<DIM, T, false>,
+          dim3(pg.nupd, w.B), dim3(kPcgBlock), g, w.winv, w.mask, w.ik[0], w.ik[1], w.ik[2], w.x, w.r, w.z,
+          w.ring(), (const T*)w.q, (const T*)w.side, w.sg, w.part, w.st, pg.ps, pg.npq, lq);
     }
     if (pg.nrz == 1 && pg.nupd > 1)  // rz / rr of the update's own parity
         L((const void*)k_partials_sum<PcgState>, dim3(w.B), dim3(1024), w.part, pg.ps, pg.nupd, 1, 1, 3, 1,
@@ -1404,7 +1419,7 @@ __device__ __forceinline__ void seg_state(const SegCtl& c, double tol2, PcgState
     p.maxit = c.maxit - c.base;
     p.iters = it0;
     p.poff = (it0 & 1) ^ 1;  // the segment's first launch has launch parity 1
-    p.qoff = (it0 - 1) & 3;  // and launch index 1 mod 4
+    p.qoff = (it0 - 1) & (kRing3 - 1);  // and launch index 1 mod 8
     p.fresh = c.fresh;
     p.it0 = it0;
 }
@@ -1553,6 +1568,7 @@ constexpr int kCg1Refresh = 16;
 static int pcg_chunk_len(const Grid& g, int B) {
     return (long long)g.n_dofs * B <= (4LL << 20) ? 64 : 16;
 }
+static_assert(16 % kRing3 == 0 && 64 % kRing3 == 0, "chunks hold whole correction groups");
 
 // Start of a segment for the fields with a nonzero scale fsc[b] (their states written
 // by the segment controller): its partials for the first launch of the next chunk
@@ -1586,7 +1602,7 @@ template <int DIM, typename T>
 static void phase_iteration(Ctx* ctx, const Grid& g, const PcgBufs<T>& w, const PcgGeom& pg, bool one_red,
                             long long it, LaunchSink& L, int timing) {
     if (one_red) cg1_step<T>(ctx, g, w, pg, (int)(it & 1), L, timing, it % kCg1Refresh == 0);
-    else pcg_iteration<DIM, T>(ctx, g, w, pg, (int)(it & 3), L, timing);
+    else pcg_iteration<DIM, T>(ctx, g, w, pg, (int)(it & (kRing3 - 1)), L, timing);
 }
 
 // K64: the dense element matrix in 2D, the reduced element blocks in 3D.
@@ -1617,7 +1633,8 @@ template <typename T>
 struct HdmWs {
     double *a64 = nullptr, *w64 = nullptr, *r64 = nullptr, *part = nullptr, *rpart = nullptr,
            *rout = nullptr, *x = nullptr, *fsc = nullptr, *corr = nullptr;
-    T *r = nullptr, *z = nullptr, *p0 = nullptr, *p1 = nullptr, *p2 = nullptr, *p3 = nullptr, *q = nullptr;
+    T *r = nullptr, *z = nullptr, *p0 = nullptr, *p1 = nullptr, *q = nullptr;
+    T* pk[kRing3 - 2] = {};  // 3D: ring slots 2..7
     T *e0 = nullptr, *e1 = nullptr;  // 2D float64: the one-reduction recursion's two further vectors
     T* side = nullptr;               // 3D: the apply's parts of shared nodes
     float *a32 = nullptr, *w32 = nullptr;
@@ -1655,10 +1672,8 @@ static void hdm_takes(Arena& ar, const Grid& g, bool mixed, int B, HdmWs<T>& w) 
     if (!(g.dim == 3 && ApplyFormsZ<T>::value)) ar.take(&w.z, N);  // the float 3D apply forms z
     ar.take(&w.p0, N);
     ar.take(&w.p1, N);
-    if (g.dim == 3) {  // the ring of four directions
-        ar.take(&w.p2, N);
-        ar.take(&w.p3, N);
-    }
+    if (g.dim == 3)  // the ring of kRing3 directions
+        for (int k = 0; k < kRing3 - 2; ++k) ar.take(&w.pk[k], N);
     ar.take(&w.q, N);
     if (g.dim == 2 && !mixed) {
         ar.take(&w.e0, N);
@@ -1781,8 +1796,7 @@ static int hdm_batch_impl(Ctx* ctx, const topo_mesh& m, const Grid& g0, const El
     w.z = ws.z;
     w.p0 = ws.p0;
     w.p1 = ws.p1;
-    w.p2 = ws.p2;
-    w.p3 = ws.p3;
+    for (int k = 0; k < kRing3 - 2; ++k) w.pk[k] = ws.pk[k];
     w.q = ws.q;
     w.e0 = ws.e0;
     w.e1 = ws.e1;
@@ -1859,13 +1873,14 @@ static int hdm_batch_impl(Ctx* ctx, const topo_mesh& m, const Grid& g0, const El
                                       (uintptr_t)g.nx, (uintptr_t)g.ny, (uintptr_t)g.nz, (uintptr_t)g.mtarget,
                                       (uintptr_t)gres.mtarget, (uintptr_t)w.alpha, (uintptr_t)w.K,
                                       (uintptr_t)w.mask, (uintptr_t)w.winv, (uintptr_t)w.x, (uintptr_t)w.r,
-                                      (uintptr_t)w.z, (uintptr_t)w.p0, (uintptr_t)w.p1, (uintptr_t)w.p2, (uintptr_t)w.p3, (uintptr_t)w.q,
+                                      (uintptr_t)w.z, (uintptr_t)w.p0, (uintptr_t)w.p1, (uintptr_t)w.q,
                                       (uintptr_t)w.e0, (uintptr_t)w.e1, (uintptr_t)w.side, (uintptr_t)w.part,
                                       (uintptr_t)w.st,
                                       (uintptr_t)w.st1, (uintptr_t)ws.a64, (uintptr_t)ws.r64, (uintptr_t)ws.rpart,
                                       (uintptr_t)ws.rout, (uintptr_t)u, (uintptr_t)f, (uintptr_t)c.ctl,
                                       (uintptr_t)c.skip, (uintptr_t)c.live, (uintptr_t)c.corr, (uintptr_t)c.fsc};
         for (int q = 0; q < 3; ++q) key_push_double(key, (double)w.ik[q]);
+        for (int k = 0; k < kRing3 - 2; ++k) key.push_back((uintptr_t)w.pk[k]);
         key_push_double(key, rtol);
         key_push_double(key, seg_min);
         rc = cached_graph(ctx, key, [&](LaunchSink& G) { chunk(G, kTimeOff); }, &exec, s);

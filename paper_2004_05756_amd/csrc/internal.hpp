@@ -101,14 +101,14 @@ void timing_drain(Ctx* c);
 
 // mode: kTimeOff never records (e.g. while building a graph), kTimeSampled records one
 // run of kTimeRun consecutive launches in `every` runs, kTimeForced records whenever
-// timing is enabled.  Runs of 4: the 3D PCG update alternates three cheaper launches
-// with one that also updates the correction (a group of 4 steps), so a sample of whole
+// timing is enabled.  Runs of 8: the 3D PCG update alternates seven cheaper launches
+// with one that also updates the correction (a group of 8 steps), so a sample of whole
 // runs averages the two kinds in their proportion.  With in_kernel,
 // a sampled launch gets the event pair (a, b) to pass to hipExtLaunchKernel, which
 // stamps them when the kernel itself starts and ends (no marker packets around it);
 // otherwise a and b are recorded on the stream before and after the launch.
 enum { kTimeOff = 0, kTimeSampled = 1, kTimeForced = 2 };
-constexpr int kTimeRun = 4;
+constexpr int kTimeRun = 8;
 struct TimedLaunch {
     Ctx* c;
     int kid;

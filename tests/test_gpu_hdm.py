@@ -196,11 +196,11 @@ def test_2d_solve_on_degenerate_shapes(nel, kind, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-@pytest.mark.parametrize("maxit", [5, 6, 7, 8])
+@pytest.mark.parametrize("maxit", [5, 6, 7, 8, 9, 11])
 def test_iteration_limit_returns_the_last_iterate(prec, maxit):
-    """A solve stopped by its iteration limit after k = 5..8 steps.  The two-kernel
-    recursion adds its steps to the correction in groups (two in 2D, four in 3D), so a
-    count that is not a multiple of the group leaves 1..3 steps pending when the segment
+    """A solve stopped by its iteration limit after k = 5..11 steps.  The two-kernel
+    recursion adds its steps to the correction in groups (two in 2D, eight in 3D), so a
+    count that is not a multiple of the group leaves 1..7 steps pending when the segment
     ends; the returned u must still be the k-th Jacobi-PCG iterate from u = 0 (Sec.
     3.1's inner solver), here scipy's CG with the same preconditioner on the oracle's
     assembled K_ff, and the reported residual must be that of the returned u."""
