@@ -108,14 +108,17 @@ const char* topo_strerror(int32_t code);
 /* Bytes of device workspace currently held by ctx (host scalar). */
 size_t topo_ctx_workspace_bytes(const topo_ctx* ctx);
 
-/* Instrumentation: bracket one launch in `every` (0 = off) of each hot kernel of ctx
- * with a pair of HIP events on the stream it runs on. */
+/* Instrumentation: bracket one run of 8 consecutive launches in `every` runs (0 = off)
+ * of each hot kernel of ctx with HIP events on the stream it runs on (runs of 8: the
+ * 3D PCG update's correction group). */
 int topo_ctx_set_timing(topo_ctx* ctx, int32_t every);
 /* Sampled launches and their summed device time in ms for one hot kernel: "apply",
  * "pcg_apply", "pcg_update", "residual", "rom_contract", "rom_reduce", "phit_v",
  * "phi_y", "chol", "chol_solve", "gradient", "pcg_step" (the one kernel per
  * iteration of the 2D float64 solve; "pcg_apply" / "pcg_update" are the two of the
- * other solves), and the number of launches of that kernel issued since the last
+ * other solves), "rom_apply" (the ROM build's transposed basis and K Phi products, per
+ * field; "rom_contract" is then its matrix-core product, per field), and the number of
+ * launches of that kernel issued since the last
  * reset while timing was on (graph replays included; may be NULL).  A launch of a
  * batched kernel covers every field of its batch.  Waits for pending samples (host
  * outputs); reset != 0 clears the kernel's counters afterwards. */

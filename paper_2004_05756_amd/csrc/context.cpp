@@ -315,7 +315,7 @@ const ElemTables* get_tables(Ctx* ctx, const topo_mesh& m) {
 
 const char* const kKernelNames[KID_COUNT] = {
     "apply", "pcg_apply", "pcg_update", "residual", "rom_contract", "rom_reduce",
-    "phit_v", "phi_y", "chol", "chol_solve", "gradient", "pcg_step"};
+    "phit_v", "phi_y", "chol", "chol_solve", "gradient", "pcg_step", "rom_apply"};
 
 static hipEvent_t timing_event(Ctx* c) {
     if (!c->timing.pool.empty()) {

@@ -56,20 +56,23 @@ __global__ void k_winv(Grid g, const double* __restrict__ a64, double* __restric
 }
 
 // ----------------------------------------------------------------------------------
-// Public apply: y_b = K(rho_b) x_b, Dirichlet rows and columns eliminated.
+// Public apply: y_b = K(rho_b) x_b, Dirichlet rows and columns eliminated.  astride:
+// elements between the alpha tables of consecutive vectors (N_e; 0 when every vector
+// shares one density field, as the columns of the ROM contraction do); vstride: entries
+// between consecutive vectors of x and y (N_u, or a padded pitch).
 // ----------------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_apply2(Grid g, const T* __restrict__ alpha,
-                                                   const T* __restrict__ K,
+__global__ __launch_bounds__(kBlock) void k_apply2(Grid g, const T* __restrict__ alpha, long long astride,
+                                                   long long vstride, const T* __restrict__ K,
                                                    const uint8_t* __restrict__ mask,
                                                    const T* __restrict__ x, T* __restrict__ y) {
     const FieldBlock fb = field_block();
     const int n = fb.blk * blockDim.x + threadIdx.x;
     if (n >= g.n_nodes) return;
     const size_t b = fb.field;
-    const T* xb = x + b * g.n_dofs;
-    T* yb = y + b * g.n_dofs;
-    const T* ab = alpha + b * g.n_elems;
+    const T* xb = x + b * vstride;
+    T* yb = y + b * vstride;
+    const T* ab = alpha + b * astride;
     int i, j, k;
     node_ijk(g, n, i, j, k);
     FetchMasked<T> f{xb, mask, g.n_nodes};
@@ -195,8 +198,8 @@ __device__ __forceinline__ void march3_prologue(const Grid& g, const MarchBlock&
 // 3D: one block per march column and field.  M is the table of reduced element blocks
 // (apply3_from_n).
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_apply3(Grid g, const T* __restrict__ alpha,
-                                                   const T* __restrict__ M,
+__global__ __launch_bounds__(kBlock) void k_apply3(Grid g, const T* __restrict__ alpha, long long astride,
+                                                   long long vstride, const T* __restrict__ M,
                                                    const uint8_t* __restrict__ mask,
                                                    const T* __restrict__ x, T* __restrict__ y) {
     __shared__ MarchLds<T> L;
@@ -205,9 +208,9 @@ __global__ __launch_bounds__(kBlock) void k_apply3(Grid g, const T* __restrict__
     const MarchBlock m = march3_block(g, fb.blk);
     for (int i = threadIdx.x; i < kFacSize; i += blockDim.x) L.M[i] = M[i];
     const MarchSlots sl = march3_slots(g, m);
-    SrcMasked<T> src{x + b * g.n_dofs, mask, g.n_nodes};
+    SrcMasked<T> src{x + b * vstride, mask, g.n_nodes};
     march3_prologue(g, m, sl, src);
-    T* yb = y + b * g.n_dofs;
+    T* yb = y + b * vstride;
     auto emit = [&](int n, const T (&out)[3], const T (&)[3]) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
@@ -215,7 +218,7 @@ __global__ __launch_bounds__(kBlock) void k_apply3(Grid g, const T* __restrict__
             yb[idx] = mask[idx] ? T(0) : out[c];
         }
     };
-    march3_run(g, m, sl, alpha + b * g.n_elems, L, src, emit);
+    march3_run(g, m, sl, alpha + b * astride, L, src, emit);
 }
 
 // ----------------------------------------------------------------------------------
@@ -2014,6 +2017,34 @@ static int hdm_solve_batch(Ctx* ctx, const topo_mesh& m, const Grid& g, const El
 
 using namespace topo;
 
+namespace topo {
+
+// W = K(rho) X for ncols vectors X = [ncols][ld] (ld >= N_u) sharing one density field
+// (alpha: its table, [N_e]), Dirichlet rows and columns eliminated: the columns of the
+// ROM contraction K_hat = X^T K X.  Entries ld - N_u past each vector are not written.
+template <typename T>
+int apply_columns(Ctx* ctx, const Grid& g0, const ElemTables* tb, const T* alpha, const uint8_t* mask,
+                  const T* x, T* y, int ncols, long long ld, hipStream_t s) {
+    Grid g = g0;
+    constexpr bool F64 = sizeof(T) == 8;
+    if (g.dim == 3) g.mtarget = march3_target(ctx, (const void*)k_apply3<T>);
+    const dim3 grid(stencil_blocks(g), ncols);
+    if (g.dim == 2)
+        hipLaunchKernelGGL((k_apply2<T>), grid, dim3(kBlock), 0, s, g, alpha, 0LL, ld,
+                           F64 ? (const T*)tb->K64 : (const T*)tb->K32, mask, x, y);
+    else
+        hipLaunchKernelGGL((k_apply3<T>), grid, dim3(kBlock), 0, s, g, alpha, 0LL, ld,
+                           F64 ? (const T*)tb->M64 : (const T*)tb->M32, mask, x, y);
+    TOPO_CHECK_LAUNCH();
+    return TOPO_OK;
+}
+template int apply_columns<float>(Ctx*, const Grid&, const ElemTables*, const float*, const uint8_t*,
+                                  const float*, float*, int, long long, hipStream_t);
+template int apply_columns<double>(Ctx*, const Grid&, const ElemTables*, const double*, const uint8_t*,
+                                   const double*, double*, int, long long, hipStream_t);
+
+}  // namespace topo
+
 extern "C" {
 
 int topo_apply(topo_ctx* ctx, const topo_mesh* mesh, const double* rho, const uint8_t* mask,
@@ -2044,18 +2075,18 @@ int topo_apply(topo_ctx* ctx, const topo_mesh* mesh, const double* rho, const ui
     TimedLaunch tl(ctx, KID_APPLY, s);
     if (prec == TOPO_FP64) {
         if (g.dim == 2)
-            hipLaunchKernelGGL((k_apply2<double>), grid, dim3(kBlock), 0, s, g, a64, tb->K64, mask,
-                               (const double*)x, (double*)y);
+            hipLaunchKernelGGL((k_apply2<double>), grid, dim3(kBlock), 0, s, g, a64, (long long)g.n_elems,
+                               (long long)g.n_dofs, tb->K64, mask, (const double*)x, (double*)y);
         else
-            hipLaunchKernelGGL((k_apply3<double>), grid, dim3(kBlock), 0, s, g, a64, tb->M64, mask,
-                               (const double*)x, (double*)y);
+            hipLaunchKernelGGL((k_apply3<double>), grid, dim3(kBlock), 0, s, g, a64, (long long)g.n_elems,
+                               (long long)g.n_dofs, tb->M64, mask, (const double*)x, (double*)y);
     } else {
         if (g.dim == 2)
-            hipLaunchKernelGGL((k_apply2<float>), grid, dim3(kBlock), 0, s, g, a32, tb->K32, mask,
-                               (const float*)x, (float*)y);
+            hipLaunchKernelGGL((k_apply2<float>), grid, dim3(kBlock), 0, s, g, a32, (long long)g.n_elems,
+                               (long long)g.n_dofs, tb->K32, mask, (const float*)x, (float*)y);
         else
-            hipLaunchKernelGGL((k_apply3<float>), grid, dim3(kBlock), 0, s, g, a32, tb->M32, mask,
-                               (const float*)x, (float*)y);
+            hipLaunchKernelGGL((k_apply3<float>), grid, dim3(kBlock), 0, s, g, a32, (long long)g.n_elems,
+                               (long long)g.n_dofs, tb->M32, mask, (const float*)x, (float*)y);
     }
     TOPO_CHECK_LAUNCH();
     return TOPO_OK;

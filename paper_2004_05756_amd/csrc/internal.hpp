@@ -81,7 +81,7 @@ bool element_factor(const topo_mesh& m, const std::vector<double>& K, std::vecto
 // ----------------------------------------------------------------------------------
 enum KernelId {
     KID_APPLY, KID_PCG_APPLY, KID_PCG_UPDATE, KID_RESIDUAL, KID_ROM_CONTRACT, KID_ROM_REDUCE,
-    KID_PHIT_V, KID_PHI_Y, KID_CHOL, KID_CHOL_SOLVE, KID_GRADIENT, KID_PCG_STEP, KID_COUNT
+    KID_PHIT_V, KID_PHI_Y, KID_CHOL, KID_CHOL_SOLVE, KID_GRADIENT, KID_PCG_STEP, KID_ROM_APPLY, KID_COUNT
 };
 extern const char* const kKernelNames[KID_COUNT];
 
@@ -378,6 +378,10 @@ int gradient_launch(Ctx* ctx, const Grid& g, const topo_mesh& m, const ElemTable
 // Resident blocks of a 256-thread kernel on the whole device (its occupancy times the
 // CU count); 1024 when the runtime cannot tell.
 int march3_target(const Ctx* ctx, const void* kernel);
+struct ElemTables;
+template <typename T>
+int apply_columns(Ctx* ctx, const Grid& g, const ElemTables* tb, const T* alpha, const uint8_t* mask,
+                  const T* x, T* y, int ncols, long long ld, hipStream_t s);
 
 // Blocks of a node-stencil launch (apply, PCG apply, residual): one per march column
 // in 3D, one per kBlock consecutive nodes in 2D.

@@ -43,24 +43,25 @@ template <> struct Mfma<double> {
 };
 
 // ----------------------------------------------------------------------------------
-// K_hat contraction.  With K_e = R^T R (symmetry-blocked factor, elemfac.hpp),
-//   K_hat = sum_e alpha_e (R P_e^T Phi)^T (R P_e^T Phi) = D^T D,
-// D stacking the rows sqrt(alpha_e) R P_e^T Phi of every element (5 per Q4, 18 per H8;
-// Dirichlet rows of Phi zeroed, columns zero-padded to KP).
-//   grid.x : element chunks (contiguous element ranges)
-//   grid.y : density fields b
-//   grid.z : groups of upper-triangle 16x16 tile pairs (I <= J)
-// Per sub-chunk of ec elements the block stages D in LDS (one thread per element and
-// column: 2^dim gathered basis rows, edge differences, the small triangular blocks),
-// then each wave accumulates its NT tile pairs K_hat_IJ += D_I^T D_J on the matrix
-// cores, 4 rows per instruction.  NT is a template parameter so that a wave's
-// accumulators stay in place over the row loop (no per-pair branch).  Float32
-// accumulators are flushed to float64 registers after every sub-chunk, and each block
-// writes one float64 partial per tile entry; a second kernel sums the partials over
-// chunks in a fixed order (deterministic).
+// K_hat contraction (Sec. 3.4).  K_hat = sum_e alpha_e Phi_e^T K_e Phi_e = Phi~^T W with
+// W = K(rho) Phi~ (Phi~: the basis with its Dirichlet rows dropped, which the apply does
+// by itself): the element products are formed once per node row by the batched apply
+// (apply_columns, the basis columns as its vectors), and the k x k product over the N_u
+// rows runs on the matrix cores.  Both operands come as k rows of ld >= N_u entries
+// (zero past N_u): Pt, the basis transposed (k_basis_rows), and Wt, the apply's output.
+//   grid.x : chunks of CH DOFs,  grid.y : groups of upper-triangle 16 x 16 tile pairs
+// Per slab of SD DOFs the block stages that slab of every row of Pt and Wt in LDS with
+// 16-byte loads (the next slab's loads in flight while the current one is multiplied),
+// then each of its GW waves accumulates its NT tile pairs K_IJ += Pt_I Wt_J^T, 4 DOFs
+// per instruction.  A block writes its chunk's tiles (float32 sums over CH DOFs in
+// float32, float64 ones in float64); k_chunk_sum adds the chunks in float64 in a fixed
+// order.
 // ----------------------------------------------------------------------------------
-constexpr int WAVES = 4;     // waves per block
-constexpr int MAX_NT = 8;    // most tile pairs per wave (template NT: 1 .. 8)
+constexpr int GW = 8;       // waves per block
+// most tile pairs per wave: 12 in float32 (182 VGPRs), 8 in float64 (202; 12 would spill)
+constexpr int max_nt(bool f64) { return f64 ? 8 : 12; }
+constexpr int KP_MAX = 512; // largest padded basis size
+constexpr int GEMM_LD = 64; // the operands' row pitch is a multiple of this
 
 __device__ __forceinline__ void pair_of(int p, int kt, int& I, int& J) {
     // enumerate (I, J), I <= J, row by row
@@ -73,196 +74,145 @@ __device__ __forceinline__ void pair_of(int p, int kt, int& I, int& J) {
     J = i + p;
 }
 
-template <int DIM, typename TP, typename TC, int NT>
-__global__ __launch_bounds__(WAVES * 64) void k_rom_contract(
-    Grid g, const TP* __restrict__ phi, int k, int ldphi, int KP, int LS,
-    const uint8_t* __restrict__ mask, const TC* __restrict__ alpha /*[B][Ne]*/,
-    const TC* __restrict__ F, int epw, int ec, double* __restrict__ partials) {
-    constexpr int NEN = 1 << DIM;
-    constexpr int NR = DIM == 2 ? kRows2 : kRows3;
+// DOFs per staged slab: a multiple of the 4 of one matrix-core step, sized so that a
+// slab of KP rows is at most 4 16-byte loads per thread and operand.  LDS row pitch
+// SD + 2: the 32 lanes of a half-wave read 16 rows x 2 DOFs on distinct banks.
+template <typename TC>
+__host__ __device__ constexpr int gemm_sd(int KP) {
+    return sizeof(TC) == 4 ? (KP <= 256 ? 32 : 16) : (KP <= 256 ? 16 : 8);
+}
+
+template <typename TC> struct Vec16;
+template <> struct Vec16<float> {
+    typedef float4 type;
+    static __device__ __forceinline__ float at(const float4& a, int v) {
+        return v == 0 ? a.x : v == 1 ? a.y : v == 2 ? a.z : a.w;
+    }
+    // a, or zeros (per component: a select of the whole vector goes through memory)
+    static __device__ __forceinline__ float4 keep(bool ok, const float4& a) {
+        return float4{ok ? a.x : 0.f, ok ? a.y : 0.f, ok ? a.z : 0.f, ok ? a.w : 0.f};
+    }
+};
+template <> struct Vec16<double> {
+    typedef double2 type;
+    static __device__ __forceinline__ double at(const double2& a, int v) { return v == 0 ? a.x : a.y; }
+    static __device__ __forceinline__ double2 keep(bool ok, const double2& a) {
+        return double2{ok ? a.x : 0.0, ok ? a.y : 0.0};
+    }
+};
+
+template <typename TC, int SD, int NT>
+__global__ __launch_bounds__(GW * 64) void k_rom_gemm(const TC* __restrict__ Pt, const TC* __restrict__ Wt,
+                                                     long long ld, long long nu, int k, int KP, int npairs,
+                                                     int kt, int ch, TC* __restrict__ partials) {
+    constexpr int LSD = SD + 2;
+    constexpr int NTH = GW * 64;
+    constexpr int V = 16 / sizeof(TC);       // entries per 16-byte load
+    constexpr int SV = SD / V;               // loads per row and slab
+    constexpr int MAXQ = 4;                  // loads per thread and operand (KP * SV <= 4 NTH)
+    static_assert(SD % V == 0 && SD % 4 == 0, "slab of whole loads and steps");
+    typedef typename Vec16<TC>::type vec_t;
     extern __shared__ __align__(16) unsigned char smem[];
-    TC* sD = (TC*)smem;  // [round_up(ec * NR, 4)][LS]
-    __shared__ TC sF[kFacSize];
-    __shared__ int sNode0[64];           // node of local node 0 of the sub-chunk's elements
-    __shared__ uint32_t sFree[64];       // bit DIM*a+c set: DOF (a, c) is free
-    __shared__ TC sSa[64];               // sqrt(alpha_e)
-
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wave = tid >> 6;
-    const int b = blockIdx.y;
-    const int kt = KP / 16;
-    const int npairs = kt * (kt + 1) / 2;
-    const int e_begin = xcd_block(blockIdx.x, gridDim.x) * epw;
-    const int e_end = min(e_begin + epw, g.n_elems);
-    const TC* alpha_b = alpha + (size_t)b * g.n_elems;
-    const int rows_full = ec * NR;
-    const int rows_alloc = (rows_full + 3) & ~3;
-
-    for (int i = tid; i < kFacSize; i += blockDim.x) sF[i] = F[i];
-    for (int i = rows_full * LS + tid; i < rows_alloc * LS; i += blockDim.x) sD[i] = TC(0);
-
-    // this wave's NT tile pairs (p = group * NT * WAVES + wave + WAVES t); past the last
-    // pair a wave repeats tile (0, 0) and drops the result
+    TC* sA = (TC*)smem;              // [KP][LSD] slab of Pt
+    TC* sB = sA + (size_t)KP * LSD;  // [KP][LSD] slab of Wt
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const long long d0 = (long long)blockIdx.x * ch;
+    const long long d1 = min(d0 + (long long)ch, nu);
+    // this wave's tile pairs; past the last pair a wave repeats tile (0, 0) and drops it
     int myI[NT], myJ[NT];
-    const int pbase = blockIdx.z * NT * WAVES + wave;
-    const bool any = pbase < npairs;  // wave-uniform
+    const int pbase = blockIdx.y * NT * GW + wave;
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
-        const int p = pbase + WAVES * t;
+        const int p = pbase + GW * t;
         if (p < npairs) pair_of(p, kt, myI[t], myJ[t]);
         else myI[t] = myJ[t] = 0;
     }
-    // float64 sums of the tiles: float32 matrix-core sums are flushed into acc64 after
-    // every sub-chunk; float64 ones accumulate in acc over the whole chunk
     typedef typename Mfma<TC>::acc_t acc_t;
-    constexpr bool F32 = sizeof(TC) == 4;
-    double acc64[NT][4];
     acc_t acc[NT];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-        acc[t] = acc_t{0, 0, 0, 0};
+    for (int t = 0; t < NT; ++t) acc[t] = acc_t{0, 0, 0, 0};
+    // staging: load q = tid + NTH u is row q / SV, entries V (q % SV) .. + V - 1 of the
+    // slab; rows >= k read as zeros, and entries past N_u are zeros of the operands (a
+    // slab never passes ld, which is a multiple of SD)
+    vec_t ra[MAXQ], rb[MAXQ];
+    const int nq = KP * SV;
+    auto fetch = [&](long long ds) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) acc64[t][v] = 0.0;
-    }
-
-    // basis offsets (in elements) of local node a and component c from local node 0
-    size_t aoff[NEN];
-#pragma unroll
-    for (int a = 0; a < NEN; ++a)
-        aoff[a] = ((size_t)(a & 1) + (size_t)((a >> 1) & 1) * g.nx1 +
-                   (size_t)(a >> 2) * g.nx1 * g.ny1) * (size_t)ldphi;
-    const size_t coff = (size_t)g.n_nodes * ldphi;
-    constexpr uint32_t kAllFree = (1u << (DIM * NEN)) - 1u;
-    const int q_el = blockDim.x / KP, q_col = blockDim.x % KP;
-    const int el_t0 = tid / KP, col_t0 = tid % KP;
-
-    for (int e0 = e_begin; e0 < e_end; e0 += ec) {
-        const int ne_here = min(ec, e_end - e0);
-        __syncthreads();  // previous sub-chunk fully consumed (and sF staged)
-        // element geometry of the sub-chunk: node indices, free-DOF bits, sqrt(alpha)
-        for (int idx = tid; idx < ec * NEN; idx += blockDim.x) {
-            const int el = idx / NEN, a = idx - el * NEN;
-            int n = 0;
-            uint32_t bits = 0;
-            if (el < ne_here) {
-                const int e = e0 + el;
-                const int ex = e % g.nx;
-                const int t2 = e / g.nx;
-                const int ey = t2 % g.ny;
-                const int ez = t2 / g.ny;
-                n = ((ez + (a >> 2)) * g.ny1 + (ey + ((a >> 1) & 1))) * g.nx1 + ex + (a & 1);
-#pragma unroll
-                for (int c = 0; c < DIM; ++c)
-                    if (!mask[(size_t)c * g.n_nodes + n]) bits |= 1u << (DIM * a + c);
-            }
-            if (a == 0) sNode0[el] = n;
-            // combine the bits of the element's nodes (NEN consecutive lanes)
-#pragma unroll
-            for (int off = 1; off < NEN; off <<= 1) bits |= __shfl_xor(bits, off, 64);
-            if (a == 0) {
-                sFree[el] = bits;
-                sSa[el] = el < ne_here ? (TC)sqrt(alpha_b[e0 + el]) : TC(0);
-            }
+        for (int u = 0; u < MAXQ; ++u) {
+            const int q = tid + NTH * u;
+            const int r = q / SV, c = (q % SV) * V;
+            const bool ok = q < nq && r < k;
+            const size_t off = ok ? (size_t)r * (size_t)ld + (size_t)(ds + c) : 0;
+            ra[u] = Vec16<TC>::keep(ok, *(const vec_t*)(Pt + off));
+            rb[u] = Vec16<TC>::keep(ok, *(const vec_t*)(Wt + off));
         }
-        __syncthreads();
-        // U items (element, column) per thread per batch: all their basis loads are in
-        // flight before the first is used.  Indices past the sub-chunk or past k are
-        // clamped to a valid row / column and their D rows are zero.  The item cursor
-        // (el, col) advances by blockDim.x = q_el * KP + q_col items per step.
-        constexpr int U = DIM == 2 ? 4 : 1;
-        const int nitems = ec * KP;
-        int el_c = el_t0, col_c = col_t0;
-        for (int idx0 = tid; idx0 < nitems; idx0 += U * blockDim.x) {
-            TP v[U][NEN][DIM];
-            int elu[U], colu[U];
+    };
+    fetch(d0);
+    const int rl = lane & 15, cl = lane >> 4;  // operand row in the tile, DOF in the step
+    for (long long ds = d0; ds < d1; ds += SD) {
+        __syncthreads();  // the previous slab is consumed
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                elu[u] = el_c;
-                colu[u] = col_c;
-                el_c += q_el;
-                col_c += q_col;
-                if (col_c >= KP) {
-                    col_c -= KP;
-                    ++el_c;
-                }
-                const TP* pe = phi + (size_t)sNode0[min(elu[u], ec - 1)] * ldphi + min(colu[u], k - 1);
+        for (int u = 0; u < MAXQ; ++u) {
+            const int q = tid + NTH * u;
+            if (q < nq) {
+                const int r = q / SV, c = (q % SV) * V;
 #pragma unroll
-                for (int a = 0; a < NEN; ++a)
-#pragma unroll
-                    for (int c = 0; c < DIM; ++c) v[u][a][c] = pe[aoff[a] + c * coff];
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int el = elu[u], col = colu[u];
-                if (idx0 + u * blockDim.x < nitems) {
-                    TC D[NR];
-                    if (el < ne_here && col < k) {
-                        const uint32_t fr = sFree[el];
-                        TC A[NEN][DIM];
-#pragma unroll
-                        for (int a = 0; a < NEN; ++a)
-#pragma unroll
-                            for (int c = 0; c < DIM; ++c) A[a][c] = (TC)v[u][a][c];
-                        if (fr != kAllFree) {  // element touching the Dirichlet boundary
-#pragma unroll
-                            for (int a = 0; a < NEN; ++a)
-#pragma unroll
-                                for (int c = 0; c < DIM; ++c)
-                                    if (!((fr >> (DIM * a + c)) & 1u)) A[a][c] = TC(0);
-                        }
-                        if constexpr (DIM == 2) elem_rows2(A, sF, sSa[el], D);
-                        else elem_rows3(A, sF, sSa[el], D);
-                    } else {
-#pragma unroll
-                        for (int r = 0; r < NR; ++r) D[r] = TC(0);
-                    }
-#pragma unroll
-                    for (int r = 0; r < NR; ++r) sD[(size_t)(el * NR + r) * LS + col] = D[r];
+                for (int v = 0; v < V; ++v) {
+                    sA[r * LSD + c + v] = Vec16<TC>::at(ra[u], v);
+                    sB[r * LSD + c + v] = Vec16<TC>::at(rb[u], v);
                 }
             }
         }
         __syncthreads();
-        // matrix-core accumulation over the rows of this sub-chunk: every operand of a
-        // 4-row step is loaded before its NT instructions
-        if (any) {
-            const int rsub = lane >> 4;   // row inside the 4-row step
-            const int csub = lane & 15;   // column inside the tile
-            const int rows = ne_here * NR;
-            const TC* drow = sD + (size_t)rsub * LS + csub;
-            for (int r0 = 0; r0 < rows; r0 += 4) {
-                TC av[NT], bv[NT];
+        if (ds + SD < d1) fetch(ds + SD);  // in flight during the products
 #pragma unroll
-                for (int t = 0; t < NT; ++t) {
-                    av[t] = drow[(size_t)r0 * LS + myI[t] * 16];
-                    bv[t] = drow[(size_t)r0 * LS + myJ[t] * 16];
-                }
+        for (int s4 = 0; s4 < SD / 4; ++s4) {
+            const int c = s4 * 4 + cl;
+            TC av[NT], bv[NT];
 #pragma unroll
-                for (int t = 0; t < NT; ++t) acc[t] = Mfma<TC>::run(av[t], bv[t], acc[t]);
+            for (int t = 0; t < NT; ++t) {
+                av[t] = sA[(myI[t] * 16 + rl) * LSD + c];
+                bv[t] = sB[(myJ[t] * 16 + rl) * LSD + c];
             }
-            if constexpr (F32) {
 #pragma unroll
-                for (int t = 0; t < NT; ++t) {
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) acc64[t][v] += (double)acc[t][v];
-                    acc[t] = acc_t{0, 0, 0, 0};
-                }
-            }
+            for (int t = 0; t < NT; ++t) acc[t] = Mfma<TC>::run(av[t], bv[t], acc[t]);
         }
     }
-    // write this block's partial tiles: partial[(b, chunk, pair)][16*16]
-    const size_t nchunks = gridDim.x;
+    // the chunk's tiles: partials[chunk][pair][16 * 16]
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
-        const int p = pbase + WAVES * t;
+        const int p = pbase + GW * t;
         if (p < npairs) {
-            double* dst = partials + (((size_t)b * nchunks + blockIdx.x) * npairs + p) * 256;
+            TC* dst = partials + ((size_t)blockIdx.x * npairs + p) * 256;
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int i = Mfma<TC>::row(lane, v);  // row of the 16x16 output tile
-                const int j = lane & 15;            // column
-                dst[i * 16 + j] = F32 ? acc64[t][v] : (double)acc[t][v];
-            }
+            for (int v = 0; v < 4; ++v) dst[Mfma<TC>::row(lane, v) * 16 + (lane & 15)] = acc[t][v];
+        }
+    }
+}
+
+// Pt[j][d] = Phi[d][j] (j < k, d < N_u), converted to the compute type, and zeros at
+// N_u <= d < ld: 64 x 64 tiles through LDS (reads along the basis rows, writes along
+// the transposed ones).  Also zeroes the same tail of Wt's rows (the apply writes only
+// the first N_u entries of each).
+template <typename TP, typename TC>
+__global__ __launch_bounds__(256) void k_basis_rows(const TP* __restrict__ phi, int ldphi, long long nu, int k,
+                                                    long long ld, TC* __restrict__ Pt, TC* __restrict__ Wt) {
+    __shared__ TC tile[64][65];
+    const long long d0 = (long long)blockIdx.x * 64;
+    const int j0 = blockIdx.y * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int r = ty; r < 64; r += 4) {
+        const long long d = d0 + r;
+        const int j = j0 + tx;
+        tile[r][tx] = (d < nu && j < k) ? (TC)phi[(size_t)d * ldphi + j] : TC(0);
+    }
+    __syncthreads();
+    for (int r = ty; r < 64; r += 4) {
+        const int j = j0 + r;
+        const long long d = d0 + tx;
+        if (j < k && d < ld) {
+            Pt[(size_t)j * ld + d] = tile[tx][r];  // zero past N_u
+            if (d >= nu) Wt[(size_t)j * ld + d] = TC(0);
         }
     }
 }
@@ -914,70 +864,96 @@ static int phit_chunks(const Grid& g) {
 }
 
 struct ContractPlan {
-    int KP, LS, kt, npairs, nt, groups, ec, epw, nchunks;
+    int KP, kt, npairs, groups, nt, sd, ch, nchunks;
+    long long ld;  // row pitch of the operands
     size_t lds_bytes;
 };
 
-static ContractPlan plan_contract(const Grid& g, int k, int B, bool f64, int cu) {
+// The plan depends on the mesh, k and precision only -- never on B -- so a field's
+// K_hat is bitwise the same alone and inside a batch.
+static ContractPlan plan_contract(const Grid& g, int k, bool f64) {
     ContractPlan p;
     p.KP = (k + 15) / 16 * 16;
-    // an odd number of 16-column groups per row: the 4 rows of one matrix-core step fall
-    // on different LDS banks
-    p.LS = p.KP + ((p.KP / 16) % 2 == 0 ? 16 : 0);
     p.kt = p.KP / 16;
     p.npairs = p.kt * (p.kt + 1) / 2;
-    // tile pairs per wave: as few groups as possible (the basis rows are staged once per
-    // group), then the pairs spread evenly over the group's waves
-    p.groups = (p.npairs + MAX_NT * WAVES - 1) / (MAX_NT * WAVES);
-    p.nt = (p.npairs + p.groups * WAVES - 1) / (p.groups * WAVES);
-    const int nr = g.dim == 2 ? kRows2 : kRows3;
-    const size_t esz = f64 ? 8 : 4;
-    const size_t budget = 64 * 1024;
-    auto bytes = [&](int e) { return (size_t)((e * nr + 3) & ~3) * p.LS * esz; };
-    int ec = 64;
-    while (ec > 1 && bytes(ec) > budget) --ec;
-    p.ec = ec;
-    // aim at ~4 blocks per CU overall (each block writes npairs partial tiles, so more
-    // chunks only add reduction traffic)
-    // The chunking depends on the mesh, k and precision only -- never on B -- so a
-    // field's K_hat is bitwise the same alone and inside a batch.
-    (void)B;
-    const long long want_blocks = 4LL * cu;
-    long long per_field = std::max(1LL, want_blocks / (long long)p.groups);
-    long long epw = (g.n_elems + per_field - 1) / per_field;
-    epw = std::max<long long>(epw, ec);
-    epw = (epw + ec - 1) / ec * ec;
-    p.epw = (int)epw;
-    p.nchunks = (int)((g.n_elems + epw - 1) / epw);
-    p.lds_bytes = bytes(ec);
+    p.groups = (p.npairs + max_nt(f64) * GW - 1) / (max_nt(f64) * GW);
+    p.nt = (p.npairs + p.groups * GW - 1) / (p.groups * GW);
+    p.sd = f64 ? gemm_sd<double>(p.KP) : gemm_sd<float>(p.KP);
+    // DOFs per chunk: float32 sums over at most 2048 products before they are added in
+    // float64 (as the matrix cores accumulate them), float64 ones over 8192
+    p.ch = f64 ? 8192 : 2048;
+    p.nchunks = (int)((g.n_dofs + p.ch - 1) / p.ch);
+    p.ld = (g.n_dofs + GEMM_LD - 1) / GEMM_LD * GEMM_LD;
+    p.lds_bytes = (size_t)2 * p.KP * (p.sd + 2) * (f64 ? 8 : 4);
     return p;
 }
 
-template <int DIM, typename TP, typename TC, int NT>
-static int launch_contract_nt(Ctx* ctx, const Grid& g, const ContractPlan& p, const TP* phi, int k,
-                              int ldphi, const uint8_t* mask, const TC* alpha, const TC* F, int B,
-                              double* partials, hipStream_t s) {
-    auto kern = k_rom_contract<DIM, TP, TC, NT>;
+template <typename TC, int SD, int NT>
+static int launch_gemm_nt(Ctx* ctx, const ContractPlan& p, const TC* Pt, const TC* Wt, long long nu, int k,
+                          TC* parts, hipStream_t s) {
+    auto kern = k_rom_gemm<TC, SD, NT>;
     TOPO_HIP(ensure_dynamic_lds((const void*)kern, p.lds_bytes));
-    TimedLaunch tl(ctx, KID_ROM_CONTRACT, s);
-    hipLaunchKernelGGL(kern, dim3(p.nchunks, B, p.groups), dim3(WAVES * 64), p.lds_bytes, s, g, phi,
-                       k, ldphi, p.KP, p.LS, mask, alpha, F, p.epw, p.ec, partials);
+    hipLaunchKernelGGL(kern, dim3(p.nchunks, p.groups), dim3(GW * 64), p.lds_bytes, s, Pt, Wt, p.ld, nu, k, p.KP,
+                       p.npairs, p.kt, p.ch, parts);
     TOPO_CHECK_LAUNCH();
     return TOPO_OK;
 }
 
-template <int DIM, typename TP, typename TC>
-static int launch_contract(Ctx* ctx, const Grid& g, const ContractPlan& p, const TP* phi, int k,
-                           int ldphi, const uint8_t* mask, const TC* alpha, const TC* F, int B,
-                           double* partials, hipStream_t s) {
-    switch (p.nt) {
-#define TOPO_NT_CASE(n) \
-    case n: return launch_contract_nt<DIM, TP, TC, n>(ctx, g, p, phi, k, ldphi, mask, alpha, F, B, partials, s);
-    TOPO_NT_CASE(1) TOPO_NT_CASE(2) TOPO_NT_CASE(3) TOPO_NT_CASE(4)
-    TOPO_NT_CASE(5) TOPO_NT_CASE(6) TOPO_NT_CASE(7)
-#undef TOPO_NT_CASE
-    default: return launch_contract_nt<DIM, TP, TC, 8>(ctx, g, p, phi, k, ldphi, mask, alpha, F, B, partials, s);
+template <typename TC, int SD>
+static int launch_gemm_sd(Ctx* ctx, const ContractPlan& p, const TC* Pt, const TC* Wt, long long nu, int k,
+                          TC* parts, hipStream_t s) {
+    // the smallest instantiated pair count per wave that covers the plan's
+    if (p.nt <= 1) return launch_gemm_nt<TC, SD, 1>(ctx, p, Pt, Wt, nu, k, parts, s);
+    if (p.nt <= 2) return launch_gemm_nt<TC, SD, 2>(ctx, p, Pt, Wt, nu, k, parts, s);
+    if (p.nt <= 3) return launch_gemm_nt<TC, SD, 3>(ctx, p, Pt, Wt, nu, k, parts, s);
+    if (p.nt <= 4) return launch_gemm_nt<TC, SD, 4>(ctx, p, Pt, Wt, nu, k, parts, s);
+    if (p.nt <= 6) return launch_gemm_nt<TC, SD, 6>(ctx, p, Pt, Wt, nu, k, parts, s);
+    if (sizeof(TC) == 8 || p.nt <= 8) return launch_gemm_nt<TC, SD, 8>(ctx, p, Pt, Wt, nu, k, parts, s);
+    if constexpr (sizeof(TC) == 4) return launch_gemm_nt<TC, SD, 12>(ctx, p, Pt, Wt, nu, k, parts, s);
+    return TOPO_EINVAL;
+}
+
+template <typename TC>
+static int launch_gemm(Ctx* ctx, const ContractPlan& p, const TC* Pt, const TC* Wt, long long nu, int k,
+                       TC* parts, hipStream_t s) {
+    constexpr int SD0 = gemm_sd<TC>(256), SD1 = gemm_sd<TC>(KP_MAX);
+    if (p.sd == SD0) return launch_gemm_sd<TC, SD0>(ctx, p, Pt, Wt, nu, k, parts, s);
+    return launch_gemm_sd<TC, SD1>(ctx, p, Pt, Wt, nu, k, parts, s);
+}
+
+// K_hat of every field (the contraction and its chunk sums), from the basis Phi (TP)
+// in the compute type TC: Pt, Wt [k][ld] and parts [nchunks][npairs][256] are workspace.
+template <typename TP, typename TC>
+static int contract_fields(Ctx* ctx, const Grid& g, const ElemTables* tb, const ContractPlan& p, const TP* phi,
+                           int k, int ldphi, const uint8_t* mask, const TC* alpha, int B, TC* Pt, TC* Wt, TC* parts,
+                           double* Khat, hipStream_t s) {
+    const long long nu = g.n_dofs;
+    {
+        TimedLaunch tl(ctx, KID_ROM_APPLY, s);
+        hipLaunchKernelGGL((k_basis_rows<TP, TC>), dim3((unsigned)(p.ld / 64), (k + 63) / 64), dim3(256), 0, s,
+                           phi, ldphi, nu, k, p.ld, Pt, Wt);
     }
+    TOPO_CHECK_LAUNCH();
+    for (int b = 0; b < B; ++b) {
+        int rc;
+        {
+            TimedLaunch tl(ctx, KID_ROM_APPLY, s);
+            rc = apply_columns<TC>(ctx, g, tb, alpha + (size_t)b * g.n_elems, mask, Pt, Wt, k, p.ld, s);
+        }
+        if (rc) return rc;
+        {
+            TimedLaunch tl(ctx, KID_ROM_CONTRACT, s);
+            rc = launch_gemm<TC>(ctx, p, Pt, Wt, nu, k, parts, s);
+        }
+        if (rc) return rc;
+        {
+            TimedLaunch tl(ctx, KID_ROM_REDUCE, s);
+            launch_chunk_sum(p.npairs * 256, p.nchunks, 1, (const TC*)parts,
+                             KhatOut{k, p.kt, Khat + (size_t)b * k * k}, s);
+        }
+        TOPO_CHECK_LAUNCH();
+    }
+    return TOPO_OK;
 }
 
 }  // namespace topo
@@ -1004,45 +980,41 @@ int topo_rom_build(topo_ctx* ctx, const topo_mesh* mesh, const void* phi, int32_
     if (!tb) return set_error(ctx, TOPO_EDEVICE, "element table upload failed");
     hipStream_t s = (hipStream_t)stream;
     const bool f64 = prec == TOPO_FP64;
-    const ContractPlan p = plan_contract(g, k, B, f64, ctx->cu_count);
-    if (p.lds_bytes > 64 * 1024)
-        return set_error(ctx, TOPO_EINVAL, "k = %d too large for the contraction tile (LDS)", k);
+    const ContractPlan p = plan_contract(g, k, f64);
+    if (p.KP > KP_MAX) return set_error(ctx, TOPO_EINVAL, "k = %d too large for the contraction (at most %d)", k, KP_MAX);
     const int nc = phit_chunks(g);
+    const size_t nk = (size_t)k * p.ld, np = (size_t)p.nchunks * p.npairs * 256;
     Arena ar;
-    double* a64 = nullptr;
-    float* a32 = nullptr;
-    double *parts, *pf;
-    if (f64) ar.take(&a64, (size_t)B * g.n_elems);
-    else ar.take(&a32, (size_t)B * g.n_elems);
-    ar.take(&parts, (size_t)B * p.nchunks * p.npairs * 256);
+    double *a64 = nullptr, *P64 = nullptr, *W64 = nullptr, *parts64 = nullptr;
+    float *a32 = nullptr, *P32 = nullptr, *W32 = nullptr, *parts32 = nullptr;
+    double* pf;
+    if (f64) {
+        ar.take(&a64, (size_t)B * g.n_elems);
+        ar.take(&P64, nk);
+        ar.take(&W64, nk);
+        ar.take(&parts64, np);
+    } else {
+        ar.take(&a32, (size_t)B * g.n_elems);
+        ar.take(&P32, nk);
+        ar.take(&W32, nk);
+        ar.take(&parts32, np);
+    }
     ar.take(&pf, (size_t)nc * k);
     rc = ar.commit(ctx, s);
     if (rc) return rc;
     rc = alpha_tables(ctx, g, *mesh, rho, B, a64, a32, s);
     if (rc) return rc;
-    if (g.dim == 2) {
-        if (f64) {
-            rc = phi_fp32 ? launch_contract<2, float, double>(ctx, g, p, (const float*)phi, k, ldphi, mask, a64, tb->F64, B, parts, s)
-                          : launch_contract<2, double, double>(ctx, g, p, (const double*)phi, k, ldphi, mask, a64, tb->F64, B, parts, s);
-        } else {
-            rc = phi_fp32 ? launch_contract<2, float, float>(ctx, g, p, (const float*)phi, k, ldphi, mask, a32, tb->F32, B, parts, s)
-                          : launch_contract<2, double, float>(ctx, g, p, (const double*)phi, k, ldphi, mask, a32, tb->F32, B, parts, s);
-        }
-    } else {
-        if (f64) {
-            rc = phi_fp32 ? launch_contract<3, float, double>(ctx, g, p, (const float*)phi, k, ldphi, mask, a64, tb->F64, B, parts, s)
-                          : launch_contract<3, double, double>(ctx, g, p, (const double*)phi, k, ldphi, mask, a64, tb->F64, B, parts, s);
-        } else {
-            rc = phi_fp32 ? launch_contract<3, float, float>(ctx, g, p, (const float*)phi, k, ldphi, mask, a32, tb->F32, B, parts, s)
-                          : launch_contract<3, double, float>(ctx, g, p, (const double*)phi, k, ldphi, mask, a32, tb->F32, B, parts, s);
-        }
-    }
+    if (f64)
+        rc = phi_fp32 ? contract_fields(ctx, g, tb, p, (const float*)phi, k, ldphi, mask, (const double*)a64, B, P64,
+                                        W64, parts64, Khat, s)
+                      : contract_fields(ctx, g, tb, p, (const double*)phi, k, ldphi, mask, (const double*)a64, B,
+                                        P64, W64, parts64, Khat, s);
+    else
+        rc = phi_fp32 ? contract_fields(ctx, g, tb, p, (const float*)phi, k, ldphi, mask, (const float*)a32, B, P32,
+                                        W32, parts32, Khat, s)
+                      : contract_fields(ctx, g, tb, p, (const double*)phi, k, ldphi, mask, (const float*)a32, B, P32,
+                                        W32, parts32, Khat, s);
     if (rc) return rc;
-    {
-        TimedLaunch tl(ctx, KID_ROM_REDUCE, s);
-        launch_chunk_sum(p.npairs * 256, p.nchunks, B, parts, KhatOut{k, p.kt, Khat}, s);
-    }
-    TOPO_CHECK_LAUNCH();
     if (fhat) {
         rc = phit_v(ctx, g, phi, phi_fp32, k, ldphi, mask, f, 0, 1, fhat, pf, nc, s);
         if (rc) return rc;
@@ -1290,14 +1262,24 @@ int topo_rom_gradient(topo_ctx* ctx, const topo_mesh* mesh, const void* phi, int
 namespace topo {
 
 size_t ws_rom_build(const Grid& g, int k, int B, bool f64, int cu) {
-    const ContractPlan p = plan_contract(g, k, B, f64, cu);
+    (void)cu;
+    const ContractPlan p = plan_contract(g, k, f64);
     const int nc = phit_chunks(g);
+    const size_t nk = (size_t)k * p.ld, np = (size_t)p.nchunks * p.npairs * 256;
     Arena ar;
-    double *a64, *parts, *pf;
-    float* a32;
-    if (f64) ar.take(&a64, (size_t)B * g.n_elems);
-    else ar.take(&a32, (size_t)B * g.n_elems);
-    ar.take(&parts, (size_t)B * p.nchunks * p.npairs * 256);
+    double *a64, *P64, *W64, *parts64, *pf;
+    float *a32, *P32, *W32, *parts32;
+    if (f64) {
+        ar.take(&a64, (size_t)B * g.n_elems);
+        ar.take(&P64, nk);
+        ar.take(&W64, nk);
+        ar.take(&parts64, np);
+    } else {
+        ar.take(&a32, (size_t)B * g.n_elems);
+        ar.take(&P32, nk);
+        ar.take(&W32, nk);
+        ar.take(&parts32, np);
+    }
     ar.take(&pf, (size_t)nc * k);
     return ar.total();
 }
