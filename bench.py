@@ -75,21 +75,21 @@ def pcg_bytes(n_dofs, n_nodes, n_elems, word, dim=2):
     step  (2D float64, one kernel per iteration): read r, w, s (stencil), p, mask,
           alpha, 1/sum(alpha) per node; read/write x (float64); write r, w, s, p
     apply (two-kernel form): read z, p_old (stencil), alpha, mask; write p_new, q
-    update (two-kernel form): read r; write r, z; read p, q, 1/sum(alpha) per node; and
-          at the last update of each group of G (x takes G steps at a time: G = 2 in 2D,
-          8 in 3D) read and write x (float64) and read the group's G - 1 earlier
-          directions: on average (16 + (G - 1) w) / G bytes per DOF
-    In 3D the update applies the mask (one byte per DOF moves from the apply to the
-    update), and the float32 apply reads r and 1/sum(alpha) per node and forms z itself,
+    update (two-kernel form): read r; write r, z; read q, 1/sum(alpha) per node; and at
+          the last update of each group of G (x takes G steps at a time: G = 2 in 2D,
+          8 in 3D) read and write x (float64) and read the group's G directions: on
+          average (16 + G w) / G bytes per DOF
+    In 3D the update applies the mask, as one byte of mask bits per node (the apply reads
+    none), and the float32 apply reads r and 1/sum(alpha) per node and forms z itself,
     so its update writes no z."""
     forms_z = dim == 3 and word == 4
     mask_apply = 1 if dim == 2 else 0
     group = 8 if dim == 3 else 2
-    x_bytes = (16 + (group - 1) * word) / group
+    x_bytes = (16 + group * word) / group
     return {
         "pcg_step": n_dofs * (8 * word + 17) + n_nodes * word + n_elems * word,
         "pcg_apply": n_dofs * (4 * word + mask_apply) + n_elems * word + (n_nodes * word if forms_z else 0),
-        "pcg_update": n_dofs * ((4 if forms_z else 5) * word + x_bytes + 1 - mask_apply) + n_nodes * word,
+        "pcg_update": n_dofs * ((3 if forms_z else 4) * word + x_bytes) + n_nodes * (word + 1 - mask_apply),
     }
 
 
@@ -110,7 +110,7 @@ def rom_contract_flops(n_elems, k, ne):
 
 
 def rom_gemm_flops(n_dofs, k):
-    """Algorithmic flops of K_hat = Phi^T W for one field on the matrix cores: the
+    """Algorithmic flops of K_hat = Phi^T W for one field on the float64 matrix cores: the
     k (k + 1) / 2 distinct entries of the symmetric product, a multiply-add per DOF each
     (W = K Phi is formed by the apply beforehand, on the vector units)."""
     return n_dofs * k * (k + 1)
@@ -836,7 +836,7 @@ def main():
         ne = m.dim * 2 ** m.dim
         fl = rom_gemm_flops(m.n_dofs, k)
         avg_s = kt["avg_us"] * 1e-6
-        peak = FP32_MFMA_PEAK_TFS if word == 4 else FP64_MFMA_PEAK_TFS
+        peak = FP64_MFMA_PEAK_TFS  # the product accumulates in float64 in both precisions
         tfs = fl / avg_s / 1e12
         out = {"bound": "mfma", "achieved": tfs, "peak": peak, "unit": "TFLOP/s", "frac": tfs / peak,
                "traffic": None, "kernel": "k_rom_gemm", "flops_per_launch": fl, "fields_per_launch": 1,

@@ -59,38 +59,39 @@ __global__ void k_winv(Grid g, const double* __restrict__ a64, double* __restric
 // Public apply: y_b = K(rho_b) x_b, Dirichlet rows and columns eliminated.  astride:
 // elements between the alpha tables of consecutive vectors (N_e; 0 when every vector
 // shares one density field, as the columns of the ROM contraction do); vstride: entries
-// between consecutive vectors of x and y (N_u, or a padded pitch).
+// between consecutive vectors of x and y (N_u, or a padded pitch).  T: arithmetic type;
+// TX, TY: the types x and y are stored in (T, or float32 x for float64 arithmetic).
 // ----------------------------------------------------------------------------------
-template <typename T>
+template <typename T, typename TX = T, typename TY = T>
 __global__ __launch_bounds__(kBlock) void k_apply2(Grid g, const T* __restrict__ alpha, long long astride,
                                                    long long vstride, const T* __restrict__ K,
                                                    const uint8_t* __restrict__ mask,
-                                                   const T* __restrict__ x, T* __restrict__ y) {
+                                                   const TX* __restrict__ x, TY* __restrict__ y) {
     const FieldBlock fb = field_block();
     const int n = fb.blk * blockDim.x + threadIdx.x;
     if (n >= g.n_nodes) return;
     const size_t b = fb.field;
-    const T* xb = x + b * vstride;
-    T* yb = y + b * vstride;
+    const TX* xb = x + b * vstride;
+    TY* yb = y + b * vstride;
     const T* ab = alpha + b * astride;
     int i, j, k;
     node_ijk(g, n, i, j, k);
-    FetchMasked<T> f{xb, mask, g.n_nodes};
+    FetchMasked<T, TX> f{xb, mask, g.n_nodes};
     T out[2];
     node_apply2<T>(g, i, j, ab, K, f, out);
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
         const size_t idx = (size_t)c * g.n_nodes + n;
-        yb[idx] = mask[idx] ? T(0) : out[c];
+        yb[idx] = mask[idx] ? TY(0) : (TY)out[c];
     }
 }
 
 // Sources of the 3D march (march3.hpp): the values of node planes, fetched two slots
 // per thread with every load issued unconditionally (an invalid node reads node 0 and
 // is zeroed afterwards).
-template <typename T>
-struct SrcMasked {  // x with Dirichlet DOFs zeroed
-    const T* __restrict__ x;
+template <typename T, typename TX = T>
+struct SrcMasked {  // x (stored as TX) with Dirichlet DOFs zeroed
+    const TX* __restrict__ x;
     const uint8_t* __restrict__ mask;
     int nn;
     T v[4][3];
@@ -98,7 +99,7 @@ struct SrcMasked {  // x with Dirichlet DOFs zeroed
         const int n = node >= 0 ? node : 0;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            const T xv = x[c * nn + n];
+            const T xv = (T)x[c * nn + n];
             const uint8_t mk = mask[c * nn + n];
             v[slot][c] = (node < 0 || mk) ? T(0) : xv;
         }
@@ -197,25 +198,25 @@ __device__ __forceinline__ void march3_prologue(const Grid& g, const MarchBlock&
 
 // 3D: one block per march column and field.  M is the table of reduced element blocks
 // (apply3_from_n).
-template <typename T>
+template <typename T, typename TX = T, typename TY = T>
 __global__ __launch_bounds__(kBlock) void k_apply3(Grid g, const T* __restrict__ alpha, long long astride,
                                                    long long vstride, const T* __restrict__ M,
                                                    const uint8_t* __restrict__ mask,
-                                                   const T* __restrict__ x, T* __restrict__ y) {
+                                                   const TX* __restrict__ x, TY* __restrict__ y) {
     __shared__ MarchLds<T> L;
     const FieldBlock fb = field_block();
     const size_t b = fb.field;
     const MarchBlock m = march3_block(g, fb.blk);
     for (int i = threadIdx.x; i < kFacSize; i += blockDim.x) L.M[i] = M[i];
     const MarchSlots sl = march3_slots(g, m);
-    SrcMasked<T> src{x + b * vstride, mask, g.n_nodes};
+    SrcMasked<T, TX> src{x + b * vstride, mask, g.n_nodes};
     march3_prologue(g, m, sl, src);
-    T* yb = y + b * vstride;
+    TY* yb = y + b * vstride;
     auto emit = [&](int n, const T (&out)[3], const T (&)[3]) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const size_t idx = (size_t)c * g.n_nodes + n;
-            yb[idx] = mask[idx] ? T(0) : out[c];
+            yb[idx] = mask[idx] ? TY(0) : (TY)out[c];
         }
     };
     march3_run(g, m, sl, alpha + b * astride, L, src, emit);
@@ -543,7 +544,8 @@ __global__ __launch_bounds__(kBlock, sizeof(T) == 4 ? 4 : 2) void k_pcg_apply3(G
 
 // One node per thread (grid (nupd, B)); the node's loads are issued before the wait on
 // the scalar reduction.  3D: q is zeroed at masked DOFs here (the 3D apply writes
-// unmasked parts), so that r stays zero there; the 2D apply masks q itself.
+// unmasked parts), so that r stays zero there, from the node's mask bits (mask: [N_n],
+// bit c for component c, k_node_mask); the 2D apply masks q itself (mask unused).
 template <int DIM, typename T, bool FLUSH>
 __global__ __launch_bounds__(kPcgBlock) void k_pcg_update(Grid g, const T* __restrict__ winv,
                                                        const uint8_t* __restrict__ mask,
@@ -595,9 +597,7 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_update(Grid g, const T* __res
             qv[c] = q[i];
         }
         if constexpr (DIM == 3) {
-            uint8_t mk[3];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) mk[c] = mask[(size_t)c * g.n_nodes + n];
+            const unsigned mk = mask[n];
             // q = the primary block's part + the parts of the blocks below the node, in
             // the order of their side sections
             const int i = n % g.nx1, jk = n / g.nx1, j = jk % g.ny1, k = jk / g.ny1;
@@ -613,7 +613,7 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_update(Grid g, const T* __res
             }
 #pragma unroll
             for (int c = 0; c < 3; ++c)
-                if (mk[c]) qv[c] = T(0);
+                if ((mk >> c) & 1u) qv[c] = T(0);
         }
     }
     const double pq = block_sum_array(pb, npq, lds);
@@ -1268,6 +1268,7 @@ struct PcgBufs {
     const T* alpha;    // [B][N_e]
     const T* K;        // 2D: dense element matrix; 3D: reduced element blocks
     const uint8_t* mask;
+    const uint8_t* mnode;  // 3D: mask bits per node
     const T* winv;     // [B][N_n]
     T ik[3];           // 1 / K_e[c][c]
     T *r, *z, *p0, *p1, *q, *e0, *e1;  // [B][N_u]
@@ -1336,7 +1337,8 @@ static void pcg_iteration(Ctx* ctx, const Grid& g, const PcgBufs<T>& w, const Pc
         L.ev1 = tl.b;
         const bool flush = (lq & (XGroup<DIM>::value - 1)) == 0;  // a group's last update
         L(flush ? (const void*)k_pcg_update<DIM, T, true> : (const void*)k_pcg_update<DIM, T, false>,
-          dim3(pg.nupd, w.B), dim3(kPcgBlock), g, w.winv, w.mask, w.ik[0], w.ik[1], w.ik[2], w.x, w.r, w.z,
+          dim3(pg.nupd, w.B), dim3(kPcgBlock), g, w.winv, DIM == 3 ? w.mnode : w.mask, w.ik[0], w.ik[1], w.ik[2],
+          w.x, w.r, w.z,
           w.ring(), (const T*)w.q, (const T*)w.side, w.sg, w.part, w.st, pg.ps, pg.npq, lq);
     }
     if (pg.nrz == 1 && pg.nupd > 1)  // rz / rr of the update's own parity
@@ -1556,6 +1558,14 @@ __global__ void k_seg_control(int B, S* __restrict__ st, SegCtl* __restrict__ ct
     seg_next(c, st[b], fsc, live, b, rtol, seg_min);
 }
 
+// Mask bits per node: bit c set when DOF (node, c) is fixed (mask [3][N_n] -> [N_n]).
+__global__ void k_node_mask(int n_nodes, const uint8_t* __restrict__ mask, uint8_t* __restrict__ bits) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= n_nodes) return;
+    const size_t nn = (size_t)n_nodes;
+    bits[n] = (uint8_t)((mask[n] ? 1u : 0u) | (mask[nn + n] ? 2u : 0u) | (mask[2 * nn + n] ? 4u : 0u));
+}
+
 // skip[b] = !solve[b]
 __global__ void k_skip_from_solve(int B, const int* __restrict__ solve, int* __restrict__ skip) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1640,6 +1650,7 @@ struct HdmWs {
     T* pk[kRing3 - 2] = {};  // 3D: ring slots 2..7
     T *e0 = nullptr, *e1 = nullptr;  // 2D float64: the one-reduction recursion's two further vectors
     T* side = nullptr;               // 3D: the apply's parts of shared nodes
+    uint8_t* mnode = nullptr;        // 3D: mask bits per node (k_node_mask)
     float *a32 = nullptr, *w32 = nullptr;
     int *skip = nullptr, *live = nullptr, *solve = nullptr, *maxit = nullptr;
     SegCtl* ctl = nullptr;
@@ -1682,7 +1693,10 @@ static void hdm_takes(Arena& ar, const Grid& g, bool mixed, int B, HdmWs<T>& w) 
         ar.take(&w.e0, N);
         ar.take(&w.e1, N);
     }
-    if (g.dim == 3) ar.take(&w.side, (size_t)B * 3 * side_geom(g).total);
+    if (g.dim == 3) {
+        ar.take(&w.side, (size_t)B * 3 * side_geom(g).total);
+        ar.take(&w.mnode, (size_t)g.n_nodes);
+    }
 }
 
 size_t ws_hdm_solve(const Grid& g, bool mixed, int B) {
@@ -1794,6 +1808,7 @@ static int hdm_batch_impl(Ctx* ctx, const topo_mesh& m, const Grid& g0, const El
     if constexpr (DIM == 2) w.K = sizeof(T) == 4 ? (const T*)tb->K32 : (const T*)tb->K64;
     else w.K = sizeof(T) == 4 ? (const T*)tb->M32 : (const T*)tb->M64;
     w.mask = mask;
+    w.mnode = ws.mnode;
     for (int q = 0; q < 3; ++q) w.ik[q] = q < DIM ? (T)(1.0 / tb->diag[q]) : T(0);
     w.r = ws.r;
     w.z = ws.z;
@@ -1847,6 +1862,9 @@ static int hdm_batch_impl(Ctx* ctx, const topo_mesh& m, const Grid& g0, const El
         L.s = s;
         hipLaunchKernelGGL(k_skip_from_solve, dim3(grid_blocks(B, 64)), dim3(64), 0, s, B, (const int*)c.solve,
                            c.skip);
+        if (DIM == 3)
+            hipLaunchKernelGGL(k_node_mask, dim3(grid_blocks(g.n_nodes)), dim3(kBlock), 0, s, (int)g.n_nodes, mask,
+                               ws.mnode);
         residual_sink(L, gres, K64, ws.a64, mask, u, f, ws.r64, B, ws.rpart, ws.rout, (const int*)c.skip);
         if (one_red)
             L((const void*)k_seg_init<Cg1State>, dim3(grid_blocks(B, 64)), dim3(64), B, ws.st1, c.ctl,
@@ -1875,7 +1893,7 @@ static int hdm_batch_impl(Ctx* ctx, const topo_mesh& m, const Grid& g0, const El
                                       (uintptr_t)B, (uintptr_t)pg.napp, (uintptr_t)pg.nupd, (uintptr_t)chunk_len,
                                       (uintptr_t)g.nx, (uintptr_t)g.ny, (uintptr_t)g.nz, (uintptr_t)g.mtarget,
                                       (uintptr_t)gres.mtarget, (uintptr_t)w.alpha, (uintptr_t)w.K,
-                                      (uintptr_t)w.mask, (uintptr_t)w.winv, (uintptr_t)w.x, (uintptr_t)w.r,
+                                      (uintptr_t)w.mask, (uintptr_t)w.mnode, (uintptr_t)w.winv, (uintptr_t)w.x, (uintptr_t)w.r,
                                       (uintptr_t)w.z, (uintptr_t)w.p0, (uintptr_t)w.p1, (uintptr_t)w.q,
                                       (uintptr_t)w.e0, (uintptr_t)w.e1, (uintptr_t)w.side, (uintptr_t)w.part,
                                       (uintptr_t)w.st,
@@ -2021,25 +2039,25 @@ namespace topo {
 
 // W = K(rho) X for ncols vectors X = [ncols][ld] (ld >= N_u) sharing one density field
 // (alpha: its table, [N_e]), Dirichlet rows and columns eliminated: the columns of the
-// ROM contraction K_hat = X^T K X.  Entries ld - N_u past each vector are not written.
-template <typename T>
-int apply_columns(Ctx* ctx, const Grid& g0, const ElemTables* tb, const T* alpha, const uint8_t* mask,
-                  const T* x, T* y, int ncols, long long ld, hipStream_t s) {
+// ROM contraction K_hat = X^T K X.  X stored as TX (float32 or float64), arithmetic and W
+// in float64.  Entries ld - N_u past each vector are not written.
+template <typename TX>
+int apply_columns(Ctx* ctx, const Grid& g0, const ElemTables* tb, const double* alpha, const uint8_t* mask,
+                  const TX* x, double* y, int ncols, long long ld, hipStream_t s) {
     Grid g = g0;
-    constexpr bool F64 = sizeof(T) == 8;
-    if (g.dim == 3) g.mtarget = march3_target(ctx, (const void*)k_apply3<T>);
+    if (g.dim == 3) g.mtarget = march3_target(ctx, (const void*)k_apply3<double, TX, double>);
     const dim3 grid(stencil_blocks(g), ncols);
     if (g.dim == 2)
-        hipLaunchKernelGGL((k_apply2<T>), grid, dim3(kBlock), 0, s, g, alpha, 0LL, ld,
-                           F64 ? (const T*)tb->K64 : (const T*)tb->K32, mask, x, y);
+        hipLaunchKernelGGL((k_apply2<double, TX, double>), grid, dim3(kBlock), 0, s, g, alpha, 0LL, ld, tb->K64,
+                           mask, x, y);
     else
-        hipLaunchKernelGGL((k_apply3<T>), grid, dim3(kBlock), 0, s, g, alpha, 0LL, ld,
-                           F64 ? (const T*)tb->M64 : (const T*)tb->M32, mask, x, y);
+        hipLaunchKernelGGL((k_apply3<double, TX, double>), grid, dim3(kBlock), 0, s, g, alpha, 0LL, ld, tb->M64,
+                           mask, x, y);
     TOPO_CHECK_LAUNCH();
     return TOPO_OK;
 }
-template int apply_columns<float>(Ctx*, const Grid&, const ElemTables*, const float*, const uint8_t*,
-                                  const float*, float*, int, long long, hipStream_t);
+template int apply_columns<float>(Ctx*, const Grid&, const ElemTables*, const double*, const uint8_t*,
+                                  const float*, double*, int, long long, hipStream_t);
 template int apply_columns<double>(Ctx*, const Grid&, const ElemTables*, const double*, const uint8_t*,
                                    const double*, double*, int, long long, hipStream_t);
 

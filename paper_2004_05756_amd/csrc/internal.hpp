@@ -379,9 +379,9 @@ int gradient_launch(Ctx* ctx, const Grid& g, const topo_mesh& m, const ElemTable
 // CU count); 1024 when the runtime cannot tell.
 int march3_target(const Ctx* ctx, const void* kernel);
 struct ElemTables;
-template <typename T>
-int apply_columns(Ctx* ctx, const Grid& g, const ElemTables* tb, const T* alpha, const uint8_t* mask,
-                  const T* x, T* y, int ncols, long long ld, hipStream_t s);
+template <typename TX>
+int apply_columns(Ctx* ctx, const Grid& g, const ElemTables* tb, const double* alpha, const uint8_t* mask,
+                  const TX* x, double* y, int ncols, long long ld, hipStream_t s);
 
 // Blocks of a node-stencil launch (apply, PCG apply, residual): one per march column
 // in 3D, one per kBlock consecutive nodes in 2D.

@@ -20,20 +20,12 @@ int residual_fp64(Ctx* ctx, const Grid& g, const ElemTables* tb, const double* a
 int alpha_tables(Ctx* ctx, const Grid& g, const topo_mesh& m, const double* rho, int B,
                  double* a64, float* a32, hipStream_t s);
 
-typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 template <typename T> struct Mfma;
-// Both 16x16x4 instructions take A[i][kk] from lane i + 16 kk and B[kk][j] from lane
-// j + 16 kk; they differ in where output element D[i][j] lands (j = lane % 16 in both):
-// f32 keeps four consecutive rows per lane, f64 interleaves rows with stride 4.
-template <> struct Mfma<float> {
-    typedef f32x4 acc_t;
-    static __device__ __forceinline__ acc_t run(float a, float b, acc_t c) {
-        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-    }
-    static __device__ __forceinline__ int row(int lane, int v) { return 4 * (lane >> 4) + v; }
-};
+// The 16x16x4 float64 instruction takes A[i][kk] from lane i + 16 kk and B[kk][j] from
+// lane j + 16 kk; output element D[i][j] lands in lane j + 16 (i % 4), entry i / 4 (rows
+// interleaved with stride 4).
 template <> struct Mfma<double> {
     typedef f64x4 acc_t;
     static __device__ __forceinline__ acc_t run(double a, double b, acc_t c) {
@@ -47,20 +39,23 @@ template <> struct Mfma<double> {
 // W = K(rho) Phi~ (Phi~: the basis with its Dirichlet rows dropped, which the apply does
 // by itself): the element products are formed once per node row by the batched apply
 // (apply_columns, the basis columns as its vectors), and the k x k product over the N_u
-// rows runs on the matrix cores.  Both operands come as k rows of ld >= N_u entries
-// (zero past N_u): Pt, the basis transposed (k_basis_rows), and Wt, the apply's output.
+// rows runs on the float64 matrix cores.  Both operands come as k rows of ld >= N_u
+// entries (zero past N_u), stored as TS (float32 in the mixed build, float64 in the FP64
+// one): Pt, the basis transposed (k_basis_rows), and Wt, the apply's output.  The
+// product accumulates in float64 whatever TS is: for a basis column with a large
+// translation-like part, Phi_i . (K Phi_j) sums terms far larger than the result (the
+// translation is annihilated only by the element operators, not term by term), and a
+// float32 accumulation lost it (K_hat 1e-2 off on the benchmark's basis).
 //   grid.x : chunks of CH DOFs,  grid.y : groups of upper-triangle 16 x 16 tile pairs
 // Per slab of SD DOFs the block stages that slab of every row of Pt and Wt in LDS with
 // 16-byte loads (the next slab's loads in flight while the current one is multiplied),
 // then each of its GW waves accumulates its NT tile pairs K_IJ += Pt_I Wt_J^T, 4 DOFs
-// per instruction.  A block writes its chunk's tiles (float32 sums over CH DOFs in
-// float32, float64 ones in float64); k_chunk_sum adds the chunks in float64 in a fixed
-// order.
+// per instruction.  A block writes its chunk's tiles; k_chunk_sum adds the chunks in a
+// fixed order.
 // ----------------------------------------------------------------------------------
 constexpr int GW = 8;       // waves per block
-// most tile pairs per wave: 12 in float32 (182 VGPRs), 8 in float64 (202; 12 would spill)
-constexpr int max_nt(bool f64) { return f64 ? 8 : 12; }
-constexpr int KP_MAX = 512; // largest padded basis size
+constexpr int MAX_NT = 8;   // most tile pairs per wave (float64 accumulators; 12 would spill)
+constexpr int KP_MAX = 1024; // largest padded basis size
 constexpr int GEMM_LD = 64; // the operands' row pitch is a multiple of this
 
 __device__ __forceinline__ void pair_of(int p, int kt, int& I, int& J) {
@@ -75,11 +70,12 @@ __device__ __forceinline__ void pair_of(int p, int kt, int& I, int& J) {
 }
 
 // DOFs per staged slab: a multiple of the 4 of one matrix-core step, sized so that a
-// slab of KP rows is at most 4 16-byte loads per thread and operand.  LDS row pitch
-// SD + 2: the 32 lanes of a half-wave read 16 rows x 2 DOFs on distinct banks.
+// slab of KP rows (up to 256, 512 or 1024) is at most 4 16-byte loads per thread and
+// operand.  LDS row pitch SD + 2: the 32 lanes of a half-wave read 16 rows x 2 DOFs on
+// distinct banks.
 template <typename TC>
 __host__ __device__ constexpr int gemm_sd(int KP) {
-    return sizeof(TC) == 4 ? (KP <= 256 ? 32 : 16) : (KP <= 256 ? 16 : 8);
+    return (KP <= 256 ? 128 : KP <= 512 ? 64 : 32) / (int)sizeof(TC);
 }
 
 template <typename TC> struct Vec16;
@@ -101,20 +97,22 @@ template <> struct Vec16<double> {
     }
 };
 
-template <typename TC, int SD, int NT>
-__global__ __launch_bounds__(GW * 64) void k_rom_gemm(const TC* __restrict__ Pt, const TC* __restrict__ Wt,
+template <typename TA, int SD, int NT>
+__global__ __launch_bounds__(GW * 64) void k_rom_gemm(const TA* __restrict__ Pt, const double* __restrict__ Wt,
                                                      long long ld, long long nu, int k, int KP, int npairs,
-                                                     int kt, int ch, TC* __restrict__ partials) {
+                                                     int kt, int ch, double* __restrict__ partials) {
     constexpr int LSD = SD + 2;
     constexpr int NTH = GW * 64;
-    constexpr int V = 16 / sizeof(TC);       // entries per 16-byte load
-    constexpr int SV = SD / V;               // loads per row and slab
-    constexpr int MAXQ = 4;                  // loads per thread and operand (KP * SV <= 4 NTH)
-    static_assert(SD % V == 0 && SD % 4 == 0, "slab of whole loads and steps");
-    typedef typename Vec16<TC>::type vec_t;
+    constexpr int VA = 16 / sizeof(TA), VB = 2;  // entries per 16-byte load of Pt, of Wt
+    constexpr int SVA = SD / VA, SVB = SD / VB;  // loads per row and slab
+    constexpr int MAXB = 4;                      // loads per thread for Wt (KP * SVB <= 4 NTH)
+    constexpr int MAXA = MAXB * VB / VA;          // and for Pt (KP * SVA <= MAXA NTH)
+    static_assert(SD % VA == 0 && SD % VB == 0 && SD % 4 == 0, "slab of whole loads and steps");
+    typedef typename Vec16<TA>::type veca_t;
+    typedef typename Vec16<double>::type vecb_t;
     extern __shared__ __align__(16) unsigned char smem[];
-    TC* sA = (TC*)smem;              // [KP][LSD] slab of Pt
-    TC* sB = sA + (size_t)KP * LSD;  // [KP][LSD] slab of Wt
+    double* sB = (double*)smem;          // [KP][LSD] slab of Wt
+    TA* sA = (TA*)(sB + (size_t)KP * LSD);  // [KP][LSD] slab of Pt
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const long long d0 = (long long)blockIdx.x * ch;
     const long long d1 = min(d0 + (long long)ch, nu);
@@ -127,24 +125,32 @@ __global__ __launch_bounds__(GW * 64) void k_rom_gemm(const TC* __restrict__ Pt,
         if (p < npairs) pair_of(p, kt, myI[t], myJ[t]);
         else myI[t] = myJ[t] = 0;
     }
-    typedef typename Mfma<TC>::acc_t acc_t;
+    typedef typename Mfma<double>::acc_t acc_t;
     acc_t acc[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[t] = acc_t{0, 0, 0, 0};
     // staging: load q = tid + NTH u is row q / SV, entries V (q % SV) .. + V - 1 of the
     // slab; rows >= k read as zeros, and entries past N_u are zeros of the operands (a
     // slab never passes ld, which is a multiple of SD)
-    vec_t ra[MAXQ], rb[MAXQ];
-    const int nq = KP * SV;
+    veca_t ra[MAXA];
+    vecb_t rb[MAXB];
+    const int nqa = KP * SVA, nqb = KP * SVB;
     auto fetch = [&](long long ds) {
 #pragma unroll
-        for (int u = 0; u < MAXQ; ++u) {
+        for (int u = 0; u < MAXA; ++u) {
             const int q = tid + NTH * u;
-            const int r = q / SV, c = (q % SV) * V;
-            const bool ok = q < nq && r < k;
+            const int r = q / SVA, c = (q % SVA) * VA;
+            const bool ok = q < nqa && r < k;
             const size_t off = ok ? (size_t)r * (size_t)ld + (size_t)(ds + c) : 0;
-            ra[u] = Vec16<TC>::keep(ok, *(const vec_t*)(Pt + off));
-            rb[u] = Vec16<TC>::keep(ok, *(const vec_t*)(Wt + off));
+            ra[u] = Vec16<TA>::keep(ok, *(const veca_t*)(Pt + off));
+        }
+#pragma unroll
+        for (int u = 0; u < MAXB; ++u) {
+            const int q = tid + NTH * u;
+            const int r = q / SVB, c = (q % SVB) * VB;
+            const bool ok = q < nqb && r < k;
+            const size_t off = ok ? (size_t)r * (size_t)ld + (size_t)(ds + c) : 0;
+            rb[u] = Vec16<double>::keep(ok, *(const vecb_t*)(Wt + off));
         }
     };
     fetch(d0);
@@ -152,15 +158,21 @@ __global__ __launch_bounds__(GW * 64) void k_rom_gemm(const TC* __restrict__ Pt,
     for (long long ds = d0; ds < d1; ds += SD) {
         __syncthreads();  // the previous slab is consumed
 #pragma unroll
-        for (int u = 0; u < MAXQ; ++u) {
+        for (int u = 0; u < MAXA; ++u) {
             const int q = tid + NTH * u;
-            if (q < nq) {
-                const int r = q / SV, c = (q % SV) * V;
+            if (q < nqa) {
+                const int r = q / SVA, c = (q % SVA) * VA;
 #pragma unroll
-                for (int v = 0; v < V; ++v) {
-                    sA[r * LSD + c + v] = Vec16<TC>::at(ra[u], v);
-                    sB[r * LSD + c + v] = Vec16<TC>::at(rb[u], v);
-                }
+                for (int v = 0; v < VA; ++v) sA[r * LSD + c + v] = Vec16<TA>::at(ra[u], v);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < MAXB; ++u) {
+            const int q = tid + NTH * u;
+            if (q < nqb) {
+                const int r = q / SVB, c = (q % SVB) * VB;
+#pragma unroll
+                for (int v = 0; v < VB; ++v) sB[r * LSD + c + v] = Vec16<double>::at(rb[u], v);
             }
         }
         __syncthreads();
@@ -168,14 +180,14 @@ __global__ __launch_bounds__(GW * 64) void k_rom_gemm(const TC* __restrict__ Pt,
 #pragma unroll
         for (int s4 = 0; s4 < SD / 4; ++s4) {
             const int c = s4 * 4 + cl;
-            TC av[NT], bv[NT];
+            double av[NT], bv[NT];
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
-                av[t] = sA[(myI[t] * 16 + rl) * LSD + c];
+                av[t] = (double)sA[(myI[t] * 16 + rl) * LSD + c];
                 bv[t] = sB[(myJ[t] * 16 + rl) * LSD + c];
             }
 #pragma unroll
-            for (int t = 0; t < NT; ++t) acc[t] = Mfma<TC>::run(av[t], bv[t], acc[t]);
+            for (int t = 0; t < NT; ++t) acc[t] = Mfma<double>::run(av[t], bv[t], acc[t]);
         }
     }
     // the chunk's tiles: partials[chunk][pair][16 * 16]
@@ -183,28 +195,27 @@ __global__ __launch_bounds__(GW * 64) void k_rom_gemm(const TC* __restrict__ Pt,
     for (int t = 0; t < NT; ++t) {
         const int p = pbase + GW * t;
         if (p < npairs) {
-            TC* dst = partials + ((size_t)blockIdx.x * npairs + p) * 256;
+            double* dst = partials + ((size_t)blockIdx.x * npairs + p) * 256;
 #pragma unroll
-            for (int v = 0; v < 4; ++v) dst[Mfma<TC>::row(lane, v) * 16 + (lane & 15)] = acc[t][v];
+            for (int v = 0; v < 4; ++v) dst[Mfma<double>::row(lane, v) * 16 + (lane & 15)] = acc[t][v];
         }
     }
 }
 
-// Pt[j][d] = Phi[d][j] (j < k, d < N_u), converted to the compute type, and zeros at
-// N_u <= d < ld: 64 x 64 tiles through LDS (reads along the basis rows, writes along
-// the transposed ones).  Also zeroes the same tail of Wt's rows (the apply writes only
-// the first N_u entries of each).
-template <typename TP, typename TC>
+// Pt[j][d] = Phi[d][j] (j < k, d < N_u), and zeros at N_u <= d < ld: 64 x 64 tiles
+// through LDS (reads along the basis rows, writes along the transposed ones).  Also
+// zeroes the same tail of Wt's rows (the apply writes only the first N_u entries of each).
+template <typename TP>
 __global__ __launch_bounds__(256) void k_basis_rows(const TP* __restrict__ phi, int ldphi, long long nu, int k,
-                                                    long long ld, TC* __restrict__ Pt, TC* __restrict__ Wt) {
-    __shared__ TC tile[64][65];
+                                                    long long ld, TP* __restrict__ Pt, double* __restrict__ Wt) {
+    __shared__ TP tile[64][65];
     const long long d0 = (long long)blockIdx.x * 64;
     const int j0 = blockIdx.y * 64;
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
     for (int r = ty; r < 64; r += 4) {
         const long long d = d0 + r;
         const int j = j0 + tx;
-        tile[r][tx] = (d < nu && j < k) ? (TC)phi[(size_t)d * ldphi + j] : TC(0);
+        tile[r][tx] = (d < nu && j < k) ? phi[(size_t)d * ldphi + j] : TP(0);
     }
     __syncthreads();
     for (int r = ty; r < 64; r += 4) {
@@ -212,7 +223,7 @@ __global__ __launch_bounds__(256) void k_basis_rows(const TP* __restrict__ phi, 
         const long long d = d0 + tx;
         if (j < k && d < ld) {
             Pt[(size_t)j * ld + d] = tile[tx][r];  // zero past N_u
-            if (d >= nu) Wt[(size_t)j * ld + d] = TC(0);
+            if (d >= nu) Wt[(size_t)j * ld + d] = 0.0;
         }
     }
 }
@@ -869,28 +880,26 @@ struct ContractPlan {
     size_t lds_bytes;
 };
 
-// The plan depends on the mesh, k and precision only -- never on B -- so a field's
-// K_hat is bitwise the same alone and inside a batch.
+// The plan depends on the mesh, k and the basis type only -- never on B -- so a field's
+// K_hat is bitwise the same alone and inside a batch.  f64: the basis is float64.
 static ContractPlan plan_contract(const Grid& g, int k, bool f64) {
     ContractPlan p;
     p.KP = (k + 15) / 16 * 16;
     p.kt = p.KP / 16;
     p.npairs = p.kt * (p.kt + 1) / 2;
-    p.groups = (p.npairs + max_nt(f64) * GW - 1) / (max_nt(f64) * GW);
+    p.groups = (p.npairs + MAX_NT * GW - 1) / (MAX_NT * GW);
     p.nt = (p.npairs + p.groups * GW - 1) / (p.groups * GW);
-    p.sd = f64 ? gemm_sd<double>(p.KP) : gemm_sd<float>(p.KP);
-    // DOFs per chunk: float32 sums over at most 2048 products before they are added in
-    // float64 (as the matrix cores accumulate them), float64 ones over 8192
-    p.ch = f64 ? 8192 : 2048;
+    p.sd = gemm_sd<double>(p.KP);
+    p.ch = 8192;  // DOFs per chunk (one float64 partial tile per chunk and pair)
     p.nchunks = (int)((g.n_dofs + p.ch - 1) / p.ch);
     p.ld = (g.n_dofs + GEMM_LD - 1) / GEMM_LD * GEMM_LD;
-    p.lds_bytes = (size_t)2 * p.KP * (p.sd + 2) * (f64 ? 8 : 4);
+    p.lds_bytes = (size_t)p.KP * (p.sd + 2) * ((f64 ? 8 : 4) + 8);  // Pt in the basis type, Wt in float64
     return p;
 }
 
 template <typename TC, int SD, int NT>
-static int launch_gemm_nt(Ctx* ctx, const ContractPlan& p, const TC* Pt, const TC* Wt, long long nu, int k,
-                          TC* parts, hipStream_t s) {
+static int launch_gemm_nt(Ctx* ctx, const ContractPlan& p, const TC* Pt, const double* Wt, long long nu, int k,
+                          double* parts, hipStream_t s) {
     auto kern = k_rom_gemm<TC, SD, NT>;
     TOPO_HIP(ensure_dynamic_lds((const void*)kern, p.lds_bytes));
     hipLaunchKernelGGL(kern, dim3(p.nchunks, p.groups), dim3(GW * 64), p.lds_bytes, s, Pt, Wt, p.ld, nu, k, p.KP,
@@ -900,37 +909,37 @@ static int launch_gemm_nt(Ctx* ctx, const ContractPlan& p, const TC* Pt, const T
 }
 
 template <typename TC, int SD>
-static int launch_gemm_sd(Ctx* ctx, const ContractPlan& p, const TC* Pt, const TC* Wt, long long nu, int k,
-                          TC* parts, hipStream_t s) {
+static int launch_gemm_sd(Ctx* ctx, const ContractPlan& p, const TC* Pt, const double* Wt, long long nu, int k,
+                          double* parts, hipStream_t s) {
     // the smallest instantiated pair count per wave that covers the plan's
     if (p.nt <= 1) return launch_gemm_nt<TC, SD, 1>(ctx, p, Pt, Wt, nu, k, parts, s);
     if (p.nt <= 2) return launch_gemm_nt<TC, SD, 2>(ctx, p, Pt, Wt, nu, k, parts, s);
     if (p.nt <= 3) return launch_gemm_nt<TC, SD, 3>(ctx, p, Pt, Wt, nu, k, parts, s);
     if (p.nt <= 4) return launch_gemm_nt<TC, SD, 4>(ctx, p, Pt, Wt, nu, k, parts, s);
     if (p.nt <= 6) return launch_gemm_nt<TC, SD, 6>(ctx, p, Pt, Wt, nu, k, parts, s);
-    if (sizeof(TC) == 8 || p.nt <= 8) return launch_gemm_nt<TC, SD, 8>(ctx, p, Pt, Wt, nu, k, parts, s);
-    if constexpr (sizeof(TC) == 4) return launch_gemm_nt<TC, SD, 12>(ctx, p, Pt, Wt, nu, k, parts, s);
-    return TOPO_EINVAL;
+    return launch_gemm_nt<TC, SD, 8>(ctx, p, Pt, Wt, nu, k, parts, s);
 }
 
 template <typename TC>
-static int launch_gemm(Ctx* ctx, const ContractPlan& p, const TC* Pt, const TC* Wt, long long nu, int k,
-                       TC* parts, hipStream_t s) {
-    constexpr int SD0 = gemm_sd<TC>(256), SD1 = gemm_sd<TC>(KP_MAX);
+static int launch_gemm(Ctx* ctx, const ContractPlan& p, const TC* Pt, const double* Wt, long long nu, int k,
+                       double* parts, hipStream_t s) {
+    constexpr int SD0 = gemm_sd<double>(256), SD1 = gemm_sd<double>(512), SD2 = gemm_sd<double>(1024);
     if (p.sd == SD0) return launch_gemm_sd<TC, SD0>(ctx, p, Pt, Wt, nu, k, parts, s);
-    return launch_gemm_sd<TC, SD1>(ctx, p, Pt, Wt, nu, k, parts, s);
+    if (p.sd == SD1) return launch_gemm_sd<TC, SD1>(ctx, p, Pt, Wt, nu, k, parts, s);
+    return launch_gemm_sd<TC, SD2>(ctx, p, Pt, Wt, nu, k, parts, s);
 }
 
-// K_hat of every field (the contraction and its chunk sums), from the basis Phi (TP)
-// in the compute type TC: Pt, Wt [k][ld] and parts [nchunks][npairs][256] are workspace.
-template <typename TP, typename TC>
+// K_hat of every field (the contraction and its chunk sums), from the basis Phi (TP):
+// Pt [k][ld] (TP), Wt [k][ld] (float64) and parts [nchunks][npairs][256] are workspace;
+// alpha [B][N_e] in float64.
+template <typename TP>
 static int contract_fields(Ctx* ctx, const Grid& g, const ElemTables* tb, const ContractPlan& p, const TP* phi,
-                           int k, int ldphi, const uint8_t* mask, const TC* alpha, int B, TC* Pt, TC* Wt, TC* parts,
-                           double* Khat, hipStream_t s) {
+                           int k, int ldphi, const uint8_t* mask, const double* alpha, int B, TP* Pt, double* Wt,
+                           double* parts, double* Khat, hipStream_t s) {
     const long long nu = g.n_dofs;
     {
         TimedLaunch tl(ctx, KID_ROM_APPLY, s);
-        hipLaunchKernelGGL((k_basis_rows<TP, TC>), dim3((unsigned)(p.ld / 64), (k + 63) / 64), dim3(256), 0, s,
+        hipLaunchKernelGGL((k_basis_rows<TP>), dim3((unsigned)(p.ld / 64), (k + 63) / 64), dim3(256), 0, s,
                            phi, ldphi, nu, k, p.ld, Pt, Wt);
     }
     TOPO_CHECK_LAUNCH();
@@ -938,17 +947,17 @@ static int contract_fields(Ctx* ctx, const Grid& g, const ElemTables* tb, const 
         int rc;
         {
             TimedLaunch tl(ctx, KID_ROM_APPLY, s);
-            rc = apply_columns<TC>(ctx, g, tb, alpha + (size_t)b * g.n_elems, mask, Pt, Wt, k, p.ld, s);
+            rc = apply_columns<TP>(ctx, g, tb, alpha + (size_t)b * g.n_elems, mask, Pt, Wt, k, p.ld, s);
         }
         if (rc) return rc;
         {
             TimedLaunch tl(ctx, KID_ROM_CONTRACT, s);
-            rc = launch_gemm<TC>(ctx, p, Pt, Wt, nu, k, parts, s);
+            rc = launch_gemm<TP>(ctx, p, Pt, Wt, nu, k, parts, s);
         }
         if (rc) return rc;
         {
             TimedLaunch tl(ctx, KID_ROM_REDUCE, s);
-            launch_chunk_sum(p.npairs * 256, p.nchunks, 1, (const TC*)parts,
+            launch_chunk_sum(p.npairs * 256, p.nchunks, 1, (const double*)parts,
                              KhatOut{k, p.kt, Khat + (size_t)b * k * k}, s);
         }
         TOPO_CHECK_LAUNCH();
@@ -979,41 +988,30 @@ int topo_rom_build(topo_ctx* ctx, const topo_mesh* mesh, const void* phi, int32_
     const ElemTables* tb = get_tables(ctx, *mesh);
     if (!tb) return set_error(ctx, TOPO_EDEVICE, "element table upload failed");
     hipStream_t s = (hipStream_t)stream;
-    const bool f64 = prec == TOPO_FP64;
-    const ContractPlan p = plan_contract(g, k, f64);
+    // The contraction's arithmetic is float64 in both precisions (see k_rom_gemm): the
+    // transposed basis keeps the basis's own type, W = K Phi is float64.
+    (void)prec;
+    const ContractPlan p = plan_contract(g, k, !phi_fp32);
     if (p.KP > KP_MAX) return set_error(ctx, TOPO_EINVAL, "k = %d too large for the contraction (at most %d)", k, KP_MAX);
     const int nc = phit_chunks(g);
     const size_t nk = (size_t)k * p.ld, np = (size_t)p.nchunks * p.npairs * 256;
     Arena ar;
-    double *a64 = nullptr, *P64 = nullptr, *W64 = nullptr, *parts64 = nullptr;
-    float *a32 = nullptr, *P32 = nullptr, *W32 = nullptr, *parts32 = nullptr;
-    double* pf;
-    if (f64) {
-        ar.take(&a64, (size_t)B * g.n_elems);
-        ar.take(&P64, nk);
-        ar.take(&W64, nk);
-        ar.take(&parts64, np);
-    } else {
-        ar.take(&a32, (size_t)B * g.n_elems);
-        ar.take(&P32, nk);
-        ar.take(&W32, nk);
-        ar.take(&parts32, np);
-    }
+    double *a64 = nullptr, *P64 = nullptr, *Wt = nullptr, *parts = nullptr, *pf = nullptr;
+    float* P32 = nullptr;
+    ar.take(&a64, (size_t)B * g.n_elems);
+    if (phi_fp32) ar.take(&P32, nk);
+    else ar.take(&P64, nk);
+    ar.take(&Wt, nk);
+    ar.take(&parts, np);
     ar.take(&pf, (size_t)nc * k);
     rc = ar.commit(ctx, s);
     if (rc) return rc;
-    rc = alpha_tables(ctx, g, *mesh, rho, B, a64, a32, s);
+    rc = alpha_tables(ctx, g, *mesh, rho, B, a64, nullptr, s);
     if (rc) return rc;
-    if (f64)
-        rc = phi_fp32 ? contract_fields(ctx, g, tb, p, (const float*)phi, k, ldphi, mask, (const double*)a64, B, P64,
-                                        W64, parts64, Khat, s)
-                      : contract_fields(ctx, g, tb, p, (const double*)phi, k, ldphi, mask, (const double*)a64, B,
-                                        P64, W64, parts64, Khat, s);
-    else
-        rc = phi_fp32 ? contract_fields(ctx, g, tb, p, (const float*)phi, k, ldphi, mask, (const float*)a32, B, P32,
-                                        W32, parts32, Khat, s)
-                      : contract_fields(ctx, g, tb, p, (const double*)phi, k, ldphi, mask, (const float*)a32, B, P32,
-                                        W32, parts32, Khat, s);
+    rc = phi_fp32 ? contract_fields(ctx, g, tb, p, (const float*)phi, k, ldphi, mask, (const double*)a64, B, P32, Wt,
+                                    parts, Khat, s)
+                  : contract_fields(ctx, g, tb, p, (const double*)phi, k, ldphi, mask, (const double*)a64, B, P64, Wt,
+                                    parts, Khat, s);
     if (rc) return rc;
     if (fhat) {
         rc = phit_v(ctx, g, phi, phi_fp32, k, ldphi, mask, f, 0, 1, fhat, pf, nc, s);
@@ -1262,24 +1260,20 @@ int topo_rom_gradient(topo_ctx* ctx, const topo_mesh* mesh, const void* phi, int
 namespace topo {
 
 size_t ws_rom_build(const Grid& g, int k, int B, bool f64, int cu) {
+    // f64: the basis is float64 (the contraction's own precision does not depend on the
+    // build's)
     (void)cu;
     const ContractPlan p = plan_contract(g, k, f64);
     const int nc = phit_chunks(g);
     const size_t nk = (size_t)k * p.ld, np = (size_t)p.nchunks * p.npairs * 256;
     Arena ar;
-    double *a64, *P64, *W64, *parts64, *pf;
-    float *a32, *P32, *W32, *parts32;
-    if (f64) {
-        ar.take(&a64, (size_t)B * g.n_elems);
-        ar.take(&P64, nk);
-        ar.take(&W64, nk);
-        ar.take(&parts64, np);
-    } else {
-        ar.take(&a32, (size_t)B * g.n_elems);
-        ar.take(&P32, nk);
-        ar.take(&W32, nk);
-        ar.take(&parts32, np);
-    }
+    double *a64, *P64, *Wt, *parts, *pf;
+    float* P32;
+    ar.take(&a64, (size_t)B * g.n_elems);
+    if (f64) ar.take(&P64, nk);
+    else ar.take(&P32, nk);
+    ar.take(&Wt, nk);
+    ar.take(&parts, np);
     ar.take(&pf, (size_t)nc * k);
     return ar.total();
 }

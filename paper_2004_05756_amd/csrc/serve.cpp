@@ -124,7 +124,8 @@ void size_job(topo_server* S, Job& j, int B) {
         j.staging_need = align_up((size_t)B * g.n_elems * 8) + align_up((size_t)B * g.n_dofs * 8);
     } else {
         const int kb = j.kb;
-        j.ws_need = std::max({ws_rom_build(g, kb, B, !mixed, S->cu), ws_rom_solve(kb, 1),
+        const bool basis64 = !S->bases[j.basis_id].fp32;
+        j.ws_need = std::max({ws_rom_build(g, kb, B, basis64, S->cu), ws_rom_solve(kb, 1),
                               ws_rom_estimate(g, kb, 1, j.max_refine)});
         j.staging_need = align_up((size_t)B * g.n_elems * 8) + align_up((size_t)B * kb * kb * 8) +
                          align_up((size_t)kb * kb * 8) + align_up((size_t)kb * 8) +

@@ -21,14 +21,14 @@ struct FetchPlain {
     __device__ __forceinline__ T operator()(int n, int c) const { return x[(size_t)c * nn + n]; }
 };
 
-template <typename T>
-struct FetchMasked {
-    const T* __restrict__ x;
+template <typename T, typename TX = T>
+struct FetchMasked {  // x (stored as TX) in the arithmetic type T, Dirichlet DOFs zeroed
+    const TX* __restrict__ x;
     const uint8_t* __restrict__ mask;
     int nn;
     __device__ __forceinline__ T operator()(int n, int c) const {
         const size_t i = (size_t)c * nn + n;
-        return mask[i] ? T(0) : x[i];
+        return mask[i] ? T(0) : (T)x[i];
     }
 };
 

@@ -20,20 +20,20 @@ def test_pcg_bytes_count_every_array_once():
         assert b["pcg_step"] == nu * (4 * w + 1 + 16 + 4 * w) + nn * w + ne * w
         # apply: z, p_old read, p_new, q written, mask; alpha per element
         assert b["pcg_apply"] == nu * (2 * w + 2 * w + 1) + ne * w
-        # update: r read + written, z written, p, q read, 1 / sum(alpha); x read + written
-        # (16) and the previous p read at every second update only: 8 + w / 2 on average
-        assert b["pcg_update"] == nu * (8 + w // 2 + 2 * w + w + 2 * w) + nn * w
-    # the 3D update applies the mask (its byte per DOF moves from the apply to the
-    # update) and takes x eight steps at a time (x read + written and seven earlier
-    # directions read at every eighth update: (16 + 7 w) / 8 per DOF); the 3D float32
-    # apply forms z from r and 1 / sum(alpha): one more read per node in the apply, no z
-    # written by the update
+        # update: r read + written, z written, q read, 1 / sum(alpha); x read + written (16)
+        # and the pair's two directions read at every second update only: 8 + w on average
+        assert b["pcg_update"] == nu * (8 + w + 2 * w + w + w) + nn * w
+    # the 3D update applies the mask (one byte of mask bits per node instead of the
+    # apply's byte per DOF) and takes x eight steps at a time (x read + written and the
+    # group's eight directions read at every eighth update: (16 + 8 w) / 8 per DOF); the
+    # 3D float32 apply forms z from r and 1 / sum(alpha): one more read per node in the
+    # apply, no z written by the update
     b3 = bench.pcg_bytes(nu, nn, ne, 4, 3)
     assert b3["pcg_apply"] == nu * (2 * 4 + 2 * 4) + ne * 4 + nn * 4
-    assert b3["pcg_update"] == nu * (2 + 3.5 + 2 * 4 + 2 * 4 + 1) + nn * 4
+    assert b3["pcg_update"] == nu * (2 + 4 + 2 * 4 + 4) + nn * (4 + 1)
     b2d, b3d = bench.pcg_bytes(nu, nn, ne, 8, 2), bench.pcg_bytes(nu, nn, ne, 8, 3)
     assert b3d["pcg_apply"] == b2d["pcg_apply"] - nu
-    assert b3d["pcg_update"] == b2d["pcg_update"] + nu - nu * (8 + 4) + nu * (2 + 7)
+    assert b3d["pcg_update"] == b2d["pcg_update"] + nn - nu * (8 + 8) + nu * (2 + 8)
 
 
 def test_kernel_names_match_the_traffic_summaries():

@@ -44,6 +44,27 @@ def test_rom_build_matches_oracle(p, k, mode):
     assert np.abs(fh - O.rom_load(phi, p.mask, p.f)).max() <= 1e-14 * max(np.abs(fh).max(), 1e-300) + 1e-300
 
 
+@pytest.mark.parametrize("mode", ["fp64", "mixed"])
+def test_rom_build_smooth_basis_entrywise(mode):
+    """K_hat of a smooth basis on a 3D mesh of some size, every entry against the oracle
+    relative to sqrt(K_ii K_jj) (Cauchy-Schwarz bound of the entry).  K Phi of smooth
+    fields cancels element contributions at every node, and Phi^T (K Phi) sums terms far
+    larger than the result when a column has a large translation-like part, so the
+    contraction runs in float64 in both precisions and must meet the oracle to 1e-10."""
+    torch = torch_cuda()
+    from paper_2004_05756_amd import FP64, MIXED
+    p, k = W.cantilever3d(32, 16, 16), 12
+    phi = _basis(p, k, np.float32, seed=21)
+    rhos = _rhos(p, 2, 23)
+    Kh, _ = ctx().rom_build(p.mesh, dev(phi), k, dev(p.mask, torch.uint8), dev(p.f, torch.float64),
+                            dev(rhos, torch.float64), prec=FP64 if mode == "fp64" else MIXED)
+    Kh = host(Kh)
+    for b in range(2):
+        ref = O.rom_operator(p.mesh, rhos[b], phi, p.mask)
+        d = np.sqrt(np.outer(np.diag(ref), np.diag(ref)))
+        assert (np.abs(Kh[b] - ref) / d).max() <= 1e-10
+
+
 @pytest.mark.parametrize("p,k", CASES[:4], ids=lambda v: getattr(v, "name", str(v)))
 def test_rom_solve_and_estimate(p, k):
     torch = torch_cuda()
