@@ -546,7 +546,8 @@ __global__ __launch_bounds__(kBlock, sizeof(T) == 4 ? 4 : 2) void k_pcg_apply3(G
 // the scalar reduction.  3D: q is zeroed at masked DOFs here (the 3D apply writes
 // unmasked parts), so that r stays zero there, from the node's mask bits (mask: [N_n],
 // bit c for component c, k_node_mask); the 2D apply masks q itself (mask unused).
-template <int DIM, typename T, bool FLUSH>
+// I: index type of the per-field arrays (32-bit when their bytes fit, update_narrow).
+template <int DIM, typename T, bool FLUSH, typename I>
 __global__ __launch_bounds__(kPcgBlock) void k_pcg_update(Grid g, const T* __restrict__ winv,
                                                        const uint8_t* __restrict__ mask,
                                                        T ik0, T ik1, T ik2, double* __restrict__ x,
@@ -583,32 +584,33 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_update(Grid g, const T* __res
     double xv[DIM];
     T rv[DIM], pv[DIM], ppv[G - 1][DIM], qv[DIM], w = T(0);
     if (own) {
-        w = winv[n];
+        w = ld_at(winv, (I)n);
 #pragma unroll
         for (int c = 0; c < DIM; ++c) {
-            const size_t i = (size_t)c * g.n_nodes + n;
+            const I i = (I)c * (I)g.n_nodes + (I)n;
             if (flush) {
-                xv[c] = x[i];
+                xv[c] = ld_at(x, i);
 #pragma unroll
-                for (int j = 1; j < G; ++j) ppv[j - 1][c] = pr.s[(phase + 1 - j) & (G - 1)][fo + i];
+                for (int j = 1; j < G; ++j) ppv[j - 1][c] = ld_at(pr.s[(phase + 1 - j) & (G - 1)] + fo, i);
             }
-            rv[c] = r[i];
-            pv[c] = p[i];
-            qv[c] = q[i];
+            rv[c] = ld_at((const T*)r, i);
+            pv[c] = ld_at(p, i);
+            qv[c] = ld_at(q, i);
         }
         if constexpr (DIM == 3) {
-            const unsigned mk = mask[n];
+            const unsigned mk = ld_at(mask, (I)n);
             // q = the primary block's part + the parts of the blocks below the node, in
             // the order of their side sections
-            const int i = n % g.nx1, jk = n / g.nx1, j = jk % g.ny1, k = jk / g.ny1;
+            const unsigned jk = sg.dnx.div((unsigned)n), kk = sg.dny.div(jk);
+            const int i = n - (int)jk * g.nx1, j = (int)(jk - kk * (unsigned)g.ny1), k = (int)kk;
             const int ax = side_axes(g, sg, i, j, k);
             if (ax) {
                 side += (size_t)f * 3 * sg.total;
                 for (int sec = 1; sec < 8; ++sec)
                     if ((sec & ax) == sec) {
-                        const long long si = side_index(sg, sec, i, j, k);
+                        const I si = (I)side_index(sg, sec, i, j, k);
 #pragma unroll
-                        for (int c = 0; c < 3; ++c) qv[c] += side[(size_t)c * sg.total + si];
+                        for (int c = 0; c < 3; ++c) qv[c] += ld_at(side, (I)c * (I)sg.total + si);
                     }
             }
 #pragma unroll
@@ -631,7 +633,7 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_update(Grid g, const T* __res
     if (own) {
 #pragma unroll
         for (int c = 0; c < DIM; ++c) {
-            const size_t i = (size_t)c * g.n_nodes + n;
+            const I i = (I)c * (I)g.n_nodes + (I)n;
             if (flush) {
                 // pairs of steps summed from the oldest pair to the newest
                 double s = G > 2 ? ao[G - 2] * (double)ppv[G - 2][c] + ao[G - 3] * (double)ppv[G - 3][c]
@@ -640,12 +642,12 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_update(Grid g, const T* __res
                 for (int k = G / 2 - 2; k >= 1; --k)
                     s += ao[2 * k] * (double)ppv[2 * k][c] + ao[2 * k - 1] * (double)ppv[2 * k - 1][c];
                 if constexpr (G > 2) s += ao[0] * (double)ppv[0][c] + (double)a * (double)pv[c];
-                x[i] = xv[c] + s;
+                st_at(x, i, xv[c] + s);
             }
             const T ri = rv[c] - a * qv[c];
             const T zi = jacobi_z(ri, w, ik[c]);
-            r[i] = ri;
-            if (DIM == 2 || !ApplyFormsZ<T>::value) z[i] = zi;  // else the 3D apply forms z
+            st_at(r, i, ri);
+            if (DIM == 2 || !ApplyFormsZ<T>::value) st_at(z, i, zi);  // else the 3D apply forms z
             v[0] += (double)ri * (double)zi;
             v[1] += (double)ri * (double)ri;
         }
@@ -1303,6 +1305,23 @@ static bool apply3_narrow(const Grid& g) {
     return sizeof(T) == 4 && 3ull * 2ull * nn * sizeof(T) < lim && (unsigned long long)g.n_elems * sizeof(T) < lim;
 }
 
+// The update takes 32-bit indices when each per-field array it touches fits in 4 GiB:
+// the float64 correction x (the largest DOF array) and the side sections (2 N_n nodes
+// bound them, as above).
+template <typename T>
+static bool update_narrow(const Grid& g) {
+    const unsigned long long lim = 1ull << 32, nn = (unsigned long long)g.n_nodes;
+    return (unsigned long long)g.n_dofs * sizeof(double) < lim && 3ull * 2ull * nn * sizeof(T) < lim;
+}
+
+template <int DIM, typename T>
+static const void* pcg_update_fn(bool flush, bool narrow) {
+    if (narrow)
+        return flush ? (const void*)k_pcg_update<DIM, T, true, unsigned>
+                     : (const void*)k_pcg_update<DIM, T, false, unsigned>;
+    return flush ? (const void*)k_pcg_update<DIM, T, true, size_t> : (const void*)k_pcg_update<DIM, T, false, size_t>;
+}
+
 template <typename T>
 static const void* pcg_apply3_fn(bool narrow) {
     if constexpr (sizeof(T) == 4)
@@ -1336,7 +1355,7 @@ static void pcg_iteration(Ctx* ctx, const Grid& g, const PcgBufs<T>& w, const Pc
         L.ev0 = tl.a;
         L.ev1 = tl.b;
         const bool flush = (lq & (XGroup<DIM>::value - 1)) == 0;  // a group's last update
-        L(flush ? (const void*)k_pcg_update<DIM, T, true> : (const void*)k_pcg_update<DIM, T, false>,
+        L(pcg_update_fn<DIM, T>(flush, update_narrow<T>(g)),
           dim3(pg.nupd, w.B), dim3(kPcgBlock), g, w.winv, DIM == 3 ? w.mnode : w.mask, w.ik[0], w.ik[1], w.ik[2],
           w.x, w.r, w.z,
           w.ring(), (const T*)w.q, (const T*)w.side, w.sg, w.part, w.st, pg.ps, pg.npq, lq);

@@ -324,11 +324,34 @@ __host__ __device__ inline int once3_blocks(const Grid& g) {
 // in y, bit 4: in z).  Along an axis in s the section holds only the interior block
 // boundaries (index = boundary number - 1), along the others every node; the sections
 // follow each other in the order of s, one component after the other ([c][total]).
+// Division by a divisor fixed at launch: floor(n / d) = (n m) >> s for 0 <= n < 2^31 and
+// 1 <= d < 2^31, with s = 31 + ceil(log2 d) and m = ceil(2^s / d) (the round-up method of
+// Granlund and Montgomery): m d - 2^s < d bounds the error n (m d - 2^s) / (d 2^s) below
+// 1/d, the distance from n / d up to the next integer, and m < 2^32.
+struct FastDiv {
+    unsigned d = 1, m = 1u << 31;
+    int s = 31;
+    __host__ __device__ unsigned div(unsigned n) const {
+        return (unsigned)(((unsigned long long)n * m) >> s);
+    }
+};
+
+inline FastDiv make_fastdiv(unsigned d) {
+    FastDiv f;
+    int l = 0;
+    while ((1ull << l) < d) ++l;
+    f.d = d;
+    f.s = 31 + l;
+    f.m = (unsigned)(((1ull << f.s) + d - 1) / d);
+    return f;
+}
+
 struct SideGeom {
     int nbx, nby, nbz;  // interior block boundaries along x, y, z
     int nnx, nny, nnz;  // nodes along x, y, z
     int kz;             // element layers per chunk
     long long total;    // nodes over all sections
+    FastDiv dnx, dny, dkz;  // division by nnx, nny, kz
     // extent of section s along x / y / z
     __host__ __device__ int ex(int s) const { return s & 1 ? nbx : nnx; }
     __host__ __device__ int ey(int s) const { return s & 2 ? nby : nny; }
@@ -339,7 +362,7 @@ __host__ __device__ inline long long side_count(const SideGeom& sg, int s) {
     return (long long)sg.ex(s) * sg.ey(s) * sg.ez(s);
 }
 
-__host__ __device__ inline SideGeom side_geom(const Grid& g) {
+inline SideGeom side_geom(const Grid& g) {
     SideGeom sg;
     sg.kz = once3_kz(g);
     sg.nbx = once3_tiles_x(g) - 1;
@@ -350,6 +373,9 @@ __host__ __device__ inline SideGeom side_geom(const Grid& g) {
     sg.nnz = g.nz1;
     sg.total = 0;
     for (int t = 1; t < 8; ++t) sg.total += side_count(sg, t);
+    sg.dnx = make_fastdiv((unsigned)sg.nnx);
+    sg.dny = make_fastdiv((unsigned)sg.nny);
+    sg.dkz = make_fastdiv((unsigned)sg.kz);
     return sg;
 }
 
@@ -360,14 +386,14 @@ __host__ __device__ inline long long side_index(const SideGeom& sg, int s, int i
     for (int t = 1; t < 7; ++t) off += t < s ? side_count(sg, t) : 0;
     const int a = s & 1 ? i / MEX - 1 : i;
     const int b = s & 2 ? j / MEY - 1 : j;
-    const int c = s & 4 ? k / sg.kz - 1 : k;
+    const int c = s & 4 ? (int)sg.dkz.div((unsigned)k) - 1 : k;
     return off + ((long long)c * sg.ey(s) + b) * sg.ex(s) + a;
 }
 
 // Axes along which node (i, j, k) lies on an interior block boundary (bit per axis).
 __host__ __device__ inline int side_axes(const Grid& g, const SideGeom& sg, int i, int j, int k) {
     return (i % MEX == 0 && i > 0 && i < g.nx ? 1 : 0) | (j % MEY == 0 && j > 0 && j < g.ny ? 2 : 0) |
-           (k % sg.kz == 0 && k > 0 && k < g.nz ? 4 : 0);
+           (k - (int)sg.dkz.div((unsigned)k) * sg.kz == 0 && k > 0 && k < g.nz ? 4 : 0);
 }
 
 // Element sensitivities dc_e = -alpha'(rho_e) u_e^T K_e u_e of B fields (rho [B][N_e],
