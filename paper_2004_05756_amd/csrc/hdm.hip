@@ -546,8 +546,9 @@ __global__ __launch_bounds__(kBlock, sizeof(T) == 4 ? 4 : 2) void k_pcg_apply3(G
 // the scalar reduction.  3D: q is zeroed at masked DOFs here (the 3D apply writes
 // unmasked parts), so that r stays zero there, from the node's mask bits (mask: [N_n],
 // bit c for component c, k_node_mask); the 2D apply masks q itself (mask unused).
-// I: index type of the per-field arrays (32-bit when their bytes fit, update_narrow).
-template <int DIM, typename T, bool FLUSH, typename I>
+// I: index type of the per-field arrays (32-bit when their bytes fit, update_narrow);
+// NPT: nodes per thread (grid (nupd of NPT kPcgBlock nodes, B)).
+template <int DIM, typename T, bool FLUSH, typename I, int NPT>
 __global__ __launch_bounds__(kPcgBlock) void k_pcg_update(Grid g, const T* __restrict__ winv,
                                                        const uint8_t* __restrict__ mask,
                                                        T ik0, T ik1, T ik2, double* __restrict__ x,
@@ -573,29 +574,34 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_update(Grid g, const T* __res
     const T* p = pr.s[(phase + 1) & (G - 1)] + fo;  // the apply's p_new
     q += fo;
     double* pb = part + (size_t)f * kPcgParts * ps;
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
-    const bool own = n < g.n_nodes;
     // the correction x takes G steps at once, at the group's last update (the earlier ones
     // only record their alpha): the directions of the group's earlier updates are older
     // slots of the ring.  Segments start at launch 1 of a chunk and chunks hold a multiple
     // of G launches, so every field's groups end together, at the launches whose index
-    // is a multiple of G: those run this kernel with FLUSH.
+    // is a multiple of G: those run this kernel with FLUSH.  A thread takes NPT nodes,
+    // kPcgBlock apart (NPT > 1 only without FLUSH: more loads in flight per thread).
     constexpr bool flush = FLUSH;
-    double xv[DIM];
-    T rv[DIM], pv[DIM], ppv[G - 1][DIM], qv[DIM], w = T(0);
-    if (own) {
-        w = ld_at(winv, (I)n);
+    static_assert(NPT == 1 || !FLUSH, "the correction update takes one node per thread");
+    const int n0 = blockIdx.x * blockDim.x * NPT + threadIdx.x;
+    double xv[NPT][DIM];
+    T rv[NPT][DIM], pv[NPT][DIM], ppv[G - 1][DIM], qv[NPT][DIM], w[NPT];
+#pragma unroll
+    for (int u = 0; u < NPT; ++u) {
+        const int n = n0 + u * kPcgBlock;
+        w[u] = T(0);
+        if (n >= g.n_nodes) continue;
+        w[u] = ld_at(winv, (I)n);
 #pragma unroll
         for (int c = 0; c < DIM; ++c) {
             const I i = (I)c * (I)g.n_nodes + (I)n;
             if (flush) {
-                xv[c] = ld_at(x, i);
+                xv[u][c] = ld_at(x, i);
 #pragma unroll
                 for (int j = 1; j < G; ++j) ppv[j - 1][c] = ld_at(pr.s[(phase + 1 - j) & (G - 1)] + fo, i);
             }
-            rv[c] = ld_at((const T*)r, i);
-            pv[c] = ld_at(p, i);
-            qv[c] = ld_at(q, i);
+            rv[u][c] = ld_at((const T*)r, i);
+            pv[u][c] = ld_at(p, i);
+            qv[u][c] = ld_at(q, i);
         }
         if constexpr (DIM == 3) {
             const unsigned mk = ld_at(mask, (I)n);
@@ -605,17 +611,17 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_update(Grid g, const T* __res
             const int i = n - (int)jk * g.nx1, j = (int)(jk - kk * (unsigned)g.ny1), k = (int)kk;
             const int ax = side_axes(g, sg, i, j, k);
             if (ax) {
-                side += (size_t)f * 3 * sg.total;
+                const T* sf = side + (size_t)f * 3 * sg.total;
                 for (int sec = 1; sec < 8; ++sec)
                     if ((sec & ax) == sec) {
                         const I si = (I)side_index(sg, sec, i, j, k);
 #pragma unroll
-                        for (int c = 0; c < 3; ++c) qv[c] += ld_at(side, (I)c * (I)sg.total + si);
+                        for (int c = 0; c < 3; ++c) qv[u][c] += ld_at(sf, (I)c * (I)sg.total + si);
                     }
             }
 #pragma unroll
             for (int c = 0; c < 3; ++c)
-                if ((mk >> c) & 1u) qv[c] = T(0);
+                if ((mk >> c) & 1u) qv[u][c] = T(0);
         }
     }
     const double pq = block_sum_array(pb, npq, lds);
@@ -630,22 +636,25 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_update(Grid g, const T* __res
     (void)ao;
     const T ik[3] = {ik0, ik1, ik2};
     double v[2] = {0.0, 0.0};
-    if (own) {
+#pragma unroll
+    for (int u = 0; u < NPT; ++u) {
+        const int n = n0 + u * kPcgBlock;
+        if (n >= g.n_nodes) continue;
 #pragma unroll
         for (int c = 0; c < DIM; ++c) {
             const I i = (I)c * (I)g.n_nodes + (I)n;
             if (flush) {
                 // pairs of steps summed from the oldest pair to the newest
                 double s = G > 2 ? ao[G - 2] * (double)ppv[G - 2][c] + ao[G - 3] * (double)ppv[G - 3][c]
-                                 : ao[0] * (double)ppv[0][c] + (double)a * (double)pv[c];
+                                 : ao[0] * (double)ppv[0][c] + (double)a * (double)pv[u][c];
 #pragma unroll
                 for (int k = G / 2 - 2; k >= 1; --k)
                     s += ao[2 * k] * (double)ppv[2 * k][c] + ao[2 * k - 1] * (double)ppv[2 * k - 1][c];
-                if constexpr (G > 2) s += ao[0] * (double)ppv[0][c] + (double)a * (double)pv[c];
-                st_at(x, i, xv[c] + s);
+                if constexpr (G > 2) s += ao[0] * (double)ppv[0][c] + (double)a * (double)pv[u][c];
+                st_at(x, i, xv[u][c] + s);
             }
-            const T ri = rv[c] - a * qv[c];
-            const T zi = jacobi_z(ri, w, ik[c]);
+            const T ri = rv[u][c] - a * qv[u][c];
+            const T zi = jacobi_z(ri, w[u], ik[c]);
             st_at(r, i, ri);
             if (DIM == 2 || !ApplyFormsZ<T>::value) st_at(z, i, zi);  // else the 3D apply forms z
             v[0] += (double)ri * (double)zi;
@@ -1247,9 +1256,22 @@ static int launch_tables(Ctx* ctx, const Grid& g, const topo_mesh& m, const doub
 // blocks for the apply, the stride of the partial arrays, and how many partials each
 // consumer sums (1 when a launch has more blocks than kPcgMaxBlocks: its partials are
 // then summed once by k_partials_sum).  The one-reduction step uses nupd / nrz.
+// The plain 3D updates take this many nodes per thread: twice the loads in flight per
+// wave (one node per thread left the plain update at 4.3 TB/s of measured traffic, the
+// flush update, with four times the loads per thread, at 5.1 TB/s).
+constexpr int kUpdateNpt = 2;
+
+// The update of launch lq is the last of its correction group (FLUSH).
+template <int DIM>
+inline bool flush_of(int lq) {
+    return (lq & (XGroup<DIM>::value - 1)) == 0;
+}
+
 struct PcgGeom {
     int nupd, napp, ps;
     int npq, nrz;  // partials read of the apply's pq and of the update's rz / rr
+    int npt;         // nodes per thread of the plain 3D updates (kUpdateNpt or 1)
+    int nupd_plain;  // their block count (and rz / rr partials)
 };
 
 static PcgGeom pcg_geom(const Grid& g) {
@@ -1259,6 +1281,11 @@ static PcgGeom pcg_geom(const Grid& g) {
     pg.ps = std::max(pg.nupd, pg.napp);
     pg.npq = pg.napp > kPcgMaxBlocks ? 1 : pg.napp;
     pg.nrz = pg.nupd > kPcgMaxBlocks ? 1 : pg.nupd;
+    // the plain 3D updates take kUpdateNpt nodes per thread when their partials go through
+    // the summing kernel (which reads the count each launch wrote); otherwise the apply
+    // reads nupd partials itself and every update writes that many
+    pg.npt = g.dim == 3 && pg.nrz == 1 && pg.nupd > 1 ? kUpdateNpt : 1;
+    pg.nupd_plain = grid_blocks(g.n_nodes, kPcgBlock * pg.npt);
     return pg;
 }
 
@@ -1314,12 +1341,18 @@ static bool update_narrow(const Grid& g) {
     return (unsigned long long)g.n_dofs * sizeof(double) < lim && 3ull * 2ull * nn * sizeof(T) < lim;
 }
 
+// npt: nodes per thread of a plain (non-flush) update, 1 or kUpdateNpt.
 template <int DIM, typename T>
-static const void* pcg_update_fn(bool flush, bool narrow) {
-    if (narrow)
-        return flush ? (const void*)k_pcg_update<DIM, T, true, unsigned>
-                     : (const void*)k_pcg_update<DIM, T, false, unsigned>;
-    return flush ? (const void*)k_pcg_update<DIM, T, true, size_t> : (const void*)k_pcg_update<DIM, T, false, size_t>;
+static const void* pcg_update_fn(bool flush, bool narrow, int npt) {
+    constexpr int W = kUpdateNpt;
+    if (flush)
+        return narrow ? (const void*)k_pcg_update<DIM, T, true, unsigned, 1>
+                      : (const void*)k_pcg_update<DIM, T, true, size_t, 1>;
+    if (npt == W)
+        return narrow ? (const void*)k_pcg_update<DIM, T, false, unsigned, W>
+                      : (const void*)k_pcg_update<DIM, T, false, size_t, W>;
+    return narrow ? (const void*)k_pcg_update<DIM, T, false, unsigned, 1>
+                  : (const void*)k_pcg_update<DIM, T, false, size_t, 1>;
 }
 
 template <typename T>
@@ -1354,15 +1387,16 @@ static void pcg_iteration(Ctx* ctx, const Grid& g, const PcgBufs<T>& w, const Pc
         TimedLaunch tl(ctx, KID_PCG_UPDATE, L.s, L.graph ? kTimeOff : timing, true);
         L.ev0 = tl.a;
         L.ev1 = tl.b;
-        const bool flush = (lq & (XGroup<DIM>::value - 1)) == 0;  // a group's last update
-        L(pcg_update_fn<DIM, T>(flush, update_narrow<T>(g)),
-          dim3(pg.nupd, w.B), dim3(kPcgBlock), g, w.winv, DIM == 3 ? w.mnode : w.mask, w.ik[0], w.ik[1], w.ik[2],
-          w.x, w.r, w.z,
+        const bool flush = flush_of<DIM>(lq);  // a group's last update
+        L(pcg_update_fn<DIM, T>(flush, update_narrow<T>(g), flush ? 1 : pg.npt),
+          dim3(flush ? pg.nupd : pg.nupd_plain, w.B), dim3(kPcgBlock), g, w.winv, DIM == 3 ? w.mnode : w.mask,
+          w.ik[0], w.ik[1], w.ik[2], w.x, w.r, w.z,
           w.ring(), (const T*)w.q, (const T*)w.side, w.sg, w.part, w.st, pg.ps, pg.npq, lq);
     }
-    if (pg.nrz == 1 && pg.nupd > 1)  // rz / rr of the update's own parity
-        L((const void*)k_partials_sum<PcgState>, dim3(w.B), dim3(1024), w.part, pg.ps, pg.nupd, 1, 1, 3, 1,
-          (const PcgState*)w.st, lp, 0, (const double*)nullptr);
+    if (pg.nrz == 1 && pg.nupd > 1)  // rz / rr of the update's own parity (its own block count)
+        L((const void*)k_partials_sum<PcgState>, dim3(w.B), dim3(1024), w.part, pg.ps,
+          flush_of<DIM>(lq) ? pg.nupd : pg.nupd_plain, 1, 1, 3, 1, (const PcgState*)w.st, lp, 0,
+          (const double*)nullptr);
 }
 
 // One step of the one-reduction recursion at launch parity lp (then s = K p when refresh).
