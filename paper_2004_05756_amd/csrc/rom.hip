@@ -890,7 +890,12 @@ static ContractPlan plan_contract(const Grid& g, int k, bool f64) {
     p.groups = (p.npairs + MAX_NT * GW - 1) / (MAX_NT * GW);
     p.nt = (p.npairs + p.groups * GW - 1) / (p.groups * GW);
     p.sd = gemm_sd<double>(p.KP);
-    p.ch = 8192;  // DOFs per chunk (one float64 partial tile per chunk and pair)
+    // DOFs per chunk (one float64 partial tile per chunk and pair): a multiple of 256
+    // (whole slabs) between 1024 and 8192, sized for about 1024 blocks per launch, so that
+    // a mesh of under a million DOFs still spreads over several blocks per CU (at 8192 a
+    // 698k-DOF field made 86 blocks for 256 CUs)
+    const long long want = (g.n_dofs * p.groups + 1023) / 1024;
+    p.ch = (int)std::min(8192LL, std::max(1024LL, (want + 255) / 256 * 256));
     p.nchunks = (int)((g.n_dofs + p.ch - 1) / p.ch);
     p.ld = (g.n_dofs + GEMM_LD - 1) / GEMM_LD * GEMM_LD;
     p.lds_bytes = (size_t)p.KP * (p.sd + 2) * ((f64 ? 8 : 4) + 8);  // Pt in the basis type, Wt in float64
