@@ -54,7 +54,10 @@ template <> struct Mfma<double> {
 // fixed order.
 // ----------------------------------------------------------------------------------
 constexpr int GW = 8;       // waves per block
-constexpr int MAX_NT = 8;   // most tile pairs per wave (float64 accumulators; 12 would spill)
+constexpr int MAX_NT = 4;   // most tile pairs per wave: 4 keep the kernel at 120 VGPRs, two
+                            // blocks per CU; 6 (160 VGPRs, one block per CU, every slab read
+                            // by two pair groups instead of three) took 10.2 against 8.7 ms per
+                            // field at k = 200 on 5.4M DOF
 constexpr int KP_MAX = 1024; // largest padded basis size
 constexpr int GEMM_LD = 64; // the operands' row pitch is a multiple of this
 
@@ -920,9 +923,7 @@ static int launch_gemm_sd(Ctx* ctx, const ContractPlan& p, const TC* Pt, const d
     if (p.nt <= 1) return launch_gemm_nt<TC, SD, 1>(ctx, p, Pt, Wt, nu, k, parts, s);
     if (p.nt <= 2) return launch_gemm_nt<TC, SD, 2>(ctx, p, Pt, Wt, nu, k, parts, s);
     if (p.nt <= 3) return launch_gemm_nt<TC, SD, 3>(ctx, p, Pt, Wt, nu, k, parts, s);
-    if (p.nt <= 4) return launch_gemm_nt<TC, SD, 4>(ctx, p, Pt, Wt, nu, k, parts, s);
-    if (p.nt <= 6) return launch_gemm_nt<TC, SD, 6>(ctx, p, Pt, Wt, nu, k, parts, s);
-    return launch_gemm_nt<TC, SD, 8>(ctx, p, Pt, Wt, nu, k, parts, s);
+    return launch_gemm_nt<TC, SD, 4>(ctx, p, Pt, Wt, nu, k, parts, s);
 }
 
 template <typename TC>
