@@ -196,12 +196,12 @@ def test_2d_solve_on_degenerate_shapes(nel, kind, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-@pytest.mark.parametrize("maxit", [5, 6, 7, 8, 9, 11])
+@pytest.mark.parametrize("maxit", [5, 6, 7, 8, 9, 11, 15, 16, 17, 31])
 def test_iteration_limit_returns_the_last_iterate(prec, maxit):
-    """A solve stopped by its iteration limit after k = 5..11 steps.  The two-kernel
+    """A solve stopped by its iteration limit after k = 5..31 steps.  The two-kernel
     recursion adds its steps to the correction in groups (two in 2D, eight in 3D), so a
     count that is not a multiple of the group leaves 1..7 steps pending when the segment
-    ends; the returned u must still be the k-th Jacobi-PCG iterate from u = 0 (Sec.
+    ends (and none at 16, two whole groups); the returned u must still be the k-th Jacobi-PCG iterate from u = 0 (Sec.
     3.1's inner solver), here scipy's CG with the same preconditioner on the oracle's
     assembled K_ff, and the reported residual must be that of the returned u."""
     import scipy.sparse as sp
