@@ -201,6 +201,33 @@ def test_config_bridge3d_192x96x96_batched_full():
         assert abs(host(J)[0] / c0 - 1) <= tol, (prec, host(J)[0], c0)
 
 
+def test_config_bridge3d_192x96x96_two_fields_alone_and_batched():
+    """Two candidate designs of the benchmark path at full size, in both precisions: each
+    field's solution bitwise the same solved alone and in the batch (on meshes over a
+    million nodes the plain updates take two nodes per thread and their partials go
+    through the summing kernel), and the float64 solutions' true residuals recomputed
+    by the oracle element by element."""
+    torch = torch_cuda()
+    from paper_2004_05756_amd import FP64, MIXED
+    cfg = W.config("bridge3d_192x96x96")
+    p, m = cfg.problem, cfg.problem.mesh
+    rhos = W.path_fields(m, cfg.rho(0), [1 / 32.0, 2 / 32.0], cfg.rho_seed0 + 100)
+    R = dev(rhos, torch.float64)
+    mk, f = dev(p.mask, torch.uint8), dev(p.f, torch.float64)
+    free = p.mask == 0
+    nf = np.linalg.norm(np.where(free, p.f, 0.0))
+    for prec in (FP64, MIXED):
+        print("bridge two fields, prec", prec, flush=True)
+        u2, inf2 = ctx().hdm_solve_batch(m, R, mk, f, rtol=cfg.rtol, prec=prec)
+        u1, inf1 = ctx().hdm_solve_batch(m, R[1:].contiguous(), mk, f, rtol=cfg.rtol, prec=prec)
+        assert inf2[1]["iters"] == inf1[0]["iters"] and torch.equal(u2[1], u1[0])
+        for b in range(2):
+            assert inf2[b]["status"] == 0 and inf2[b]["rel_resid"] <= cfg.rtol
+            if prec == FP64:
+                res = np.linalg.norm(np.where(free, p.f - O.apply_ebe(m, rhos[b], p.mask, host(u2[b])), 0.0)) / nf
+                assert res <= cfg.rtol * 1.01, (b, res)
+
+
 def test_config_bridge3d_192x96x96_sampled():
     """5,447,811 DOF, 16 density fields: the batched float32 / float64 apply and the
     HDM state checked on 256 sampled nodes, each computed by the oracle element by
