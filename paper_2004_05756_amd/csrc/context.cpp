@@ -19,6 +19,8 @@ Grid make_grid(const topo_mesh& m) {
     g.n_nodes = g.nx1 * g.ny1 * g.nz1;
     g.n_elems = g.nx * g.ny * g.nz;
     g.n_dofs = (long long)g.dim * g.n_nodes;
+    g.dnx1 = make_fastdiv((unsigned)g.nx1);
+    g.dny1 = make_fastdiv((unsigned)g.ny1);
     return g;
 }
 

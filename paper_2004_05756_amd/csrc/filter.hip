@@ -85,10 +85,10 @@ static HelmElem helm_element(const topo_mesh& m, double r) {
 }
 
 __device__ __forceinline__ void node_ijk(const Grid& g, int n, int& i, int& j, int& k) {
-    i = n % g.nx1;
-    const int t = n / g.nx1;
-    j = t % g.ny1;
-    k = t / g.ny1;
+    const unsigned t = g.dnx1.div((unsigned)n), kk = g.dny1.div(t);
+    i = n - (int)t * g.nx1;
+    j = (int)(t - kk * (unsigned)g.ny1);
+    k = (int)kk;
 }
 
 // out[b][n] = scale * sum over the elements around node n of in[b][e].

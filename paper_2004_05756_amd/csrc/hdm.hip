@@ -368,8 +368,9 @@ __device__ __forceinline__ int pcg_apply_scalars(const double* part, PcgState* s
 }
 
 // 2D: one node per thread (the launch covers every node of every field).  The node's
-// loads are issued before it waits on the scalar reduction.
-template <typename T>
+// loads are issued before it waits on the scalar reduction.  I: index type of the
+// neighbourhood loads (32-bit when the per-field arrays fit, narrow2).
+template <typename T, typename I>
 __global__ __launch_bounds__(kPcgBlock) void k_pcg_apply2(Grid g, const T* __restrict__ alpha,
                                                        const T* __restrict__ K,
                                                        const uint8_t* __restrict__ mask,
@@ -396,9 +397,9 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_apply2(Grid g, const T* __res
     if (own) {
         int i, j, k;
         node_ijk(g, n, i, j, k);
-        load_nbhd2(g, i, j, FetchPlain<T>{z, g.n_nodes}, zs);
-        load_nbhd2(g, i, j, FetchPlain<T>{p_old, g.n_nodes}, ps_);
-        load_alpha2(g, i, j, alpha, al);
+        load_nbhd2(g, i, j, FetchPlain<T, I>{z, g.n_nodes}, zs);
+        load_nbhd2(g, i, j, FetchPlain<T, I>{p_old, g.n_nodes}, ps_);
+        load_alpha2<T, I>(g, i, j, alpha, al);
 #pragma unroll
         for (int c = 0; c < 2; ++c) mk[c] = mask[(size_t)c * g.n_nodes + n];
     }
@@ -750,7 +751,7 @@ enum { kCg1Step = 0, kCg1Fresh = 1, kCg1Continued = 2 };
 __device__ __forceinline__ double* cg1_part(double* p, int ps, int k) { return p + (size_t)k * ps; }
 
 // Node value of a per-node array on the 3x3 neighbourhood (zero outside the grid).
-template <typename T>
+template <typename T, typename I = size_t>
 __device__ __forceinline__ void load_node_nbhd2(const Grid& g, int i, int j, const T* __restrict__ a,
                                                 T (&v)[3][3]) {
 #pragma unroll
@@ -759,15 +760,15 @@ __device__ __forceinline__ void load_node_nbhd2(const Grid& g, int i, int j, con
         for (int dx = 0; dx < 3; ++dx) {
             const int ii = i + dx - 1, jj = j + dy - 1;
             const bool ok = (ii >= 0) & (ii < g.nx1) & (jj >= 0) & (jj < g.ny1);
-            v[dy][dx] = ok ? a[jj * g.nx1 + ii] : T(0);
+            v[dy][dx] = ok ? ld_at(a, (I)(jj * g.nx1 + ii)) : T(0);
         }
 }
 
 // One step of every running field.  The first step of a segment is fresh (beta = 0) or
 // continued (after a residual replacement: the direction K-conjugate to the kept p,
 // with the exact p^T K p, from the u.s / p.s partials of k_cg1_start2); the kind is
-// read from the field's state.
-template <typename T>
+// read from the field's state.  I: index type of the neighbourhood loads (narrow2).
+template <typename T, typename I>
 __global__ __launch_bounds__(kPcgBlock) void k_cg1_step2(
     Grid g, const T* __restrict__ alpha, const T* __restrict__ K, const uint8_t* __restrict__ mask,
     const T* __restrict__ winv, T ik0, T ik1, T* __restrict__ R0, T* __restrict__ R1, T* __restrict__ W0,
@@ -799,11 +800,11 @@ __global__ __launch_bounds__(kPcgBlock) void k_cg1_step2(
     int i = 0, j = 0, k = 0;
     if (own) {  // every load is issued before the wait on the scalar reduction
         node_ijk(g, n, i, j, k);
-        load_nbhd2(g, i, j, FetchPlain<T>{Rin, g.n_nodes}, rs);
-        load_nbhd2(g, i, j, FetchPlain<T>{Win, g.n_nodes}, ws);
-        load_nbhd2(g, i, j, FetchPlain<T>{Sin, g.n_nodes}, ss);
-        load_node_nbhd2(g, i, j, winv, wv);
-        load_alpha2(g, i, j, alpha, al);
+        load_nbhd2(g, i, j, FetchPlain<T, I>{Rin, g.n_nodes}, rs);
+        load_nbhd2(g, i, j, FetchPlain<T, I>{Win, g.n_nodes}, ws);
+        load_nbhd2(g, i, j, FetchPlain<T, I>{Sin, g.n_nodes}, ss);
+        load_node_nbhd2<T, I>(g, i, j, winv, wv);
+        load_alpha2<T, I>(g, i, j, alpha, al);
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
             const size_t idx = (size_t)c * g.n_nodes + n;
@@ -1332,6 +1333,13 @@ static bool apply3_narrow(const Grid& g) {
     return sizeof(T) == 4 && 3ull * 2ull * nn * sizeof(T) < lim && (unsigned long long)g.n_elems * sizeof(T) < lim;
 }
 
+// The 2D stencil kernels take 32-bit neighbourhood indices when every per-field array
+// they read fits in 4 GiB (DOF vectors up to float64, alpha per element).
+static bool narrow2(const Grid& g) {
+    const unsigned long long lim = 1ull << 32;
+    return (unsigned long long)g.n_dofs * sizeof(double) < lim && (unsigned long long)g.n_elems * sizeof(double) < lim;
+}
+
 // The update takes 32-bit indices when each per-field array it touches fits in 4 GiB:
 // the float64 correction x (the largest DOF array) and the side sections (2 N_n nodes
 // bound them, as above).
@@ -1373,7 +1381,8 @@ static void pcg_iteration(Ctx* ctx, const Grid& g, const PcgBufs<T>& w, const Pc
         L.ev0 = tl.a;
         L.ev1 = tl.b;
         if constexpr (DIM == 2)
-            L((const void*)k_pcg_apply2<T>, dim3(pg.napp, w.B), dim3(kPcgBlock), g, w.alpha, w.K, w.mask,
+            L(narrow2(g) ? (const void*)k_pcg_apply2<T, unsigned> : (const void*)k_pcg_apply2<T, size_t>,
+              dim3(pg.napp, w.B), dim3(kPcgBlock), g, w.alpha, w.K, w.mask,
               (const T*)w.z, w.p0, w.p1, w.q, w.part, w.st, pg.ps, pg.nrz, lp);
         else
             L(pcg_apply3_fn<T>(w.narrow), dim3(pg.napp, w.B), dim3(kBlock), g, w.alpha, w.Mv,
@@ -1407,7 +1416,8 @@ static void cg1_step(Ctx* ctx, const Grid& g, const PcgBufs<T>& w, const PcgGeom
         TimedLaunch tl(ctx, KID_PCG_STEP, L.s, L.graph ? kTimeOff : timing, true);
         L.ev0 = tl.a;
         L.ev1 = tl.b;
-        L((const void*)k_cg1_step2<T>, dim3(pg.nupd, w.B), dim3(kPcgBlock), g, w.alpha, w.K, w.mask, w.winv,
+        L(narrow2(g) ? (const void*)k_cg1_step2<T, unsigned> : (const void*)k_cg1_step2<T, size_t>,
+          dim3(pg.nupd, w.B), dim3(kPcgBlock), g, w.alpha, w.K, w.mask, w.winv,
           w.ik[0], w.ik[1], w.r, w.z, w.q, w.e0, w.p0, w.p1, w.e1, w.x, w.part, w.st1, pg.ps, pg.nrz, lp);
     }
     if (pg.nrz == 1 && pg.nupd > 1) {  // the set the step wrote: its parity ^ 1

@@ -17,6 +17,49 @@
 
 namespace topo {
 
+// Division by a divisor fixed at launch: floor(n / d) = (n m) >> s for 0 <= n < 2^31 and
+// 1 <= d < 2^31, with s = 31 + ceil(log2 d) and m = ceil(2^s / d) (the round-up method of
+// Granlund and Montgomery): m d - 2^s < d bounds the error n (m d - 2^s) / (d 2^s) below
+// 1/d, the distance from n / d up to the next integer, and m < 2^32.
+struct FastDiv {
+    unsigned d = 1, m = 1u << 31;
+    int s = 31;
+    __host__ __device__ unsigned div(unsigned n) const {
+        return (unsigned)(((unsigned long long)n * m) >> s);
+    }
+};
+
+inline FastDiv make_fastdiv(unsigned d) {
+    FastDiv f;
+    int l = 0;
+    while ((1ull << l) < d) ++l;
+    f.d = d;
+    f.s = 31 + l;
+    f.m = (unsigned)(((1ull << f.s) + d - 1) / d);
+    return f;
+}
+
+// Element access at index i of an array whose base is uniform: with a 32-bit index the
+// byte offset is formed in 32 bits, so that a load or store takes the base in scalar
+// registers and one 32-bit offset (no 64-bit address per access); with a 64-bit index
+// (arrays of 4 GiB or more, and the float64 apply) it is a plain subscript.
+template <typename T>
+__device__ __forceinline__ T ld_at(const T* __restrict__ b, unsigned i) {
+    return *(const T*)((const char*)b + i * (unsigned)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ T ld_at(const T* __restrict__ b, size_t i) {
+    return b[i];
+}
+template <typename T>
+__device__ __forceinline__ void st_at(T* __restrict__ b, unsigned i, T v) {
+    *(T*)((char*)b + i * (unsigned)sizeof(T)) = v;
+}
+template <typename T>
+__device__ __forceinline__ void st_at(T* __restrict__ b, size_t i, T v) {
+    b[i] = v;
+}
+
 // ----------------------------------------------------------------------------------
 // Structured grid as seen by the kernels
 // ----------------------------------------------------------------------------------
@@ -28,6 +71,7 @@ struct Grid {
     int n_elems;
     long long n_dofs;
     int mtarget = 0;    // 3D march: resident blocks of the kernel per field (0: 1024)
+    FastDiv dnx1, dny1; // division by nx1, ny1 (node coordinates from a node index)
 };
 
 Grid make_grid(const topo_mesh& m);
@@ -324,28 +368,6 @@ __host__ __device__ inline int once3_blocks(const Grid& g) {
 // in y, bit 4: in z).  Along an axis in s the section holds only the interior block
 // boundaries (index = boundary number - 1), along the others every node; the sections
 // follow each other in the order of s, one component after the other ([c][total]).
-// Division by a divisor fixed at launch: floor(n / d) = (n m) >> s for 0 <= n < 2^31 and
-// 1 <= d < 2^31, with s = 31 + ceil(log2 d) and m = ceil(2^s / d) (the round-up method of
-// Granlund and Montgomery): m d - 2^s < d bounds the error n (m d - 2^s) / (d 2^s) below
-// 1/d, the distance from n / d up to the next integer, and m < 2^32.
-struct FastDiv {
-    unsigned d = 1, m = 1u << 31;
-    int s = 31;
-    __host__ __device__ unsigned div(unsigned n) const {
-        return (unsigned)(((unsigned long long)n * m) >> s);
-    }
-};
-
-inline FastDiv make_fastdiv(unsigned d) {
-    FastDiv f;
-    int l = 0;
-    while ((1ull << l) < d) ++l;
-    f.d = d;
-    f.s = 31 + l;
-    f.m = (unsigned)(((1ull << f.s) + d - 1) / d);
-    return f;
-}
-
 struct SideGeom {
     int nbx, nby, nbz;  // interior block boundaries along x, y, z
     int nnx, nny, nnz;  // nodes along x, y, z

@@ -16,27 +16,6 @@
 
 namespace topo {
 
-// Element access at index i of an array whose base is uniform: with a 32-bit index the
-// byte offset is formed in 32 bits, so that a load or store takes the base in scalar
-// registers and one 32-bit offset (no 64-bit address per access); with a 64-bit index
-// (arrays of 4 GiB or more, and the float64 apply) it is a plain subscript.
-template <typename T>
-__device__ __forceinline__ T ld_at(const T* __restrict__ b, unsigned i) {
-    return *(const T*)((const char*)b + i * (unsigned)sizeof(T));
-}
-template <typename T>
-__device__ __forceinline__ T ld_at(const T* __restrict__ b, size_t i) {
-    return b[i];
-}
-template <typename T>
-__device__ __forceinline__ void st_at(T* __restrict__ b, unsigned i, T v) {
-    *(T*)((char*)b + i * (unsigned)sizeof(T)) = v;
-}
-template <typename T>
-__device__ __forceinline__ void st_at(T* __restrict__ b, size_t i, T v) {
-    b[i] = v;
-}
-
 constexpr int MPX = MEX + 1, MPY = MEY + 1;         // staged node plane
 constexpr int MPN = MPX * MPY;                      // 297 nodes
 static_assert(MEX * MEY == kBlock, "one thread per element column");

@@ -13,12 +13,14 @@
 
 namespace topo {
 
-// Input fetchers: value of component c at node n (n is always in range).
-template <typename T>
+// Input fetchers: value of component c at node n (n is always in range).  I: index type
+// of the per-field array (32-bit when its bytes fit: the load then takes the uniform base
+// and one 32-bit offset instead of a 64-bit address per neighbour).
+template <typename T, typename I = size_t>
 struct FetchPlain {
     const T* __restrict__ x;
     int nn;
-    __device__ __forceinline__ T operator()(int n, int c) const { return x[(size_t)c * nn + n]; }
+    __device__ __forceinline__ T operator()(int n, int c) const { return ld_at(x, (I)c * (I)nn + (I)n); }
 };
 
 template <typename T, typename TX = T>
@@ -50,7 +52,7 @@ __device__ __forceinline__ void load_nbhd2(const Grid& g, int i, int j, const Fe
         }
 }
 
-template <typename T>
+template <typename T, typename I = size_t>
 __device__ __forceinline__ void load_alpha2(const Grid& g, int i, int j, const T* __restrict__ alpha,
                                             T (&al)[2][2]) {
 #pragma unroll
@@ -59,7 +61,7 @@ __device__ __forceinline__ void load_alpha2(const Grid& g, int i, int j, const T
         for (int ex = 0; ex < 2; ++ex) {
             const int exx = i - 1 + ex, eyy = j - 1 + ey;
             const bool ok = (exx >= 0) & (exx < g.nx) & (eyy >= 0) & (eyy < g.ny);
-            al[ey][ex] = ok ? alpha[eyy * g.nx + exx] : T(0);
+            al[ey][ex] = ok ? ld_at(alpha, (I)(eyy * g.nx + exx)) : T(0);
         }
 }
 
@@ -134,10 +136,10 @@ __device__ __forceinline__ T node_alpha_sum(const Grid& g, int i, int j, int k,
 }
 
 __device__ __forceinline__ void node_ijk(const Grid& g, int n, int& i, int& j, int& k) {
-    i = n % g.nx1;
-    const int t = n / g.nx1;
-    j = t % g.ny1;
-    k = t / g.ny1;
+    const unsigned t = g.dnx1.div((unsigned)n), kk = g.dny1.div(t);
+    i = n - (int)t * g.nx1;
+    j = (int)(t - kk * (unsigned)g.ny1);
+    k = (int)kk;
 }
 
 }  // namespace topo
