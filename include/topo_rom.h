@@ -62,8 +62,9 @@ extern "C" {
 
 /* Precision of the hot loops. */
 #define TOPO_FP64 0   /* everything in float64                                      */
-#define TOPO_MIXED 1  /* float32 apply / contraction with float64 refinement,       */
-                      /* float64 dots, norms, compliance and reduced Cholesky        */
+#define TOPO_MIXED 1  /* float32 inner PCG (float64 correction and residual        */
+                      /* replacement), float64 dots, norms, compliance, K_hat and     */
+                      /* reduced Cholesky; float32 basis with float64 refinement      */
 
 typedef struct topo_ctx topo_ctx;
 
@@ -132,8 +133,8 @@ int topo_ctx_kernel_time(topo_ctx* ctx, const char* kernel, int64_t* samples,
  * a = ax + 2*ay (+ 4*az).  K0: HOST array of (dim*2^dim)^2 doubles, row-major. */
 int topo_element_stiffness(const topo_mesh* mesh, double* K0);
 
-/* Symmetry-blocked factor K_e = R^T R that the apply, the residual and the K_hat
- * contraction evaluate (R: 5 rows for Q4, 18 for H8).  In the Walsh-Hadamard basis
+/* Symmetry-blocked factor K_e = R^T R that the 3D apply and residual evaluate (in its
+ * reduced-block form) (R: 5 rows for Q4, 18 for H8).  In the Walsh-Hadamard basis
  * N[m][c] = -sum_a (-1)^{popcount(m & a)} x[a][c] of an element vector x, K_e splits
  * into one block per reflection character n (entries (n ^ 2^c, c), c < dim).  Blocks
  * with one set bit drop their rigid translation entry; blocks with two set bits c < d
@@ -202,17 +203,19 @@ int topo_hdm_gradient_batch(topo_ctx* ctx, const topo_mesh* mesh, const double* 
 /* ---- reduced-order model --------------------------------------------------------- */
 
 /* Reduced operators of B density fields sharing one basis (Sec. 3.1, element-sum
- * form of K_hat, computed per element with dense operations as the paper's dense
- * assembly remark suggests):
+ * form of K_hat; Sec. 3.4 cost analysis):
  *   Khat[b] = sum_e alpha(rho_be) (P_e^T Phi)^T K_e (P_e^T Phi)   [B][k][k] f64 out,
  *   fhat    = Phi^T f                                             [k] f64 out (may
  *             be NULL; it depends on the basis only).
- * Evaluated as K_hat = D^T D with D stacking sqrt(alpha_e) R P_e^T Phi per element,
- * K_e = R^T R being the element operator's symmetry-blocked factor (5 rows per Q4,
- * 18 per H8, rigid modes dropped exactly).  TOPO_MIXED contracts in float32 on the
- * matrix cores with float64 cross-tile sums; TOPO_FP64 contracts in float64 (Phi
- * promoted when phi_fp32 != 0).
- *   rho: [B][n_elems] f64. */
+ * Evaluated per field as W = K(rho_b) Phi, the k basis columns (masked rows zero) taken
+ * as the vectors of one batched matrix-free apply in float64, then K_hat = Phi^T W as
+ * one product over the N_u rows, accumulated in float64 on the matrix cores with
+ * per-chunk partials summed in a fixed order.  The arithmetic is float64 in both
+ * precisions (prec is validated but selects nothing here; a float32 basis is read as
+ * its float32 values).  A field's K_hat does not depend on B.
+ *   rho: [B][n_elems] f64.  Errors: TOPO_EINVAL (sizes, k beyond 1024 after padding to
+ *   16, null pointers), TOPO_ENOMEM (workspace beyond the context budget),
+ *   TOPO_EDEVICE. */
 int topo_rom_build(topo_ctx* ctx, const topo_mesh* mesh, const void* phi,
                    int32_t phi_fp32, int32_t k, int32_t ldphi, const uint8_t* mask,
                    const double* f, const double* rho, int32_t B, double* Khat,
